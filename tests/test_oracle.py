@@ -1,0 +1,534 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks an oracle function against something other than itself:
+closed forms, invariants, special cases that reduce to a textbook formula,
+brute force on tiny inputs, or finite differences.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import meshgen as mg
+from oracle import barrier, ccd, contact, fem, geometry as geo, local, solver
+
+RNG = np.random.default_rng(1234)
+
+
+def rand_rot(k):
+    return mg.random_rotations(np.random.default_rng(7), k)
+
+
+# --------------------------------------------------------------------------
+# Eq. (1): deformation gradient, rotation fit, element energy
+# --------------------------------------------------------------------------
+def test_affine_map_has_exact_deformation_gradient():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    _, B, V = fem.rest_data(sc.X, sc.tets)
+    M = np.array([[1.1, 0.2, -0.05], [0.03, 0.9, 0.1], [-0.2, 0.05, 1.3]])
+    x = sc.X @ M.T + np.array([0.3, -0.1, 2.0])
+    F = local.deformation_gradients(x, sc.tets, B)
+    assert np.allclose(F, M[None], atol=1e-12)
+    # G_i x_local = vec(F) row-major
+    G = fem.gradient_operators(B)
+    xl = x[sc.tets].reshape(-1, 12)
+    assert np.allclose(np.einsum("mij,mj->mi", G, xl), F.reshape(-1, 9), atol=1e-12)
+
+
+def test_rest_volumes_tile_the_hexes():
+    sc = mg.slabs(0, nx=3, ny=2, nz=2, h=0.01)
+    _, _, V = fem.rest_data(sc.X, sc.tets)
+    assert np.allclose(V, 0.01 ** 3 / 6, rtol=1e-12)
+    assert np.isclose(V.sum(), 2 * 3 * 2 * 2 * 0.01 ** 3, rtol=1e-12)
+
+
+def test_inverted_rest_tet_is_rejected():
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    with pytest.raises(ValueError):
+        fem.rest_data(X, np.array([[0, 2, 1, 3]]))
+    with pytest.raises(ValueError):
+        fem.rest_data(np.zeros((4, 3)), np.array([[0, 1, 2, 3]]))
+
+
+def test_rotation_fit_recovers_constructed_rotation():
+    k = 50
+    R0 = rand_rot(k)
+    L = RNG.standard_normal((k, 3, 3))
+    S = L @ np.swapaxes(L, 1, 2) + 0.5 * np.eye(3)      # SPD
+    M = R0 @ S
+    # with A = I, F = M: the nearest rotation to R0 S (S SPD) is R0
+    R = local.best_rotations(M, np.broadcast_to(np.eye(3), (k, 3, 3)))
+    assert np.allclose(R, R0, atol=1e-12)
+
+
+def test_rotation_fit_beats_sampled_rotations():
+    F = RNG.standard_normal((6, 3, 3))
+    A = RNG.standard_normal((6, 3, 3))
+    A = 0.5 * (A + np.swapaxes(A, 1, 2)) + 2 * np.eye(3)
+    R = local.best_rotations(F, A)
+    assert np.allclose(np.linalg.det(R), 1.0)
+    assert np.allclose(R @ np.swapaxes(R, 1, 2), np.eye(3), atol=1e-12)
+    best = np.sum((F - R @ A) ** 2, axis=(1, 2))
+    samples = mg.random_rotations(np.random.default_rng(3), 20000)
+    for i in range(F.shape[0]):
+        e = np.sum((F[i][None] - samples @ A[i]) ** 2, axis=(1, 2))
+        assert best[i] <= e.min() + 1e-12
+
+
+def test_element_energy_closed_form():
+    """min_R ||F - R A||^2 = ||F||^2 + ||A||^2 - 2 (s1 + s2 + sign(det FA) s3)."""
+    F = RNG.standard_normal((40, 3, 3))
+    A = RNG.standard_normal((40, 3, 3))
+    A = 0.5 * (A + np.swapaxes(A, 1, 2))
+    s = np.linalg.svd(F @ A, compute_uv=False)
+    sg = np.sign(np.linalg.det(F @ A))
+    closed = (np.sum(F ** 2, axis=(1, 2)) + np.sum(A ** 2, axis=(1, 2))
+              - 2 * (s[:, 0] + s[:, 1] + sg * s[:, 2]))
+    E = local.element_energies(F, A, np.full(40, 2.0))
+    assert np.allclose(E, closed, rtol=1e-12, atol=1e-12)
+
+
+def test_identity_state_projects_to_identity():
+    F = np.broadcast_to(np.eye(3), (5, 3, 3)).copy()
+    R, P = local.projections(F, F.copy())
+    assert np.allclose(P, np.eye(3)) and np.allclose(local.element_energies(F, F, np.ones(5)), 0)
+
+
+def test_actuation_matrix_definition():
+    R = rand_rot(4)
+    a = np.array([0.0, 0.1, 0.2, 0.3])
+    A = fem.actuation_matrices(a, R)
+    for i in range(4):
+        ev = np.sort(np.linalg.eigvalsh(A[i]))
+        assert np.allclose(ev, np.sort([1 - a[i], 1 + a[i] / 2, 1 + a[i] / 2]))
+        assert np.allclose(A[i] @ R[i][:, 0], (1 - a[i]) * R[i][:, 0])
+    dA = fem.actuation_derivative(R)
+    h = 1e-6
+    fd = (fem.actuation_matrices(a + h, R) - fem.actuation_matrices(a - h, R)) / (2 * h)
+    assert np.allclose(dA, fd, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Eq. (2): the constant PD matrix
+# --------------------------------------------------------------------------
+def test_pd_matrix_structure():
+    sc = mg.slabs(0, nx=3, ny=3, nz=1)
+    prob = solver.setup_scene(sc)
+    H = prob.H.toarray()
+    n = sc.n
+    # translation invariance: rows sum to zero per coordinate
+    for c in range(3):
+        t = np.zeros(3 * n)
+        t[c::3] = 1.0
+        assert np.abs(H @ t).max() < 1e-9 * np.abs(H).max()
+    # Kronecker structure H = H_s (x) I_3
+    Hs = H[0::3, 0::3]
+    assert np.allclose(H, np.kron(Hs, np.eye(3)), atol=1e-12 * np.abs(H).max())
+    # SPD once the fixed vertices are removed
+    f = prob.free
+    ev = np.linalg.eigvalsh(H[np.ix_(f, f)])
+    assert ev.min() > 0
+
+
+def test_pd_gradient_is_energy_gradient():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    prob = solver.setup_scene(sc)
+    A = fem.actuation_matrices(sc.act_a, sc.act_R)
+    x = sc.X + 1e-3 * RNG.standard_normal(sc.X.shape)
+
+    def E(xx):
+        F = local.deformation_gradients(xx, prob.tets, prob.B)
+        return local.element_energies(F, A, prob.w).sum()
+
+    F = local.deformation_gradients(x, prob.tets, prob.B)
+    _, P = local.projections(F, A)
+    g = solver.pd_gradient(prob, F, P)
+    h = 1e-7
+    for dof in RNG.choice(3 * sc.n, 12, replace=False):
+        xp, xm = x.copy().reshape(-1), x.copy().reshape(-1)
+        xp[dof] += h
+        xm[dof] -= h
+        fd = (E(xp.reshape(-1, 3)) - E(xm.reshape(-1, 3))) / (2 * h)
+        assert np.isclose(g[dof], fd, rtol=1e-5, atol=1e-10 * np.abs(g).max())
+
+
+def test_rest_state_with_identity_actuation_has_zero_gradient():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    prob = solver.setup_scene(sc)
+    A = fem.actuation_matrices(np.zeros(sc.m), sc.act_R)
+    F = local.deformation_gradients(sc.X, prob.tets, prob.B)
+    _, P = local.projections(F, A)
+    assert np.abs(solver.pd_gradient(prob, F, P)).max() < 1e-10
+
+
+# --------------------------------------------------------------------------
+# distances between closed primitives
+# --------------------------------------------------------------------------
+def test_point_above_triangle_interior():
+    a, b, c = np.array([0, 0, 0.0]), np.array([1, 0, 0.0]), np.array([0, 1, 0.0])
+    p = np.array([0.2, 0.3, 0.37])
+    d2, kind, idx = geo.point_triangle(p, a, b, c)
+    assert np.isclose(d2[0], 0.37 ** 2) and kind[0] == geo.PT
+
+
+def test_point_triangle_edge_and_vertex_regions():
+    a, b, c = np.array([0, 0, 0.0]), np.array([1, 0, 0.0]), np.array([0, 1, 0.0])
+    d2, kind, idx = geo.point_triangle(np.array([0.5, -0.2, 0.1]), a, b, c)
+    assert np.isclose(d2[0], 0.2 ** 2 + 0.1 ** 2) and kind[0] == geo.PE and list(idx[0][:3]) == [0, 1, 2]
+    d2, kind, idx = geo.point_triangle(np.array([-0.3, -0.4, 0.0]), a, b, c)
+    assert np.isclose(d2[0], 0.25) and kind[0] == geo.PP and list(idx[0][:2]) == [0, 1]
+
+
+def test_skew_and_parallel_segments():
+    a0, a1 = np.array([0, 0, 0.0]), np.array([1, 0, 0.0])
+    d2, kind, _ = geo.edge_edge(a0, a1, np.array([0.5, -1, 0.25]), np.array([0.5, 1, 0.25]))
+    assert np.isclose(d2[0], 0.0625) and kind[0] == geo.EE
+    # parallel, overlapping: distance is the offset
+    d2, kind, _ = geo.edge_edge(a0, a1, np.array([0.2, 0.3, 0.0]), np.array([1.4, 0.3, 0.0]))
+    assert np.isclose(d2[0], 0.09) and kind[0] in (geo.PE, geo.PP)
+    # collinear, disjoint: gap between the ends
+    d2, _, _ = geo.edge_edge(a0, a1, np.array([1.5, 0, 0.0]), np.array([3, 0, 0.0]))
+    assert np.isclose(d2[0], 0.25)
+
+
+def _sample_tri(a, b, c, n=120):
+    u, v = np.meshgrid(np.linspace(0, 1, n), np.linspace(0, 1, n))
+    ok = u + v <= 1
+    u, v = u[ok], v[ok]
+    return a + u[:, None] * (b - a) + v[:, None] * (c - a)
+
+
+def _sample_seg(a, b, n=2000):
+    t = np.linspace(0, 1, n)[:, None]
+    return a + t * (b - a)
+
+
+def test_distances_against_dense_sampling():
+    rng = np.random.default_rng(5)
+    for _ in range(25):
+        p, a, b, c = rng.standard_normal((4, 3))
+        d = np.sqrt(geo.point_triangle(p, a, b, c)[0][0])
+        S = _sample_tri(a, b, c)
+        ds = np.linalg.norm(S - p, axis=1).min()
+        assert d <= ds + 1e-12 and ds - d < 0.05 * np.linalg.norm(b - a) + 0.05
+        a0, a1, b0, b1 = rng.standard_normal((4, 3))
+        d = np.sqrt(geo.edge_edge(a0, a1, b0, b1)[0][0])
+        SA, SB = _sample_seg(a0, a1, 600), _sample_seg(b0, b1, 600)
+        dd = np.linalg.norm(SA[:, None] - SB[None], axis=2).min()
+        assert d <= dd + 1e-12 and dd - d < 1e-2
+
+
+def test_feature_formula_matches_classified_distance():
+    rng = np.random.default_rng(9)
+    P = rng.standard_normal((500, 4, 3))
+    d2, kind, idx = geo.point_triangle(P[:, 0], P[:, 1], P[:, 2], P[:, 3])
+    assert np.allclose(barrier.squared_distance_by_feature(P, kind, idx), d2, rtol=1e-10, atol=1e-14)
+    d2, kind, idx = geo.edge_edge(P[:, 0], P[:, 1], P[:, 2], P[:, 3])
+    assert np.allclose(barrier.squared_distance_by_feature(P, kind, idx), d2, rtol=1e-10, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Eq. (3): barrier and derivatives
+# --------------------------------------------------------------------------
+DHAT, KAPPA = 5e-4, 1e3
+
+
+def _b1(d):
+    return -2 * (d - DHAT) * np.log(d / DHAT) - (d - DHAT) ** 2 / d
+
+
+def _b2(d):
+    return -2 * np.log(d / DHAT) - 4 * (d - DHAT) / d + (d - DHAT) ** 2 / d ** 2
+
+
+def test_barrier_vanishes_smoothly_at_threshold():
+    assert barrier.barrier(np.array([DHAT, 2 * DHAT]), DHAT).max() == 0
+    assert np.isclose(_b1(DHAT), 0) and np.isclose(_b2(DHAT), 0)
+    assert barrier.barrier(np.array([1e-6]), DHAT)[0] > 0
+
+
+def test_single_point_triangle_closed_form():
+    """Point at height h over a triangle interior: grad_p = kappa b'(h) n, Hess_pp = kappa b''(h) n n^T."""
+    h = 2e-4
+    tri = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.0]])
+    X4 = np.concatenate([np.array([[0.002, 0.003, h]]), tri])[None]
+    d2, kind, idx = geo.point_triangle(X4[:, 0], X4[:, 1], X4[:, 2], X4[:, 3])
+    E, G, H = barrier.pair_derivatives(X4, kind, idx, DHAT, KAPPA)
+    n = np.array([0, 0, 1.0])
+    assert np.isclose(E[0], KAPPA * barrier.barrier(np.array([h]), DHAT)[0], rtol=1e-12)
+    assert np.allclose(G[0, :3], KAPPA * _b1(h) * n, rtol=1e-10)
+    assert np.allclose(G[0].reshape(4, 3).sum(axis=0), 0, atol=1e-9 * np.abs(G).max())
+    assert np.allclose(H[0, :3, :3], KAPPA * _b2(h) * np.outer(n, n), rtol=1e-9, atol=1e-9 * abs(_b2(h)) * KAPPA)
+
+
+def _fd_pair(X4, dhat, kappa, eps):
+    """Central FD of the barrier built from the min-over-candidates distance."""
+    def energy(Y):
+        Y = Y.reshape(1, 4, 3)
+        if pair_is_pt:
+            d2 = geo.point_triangle(Y[:, 0], Y[:, 1], Y[:, 2], Y[:, 3])[0]
+        else:
+            d2 = geo.edge_edge(Y[:, 0], Y[:, 1], Y[:, 2], Y[:, 3])[0]
+        return kappa * barrier.barrier(np.sqrt(d2), dhat)[0]
+    global pair_is_pt
+    x = X4.reshape(-1)
+    g = np.zeros(12)
+    for i in range(12):
+        e = np.zeros(12)
+        e[i] = eps
+        g[i] = (energy(x + e) - energy(x - e)) / (2 * eps)
+    return g
+
+
+def _grad_fn(X4, is_pt):
+    def gfun(y):
+        Y = y.reshape(1, 4, 3)
+        f = geo.point_triangle if is_pt else geo.edge_edge
+        d2, kind, idx = f(Y[:, 0], Y[:, 1], Y[:, 2], Y[:, 3])
+        return barrier.pair_derivatives(Y, kind, idx, DHAT, KAPPA)[1][0]
+    return gfun
+
+
+@pytest.mark.parametrize("is_pt", [True, False])
+def test_barrier_derivatives_against_finite_differences(is_pt):
+    global pair_is_pt
+    pair_is_pt = is_pt
+    rng = np.random.default_rng(11 if is_pt else 12)
+    checked = 0
+    while checked < 6:
+        base = rng.uniform(-0.005, 0.005, (3, 3))
+        if is_pt:
+            p = base.mean(axis=0) + rng.uniform(-1e-3, 1e-3, 3)
+            n = np.cross(base[1] - base[0], base[2] - base[0])
+            p = p + n / np.linalg.norm(n) * rng.uniform(1e-4, 4e-4)
+            X4 = np.concatenate([p[None], base])[None]
+            d2, kind, idx = geo.point_triangle(X4[:, 0], X4[:, 1], X4[:, 2], X4[:, 3])
+        else:
+            a0, a1 = base[0], base[1]
+            mid = 0.5 * (a0 + a1)
+            dirb = rng.standard_normal(3)
+            off = rng.standard_normal(3)
+            off /= np.linalg.norm(off)
+            b0 = mid + off * 3e-4 - 0.004 * dirb / np.linalg.norm(dirb)
+            b1 = mid + off * 3e-4 + 0.004 * dirb / np.linalg.norm(dirb)
+            X4 = np.stack([a0, a1, b0, b1])[None]
+            d2, kind, idx = geo.edge_edge(X4[:, 0], X4[:, 1], X4[:, 2], X4[:, 3])
+        d = np.sqrt(d2[0])
+        if not (5e-5 < d < 4.5e-4):
+            continue
+        E, G, H = barrier.pair_derivatives(X4, kind, idx, DHAT, KAPPA)
+        eps = 1e-9
+        g_fd = _fd_pair(X4[0], DHAT, KAPPA, eps)
+        assert np.allclose(G[0], g_fd, rtol=2e-4, atol=2e-4 * np.abs(G[0]).max())
+        gfun = _grad_fn(X4, is_pt)
+        x = X4.reshape(-1)
+        Hfd = np.zeros((12, 12))
+        for i in range(12):
+            e = np.zeros(12)
+            e[i] = eps
+            Hfd[:, i] = (gfun(x + e) - gfun(x - e)) / (2 * eps)
+        assert np.allclose(H[0], Hfd, rtol=1e-4, atol=1e-4 * np.abs(H[0]).max())
+        assert np.allclose(H[0], H[0].T, atol=1e-9 * np.abs(H[0]).max())
+        assert np.allclose(G[0].reshape(4, 3).sum(axis=0), 0, atol=1e-8 * np.abs(G[0]).max())
+        checked += 1
+
+
+def test_psd_projection():
+    rng = np.random.default_rng(2)
+    M = rng.standard_normal((20, 12, 12))
+    M = M + np.swapaxes(M, 1, 2)
+    P = barrier.project_psd(M)
+    for i in range(20):
+        ev = np.linalg.eigvalsh(P[i])
+        assert ev.min() > -1e-12 * np.abs(ev).max()
+        # nearest PSD matrix in Frobenius norm: residual is negative semidefinite
+        assert np.linalg.eigvalsh(M[i] - P[i]).max() < 1e-10
+    Q = np.einsum("kij,klj->kil", M, M)
+    assert np.allclose(barrier.project_psd(Q), Q, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# constraint sets
+# --------------------------------------------------------------------------
+def _brute_sets(x, prox, dhat):
+    pt, ee = [], []
+    for v in prox.verts:
+        for f, tri in enumerate(prox.tris):
+            if v in tri:
+                continue
+            d2 = geo.point_triangle(x[v], x[tri[0]], x[tri[1]], x[tri[2]])[0][0]
+            if d2 < dhat * dhat:
+                pt.append((v, f))
+    E = prox.edges
+    for i in range(len(E)):
+        for j in range(i + 1, len(E)):
+            if len(set(E[i]) & set(E[j])):
+                continue
+            d2 = geo.edge_edge(x[E[i][0]], x[E[i][1]], x[E[j][0]], x[E[j][1]])[0][0]
+            if d2 < dhat * dhat:
+                ee.append((i, j))
+    return np.array(pt, dtype=np.int64).reshape(-1, 2), np.array(ee, dtype=np.int64).reshape(-1, 2)
+
+
+def test_constraint_set_equals_brute_force_on_tiny_mesh():
+    sc = mg.slabs(0, nx=3, ny=3, nz=1, gap=1e-3)
+    prox = contact.make_proxy(sc.surf_tris)
+    rng = np.random.default_rng(4)
+    x = sc.X.copy()
+    upper = x[:, 2] > 0.0105
+    x[upper, 2] -= 7e-4                              # gap 0.3 mm < dhat
+    x += rng.uniform(-1e-4, 1e-4, x.shape)
+    cs = contact.constraint_set(x, prox, DHAT)
+    bpt, bee = _brute_sets(x, prox, DHAT)
+    assert cs.size > 0
+    assert np.array_equal(cs.pt, bpt) and np.array_equal(cs.ee, bee)
+
+
+# --------------------------------------------------------------------------
+# Eq. (4)-(11): the global step
+# --------------------------------------------------------------------------
+def _contact_state(seed=0):
+    sc = mg.slabs(seed, nx=3, ny=3, nz=2, gap=1e-3)
+    prob = solver.setup_scene(sc)
+    x = sc.X.copy()
+    x[x[:, 2] > 0.0205, 2] -= 7e-4
+    x += np.random.default_rng(seed).uniform(-5e-5, 5e-5, x.shape) * (sc.dirichlet[:, None] == 0)
+    return sc, prob, x
+
+
+def test_sparse_lu_step_equals_dense_solve_and_schur_woodbury():
+    sc, prob, x = _contact_state()
+    A = fem.actuation_matrices(sc.act_a * 0.5, sc.act_R)
+    F = local.deformation_gradients(x, prob.tets, prob.B)
+    _, P = local.projections(F, A)
+    cs = contact.constraint_set(x, prob.prox, prob.dhat)
+    assert cs.size > 0
+    _, gB, Bm, _ = solver.barrier_terms(prob, x, cs)
+    g = solver.pd_gradient(prob, F, P) + gB
+    f = prob.free
+    K = (prob.H + Bm).toarray()[np.ix_(f, f)]
+    dx_lu = -spla.splu((prob.H + Bm).tocsc()[f][:, f].tocsc()).solve(g[f])
+    dx_dense = -np.linalg.solve(K, g[f])
+    assert np.allclose(dx_lu, dx_dense, rtol=1e-10, atol=1e-12 * np.abs(dx_dense).max())
+    # Eq. (6)-(8): split free DOFs into x1 (no contact) and x2 (proxy vertices)
+    fv = f[0::3] // 3
+    in2 = sc.region[fv] == 1
+    d1 = (3 * fv[~in2][:, None] + np.arange(3)).reshape(-1)
+    d2 = (3 * fv[in2][:, None] + np.arange(3)).reshape(-1)
+    H = prob.H.toarray()
+    Bd = Bm.toarray()
+    assert np.abs(Bd[np.ix_(d1, d1)]).max() == 0 and np.abs(Bd[np.ix_(d1, d2)]).max() == 0
+    H11, H12, H21, H22 = H[np.ix_(d1, d1)], H[np.ix_(d1, d2)], H[np.ix_(d2, d1)], H[np.ix_(d2, d2)]
+    r1, r2 = -g[d1], -g[d2]
+    L1 = np.linalg.cholesky(H11)
+    Sig = H22 - H21 @ np.linalg.solve(H11, H12)
+    B22 = Bd[np.ix_(d2, d2)]
+    # Eq. (7): block factorisation reproduces the permuted matrix
+    Lb = np.block([[L1, np.zeros_like(H12)], [H21 @ np.linalg.inv(L1).T, np.eye(len(d2))]])
+    Db = np.block([[np.eye(len(d1)), np.zeros_like(H12)], [np.zeros_like(H21), Sig + B22]])
+    Ub = np.block([[L1.T, np.linalg.solve(L1, H12)], [np.zeros_like(H21), np.eye(len(d2))]])
+    Kp = np.block([[H11, H12], [H21, H22 + B22]])
+    assert np.allclose(Lb @ Db @ Ub, Kp, rtol=1e-10, atol=1e-10 * np.abs(Kp).max())
+    # Eq. (11) on the affected DOFs, in the form without B-check inverse
+    c_rows = np.nonzero(np.abs(B22).sum(axis=1) > 0)[0]
+    Bc = B22[np.ix_(c_rows, c_rows)]
+    Sinv = np.linalg.inv(Sig)
+    rt2 = r2 - H21 @ np.linalg.solve(H11, r1)
+    z = Sinv @ rt2
+    C = Sinv[np.ix_(c_rows, c_rows)]
+    u = np.linalg.solve(np.linalg.inv(C) + Bc, np.linalg.solve(C, z[c_rows]))
+    dx2 = z - Sinv[:, c_rows] @ (Bc @ u)
+    dx1 = np.linalg.solve(H11, r1 - H12 @ dx2)
+    full = np.zeros(3 * sc.n)
+    full[d1], full[d2] = dx1, dx2
+    assert np.allclose(full[f], dx_dense, rtol=1e-8, atol=1e-9 * np.abs(dx_dense).max())
+    # Sigma^-1 equals the (2,2) block of the inverse PD matrix
+    Hff_inv = np.linalg.inv(np.block([[H11, H12], [H21, H22]]))
+    assert np.allclose(Sinv, Hff_inv[len(d1):, len(d1):], rtol=1e-8, atol=1e-8 * np.abs(Sinv).max())
+
+
+# --------------------------------------------------------------------------
+# CCD
+# --------------------------------------------------------------------------
+def test_ccd_point_approaching_static_triangle():
+    tri = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.0]])
+    d0, v = 4e-4, 1e-3
+    x = np.concatenate([tri, [[0.002, 0.003, d0]]])
+    dx = np.zeros_like(x)
+    dx[3, 2] = -v
+    prox = contact.Proxy(verts=np.array([3]), tris=np.array([[0, 1, 2]]), edges=np.zeros((0, 2), np.int64))
+    t = ccd.pair_step_bounds(x, dx, prox, np.array([[3, 0]]), np.zeros((0, 2), np.int64))
+    assert np.isclose(t[0], min(1.0, (1 - ccd.ETA) * d0 / v), rtol=1e-12)
+    dx[3, 2] = -1e-5
+    t = ccd.pair_step_bounds(x, dx, prox, np.array([[3, 0]]), np.zeros((0, 2), np.int64))
+    assert t[0] == 1.0
+
+
+def test_ccd_keeps_every_pair_above_target_gap():
+    sc, prob, x = _contact_state(1)
+    rng = np.random.default_rng(8)
+    dx = rng.standard_normal(x.shape) * 1e-3 * (sc.dirichlet[:, None] == 0)
+    alpha_m, spt, see = ccd.step_bound(x, dx, prob.prox, prob.dhat)
+    assert 0 < alpha_m < 1
+    X4 = contact.pair_points(x, prob.prox, spt, see)
+    d0 = np.sqrt(contact.pair_distances(x, prob.prox, spt, see)[0])
+    for s in np.linspace(0, 1, 41):
+        d = np.sqrt(contact.pair_distances(x + s * alpha_m * dx, prob.prox, spt, see)[0])
+        assert np.all(d >= ccd.ETA * d0 * (1 - 1e-9))
+    assert X4.shape[0] > 0
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1: whole-frame invariants
+# --------------------------------------------------------------------------
+def test_zero_actuation_returns_rest_shape():
+    sc = mg.slabs(0, nx=3, ny=3, nz=1)
+    prob = solver.setup_scene(sc)
+    A = fem.actuation_matrices(np.zeros(sc.m), sc.act_R)
+    r = solver.frame(prob, sc.X, A, iters=3)
+    assert np.abs(r.x - sc.X).max() < 1e-15
+    rng = np.random.default_rng(0)
+    x0 = sc.X + 2e-4 * rng.standard_normal(sc.X.shape) * (sc.dirichlet[:, None] == 0)
+    r = solver.frame(prob, x0, A, tol=1e-13, max_iters=300)
+    assert np.abs(r.x - sc.X).max() < 1e-11
+
+
+def _plain_pd(prob, x, A, iters):
+    """Plain projective dynamics: x <- H^-1 sum w G^T p on the free DOFs (Eq. 2)."""
+    f = prob.free
+    lu = spla.splu(prob.H.tocsc()[f][:, f].tocsc())
+    x = x.copy().reshape(-1)
+    fixed = np.setdiff1d(np.arange(x.size), f)
+    for _ in range(iters):
+        F = local.deformation_gradients(x.reshape(-1, 3), prob.tets, prob.B)
+        _, P = local.projections(F, A)
+        rhs = np.zeros(x.size)
+        ge = prob.w[:, None] * np.einsum("mki,mk->mi", prob.G, P.reshape(-1, 9))
+        np.add.at(rhs, fem.local_dofs(prob.tets).reshape(-1), ge.reshape(-1))
+        rhs_f = rhs[f] - prob.H.tocsc()[f][:, fixed] @ x[fixed]
+        x[f] = lu.solve(rhs_f)
+    return x.reshape(-1, 3)
+
+
+def test_no_contact_equals_plain_pd():
+    sc = mg.slabs(0, nx=3, ny=3, nz=1, gap=0.02)
+    prob = solver.setup_scene(sc)
+    A = fem.actuation_matrices(0.3 * sc.act_a, sc.act_R)
+    r = solver.frame(prob, sc.X, A, iters=6)
+    assert max(r.n_pt) == 0 and max(r.n_ee) == 0 and all(a == 1.0 for a in r.alpha)
+    ref = _plain_pd(prob, sc.X, A, 6)
+    assert np.abs(r.x - ref).max() < 1e-12 * np.abs(sc.X).max()
+
+
+def test_frames_stay_intersection_free_and_energy_decreases():
+    sc = mg.slabs(0, nx=4, ny=4, nz=1, gap=1e-3)
+    prob = solver.setup_scene(sc)
+    x = sc.X.copy()
+    for t in (0.5, 1.0):
+        A = fem.actuation_matrices(t * sc.act_a, sc.act_R)
+        r = solver.frame(prob, x, A, iters=8, trace=True)
+        for rec in r.trace:
+            assert 0 < rec.alpha <= rec.alpha_m <= 1
+        x = r.x
+        dmin = contact.min_distance(x, prob.prox)
+        assert dmin > 0
+    assert max(r.n_pt) > 0
