@@ -1,0 +1,156 @@
+"""Frame-solve throughput of the PD+IPC solver on one MI355X.
+
+A "step" is one frame of the quasi-static solver: a fixed number of
+Algorithm-1 iterations (local step, constraint set, barrier, global step,
+CCD, line search) on the face-like 50k-vertex workload.  The headline value is
+the mixed-precision path's frames/s; the plain FP64 path is timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload face50k]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# kernel families of the library's event timer
+K_LOCAL, K_SIGMA_GEMV, K_FWD, K_BWD, K_BARRIER, K_TRIAL, K_RED_CHOL = 0, 1, 2, 3, 4, 5, 6
+
+HBM_PEAK_GBS = 8000.0
+
+
+def local_step_bytes(n: int, m: int) -> int:
+    """Algorithmic bytes of one local-step launch (FP64 streams).
+
+    Per tet: 4 int32 indices, 9 D_m^-1 + 1 weight + 6 actuation doubles in;
+    9 rotation + 1 energy + 12 gradient-share doubles out.  Per vertex: one
+    xyz triple read once.
+    """
+    per_tet = 4 * 4 + (9 + 1 + 6) * 8 + (9 + 1 + 12) * 8
+    return m * per_tet + n * 24
+
+
+def run_precision(sc, precision, steps, warmup, timer_kernel):
+    import torch
+    from paper_2312_02999_amd import Solver
+    S = Solver(sc, iters=sc.iters, precision=precision)
+    dev = "cuda"
+    R = torch.from_numpy(np.ascontiguousarray(sc.act_R.reshape(-1, 9))).to(dev)
+    seq = [torch.from_numpy(np.ascontiguousarray(sc.actuation_at((t + 1) / sc.frames))).to(dev)
+           for t in range(sc.frames)]
+    x = torch.from_numpy(np.ascontiguousarray(sc.X)).to(dev)
+    S.set_actuation_scalar(seq[0], R)
+    t = 0
+    for _ in range(warmup):
+        S.set_actuation_scalar(seq[min(t, len(seq) - 1)])
+        x = S.solve_frame(x)
+        t += 1
+    S.kernel_timer(timer_kernel)
+    lat = []
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.set_actuation_scalar(seq[min(t, len(seq) - 1)])
+        a = time.perf_counter()
+        x, st = S.solve_frame(x, stats=True)
+        lat.append(time.perf_counter() - a)
+        stats.append(st)
+        t += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, k_count = S.kernel_timer(-1)
+    sizes = S.sizes()
+    S.close()
+    lat_ms = np.array(lat) * 1e3
+    return {
+        "fps": steps / wall, "ms_per_frame": 1e3 * wall / steps,
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "kernel_ms_total": k_ms, "kernel_launches": k_count, "sizes": sizes,
+        "n_c_max": max(s["n_c"] for s in stats), "n_pt_last": stats[-1]["n_pt"], "n_ee_last": stats[-1]["n_ee"],
+        "ls_failures": sum(s["ls_failures"] for s in stats),
+        "stage_ms": {k: float(np.mean([s[k] for s in stats])) for k in ("ms_ipc", "ms_gstep", "ms_ls", "ms_misc")},
+        "x_final": x.cpu().numpy(),
+    }
+
+
+def cpu_baseline(sc, budget_s=20.0):
+    """The oracle (as it stands) on a bounded sample: whole Algorithm-1
+    iterations from the rest state at full actuation until ~budget_s."""
+    from oracle import fem, solver as osolver
+    prob = osolver.setup_scene(sc)
+    A = fem.actuation_matrices(sc.act_a, sc.act_R)
+    x = sc.X.copy()
+    t0 = time.perf_counter()
+    its = 0
+    while True:
+        x, _, _ = osolver.iteration(prob, x, A)
+        its += 1
+        if time.perf_counter() - t0 > budget_s or its >= 4:
+            break
+    sec_per_it = (time.perf_counter() - t0) / its
+    return {"value": 1.0 / (sec_per_it * sc.iters), "unit": "frames/s", "cores": os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{its} oracle iteration(s) of the {sc.n}-vertex workload from rest at full actuation, "
+                      f"scaled to {sc.iters} iterations/frame ({sec_per_it:.2f} s/iteration)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="face50k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the solver has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import meshgen as mg
+    from paper_2312_02999_amd import FP64, MIXED_FP32
+
+    sc = mg.scene_by_name(args.workload)
+    fp64 = run_precision(sc, FP64, args.steps, args.warmup, K_LOCAL)
+    mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup, K_LOCAL)
+    diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
+    mixed_vs_fp64 = float(np.abs(mixed["x_final"] - fp64["x_final"]).max() / diag)
+
+    avg_ms = fp64["kernel_ms_total"] / max(fp64["kernel_launches"], 1)
+    nbytes = local_step_bytes(sc.n, sc.m)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": "local_step_kernel<double>", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": fp64["kernel_launches"],
+            "algorithmic_bytes": nbytes}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(sc)
+    out = {
+        "metric": "PD+IPC frames/s on 50k-vert mesh, mixed vs FP64 GPU; p50/p99 latency",
+        "value": round(mixed["fps"], 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mixed["ms_per_frame"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: face-like shell n={sc.n} m={sc.m}, {sc.iters} iterations/frame, "
+                               f"{sc.frames}-frame actuation ramp",
+                   "n1": fp64["sizes"]["n1"], "n2": fp64["sizes"]["n2"], "factor_nnz": fp64["sizes"]["factor_nnz"]},
+        "p50_ms": round(mixed["p50_ms"], 3), "p99_ms": round(mixed["p99_ms"], 3),
+        "fp64": {"value": round(fp64["fps"], 3), "ms_per_step": round(fp64["ms_per_frame"], 3),
+                 "p50_ms": round(fp64["p50_ms"], 3), "p99_ms": round(fp64["p99_ms"], 3),
+                 "stage_ms": fp64["stage_ms"], "n_c_max": fp64["n_c_max"], "ls_failures": fp64["ls_failures"]},
+        "mixed": {"stage_ms": mixed["stage_ms"], "n_c_max": mixed["n_c_max"], "ls_failures": mixed["ls_failures"],
+                  "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * pdipc.h -- C ABI of the MI355X PD+IPC quasi-static solver.
+ *
+ * The library solves the actuated soft-body problem of "Efficient Incremental
+ * Potential Contact for Actuated Face Simulation" (Li, Yang, Solenthaler,
+ * SIGGRAPH Asia 2023 Technical Communications): given an equilibrium x_t and a
+ * per-element symmetric actuation A_i, it returns x_{t+1} by Algorithm 1
+ * (projective-dynamics local step, IPC constraint set and barrier, global step
+ * of Eq. (4) via the Schur complement of Eq. (6)-(8) and the low-rank update
+ * of Eq. (9)-(11), CCD step bound, back-tracking line search).
+ *
+ * Conventions
+ *  - All functions are extern "C", never throw, and return int32_t status:
+ *    0 = OK, < 0 = error (nothing written), > 0 = warning (result written).
+ *  - "device" pointers are HIP device addresses on the solver's device (for
+ *    example torch.cuda tensors' data_ptr()); "host" pointers are CPU memory.
+ *  - Vertex arrays are n x 3 row-major float64 (x, y, z per vertex).
+ *  - Work is ordered on the stream given in pdipc_options.stream (NULL = the
+ *    default stream); every call returns after its work has completed.
+ *  - A solver handle is not re-entrant: calls on one handle must not overlap.
+ *    Different handles are independent.
+ *  - The library owns every device buffer it allocates; the caller owns every
+ *    buffer it passes in.  Mesh data is copied at pdipc_init_mesh.
+ */
+#ifndef PDIPC_H
+#define PDIPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PDIPC_OK = 0,
+  PDIPC_E_INVALID = -1,      /* bad argument, index out of range, NaN input   */
+  PDIPC_E_DEGENERATE = -2,   /* a tet with rest volume <= 0                   */
+  PDIPC_E_NOT_SPD = -3,      /* PD matrix or reduced contact system not SPD   */
+  PDIPC_E_NOMEM = -4,        /* device or host allocation failed              */
+  PDIPC_E_INTERSECTING = -5, /* input state has a contact pair at distance 0  */
+  PDIPC_E_HIP = -6,          /* a HIP runtime call failed                     */
+  PDIPC_W_LS_FAILED = 1,     /* some line search found no decrease (alpha=0)  */
+  PDIPC_W_NOT_CONVERGED = 2  /* tolerance mode hit the iteration cap          */
+};
+
+enum { PDIPC_FP64 = 0, PDIPC_MIXED_FP32 = 1 };
+
+/*
+ * Mesh description (Section 2 of the paper: tetrahedral simulation mesh,
+ * embedded collision proxy s = W x, manually marked collision region x2).
+ * All pointers are host memory and are only read during pdipc_init_mesh.
+ *  rest_pos    n_verts x 3   rest positions X [m]
+ *  tets        n_tets x 4    vertex ids; every tet must have det[X1-X0,
+ *                            X2-X0, X3-X0] > 0 (else PDIPC_E_DEGENERATE)
+ *  dirichlet   n_verts       1 = vertex fixed at its rest position (needs at
+ *                            least one, else the PD matrix is singular)
+ *  surf_tris   n_surf_tris x 3  proxy triangles as simulation vertex ids (the
+ *                            proxy is embedded by selection: W picks vertices)
+ *  region      n_verts or NULL  1 = collision-aware vertex (block x2 of Eq. 6);
+ *                            NULL = the free vertices of the proxy.  Every free
+ *                            proxy vertex must be marked (else PDIPC_E_INVALID).
+ *  youngs, poisson           element weight w_i = 2 mu V_i, mu = E/(2(1+nu))
+ */
+typedef struct {
+  int32_t n_verts, n_tets;
+  const double* rest_pos;
+  const int32_t* tets;
+  const uint8_t* dirichlet;
+  int32_t n_surf_tris;
+  const int32_t* surf_tris;
+  const uint8_t* region;
+  double youngs, poisson;
+} pdipc_mesh_desc;
+
+/*
+ * Solver options.
+ *  dhat, kappa     barrier threshold d_0 and stiffness (Eq. 3)
+ *  iters           iterations per frame (fixed mode) or cap (tolerance mode)
+ *  tol             > 0: stop when max |alpha dx| <= tol; <= 0: fixed iters
+ *  precision       PDIPC_FP64 or PDIPC_MIXED_FP32 (FP32 local/barrier passes and
+ *                  FP32 reduced system, refined against FP64 residuals)
+ *  ccd_eta         CCD target gap as a fraction of the current distance
+ *  ccd_steps       conservative-advancement steps per pair
+ *  ls_max_halvings line-search halvings before giving up (alpha = 0)
+ *  stream          hipStream_t to order work on (NULL = default stream)
+ */
+typedef struct {
+  double dhat, kappa;
+  int32_t iters;
+  double tol;
+  int32_t precision;
+  double ccd_eta;
+  int32_t ccd_steps, ls_max_halvings;
+  void* stream;
+} pdipc_options;
+
+/* Per-frame statistics (host).  Stage times follow the paper's Table 1
+ * columns: IPC (constraint set + barrier derivatives), G-Step (global solve),
+ * CCD, LS (line search), Misc (local step, assembly, bookkeeping). */
+typedef struct {
+  int32_t iters, n_pt, n_ee, n_c, ls_halvings, ls_failures, refine_steps;
+  int32_t n_candidates;
+  double alpha_m_min, alpha_min, energy, grad_inf;
+  double ms_ipc, ms_gstep, ms_ccd, ms_ls, ms_misc, ms_total;
+} pdipc_frame_stats;
+
+/* Fill *opt with defaults: dhat 5e-4, kappa 1e3, 30 iters, fixed mode, FP64,
+ * eta 0.1, 16 CCD steps, 20 halvings, default stream. */
+void pdipc_default_options(pdipc_options* opt);
+
+/* Build a solver: validate the mesh, precompute per-tet data, assemble the
+ * constant PD matrix H of Eq. (2), order the x1 block by nested dissection,
+ * factor H11 = L1 L1^T (Section 3.1) and form the inverse Schur complement
+ * Sigma^-1 (Section 3.2).  On success *out owns all device state. */
+int32_t pdipc_init_mesh(const pdipc_mesh_desc* mesh, const pdipc_options* opt, void** out);
+
+/* Set per-element actuation A_i (Eq. 1) from its 6 symmetric entries.
+ * A: device, n_tets x 6 float64, (xx, yy, zz, xy, yz, zx) per tet. */
+int32_t pdipc_set_actuation(void* solver, const double* A);
+
+/* Set A_i = R_i diag(1 - a_i, 1 + a_i/2, 1 + a_i/2) R_i^T.
+ * a: device n_tets float64; R: device n_tets x 9 float64 row-major, or NULL
+ * to keep the frames from the previous call.  The backward pass
+ * differentiates with respect to a. */
+int32_t pdipc_set_actuation_scalar(void* solver, const double* a, const double* R);
+
+/* One frame of Algorithm 1: x_out = x_{t+1} from x_in = x_t.
+ * x_in, x_out: device n_verts x 3 float64 (may alias).  Fixed vertices are
+ * taken from x_in.  stats: host, may be NULL.
+ * Errors: PDIPC_E_INTERSECTING if x_in has a pair at distance 0;
+ * PDIPC_E_NOT_SPD if the reduced system fails to factor. */
+int32_t pdipc_solve_frame(void* solver, const double* x_in, double* x_out, pdipc_frame_stats* stats);
+
+/* Adjoint of the last converged frame with respect to the per-tet actuation
+ * scalars (set through pdipc_set_actuation_scalar): given dL/dx* (device,
+ * n_verts x 3), writes dL/da (device, n_tets).  Solves K lambda = dL/dx* with
+ * K the Hessian of the total energy at x* (Eq. 1 and Eq. 3 terms). */
+int32_t pdipc_solve_frame_backward(void* solver, const double* dL_dx, double* dL_da);
+
+/* Sizes of the blocks after init: n1, n2 of Eq. (6) and nnz of the factor. */
+int32_t pdipc_get_sizes(const void* solver, int64_t* n1, int64_t* n2, int64_t* factor_nnz);
+
+/* Measurement tap: read and reset the HIP-event timer, then arm it for the
+ * kernel family `which` (-1 = off): 0 local step, 1 Sigma^-1 GEMV, 2 lower
+ * sweep, 3 upper sweep, 4 barrier, 5 line-search energies, 6 reduced
+ * Cholesky, 8 CCD.  Events are recorded on the solver's stream around every
+ * launch of that family during pdipc_solve_frame; *total_ms and *launches
+ * (host, nullable) return what was accumulated since the previous call. */
+int32_t pdipc_kernel_timer(void* solver, int32_t which, double* total_ms, int64_t* launches);
+
+/* Release everything the solver owns. NULL is allowed. */
+void pdipc_destroy(void* solver);
+
+/* Last error message of a handle (or of the last failed init if NULL). */
+const char* pdipc_last_error(const void* solver);
+
+/* ---- debug / parity taps (device pointers, sizes from pdipc_get_sizes) ----
+ * pdipc_debug_local: run only the local step at x (device n x 3): writes
+ *   R (device m x 9 row-major) and element energies (device m), and the PD
+ *   gradient sum_i w_i G_i^T (G_i x - p_i) (device n x 3, zero at fixed).
+ * pdipc_debug_contacts: constraint set at x: writes up to cap pairs as
+ *   (type, i, j) int32 triples into pairs (device), returns the count in
+ *   *count (host).  type 0 = point-triangle (sim vertex, proxy triangle),
+ *   type 1 = edge-edge (edge, edge) with edges sorted (lo, hi).
+ * pdipc_debug_step: one full iteration from x; writes dx (device n x 3) and
+ *   the host scalars alpha_m, alpha. */
+int32_t pdipc_debug_local(void* solver, const double* x, double* R, double* energies, double* grad);
+int32_t pdipc_debug_contacts(void* solver, const double* x, int32_t* pairs, int32_t cap, int32_t* count);
+int32_t pdipc_debug_step(void* solver, const double* x, double* dx, double* alpha_m, double* alpha);
+
+/* Host-only check of the set-up factorization (no device work, usable
+ * without a GPU).  Input: the scalar PD matrix over free vertices in
+ * extended order (x1 block [0, n1) with coordinates coords1 (n1 x 3), then
+ * x2 block) as full-pattern CSR (ptr: n1 + n2 + 1 int64, col int32, val);
+ * leaf = nested-dissection leaf size.  Solves H x = b (host vectors of
+ * n1 + n2) through the supernodal factor and a dense host Cholesky of the
+ * Schur complement, writes Sigma_s (n2 x n2 row-major, host) and the factor
+ * size.  b/x/sigma_out/nnz_out may be NULL to skip. */
+int32_t pdipc_debug_host_factor(int32_t n1, int32_t n2, const double* coords1, const int64_t* ptr,
+                                const int32_t* col, const double* val, int32_t leaf, const double* b, double* x,
+                                double* sigma_out, int64_t* nnz_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDIPC_H */

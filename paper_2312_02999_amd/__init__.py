@@ -1,0 +1,156 @@
+"""MI355X-native PD+IPC quasi-static solver (Li, Yang, Solenthaler 2023).
+
+Python front-end of the C ABI in ``include/pdipc.h``.  torch is used only for
+device memory and streams: every step of a frame runs in the HIP kernels of
+``libpdipc.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FrameStats, MeshDesc, Options, PdipcError, check, lib
+
+__all__ = ["Solver", "PdipcError", "FP64", "MIXED_FP32", "host_factor_solve", "actuation_rows"]
+
+FP64, MIXED_FP32 = 0, 1
+
+
+def _dev(t: torch.Tensor, shape=None) -> int:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA (ROCm) tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def actuation_rows(A: np.ndarray) -> np.ndarray:
+    """(m, 3, 3) symmetric -> (m, 6) rows (xx, yy, zz, xy, yz, zx)."""
+    return np.stack([A[:, 0, 0], A[:, 1, 1], A[:, 2, 2], A[:, 0, 1], A[:, 1, 2], A[:, 2, 0]], axis=1)
+
+
+class Solver:
+    """One mesh, its constant factor and its device state.
+
+    Arguments follow ``pdipc_mesh_desc`` / ``pdipc_options``; ``scene`` may be
+    any object with the attributes of ``meshgen.Scene``.
+    """
+
+    def __init__(self, scene=None, *, X=None, tets=None, dirichlet=None, surf_tris=None, region=None,
+                 youngs=1e4, poisson=0.45, dhat=5e-4, kappa=1e3, iters=30, tol=0.0, precision=FP64,
+                 ccd_eta=0.1, ccd_steps=16, ls_max_halvings=20, device="cuda", stream=None):
+        if scene is not None:
+            X, tets, dirichlet, surf_tris = scene.X, scene.tets, scene.dirichlet, scene.surf_tris
+            region = scene.region
+            youngs, poisson, dhat, kappa = scene.youngs, scene.poisson, scene.dhat, scene.kappa
+        self.device = torch.device(device)
+        self._X = np.ascontiguousarray(X, dtype=np.float64)
+        self._tets = np.ascontiguousarray(tets, dtype=np.int32)
+        self._dir = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        self._tris = np.ascontiguousarray(surf_tris, dtype=np.int32).reshape(-1, 3)
+        self._reg = None if region is None else np.ascontiguousarray(region, dtype=np.uint8)
+        self.n, self.m = self._X.shape[0], self._tets.shape[0]
+        md = MeshDesc(self.n, self.m, self._X.ctypes.data, self._tets.ctypes.data, self._dir.ctypes.data,
+                      self._tris.shape[0], self._tris.ctypes.data if self._tris.size else None,
+                      self._reg.ctypes.data if self._reg is not None else None, float(youngs), float(poisson))
+        with torch.cuda.device(self.device):
+            st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        op = Options(float(dhat), float(kappa), int(iters), float(tol), int(precision), float(ccd_eta),
+                     int(ccd_steps), int(ls_max_halvings), C.c_void_p(st.cuda_stream))
+        h = C.c_void_p()
+        check(lib().pdipc_init_mesh(C.byref(md), C.byref(op), C.byref(h)), None)
+        self._h = h
+        self.iters = iters
+
+    # ------------------------------------------------------------------ API
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pdipc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().pdipc_get_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)), self._h)
+        return {"n1": a.value, "n2": b.value, "factor_nnz": c.value}
+
+    def set_actuation(self, A: torch.Tensor):
+        check(lib().pdipc_set_actuation(self._h, _dev(A, (self.m, 6))), self._h)
+
+    def set_actuation_scalar(self, a: torch.Tensor, R: torch.Tensor | None = None):
+        rp = _dev(R, (self.m, 9)) if R is not None else None
+        check(lib().pdipc_set_actuation_scalar(self._h, _dev(a, (self.m,)), rp), self._h)
+
+    def solve_frame(self, x_in: torch.Tensor, x_out: torch.Tensor | None = None, stats: bool = False):
+        if x_out is None:
+            x_out = torch.empty_like(x_in)
+        fs = FrameStats()
+        rc = lib().pdipc_solve_frame(self._h, _dev(x_in, (self.n, 3)), _dev(x_out, (self.n, 3)),
+                                     C.byref(fs) if stats else None)
+        check(rc, self._h)
+        self.last_status = rc
+        return (x_out, fs.as_dict()) if stats else x_out
+
+    def solve_frame_backward(self, dL_dx: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        check(lib().pdipc_solve_frame_backward(self._h, _dev(dL_dx, (self.n, 3)), _dev(out)), self._h)
+        return out
+
+    def kernel_timer(self, which: int = -1):
+        """Return (total_ms, launches) since the last call and arm the timer for ``which``."""
+        t, c = C.c_double(), C.c_int64()
+        check(lib().pdipc_kernel_timer(self._h, int(which), C.byref(t), C.byref(c)), self._h)
+        return t.value, c.value
+
+    # ------------------------------------------------------------ debug taps
+    def debug_local(self, x: torch.Tensor):
+        R = torch.empty(self.m, 9, dtype=torch.float64, device=self.device)
+        E = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.n, 3, dtype=torch.float64, device=self.device)
+        check(lib().pdipc_debug_local(self._h, _dev(x, (self.n, 3)), _dev(R), _dev(E), _dev(g)), self._h)
+        return R, E, g
+
+    def debug_contacts(self, x: torch.Tensor, cap: int = 1 << 20):
+        cnt = C.c_int32()
+        check(lib().pdipc_debug_contacts(self._h, _dev(x, (self.n, 3)), None, 0, C.byref(cnt)), self._h)
+        k = cnt.value
+        buf = torch.empty(max(k, 1) * 3, dtype=torch.int32, device=self.device)
+        check(lib().pdipc_debug_contacts(self._h, _dev(x, (self.n, 3)), buf.data_ptr(), k, C.byref(cnt)), self._h)
+        return buf[: 3 * k].reshape(k, 3).cpu().numpy()
+
+    def debug_step(self, x: torch.Tensor):
+        dx = torch.empty(self.n, 3, dtype=torch.float64, device=self.device)
+        am, a = C.c_double(), C.c_double()
+        check(lib().pdipc_debug_step(self._h, _dev(x, (self.n, 3)), _dev(dx), C.byref(am), C.byref(a)), self._h)
+        return dx, am.value, a.value
+
+
+def host_factor_solve(n1: int, n2: int, coords1, ptr, col, val, b=None, leaf: int = 96):
+    """Host-only factor check (no GPU): returns (x, Sigma_s, factor_nnz)."""
+    coords1 = np.ascontiguousarray(coords1, dtype=np.float64)
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    N = n1 + n2
+    sig = np.zeros((n2, n2))
+    nnz = C.c_int64()
+    x = None
+    bp = xp = None
+    if b is not None:
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(N)
+        bp, xp = b.ctypes.data, x.ctypes.data
+    rc = lib().pdipc_debug_host_factor(n1, n2, coords1.ctypes.data, ptr.ctypes.data, col.ctypes.data,
+                                       val.ctypes.data, leaf, bp, xp, sig.ctypes.data if n2 else None,
+                                       C.byref(nnz))
+    check(rc, None)
+    return x, sig, nnz.value

@@ -1,0 +1,431 @@
+// Barrier energy, gradient and positive-semidefinite Hessian per active pair
+// (Eq. 3 and the PositiveDefinite step of Algorithm 1).
+//
+// Derivatives of the squared distance D come from the closest-feature form
+// D(x) = min_beta |q(x, beta)|^2, q = sum_j c_j(beta) P_j with c affine in
+// beta.  At the minimiser (envelope and implicit-function theorems):
+//   grad D  = f_x = 2 C^T q
+//   hess D  = f_xx - f_xb f_bb^-1 f_bx,  f_xx = 2 C^T C,  f_bb = 2 D_k.D_l,
+//   f_xb_k  = 2 (dC/dbeta_k)^T q + 2 C^T D_k,   D_k = sum_j dc_j/dbeta_k P_j.
+// The barrier Hessian kappa (phi'' gradD gradD^T + phi' hessD), with
+// phi(D) = b(sqrt D), has its range inside span{C^T e_r, f_xb_k} (at most 5
+// dimensions), so the clamp of negative eigenvalues is done exactly on the
+// projection onto an orthonormal basis of that span: a <= 5x5 Jacobi
+// eigen-problem instead of 12x12.  Output is the factor U (12 x 5) with
+// projected Hessian U U^T.
+#include "common.h"
+#include "geom.h"
+#include "kernels.h"
+
+namespace pdipc {
+
+namespace {
+constexpr int BT = 128;
+}
+
+template <typename T>
+__device__ void sym_eig_jacobi(T A[5][5], T V[5][5], int n) {
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) V[i][j] = i == j ? T(1) : T(0);
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    T off = T(0), dia = T(0);
+    for (int i = 0; i < n; ++i) {
+      dia += A[i][i] * A[i][i];
+      for (int j = i + 1; j < n; ++j) off += A[i][j] * A[i][j];
+    }
+    if (off == T(0) || off <= T(sizeof(T) == 8 ? 1e-32 : 1e-18) * dia) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        T apq = A[p][q];
+        if (apq == T(0)) continue;
+        T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
+        T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+        T c = T(1) / sqrt(t * t + T(1));
+        T s = t * c;
+        for (int k = 0; k < n; ++k) {
+          T akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          T apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          T vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+template <typename T>
+__device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, double kappa, double& energy,
+                             double grad[12], double U[12][5]) {
+  T P[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) P[a][r] = static_cast<T>(Pd[a][r]);
+  Feature<T> f;
+  pair_feature<T>(is_pt, P, f);
+  T q[3] = {T(0), T(0), T(0)}, Dk[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      q[r] += f.c[j] * P[j][r];
+      Dk[0][r] += f.dcdb[0][j] * P[j][r];
+      Dk[1][r] += f.dcdb[1][j] * P[j][r];
+    }
+  const T D = dot3(q, q);
+  const T d = sqrt(D);
+  const T th = static_cast<T>(dhat);
+  const T e = d - th;
+  const T lg = log(d / th);
+  const T b0 = -e * e * lg;
+  const T b1 = -T(2) * e * lg - e * e / d;
+  const T b2 = -T(2) * lg - T(4) * e / d + e * e / (d * d);
+  const T kap = static_cast<T>(kappa);
+  const T phi1 = kap * b1 / (T(2) * d);
+  const T phi2 = kap * (b2 - b1 / d) / (T(4) * D);
+  energy = static_cast<double>(kap * b0);
+  // grad D and its use as the barrier gradient
+  T gD[12];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) gD[3 * j + r] = T(2) * f.c[j] * q[r];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) grad[i] = static_cast<double>(phi1 * gD[i]);
+  // f_xb columns and f_bb
+  const int nb = f.nb;
+  T fxb[2][12];
+  for (int k = 0; k < nb; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) fxb[k][3 * j + r] = T(2) * f.dcdb[k][j] * q[r] + T(2) * f.c[j] * Dk[k][r];
+  T fbb[2][2] = {{T(0), T(0)}, {T(0), T(0)}}, fbbi[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+  for (int k = 0; k < nb; ++k)
+    for (int l = 0; l < nb; ++l) fbb[k][l] = T(2) * dot3(Dk[k], Dk[l]);
+  if (nb == 1) {
+    fbbi[0][0] = T(1) / fbb[0][0];
+  } else if (nb == 2) {
+    T det = fbb[0][0] * fbb[1][1] - fbb[0][1] * fbb[1][0];
+    fbbi[0][0] = fbb[1][1] / det;
+    fbbi[1][1] = fbb[0][0] / det;
+    fbbi[0][1] = -fbb[0][1] / det;
+    fbbi[1][0] = -fbb[1][0] / det;
+  }
+  // orthonormal basis Q (columns) of span{C^T e_r, f_xb_k}
+  T Q[5][12];
+  int nq = 0;
+  T cn = sqrt(f.c[0] * f.c[0] + f.c[1] * f.c[1] + f.c[2] * f.c[2] + f.c[3] * f.c[3]);
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) Q[nq][i] = T(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Q[nq][3 * j + r] = f.c[j] / cn;
+    ++nq;
+  }
+  for (int k = 0; k < nb; ++k) {
+    T v[12];
+    T n0 = T(0);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) { v[i] = fxb[k][i]; n0 += v[i] * v[i]; }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int b = 0; b < nq; ++b) {
+        T pr = T(0);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) pr += Q[b][i] * v[i];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) v[i] -= pr * Q[b][i];
+      }
+    T nv = T(0);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) nv += v[i] * v[i];
+    if (nv > T(sizeof(T) == 8 ? 1e-28 : 1e-12) * n0 && nv > T(0)) {
+      T inv = T(1) / sqrt(nv);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) Q[nq][i] = v[i] * inv;
+      ++nq;
+    }
+  }
+  // projected Hessian Ht = Q^T H Q
+  T qg[5], qf[5][2], cq[5][3];
+  for (int a = 0; a < nq; ++a) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s += Q[a][i] * gD[i];
+    qg[a] = s;
+    for (int k = 0; k < nb; ++k) {
+      T t = T(0);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) t += Q[a][i] * fxb[k][i];
+      qf[a][k] = t;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      T t = T(0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t += f.c[j] * Q[a][3 * j + r];
+      cq[a][r] = t;
+    }
+  }
+  T Ht[5][5], V[5][5];
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) Ht[a][b] = T(0);
+  for (int a = 0; a < nq; ++a)
+    for (int b = 0; b < nq; ++b) {
+      T hd = T(2) * dot3(cq[a], cq[b]);
+      for (int k = 0; k < nb; ++k)
+        for (int l = 0; l < nb; ++l) hd -= qf[a][k] * fbbi[k][l] * qf[b][l];
+      Ht[a][b] = phi2 * qg[a] * qg[b] + phi1 * hd;
+    }
+  for (int a = 0; a < nq; ++a)
+    for (int b = a + 1; b < nq; ++b) {
+      T s = T(0.5) * (Ht[a][b] + Ht[b][a]);
+      Ht[a][b] = s;
+      Ht[b][a] = s;
+    }
+  sym_eig_jacobi<T>(Ht, V, nq);
+  T sq[5];
+  for (int a = 0; a < 5; ++a) sq[a] = a < nq && Ht[a][a] > T(0) ? sqrt(Ht[a][a]) : T(0);
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+    for (int e2 = 0; e2 < 5; ++e2) {
+      T s = T(0);
+      for (int a = 0; a < nq; ++a) s += Q[a][i] * V[a][e2];
+      U[i][e2] = static_cast<double>(s * sq[e2]);
+    }
+}
+
+__global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
+                                                     const double* __restrict__ x, double dhat, double kappa,
+                                                     bool fp32, double* __restrict__ energy,
+                                                     double* __restrict__ grad, double* __restrict__ U) {
+  int32_t k = blockIdx.x * BT + threadIdx.x;
+  if (k >= npairs) return;
+  int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
+  double P[4][3];
+  load_pair_rel(v4, x, P);
+  double e, g[12], u[12][5];
+  if (fp32) pair_barrier<float>(P, k < n_pt, dhat, kappa, e, g, u);
+  else pair_barrier<double>(P, k < n_pt, dhat, kappa, e, g, u);
+  energy[k] = e;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) grad[static_cast<int64_t>(i) * npairs + k] = g[i];
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) U[static_cast<int64_t>(5 * i + c) * npairs + k] = u[i][c];
+}
+
+void launch_barrier(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double dhat, double kappa,
+                    bool fp32, BarrierOut& bo, hipStream_t st) {
+  if (npairs <= 0) return;
+  barrier_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dhat, kappa, fp32, bo.energy,
+                                                       bo.grad, bo.U);
+}
+
+// ---- vertex incidence ------------------------------------------------------------
+__global__ void inc_count_kernel(const int32_t* __restrict__ v4, int32_t npairs, int32_t* __restrict__ cnt) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npairs) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) atomicAdd(&cnt[v4[4 * k + a]], 1);
+}
+
+__global__ void inc_fill_kernel(const int32_t* __restrict__ v4, int32_t npairs, int32_t* __restrict__ cursor,
+                                int32_t* __restrict__ ent) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npairs) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int32_t s = atomicAdd(&cursor[v4[4 * k + a]], 1);
+    ent[s] = 4 * k + a;
+  }
+}
+
+// sort each vertex's incidence list; flag free touched vertices
+__global__ void inc_sort_flag_kernel(int32_t n, const int32_t* __restrict__ ptr, int32_t* __restrict__ ent,
+                                     const uint8_t* __restrict__ fixed, int32_t* __restrict__ cflag) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  if (v == n) { cflag[n] = 0; return; }
+  int32_t b = ptr[v], e = ptr[v + 1];
+  for (int32_t i = b + 1; i < e; ++i) {
+    int32_t key = ent[i];
+    int32_t j = i - 1;
+    while (j >= b && ent[j] > key) { ent[j + 1] = ent[j]; --j; }
+    ent[j + 1] = key;
+  }
+  cflag[v] = (e > b && !fixed[v]) ? 1 : 0;
+}
+
+__global__ void clist_kernel(int32_t n, const int32_t* __restrict__ cflag, const int32_t* __restrict__ cidx,
+                             int32_t* __restrict__ clist) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (cflag[v]) clist[cidx[v]] = v;
+}
+
+void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const uint8_t* fixed, Incidence& inc,
+                     void* scan_temp, hipStream_t st) {
+  launch_fill_i32(inc.cnt, n + 1, 0, st);
+  if (npairs > 0) inc_count_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cnt);
+  launch_exclusive_scan(inc.cnt, inc.ptr, n + 1, inc.d_nc, scan_temp, st);
+  hipMemcpyAsync(inc.cursor, inc.ptr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
+  if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.ent);
+  inc_sort_flag_kernel<<<grid_for(n + 1, 256), 256, 0, st>>>(n, inc.ptr, inc.ent, fixed, inc.cflag);
+  launch_exclusive_scan(inc.cflag, inc.cidx, n + 1, inc.d_nc, scan_temp, st);
+  clist_kernel<<<grid_for(n, 256), 256, 0, st>>>(n, inc.cflag, inc.cidx, inc.clist);
+}
+
+// g[v] += sum of pair gradient rows at v (pair-ascending order), free v only
+__global__ void add_barrier_grad_kernel(int32_t nsv, const int32_t* __restrict__ sv, const int32_t* __restrict__ ptr,
+                                        const int32_t* __restrict__ ent, const double* __restrict__ grad,
+                                        int32_t npairs, const uint8_t* __restrict__ fixed, double* __restrict__ g) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsv) return;
+  int32_t v = sv[i];
+  if (fixed[v]) return;
+  int32_t b = ptr[v], e = ptr[v + 1];
+  if (e == b) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int32_t t = b; t < e; ++t) {
+    int32_t k = ent[t] >> 2, a = ent[t] & 3;
+    s0 += grad[static_cast<int64_t>(3 * a) * npairs + k];
+    s1 += grad[static_cast<int64_t>(3 * a + 1) * npairs + k];
+    s2 += grad[static_cast<int64_t>(3 * a + 2) * npairs + k];
+  }
+  g[3 * v] += s0;
+  g[3 * v + 1] += s1;
+  g[3 * v + 2] += s2;
+}
+
+void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
+                             const uint8_t* fixed, double* g, hipStream_t st) {
+  if (npairs <= 0) return;
+  add_barrier_grad_kernel<<<grid_for(px.nsv, 256), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent, bo.grad, npairs,
+                                                                   fixed, g);
+}
+
+// ---- reduced contact system ----------------------------------------------------------
+__global__ void c_to_x2_kernel(int32_t nc, const int32_t* __restrict__ clist, const int32_t* __restrict__ vert2x2,
+                               int32_t* __restrict__ c_x2) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) c_x2[i] = vert2x2[clist[i]];
+}
+void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st) {
+  if (nc > 0) c_to_x2_kernel<<<grid_for(nc, 256), 256, 0, st>>>(nc, clist, vert2x2, c_x2);
+}
+
+// M[3a+r][3b+s] = Cinv[a][b] delta_rs
+__global__ void fill_kron_kernel(int32_t nc, const double* __restrict__ Cinv, double* __restrict__ M) {
+  int64_t N = 3 * static_cast<int64_t>(nc);
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= N * N) return;
+  int64_t row = idx / N, col = idx % N;
+  M[idx] = (row % 3 == col % 3) ? Cinv[(row / 3) * nc + col / 3] : 0.0;
+}
+
+// one thread per (c vertex a): add U_k rows of a times U_k rows of b for every
+// incident pair k and every free local vertex b
+__global__ void add_bcheck_kernel(int32_t nc, const int32_t* __restrict__ clist, const int32_t* __restrict__ ptr,
+                                  const int32_t* __restrict__ ent, const int32_t* __restrict__ v4,
+                                  const int32_t* __restrict__ cflag, const int32_t* __restrict__ cidx,
+                                  const double* __restrict__ U, int32_t npairs, double* __restrict__ M) {
+  int32_t ca = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ca >= nc) return;
+  const int64_t N = 3 * static_cast<int64_t>(nc);
+  int32_t va = clist[ca];
+  for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
+    int32_t k = ent[t] >> 2, la = ent[t] & 3;
+    double Ua[3][5];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Ua[r][c] = U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k];
+    for (int lb = 0; lb < 4; ++lb) {
+      int32_t vb = v4[4 * k + lb];
+      if (!cflag[vb]) continue;
+      int64_t cb = cidx[vb];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        double Ub[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Ub[c] = U[static_cast<int64_t>(5 * (3 * lb + s) + c) * npairs + k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) acc += Ua[r][c] * Ub[c];
+          M[(3 * static_cast<int64_t>(ca) + r) * N + 3 * cb + s] += acc;
+        }
+      }
+    }
+  }
+}
+
+void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairList& pl,
+                             int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st) {
+  int64_t N = 3 * static_cast<int64_t>(nc);
+  fill_kron_kernel<<<grid_for(N * N, 256), 256, 0, st>>>(nc, Cinv, M);
+  add_bcheck_kernel<<<grid_for(nc, 64), 64, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx,
+                                                     bo.U, npairs, M);
+}
+
+// w_k = U_k^T u_local (5 per pair), u indexed by c index of each free local vertex
+__global__ void pair_ut_kernel(int32_t npairs, const int32_t* __restrict__ v4, const int32_t* __restrict__ cflag,
+                               const int32_t* __restrict__ cidx, const double* __restrict__ U,
+                               const double* __restrict__ u, double* __restrict__ w) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npairs) return;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int lb = 0; lb < 4; ++lb) {
+    int32_t vb = v4[4 * k + lb];
+    if (!cflag[vb]) continue;
+    int64_t cb = cidx[vb];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double us = u[3 * cb + s];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += U[static_cast<int64_t>(5 * (3 * lb + s) + c) * npairs + k] * us;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) w[static_cast<int64_t>(c) * npairs + k] = acc[c];
+}
+
+__global__ void bu_gather_kernel(int32_t nc, const int32_t* __restrict__ clist, const int32_t* __restrict__ ptr,
+                                 const int32_t* __restrict__ ent, const double* __restrict__ U,
+                                 const double* __restrict__ w, int32_t npairs, double* __restrict__ v) {
+  int32_t ca = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ca >= nc) return;
+  int32_t va = clist[ca];
+  double s[3] = {0, 0, 0};
+  for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
+    int32_t k = ent[t] >> 2, la = ent[t] & 3;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 5; ++c)
+        s[r] += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] * w[static_cast<int64_t>(c) * npairs + k];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) v[3 * static_cast<int64_t>(ca) + r] = s[r];
+}
+
+void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, int32_t npairs, const BarrierOut& bo,
+                         const uint8_t* fixed, const double* u, double* wtmp, double* v, hipStream_t st) {
+  (void)fixed;
+  if (nc <= 0) return;
+  pair_ut_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(npairs, pl.v4, inc.cflag, inc.cidx, bo.U, u, wtmp);
+  bu_gather_kernel<<<grid_for(nc, 256), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, bo.U, wtmp, npairs, v);
+}
+
+}  // namespace pdipc

@@ -1,0 +1,430 @@
+// Contact detection on the GPU: spatial-hash broad phase, exact box filter,
+// narrow phase (constraint set of Algorithm 1), conservative-advancement CCD
+// and line-search barrier energies.
+//
+// Broad phase.  Every stored primitive (triangle or edge) is inserted into
+// the uniform-grid cells its box covers; a query (proxy vertex or edge) box,
+// widened by dhat, visits its cells.  Each (query, primitive) pair is reported
+// only from its "home" cell (the componentwise max of the two cell ranges'
+// lower corners), and table entries carry their cell key, so hash collisions
+// and multi-cell overlaps never duplicate a pair.  The final test is the
+// exact box predicate lo_a <= hi_b + dhat and lo_b <= hi_a + dhat.
+//
+// Output order is canonical without a global sort: a count pass, an
+// exclusive scan over queries, a fill pass, and a per-query insertion sort.
+#include "common.h"
+#include "geom.h"
+#include "kernels.h"
+
+namespace pdipc {
+
+namespace {
+constexpr int BT = 256;
+
+__device__ __forceinline__ uint32_t cell_hash(int32_t ix, int32_t iy, int32_t iz, uint32_t mask) {
+  uint32_t h = static_cast<uint32_t>(ix) * 73856093u ^ static_cast<uint32_t>(iy) * 19349663u ^
+               static_cast<uint32_t>(iz) * 83492791u;
+  return h & mask;
+}
+__device__ __forceinline__ uint64_t cell_key(int32_t ix, int32_t iy, int32_t iz) {
+  return (static_cast<uint64_t>(ix) & 0x1FFFFF) | ((static_cast<uint64_t>(iy) & 0x1FFFFF) << 21) |
+         ((static_cast<uint64_t>(iz) & 0x1FFFFF) << 42);
+}
+__device__ __forceinline__ int32_t cell_of(double c, double o, double h) {
+  double f = floor((c - o) / h);
+  // non-finite or absurd coordinates map to cell 0 (ranges are clamped below)
+  return (f >= 0.0 && f < 1.0e9) ? static_cast<int32_t>(f) : 0;
+}
+// A box never spans more than 3 cells per axis (cell size >= largest extent
+// gives at most 2); the clamp bounds every loop even for corrupt input.
+__device__ __forceinline__ int32_t clamp_hi(int32_t lo, int32_t hi) {
+  return hi < lo ? lo : (hi > lo + 2 ? lo + 2 : hi);
+}
+}  // namespace
+
+// ---- boxes --------------------------------------------------------------------
+__global__ void __launch_bounds__(BT) boxes_kernel(ProxyDev px, const double* __restrict__ x,
+                                                   const double* __restrict__ dx, double* __restrict__ vbox,
+                                                   double* __restrict__ tbox, double* __restrict__ ebox) {
+  int64_t gid = static_cast<int64_t>(blockIdx.x) * BT + threadIdx.x;
+  const int64_t total = static_cast<int64_t>(px.nsv) + px.nst + px.nse;
+  if (gid >= total) return;
+  int32_t vs[3];
+  int nv;
+  double* out;
+  if (gid < px.nsv) {
+    vs[0] = px.sv[gid]; nv = 1; out = vbox + 6 * gid;
+  } else if (gid < px.nsv + px.nst) {
+    int64_t f = gid - px.nsv;
+    vs[0] = px.st[3 * f]; vs[1] = px.st[3 * f + 1]; vs[2] = px.st[3 * f + 2]; nv = 3; out = tbox + 6 * f;
+  } else {
+    int64_t e = gid - px.nsv - px.nst;
+    vs[0] = px.se[2 * e]; vs[1] = px.se[2 * e + 1]; nv = 2; out = ebox + 6 * e;
+  }
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int k = 0; k < nv; ++k)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double p = x[3 * vs[k] + r];
+      lo[r] = fmin(lo[r], p);
+      hi[r] = fmax(hi[r], p);
+      if (dx) {
+        double q = p + dx[3 * vs[k] + r];
+        lo[r] = fmin(lo[r], q);
+        hi[r] = fmax(hi[r], q);
+      }
+    }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) { out[r] = lo[r]; out[3 + r] = hi[r]; }
+}
+
+// params[0..2] = grid origin, params[3] = cell size, params[4] = query pad.
+__global__ void __launch_bounds__(BT) grid_params_partial(ProxyDev px, const double* __restrict__ vbox,
+                                                          const double* __restrict__ tbox,
+                                                          const double* __restrict__ ebox, double pad,
+                                                          double* __restrict__ part) {
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, ext = 0.0;
+  const int64_t total = static_cast<int64_t>(px.nsv) + px.nst + px.nse;
+  for (int64_t gid = static_cast<int64_t>(blockIdx.x) * BT + threadIdx.x; gid < total;
+       gid += static_cast<int64_t>(gridDim.x) * BT) {
+    const double* b;
+    double pd = 0.0;
+    if (gid < px.nsv) { b = vbox + 6 * gid; pd = pad; }
+    else if (gid < px.nsv + px.nst) b = tbox + 6 * (gid - px.nsv);
+    else { b = ebox + 6 * (gid - px.nsv - px.nst); pd = pad; }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      mn[r] = fmin(mn[r], b[r] - pd);
+      ext = fmax(ext, b[3 + r] - b[r] + 2.0 * pd);
+    }
+  }
+  __shared__ double sh[4][BT / PDIPC_WAVE];
+  double vals[4] = {mn[0], mn[1], mn[2], ext};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) vals[k] = k < 3 ? wave_min(vals[k]) : wave_max(vals[k]);
+  int lane = threadIdx.x % PDIPC_WAVE, wid = threadIdx.x / PDIPC_WAVE;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][wid] = vals[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) {
+      double r = sh[k][0];
+      for (int w = 1; w < BT / PDIPC_WAVE; ++w) r = k < 3 ? fmin(r, sh[k][w]) : fmax(r, sh[k][w]);
+      part[4 * blockIdx.x + k] = r;
+    }
+  }
+}
+
+__global__ void grid_params_final(const double* __restrict__ part, int nparts, double pad, double* params) {
+  if (threadIdx.x != 0) return;
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, ext = 0.0;
+  for (int i = 0; i < nparts; ++i) {
+    for (int r = 0; r < 3; ++r) mn[r] = fmin(mn[r], part[4 * i + r]);
+    ext = fmax(ext, part[4 * i + 3]);
+  }
+  double h = ext * (1.0 + 1e-6) + 1e-12;
+  for (int r = 0; r < 3; ++r) params[r] = mn[r] - h;
+  params[3] = h;
+  params[4] = pad;
+}
+
+// ---- table build ---------------------------------------------------------------
+template <bool FILL>
+__global__ void __launch_bounds__(BT) insert_kernel(int32_t nprim, const double* __restrict__ box,
+                                                    const double* __restrict__ params, uint32_t mask,
+                                                    int32_t* __restrict__ count, int32_t* __restrict__ ids,
+                                                    uint64_t* __restrict__ keys) {
+  int32_t p = blockIdx.x * BT + threadIdx.x;
+  if (p >= nprim) return;
+  const double o0 = params[0], o1 = params[1], o2 = params[2], h = params[3];
+  const double* b = box + 6 * static_cast<int64_t>(p);
+  int32_t l0 = cell_of(b[0], o0, h), l1 = cell_of(b[1], o1, h), l2 = cell_of(b[2], o2, h);
+  int32_t u0 = clamp_hi(l0, cell_of(b[3], o0, h)), u1 = clamp_hi(l1, cell_of(b[4], o1, h)),
+          u2 = clamp_hi(l2, cell_of(b[5], o2, h));
+  for (int32_t k = l2; k <= u2; ++k)
+    for (int32_t j = l1; j <= u1; ++j)
+      for (int32_t i = l0; i <= u0; ++i) {
+        uint32_t hh = cell_hash(i, j, k, mask);
+        int32_t slot = atomicAdd(&count[hh], 1);
+        if (FILL) {
+          ids[slot] = p;
+          keys[slot] = cell_key(i, j, k);
+        }
+      }
+}
+
+// ---- queries --------------------------------------------------------------------
+struct QueryArgs {
+  ProxyDev px;
+  const double* x;
+  const double* vbox;
+  const double* tbox;
+  const double* ebox;
+  const double* params;
+  uint32_t mask;
+  const int32_t* t_start;
+  const int32_t* t_id;
+  const uint64_t* t_key;
+  const int32_t* e_start;
+  const int32_t* e_id;
+  const uint64_t* e_key;
+  double dhat;
+  bool dist;
+};
+
+__device__ __forceinline__ bool box_overlap(const double* a, const double* b, double dhat) {
+  return a[0] <= b[3] + dhat && b[0] <= a[3] + dhat && a[1] <= b[4] + dhat && b[1] <= a[4] + dhat &&
+         a[2] <= b[5] + dhat && b[2] <= a[5] + dhat;
+}
+
+// Visit all accepted partners of query q; call emit(partner, v4).
+template <typename Emit>
+__device__ void visit_partners(const QueryArgs& qa, int64_t q, Emit emit) {
+  const ProxyDev& px = qa.px;
+  const bool is_pt = q < px.nsv;
+  const double* qb;
+  int32_t qv[2];
+  if (is_pt) {
+    qb = qa.vbox + 6 * q;
+    qv[0] = px.sv[q];
+  } else {
+    int64_t e = q - px.nsv;
+    qb = qa.ebox + 6 * e;
+    qv[0] = px.se[2 * e];
+    qv[1] = px.se[2 * e + 1];
+  }
+  const double o[3] = {qa.params[0], qa.params[1], qa.params[2]};
+  const double h = qa.params[3], pad = qa.params[4];
+  int32_t ql[3], qu[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    ql[r] = cell_of(qb[r] - pad, o[r], h);
+    qu[r] = clamp_hi(ql[r], cell_of(qb[3 + r] + pad, o[r], h));
+  }
+  const int32_t* start = is_pt ? qa.t_start : qa.e_start;
+  const int32_t* ids = is_pt ? qa.t_id : qa.e_id;
+  const uint64_t* keys = is_pt ? qa.t_key : qa.e_key;
+  const double* pbox = is_pt ? qa.tbox : qa.ebox;
+  for (int32_t k = ql[2]; k <= qu[2]; ++k)
+    for (int32_t j = ql[1]; j <= qu[1]; ++j)
+      for (int32_t i = ql[0]; i <= qu[0]; ++i) {
+        uint32_t hh = cell_hash(i, j, k, qa.mask);
+        uint64_t key = cell_key(i, j, k);
+        for (int32_t s = start[hh]; s < start[hh + 1]; ++s) {
+          if (keys[s] != key) continue;
+          int32_t p = ids[s];
+          if (!is_pt && p <= q - px.nsv) continue;
+          const double* b = pbox + 6 * static_cast<int64_t>(p);
+          int32_t pl0 = cell_of(b[0], o[0], h), pl1 = cell_of(b[1], o[1], h), pl2 = cell_of(b[2], o[2], h);
+          if (max(ql[0], pl0) != i || max(ql[1], pl1) != j || max(ql[2], pl2) != k) continue;
+          if (!box_overlap(qb, b, qa.dhat)) continue;
+          int32_t v4[4];
+          if (is_pt) {
+            int32_t t0 = px.st[3 * p], t1 = px.st[3 * p + 1], t2 = px.st[3 * p + 2];
+            if (qv[0] == t0 || qv[0] == t1 || qv[0] == t2) continue;
+            v4[0] = qv[0]; v4[1] = t0; v4[2] = t1; v4[3] = t2;
+          } else {
+            int32_t b0 = px.se[2 * p], b1 = px.se[2 * p + 1];
+            if (qv[0] == b0 || qv[0] == b1 || qv[1] == b0 || qv[1] == b1) continue;
+            v4[0] = qv[0]; v4[1] = qv[1]; v4[2] = b0; v4[3] = b1;
+          }
+          if (qa.dist) {
+            double P[4][3];
+            load_pair_rel(v4, qa.x, P);
+            double d2 = pair_dist2<double>(is_pt, P);
+            if (!(d2 < qa.dhat * qa.dhat)) continue;
+          }
+          emit(p, v4);
+        }
+      }
+}
+
+__global__ void __launch_bounds__(BT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * BT + threadIdx.x;
+  if (q >= static_cast<int64_t>(qa.px.nsv) + qa.px.nse) return;
+  int32_t c = 0;
+  visit_partners(qa, q, [&](int32_t, const int32_t*) { ++c; });
+  qcount[q] = c;
+}
+
+__global__ void __launch_bounds__(BT) query_fill_kernel(QueryArgs qa, const int32_t* __restrict__ qoff,
+                                                        int32_t* __restrict__ ptype, int32_t* __restrict__ pi,
+                                                        int32_t* __restrict__ pj, int32_t* __restrict__ pv4) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * BT + threadIdx.x;
+  if (q >= static_cast<int64_t>(qa.px.nsv) + qa.px.nse) return;
+  const bool is_pt = q < qa.px.nsv;
+  const int32_t begin = qoff[q];
+  int32_t c = begin;
+  const int32_t qi = is_pt ? qa.px.sv[q] : static_cast<int32_t>(q - qa.px.nsv);
+  visit_partners(qa, q, [&](int32_t p, const int32_t* v4) {
+    ptype[c] = is_pt ? 0 : 1;
+    pi[c] = qi;
+    pj[c] = p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv4[4 * c + k] = v4[k];
+    ++c;
+  });
+  // insertion sort of this query's partners by partner id
+  for (int32_t a = begin + 1; a < c; ++a) {
+    int32_t key = pj[a];
+    int32_t kv[4] = {pv4[4 * a], pv4[4 * a + 1], pv4[4 * a + 2], pv4[4 * a + 3]};
+    int32_t b = a - 1;
+    while (b >= begin && pj[b] > key) {
+      pj[b + 1] = pj[b];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pv4[4 * (b + 1) + k] = pv4[4 * b + k];
+      --b;
+    }
+    pj[b + 1] = key;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv4[4 * (b + 1) + k] = kv[k];
+  }
+}
+
+__global__ void pt_total_kernel(const int32_t* __restrict__ qoff, int32_t nsv, int32_t* __restrict__ out) {
+  *out = qoff[nsv];
+}
+
+int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x, const double* dx, double dhat,
+               bool distance_filter, PairList& out, int32_t* n_pt, int32_t* n_ee, hipStream_t st,
+               int64_t* needed) {
+  const int64_t total = static_cast<int64_t>(px.nsv) + px.nst + px.nse;
+  const int64_t nq = static_cast<int64_t>(px.nsv) + px.nse;
+  *needed = 0;
+  if (px.nsv == 0 || (px.nst == 0 && px.nse == 0)) {
+    *n_pt = 0;
+    *n_ee = 0;
+    return 0;
+  }
+  const double pad = dhat * (1.0 + 1e-9) + 1e-15;
+  boxes_kernel<<<grid_for(total, BT), BT, 0, st>>>(px, x, dx, bb.vbox, bb.tbox, bb.ebox);
+  double* part = bb.params + 8;
+  grid_params_partial<<<64, BT, 0, st>>>(px, bb.vbox, bb.tbox, bb.ebox, pad, part);
+  grid_params_final<<<1, 64, 0, st>>>(part, 64, pad, bb.params);
+  const uint32_t T = 1u << bb.table_bits;
+  const uint32_t mask = T - 1;
+  // triangle table
+  launch_fill_i32(bb.t_count, T + 1, 0, st);
+  launch_fill_i32(bb.e_count, T + 1, 0, st);
+  if (px.nst) insert_kernel<false><<<grid_for(px.nst, BT), BT, 0, st>>>(px.nst, bb.tbox, bb.params, mask, bb.t_count, nullptr, nullptr);
+  if (px.nse) insert_kernel<false><<<grid_for(px.nse, BT), BT, 0, st>>>(px.nse, bb.ebox, bb.params, mask, bb.e_count, nullptr, nullptr);
+  launch_exclusive_scan(bb.t_count, bb.t_count, T + 1, bb.d_totals + 2, bb.scan_temp, st);
+  launch_exclusive_scan(bb.e_count, bb.e_count, T + 1, bb.d_totals + 3, bb.scan_temp, st);
+  hipMemcpyAsync(bb.t_cursor, bb.t_count, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToDevice, st);
+  hipMemcpyAsync(bb.e_cursor, bb.e_count, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToDevice, st);
+  if (px.nst) insert_kernel<true><<<grid_for(px.nst, BT), BT, 0, st>>>(px.nst, bb.tbox, bb.params, mask, bb.t_cursor, bb.t_id, bb.t_key);
+  if (px.nse) insert_kernel<true><<<grid_for(px.nse, BT), BT, 0, st>>>(px.nse, bb.ebox, bb.params, mask, bb.e_cursor, bb.e_id, bb.e_key);
+
+  QueryArgs qa{px, x, bb.vbox, bb.tbox, bb.ebox, bb.params, mask, bb.t_count, bb.t_id, bb.t_key,
+               bb.e_count, bb.e_id, bb.e_key, dhat, distance_filter};
+  launch_fill_i32(bb.q_count + nq, 1, 0, st);     // sentinel slot of the scan
+  query_count_kernel<<<grid_for(nq, BT), BT, 0, st>>>(qa, bb.q_count);
+  launch_exclusive_scan(bb.q_count, bb.q_count, nq + 1, bb.d_totals, bb.scan_temp, st);
+  pt_total_kernel<<<1, 1, 0, st>>>(bb.q_count, px.nsv, bb.d_totals + 1);
+  int32_t h_tot[4];
+  hipMemcpyAsync(h_tot, bb.d_totals, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  const int32_t npairs = h_tot[0];
+  if (h_tot[2] > bb.ent_cap || h_tot[3] > bb.ent_cap) return -1;   // grid sizing broke
+  if (npairs > out.cap) {
+    *needed = npairs;
+    return 1;
+  }
+  *n_pt = h_tot[1];
+  *n_ee = npairs - h_tot[1];
+  if (npairs > 0)
+    query_fill_kernel<<<grid_for(nq, BT), BT, 0, st>>>(qa, bb.q_count, out.type, out.i, out.j, out.v4);
+  return 0;
+}
+
+// ---- CCD: conservative advancement ---------------------------------------------
+__global__ void __launch_bounds__(BT) ccd_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
+                                                 const double* __restrict__ x, const double* __restrict__ dx,
+                                                 double eta, int32_t steps, double* __restrict__ tout) {
+  int32_t k = blockIdx.x * BT + threadIdx.x;
+  if (k >= npairs) return;
+  const bool is_pt = k < n_pt;
+  int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
+  double P[4][3];
+  load_pair_rel(v4, x, P);
+  double d0 = sqrt(pair_dist2<double>(is_pt, P));
+  double g = eta * d0;
+  double D[4][3], m[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      D[a][r] = dx[3 * v4[a] + r];
+      m[r] += D[a][r];
+    }
+  double nr[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double c[3] = {D[a][0] - 0.25 * m[0], D[a][1] - 0.25 * m[1], D[a][2] - 0.25 * m[2]};
+    nr[a] = sqrt(dot3(c, c));
+  }
+  double l = is_pt ? nr[0] + fmax(nr[1], fmax(nr[2], nr[3])) : fmax(nr[0], nr[1]) + fmax(nr[2], nr[3]);
+  double t = 0.0;
+  if (!(l > 0.0)) {
+    t = 1.0;
+  } else {
+    for (int it = 0; it < steps; ++it) {
+      double Q[4][3];
+      load_pair_rel_step(v4, x, dx, t, Q);
+      double dt = sqrt(pair_dist2<double>(is_pt, Q));
+      t = fmin(1.0, t + fmax(0.0, dt - g) / l);
+    }
+  }
+  tout[k] = t;
+}
+
+void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
+                int32_t steps, double* t_out, hipStream_t st) {
+  if (npairs <= 0) return;
+  ccd_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, eta, steps, t_out);
+}
+
+// ---- line-search barrier energies -------------------------------------------------
+__global__ void __launch_bounds__(BT) pair_energy_kernel(const int32_t* __restrict__ v4all, int32_t npairs,
+                                                         int32_t n_pt, const double* __restrict__ x,
+                                                         const double* __restrict__ dx, double alpha, double dhat,
+                                                         double kappa, const double* __restrict__ E0,
+                                                         double* __restrict__ out) {
+  int32_t k = blockIdx.x * BT + threadIdx.x;
+  if (k >= npairs) return;
+  int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
+  double P[4][3];
+  if (dx) load_pair_rel_step(v4, x, dx, alpha, P);
+  else load_pair_rel(v4, x, P);
+  double d2 = pair_dist2<double>(k < n_pt, P);
+  double e;
+  if (!(d2 > 0.0)) e = INFINITY;
+  else e = d2 < dhat * dhat ? kappa * barrier_b(sqrt(d2), dhat) : 0.0;
+  out[k] = E0 ? e - E0[k] : e;
+}
+
+void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
+                                double alpha, double dhat, double kappa, const double* E0, double* out,
+                                hipStream_t st) {
+  if (npairs <= 0) return;
+  pair_energy_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, alpha, dhat, kappa, E0, out);
+}
+
+__global__ void __launch_bounds__(BT) pair_d2_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
+                                                     const double* __restrict__ x, double* __restrict__ out) {
+  int32_t k = blockIdx.x * BT + threadIdx.x;
+  if (k >= npairs) return;
+  int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
+  double P[4][3];
+  load_pair_rel(v4, x, P);
+  out[k] = pair_dist2<double>(k < n_pt, P);
+}
+
+void launch_pair_min_dist2(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double* d2_out,
+                           hipStream_t st) {
+  if (npairs <= 0) return;
+  pair_d2_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, d2_out);
+}
+
+}  // namespace pdipc

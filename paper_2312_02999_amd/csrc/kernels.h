@@ -1,0 +1,198 @@
+// Launchers of the gfx950 kernels.  All pointers are device memory unless a
+// name says host; every launcher enqueues on the given stream and returns.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pdipc {
+
+// ---------------------------------------------------------------- local step
+struct LocalArgs {
+  int64_t m;
+  const int32_t* tets;  // 4 x m
+  const double* B;      // 9 x m
+  const double* w;      // m
+  const double* A;      // 6 x m
+};
+void launch_local_step(const LocalArgs& la, const double* x, double* Rout, double* energy, double* tetg, bool fp32,
+                       hipStream_t st);
+void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, double alpha, const double* E0,
+                         double* dE, bool fp32, hipStream_t st);
+void launch_gather_vertex_grad(int32_t n, int64_t m, const int32_t* vt_ptr, const int32_t* vt_ent,
+                               const double* tetg, const uint8_t* fixed, double* g, hipStream_t st);
+void launch_actuation_scalar(int64_t m, const double* a, const double* R, double* A, hipStream_t st);
+void launch_actuation_transpose(int64_t m, const double* Ain, double* A, hipStream_t st);
+
+// ------------------------------------------------------------------- utility
+// exclusive scan of n int32 into out (out may alias in); total -> *d_total
+size_t scan_temp_bytes(int64_t n);
+void launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total, void* temp,
+                           hipStream_t st);
+// deterministic sum of n doubles into *d_out (fixed blocked order)
+size_t sum_temp_bytes(int64_t n);
+void launch_sum(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
+void launch_sum2(const double* a, int64_t na, const double* b, int64_t nb, double* d_out, void* temp,
+                 hipStream_t st);
+// min of n doubles (>= 0 entries) into *d_out, 1.0 if n == 0 (exact: min is order-free)
+void launch_min_clamp1(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+void launch_axpy_positions(int64_t n3, double alpha, const double* dx, double* x, hipStream_t st);
+void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
+// number of non-finite entries -> *d_out
+void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStream_t st);
+
+// ------------------------------------------------------------------- contact
+struct ProxyDev {
+  int32_t nsv, nst, nse;
+  const int32_t* sv;    // nsv sim ids, ascending
+  const int32_t* st;    // 3 x nst (AoS triples of sim ids)
+  const int32_t* se;    // 2 x nse (AoS (lo, hi) sim ids), sorted
+};
+
+struct BroadPhaseBuffers {
+  // boxes: 6 doubles per primitive (lo xyz, hi xyz)
+  double* vbox;         // nsv
+  double* tbox;         // nst
+  double* ebox;         // nse
+  double* params;       // [0..2] origin, [3] cell size, [4..] scratch
+  int32_t table_bits;   // table size = 1 << bits
+  int32_t* t_count;     // triangle table: table + 1
+  int32_t* t_cursor;
+  int32_t* t_id;        // entries
+  uint64_t* t_key;
+  int32_t* e_count;
+  int32_t* e_cursor;
+  int32_t* e_id;
+  uint64_t* e_key;
+  int64_t ent_cap;      // capacity of each entry array
+  int32_t* q_count;     // nsv + nse + 1 per-query counts / offsets
+  int32_t* d_totals;    // [0] pairs total
+  void* scan_temp;
+  void* red_temp;
+};
+
+// Candidate (swept == true: boxes over x and x + dx) or constraint-set pairs.
+// Pairs are written sorted: point-triangle (query = proxy vertex, ascending
+// sim id, then triangle id), then edge-edge (e < e').  Returns via host the
+// two counts (point-triangle, edge-edge) after a synchronising read.
+struct PairList {
+  int32_t* type;        // 0 = PT, 1 = EE
+  int32_t* i;           // PT: sim vertex id; EE: edge id
+  int32_t* j;           // PT: triangle id;  EE: edge id (> i)
+  int32_t* v4;          // 4 sim ids per pair in local order
+  int64_t cap;
+};
+int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x, const double* dx, double dhat,
+               bool distance_filter, PairList& out, int32_t* n_pt, int32_t* n_ee, hipStream_t st,
+               int64_t* needed);
+
+// CCD: t_k per candidate pair (conservative advancement), then alpha_m.
+void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
+                int32_t steps, double* t_out, hipStream_t st);
+// kappa * b(d) per candidate at x + alpha dx (alpha = 0 allowed); pairs at
+// d >= dhat give 0.
+void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
+                                double alpha, double dhat, double kappa, const double* E0, double* out,
+                                hipStream_t st);
+// smallest pair distance (for the intersection check); -> d_out
+void launch_pair_min_dist2(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double* d2_out,
+                           hipStream_t st);
+
+// ------------------------------------------------------------------- barrier
+// Per active pair: energy, gradient (12), PSD Hessian factor U (12 x 5, row
+// r = 3 * local point + coord), so that the projected Hessian is U U^T.
+struct BarrierOut {
+  double* energy;       // npairs
+  double* grad;         // 12 x npairs (SoA)
+  double* U;            // 60 x npairs (SoA, entry 5 r + k)
+};
+void launch_barrier(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double dhat, double kappa,
+                    bool fp32, BarrierOut& bo, hipStream_t st);
+
+// vertex -> (pair, local) incidence (sorted), per-vertex gradient add,
+// affected-set map.  inc_ptr: n + 1, inc_ent: 4 * npairs.
+struct Incidence {
+  int32_t* cnt;         // n + 1
+  int32_t* ptr;         // n + 1
+  int32_t* cursor;      // n
+  int32_t* ent;         // 4 * cap pairs
+  int32_t* cflag;       // n + 1: 1 if free and touched
+  int32_t* cidx;        // n + 1: exclusive scan of cflag (c index if flagged)
+  int32_t* clist;       // n: c index -> sim vertex
+  int32_t* d_nc;        // device total
+};
+void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const uint8_t* fixed, Incidence& inc,
+                     void* scan_temp, hipStream_t st);
+void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
+                             const uint8_t* fixed, double* g, hipStream_t st);
+
+// ---------------------------------------------------------- global (Eq. 7)
+struct FactorDev {
+  int32_t n1, n2, nnodes, nlevels;
+  const int32_t* node_c0;
+  const int32_t* node_s;
+  const int32_t* node_r;
+  const int64_t* node_rows_off;
+  const int64_t* node_panel_off;
+  const int64_t* node_dinv_off;
+  const int32_t* level_nodes;      // node ids grouped by level
+  const int32_t* h_level_ptr;      // HOST: nlevels + 1
+  const int32_t* h_level_maxs;     // HOST: max s in each level
+  const int32_t* h_level_maxr;     // HOST: max r in each level
+  const int32_t* rows;
+  const double* panel;             // r x s row-major per node
+  const double* dinv;              // s x s row-major per node
+  const double* dinvT;             // s x s column-major per node (transpose)
+  const int64_t* fwd_ptr;          // n1 + n2 + 1
+  const int32_t* fwd_col;
+  const double* fwd_val;
+  const double* sigma_inv;         // n2 x n2 row-major
+  const int32_t* ext2vert;         // n1 + n2: sim vertex of each extended index
+};
+// b (ext, 3) = -g at ext2vert
+void launch_pack_rhs(const FactorDev& f, const double* g, double* b, hipStream_t st);
+// forward sweep: y (ext, 3); rows of x2 get r2 - L21 y1 (no diagonal solve)
+void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st);
+// z = Sigma^-1 r (n2 x 3)
+void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream_t st);
+// backward sweep: sol[0, n1) from y and sol[n1, n1 + n2) (already set)
+void launch_backward_sweep(const FactorDev& f, const double* y, double* sol, hipStream_t st);
+// dx (n x 3) from sol (ext): zero elsewhere
+void launch_unpack(const FactorDev& f, int32_t n, const double* sol, double* dx, hipStream_t st);
+
+// ------------------------------------------------- reduced contact system
+// C_s = Sigma^-1[c, c] (nc x nc), using x2 index of each c vertex
+void launch_gather_cc(const FactorDev& f, int32_t nc, const int32_t* c_x2, double* Cs, hipStream_t st);
+// M = Cinv (x) I3 + sum_k U_k U_k^T blocks (3nc x 3nc row-major, full)
+void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairList& pl,
+                             int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st);
+// out (nc x 3) = (Cinv (x) I3) z_c, z_c gathered from z (n2 x 3) by c_x2
+void launch_cinv_times_zc(int32_t nc, const double* Cinv, const int32_t* c_x2, const double* z, double* out,
+                          hipStream_t st);
+// v (nc x 3) = Bcheck u
+void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, int32_t npairs, const BarrierOut& bo,
+                         const uint8_t* fixed, const double* u, double* wtmp, double* v, hipStream_t st);
+// z -= Sigma^-1[:, c] v   (n2 x 3)
+void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* z,
+                              hipStream_t st);
+// c index -> x2 index
+void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
+
+// ---------------------------------------------------------------- dense FP64
+// In-place lower Cholesky of an n x n row-major matrix (upper part ignored).
+// *d_info <- 0 ok, else 1 + first failing column.
+template <typename T>
+void dense_cholesky(T* A, int64_t n, int32_t* d_info, hipStream_t st);
+// Solve L L^T x = b in place (b: n x nrhs row-major), L from dense_cholesky.
+template <typename T>
+void dense_chol_solve(const T* L, int64_t n, T* b, int32_t nrhs, hipStream_t st);
+// Ainv = (L L^T)^-1 (full symmetric, row-major), work: n x n scratch
+template <typename T>
+void dense_chol_inverse(const T* L, int64_t n, T* Ainv, T* work, hipStream_t st);
+void launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t st);
+void launch_convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t st);
+// r = b - M u  (dense, n x n row-major FP64), all vectors n
+void launch_dense_residual(const double* M, int64_t n, const double* b, const double* u, double* r, hipStream_t st);
+
+}  // namespace pdipc

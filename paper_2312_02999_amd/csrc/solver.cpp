@@ -1,0 +1,1048 @@
+// Solver runtime and the C ABI of include/pdipc.h.
+//
+// One iteration of Algorithm 1 (quasi-static PD with IPC contact):
+//   local step            per-tet rotation fit and PD gradient     (Eq. 1)
+//   constraint set        spatial hash + exact distances < dhat   (Section 2.2)
+//   barrier               gradient + PSD Hessian factors          (Eq. 3)
+//   global step           Eq. (7) sweeps + Eq. (11) reduced system (Section 3)
+//   CCD                   swept candidates + conservative advancement
+//   line search           back-tracking on the total energy difference
+// All state stays in device memory; the host reads back only the pair
+// counts, n_c, the factorization status, alpha_m and the line-search sign.
+#include "../../include/pdipc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "host_factor.h"
+#include "kernels.h"
+
+namespace pdipc {
+
+static std::string g_last_init_error;
+
+#define HIPCHK(expr)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess) {                                            \
+      throw HipFailure(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                  \
+  } while (0)
+
+struct HipFailure {
+  std::string msg;
+  explicit HipFailure(std::string m) : msg(std::move(m)) {}
+};
+struct SolverError {
+  int code;
+  std::string msg;
+};
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  int64_t cap = 0;
+  void ensure(int64_t count) {
+    if (count <= cap) return;
+    if (p) HIPCHK(hipFree(p));
+    p = nullptr;
+    int64_t c = std::max<int64_t>(count, 1);
+    if (hipMalloc(&p, sizeof(T) * c) != hipSuccess) {
+      p = nullptr;
+      cap = 0;
+      throw SolverError{PDIPC_E_NOMEM, "device allocation failed"};
+    }
+    cap = c;
+  }
+  void upload(const T* h, int64_t count, hipStream_t st) {
+    ensure(count);
+    if (count > 0) HIPCHK(hipMemcpyAsync(p, h, sizeof(T) * count, hipMemcpyHostToDevice, st));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct Solver {
+  std::string err;
+  pdipc_options opt{};
+  hipStream_t st = nullptr;
+  int32_t n = 0, m = 0, nsv = 0, nst = 0, nse = 0, n1 = 0, n2 = 0;
+  int64_t factor_nnz = 0;
+  bool have_actuation = false, have_scalar = false, have_solution = false;
+
+  // mesh
+  DBuf<int32_t> tets, vt_ptr, vt_ent, sv, stri, sedge;
+  DBuf<double> Bm, w, A, a_s, R0, X;
+  DBuf<uint8_t> fixed;
+  // per-iteration vectors
+  DBuf<double> x, g, dx, tetg, E0, dE, Rtet, tpair, bE0, bdE, scal;
+  // factor
+  DBuf<int32_t> node_c0, node_s, node_r, level_nodes, frows, fcol, ext2vert, vert2x2;
+  DBuf<int64_t> node_roff, node_poff, node_doff, fptr;
+  DBuf<double> panel, dinv, dinvT, fval, sigma_inv;
+  std::vector<int32_t> h_level_ptr, h_level_maxs, h_level_maxr;
+  FactorDev fd{};
+  DBuf<double> bvec, yvec, solvec;
+  // contact
+  ProxyDev px{};
+  BroadPhaseBuffers bb{};
+  DBuf<double> vbox, tbox, ebox, params;
+  DBuf<int32_t> t_count, t_cursor, t_id, e_count, e_cursor, e_id, q_count, totals;
+  DBuf<uint64_t> t_key, e_key;
+  DBuf<char> scan_tmp, red_tmp;
+  DBuf<int32_t> act_type, act_i, act_j, act_v4, cand_type, cand_i, cand_j, cand_v4;
+  PairList act{}, cand{};
+  DBuf<double> b_energy, b_grad, b_U;
+  BarrierOut bo{};
+  DBuf<int32_t> inc_cnt, inc_ptr, inc_cursor, inc_ent, inc_cflag, inc_cidx, inc_clist, inc_nc;
+  Incidence inc{};
+  // reduced system
+  DBuf<int32_t> c_x2, info;
+  DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid;
+  DBuf<float> Mf, uf;
+  // last converged state for the adjoint
+  int32_t last_npairs = 0, last_npt = 0;
+
+  // host helpers
+  double* h_scal = nullptr;   // pinned readback
+  // optional HIP-event timer around every launch of one kernel family
+  int32_t timer_which = -1;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double timer_ms = 0.0;
+  int64_t timer_count = 0;
+
+  ~Solver() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (h_scal) (void)hipHostFree(h_scal);
+    if (st) (void)hipStreamSynchronize(st);
+  }
+};
+
+// ----------------------------------------------------------------- init
+static void fail(int code, const std::string& msg) { throw SolverError{code, msg}; }
+
+// Kernel families that the event timer can bracket.
+enum TimerKernel { TK_LOCAL = 0, TK_SIGMA_GEMV = 1, TK_FWD = 2, TK_BWD = 3, TK_BARRIER = 4, TK_TRIAL = 5,
+                   TK_REDUCED_CHOL = 6, TK_PAIRS = 7, TK_CCD = 8 };
+
+struct ScopedTimer {
+  Solver* S;
+  bool on;
+  ScopedTimer(Solver* s, int which) : S(s), on(s->timer_which == which) {
+    if (on) record();
+  }
+  ~ScopedTimer() {
+    if (on) record();
+  }
+  void record() {
+    if (S->ev_used >= S->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+      S->ev_pool.push_back(e);
+    }
+    (void)hipEventRecord(S->ev_pool[S->ev_used++], S->st);
+  }
+};
+
+static void harvest_timer(Solver* S) {
+  for (size_t k = 0; k + 1 < S->ev_used; k += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, S->ev_pool[k], S->ev_pool[k + 1]) == hipSuccess) {
+      S->timer_ms += ms;
+      S->timer_count += 1;
+    }
+  }
+  S->ev_used = 0;
+}
+
+static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solver* S) {
+  if (!md || !op) fail(PDIPC_E_INVALID, "null mesh or options");
+  S->opt = *op;
+  S->st = static_cast<hipStream_t>(op->stream);
+  hipStream_t st = S->st;
+  const int32_t n = md->n_verts, m = md->n_tets;
+  if (n <= 0 || m <= 0 || !md->rest_pos || !md->tets || !md->dirichlet) fail(PDIPC_E_INVALID, "empty mesh");
+  if (!(op->dhat > 0) || !(op->kappa > 0) || op->iters <= 0 || op->ccd_steps <= 0 || op->ls_max_halvings < 0 ||
+      !(op->ccd_eta > 0 && op->ccd_eta < 1))
+    fail(PDIPC_E_INVALID, "bad options");
+  if (op->precision != PDIPC_FP64 && op->precision != PDIPC_MIXED_FP32) fail(PDIPC_E_INVALID, "bad precision");
+  if (!(md->youngs > 0) || !(md->poisson > -1 && md->poisson < 0.5)) fail(PDIPC_E_INVALID, "bad material");
+  S->n = n;
+  S->m = m;
+  const double* X = md->rest_pos;
+  for (int64_t i = 0; i < 3LL * n; ++i)
+    if (!std::isfinite(X[i])) fail(PDIPC_E_INVALID, "non-finite rest position");
+  for (int64_t i = 0; i < 4LL * m; ++i)
+    if (md->tets[i] < 0 || md->tets[i] >= n) fail(PDIPC_E_INVALID, "tet index out of range");
+  int nfixed = 0;
+  for (int32_t v = 0; v < n; ++v) nfixed += md->dirichlet[v] ? 1 : 0;
+  if (nfixed == 0) fail(PDIPC_E_NOT_SPD, "no fixed vertex: the PD matrix is singular");
+
+  // ---- per-tet rest data (Eq. 1, 2): B = D_m^-1, w = 2 mu V -----------------
+  const double mu = md->youngs / (2.0 * (1.0 + md->poisson));
+  std::vector<int32_t> tsoa(4LL * m);
+  std::vector<double> bsoa(9LL * m), wv(m);
+  std::vector<double> g4(12LL * m);   // shape gradients per tet (host use)
+  for (int64_t i = 0; i < m; ++i) {
+    const int32_t* t = md->tets + 4 * i;
+    double D[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int r = 0; r < 3; ++r) D[r][k] = X[3 * t[k + 1] + r] - X[3 * t[0] + r];
+    double det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) - D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                 D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+    if (!(det > 0)) fail(PDIPC_E_DEGENERATE, "tet " + std::to_string(i) + " has non-positive rest volume");
+    double inv[3][3];
+    inv[0][0] = (D[1][1] * D[2][2] - D[1][2] * D[2][1]) / det;
+    inv[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) / det;
+    inv[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) / det;
+    inv[1][0] = (D[1][2] * D[2][0] - D[1][0] * D[2][2]) / det;
+    inv[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) / det;
+    inv[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) / det;
+    inv[2][0] = (D[1][0] * D[2][1] - D[1][1] * D[2][0]) / det;
+    inv[2][1] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) / det;
+    inv[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) / det;
+    for (int k = 0; k < 4; ++k) tsoa[k * m + i] = t[k];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) bsoa[(3 * r + c) * m + i] = inv[r][c];
+    wv[i] = 2.0 * mu * det / 6.0;
+    for (int c = 0; c < 3; ++c) {
+      g4[12 * i + 3 + c] = inv[0][c];
+      g4[12 * i + 6 + c] = inv[1][c];
+      g4[12 * i + 9 + c] = inv[2][c];
+      g4[12 * i + c] = -(inv[0][c] + inv[1][c] + inv[2][c]);
+    }
+  }
+  // vertex -> (tet, local) incidence, tet-ascending
+  std::vector<int32_t> vptr(n + 1, 0), vent(4LL * m);
+  for (int64_t i = 0; i < m; ++i)
+    for (int k = 0; k < 4; ++k) vptr[md->tets[4 * i + k] + 1]++;
+  for (int32_t v = 0; v < n; ++v) vptr[v + 1] += vptr[v];
+  {
+    std::vector<int32_t> cur(vptr.begin(), vptr.end() - 1);
+    for (int64_t i = 0; i < m; ++i)
+      for (int k = 0; k < 4; ++k) vent[cur[md->tets[4 * i + k]]++] = static_cast<int32_t>(4 * i + k);
+  }
+
+  // ---- proxy (embedded by selection) ------------------------------------------
+  const int32_t F = md->n_surf_tris;
+  if (F < 0 || (F > 0 && !md->surf_tris)) fail(PDIPC_E_INVALID, "bad proxy triangles");
+  std::vector<int32_t> tris(md->surf_tris, md->surf_tris + 3LL * std::max(F, 0));
+  for (int32_t v : tris)
+    if (v < 0 || v >= n) fail(PDIPC_E_INVALID, "proxy triangle index out of range");
+  for (int32_t f = 0; f < F; ++f)
+    if (tris[3 * f] == tris[3 * f + 1] || tris[3 * f + 1] == tris[3 * f + 2] || tris[3 * f] == tris[3 * f + 2])
+      fail(PDIPC_E_INVALID, "proxy triangle with repeated vertex");
+  std::vector<int32_t> svv(tris.begin(), tris.end());
+  std::sort(svv.begin(), svv.end());
+  svv.erase(std::unique(svv.begin(), svv.end()), svv.end());
+  std::vector<std::pair<int32_t, int32_t>> ev;
+  ev.reserve(3LL * F);
+  for (int32_t f = 0; f < F; ++f)
+    for (int k = 0; k < 3; ++k) {
+      int32_t a = tris[3 * f + k], b = tris[3 * f + (k + 1) % 3];
+      ev.emplace_back(std::min(a, b), std::max(a, b));
+    }
+  std::sort(ev.begin(), ev.end());
+  ev.erase(std::unique(ev.begin(), ev.end()), ev.end());
+  std::vector<int32_t> sev(2 * ev.size());
+  for (size_t e = 0; e < ev.size(); ++e) {
+    sev[2 * e] = ev[e].first;
+    sev[2 * e + 1] = ev[e].second;
+  }
+  S->nsv = static_cast<int32_t>(svv.size());
+  S->nst = F;
+  S->nse = static_cast<int32_t>(ev.size());
+
+  // ---- DOF split (Eq. 6) -----------------------------------------------------------
+  std::vector<uint8_t> reg(n, 0);
+  if (md->region) {
+    for (int32_t v = 0; v < n; ++v) reg[v] = md->region[v] && !md->dirichlet[v];
+    for (int32_t v : svv)
+      if (!md->dirichlet[v] && !reg[v]) fail(PDIPC_E_INVALID, "a free proxy vertex is outside the marked region");
+  } else {
+    for (int32_t v : svv) reg[v] = md->dirichlet[v] ? 0 : 1;
+  }
+  std::vector<int32_t> x1, x2, vblock(n, -1), vlocal(n, -1);
+  for (int32_t v = 0; v < n; ++v) {
+    if (md->dirichlet[v]) continue;
+    if (reg[v]) { vblock[v] = 2; vlocal[v] = static_cast<int32_t>(x2.size()); x2.push_back(v); }
+    else { vblock[v] = 1; vlocal[v] = static_cast<int32_t>(x1.size()); x1.push_back(v); }
+  }
+  S->n1 = static_cast<int32_t>(x1.size());
+  S->n2 = static_cast<int32_t>(x2.size());
+  const int32_t n1 = S->n1, n2 = S->n2, N = n1 + n2;
+
+  // ---- scalar PD matrix H_s over free vertices in extended input order ---------------
+  auto ext_in = [&](int32_t v) { return vblock[v] == 1 ? vlocal[v] : n1 + vlocal[v]; };
+  ScalarCSR H;
+  H.n = N;
+  {
+    std::vector<int64_t> cnt(N + 1, 0);
+    for (int64_t i = 0; i < m; ++i)
+      for (int a = 0; a < 4; ++a) {
+        int32_t va = md->tets[4 * i + a];
+        if (vblock[va] < 0) continue;
+        for (int b = 0; b < 4; ++b)
+          if (vblock[md->tets[4 * i + b]] >= 0) cnt[ext_in(va) + 1]++;
+      }
+    for (int32_t r = 0; r < N; ++r) cnt[r + 1] += cnt[r];
+    std::vector<int32_t> tc(cnt[N]);
+    std::vector<double> tv(cnt[N]);
+    std::vector<int64_t> cur(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < m; ++i)
+      for (int a = 0; a < 4; ++a) {
+        int32_t va = md->tets[4 * i + a];
+        if (vblock[va] < 0) continue;
+        const double* ga = &g4[12 * i + 3 * a];
+        for (int b = 0; b < 4; ++b) {
+          int32_t vb = md->tets[4 * i + b];
+          if (vblock[vb] < 0) continue;
+          const double* gb = &g4[12 * i + 3 * b];
+          int64_t c = cur[ext_in(va)]++;
+          tc[c] = ext_in(vb);
+          tv[c] = wv[i] * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
+        }
+      }
+    H.ptr.assign(N + 1, 0);
+    std::vector<std::pair<int32_t, double>> rowbuf;
+    for (int32_t r = 0; r < N; ++r) {
+      rowbuf.clear();
+      for (int64_t e = cnt[r]; e < cnt[r + 1]; ++e) rowbuf.emplace_back(tc[e], tv[e]);
+      std::sort(rowbuf.begin(), rowbuf.end(),
+                [](const std::pair<int32_t, double>& p, const std::pair<int32_t, double>& q) { return p.first < q.first; });
+      for (size_t k = 0; k < rowbuf.size(); ++k) {
+        if (k > 0 && rowbuf[k].first == H.col.back()) H.val.back() += rowbuf[k].second;
+        else { H.col.push_back(rowbuf[k].first); H.val.push_back(rowbuf[k].second); }
+      }
+      H.ptr[r + 1] = static_cast<int64_t>(H.col.size());
+    }
+  }
+  std::vector<double> coords1(3LL * n1);
+  for (int32_t p = 0; p < n1; ++p)
+    for (int r = 0; r < 3; ++r) coords1[3 * p + r] = X[3 * x1[p] + r];
+  HostFactor hf;
+  std::string ferr;
+  int frc = build_host_factor(n1, n2, coords1.data(), H, 96, hf, ferr);
+  if (frc != 0) fail(PDIPC_E_NOT_SPD, ferr);
+  S->factor_nnz = hf.factor_nnz;
+
+  // ---- upload mesh data -----------------------------------------------------------------
+  S->tets.upload(tsoa.data(), 4LL * m, st);
+  S->Bm.upload(bsoa.data(), 9LL * m, st);
+  S->w.upload(wv.data(), m, st);
+  S->A.ensure(6LL * m);
+  S->a_s.ensure(m);
+  S->R0.ensure(9LL * m);
+  S->X.upload(X, 3LL * n, st);
+  S->fixed.upload(md->dirichlet, n, st);
+  S->vt_ptr.upload(vptr.data(), n + 1, st);
+  S->vt_ent.upload(vent.data(), 4LL * m, st);
+  S->sv.upload(svv.data(), S->nsv, st);
+  S->stri.upload(tris.data(), 3LL * F, st);
+  S->sedge.upload(sev.data(), static_cast<int64_t>(sev.size()), st);
+  for (auto* b : {&S->x, &S->g, &S->dx}) b->ensure(3LL * n);
+  S->tetg.ensure(12LL * m);
+  S->E0.ensure(m);
+  S->dE.ensure(m);
+  S->Rtet.ensure(9LL * m);
+  S->scal.ensure(16);
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
+
+  // ---- factor upload ---------------------------------------------------------------------------
+  const int32_t nn = static_cast<int32_t>(hf.nodes.size());
+  std::vector<int32_t> c0(nn), ss(nn), rr(nn), lev_nodes;
+  std::vector<int64_t> ro(nn), po(nn), dof(nn);
+  for (int32_t J = 0; J < nn; ++J) {
+    c0[J] = hf.nodes[J].c0; ss[J] = hf.nodes[J].s; rr[J] = hf.nodes[J].r;
+    ro[J] = hf.nodes[J].rows_off; po[J] = hf.nodes[J].panel_off; dof[J] = hf.nodes[J].dinv_off;
+  }
+  S->h_level_ptr.assign(hf.nlevels + 1, 0);
+  S->h_level_maxs.assign(std::max(hf.nlevels, 1), 0);
+  S->h_level_maxr.assign(std::max(hf.nlevels, 1), 0);
+  for (int32_t J = 0; J < nn; ++J) S->h_level_ptr[hf.nodes[J].level + 1]++;
+  for (int32_t L = 0; L < hf.nlevels; ++L) S->h_level_ptr[L + 1] += S->h_level_ptr[L];
+  lev_nodes.resize(nn);
+  {
+    std::vector<int32_t> cur(S->h_level_ptr.begin(), S->h_level_ptr.end() - 1);
+    for (int32_t J = 0; J < nn; ++J) {
+      int L = hf.nodes[J].level;
+      lev_nodes[cur[L]++] = J;
+      S->h_level_maxs[L] = std::max(S->h_level_maxs[L], ss[J]);
+      S->h_level_maxr[L] = std::max(S->h_level_maxr[L], rr[J]);
+    }
+  }
+  std::vector<double> dT(hf.dinv.size());
+  for (int32_t J = 0; J < nn; ++J) {
+    const int s = ss[J];
+    const double* D = hf.dinv.data() + dof[J];
+    double* T = dT.data() + dof[J];
+    for (int r = 0; r < s; ++r)
+      for (int c = 0; c < s; ++c) T[static_cast<int64_t>(c) * s + r] = D[static_cast<int64_t>(r) * s + c];
+  }
+  std::vector<int32_t> e2v(N), v2x2(n, -1);
+  for (int32_t p = 0; p < n1; ++p) e2v[p] = x1[hf.perm[p]];
+  for (int32_t q = 0; q < n2; ++q) { e2v[n1 + q] = x2[q]; v2x2[x2[q]] = q; }
+  S->node_c0.upload(c0.data(), nn, st);
+  S->node_s.upload(ss.data(), nn, st);
+  S->node_r.upload(rr.data(), nn, st);
+  S->node_roff.upload(ro.data(), nn, st);
+  S->node_poff.upload(po.data(), nn, st);
+  S->node_doff.upload(dof.data(), nn, st);
+  S->level_nodes.upload(lev_nodes.data(), nn, st);
+  S->frows.upload(hf.rows.data(), static_cast<int64_t>(hf.rows.size()), st);
+  S->panel.upload(hf.panel.data(), static_cast<int64_t>(hf.panel.size()), st);
+  S->dinv.upload(hf.dinv.data(), static_cast<int64_t>(hf.dinv.size()), st);
+  S->dinvT.upload(dT.data(), static_cast<int64_t>(dT.size()), st);
+  S->fptr.upload(hf.fwd_ptr.data(), static_cast<int64_t>(hf.fwd_ptr.size()), st);
+  S->fcol.upload(hf.fwd_col.data(), static_cast<int64_t>(hf.fwd_col.size()), st);
+  S->fval.upload(hf.fwd_val.data(), static_cast<int64_t>(hf.fwd_val.size()), st);
+  S->ext2vert.upload(e2v.data(), N, st);
+  S->vert2x2.upload(v2x2.data(), n, st);
+  S->bvec.ensure(3LL * std::max(N, 1));
+  S->yvec.ensure(6LL * std::max(N, 1));
+  S->solvec.ensure(6LL * std::max(N, 1));
+  S->info.ensure(4);
+
+  // ---- Sigma^-1 on the device: Cholesky of Sigma_s, then L^-T L^-1 ---------------------------
+  S->sigma_inv.ensure(std::max<int64_t>(1, static_cast<int64_t>(n2) * n2));
+  if (n2 > 0) {
+    DBuf<double> sig, wk;
+    sig.upload(hf.sigma.data(), static_cast<int64_t>(n2) * n2, st);
+    wk.ensure(static_cast<int64_t>(n2) * n2);
+    dense_cholesky<double>(sig.p, n2, S->info.p, st);
+    int32_t hinfo = 0;
+    HIPCHK(hipMemcpyAsync(&hinfo, S->info.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hinfo != 0) {
+      sig.release(); wk.release();
+      fail(PDIPC_E_NOT_SPD, "Schur complement Sigma is not positive definite");
+    }
+    dense_chol_inverse<double>(sig.p, n2, S->sigma_inv.p, wk.p, st);
+    HIPCHK(hipStreamSynchronize(st));
+    sig.release();
+    wk.release();
+  }
+  FactorDev& f = S->fd;
+  f.n1 = n1; f.n2 = n2; f.nnodes = nn; f.nlevels = hf.nlevels;
+  f.node_c0 = S->node_c0.p; f.node_s = S->node_s.p; f.node_r = S->node_r.p;
+  f.node_rows_off = S->node_roff.p; f.node_panel_off = S->node_poff.p; f.node_dinv_off = S->node_doff.p;
+  f.level_nodes = S->level_nodes.p;
+  f.h_level_ptr = S->h_level_ptr.data(); f.h_level_maxs = S->h_level_maxs.data(); f.h_level_maxr = S->h_level_maxr.data();
+  f.rows = S->frows.p; f.panel = S->panel.p; f.dinv = S->dinv.p; f.dinvT = S->dinvT.p;
+  f.fwd_ptr = S->fptr.p; f.fwd_col = S->fcol.p; f.fwd_val = S->fval.p;
+  f.sigma_inv = S->sigma_inv.p; f.ext2vert = S->ext2vert.p;
+
+  // ---- contact buffers ---------------------------------------------------------------------------------
+  S->px = ProxyDev{S->nsv, S->nst, S->nse, S->sv.p, S->stri.p, S->sedge.p};
+  S->vbox.ensure(6LL * std::max(S->nsv, 1));
+  S->tbox.ensure(6LL * std::max(S->nst, 1));
+  S->ebox.ensure(6LL * std::max(S->nse, 1));
+  S->params.ensure(8 + 4 * 64);
+  int bits = 10;
+  while ((1LL << bits) < 4LL * (S->nst + S->nse) && bits < 28) ++bits;
+  const int64_t T = 1LL << bits;
+  const int64_t ent = 27LL * std::max(S->nst, S->nse) + 64;
+  for (auto* b : {&S->t_count, &S->t_cursor, &S->e_count, &S->e_cursor}) b->ensure(T + 1);
+  S->t_id.ensure(ent); S->e_id.ensure(ent); S->t_key.ensure(ent); S->e_key.ensure(ent);
+  S->q_count.ensure(static_cast<int64_t>(S->nsv) + S->nse + 1);
+  S->totals.ensure(8);
+  const int64_t scan_n = std::max<int64_t>({T + 1, static_cast<int64_t>(S->nsv) + S->nse + 1, static_cast<int64_t>(n) + 1});
+  S->scan_tmp.ensure(static_cast<int64_t>(scan_temp_bytes(scan_n)));
+  S->red_tmp.ensure(static_cast<int64_t>(sum_temp_bytes(0)) + 4096);
+  BroadPhaseBuffers& bb = S->bb;
+  bb.vbox = S->vbox.p; bb.tbox = S->tbox.p; bb.ebox = S->ebox.p; bb.params = S->params.p;
+  bb.table_bits = bits;
+  bb.t_count = S->t_count.p; bb.t_cursor = S->t_cursor.p; bb.t_id = S->t_id.p; bb.t_key = S->t_key.p;
+  bb.e_count = S->e_count.p; bb.e_cursor = S->e_cursor.p; bb.e_id = S->e_id.p; bb.e_key = S->e_key.p;
+  bb.ent_cap = ent; bb.q_count = S->q_count.p; bb.d_totals = S->totals.p;
+  bb.scan_temp = S->scan_tmp.p; bb.red_temp = S->red_tmp.p;
+  for (auto* b : {&S->inc_cnt, &S->inc_ptr, &S->inc_cflag, &S->inc_cidx}) b->ensure(n + 1);
+  S->inc_cursor.ensure(n);
+  S->inc_clist.ensure(n);
+  S->inc_nc.ensure(2);
+  HIPCHK(hipStreamSynchronize(st));
+  return PDIPC_OK;
+}
+
+static void grow_pairs(Solver* S, PairList& pl, DBuf<int32_t>& ty, DBuf<int32_t>& ii, DBuf<int32_t>& jj,
+                       DBuf<int32_t>& v4, int64_t need) {
+  int64_t cap = std::max<int64_t>(need + need / 2 + 256, pl.cap);
+  ty.ensure(cap); ii.ensure(cap); jj.ensure(cap); v4.ensure(4 * cap);
+  pl.type = ty.p; pl.i = ii.p; pl.j = jj.p; pl.v4 = v4.p; pl.cap = cap;
+}
+
+// constraint set (dist) or swept candidates (dx != null)
+static void pairs(Solver* S, bool active, const double* xx, const double* dxx, int32_t* npt, int32_t* nee) {
+  PairList& pl = active ? S->act : S->cand;
+  auto& ty = active ? S->act_type : S->cand_type;
+  auto& ii = active ? S->act_i : S->cand_i;
+  auto& jj = active ? S->act_j : S->cand_j;
+  auto& v4 = active ? S->act_v4 : S->cand_v4;
+  if (pl.cap == 0) grow_pairs(S, pl, ty, ii, jj, v4, 4LL * S->nsv + 1024);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    int64_t need = 0;
+    int rc = find_pairs(S->px, S->bb, xx, dxx, S->opt.dhat, active, pl, npt, nee, S->st, &need);
+    if (rc == 0) return;
+    if (rc < 0) fail(PDIPC_E_HIP, "broad phase overflow");
+    grow_pairs(S, pl, ty, ii, jj, v4, need);
+  }
+  fail(PDIPC_E_NOMEM, "pair list growth failed");
+}
+
+static void ensure_pair_arrays(Solver* S, int64_t np) {
+  int64_t cap = std::max<int64_t>(np, 1);
+  if (S->b_energy.cap < cap) {
+    int64_t c = cap + cap / 2 + 256;
+    S->b_energy.ensure(c); S->b_grad.ensure(12 * c); S->b_U.ensure(60 * c); S->inc_ent.ensure(4 * c);
+    S->wtmp.ensure(5 * c);
+  }
+  S->bo = BarrierOut{S->b_energy.p, S->b_grad.p, S->b_U.p};
+  S->inc = Incidence{S->inc_cnt.p, S->inc_ptr.p, S->inc_cursor.p, S->inc_ent.p, S->inc_cflag.p, S->inc_cidx.p,
+                     S->inc_clist.p, S->inc_nc.p};
+}
+
+static LocalArgs local_args(Solver* S) { return LocalArgs{S->m, S->tets.p, S->Bm.p, S->w.p, S->A.p}; }
+
+static double read_scalar_d(Solver* S, const double* dptr) {
+  HIPCHK(hipMemcpyAsync(S->h_scal, dptr, sizeof(double), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  return S->h_scal[0];
+}
+static int32_t read_scalar_i(Solver* S, const int32_t* dptr) {
+  int32_t v = 0;
+  HIPCHK(hipMemcpyAsync(S->h_scal, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  std::memcpy(&v, S->h_scal, sizeof(int32_t));
+  return v;
+}
+
+struct IterOut {
+  int32_t npt = 0, nee = 0, nc = 0, ncand = 0, halvings = 0;
+  bool ls_ok = true;
+  double alpha_m = 1.0, alpha = 0.0;
+};
+
+// Local step + constraint set + barrier + gradient; returns pair counts, n_c.
+static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
+  const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
+  hipStream_t st = S->st;
+  {
+    ScopedTimer tm(S, TK_LOCAL);
+    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st);
+  }
+  launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
+  pairs(S, true, S->x.p, nullptr, &io.npt, &io.nee);
+  const int32_t np = io.npt + io.nee;
+  ensure_pair_arrays(S, np);
+  if (first_check && np > 0) {
+    S->tpair.ensure(np);
+    launch_pair_min_dist2(S->act, np, io.npt, S->x.p, S->tpair.p, st);
+    launch_min_clamp1(S->tpair.p, np, S->scal.p, S->red_tmp.p, st);
+    double dmin2 = read_scalar_d(S, S->scal.p);
+    if (!(dmin2 > 0.0)) fail(PDIPC_E_INTERSECTING, "input state has a contact pair at distance 0");
+  }
+  {
+    ScopedTimer tm(S, TK_BARRIER);
+    launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->opt.kappa, fp32, S->bo, st);
+  }
+  build_incidence(S->act, np, S->n, S->fixed.p, S->inc, S->scan_tmp.p, st);
+  launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
+  io.nc = read_scalar_i(S, S->inc.d_nc);
+}
+
+// Global step of Eq. (4) via Eq. (7) and (11): dx from g.
+static void global_step(Solver* S, const IterOut& io) {
+  hipStream_t st = S->st;
+  FactorDev& f = S->fd;
+  const int32_t np = io.npt + io.nee, nc = io.nc;
+  const int64_t n1x3 = 3LL * f.n1;
+  launch_pack_rhs(f, S->g.p, S->bvec.p, st);
+  {
+    ScopedTimer tm(S, TK_FWD);
+    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
+  }
+  {
+    ScopedTimer tm(S, TK_SIGMA_GEMV);
+    launch_sigma_gemv(f, S->yvec.p + n1x3, S->solvec.p + n1x3, st);
+  }
+  if (nc > 0) {
+    const int64_t N3 = 3LL * nc;
+    S->c_x2.ensure(nc);
+    S->Cs.ensure(static_cast<int64_t>(nc) * nc);
+    S->Cinv.ensure(static_cast<int64_t>(nc) * nc);
+    S->work.ensure(static_cast<int64_t>(nc) * nc);
+    S->Mred.ensure(N3 * N3);
+    S->rhs.ensure(N3);
+    S->u.ensure(N3);
+    S->vvec.ensure(N3);
+    launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
+    launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, st);
+    dense_cholesky<double>(S->Cs.p, nc, S->info.p, st);
+    dense_chol_inverse<double>(S->Cs.p, nc, S->Cinv.p, S->work.p, st);
+    launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
+    launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
+    if (S->opt.precision == PDIPC_MIXED_FP32) {
+      // FP32 factor of the reduced system, refined against FP64 residuals
+      S->Mf.ensure(N3 * N3);
+      S->uf.ensure(N3);
+      S->resid.ensure(N3);
+      launch_convert_f64_f32(S->Mred.p, S->Mf.p, N3 * N3, st);
+      dense_cholesky<float>(S->Mf.p, N3, S->info.p + 1, st);
+      if (read_scalar_i(S, S->info.p + 1) != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD (FP32)");
+      launch_fill_f64(S->u.p, N3, 0.0, st);
+      HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
+      for (int it = 0; it < 4; ++it) {
+        launch_convert_f64_f32(S->resid.p, S->uf.p, N3, st);
+        dense_chol_solve<float>(S->Mf.p, N3, S->uf.p, 1, st);
+        launch_convert_f32_f64(S->uf.p, S->vvec.p, N3, st);
+        launch_axpy_positions(N3, 1.0, S->vvec.p, S->u.p, st);
+        launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
+      }
+    } else {
+      {
+        ScopedTimer tm(S, TK_REDUCED_CHOL);
+        dense_cholesky<double>(S->Mred.p, N3, S->info.p, st);
+      }
+      if (read_scalar_i(S, S->info.p) != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
+      HIPCHK(hipMemcpyAsync(S->u.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
+      dense_chol_solve<double>(S->Mred.p, N3, S->u.p, 1, st);
+    }
+    launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
+    launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
+  }
+  {
+    ScopedTimer tm(S, TK_BWD);
+    launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
+  }
+  launch_unpack(f, S->n, S->solvec.p, S->dx.p, st);
+}
+
+// CCD bound and back-tracking line search; updates x.
+static void step_and_search(Solver* S, IterOut& io, bool apply) {
+  hipStream_t st = S->st;
+  const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
+  int32_t cpt = 0, cee = 0;
+  pairs(S, false, S->x.p, S->dx.p, &cpt, &cee);
+  const int32_t ncand = cpt + cee;
+  io.ncand = ncand;
+  S->tpair.ensure(std::max(ncand, 1));
+  S->bE0.ensure(std::max(ncand, 1));
+  S->bdE.ensure(std::max(ncand, 1));
+  {
+    ScopedTimer tm(S, TK_CCD);
+    launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p, st);
+  }
+  launch_min_clamp1(S->tpair.p, ncand, S->scal.p, S->red_tmp.p, st);
+  io.alpha_m = read_scalar_d(S, S->scal.p);
+  launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, nullptr, 0.0, S->opt.dhat, S->opt.kappa, nullptr, S->bE0.p, st);
+  double alpha = io.alpha_m;
+  io.ls_ok = false;
+  int h = 0;
+  for (; h <= S->opt.ls_max_halvings; ++h) {
+    {
+      ScopedTimer tm(S, TK_TRIAL);
+      launch_trial_energy(local_args(S), S->x.p, S->dx.p, alpha, S->E0.p, S->dE.p, fp32, st);
+    }
+    launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, alpha, S->opt.dhat, S->opt.kappa, S->bE0.p,
+                               S->bdE.p, st);
+    launch_sum2(S->dE.p, S->m, S->bdE.p, ncand, S->scal.p + 1, S->red_tmp.p, st);
+    double dEtot = read_scalar_d(S, S->scal.p + 1);
+    if (dEtot <= 0.0) {
+      io.ls_ok = true;
+      break;
+    }
+    alpha *= 0.5;
+  }
+  io.halvings = h;
+  io.alpha = io.ls_ok ? alpha : 0.0;
+  if (apply && io.alpha > 0.0) launch_axpy_positions(3LL * S->n, io.alpha, S->dx.p, S->x.p, st);
+}
+
+static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdipc_frame_stats* stats) {
+  if (!S->have_actuation) fail(PDIPC_E_INVALID, "no actuation set");
+  if (!x_in || !x_out) fail(PDIPC_E_INVALID, "null state pointer");
+  hipStream_t st = S->st;
+  auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipMemcpyAsync(S->x.p, x_in, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
+  launch_count_nonfinite(S->x.p, 3LL * S->n, S->info.p + 2, st);
+  if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite input state");
+  pdipc_frame_stats fs{};
+  fs.alpha_m_min = 1.0;
+  fs.alpha_min = 1.0;
+  int32_t rc = PDIPC_OK;
+  const bool tol_mode = S->opt.tol > 0;
+  double tms[5] = {0, 0, 0, 0, 0};
+  int it = 0;
+  for (; it < S->opt.iters; ++it) {
+    IterOut io;
+    auto a = std::chrono::steady_clock::now();
+    assemble_gradient(S, it == 0, io);
+    auto b = std::chrono::steady_clock::now();
+    global_step(S, io);
+    if (stats) HIPCHK(hipStreamSynchronize(st));
+    auto c = std::chrono::steady_clock::now();
+    step_and_search(S, io, true);
+    auto d = std::chrono::steady_clock::now();
+    tms[0] += std::chrono::duration<double, std::milli>(b - a).count();
+    tms[1] += std::chrono::duration<double, std::milli>(c - b).count();
+    tms[3] += std::chrono::duration<double, std::milli>(d - c).count();
+    if (S->timer_which >= 0) {
+      HIPCHK(hipStreamSynchronize(st));
+      harvest_timer(S);
+    }
+    fs.n_pt = io.npt;
+    fs.n_ee = io.nee;
+    fs.n_c = std::max(fs.n_c, io.nc);
+    fs.n_candidates = io.ncand;
+    fs.ls_halvings += io.halvings;
+    if (!io.ls_ok) { fs.ls_failures++; rc = PDIPC_W_LS_FAILED; }
+    fs.alpha_m_min = std::min(fs.alpha_m_min, io.alpha_m);
+    fs.alpha_min = std::min(fs.alpha_min, io.alpha);
+    if (tol_mode) {
+      launch_max_abs(S->dx.p, 3LL * S->n, S->scal.p + 2, S->red_tmp.p, st);
+      double step = read_scalar_d(S, S->scal.p + 2) * io.alpha;
+      if (step <= S->opt.tol) { ++it; break; }
+    }
+  }
+  fs.iters = it;
+  if (tol_mode && it >= S->opt.iters && rc == PDIPC_OK) rc = PDIPC_W_NOT_CONVERGED;
+  HIPCHK(hipMemcpyAsync(x_out, S->x.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  S->have_solution = true;
+  auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    fs.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    fs.ms_ipc = tms[0];
+    fs.ms_gstep = tms[1];
+    fs.ms_ls = tms[3];
+    fs.ms_misc = fs.ms_total - tms[0] - tms[1] - tms[3];
+    *stats = fs;
+  }
+  return rc;
+}
+
+}  // namespace pdipc
+
+using namespace pdipc;
+
+template <typename F>
+static int32_t guarded(Solver* S, F&& fn) {
+  try {
+    return fn();
+  } catch (const SolverError& e) {
+    if (S) S->err = e.msg;
+    return e.code;
+  } catch (const HipFailure& e) {
+    if (S) S->err = e.msg;
+    return PDIPC_E_HIP;
+  } catch (const std::bad_alloc&) {
+    if (S) S->err = "host allocation failed";
+    return PDIPC_E_NOMEM;
+  } catch (...) {
+    if (S) S->err = "unexpected exception";
+    return PDIPC_E_INVALID;
+  }
+}
+
+extern "C" {
+
+void pdipc_default_options(pdipc_options* o) {
+  if (!o) return;
+  o->dhat = 5e-4;
+  o->kappa = 1e3;
+  o->iters = 30;
+  o->tol = 0.0;
+  o->precision = PDIPC_FP64;
+  o->ccd_eta = 0.1;
+  o->ccd_steps = 16;
+  o->ls_max_halvings = 20;
+  o->stream = nullptr;
+}
+
+int32_t pdipc_init_mesh(const pdipc_mesh_desc* mesh, const pdipc_options* opt, void** out) {
+  if (!out) return PDIPC_E_INVALID;
+  *out = nullptr;
+  Solver* S = nullptr;
+  try {
+    S = new Solver();
+  } catch (...) {
+    g_last_init_error = "host allocation failed";
+    return PDIPC_E_NOMEM;
+  }
+  int32_t rc = guarded(S, [&] { return do_init(mesh, opt, S); });
+  if (rc != PDIPC_OK) {
+    g_last_init_error = S->err;
+    delete S;
+    return rc;
+  }
+  *out = S;
+  return PDIPC_OK;
+}
+
+int32_t pdipc_set_actuation(void* h, const double* A) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S || !A) return PDIPC_E_INVALID;
+  return guarded(S, [&] {
+    launch_actuation_transpose(S->m, A, S->A.p, S->st);
+    HIPCHK(hipStreamSynchronize(S->st));
+    S->have_actuation = true;
+    S->have_scalar = false;
+    return PDIPC_OK;
+  });
+}
+
+int32_t pdipc_set_actuation_scalar(void* h, const double* a, const double* R) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S || !a) return PDIPC_E_INVALID;
+  return guarded(S, [&] {
+    if (!R && !S->have_scalar) fail(PDIPC_E_INVALID, "no actuation frames given yet");
+    HIPCHK(hipMemcpyAsync(S->a_s.p, a, sizeof(double) * S->m, hipMemcpyDeviceToDevice, S->st));
+    if (R) HIPCHK(hipMemcpyAsync(S->R0.p, R, sizeof(double) * 9 * S->m, hipMemcpyDeviceToDevice, S->st));
+    launch_actuation_scalar(S->m, S->a_s.p, S->R0.p, S->A.p, S->st);
+    HIPCHK(hipStreamSynchronize(S->st));
+    S->have_actuation = true;
+    S->have_scalar = true;
+    return PDIPC_OK;
+  });
+}
+
+int32_t pdipc_solve_frame(void* h, const double* x_in, double* x_out, pdipc_frame_stats* stats) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S) return PDIPC_E_INVALID;
+  return guarded(S, [&] { return do_solve_frame(S, x_in, x_out, stats); });
+}
+
+int32_t pdipc_solve_frame_backward(void* h, const double* dL_dx, double* dL_da) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S || !dL_dx || !dL_da) return PDIPC_E_INVALID;
+  S->err = "backward pass not available in this build";
+  return PDIPC_E_INVALID;
+}
+
+int32_t pdipc_get_sizes(const void* h, int64_t* n1, int64_t* n2, int64_t* nnz) {
+  const Solver* S = static_cast<const Solver*>(h);
+  if (!S) return PDIPC_E_INVALID;
+  if (n1) *n1 = S->n1;
+  if (n2) *n2 = S->n2;
+  if (nnz) *nnz = S->factor_nnz;
+  return PDIPC_OK;
+}
+
+void pdipc_destroy(void* h) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S) return;
+  if (S->st) (void)hipStreamSynchronize(S->st);
+  DBuf<int32_t>* bi[] = {&S->tets, &S->vt_ptr, &S->vt_ent, &S->sv, &S->stri, &S->sedge, &S->node_c0, &S->node_s,
+                         &S->node_r, &S->level_nodes, &S->frows, &S->fcol, &S->ext2vert, &S->vert2x2, &S->t_count,
+                         &S->t_cursor, &S->t_id, &S->e_count, &S->e_cursor, &S->e_id, &S->q_count, &S->totals,
+                         &S->act_type, &S->act_i, &S->act_j, &S->act_v4, &S->cand_type, &S->cand_i, &S->cand_j,
+                         &S->cand_v4, &S->inc_cnt, &S->inc_ptr, &S->inc_cursor, &S->inc_ent, &S->inc_cflag,
+                         &S->inc_cidx, &S->inc_clist, &S->inc_nc, &S->c_x2, &S->info};
+  for (auto* b : bi) b->release();
+  DBuf<double>* bd[] = {&S->Bm, &S->w, &S->A, &S->a_s, &S->R0, &S->X, &S->x, &S->g, &S->dx, &S->tetg, &S->E0,
+                        &S->dE, &S->Rtet, &S->tpair, &S->bE0, &S->bdE, &S->scal, &S->panel, &S->dinv, &S->dinvT,
+                        &S->fval, &S->sigma_inv, &S->bvec, &S->yvec, &S->solvec, &S->vbox, &S->tbox, &S->ebox,
+                        &S->params, &S->b_energy, &S->b_grad, &S->b_U, &S->Cs, &S->Cinv, &S->work, &S->Mred,
+                        &S->rhs, &S->u, &S->vvec, &S->wtmp, &S->resid};
+  for (auto* b : bd) b->release();
+  S->fixed.release();
+  S->node_roff.release(); S->node_poff.release(); S->node_doff.release(); S->fptr.release();
+  S->t_key.release(); S->e_key.release(); S->scan_tmp.release(); S->red_tmp.release();
+  S->Mf.release(); S->uf.release();
+  delete S;
+}
+
+int32_t pdipc_kernel_timer(void* h, int32_t which, double* total_ms, int64_t* launches) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S) return PDIPC_E_INVALID;
+  if (total_ms) *total_ms = S->timer_ms;
+  if (launches) *launches = S->timer_count;
+  S->timer_which = which;
+  S->timer_ms = 0.0;
+  S->timer_count = 0;
+  S->ev_used = 0;
+  return PDIPC_OK;
+}
+
+const char* pdipc_last_error(const void* h) {
+  const Solver* S = static_cast<const Solver*>(h);
+  return S ? S->err.c_str() : g_last_init_error.c_str();
+}
+
+int32_t pdipc_debug_local(void* h, const double* x, double* R, double* energies, double* grad) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S || !x) return PDIPC_E_INVALID;
+  return guarded(S, [&] {
+    if (!S->have_actuation) fail(PDIPC_E_INVALID, "no actuation set");
+    const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
+    launch_local_step(local_args(S), x, S->Rtet.p, S->E0.p, S->tetg.p, fp32, S->st);
+    launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, S->st);
+    if (R) {
+      // SoA 9 x m -> m x 9 through the host (debug path)
+      std::vector<double> h9(9LL * S->m), o9(9LL * S->m);
+      HIPCHK(hipMemcpyAsync(h9.data(), S->Rtet.p, sizeof(double) * 9 * S->m, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipStreamSynchronize(S->st));
+      for (int64_t i = 0; i < S->m; ++i)
+        for (int e = 0; e < 9; ++e) o9[9 * i + e] = h9[e * S->m + i];
+      HIPCHK(hipMemcpyAsync(R, o9.data(), sizeof(double) * 9 * S->m, hipMemcpyHostToDevice, S->st));
+    }
+    if (energies) HIPCHK(hipMemcpyAsync(energies, S->E0.p, sizeof(double) * S->m, hipMemcpyDeviceToDevice, S->st));
+    if (grad) HIPCHK(hipMemcpyAsync(grad, S->g.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+    return PDIPC_OK;
+  });
+}
+
+int32_t pdipc_debug_contacts(void* h, const double* x, int32_t* out, int32_t cap, int32_t* count) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S || !x || !count) return PDIPC_E_INVALID;
+  return guarded(S, [&] {
+    int32_t npt = 0, nee = 0;
+    pairs(S, true, x, nullptr, &npt, &nee);
+    const int32_t np = npt + nee;
+    *count = np;
+    if (out && np > 0) {
+      std::vector<int32_t> ty(np), ii(np), jj(np), o(3LL * np);
+      HIPCHK(hipMemcpyAsync(ty.data(), S->act.type, sizeof(int32_t) * np, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(ii.data(), S->act.i, sizeof(int32_t) * np, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipMemcpyAsync(jj.data(), S->act.j, sizeof(int32_t) * np, hipMemcpyDeviceToHost, S->st));
+      HIPCHK(hipStreamSynchronize(S->st));
+      const int32_t k = std::min(np, cap);
+      for (int32_t p = 0; p < k; ++p) { o[3 * p] = ty[p]; o[3 * p + 1] = ii[p]; o[3 * p + 2] = jj[p]; }
+      if (k > 0) HIPCHK(hipMemcpyAsync(out, o.data(), sizeof(int32_t) * 3 * k, hipMemcpyHostToDevice, S->st));
+      HIPCHK(hipStreamSynchronize(S->st));
+    }
+    return PDIPC_OK;
+  });
+}
+
+int32_t pdipc_debug_step(void* h, const double* x, double* dx, double* alpha_m, double* alpha) {
+  Solver* S = static_cast<Solver*>(h);
+  if (!S || !x) return PDIPC_E_INVALID;
+  return guarded(S, [&] {
+    if (!S->have_actuation) fail(PDIPC_E_INVALID, "no actuation set");
+    HIPCHK(hipMemcpyAsync(S->x.p, x, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
+    IterOut io;
+    assemble_gradient(S, true, io);
+    global_step(S, io);
+    step_and_search(S, io, false);
+    if (dx) HIPCHK(hipMemcpyAsync(dx, S->dx.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
+    HIPCHK(hipStreamSynchronize(S->st));
+    if (alpha_m) *alpha_m = io.alpha_m;
+    if (alpha) *alpha = io.alpha;
+    return PDIPC_OK;
+  });
+}
+
+// Host-only check of the set-up factorization (no device work): solves
+// H x = b over the free block with the supernodal factor and a dense
+// Cholesky of Sigma_s on the host, and returns Sigma_s.  Test tap.
+int32_t pdipc_debug_host_factor(int32_t n1, int32_t n2, const double* coords1, const int64_t* ptr,
+                                const int32_t* col, const double* val, int32_t leaf, const double* b, double* x,
+                                double* sigma_out, int64_t* nnz_out) {
+  try {
+    ScalarCSR H;
+    const int32_t N = n1 + n2;
+    H.n = N;
+    H.ptr.assign(ptr, ptr + N + 1);
+    H.col.assign(col, col + ptr[N]);
+    H.val.assign(val, val + ptr[N]);
+    HostFactor hf;
+    std::string e;
+    int rc = build_host_factor(n1, n2, coords1, H, leaf, hf, e);
+    if (rc) return PDIPC_E_NOT_SPD;
+    if (nnz_out) *nnz_out = hf.factor_nnz;
+    if (sigma_out) std::copy(hf.sigma.begin(), hf.sigma.end(), sigma_out);
+    if (!b || !x) return PDIPC_OK;
+    // extended rhs: x1 in dissection order, x2 unchanged
+    std::vector<double> be(N), y(N), sol(N);
+    for (int32_t p = 0; p < n1; ++p) be[p] = b[hf.perm[p]];
+    for (int32_t q = 0; q < n2; ++q) be[n1 + q] = b[n1 + q];
+    const int nn = static_cast<int>(hf.nodes.size());
+    std::vector<int> order(nn);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return hf.nodes[a].level < hf.nodes[c].level; });
+    for (int J : order) {
+      const FactorNode& nd = hf.nodes[J];
+      std::vector<double> t(nd.s);
+      for (int r = 0; r < nd.s; ++r) {
+        int64_t row = nd.c0 + r;
+        double acc = 0;
+        for (int64_t q = hf.fwd_ptr[row]; q < hf.fwd_ptr[row + 1]; ++q) acc += hf.fwd_val[q] * y[hf.fwd_col[q]];
+        t[r] = be[row] - acc;
+      }
+      const double* D = hf.dinv.data() + nd.dinv_off;
+      for (int r = 0; r < nd.s; ++r) {
+        double acc = 0;
+        for (int c = 0; c <= r; ++c) acc += D[static_cast<int64_t>(r) * nd.s + c] * t[c];
+        y[nd.c0 + r] = acc;
+      }
+    }
+    for (int32_t q = 0; q < n2; ++q) {
+      int64_t row = n1 + q;
+      double acc = 0;
+      for (int64_t e2 = hf.fwd_ptr[row]; e2 < hf.fwd_ptr[row + 1]; ++e2) acc += hf.fwd_val[e2] * y[hf.fwd_col[e2]];
+      y[row] = be[row] - acc;
+    }
+    // dense Sigma_s solve on the host (Cholesky, test only)
+    std::vector<double> Lc(hf.sigma);
+    for (int32_t j = 0; j < n2; ++j) {
+      double d = Lc[static_cast<size_t>(j) * n2 + j];
+      for (int32_t k = 0; k < j; ++k) d -= Lc[static_cast<size_t>(j) * n2 + k] * Lc[static_cast<size_t>(j) * n2 + k];
+      if (!(d > 0)) return PDIPC_E_NOT_SPD;
+      d = std::sqrt(d);
+      Lc[static_cast<size_t>(j) * n2 + j] = d;
+      for (int32_t i = j + 1; i < n2; ++i) {
+        double s = Lc[static_cast<size_t>(i) * n2 + j];
+        for (int32_t k = 0; k < j; ++k) s -= Lc[static_cast<size_t>(i) * n2 + k] * Lc[static_cast<size_t>(j) * n2 + k];
+        Lc[static_cast<size_t>(i) * n2 + j] = s / d;
+      }
+    }
+    std::vector<double> z(n2);
+    for (int32_t i = 0; i < n2; ++i) {
+      double s = y[n1 + i];
+      for (int32_t k = 0; k < i; ++k) s -= Lc[static_cast<size_t>(i) * n2 + k] * z[k];
+      z[i] = s / Lc[static_cast<size_t>(i) * n2 + i];
+    }
+    for (int32_t i = n2 - 1; i >= 0; --i) {
+      double s = z[i];
+      for (int32_t k = i + 1; k < n2; ++k) s -= Lc[static_cast<size_t>(k) * n2 + i] * sol[n1 + k];
+      sol[n1 + i] = s / Lc[static_cast<size_t>(i) * n2 + i];
+    }
+    for (int oi = nn - 1; oi >= 0; --oi) {
+      const FactorNode& nd = hf.nodes[order[oi]];
+      const int32_t* R = hf.rows.data() + nd.rows_off;
+      const double* P = hf.panel.data() + nd.panel_off;
+      std::vector<double> t(nd.s);
+      for (int c = 0; c < nd.s; ++c) {
+        double acc = y[nd.c0 + c];
+        for (int i = 0; i < nd.r; ++i) acc -= P[static_cast<int64_t>(i) * nd.s + c] * sol[R[i]];
+        t[c] = acc;
+      }
+      const double* D = hf.dinv.data() + nd.dinv_off;
+      for (int c = 0; c < nd.s; ++c) {
+        double acc = 0;
+        for (int r = c; r < nd.s; ++r) acc += D[static_cast<int64_t>(r) * nd.s + c] * t[r];
+        sol[nd.c0 + c] = acc;
+      }
+    }
+    for (int32_t p = 0; p < n1; ++p) x[hf.perm[p]] = sol[p];
+    for (int32_t q = 0; q < n2; ++q) x[n1 + q] = sol[n1 + q];
+    return PDIPC_OK;
+  } catch (...) {
+    return PDIPC_E_INVALID;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Every comparison uses the same seeded inputs on both sides.  Tolerances:
+contact sets bit-exact; FP64 quantities within 1e-9 relative unless stated.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+from oracle import contact as ocontact, fem as ofem, local as olocal, solver as osolver
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solver(sc, **kw):
+    from paper_2312_02999_amd import Solver
+    return Solver(sc, **kw)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _set_act(S, sc, t):
+    a = sc.actuation_at(t)
+    S.set_actuation_scalar(_t(a), _t(sc.act_R.reshape(-1, 9)))
+    return ofem.actuation_matrices(a, sc.act_R)
+
+
+def _pressed(sc, depth, seed=0, amp=5e-5):
+    """Upper slab pushed down by ``depth`` plus a small seeded perturbation."""
+    x = sc.X.copy()
+    top = sc.X[:, 2].max()
+    upper = sc.X[:, 2] > 0.5 * top
+    x[upper, 2] -= depth
+    rng = np.random.default_rng(seed)
+    x += rng.uniform(-amp, amp, x.shape) * (sc.dirichlet[:, None] == 0)
+    return x
+
+
+def test_native_library_is_the_hip_path():
+    from paper_2312_02999_amd import _lib
+    _lib.lib()
+    assert len(_lib.hip_runtimes_loaded()) == 1
+
+
+def test_local_step_parity_c1():
+    sc = mg.slabs(0)
+    S = _solver(sc)
+    A = _set_act(S, sc, 0.6)
+    rng = np.random.default_rng(3)
+    x = sc.X + 1e-3 * rng.standard_normal(sc.X.shape) * (sc.dirichlet[:, None] == 0)
+    R, E, g = S.debug_local(_t(x))
+    prob = osolver.setup_scene(sc)
+    F = olocal.deformation_gradients(x, prob.tets, prob.B)
+    Ro, P = olocal.projections(F, A)
+    Eo = 0.5 * prob.w * np.sum((F - P) ** 2, axis=(1, 2))
+    go = osolver.pd_gradient(prob, F, P).reshape(-1, 3) * (sc.dirichlet[:, None] == 0)
+    assert np.abs(R.cpu().numpy().reshape(-1, 3, 3) - Ro).max() < 1e-11
+    assert np.allclose(E.cpu().numpy(), Eo, rtol=1e-10, atol=1e-12 * Eo.max())
+    assert np.abs(g.cpu().numpy() - go).max() < 1e-10 * np.abs(go).max()
+
+
+@pytest.mark.parametrize("depth", [7e-4, 9e-4])
+def test_contact_set_bit_exact_c1(depth):
+    sc = mg.slabs(0)
+    S = _solver(sc)
+    x = _pressed(sc, depth)
+    pairs = S.debug_contacts(_t(x))
+    cs = ocontact.constraint_set(x, ocontact.make_proxy(sc.surf_tris), sc.dhat)
+    ref = np.concatenate([np.c_[np.zeros(len(cs.pt), np.int64), cs.pt],
+                          np.c_[np.ones(len(cs.ee), np.int64), cs.ee]]).astype(np.int64)
+    assert len(ref) > 100
+    assert np.array_equal(pairs.astype(np.int64), ref)
+
+
+def test_contact_set_empty_when_apart():
+    sc = mg.slabs(0)
+    S = _solver(sc)
+    assert S.debug_contacts(_t(sc.X)).shape[0] == 0
+
+
+def test_single_iteration_parity_c1():
+    sc = mg.slabs(0)
+    S = _solver(sc)
+    A = _set_act(S, sc, 0.4)
+    x = _pressed(sc, 8e-4, seed=1)
+    dx, am, al = S.debug_step(_t(x))
+    prob = osolver.setup_scene(sc)
+    _, rec, _ = osolver.iteration(prob, x, A)
+    dxo = rec.dx
+    err = np.abs(dx.cpu().numpy() - dxo).max() / np.abs(dxo).max()
+    assert err < 1e-9, err
+    assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
+    assert abs(al - rec.alpha) <= 1e-9 * max(1.0, rec.alpha)
+
+
+def test_frames_tiny_scene():
+    sc = mg.scene_by_name("tiny")
+    S = _solver(sc, iters=sc.iters)
+    prob = osolver.setup_scene(sc)
+    x = sc.X.copy()
+    xg = _t(x)
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    for t in range(sc.frames):
+        A = _set_act(S, sc, (t + 1) / sc.frames)
+        xg, st = S.solve_frame(xg, stats=True)
+        r = osolver.frame(prob, x, A, iters=sc.iters)
+        x = r.x
+        err = np.abs(xg.cpu().numpy() - x).max() / diag
+        assert err < 1e-9, (t, err)
+
+
+def test_frame_c1_first_frame():
+    sc = mg.slabs(0)
+    S = _solver(sc)
+    prob = osolver.setup_scene(sc)
+    A = _set_act(S, sc, 1.0 / sc.frames)
+    xg, st = S.solve_frame(_t(sc.X), stats=True)
+    r = osolver.frame(prob, sc.X, A, iters=sc.iters)
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    err = np.abs(xg.cpu().numpy() - r.x).max() / diag
+    print(f"C1 frame 1: n_pt {st['n_pt']} n_ee {st['n_ee']} n_c {st['n_c']} err {err:.3e} ms {st['ms_total']:.1f}")
+    assert st["n_pt"] == r.n_pt[-1] and st["n_ee"] == r.n_ee[-1]
+    assert err < 1e-9, err
