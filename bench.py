@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="face50k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
+                    help="profile one path only (the JSON line then lacks the other)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver has no multi-GPU path); got --gpus {args.gpus}",
@@ -119,6 +121,11 @@ def main():
     from paper_2312_02999_amd import FP64, MIXED_FP32
 
     sc = mg.scene_by_name(args.workload)
+    if args.only:
+        r = run_precision(sc, FP64 if args.only == "fp64" else MIXED_FP32, args.steps, args.warmup, K_LOCAL)
+        r.pop("x_final")
+        print(json.dumps({"only": args.only, **r}))
+        return
     fp64 = run_precision(sc, FP64, args.steps, args.warmup, K_LOCAL)
     mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup, K_LOCAL)
     diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))

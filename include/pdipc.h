@@ -168,6 +168,14 @@ int32_t pdipc_debug_local(void* solver, const double* x, double* R, double* ener
 int32_t pdipc_debug_contacts(void* solver, const double* x, int32_t* pairs, int32_t cap, int32_t* count);
 int32_t pdipc_debug_step(void* solver, const double* x, double* dx, double* alpha_m, double* alpha);
 
+/* Dense SPD kernels on caller data (test tap, default stream): factor the
+ * device matrix A (n x n row-major, symmetric positive definite; not
+ * modified), solve A x = b in place for b (device n x nrhs, nrhs <= 4, may
+ * be NULL) and write A^-1 to Ainv (device n x n, may be NULL).  precision 1
+ * runs the FP32 kernels on a rounded copy.  PDIPC_E_NOT_SPD on a non-positive
+ * pivot. */
+int32_t pdipc_debug_dense(const double* A, int64_t n, double* b, int32_t nrhs, double* Ainv, int32_t precision);
+
 /* Host-only check of the set-up factorization (no device work, usable
  * without a GPU).  Input: the scalar PD matrix over free vertices in
  * extended order (x1 block [0, n1) with coordinates coords1 (n1 x 3), then

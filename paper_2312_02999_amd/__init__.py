@@ -134,6 +134,17 @@ class Solver:
         return dx, am.value, a.value
 
 
+def dense_spd(A: torch.Tensor, b: torch.Tensor | None = None, inverse: bool = False, precision: int = FP64):
+    """Dense SPD kernels on device data: returns (x or None, A^-1 or None)."""
+    n = A.shape[0]
+    x = None if b is None else b.clone().contiguous()
+    nrhs = 0 if x is None else (1 if x.dim() == 1 else x.shape[1])
+    inv = torch.empty_like(A) if inverse else None
+    check(lib().pdipc_debug_dense(_dev(A, (n, n)), n, _dev(x) if x is not None else None, nrhs,
+                                  _dev(inv) if inv is not None else None, int(precision)), None)
+    return x, inv
+
+
 def host_factor_solve(n1: int, n2: int, coords1, ptr, col, val, b=None, leaf: int = 96):
     """Host-only factor check (no GPU): returns (x, Sigma_s, factor_nnz)."""
     coords1 = np.ascontiguousarray(coords1, dtype=np.float64)

@@ -26,7 +26,7 @@ EXPORTS = [
     "pdipc_default_options", "pdipc_init_mesh", "pdipc_set_actuation", "pdipc_set_actuation_scalar",
     "pdipc_solve_frame", "pdipc_solve_frame_backward", "pdipc_get_sizes", "pdipc_destroy",
     "pdipc_last_error", "pdipc_debug_local", "pdipc_debug_contacts", "pdipc_debug_step",
-    "pdipc_debug_host_factor", "pdipc_kernel_timer",
+    "pdipc_debug_host_factor", "pdipc_kernel_timer", "pdipc_debug_dense",
 ]
 
 
@@ -96,6 +96,8 @@ def lib():
     L.pdipc_debug_host_factor.restype = i32
     L.pdipc_kernel_timer.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]
     L.pdipc_kernel_timer.restype = i32
+    L.pdipc_debug_dense.argtypes = [dp, i64, dp, i32, dp, i32]
+    L.pdipc_debug_dense.restype = i32
     _lib = L
     return L
 

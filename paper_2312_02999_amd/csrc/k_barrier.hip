@@ -20,42 +20,53 @@
 namespace pdipc {
 
 namespace {
-constexpr int BT = 128;
+constexpr int BT = 64;
 }
 
+// Cyclic Jacobi on a symmetric 5x5 (fixed size: fully unrolled, no scratch).
 template <typename T>
-__device__ void sym_eig_jacobi(T A[5][5], T V[5][5], int n) {
+__device__ __forceinline__ void sym_eig_jacobi5(T A[5][5], T V[5][5]) {
+#pragma unroll
   for (int i = 0; i < 5; ++i)
+#pragma unroll
     for (int j = 0; j < 5; ++j) V[i][j] = i == j ? T(1) : T(0);
-  for (int sweep = 0; sweep < 16; ++sweep) {
+  for (int sweep = 0; sweep < 12; ++sweep) {
     T off = T(0), dia = T(0);
-    for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
       dia += A[i][i] * A[i][i];
-      for (int j = i + 1; j < n; ++j) off += A[i][j] * A[i][j];
+#pragma unroll
+      for (int j = i + 1; j < 5; ++j) off += A[i][j] * A[i][j];
     }
     if (off == T(0) || off <= T(sizeof(T) == 8 ? 1e-32 : 1e-18) * dia) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 5; ++q) {
         T apq = A[p][q];
-        if (apq == T(0)) continue;
-        T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
-        T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
-        T c = T(1) / sqrt(t * t + T(1));
-        T s = t * c;
-        for (int k = 0; k < n; ++k) {
-          T akp = A[k][p], akq = A[k][q];
-          A[k][p] = c * akp - s * akq;
-          A[k][q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          T apk = A[p][k], aqk = A[q][k];
-          A[p][k] = c * apk - s * aqk;
-          A[q][k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          T vkp = V[k][p], vkq = V[k][q];
-          V[k][p] = c * vkp - s * vkq;
-          V[k][q] = s * vkp + c * vkq;
+        if (apq != T(0)) {
+          T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
+          T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+          T c = T(1) / sqrt(t * t + T(1));
+          T s = t * c;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            T akp = A[k][p], akq = A[k][q];
+            A[k][p] = c * akp - s * akq;
+            A[k][q] = s * akp + c * akq;
+          }
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            T apk = A[p][k], aqk = A[q][k];
+            A[p][k] = c * apk - s * aqk;
+            A[q][k] = s * apk + c * aqk;
+          }
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            T vkp = V[k][p], vkq = V[k][q];
+            V[k][p] = c * vkp - s * vkq;
+            V[k][q] = s * vkp + c * vkq;
+          }
         }
       }
   }
@@ -92,7 +103,6 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
   const T phi1 = kap * b1 / (T(2) * d);
   const T phi2 = kap * (b2 - b1 / d) / (T(4) * D);
   energy = static_cast<double>(kap * b0);
-  // grad D and its use as the barrier gradient
   T gD[12];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -100,44 +110,49 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
     for (int r = 0; r < 3; ++r) gD[3 * j + r] = T(2) * f.c[j] * q[r];
 #pragma unroll
   for (int i = 0; i < 12; ++i) grad[i] = static_cast<double>(phi1 * gD[i]);
-  // f_xb columns and f_bb
-  const int nb = f.nb;
+  // f_xb columns (zero for missing parameters) and f_bb^-1
+  const T use0 = f.nb >= 1 ? T(1) : T(0), use1 = f.nb >= 2 ? T(1) : T(0);
   T fxb[2][12];
-  for (int k = 0; k < nb; ++k)
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      fxb[0][3 * j + r] = use0 * (T(2) * f.dcdb[0][j] * q[r] + T(2) * f.c[j] * Dk[0][r]);
+      fxb[1][3 * j + r] = use1 * (T(2) * f.dcdb[1][j] * q[r] + T(2) * f.c[j] * Dk[1][r]);
+    }
+  T fbbi[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+  {
+    T b00 = T(2) * dot3(Dk[0], Dk[0]), b01 = T(2) * dot3(Dk[0], Dk[1]), b11 = T(2) * dot3(Dk[1], Dk[1]);
+    if (f.nb == 1) {
+      fbbi[0][0] = T(1) / b00;
+    } else if (f.nb == 2) {
+      T det = b00 * b11 - b01 * b01;
+      fbbi[0][0] = b11 / det;
+      fbbi[1][1] = b00 / det;
+      fbbi[0][1] = fbbi[1][0] = -b01 / det;
+    }
+  }
+  // orthonormal basis Q of span{C^T e_r, f_xb_k}: three C columns, then up to two more
+  T Q[5][12];
+  const T cn = sqrt(f.c[0] * f.c[0] + f.c[1] * f.c[1] + f.c[2] * f.c[2] + f.c[3] * f.c[3]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) fxb[k][3 * j + r] = T(2) * f.dcdb[k][j] * q[r] + T(2) * f.c[j] * Dk[k][r];
-  T fbb[2][2] = {{T(0), T(0)}, {T(0), T(0)}}, fbbi[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
-  for (int k = 0; k < nb; ++k)
-    for (int l = 0; l < nb; ++l) fbb[k][l] = T(2) * dot3(Dk[k], Dk[l]);
-  if (nb == 1) {
-    fbbi[0][0] = T(1) / fbb[0][0];
-  } else if (nb == 2) {
-    T det = fbb[0][0] * fbb[1][1] - fbb[0][1] * fbb[1][0];
-    fbbi[0][0] = fbb[1][1] / det;
-    fbbi[1][1] = fbb[0][0] / det;
-    fbbi[0][1] = -fbb[0][1] / det;
-    fbbi[1][0] = -fbb[1][0] / det;
-  }
-  // orthonormal basis Q (columns) of span{C^T e_r, f_xb_k}
-  T Q[5][12];
-  int nq = 0;
-  T cn = sqrt(f.c[0] * f.c[0] + f.c[1] * f.c[1] + f.c[2] * f.c[2] + f.c[3] * f.c[3]);
-  for (int r = 0; r < 3; ++r) {
+      for (int rr = 0; rr < 3; ++rr) Q[r][3 * j + rr] = rr == r ? f.c[j] / cn : T(0);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) Q[nq][i] = T(0);
+  for (int k = 0; k < 2; ++k) {
+    T v[12], n0 = T(0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Q[nq][3 * j + r] = f.c[j] / cn;
-    ++nq;
-  }
-  for (int k = 0; k < nb; ++k) {
-    T v[12];
-    T n0 = T(0);
+    for (int i = 0; i < 12; ++i) {
+      v[i] = fxb[k][i];
+      n0 += v[i] * v[i];
+    }
 #pragma unroll
-    for (int i = 0; i < 12; ++i) { v[i] = fxb[k][i]; n0 += v[i] * v[i]; }
     for (int pass = 0; pass < 2; ++pass)
-      for (int b = 0; b < nq; ++b) {
+#pragma unroll
+      for (int b = 0; b < 3 + k; ++b) {
         T pr = T(0);
 #pragma unroll
         for (int i = 0; i < 12; ++i) pr += Q[b][i] * v[i];
@@ -147,26 +162,25 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
     T nv = T(0);
 #pragma unroll
     for (int i = 0; i < 12; ++i) nv += v[i] * v[i];
-    if (nv > T(sizeof(T) == 8 ? 1e-28 : 1e-12) * n0 && nv > T(0)) {
-      T inv = T(1) / sqrt(nv);
+    const bool keep = nv > T(sizeof(T) == 8 ? 1e-28 : 1e-12) * n0 && nv > T(0);
+    const T inv = keep ? T(1) / sqrt(nv) : T(0);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) Q[nq][i] = v[i] * inv;
-      ++nq;
-    }
+    for (int i = 0; i < 12; ++i) Q[3 + k][i] = v[i] * inv;
   }
-  // projected Hessian Ht = Q^T H Q
+  // Ht = Q^T H Q with H = phi2 gD gD^T + phi1 (2 C^T C - f_xb f_bb^-1 f_bx)
   T qg[5], qf[5][2], cq[5][3];
-  for (int a = 0; a < nq; ++a) {
-    T s = T(0);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) s += Q[a][i] * gD[i];
-    qg[a] = s;
-    for (int k = 0; k < nb; ++k) {
-      T t = T(0);
+  for (int a = 0; a < 5; ++a) {
+    T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) t += Q[a][i] * fxb[k][i];
-      qf[a][k] = t;
+    for (int i = 0; i < 12; ++i) {
+      s0 += Q[a][i] * gD[i];
+      s1 += Q[a][i] * fxb[0][i];
+      s2 += Q[a][i] * fxb[1][i];
     }
+    qg[a] = s0;
+    qf[a][0] = s1;
+    qf[a][1] = s2;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       T t = T(0);
@@ -176,30 +190,37 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
     }
   }
   T Ht[5][5], V[5][5];
+#pragma unroll
   for (int a = 0; a < 5; ++a)
-    for (int b = 0; b < 5; ++b) Ht[a][b] = T(0);
-  for (int a = 0; a < nq; ++a)
-    for (int b = 0; b < nq; ++b) {
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
       T hd = T(2) * dot3(cq[a], cq[b]);
-      for (int k = 0; k < nb; ++k)
-        for (int l = 0; l < nb; ++l) hd -= qf[a][k] * fbbi[k][l] * qf[b][l];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) hd -= qf[a][k] * fbbi[k][l] * qf[b][l];
       Ht[a][b] = phi2 * qg[a] * qg[b] + phi1 * hd;
     }
-  for (int a = 0; a < nq; ++a)
-    for (int b = a + 1; b < nq; ++b) {
-      T s = T(0.5) * (Ht[a][b] + Ht[b][a]);
-      Ht[a][b] = s;
-      Ht[b][a] = s;
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 5; ++b) {
+      T sm = T(0.5) * (Ht[a][b] + Ht[b][a]);
+      Ht[a][b] = sm;
+      Ht[b][a] = sm;
     }
-  sym_eig_jacobi<T>(Ht, V, nq);
+  sym_eig_jacobi5<T>(Ht, V);
   T sq[5];
-  for (int a = 0; a < 5; ++a) sq[a] = a < nq && Ht[a][a] > T(0) ? sqrt(Ht[a][a]) : T(0);
+#pragma unroll
+  for (int a = 0; a < 5; ++a) sq[a] = Ht[a][a] > T(0) ? sqrt(Ht[a][a]) : T(0);
 #pragma unroll
   for (int i = 0; i < 12; ++i)
+#pragma unroll
     for (int e2 = 0; e2 < 5; ++e2) {
-      T s = T(0);
-      for (int a = 0; a < nq; ++a) s += Q[a][i] * V[a][e2];
-      U[i][e2] = static_cast<double>(s * sq[e2]);
+      T sm = T(0);
+#pragma unroll
+      for (int a = 0; a < 5; ++a) sm += Q[a][i] * V[a][e2];
+      U[i][e2] = static_cast<double>(sm * sq[e2]);
     }
 }
 
@@ -250,20 +271,41 @@ __global__ void inc_fill_kernel(const int32_t* __restrict__ v4, int32_t npairs, 
   }
 }
 
-// sort each vertex's incidence list; flag free touched vertices
-__global__ void inc_sort_flag_kernel(int32_t n, const int32_t* __restrict__ ptr, int32_t* __restrict__ ent,
-                                     const uint8_t* __restrict__ fixed, int32_t* __restrict__ cflag) {
+// Sort each proxy vertex's incidence list (keys are unique: 4 * pair + local),
+// one wave per vertex: every lane ranks its key against the others.  Lists
+// longer than a wave fall back to an insertion sort by one lane.
+__global__ void __launch_bounds__(256) inc_sort_kernel(int32_t nsv, const int32_t* __restrict__ sv,
+                                                       const int32_t* __restrict__ ptr, int32_t* __restrict__ ent) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
+  if (w >= nsv) return;
+  const int32_t v = sv[w];
+  const int32_t b = ptr[v], e = ptr[v + 1], cnt = e - b;
+  if (cnt <= 1) return;
+  if (cnt <= PDIPC_WAVE) {
+    int32_t key = lane < cnt ? ent[b + lane] : 0x7fffffff;
+    int32_t rank = 0;
+    for (int j = 0; j < cnt; ++j) {
+      int32_t kj = __shfl(key, j, PDIPC_WAVE);
+      rank += (kj < key) ? 1 : 0;
+    }
+    if (lane < cnt) ent[b + rank] = key;
+  } else if (lane == 0) {
+    for (int32_t i = b + 1; i < e; ++i) {
+      int32_t key = ent[i];
+      int32_t j = i - 1;
+      while (j >= b && ent[j] > key) { ent[j + 1] = ent[j]; --j; }
+      ent[j + 1] = key;
+    }
+  }
+}
+
+// cflag[v] = 1 for a free vertex touched by at least one pair
+__global__ void cflag_kernel(int32_t n, const int32_t* __restrict__ ptr, const uint8_t* __restrict__ fixed,
+                             int32_t* __restrict__ cflag) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v > n) return;
-  if (v == n) { cflag[n] = 0; return; }
-  int32_t b = ptr[v], e = ptr[v + 1];
-  for (int32_t i = b + 1; i < e; ++i) {
-    int32_t key = ent[i];
-    int32_t j = i - 1;
-    while (j >= b && ent[j] > key) { ent[j + 1] = ent[j]; --j; }
-    ent[j + 1] = key;
-  }
-  cflag[v] = (e > b && !fixed[v]) ? 1 : 0;
+  cflag[v] = (v < n && ptr[v + 1] > ptr[v] && !fixed[v]) ? 1 : 0;
 }
 
 __global__ void clist_kernel(int32_t n, const int32_t* __restrict__ cflag, const int32_t* __restrict__ cidx,
@@ -273,14 +315,15 @@ __global__ void clist_kernel(int32_t n, const int32_t* __restrict__ cflag, const
   if (cflag[v]) clist[cidx[v]] = v;
 }
 
-void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const uint8_t* fixed, Incidence& inc,
-                     void* scan_temp, hipStream_t st) {
+void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyDev& px, const uint8_t* fixed,
+                     Incidence& inc, void* scan_temp, hipStream_t st) {
   launch_fill_i32(inc.cnt, n + 1, 0, st);
   if (npairs > 0) inc_count_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cnt);
   launch_exclusive_scan(inc.cnt, inc.ptr, n + 1, inc.d_nc, scan_temp, st);
   hipMemcpyAsync(inc.cursor, inc.ptr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
   if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.ent);
-  inc_sort_flag_kernel<<<grid_for(n + 1, 256), 256, 0, st>>>(n, inc.ptr, inc.ent, fixed, inc.cflag);
+  if (npairs > 0) inc_sort_kernel<<<grid_for(px.nsv, 4), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent);
+  cflag_kernel<<<grid_for(n + 1, 256), 256, 0, st>>>(n, inc.ptr, fixed, inc.cflag);
   launch_exclusive_scan(inc.cflag, inc.cidx, n + 1, inc.d_nc, scan_temp, st);
   clist_kernel<<<grid_for(n, 256), 256, 0, st>>>(n, inc.cflag, inc.cidx, inc.clist);
 }
@@ -333,41 +376,35 @@ __global__ void fill_kron_kernel(int32_t nc, const double* __restrict__ Cinv, do
   M[idx] = (row % 3 == col % 3) ? Cinv[(row / 3) * nc + col / 3] : 0.0;
 }
 
-// one thread per (c vertex a): add U_k rows of a times U_k rows of b for every
-// incident pair k and every free local vertex b
-__global__ void add_bcheck_kernel(int32_t nc, const int32_t* __restrict__ clist, const int32_t* __restrict__ ptr,
-                                  const int32_t* __restrict__ ent, const int32_t* __restrict__ v4,
-                                  const int32_t* __restrict__ cflag, const int32_t* __restrict__ cidx,
-                                  const double* __restrict__ U, int32_t npairs, double* __restrict__ M) {
-  int32_t ca = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per c vertex a (its three rows of M).  The wave walks a's incident
+// pairs in ascending order; lane (lb, r, s) adds U_k[3 la + r] . U_k[3 lb + s]
+// into M[3 a + r][3 c(lb) + s].  Within one pair the four local vertices map to
+// distinct c columns, so no two lanes write one entry in the same step and the
+// summation order is fixed.
+__global__ void __launch_bounds__(256) add_bcheck_kernel(int32_t nc, const int32_t* __restrict__ clist,
+                                                         const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
+                                                         const int32_t* __restrict__ v4, const int32_t* __restrict__ cflag,
+                                                         const int32_t* __restrict__ cidx, const double* __restrict__ U,
+                                                         int32_t npairs, double* __restrict__ M) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t ca = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
   if (ca >= nc) return;
   const int64_t N = 3 * static_cast<int64_t>(nc);
-  int32_t va = clist[ca];
+  const int32_t va = clist[ca];
+  const int lb = lane / 9, r = (lane % 9) / 3, sc = lane % 3;
+  const bool active = lane < 36;
   for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
-    int32_t k = ent[t] >> 2, la = ent[t] & 3;
-    double Ua[3][5];
+    const int32_t k = ent[t] >> 2, la = ent[t] & 3;
+    if (!active) continue;
+    const int32_t vb = v4[4 * k + lb];
+    if (!cflag[vb]) continue;
+    const int64_t cb = cidx[vb];
+    double acc = 0.0;
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 5; ++c) Ua[r][c] = U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k];
-    for (int lb = 0; lb < 4; ++lb) {
-      int32_t vb = v4[4 * k + lb];
-      if (!cflag[vb]) continue;
-      int64_t cb = cidx[vb];
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        double Ub[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) Ub[c] = U[static_cast<int64_t>(5 * (3 * lb + s) + c) * npairs + k];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          double acc = 0.0;
-#pragma unroll
-          for (int c = 0; c < 5; ++c) acc += Ua[r][c] * Ub[c];
-          M[(3 * static_cast<int64_t>(ca) + r) * N + 3 * cb + s] += acc;
-        }
-      }
-    }
+    for (int c = 0; c < 5; ++c)
+      acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
+             U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
+    M[(3 * ca + r) * N + 3 * cb + sc] += acc;
   }
 }
 
@@ -375,8 +412,8 @@ void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& in
                              int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st) {
   int64_t N = 3 * static_cast<int64_t>(nc);
   fill_kron_kernel<<<grid_for(N * N, 256), 256, 0, st>>>(nc, Cinv, M);
-  add_bcheck_kernel<<<grid_for(nc, 64), 64, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx,
-                                                     bo.U, npairs, M);
+  add_bcheck_kernel<<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx,
+                                                      bo.U, npairs, M);
 }
 
 // w_k = U_k^T u_local (5 per pair), u indexed by c index of each free local vertex

@@ -240,18 +240,20 @@ __device__ void visit_partners(const QueryArgs& qa, int64_t q, Emit emit) {
       }
 }
 
-__global__ void __launch_bounds__(BT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * BT + threadIdx.x;
+constexpr int QT = 64;   // small blocks: few queries, spread over many CUs
+
+__global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
+  int64_t q = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
   if (q >= static_cast<int64_t>(qa.px.nsv) + qa.px.nse) return;
   int32_t c = 0;
   visit_partners(qa, q, [&](int32_t, const int32_t*) { ++c; });
   qcount[q] = c;
 }
 
-__global__ void __launch_bounds__(BT) query_fill_kernel(QueryArgs qa, const int32_t* __restrict__ qoff,
+__global__ void __launch_bounds__(QT) query_fill_kernel(QueryArgs qa, const int32_t* __restrict__ qoff,
                                                         int32_t* __restrict__ ptype, int32_t* __restrict__ pi,
                                                         int32_t* __restrict__ pj, int32_t* __restrict__ pv4) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * BT + threadIdx.x;
+  int64_t q = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
   if (q >= static_cast<int64_t>(qa.px.nsv) + qa.px.nse) return;
   const bool is_pt = q < qa.px.nsv;
   const int32_t begin = qoff[q];
@@ -319,7 +321,7 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
   QueryArgs qa{px, x, bb.vbox, bb.tbox, bb.ebox, bb.params, mask, bb.t_count, bb.t_id, bb.t_key,
                bb.e_count, bb.e_id, bb.e_key, dhat, distance_filter};
   launch_fill_i32(bb.q_count + nq, 1, 0, st);     // sentinel slot of the scan
-  query_count_kernel<<<grid_for(nq, BT), BT, 0, st>>>(qa, bb.q_count);
+  query_count_kernel<<<grid_for(nq, QT), QT, 0, st>>>(qa, bb.q_count);
   launch_exclusive_scan(bb.q_count, bb.q_count, nq + 1, bb.d_totals, bb.scan_temp, st);
   pt_total_kernel<<<1, 1, 0, st>>>(bb.q_count, px.nsv, bb.d_totals + 1);
   int32_t h_tot[4];
@@ -334,7 +336,65 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
   *n_pt = h_tot[1];
   *n_ee = npairs - h_tot[1];
   if (npairs > 0)
-    query_fill_kernel<<<grid_for(nq, BT), BT, 0, st>>>(qa, bb.q_count, out.type, out.i, out.j, out.v4);
+    query_fill_kernel<<<grid_for(nq, QT), QT, 0, st>>>(qa, bb.q_count, out.type, out.i, out.j, out.v4);
+  return 0;
+}
+
+// ---- constraint set as the active subset of a candidate list -------------------
+// Candidates swept over x_prev -> x_prev + dx contain every pair within dhat at
+// any x_prev + alpha dx, alpha in [0, 1]; filtering them by the exact distance
+// at the new iterate gives the same sorted set as a fresh broad phase.
+__global__ void __launch_bounds__(BT) active_flag_kernel(const int32_t* __restrict__ v4all, int32_t npairs,
+                                                         int32_t n_pt, const double* __restrict__ x, double dhat,
+                                                         int32_t* __restrict__ flag) {
+  int32_t k = blockIdx.x * BT + threadIdx.x;
+  if (k > npairs) return;
+  if (k == npairs) { flag[k] = 0; return; }
+  int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
+  double P[4][3];
+  load_pair_rel(v4, x, P);
+  double d2 = pair_dist2<double>(k < n_pt, P);
+  flag[k] = d2 < dhat * dhat ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(BT) compact_pairs_kernel(PairList src, int32_t npairs, const int32_t* __restrict__ flag,
+                                                           const int32_t* __restrict__ pos, PairList dst) {
+  int32_t k = blockIdx.x * BT + threadIdx.x;
+  if (k >= npairs || !flag[k]) return;
+  int32_t o = pos[k];
+  dst.type[o] = src.type[k];
+  dst.i[o] = src.i[k];
+  dst.j[o] = src.j[k];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) dst.v4[4 * o + a] = src.v4[4 * k + a];
+}
+
+__global__ void pt_count_kernel(const int32_t* __restrict__ pos, int32_t n_pt, int32_t* __restrict__ out) {
+  *out = pos[n_pt];
+}
+
+int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const double* x, double dhat, PairList& out,
+                  int32_t* flag, int32_t* pos, int32_t* d_tot, void* scan_temp, int32_t* n_pt, int32_t* n_ee,
+                  hipStream_t st, int64_t* needed) {
+  *needed = 0;
+  if (ncand <= 0) {
+    *n_pt = 0;
+    *n_ee = 0;
+    return 0;
+  }
+  active_flag_kernel<<<grid_for(ncand + 1, BT), BT, 0, st>>>(cand.v4, ncand, cand_pt, x, dhat, flag);
+  launch_exclusive_scan(flag, pos, ncand + 1, d_tot, scan_temp, st);
+  pt_count_kernel<<<1, 1, 0, st>>>(pos, cand_pt, d_tot + 1);
+  int32_t h[2];
+  hipMemcpyAsync(h, d_tot, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  if (h[0] > out.cap) {
+    *needed = h[0];
+    return 1;
+  }
+  *n_pt = h[1];
+  *n_ee = h[0] - h[1];
+  if (h[0] > 0) compact_pairs_kernel<<<grid_for(ncand, BT), BT, 0, st>>>(cand, ncand, flag, pos, out);
   return 0;
 }
 

@@ -11,71 +11,6 @@ namespace {
 constexpr int NB = 64;
 }
 
-// ---- diagonal block: unblocked Cholesky in LDS --------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) potrf_diag_kernel(T* __restrict__ A, int64_t n, int64_t k, int kb,
-                                                         int32_t* __restrict__ info) {
-  __shared__ T L[NB][NB + 1];
-  for (int idx = threadIdx.x; idx < kb * kb; idx += blockDim.x) {
-    int i = idx / kb, j = idx % kb;
-    L[i][j] = A[(k + i) * n + k + j];
-  }
-  __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    if (threadIdx.x == 0) {
-      T d = L[j][j];
-      if (!(d > T(0))) {
-        if (*info == 0) *info = static_cast<int32_t>(k + j + 1);
-        d = T(1);
-      }
-      L[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    T djj = L[j][j];
-    for (int i = j + 1 + threadIdx.x; i < kb; i += blockDim.x) L[i][j] /= djj;
-    __syncthreads();
-    const int m = kb - j - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      int i = j + 1 + idx / m, l = j + 1 + idx % m;
-      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < kb * kb; idx += blockDim.x) {
-    int i = idx / kb, j = idx % kb;
-    if (j <= i) A[(k + i) * n + k + j] = L[i][j];
-  }
-}
-
-// ---- panel below the diagonal: X L_kk^T = A_ik, one row per thread --------------
-template <typename T>
-__global__ void __launch_bounds__(64) trsm_panel_kernel(T* __restrict__ A, int64_t n, int64_t k, int kb) {
-  __shared__ T L[NB][NB + 1];
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    int i = idx / NB, j = idx % NB;
-    T v;
-    if (i < kb && j < kb) v = j <= i ? A[(k + i) * n + k + j] : T(0);
-    else v = (i == j) ? T(1) : T(0);
-    L[i][j] = v;
-  }
-  __syncthreads();
-  const int64_t row = k + kb + static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
-  if (row >= n) return;
-  T x[NB];
-#pragma unroll
-  for (int l = 0; l < NB; ++l) x[l] = l < kb ? A[row * n + k + l] : T(0);
-#pragma unroll
-  for (int l = 0; l < NB; ++l) {
-    T s = x[l];
-#pragma unroll
-    for (int p = 0; p < l; ++p) s -= x[p] * L[l][p];
-    x[l] = s / L[l][l];
-  }
-#pragma unroll
-  for (int l = 0; l < NB; ++l)
-    if (l < kb) A[row * n + k + l] = x[l];
-}
-
 // ---- tiled GEMM: C = beta C + alpha op(A) op(B), 64x64 tiles, K chunks of 16 ----
 template <typename T, bool TA, bool TB>
 __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A,
@@ -132,40 +67,214 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
     }
 }
 
+// ---- Cholesky -----------------------------------------------------------------
+// Right-looking with 64-wide blocks, one launch per block step.  Step k (k >= 0)
+// handles the trailing lower tiles (i, j), k < j <= i:
+//   P_i = A_ik Linv_k^T          (panel solve via the stored inverse of L_kk)
+//   A_ij -= P_i P_j^T            (trailing update)
+// the diagonal tile (i, i) also writes P_i into L, and tile (k+1, k+1), after
+// its last update, factors itself and stores L_{k+1,k+1} and its inverse.
+// A is the workspace (destroyed); L and the block inverses are the outputs.
+// Ragged last blocks are padded with the identity.
+
+// Factor the 64x64 tile in LDS (lower, padded beyond kb with identity) and
+// write its inverse into X; 256 threads.
 template <typename T>
-void dense_cholesky(T* A, int64_t n, int32_t* d_info, hipStream_t st) {
-  launch_fill_i32(d_info, 1, 0, st);
-  for (int64_t k = 0; k < n; k += NB) {
-    int kb = static_cast<int>(n - k < NB ? n - k : NB);
-    potrf_diag_kernel<T><<<1, 256, 0, st>>>(A, n, k, kb, d_info);
-    int64_t rem = n - k - kb;
-    if (rem > 0) {
-      trsm_panel_kernel<T><<<grid_for(rem, 64), 64, 0, st>>>(A, n, k, kb);
-      unsigned tiles = grid_for(rem, 64);
-      dim3 grid(tiles, tiles);
-      const T* P = A + (k + kb) * n + k;
-      T* C = A + (k + kb) * n + k + kb;
-      gemm_kernel<T, false, true><<<grid, 256, 0, st>>>(rem, rem, kb, T(-1), P, n, P, n, T(1), C, n, 1);
+__device__ void tile_factor_inverse(T (*Tl)[NB + 1], T (*X)[NB + 1], int kb, int64_t k0, int32_t* info) {
+  for (int j = 0; j < NB; ++j) {
+    T d = Tl[j][j];
+    if (j < kb && !(d > T(0)) && threadIdx.x == 0 && *info == 0) *info = static_cast<int32_t>(k0 + j + 1);
+    if (!(d > T(0))) d = T(1);
+    d = sqrt(d);
+    __syncthreads();
+    for (int i = j + threadIdx.x; i < NB; i += blockDim.x) Tl[i][j] = (i == j) ? d : Tl[i][j] / d;
+    __syncthreads();
+    const int m = NB - j - 1;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      int i = j + 1 + idx / m, l = j + 1 + idx % m;
+      if (l <= i) Tl[i][l] -= Tl[i][j] * Tl[l][j];
     }
+    __syncthreads();
+  }
+  if (threadIdx.x < NB) {
+    const int c = threadIdx.x;
+    for (int r = 0; r < NB; ++r) {
+      if (r < c) { X[r][c] = T(0); continue; }
+      T acc = (r == c) ? T(1) : T(0);
+      for (int p = c; p < r; ++p) acc -= Tl[r][p] * X[p][c];
+      X[r][c] = acc / Tl[r][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ L,
+                                                         T* __restrict__ Linv, int32_t* __restrict__ info) {
+  __shared__ T Tl[NB][NB + 1];
+  __shared__ T X[NB][NB + 1];
+  const int kb = static_cast<int>(n < NB ? n : NB);
+  if (threadIdx.x == 0) *info = 0;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    Tl[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
+  }
+  __syncthreads();
+  tile_factor_inverse<T>(Tl, X, kb, 0, info);
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    Linv[idx] = X[r][c];
+    if (r < kb && c < kb) L[r * n + c] = c <= r ? Tl[r][c] : T(0);
   }
 }
 
-// ---- solves: one workgroup, blocked forward then backward substitution -------
+// P = Araw Linv^T into LDS (rows beyond the matrix are zero)
 template <typename T>
-__global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ L, int64_t n, T* __restrict__ b,
-                                                          int nrhs) {
+__device__ void panel_times_linvT(const T* __restrict__ A, int64_t n, int64_t r0, int64_t k0, const T (*Li)[NB + 1],
+                                  T (*Raw)[NB + 1], T (*P)[NB + 1]) {
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    int64_t gr = r0 + r, gc = k0 + c;
+    Raw[r][c] = (gr < n && gc < n) ? A[gr * n + gc] : T(0);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+  for (int p = 0; p < NB; ++p) {
+    T x[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[q] = Raw[ty + 16 * q][p];
+      y[q] = Li[tx + 16 * q][p];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) P[ty + 16 * a][tx + 16 * b] = acc[a][b];
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) chol_step_kernel(T* __restrict__ A, int64_t n, int64_t k, T* __restrict__ L,
+                                                        T* __restrict__ Linv, int32_t* __restrict__ info) {
+  extern __shared__ unsigned char smem_raw[];
+  T (*Li)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);
+  T (*Pi)[NB + 1] = Li + NB;
+  T (*Pj)[NB + 1] = Pi + NB;
+  T (*Wk)[NB + 1] = Pj + NB;            // scratch: raw panel, then the tile
+  const int64_t nblk = (n + NB - 1) / NB;
+  // tile index -> (i, j) with k < j <= i < nblk
+  const int64_t m = nblk - k - 1;
+  int64_t t = blockIdx.x, ii = 0;
+  while (t >= m - ii) { t -= m - ii; ++ii; }
+  const int64_t bj = k + 1 + ii, bi = bj + t;
+  const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
+  const T* Lk = Linv + k * NB * NB;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Li[idx / NB][idx % NB] = Lk[idx];
+  __syncthreads();
+  panel_times_linvT<T>(A, n, i0, k0, Li, Wk, Pi);
+  if (bi != bj) panel_times_linvT<T>(A, n, j0, k0, Li, Wk, Pj);
+  T (*Q)[NB + 1] = (bi != bj) ? Pj : Pi;
+  if (bi == bj) {
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      int r = idx / NB, c = idx % NB;
+      int64_t gr = i0 + r, gc = k0 + c;
+      if (gr < n && gc < n) L[gr * n + gc] = Pi[r][c];
+    }
+  }
+  // trailing update of tile (bi, bj), kept in Wk
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+  for (int p = 0; p < NB; ++p) {
+    T x[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[q] = Pi[ty + 16 * q][p];
+      y[q] = Q[tx + 16 * q][p];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+  }
+  __syncthreads();
+  const bool last = (bi == k + 1) && (bj == k + 1);
+  const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int r = ty + 16 * a, c = tx + 16 * b;
+      int64_t gr = i0 + r, gc = j0 + c;
+      T v;
+      if (gr < n && gc < n) {
+        v = A[gr * n + gc] - acc[a][b];
+        if (!last) A[gr * n + gc] = v;
+      } else {
+        v = (r == c) ? T(1) : T(0);
+      }
+      Wk[r][c] = v;
+    }
+  __syncthreads();
+  if (!last) return;
+  // factor the next diagonal tile and store it with its inverse
+  tile_factor_inverse<T>(Wk, Pj, kb, i0, info);
+  T* Lnext = Linv + (k + 1) * NB * NB;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    int r = idx / NB, c = idx % NB;
+    Lnext[idx] = Pj[r][c];
+    int64_t gr = i0 + r, gc = i0 + c;
+    if (gr < n && gc < n) L[gr * n + gc] = c <= r ? Wk[r][c] : T(0);
+  }
+}
+
+template <typename T>
+void dense_cholesky(T* A, int64_t n, T* L, T* Linv, int32_t* d_info, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t nblk = (n + NB - 1) / NB;
+  launch_fill_i32(d_info, 1, 0, st);
+  // only the lower blocks of L are ever read: the upper part is left as is
+  chol_first_kernel<T><<<1, 256, 0, st>>>(A, n, L, Linv, d_info);
+  const size_t shm = sizeof(T) * 4 * NB * (NB + 1);
+  for (int64_t k = 0; k + 1 < nblk; ++k) {
+    const int64_t m = nblk - k - 1;
+    chol_step_kernel<T><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Linv, d_info);
+  }
+}
+
+// ---- solves: one workgroup, blocked with the stored diagonal inverses ----------
+template <typename T>
+__global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ L, const T* __restrict__ Linv,
+                                                          int64_t n, T* __restrict__ b, int nrhs) {
   __shared__ T t[NB][4];
   __shared__ T red[16][NB][4];
   const int lane = threadIdx.x % PDIPC_WAVE, wave = threadIdx.x / PDIPC_WAVE;
+  const int64_t nblk = (n + NB - 1) / NB;
   // forward: L y = b
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
+  for (int64_t bk = 0; bk < nblk; ++bk) {
+    const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    for (int r = wave; r < kb; r += 16) {
+    for (int r = wave; r < NB; r += 16) {
       T s[4] = {T(0), T(0), T(0), T(0)};
-      const T* Lr = L + (k0 + r) * n;
-      for (int64_t c = lane; c < k0; c += PDIPC_WAVE) {
-        T v = Lr[c];
-        for (int q = 0; q < nrhs; ++q) s[q] += v * b[c * nrhs + q];
+      if (r < kb) {
+        const T* Lr = L + (k0 + r) * n;
+        for (int64_t c = lane; c < k0; c += PDIPC_WAVE) {
+          T v = Lr[c];
+          for (int q = 0; q < nrhs; ++q) s[q] += v * b[c * nrhs + q];
+        }
       }
       for (int q = 0; q < nrhs; ++q) {
         T w = s[q];
@@ -174,132 +283,144 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
         s[q] = w;
       }
       if (lane == 0)
-        for (int q = 0; q < nrhs; ++q) t[r][q] = b[(k0 + r) * nrhs + q] - s[q];
+        for (int q = 0; q < 4; ++q) t[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] - s[q] : T(0);
     }
     __syncthreads();
-    if (threadIdx.x < nrhs) {
-      const int q = threadIdx.x;
-      for (int r = 0; r < kb; ++r) {
-        T s = t[r][q];
-        const T* Lr = L + (k0 + r) * n + k0;
-        for (int p = 0; p < r; ++p) s -= Lr[p] * t[p][q];
-        t[r][q] = s / Lr[r];
-      }
+    const T* Lk = Linv + bk * NB * NB;
+    if (threadIdx.x < NB * 4) {
+      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
+      T acc = T(0);
+      for (int c = 0; c <= r; ++c) acc += Lk[r * NB + c] * t[c][q];
+      if (r < kb && q < nrhs) b[(k0 + r) * nrhs + q] = acc;
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kb * nrhs; idx += blockDim.x) b[(k0 + idx / nrhs) * nrhs + idx % nrhs] = t[idx / nrhs][idx % nrhs];
     __syncthreads();
   }
   // backward: L^T x = y
-  const int64_t nblk = (n + NB - 1) / NB;
-  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
-    const int64_t k0 = bi * NB;
+  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
+    const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    // partial sums over rows i >= k0 + kb of L[i][k0 + c] x_i, split over waves
-    for (int c = lane; c < NB; c += PDIPC_WAVE) {
+    {
       T s[4] = {T(0), T(0), T(0), T(0)};
-      if (c < kb)
+      if (lane < kb)
         for (int64_t i = k0 + kb + wave; i < n; i += 16) {
-          T v = L[i * n + k0 + c];
+          T v = L[i * n + k0 + lane];
           for (int q = 0; q < nrhs; ++q) s[q] += v * b[i * nrhs + q];
         }
-      for (int q = 0; q < 4; ++q) red[wave][c][q] = s[q];
+      for (int q = 0; q < 4; ++q) red[wave][lane][q] = s[q];
     }
     __syncthreads();
-    if (threadIdx.x < kb)
-      for (int q = 0; q < nrhs; ++q) {
-        T s = T(0);
-        for (int w = 0; w < 16; ++w) s += red[w][threadIdx.x][q];
-        t[threadIdx.x][q] = b[(k0 + threadIdx.x) * nrhs + q] - s;
-      }
-    __syncthreads();
-    if (threadIdx.x < nrhs) {
-      const int q = threadIdx.x;
-      for (int r = kb - 1; r >= 0; --r) {
-        T s = t[r][q];
-        for (int p = r + 1; p < kb; ++p) s -= L[(k0 + p) * n + k0 + r] * t[p][q];
-        t[r][q] = s / L[(k0 + r) * n + k0 + r];
-      }
+    if (threadIdx.x < NB * 4) {
+      const int c = threadIdx.x / 4, q = threadIdx.x % 4;
+      T acc = T(0);
+      for (int w = 0; w < 16; ++w) acc += red[w][c][q];
+      t[c][q] = (c < kb && q < nrhs) ? b[(k0 + c) * nrhs + q] - acc : T(0);
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kb * nrhs; idx += blockDim.x) b[(k0 + idx / nrhs) * nrhs + idx % nrhs] = t[idx / nrhs][idx % nrhs];
+    const T* Lk = Linv + bk * NB * NB;
+    if (threadIdx.x < NB * 4) {
+      const int c = threadIdx.x / 4, q = threadIdx.x % 4;
+      T acc = T(0);
+      for (int r = c; r < NB; ++r) acc += Lk[r * NB + c] * t[r][q];
+      if (c < kb && q < nrhs) b[(k0 + c) * nrhs + q] = acc;
+    }
     __syncthreads();
   }
 }
 
 template <typename T>
-void dense_chol_solve(const T* L, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
+void dense_chol_solve(const T* L, const T* Linv, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
   if (n <= 0) return;
-  chol_solve_kernel<T><<<1, 1024, 0, st>>>(L, n, b, nrhs);
+  chol_solve_kernel<T><<<1, 1024, 0, st>>>(L, Linv, n, b, nrhs);
 }
 
-// ---- inverse of the lower factor, one block column per workgroup --------------
-// Y = L^-1: for block column j, Y_jj = L_jj^-1 and for i > j
-// Y_ij = -L_ii^-1 sum_{j <= p < i} L_ip Y_pj.
+// ---- Y = L^-1 by block columns: Y_jj = Linv_j, Y_ij = -Linv_i sum_{j<=p<i} L_ip Y_pj --
 template <typename T>
-__global__ void __launch_bounds__(256) lower_inverse_kernel(const T* __restrict__ L, int64_t n, T* __restrict__ Y) {
-  __shared__ T Lt[NB][NB + 1];
-  __shared__ T Acc[NB][NB + 1];
-  __shared__ T Yp[NB][NB + 1];
-  const int64_t j0 = static_cast<int64_t>(blockIdx.x) * NB;
+__global__ void __launch_bounds__(256) lower_inverse_kernel(const T* __restrict__ L, const T* __restrict__ Linv,
+                                                            int64_t n, T* __restrict__ Y) {
+  extern __shared__ unsigned char smem_raw[];
+  T (*Lt)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);
+  T (*Yp)[NB + 1] = Lt + NB;
+  T (*Acc)[NB + 1] = Yp + NB;
+  const int64_t bj = blockIdx.x;
+  const int64_t j0 = bj * NB;
   const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
   const int64_t nblk = (n + NB - 1) / NB;
-  // zero the strictly upper part of this block column
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   for (int64_t idx = threadIdx.x; idx < j0 * jb; idx += blockDim.x) Y[(idx / jb) * n + j0 + idx % jb] = T(0);
-  for (int64_t bi = blockIdx.x; bi < nblk; ++bi) {
+  for (int64_t bi = bj; bi < nblk; ++bi) {
     const int64_t i0 = bi * NB;
     const int ib = static_cast<int>(n - i0 < NB ? n - i0 : NB);
-    // Acc = (i == j ? I : 0) - sum_p L_ip Y_pj
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      int r = idx / NB, c = idx % NB;
-      Acc[r][c] = (bi == blockIdx.x && r == c) ? T(1) : T(0);
-    }
-    __syncthreads();
-    for (int64_t bp = blockIdx.x; bp < bi; ++bp) {
+    T acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+    for (int64_t bp = bj; bp < bi; ++bp) {
       const int64_t p0 = bp * NB;
       for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
         int r = idx / NB, c = idx % NB;
-        Lt[r][c] = (r < ib) ? L[(i0 + r) * n + p0 + c] : T(0);
-        Yp[r][c] = (c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
+        Lt[r][c] = (r < ib && p0 + c < n) ? L[(i0 + r) * n + p0 + c] : T(0);
+        Yp[r][c] = (p0 + r < n && c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-        int r = idx / NB, c = idx % NB;
-        T s = T(0);
-#pragma unroll 8
-        for (int p = 0; p < NB; ++p) s += Lt[r][p] * Yp[p][c];
-        Acc[r][c] -= s;
+      for (int p = 0; p < NB; ++p) {
+        T x[4], y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[q] = Lt[ty + 16 * q][p];
+          y[q] = Yp[p][tx + 16 * q];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
       }
       __syncthreads();
     }
-    // solve L_ii X = Acc (column per thread)
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      int r = idx / NB, c = idx % NB;
-      Lt[r][c] = (r < ib && c < ib) ? (c <= r ? L[(i0 + r) * n + i0 + c] : T(0)) : (r == c ? T(1) : T(0));
-    }
-    __syncthreads();
-    if (threadIdx.x < NB) {
-      const int c = threadIdx.x;
-      for (int r = 0; r < NB; ++r) {
-        T s = Acc[r][c];
-        for (int p = 0; p < r; ++p) s -= Lt[r][p] * Acc[p][c];
-        Acc[r][c] = s / Lt[r][r];
+    // Acc = (i == j ? I : -acc), then Y_ij = Linv_i Acc
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        int r = ty + 16 * a, c = tx + 16 * b;
+        Acc[r][c] = (bi == bj) ? ((r == c) ? T(1) : T(0)) : -acc[a][b];
       }
-    }
+    const T* Li = Linv + bi * NB * NB;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Lt[idx / NB][idx % NB] = Li[idx];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < ib * jb; idx += blockDim.x) {
-      int r = idx / jb, c = idx % jb;
-      Y[(i0 + r) * n + j0 + c] = Acc[r][c];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+    for (int p = 0; p < NB; ++p) {
+      T x[4], y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[q] = Lt[ty + 16 * q][p];
+        y[q] = Acc[p][tx + 16 * q];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
     }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        int r = ty + 16 * a, c = tx + 16 * b;
+        if (r < ib && c < jb) Y[(i0 + r) * n + j0 + c] = acc[a][b];
+      }
     __syncthreads();
   }
 }
 
 template <typename T>
-void dense_chol_inverse(const T* L, int64_t n, T* Ainv, T* work, hipStream_t st) {
+void dense_chol_inverse(const T* L, const T* Linv, int64_t n, T* Ainv, T* work, hipStream_t st) {
   if (n <= 0) return;
   const unsigned nblk = grid_for(n, NB);
-  lower_inverse_kernel<T><<<nblk, 256, 0, st>>>(L, n, work);
+  const size_t shm = sizeof(T) * 3 * NB * (NB + 1);
+  lower_inverse_kernel<T><<<nblk, 256, shm, st>>>(L, Linv, n, work);
   dim3 grid(nblk, nblk);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
 }
@@ -335,11 +456,11 @@ void launch_dense_residual(const double* M, int64_t n, const double* b, const do
   if (n > 0) dense_residual_kernel<<<grid_for(n, 4), 256, 0, st>>>(M, n, b, u, r);
 }
 
-template void dense_cholesky<double>(double*, int64_t, int32_t*, hipStream_t);
-template void dense_cholesky<float>(float*, int64_t, int32_t*, hipStream_t);
-template void dense_chol_solve<double>(const double*, int64_t, double*, int32_t, hipStream_t);
-template void dense_chol_solve<float>(const float*, int64_t, float*, int32_t, hipStream_t);
-template void dense_chol_inverse<double>(const double*, int64_t, double*, double*, hipStream_t);
-template void dense_chol_inverse<float>(const float*, int64_t, float*, float*, hipStream_t);
+template void dense_cholesky<double>(double*, int64_t, double*, double*, int32_t*, hipStream_t);
+template void dense_cholesky<float>(float*, int64_t, float*, float*, int32_t*, hipStream_t);
+template void dense_chol_solve<double>(const double*, const double*, int64_t, double*, int32_t, hipStream_t);
+template void dense_chol_solve<float>(const float*, const float*, int64_t, float*, int32_t, hipStream_t);
+template void dense_chol_inverse<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template void dense_chol_inverse<float>(const float*, const float*, int64_t, float*, float*, hipStream_t);
 
 }  // namespace pdipc

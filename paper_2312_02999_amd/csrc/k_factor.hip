@@ -28,9 +28,30 @@ void launch_pack_rhs(const FactorDev& f, const double* g, double* b, hipStream_t
   if (N > 0) pack_rhs_kernel<<<grid_for(N, 256), 256, 0, st>>>(N, f.ext2vert, g, b);
 }
 
-// t_row = b_row - sum_e val_e y_col(e), one wave per row
-__device__ __forceinline__ void row_gather(const FactorDev& f, int64_t row, const double* __restrict__ b,
-                                           const double* __restrict__ y, int lane, double out[3]) {
+// Level-scheduled sweeps.  Every level runs two launches per direction, one
+// wavefront per row (lower sweep) or column (upper sweep) of that level's
+// supernodes, lanes over the reduction dimension (coalesced):
+//   lower  t_rho = b_rho - sum_e L[rho, e] y_e     (CSR row of the factor)
+//          y_J   = Dinv_J t_J                      (row-major Dinv)
+//   upper  s_c   = y_c - sum_i L[R_i, c] x_{R_i}   (transposed panel)
+//          x_J   = Dinv_J^T s_J                    (row-major Dinv^T)
+namespace {
+constexpr int WPB = FT / PDIPC_WAVE;   // waves per block
+}
+
+__device__ __forceinline__ void wave_sum3(double& a0, double& a1, double& a2) {
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+}
+
+__global__ void __launch_bounds__(FT) fwd_gather_kernel(FactorDev f, int32_t row0, int32_t nrows,
+                                                        const double* __restrict__ b, const double* __restrict__ y,
+                                                        double* __restrict__ out) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
+  if (k >= nrows) return;
+  const int64_t row = f.lvl_rows[row0 + k];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int64_t e = f.fwd_ptr[row] + lane; e < f.fwd_ptr[row + 1]; e += PDIPC_WAVE) {
     int32_t c = f.fwd_col[e];
@@ -39,77 +60,79 @@ __device__ __forceinline__ void row_gather(const FactorDev& f, int64_t row, cons
     a1 += v * y[3 * c + 1];
     a2 += v * y[3 * c + 2];
   }
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
-  a2 = wave_sum(a2);
-  out[0] = b[3 * row] - a0;
-  out[1] = b[3 * row + 1] - a1;
-  out[2] = b[3 * row + 2] - a2;
+  wave_sum3(a0, a1, a2);
+  if (lane == 0) {
+    out[3 * row] = b[3 * row] - a0;
+    out[3 * row + 1] = b[3 * row + 1] - a1;
+    out[3 * row + 2] = b[3 * row + 2] - a2;
+  }
 }
 
-__global__ void __launch_bounds__(FT) fwd_level_kernel(FactorDev f, const int32_t* __restrict__ nodes,
-                                                       const double* __restrict__ b, double* __restrict__ y,
-                                                       double* __restrict__ tbuf) {
-  const int32_t J = nodes[blockIdx.x];
+// y_rho = sum_{c <= r} Dinv_J[r][c] t_{c0 + c}
+__global__ void __launch_bounds__(FT) fwd_diag_kernel(FactorDev f, int32_t row0, int32_t nrows,
+                                                      const double* __restrict__ t, double* __restrict__ y) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
+  if (k >= nrows) return;
+  const int64_t row = f.lvl_rows[row0 + k];
+  const int32_t J = f.lvl_row_node[row0 + k];
   const int32_t c0 = f.node_c0[J], s = f.node_s[J];
-  const int lane = threadIdx.x % PDIPC_WAVE, wave = threadIdx.x / PDIPC_WAVE;
-  const int nw = blockDim.x / PDIPC_WAVE;
-  for (int r = wave; r < s; r += nw) {
-    double t[3];
-    row_gather(f, c0 + r, b, y, lane, t);
-    if (lane == 0) {
-      tbuf[3 * (c0 + r)] = t[0];
-      tbuf[3 * (c0 + r) + 1] = t[1];
-      tbuf[3 * (c0 + r) + 2] = t[2];
-    }
+  const int32_t r = static_cast<int32_t>(row - c0);
+  const double* D = f.dinv + f.node_dinv_off[J] + static_cast<int64_t>(r) * s;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t c = lane; c <= r; c += PDIPC_WAVE) {
+    double d = D[c];
+    a0 += d * t[3 * (c0 + c)];
+    a1 += d * t[3 * (c0 + c) + 1];
+    a2 += d * t[3 * (c0 + c) + 2];
   }
-  __syncthreads();
-  const double* DT = f.dinvT + f.node_dinv_off[J];   // DT[c * s + r] = Dinv[r][c]
-  for (int r = threadIdx.x; r < s; r += blockDim.x) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int c = 0; c <= r; ++c) {
-      double d = DT[static_cast<int64_t>(c) * s + r];
-      a0 += d * tbuf[3 * (c0 + c)];
-      a1 += d * tbuf[3 * (c0 + c) + 1];
-      a2 += d * tbuf[3 * (c0 + c) + 2];
-    }
-    y[3 * (c0 + r)] = a0;
-    y[3 * (c0 + r) + 1] = a1;
-    y[3 * (c0 + r) + 2] = a2;
+  wave_sum3(a0, a1, a2);
+  if (lane == 0) {
+    y[3 * row] = a0;
+    y[3 * row + 1] = a1;
+    y[3 * row + 2] = a2;
   }
 }
 
 // rows of x2: y2 = r2 - L21 y1
 __global__ void __launch_bounds__(FT) fwd_x2_kernel(FactorDev f, const double* __restrict__ b, double* __restrict__ y) {
   const int lane = threadIdx.x % PDIPC_WAVE;
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * (FT / PDIPC_WAVE) + threadIdx.x / PDIPC_WAVE;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
   if (q >= f.n2) return;
   const int64_t row = f.n1 + q;
-  double t[3];
-  row_gather(f, row, b, y, lane, t);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t e = f.fwd_ptr[row] + lane; e < f.fwd_ptr[row + 1]; e += PDIPC_WAVE) {
+    int32_t c = f.fwd_col[e];
+    double v = f.fwd_val[e];
+    a0 += v * y[3 * c];
+    a1 += v * y[3 * c + 1];
+    a2 += v * y[3 * c + 2];
+  }
+  wave_sum3(a0, a1, a2);
   if (lane == 0) {
-    y[3 * row] = t[0];
-    y[3 * row + 1] = t[1];
-    y[3 * row + 2] = t[2];
+    y[3 * row] = b[3 * row] - a0;
+    y[3 * row + 1] = b[3 * row + 1] - a1;
+    y[3 * row + 2] = b[3 * row + 2] - a2;
   }
 }
 
 void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st) {
-  // tbuf lives after y in the same allocation (caller provides 2 * 3 * N)
+  // t lives after y in the same allocation (caller provides 2 * 3 * N)
   double* tbuf = y + 3 * static_cast<int64_t>(f.n1 + f.n2);
   for (int L = 0; L < f.nlevels; ++L) {
-    int32_t cnt = f.h_level_ptr[L + 1] - f.h_level_ptr[L];
-    if (cnt > 0)
-      fwd_level_kernel<<<cnt, FT, 0, st>>>(f, f.level_nodes + f.h_level_ptr[L], b, y, tbuf);
+    const int32_t r0 = f.h_lvl_row_ptr[L], nr = f.h_lvl_row_ptr[L + 1] - r0;
+    if (nr <= 0) continue;
+    fwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, b, y, tbuf);
+    fwd_diag_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, tbuf, y);
   }
-  if (f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, FT / PDIPC_WAVE), FT, 0, st>>>(f, b, y);
+  if (f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f, b, y);
 }
 
 // z = Sigma^-1 r, r and z are n2 x 3 (x2 part of the extended vectors)
 __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double* __restrict__ S,
                                                         const double* __restrict__ r, double* __restrict__ z) {
   const int lane = threadIdx.x % PDIPC_WAVE;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * (FT / PDIPC_WAVE) + threadIdx.x / PDIPC_WAVE;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
   if (i >= n2) return;
   const double* Si = S + i * n2;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -119,9 +142,7 @@ __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double
     a1 += v * r[3 * j + 1];
     a2 += v * r[3 * j + 2];
   }
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
-  a2 = wave_sum(a2);
+  wave_sum3(a0, a1, a2);
   if (lane == 0) {
     z[3 * i] = a0;
     z[3 * i + 1] = a1;
@@ -130,51 +151,71 @@ __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double
 }
 
 void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream_t st) {
-  if (f.n2 > 0) sigma_gemv_kernel<<<grid_for(f.n2, FT / PDIPC_WAVE), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
+  if (f.n2 > 0) sigma_gemv_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
 }
 
-__global__ void __launch_bounds__(FT) bwd_level_kernel(FactorDev f, const int32_t* __restrict__ nodes,
-                                                       const double* __restrict__ y, double* __restrict__ sol,
-                                                       double* __restrict__ tbuf) {
-  const int32_t J = nodes[blockIdx.x];
-  const int32_t c0 = f.node_c0[J], s = f.node_s[J], r = f.node_r[J];
+// s_c = y_c - sum_i panelT_J[c][i] sol[R_J[i]]
+__global__ void __launch_bounds__(FT) bwd_gather_kernel(FactorDev f, int32_t row0, int32_t nrows,
+                                                        const double* __restrict__ y, const double* __restrict__ sol,
+                                                        double* __restrict__ out) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
+  if (k >= nrows) return;
+  const int64_t col = f.lvl_rows[row0 + k];
+  const int32_t J = f.lvl_row_node[row0 + k];
+  const int32_t c0 = f.node_c0[J], r = f.node_r[J];
+  const int32_t c = static_cast<int32_t>(col - c0);
+  const double* P = f.panelT + f.node_panel_off[J] + static_cast<int64_t>(c) * r;
   const int32_t* R = f.rows + f.node_rows_off[J];
-  const double* Pn = f.panel + f.node_panel_off[J];     // r x s row-major
-  for (int c = threadIdx.x; c < s; c += blockDim.x) {
-    double a0 = y[3 * (c0 + c)], a1 = y[3 * (c0 + c) + 1], a2 = y[3 * (c0 + c) + 2];
-    for (int i = 0; i < r; ++i) {
-      double v = Pn[static_cast<int64_t>(i) * s + c];
-      int32_t k = R[i];
-      a0 -= v * sol[3 * k];
-      a1 -= v * sol[3 * k + 1];
-      a2 -= v * sol[3 * k + 2];
-    }
-    tbuf[3 * (c0 + c)] = a0;
-    tbuf[3 * (c0 + c) + 1] = a1;
-    tbuf[3 * (c0 + c) + 2] = a2;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t i = lane; i < r; i += PDIPC_WAVE) {
+    double v = P[i];
+    int64_t q = R[i];
+    a0 += v * sol[3 * q];
+    a1 += v * sol[3 * q + 1];
+    a2 += v * sol[3 * q + 2];
   }
-  __syncthreads();
-  const double* D = f.dinv + f.node_dinv_off[J];        // row-major Dinv
-  for (int c = threadIdx.x; c < s; c += blockDim.x) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int rr = c; rr < s; ++rr) {
-      double d = D[static_cast<int64_t>(rr) * s + c];
-      a0 += d * tbuf[3 * (c0 + rr)];
-      a1 += d * tbuf[3 * (c0 + rr) + 1];
-      a2 += d * tbuf[3 * (c0 + rr) + 2];
-    }
-    sol[3 * (c0 + c)] = a0;
-    sol[3 * (c0 + c) + 1] = a1;
-    sol[3 * (c0 + c) + 2] = a2;
+  wave_sum3(a0, a1, a2);
+  if (lane == 0) {
+    out[3 * col] = y[3 * col] - a0;
+    out[3 * col + 1] = y[3 * col + 1] - a1;
+    out[3 * col + 2] = y[3 * col + 2] - a2;
+  }
+}
+
+// x_c = sum_{r >= c} Dinv_J[r][c] s_{c0 + r} = sum_r DinvT_J[c][r] s_{c0 + r}
+__global__ void __launch_bounds__(FT) bwd_diag_kernel(FactorDev f, int32_t row0, int32_t nrows,
+                                                      const double* __restrict__ t, double* __restrict__ sol) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
+  if (k >= nrows) return;
+  const int64_t col = f.lvl_rows[row0 + k];
+  const int32_t J = f.lvl_row_node[row0 + k];
+  const int32_t c0 = f.node_c0[J], s = f.node_s[J];
+  const int32_t c = static_cast<int32_t>(col - c0);
+  const double* DT = f.dinvT + f.node_dinv_off[J] + static_cast<int64_t>(c) * s;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t rr = c + lane; rr < s; rr += PDIPC_WAVE) {
+    double d = DT[rr];
+    a0 += d * t[3 * (c0 + rr)];
+    a1 += d * t[3 * (c0 + rr) + 1];
+    a2 += d * t[3 * (c0 + rr) + 2];
+  }
+  wave_sum3(a0, a1, a2);
+  if (lane == 0) {
+    sol[3 * col] = a0;
+    sol[3 * col + 1] = a1;
+    sol[3 * col + 2] = a2;
   }
 }
 
 void launch_backward_sweep(const FactorDev& f, const double* y, double* sol, hipStream_t st) {
   double* tbuf = sol + 3 * static_cast<int64_t>(f.n1 + f.n2);
   for (int L = f.nlevels - 1; L >= 0; --L) {
-    int32_t cnt = f.h_level_ptr[L + 1] - f.h_level_ptr[L];
-    if (cnt > 0)
-      bwd_level_kernel<<<cnt, FT, 0, st>>>(f, f.level_nodes + f.h_level_ptr[L], y, sol, tbuf);
+    const int32_t r0 = f.h_lvl_row_ptr[L], nr = f.h_lvl_row_ptr[L + 1] - r0;
+    if (nr <= 0) continue;
+    bwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, y, sol, tbuf);
+    bwd_diag_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, tbuf, sol);
   }
 }
 

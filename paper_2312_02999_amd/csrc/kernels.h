@@ -87,6 +87,12 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
                bool distance_filter, PairList& out, int32_t* n_pt, int32_t* n_ee, hipStream_t st,
                int64_t* needed);
 
+// Constraint set at x as the pairs of a (sorted) candidate list with squared
+// distance below dhat^2; order preserved.  flag, pos: ncand + 1 ints.
+int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const double* x, double dhat, PairList& out,
+                  int32_t* flag, int32_t* pos, int32_t* d_tot, void* scan_temp, int32_t* n_pt, int32_t* n_ee,
+                  hipStream_t st, int64_t* needed);
+
 // CCD: t_k per candidate pair (conservative advancement), then alpha_m.
 void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
                 int32_t steps, double* t_out, hipStream_t st);
@@ -122,8 +128,8 @@ struct Incidence {
   int32_t* clist;       // n: c index -> sim vertex
   int32_t* d_nc;        // device total
 };
-void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const uint8_t* fixed, Incidence& inc,
-                     void* scan_temp, hipStream_t st);
+void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyDev& px, const uint8_t* fixed,
+                     Incidence& inc, void* scan_temp, hipStream_t st);
 void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
                              const uint8_t* fixed, double* g, hipStream_t st);
 
@@ -140,10 +146,13 @@ struct FactorDev {
   const int32_t* h_level_ptr;      // HOST: nlevels + 1
   const int32_t* h_level_maxs;     // HOST: max s in each level
   const int32_t* h_level_maxr;     // HOST: max r in each level
+  const int32_t* h_lvl_row_ptr;    // HOST: nlevels + 1 offsets into lvl_rows
+  const int32_t* lvl_rows;         // extended index of every x1 column, by level
+  const int32_t* lvl_row_node;     // its supernode
   const int32_t* rows;
-  const double* panel;             // r x s row-major per node
+  const double* panelT;            // s x r row-major per node: L[R(J), cols(J)]^T
   const double* dinv;              // s x s row-major per node
-  const double* dinvT;             // s x s column-major per node (transpose)
+  const double* dinvT;             // s x s row-major per node of Dinv^T
   const int64_t* fwd_ptr;          // n1 + n2 + 1
   const int32_t* fwd_col;
   const double* fwd_val;
@@ -179,17 +188,21 @@ void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x
 // c index -> x2 index
 void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
 
-// ---------------------------------------------------------------- dense FP64
-// In-place lower Cholesky of an n x n row-major matrix (upper part ignored).
-// *d_info <- 0 ok, else 1 + first failing column.
+// ---------------------------------------------------------------- dense SPD
+// Lower Cholesky of an n x n row-major SPD matrix A (full symmetric input,
+// destroyed).  Writes the lower blocks of L (n x n row-major; the strict
+// upper part is not written) and the inverse of every 64 x 64 diagonal block
+// (Linv: ceil(n/64) blocks of 64 x 64).  *d_info <- 0 ok, else 1 + the first
+// failing column.
+inline int64_t dense_linv_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
 template <typename T>
-void dense_cholesky(T* A, int64_t n, int32_t* d_info, hipStream_t st);
-// Solve L L^T x = b in place (b: n x nrhs row-major), L from dense_cholesky.
+void dense_cholesky(T* A, int64_t n, T* L, T* Linv, int32_t* d_info, hipStream_t st);
+// Solve L L^T x = b in place (b: n x nrhs row-major, nrhs <= 4).
 template <typename T>
-void dense_chol_solve(const T* L, int64_t n, T* b, int32_t nrhs, hipStream_t st);
+void dense_chol_solve(const T* L, const T* Linv, int64_t n, T* b, int32_t nrhs, hipStream_t st);
 // Ainv = (L L^T)^-1 (full symmetric, row-major), work: n x n scratch
 template <typename T>
-void dense_chol_inverse(const T* L, int64_t n, T* Ainv, T* work, hipStream_t st);
+void dense_chol_inverse(const T* L, const T* Linv, int64_t n, T* Ainv, T* work, hipStream_t st);
 void launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t st);
 // r = b - M u  (dense, n x n row-major FP64), all vectors n

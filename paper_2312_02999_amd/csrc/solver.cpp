@@ -87,10 +87,10 @@ struct Solver {
   // per-iteration vectors
   DBuf<double> x, g, dx, tetg, E0, dE, Rtet, tpair, bE0, bdE, scal;
   // factor
-  DBuf<int32_t> node_c0, node_s, node_r, level_nodes, frows, fcol, ext2vert, vert2x2;
+  DBuf<int32_t> node_c0, node_s, node_r, level_nodes, frows, fcol, ext2vert, vert2x2, lvl_rows, lvl_row_node;
   DBuf<int64_t> node_roff, node_poff, node_doff, fptr;
-  DBuf<double> panel, dinv, dinvT, fval, sigma_inv;
-  std::vector<int32_t> h_level_ptr, h_level_maxs, h_level_maxr;
+  DBuf<double> panelT, dinv, dinvT, fval, sigma_inv;
+  std::vector<int32_t> h_level_ptr, h_level_maxs, h_level_maxr, h_lvl_row_ptr;
   FactorDev fd{};
   DBuf<double> bvec, yvec, solvec;
   // contact
@@ -108,8 +108,12 @@ struct Solver {
   Incidence inc{};
   // reduced system
   DBuf<int32_t> c_x2, info;
-  DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid;
-  DBuf<float> Mf, uf;
+  DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid, CsL, CsLi, ML, MLi;
+  DBuf<float> Mf, uf, MLf, MLif;
+  // swept candidates of the last step (x_prev -> x_prev + dx), valid for x on that path
+  bool cand_valid = false;
+  int32_t cand_n = 0, cand_pt = 0;
+  DBuf<int32_t> cflagbuf, cposbuf;
   // last converged state for the adjoint
   int32_t last_npairs = 0, last_npt = 0;
 
@@ -382,6 +386,30 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
       S->h_level_maxr[L] = std::max(S->h_level_maxr[L], rr[J]);
     }
   }
+  // rows of each level (columns of its supernodes), for wave-per-row sweeps
+  S->h_lvl_row_ptr.assign(hf.nlevels + 1, 0);
+  std::vector<int32_t> lrows, lnode;
+  lrows.reserve(n1);
+  lnode.reserve(n1);
+  for (int32_t L = 0; L < hf.nlevels; ++L) {
+    for (int32_t k = S->h_level_ptr[L]; k < S->h_level_ptr[L + 1]; ++k) {
+      const int32_t J = lev_nodes[k];
+      for (int32_t c = 0; c < ss[J]; ++c) {
+        lrows.push_back(c0[J] + c);
+        lnode.push_back(J);
+      }
+    }
+    S->h_lvl_row_ptr[L + 1] = static_cast<int32_t>(lrows.size());
+  }
+  // transposed panels (s x r row-major) for the upper sweep
+  std::vector<double> pT(hf.panel.size());
+  for (int32_t J = 0; J < nn; ++J) {
+    const int s_ = ss[J], r_ = rr[J];
+    const double* P = hf.panel.data() + po[J];
+    double* Q = pT.data() + po[J];
+    for (int i = 0; i < r_; ++i)
+      for (int c = 0; c < s_; ++c) Q[static_cast<int64_t>(c) * r_ + i] = P[static_cast<int64_t>(i) * s_ + c];
+  }
   std::vector<double> dT(hf.dinv.size());
   for (int32_t J = 0; J < nn; ++J) {
     const int s = ss[J];
@@ -401,7 +429,9 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   S->node_doff.upload(dof.data(), nn, st);
   S->level_nodes.upload(lev_nodes.data(), nn, st);
   S->frows.upload(hf.rows.data(), static_cast<int64_t>(hf.rows.size()), st);
-  S->panel.upload(hf.panel.data(), static_cast<int64_t>(hf.panel.size()), st);
+  S->panelT.upload(pT.data(), static_cast<int64_t>(pT.size()), st);
+  S->lvl_rows.upload(lrows.data(), static_cast<int64_t>(lrows.size()), st);
+  S->lvl_row_node.upload(lnode.data(), static_cast<int64_t>(lnode.size()), st);
   S->dinv.upload(hf.dinv.data(), static_cast<int64_t>(hf.dinv.size()), st);
   S->dinvT.upload(dT.data(), static_cast<int64_t>(dT.size()), st);
   S->fptr.upload(hf.fwd_ptr.data(), static_cast<int64_t>(hf.fwd_ptr.size()), st);
@@ -417,21 +447,26 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   // ---- Sigma^-1 on the device: Cholesky of Sigma_s, then L^-T L^-1 ---------------------------
   S->sigma_inv.ensure(std::max<int64_t>(1, static_cast<int64_t>(n2) * n2));
   if (n2 > 0) {
-    DBuf<double> sig, wk;
+    DBuf<double> sig, wk, sl, sli;
     sig.upload(hf.sigma.data(), static_cast<int64_t>(n2) * n2, st);
     wk.ensure(static_cast<int64_t>(n2) * n2);
-    dense_cholesky<double>(sig.p, n2, S->info.p, st);
+    sl.ensure(static_cast<int64_t>(n2) * n2);
+    sli.ensure(dense_linv_size(n2));
+    dense_cholesky<double>(sig.p, n2, sl.p, sli.p, S->info.p, st);
     int32_t hinfo = 0;
     HIPCHK(hipMemcpyAsync(&hinfo, S->info.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (hinfo != 0) {
-      sig.release(); wk.release();
+      sig.release(); wk.release(); sl.release(); sli.release();
       fail(PDIPC_E_NOT_SPD, "Schur complement Sigma is not positive definite");
     }
-    dense_chol_inverse<double>(sig.p, n2, S->sigma_inv.p, wk.p, st);
+    dense_chol_inverse<double>(sl.p, sli.p, n2, S->sigma_inv.p, wk.p, st);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     sig.release();
     wk.release();
+    sl.release();
+    sli.release();
   }
   FactorDev& f = S->fd;
   f.n1 = n1; f.n2 = n2; f.nnodes = nn; f.nlevels = hf.nlevels;
@@ -439,7 +474,8 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   f.node_rows_off = S->node_roff.p; f.node_panel_off = S->node_poff.p; f.node_dinv_off = S->node_doff.p;
   f.level_nodes = S->level_nodes.p;
   f.h_level_ptr = S->h_level_ptr.data(); f.h_level_maxs = S->h_level_maxs.data(); f.h_level_maxr = S->h_level_maxr.data();
-  f.rows = S->frows.p; f.panel = S->panel.p; f.dinv = S->dinv.p; f.dinvT = S->dinvT.p;
+  f.h_lvl_row_ptr = S->h_lvl_row_ptr.data(); f.lvl_rows = S->lvl_rows.p; f.lvl_row_node = S->lvl_row_node.p;
+  f.rows = S->frows.p; f.panelT = S->panelT.p; f.dinv = S->dinv.p; f.dinvT = S->dinvT.p;
   f.fwd_ptr = S->fptr.p; f.fwd_col = S->fcol.p; f.fwd_val = S->fval.p;
   f.sigma_inv = S->sigma_inv.p; f.ext2vert = S->ext2vert.p;
 
@@ -500,6 +536,25 @@ static void pairs(Solver* S, bool active, const double* xx, const double* dxx, i
   fail(PDIPC_E_NOMEM, "pair list growth failed");
 }
 
+// Constraint set from the previous step's swept candidates (same sorted set as
+// a fresh broad phase at any point of that step).
+static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee) {
+  PairList& pl = S->act;
+  if (pl.cap == 0) grow_pairs(S, pl, S->act_type, S->act_i, S->act_j, S->act_v4, 4LL * S->nsv + 1024);
+  S->cflagbuf.ensure(S->cand_n + 1);
+  S->cposbuf.ensure(S->cand_n + 1);
+  S->scan_tmp.ensure(static_cast<int64_t>(scan_temp_bytes(S->cand_n + 1)));
+  S->bb.scan_temp = S->scan_tmp.p;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    int64_t need = 0;
+    int rc = filter_active(S->cand, S->cand_n, S->cand_pt, S->x.p, S->opt.dhat, pl, S->cflagbuf.p, S->cposbuf.p,
+                           S->totals.p + 4, S->scan_tmp.p, npt, nee, S->st, &need);
+    if (rc == 0) return;
+    grow_pairs(S, pl, S->act_type, S->act_i, S->act_j, S->act_v4, need);
+  }
+  fail(PDIPC_E_NOMEM, "pair list growth failed");
+}
+
 static void ensure_pair_arrays(Solver* S, int64_t np) {
   int64_t cap = std::max<int64_t>(np, 1);
   if (S->b_energy.cap < cap) {
@@ -542,7 +597,8 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
     launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st);
   }
   launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
-  pairs(S, true, S->x.p, nullptr, &io.npt, &io.nee);
+  if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee);
+  else pairs(S, true, S->x.p, nullptr, &io.npt, &io.nee);
   const int32_t np = io.npt + io.nee;
   ensure_pair_arrays(S, np);
   if (first_check && np > 0) {
@@ -556,7 +612,7 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
     ScopedTimer tm(S, TK_BARRIER);
     launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->opt.kappa, fp32, S->bo, st);
   }
-  build_incidence(S->act, np, S->n, S->fixed.p, S->inc, S->scan_tmp.p, st);
+  build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
   launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
   io.nc = read_scalar_i(S, S->inc.d_nc);
 }
@@ -583,28 +639,34 @@ static void global_step(Solver* S, const IterOut& io) {
     S->Cinv.ensure(static_cast<int64_t>(nc) * nc);
     S->work.ensure(static_cast<int64_t>(nc) * nc);
     S->Mred.ensure(N3 * N3);
+    S->CsL.ensure(static_cast<int64_t>(nc) * nc);
+    S->CsLi.ensure(dense_linv_size(nc));
+    S->ML.ensure(N3 * N3);
+    S->MLi.ensure(dense_linv_size(N3));
     S->rhs.ensure(N3);
     S->u.ensure(N3);
     S->vvec.ensure(N3);
     launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
     launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, st);
-    dense_cholesky<double>(S->Cs.p, nc, S->info.p, st);
-    dense_chol_inverse<double>(S->Cs.p, nc, S->Cinv.p, S->work.p, st);
+    dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p, st);
+    dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, st);
     launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
     if (S->opt.precision == PDIPC_MIXED_FP32) {
       // FP32 factor of the reduced system, refined against FP64 residuals
       S->Mf.ensure(N3 * N3);
+      S->MLf.ensure(N3 * N3);
+      S->MLif.ensure(dense_linv_size(N3));
       S->uf.ensure(N3);
       S->resid.ensure(N3);
       launch_convert_f64_f32(S->Mred.p, S->Mf.p, N3 * N3, st);
-      dense_cholesky<float>(S->Mf.p, N3, S->info.p + 1, st);
+      dense_cholesky<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, st);
       if (read_scalar_i(S, S->info.p + 1) != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD (FP32)");
       launch_fill_f64(S->u.p, N3, 0.0, st);
       HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
       for (int it = 0; it < 4; ++it) {
         launch_convert_f64_f32(S->resid.p, S->uf.p, N3, st);
-        dense_chol_solve<float>(S->Mf.p, N3, S->uf.p, 1, st);
+        dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
         launch_convert_f32_f64(S->uf.p, S->vvec.p, N3, st);
         launch_axpy_positions(N3, 1.0, S->vvec.p, S->u.p, st);
         launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
@@ -612,11 +674,11 @@ static void global_step(Solver* S, const IterOut& io) {
     } else {
       {
         ScopedTimer tm(S, TK_REDUCED_CHOL);
-        dense_cholesky<double>(S->Mred.p, N3, S->info.p, st);
+        dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, st);
       }
       if (read_scalar_i(S, S->info.p) != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
       HIPCHK(hipMemcpyAsync(S->u.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
-      dense_chol_solve<double>(S->Mred.p, N3, S->u.p, 1, st);
+      dense_chol_solve<double>(S->ML.p, S->MLi.p, N3, S->u.p, 1, st);
     }
     launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
     launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
@@ -636,6 +698,9 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   pairs(S, false, S->x.p, S->dx.p, &cpt, &cee);
   const int32_t ncand = cpt + cee;
   io.ncand = ncand;
+  S->cand_n = ncand;
+  S->cand_pt = cpt;
+  S->cand_valid = apply;
   S->tpair.ensure(std::max(ncand, 1));
   S->bE0.ensure(std::max(ncand, 1));
   S->bdE.ensure(std::max(ncand, 1));
@@ -675,6 +740,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   hipStream_t st = S->st;
   auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipMemcpyAsync(S->x.p, x_in, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
+  S->cand_valid = false;
   launch_count_nonfinite(S->x.p, 3LL * S->n, S->info.p + 2, st);
   if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite input state");
   pdipc_frame_stats fs{};
@@ -697,6 +763,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
     tms[0] += std::chrono::duration<double, std::milli>(b - a).count();
     tms[1] += std::chrono::duration<double, std::milli>(c - b).count();
     tms[3] += std::chrono::duration<double, std::milli>(d - c).count();
+    HIPCHK(hipGetLastError());
     if (S->timer_which >= 0) {
       HIPCHK(hipStreamSynchronize(st));
       harvest_timer(S);
@@ -844,14 +911,14 @@ void pdipc_destroy(void* h) {
   if (!S) return;
   if (S->st) (void)hipStreamSynchronize(S->st);
   DBuf<int32_t>* bi[] = {&S->tets, &S->vt_ptr, &S->vt_ent, &S->sv, &S->stri, &S->sedge, &S->node_c0, &S->node_s,
-                         &S->node_r, &S->level_nodes, &S->frows, &S->fcol, &S->ext2vert, &S->vert2x2, &S->t_count,
+                         &S->node_r, &S->level_nodes, &S->frows, &S->fcol, &S->ext2vert, &S->vert2x2, &S->lvl_rows, &S->lvl_row_node, &S->t_count,
                          &S->t_cursor, &S->t_id, &S->e_count, &S->e_cursor, &S->e_id, &S->q_count, &S->totals,
                          &S->act_type, &S->act_i, &S->act_j, &S->act_v4, &S->cand_type, &S->cand_i, &S->cand_j,
                          &S->cand_v4, &S->inc_cnt, &S->inc_ptr, &S->inc_cursor, &S->inc_ent, &S->inc_cflag,
-                         &S->inc_cidx, &S->inc_clist, &S->inc_nc, &S->c_x2, &S->info};
+                         &S->inc_cidx, &S->inc_clist, &S->inc_nc, &S->c_x2, &S->info, &S->cflagbuf, &S->cposbuf};
   for (auto* b : bi) b->release();
   DBuf<double>* bd[] = {&S->Bm, &S->w, &S->A, &S->a_s, &S->R0, &S->X, &S->x, &S->g, &S->dx, &S->tetg, &S->E0,
-                        &S->dE, &S->Rtet, &S->tpair, &S->bE0, &S->bdE, &S->scal, &S->panel, &S->dinv, &S->dinvT,
+                        &S->dE, &S->Rtet, &S->tpair, &S->bE0, &S->bdE, &S->scal, &S->panelT, &S->dinv, &S->dinvT,
                         &S->fval, &S->sigma_inv, &S->bvec, &S->yvec, &S->solvec, &S->vbox, &S->tbox, &S->ebox,
                         &S->params, &S->b_energy, &S->b_grad, &S->b_U, &S->Cs, &S->Cinv, &S->work, &S->Mred,
                         &S->rhs, &S->u, &S->vvec, &S->wtmp, &S->resid};
@@ -859,7 +926,8 @@ void pdipc_destroy(void* h) {
   S->fixed.release();
   S->node_roff.release(); S->node_poff.release(); S->node_doff.release(); S->fptr.release();
   S->t_key.release(); S->e_key.release(); S->scan_tmp.release(); S->red_tmp.release();
-  S->Mf.release(); S->uf.release();
+  S->Mf.release(); S->uf.release(); S->MLf.release(); S->MLif.release();
+  S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release();
   delete S;
 }
 
@@ -909,6 +977,7 @@ int32_t pdipc_debug_contacts(void* h, const double* x, int32_t* out, int32_t cap
   if (!S || !x || !count) return PDIPC_E_INVALID;
   return guarded(S, [&] {
     int32_t npt = 0, nee = 0;
+    S->cand_valid = false;
     pairs(S, true, x, nullptr, &npt, &nee);
     const int32_t np = npt + nee;
     *count = np;
@@ -933,6 +1002,7 @@ int32_t pdipc_debug_step(void* h, const double* x, double* dx, double* alpha_m, 
   return guarded(S, [&] {
     if (!S->have_actuation) fail(PDIPC_E_INVALID, "no actuation set");
     HIPCHK(hipMemcpyAsync(S->x.p, x, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
+    S->cand_valid = false;
     IterOut io;
     assemble_gradient(S, true, io);
     global_step(S, io);
@@ -943,6 +1013,59 @@ int32_t pdipc_debug_step(void* h, const double* x, double* dx, double* alpha_m, 
     if (alpha) *alpha = io.alpha;
     return PDIPC_OK;
   });
+}
+
+// Dense SPD kernels on caller data (device): factor A (n x n, preserved), solve
+// A x = b in place (b: n x nrhs), and write A^-1 if Ainv is not NULL.
+// precision 1 runs the FP32 kernels on a rounded copy.  Test tap.
+int32_t pdipc_debug_dense(const double* A, int64_t n, double* b, int32_t nrhs, double* Ainv, int32_t precision) {
+  if (!A || n <= 0 || nrhs < 0 || nrhs > 4) return PDIPC_E_INVALID;
+  try {
+    hipStream_t st = nullptr;
+    const int64_t nn = n * n;
+    DBuf<int32_t> info;
+    info.ensure(1);
+    int32_t hinfo = 0;
+    if (precision == 0) {
+      DBuf<double> W, L, Li, wk;
+      W.ensure(nn); L.ensure(nn); Li.ensure(dense_linv_size(n)); wk.ensure(nn);
+      HIPCHK(hipMemcpyAsync(W.p, A, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+      dense_cholesky<double>(W.p, n, L.p, Li.p, info.p, st);
+      if (b && nrhs > 0) dense_chol_solve<double>(L.p, Li.p, n, b, nrhs, st);
+      if (Ainv) dense_chol_inverse<double>(L.p, Li.p, n, Ainv, wk.p, st);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      W.release(); L.release(); Li.release(); wk.release();
+    } else {
+      DBuf<float> W, L, Li, wk, bf, invf;
+      W.ensure(nn); L.ensure(nn); Li.ensure(dense_linv_size(n)); wk.ensure(nn);
+      launch_convert_f64_f32(A, W.p, nn, st);
+      dense_cholesky<float>(W.p, n, L.p, Li.p, info.p, st);
+      if (b && nrhs > 0) {
+        bf.ensure(n * nrhs);
+        launch_convert_f64_f32(b, bf.p, n * nrhs, st);
+        dense_chol_solve<float>(L.p, Li.p, n, bf.p, nrhs, st);
+        launch_convert_f32_f64(bf.p, b, n * nrhs, st);
+      }
+      if (Ainv) {
+        invf.ensure(nn);
+        dense_chol_inverse<float>(L.p, Li.p, n, invf.p, wk.p, st);
+        launch_convert_f32_f64(invf.p, Ainv, nn, st);
+      }
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      W.release(); L.release(); Li.release(); wk.release(); bf.release(); invf.release();
+    }
+    info.release();
+    return hinfo == 0 ? PDIPC_OK : PDIPC_E_NOT_SPD;
+  } catch (const SolverError& e) {
+    return e.code;
+  } catch (const HipFailure& e) {
+    g_last_init_error = e.msg;
+    return PDIPC_E_HIP;
+  }
 }
 
 // Host-only check of the set-up factorization (no device work): solves

@@ -132,3 +132,27 @@ def test_frame_c1_first_frame():
     print(f"C1 frame 1: n_pt {st['n_pt']} n_ee {st['n_ee']} n_c {st['n_c']} err {err:.3e} ms {st['ms_total']:.1f}")
     assert st["n_pt"] == r.n_pt[-1] and st["n_ee"] == r.n_ee[-1]
     assert err < 1e-9, err
+
+
+@pytest.mark.parametrize("n", [5, 64, 130, 257, 700])
+def test_dense_spd_kernels(n):
+    """Cholesky, solve and inverse against numpy at ragged multi-tile sizes."""
+    from paper_2312_02999_amd import dense_spd
+    rng = np.random.default_rng(n)
+    G = rng.standard_normal((n, n))
+    A = G @ G.T / n + np.eye(n) * 0.5
+    b = rng.standard_normal((n, 3))
+    x, inv = dense_spd(_t(A), _t(b), inverse=True)
+    xr = np.linalg.solve(A, b)
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-10 * max(1.0, np.abs(xr).max())
+    assert np.abs(inv.cpu().numpy() - np.linalg.inv(A)).max() < 1e-10 * np.abs(np.linalg.inv(A)).max()
+    xf, _ = dense_spd(_t(A), _t(b), precision=1)
+    assert np.abs(xf.cpu().numpy() - xr).max() < 1e-3 * max(1.0, np.abs(xr).max())
+
+
+def test_dense_spd_rejects_indefinite():
+    from paper_2312_02999_amd import dense_spd, PdipcError
+    A = np.eye(70)
+    A[66, 66] = -1.0
+    with pytest.raises(PdipcError):
+        dense_spd(_t(A), _t(np.ones((70, 1))))
