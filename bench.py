@@ -76,6 +76,8 @@ def run_precision(sc, precision, steps, warmup, timer_kernel):
         "kernel_ms_total": k_ms, "kernel_launches": k_count, "sizes": sizes,
         "n_c_max": max(s["n_c"] for s in stats), "n_pt_last": stats[-1]["n_pt"], "n_ee_last": stats[-1]["n_ee"],
         "ls_failures": sum(s["ls_failures"] for s in stats),
+        "refine_steps": sum(s["refine_steps"] for s in stats),
+        "refine_fallbacks": sum(s["refine_fallbacks"] for s in stats),
         "stage_ms": {k: float(np.mean([s[k] for s in stats])) for k in ("ms_ipc", "ms_gstep", "ms_ls", "ms_misc")},
         "x_final": x.cpu().numpy(),
     }
@@ -152,6 +154,7 @@ def main():
                  "p50_ms": round(fp64["p50_ms"], 3), "p99_ms": round(fp64["p99_ms"], 3),
                  "stage_ms": fp64["stage_ms"], "n_c_max": fp64["n_c_max"], "ls_failures": fp64["ls_failures"]},
         "mixed": {"stage_ms": mixed["stage_ms"], "n_c_max": mixed["n_c_max"], "ls_failures": mixed["ls_failures"],
+                  "refine_steps": mixed["refine_steps"], "refine_fallbacks": mixed["refine_fallbacks"],
                   "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -96,10 +96,12 @@ typedef struct {
 
 /* Per-frame statistics (host).  Stage times follow the paper's Table 1
  * columns: IPC (constraint set + barrier derivatives), G-Step (global solve),
- * CCD, LS (line search), Misc (local step, assembly, bookkeeping). */
+ * CCD, LS (line search), Misc (local step, assembly, bookkeeping).
+ * refine_steps / refine_fallbacks: mixed-precision refinement solves and the
+ * iterations whose reduced system fell back to the FP64 factor. */
 typedef struct {
   int32_t iters, n_pt, n_ee, n_c, ls_halvings, ls_failures, refine_steps;
-  int32_t n_candidates;
+  int32_t n_candidates, refine_fallbacks;
   double alpha_m_min, alpha_min, energy, grad_inf;
   double ms_ipc, ms_gstep, ms_ccd, ms_ls, ms_misc, ms_total;
 } pdipc_frame_stats;
@@ -136,6 +138,9 @@ int32_t pdipc_solve_frame(void* solver, const double* x_in, double* x_out, pdipc
  * n_verts x 3), writes dL/da (device, n_tets).  Solves K lambda = dL/dx* with
  * K the Hessian of the total energy at x* (Eq. 1 and Eq. 3 terms). */
 int32_t pdipc_solve_frame_backward(void* solver, const double* dL_dx, double* dL_da);
+
+/* Device memory currently held by the solver, in bytes (host out). */
+int32_t pdipc_device_bytes(const void* solver, int64_t* bytes);
 
 /* Sizes of the blocks after init: n1, n2 of Eq. (6) and nnz of the factor. */
 int32_t pdipc_get_sizes(const void* solver, int64_t* n1, int64_t* n2, int64_t* factor_nnz);

@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import FrameStats, MeshDesc, Options, PdipcError, check, lib
 
-__all__ = ["Solver", "PdipcError", "FP64", "MIXED_FP32", "host_factor_solve", "actuation_rows"]
+__all__ = ["Solver", "PdipcError", "FP64", "MIXED_FP32", "host_factor_solve", "actuation_rows", "PDIPCFrame",
+           "dense_spd"]
 
 FP64, MIXED_FP32 = 0, 1
 
@@ -83,6 +84,11 @@ class Solver:
         check(lib().pdipc_get_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)), self._h)
         return {"n1": a.value, "n2": b.value, "factor_nnz": c.value}
 
+    def device_bytes(self) -> int:
+        b = C.c_int64()
+        check(lib().pdipc_device_bytes(self._h, C.byref(b)), self._h)
+        return b.value
+
     def set_actuation(self, A: torch.Tensor):
         check(lib().pdipc_set_actuation(self._h, _dev(A, (self.m, 6))), self._h)
 
@@ -132,6 +138,26 @@ class Solver:
         am, a = C.c_double(), C.c_double()
         check(lib().pdipc_debug_step(self._h, _dev(x, (self.n, 3)), _dev(dx), C.byref(am), C.byref(a)), self._h)
         return dx, am.value, a.value
+
+
+class PDIPCFrame(torch.autograd.Function):
+    """x* = frame(a; x_init) as a differentiable function of the per-tet
+    actuation scalars a (frames R fixed).  The backward pass is the adjoint of
+    the converged quasi-static solve (``pdipc_solve_frame_backward``); the
+    gradient with respect to x_init is None because an equilibrium does not
+    depend on its initial guess.  The solver must not run another frame
+    between forward and backward."""
+
+    @staticmethod
+    def forward(ctx, a, x_init, solver, R):
+        solver.set_actuation_scalar(a.detach().contiguous(), R)
+        x = solver.solve_frame(x_init.detach().contiguous())
+        ctx.solver = solver
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        return ctx.solver.solve_frame_backward(gx.contiguous()), None, None, None
 
 
 def dense_spd(A: torch.Tensor, b: torch.Tensor | None = None, inverse: bool = False, precision: int = FP64):

@@ -26,7 +26,7 @@ EXPORTS = [
     "pdipc_default_options", "pdipc_init_mesh", "pdipc_set_actuation", "pdipc_set_actuation_scalar",
     "pdipc_solve_frame", "pdipc_solve_frame_backward", "pdipc_get_sizes", "pdipc_destroy",
     "pdipc_last_error", "pdipc_debug_local", "pdipc_debug_contacts", "pdipc_debug_step",
-    "pdipc_debug_host_factor", "pdipc_kernel_timer", "pdipc_debug_dense",
+    "pdipc_debug_host_factor", "pdipc_kernel_timer", "pdipc_debug_dense", "pdipc_device_bytes",
 ]
 
 
@@ -46,7 +46,7 @@ class Options(C.Structure):
 class FrameStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_pt", C.c_int32), ("n_ee", C.c_int32), ("n_c", C.c_int32),
                 ("ls_halvings", C.c_int32), ("ls_failures", C.c_int32), ("refine_steps", C.c_int32),
-                ("n_candidates", C.c_int32), ("alpha_m_min", C.c_double), ("alpha_min", C.c_double),
+                ("n_candidates", C.c_int32), ("refine_fallbacks", C.c_int32), ("alpha_m_min", C.c_double), ("alpha_min", C.c_double),
                 ("energy", C.c_double), ("grad_inf", C.c_double), ("ms_ipc", C.c_double),
                 ("ms_gstep", C.c_double), ("ms_ccd", C.c_double), ("ms_ls", C.c_double),
                 ("ms_misc", C.c_double), ("ms_total", C.c_double)]
@@ -98,6 +98,8 @@ def lib():
     L.pdipc_kernel_timer.restype = i32
     L.pdipc_debug_dense.argtypes = [dp, i64, dp, i32, dp, i32]
     L.pdipc_debug_dense.restype = i32
+    L.pdipc_device_bytes.argtypes = [vp, C.POINTER(i64)]
+    L.pdipc_device_bytes.restype = i32
     _lib = L
     return L
 

@@ -224,6 +224,27 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
     }
 }
 
+// FP64 barrier energy and gradient only
+__device__ void pair_energy_grad(const double P[4][3], bool is_pt, double dhat, double kappa, double& energy,
+                                 double grad[12]) {
+  Feature<double> f;
+  pair_feature<double>(is_pt, P, f);
+  double q[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) q[r] += f.c[j] * P[j][r];
+  const double D = dot3(q, q), d = sqrt(D);
+  const double e = d - dhat, lg = log(d / dhat);
+  const double b1 = -2.0 * e * lg - e * e / d;
+  const double phi1 = kappa * b1 / (2.0 * d);
+  energy = -kappa * e * e * lg;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) grad[3 * j + r] = phi1 * 2.0 * f.c[j] * q[r];
+}
+
 __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
                                                      const double* __restrict__ x, double dhat, double kappa,
                                                      bool fp32, double* __restrict__ energy,
@@ -234,8 +255,13 @@ __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__
   double P[4][3];
   load_pair_rel(v4, x, P);
   double e, g[12], u[12][5];
-  if (fp32) pair_barrier<float>(P, k < n_pt, dhat, kappa, e, g, u);
-  else pair_barrier<double>(P, k < n_pt, dhat, kappa, e, g, u);
+  if (fp32) {
+    // FP32 Hessian factor; energy and gradient (which fix the equilibrium) in FP64
+    pair_barrier<float>(P, k < n_pt, dhat, kappa, e, g, u);
+    pair_energy_grad(P, k < n_pt, dhat, kappa, e, g);
+  } else {
+    pair_barrier<double>(P, k < n_pt, dhat, kappa, e, g, u);
+  }
   energy[k] = e;
 #pragma unroll
   for (int i = 0; i < 12; ++i) grad[static_cast<int64_t>(i) * npairs + k] = g[i];
@@ -271,32 +297,22 @@ __global__ void inc_fill_kernel(const int32_t* __restrict__ v4, int32_t npairs, 
   }
 }
 
-// Sort each proxy vertex's incidence list (keys are unique: 4 * pair + local),
-// one wave per vertex: every lane ranks its key against the others.  Lists
-// longer than a wave fall back to an insertion sort by one lane.
+// Sort each proxy vertex's incidence list (keys are unique: 4 * pair + local)
+// into a second array, one wave per vertex: each lane ranks its keys against
+// the whole list (any length), then scatters them to their rank.
 __global__ void __launch_bounds__(256) inc_sort_kernel(int32_t nsv, const int32_t* __restrict__ sv,
-                                                       const int32_t* __restrict__ ptr, int32_t* __restrict__ ent) {
+                                                       const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
+                                                       int32_t* __restrict__ out) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
   if (w >= nsv) return;
   const int32_t v = sv[w];
   const int32_t b = ptr[v], e = ptr[v + 1], cnt = e - b;
-  if (cnt <= 1) return;
-  if (cnt <= PDIPC_WAVE) {
-    int32_t key = lane < cnt ? ent[b + lane] : 0x7fffffff;
+  for (int32_t i = lane; i < cnt; i += PDIPC_WAVE) {
+    const int32_t key = ent[b + i];
     int32_t rank = 0;
-    for (int j = 0; j < cnt; ++j) {
-      int32_t kj = __shfl(key, j, PDIPC_WAVE);
-      rank += (kj < key) ? 1 : 0;
-    }
-    if (lane < cnt) ent[b + rank] = key;
-  } else if (lane == 0) {
-    for (int32_t i = b + 1; i < e; ++i) {
-      int32_t key = ent[i];
-      int32_t j = i - 1;
-      while (j >= b && ent[j] > key) { ent[j + 1] = ent[j]; --j; }
-      ent[j + 1] = key;
-    }
+    for (int32_t j = 0; j < cnt; ++j) rank += ent[b + j] < key ? 1 : 0;
+    out[b + rank] = key;
   }
 }
 
@@ -321,8 +337,8 @@ void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyD
   if (npairs > 0) inc_count_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cnt);
   launch_exclusive_scan(inc.cnt, inc.ptr, n + 1, inc.d_nc, scan_temp, st);
   hipMemcpyAsync(inc.cursor, inc.ptr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
-  if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.ent);
-  if (npairs > 0) inc_sort_kernel<<<grid_for(px.nsv, 4), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent);
+  if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.raw);
+  if (npairs > 0) inc_sort_kernel<<<grid_for(px.nsv, 4), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.raw, inc.ent);
   cflag_kernel<<<grid_for(n + 1, 256), 256, 0, st>>>(n, inc.ptr, fixed, inc.cflag);
   launch_exclusive_scan(inc.cflag, inc.cidx, n + 1, inc.d_nc, scan_temp, st);
   clist_kernel<<<grid_for(n, 256), 256, 0, st>>>(n, inc.cflag, inc.cidx, inc.clist);

@@ -178,13 +178,14 @@ __device__ __forceinline__ bool box_overlap(const double* a, const double* b, do
          a[2] <= b[5] + dhat && b[2] <= a[5] + dhat;
 }
 
-// Visit all accepted partners of query q; call emit(partner, v4).
+// Visit the accepted partners of query q inside cell slot `slot` (0..26) of
+// its (at most 3 x 3 x 3) cell range; call emit(partner).
 template <typename Emit>
-__device__ void visit_partners(const QueryArgs& qa, int64_t q, Emit emit) {
+__device__ void visit_slot(const QueryArgs& qa, int64_t q, int slot, Emit emit) {
   const ProxyDev& px = qa.px;
   const bool is_pt = q < px.nsv;
   const double* qb;
-  int32_t qv[2];
+  int32_t qv[2] = {0, 0};
   if (is_pt) {
     qb = qa.vbox + 6 * q;
     qv[0] = px.sv[q];
@@ -202,90 +203,99 @@ __device__ void visit_partners(const QueryArgs& qa, int64_t q, Emit emit) {
     ql[r] = cell_of(qb[r] - pad, o[r], h);
     qu[r] = clamp_hi(ql[r], cell_of(qb[3 + r] + pad, o[r], h));
   }
+  const int32_t i = ql[0] + slot % 3, j = ql[1] + (slot / 3) % 3, k = ql[2] + slot / 9;
+  if (i > qu[0] || j > qu[1] || k > qu[2]) return;
   const int32_t* start = is_pt ? qa.t_start : qa.e_start;
   const int32_t* ids = is_pt ? qa.t_id : qa.e_id;
   const uint64_t* keys = is_pt ? qa.t_key : qa.e_key;
   const double* pbox = is_pt ? qa.tbox : qa.ebox;
-  for (int32_t k = ql[2]; k <= qu[2]; ++k)
-    for (int32_t j = ql[1]; j <= qu[1]; ++j)
-      for (int32_t i = ql[0]; i <= qu[0]; ++i) {
-        uint32_t hh = cell_hash(i, j, k, qa.mask);
-        uint64_t key = cell_key(i, j, k);
-        for (int32_t s = start[hh]; s < start[hh + 1]; ++s) {
-          if (keys[s] != key) continue;
-          int32_t p = ids[s];
-          if (!is_pt && p <= q - px.nsv) continue;
-          const double* b = pbox + 6 * static_cast<int64_t>(p);
-          int32_t pl0 = cell_of(b[0], o[0], h), pl1 = cell_of(b[1], o[1], h), pl2 = cell_of(b[2], o[2], h);
-          if (max(ql[0], pl0) != i || max(ql[1], pl1) != j || max(ql[2], pl2) != k) continue;
-          if (!box_overlap(qb, b, qa.dhat)) continue;
-          int32_t v4[4];
-          if (is_pt) {
-            int32_t t0 = px.st[3 * p], t1 = px.st[3 * p + 1], t2 = px.st[3 * p + 2];
-            if (qv[0] == t0 || qv[0] == t1 || qv[0] == t2) continue;
-            v4[0] = qv[0]; v4[1] = t0; v4[2] = t1; v4[3] = t2;
-          } else {
-            int32_t b0 = px.se[2 * p], b1 = px.se[2 * p + 1];
-            if (qv[0] == b0 || qv[0] == b1 || qv[1] == b0 || qv[1] == b1) continue;
-            v4[0] = qv[0]; v4[1] = qv[1]; v4[2] = b0; v4[3] = b1;
-          }
-          if (qa.dist) {
-            double P[4][3];
-            load_pair_rel(v4, qa.x, P);
-            double d2 = pair_dist2<double>(is_pt, P);
-            if (!(d2 < qa.dhat * qa.dhat)) continue;
-          }
-          emit(p, v4);
-        }
-      }
+  const uint32_t hh = cell_hash(i, j, k, qa.mask);
+  const uint64_t key = cell_key(i, j, k);
+  for (int32_t s = start[hh]; s < start[hh + 1]; ++s) {
+    if (keys[s] != key) continue;
+    int32_t p = ids[s];
+    if (!is_pt && p <= q - px.nsv) continue;
+    const double* b = pbox + 6 * static_cast<int64_t>(p);
+    int32_t pl0 = cell_of(b[0], o[0], h), pl1 = cell_of(b[1], o[1], h), pl2 = cell_of(b[2], o[2], h);
+    if (max(ql[0], pl0) != i || max(ql[1], pl1) != j || max(ql[2], pl2) != k) continue;
+    if (!box_overlap(qb, b, qa.dhat)) continue;
+    int32_t v4[4];
+    if (is_pt) {
+      int32_t t0 = px.st[3 * p], t1 = px.st[3 * p + 1], t2 = px.st[3 * p + 2];
+      if (qv[0] == t0 || qv[0] == t1 || qv[0] == t2) continue;
+      v4[0] = qv[0]; v4[1] = t0; v4[2] = t1; v4[3] = t2;
+    } else {
+      int32_t b0 = px.se[2 * p], b1 = px.se[2 * p + 1];
+      if (qv[0] == b0 || qv[0] == b1 || qv[1] == b0 || qv[1] == b1) continue;
+      v4[0] = qv[0]; v4[1] = qv[1]; v4[2] = b0; v4[3] = b1;
+    }
+    if (qa.dist) {
+      double P[4][3];
+      load_pair_rel(v4, qa.x, P);
+      double d2 = pair_dist2<double>(is_pt, P);
+      if (!(d2 < qa.dhat * qa.dhat)) continue;
+    }
+    emit(p);
+  }
 }
 
-constexpr int QT = 64;   // small blocks: few queries, spread over many CUs
+constexpr int QT = 256;
+constexpr int SLOTS = 27;
 
 __global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
-  if (q >= static_cast<int64_t>(qa.px.nsv) + qa.px.nse) return;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
+  const int64_t nq = static_cast<int64_t>(qa.px.nsv) + qa.px.nse;
+  if (t >= nq * SLOTS) return;
   int32_t c = 0;
-  visit_partners(qa, q, [&](int32_t, const int32_t*) { ++c; });
-  qcount[q] = c;
+  visit_slot(qa, t / SLOTS, static_cast<int>(t % SLOTS), [&](int32_t) { ++c; });
+  qcount[t] = c;
 }
 
 __global__ void __launch_bounds__(QT) query_fill_kernel(QueryArgs qa, const int32_t* __restrict__ qoff,
-                                                        int32_t* __restrict__ ptype, int32_t* __restrict__ pi,
-                                                        int32_t* __restrict__ pj, int32_t* __restrict__ pv4) {
-  int64_t q = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
-  if (q >= static_cast<int64_t>(qa.px.nsv) + qa.px.nse) return;
-  const bool is_pt = q < qa.px.nsv;
-  const int32_t begin = qoff[q];
-  int32_t c = begin;
-  const int32_t qi = is_pt ? qa.px.sv[q] : static_cast<int32_t>(q - qa.px.nsv);
-  visit_partners(qa, q, [&](int32_t p, const int32_t* v4) {
-    ptype[c] = is_pt ? 0 : 1;
-    pi[c] = qi;
-    pj[c] = p;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pv4[4 * c + k] = v4[k];
-    ++c;
-  });
-  // insertion sort of this query's partners by partner id
-  for (int32_t a = begin + 1; a < c; ++a) {
-    int32_t key = pj[a];
-    int32_t kv[4] = {pv4[4 * a], pv4[4 * a + 1], pv4[4 * a + 2], pv4[4 * a + 3]};
-    int32_t b = a - 1;
-    while (b >= begin && pj[b] > key) {
-      pj[b + 1] = pj[b];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) pv4[4 * (b + 1) + k] = pv4[4 * b + k];
-      --b;
+                                                        int32_t* __restrict__ tmpj) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
+  const int64_t nq = static_cast<int64_t>(qa.px.nsv) + qa.px.nse;
+  if (t >= nq * SLOTS) return;
+  int32_t c = qoff[t];
+  visit_slot(qa, t / SLOTS, static_cast<int>(t % SLOTS), [&](int32_t p) { tmpj[c++] = p; });
+}
+
+// one wave per query: rank its partners (unique ids) and emit sorted pairs
+__global__ void __launch_bounds__(256) query_emit_kernel(ProxyDev px, const int32_t* __restrict__ qoff,
+                                                         const int32_t* __restrict__ tmpj, int32_t* __restrict__ ptype,
+                                                         int32_t* __restrict__ pi, int32_t* __restrict__ pj,
+                                                         int32_t* __restrict__ pv4) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
+  const int64_t nq = static_cast<int64_t>(px.nsv) + px.nse;
+  if (q >= nq) return;
+  const int32_t b = qoff[q * SLOTS], e = qoff[q * SLOTS + SLOTS], cnt = e - b;
+  const bool is_pt = q < px.nsv;
+  const int32_t qi = is_pt ? px.sv[q] : static_cast<int32_t>(q - px.nsv);
+  for (int32_t a = lane; a < cnt; a += PDIPC_WAVE) {
+    const int32_t key = tmpj[b + a];
+    int32_t rank = 0;
+    for (int32_t j = 0; j < cnt; ++j) rank += tmpj[b + j] < key ? 1 : 0;
+    const int32_t o = b + rank;
+    ptype[o] = is_pt ? 0 : 1;
+    pi[o] = qi;
+    pj[o] = key;
+    if (is_pt) {
+      pv4[4 * o] = qi;
+      pv4[4 * o + 1] = px.st[3 * key];
+      pv4[4 * o + 2] = px.st[3 * key + 1];
+      pv4[4 * o + 3] = px.st[3 * key + 2];
+    } else {
+      pv4[4 * o] = px.se[2 * qi];
+      pv4[4 * o + 1] = px.se[2 * qi + 1];
+      pv4[4 * o + 2] = px.se[2 * key];
+      pv4[4 * o + 3] = px.se[2 * key + 1];
     }
-    pj[b + 1] = key;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pv4[4 * (b + 1) + k] = kv[k];
   }
 }
 
 __global__ void pt_total_kernel(const int32_t* __restrict__ qoff, int32_t nsv, int32_t* __restrict__ out) {
-  *out = qoff[nsv];
+  *out = qoff[static_cast<int64_t>(nsv) * SLOTS];
 }
 
 int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x, const double* dx, double dhat,
@@ -293,6 +303,7 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
                int64_t* needed) {
   const int64_t total = static_cast<int64_t>(px.nsv) + px.nst + px.nse;
   const int64_t nq = static_cast<int64_t>(px.nsv) + px.nse;
+  const int64_t nslots = nq * SLOTS;
   *needed = 0;
   if (px.nsv == 0 || (px.nst == 0 && px.nse == 0)) {
     *n_pt = 0;
@@ -306,7 +317,6 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
   grid_params_final<<<1, 64, 0, st>>>(part, 64, pad, bb.params);
   const uint32_t T = 1u << bb.table_bits;
   const uint32_t mask = T - 1;
-  // triangle table
   launch_fill_i32(bb.t_count, T + 1, 0, st);
   launch_fill_i32(bb.e_count, T + 1, 0, st);
   if (px.nst) insert_kernel<false><<<grid_for(px.nst, BT), BT, 0, st>>>(px.nst, bb.tbox, bb.params, mask, bb.t_count, nullptr, nullptr);
@@ -320,23 +330,25 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
 
   QueryArgs qa{px, x, bb.vbox, bb.tbox, bb.ebox, bb.params, mask, bb.t_count, bb.t_id, bb.t_key,
                bb.e_count, bb.e_id, bb.e_key, dhat, distance_filter};
-  launch_fill_i32(bb.q_count + nq, 1, 0, st);     // sentinel slot of the scan
-  query_count_kernel<<<grid_for(nq, QT), QT, 0, st>>>(qa, bb.q_count);
-  launch_exclusive_scan(bb.q_count, bb.q_count, nq + 1, bb.d_totals, bb.scan_temp, st);
+  launch_fill_i32(bb.q_count + nslots, 1, 0, st);     // sentinel slot of the scan
+  query_count_kernel<<<grid_for(nslots, QT), QT, 0, st>>>(qa, bb.q_count);
+  launch_exclusive_scan(bb.q_count, bb.q_count, nslots + 1, bb.d_totals, bb.scan_temp, st);
   pt_total_kernel<<<1, 1, 0, st>>>(bb.q_count, px.nsv, bb.d_totals + 1);
   int32_t h_tot[4];
   hipMemcpyAsync(h_tot, bb.d_totals, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
   const int32_t npairs = h_tot[0];
   if (h_tot[2] > bb.ent_cap || h_tot[3] > bb.ent_cap) return -1;   // grid sizing broke
-  if (npairs > out.cap) {
+  if (npairs > out.cap || npairs > bb.tmp_cap) {
     *needed = npairs;
     return 1;
   }
   *n_pt = h_tot[1];
   *n_ee = npairs - h_tot[1];
-  if (npairs > 0)
-    query_fill_kernel<<<grid_for(nq, QT), QT, 0, st>>>(qa, bb.q_count, out.type, out.i, out.j, out.v4);
+  if (npairs > 0) {
+    query_fill_kernel<<<grid_for(nslots, QT), QT, 0, st>>>(qa, bb.q_count, bb.tmpj);
+    query_emit_kernel<<<grid_for(nq, 4), 256, 0, st>>>(px, bb.q_count, bb.tmpj, out.type, out.i, out.j, out.v4);
+  }
   return 0;
 }
 

@@ -27,19 +27,27 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
   const int64_t i0 = ti * 64, j0 = tj * 64;
-  for (int64_t k0 = 0; k0 < K; k0 += 16) {
-    for (int idx = threadIdx.x; idx < 16 * 64; idx += 256) {
+  T pa[4], pb[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int idx = threadIdx.x + 256 * u;
       int kk = idx / 64, r = idx % 64;
-      int64_t gi = i0 + r, gk = k0 + kk;
-      T va = T(0);
-      if (gi < M && gk < K) va = TA ? A[gk * lda + gi] : A[gi * lda + gk];
-      As[kk][r] = va;
-      int64_t gj = j0 + r;
-      T vb = T(0);
-      if (gj < N && gk < K) vb = TB ? B[gj * ldb + gk] : B[gk * ldb + gj];
-      Bs[kk][r] = vb;
+      int64_t gi = i0 + r, gk = k0 + kk, gj = j0 + r;
+      pa[u] = (gi < M && gk < K) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : T(0);
+      pb[u] = (gj < N && gk < K) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : T(0);
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int idx = threadIdx.x + 256 * u;
+      As[idx / 64][idx % 64] = pa[u];
+      Bs[idx / 64][idx % 64] = pb[u];
     }
     __syncthreads();
+    if (k0 + 16 < K) fetch(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       T a[4], b[4];
@@ -73,46 +81,95 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
 //   P_i = A_ik Linv_k^T          (panel solve via the stored inverse of L_kk)
 //   A_ij -= P_i P_j^T            (trailing update)
 // the diagonal tile (i, i) also writes P_i into L, and tile (k+1, k+1), after
-// its last update, factors itself and stores L_{k+1,k+1} and its inverse.
-// A is the workspace (destroyed); L and the block inverses are the outputs.
+// its last update, factors itself and stores the inverse of L_{k+1,k+1}.
+// A is the workspace (destroyed); the off-diagonal blocks of L and the
+// diagonal-block inverses are the outputs (the solves never need L_kk).
 // Ragged last blocks are padded with the identity.
 
-// Factor the 64x64 tile in LDS (lower, padded beyond kb with identity) and
-// write its inverse into X; 256 threads.
+// Factor the 64x64 tile held in LDS (lower part; rows and columns beyond kb
+// are the identity) and write the inverse of its Cholesky factor to Linv
+// (global, 64 x 64 row-major).  256 threads; thread (ty, tx) keeps rows
+// 4ty..4ty+3 x columns 4tx..4tx+3 of the tile and of the inverse in
+// registers.  Step j broadcasts column j of the tile and row j of the
+// inverse through double-buffered LDS vectors:
+//   L[:, j] = T[:, j] / sqrt(T[j][j]);  T[i][l] -= L[i][j] L[l][j]  (i, l > j)
+//   X[j, :] /= L[j][j];                 X[i, :] -= L[i][j] X[j, :]  (i > j)
+// starting from X = I, which leaves X = L^-1 (forward elimination on I).
 template <typename T>
-__device__ void tile_factor_inverse(T (*Tl)[NB + 1], T (*X)[NB + 1], int kb, int64_t k0, int32_t* info) {
-  for (int j = 0; j < NB; ++j) {
-    T d = Tl[j][j];
-    if (j < kb && !(d > T(0)) && threadIdx.x == 0 && *info == 0) *info = static_cast<int32_t>(k0 + j + 1);
-    if (!(d > T(0))) d = T(1);
-    d = sqrt(d);
-    __syncthreads();
-    for (int i = j + threadIdx.x; i < NB; i += blockDim.x) Tl[i][j] = (i == j) ? d : Tl[i][j] / d;
-    __syncthreads();
-    const int m = NB - j - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      int i = j + 1 + idx / m, l = j + 1 + idx % m;
-      if (l <= i) Tl[i][l] -= Tl[i][j] * Tl[l][j];
+__device__ void tile_factor_inverse(const T (*Tl)[NB + 1], T* __restrict__ Linv, int kb, int64_t k0,
+                                    int32_t* info, T (*colbuf)[NB], T (*rowbuf)[NB]) {
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  const int r0 = 4 * ty, c0 = 4 * tx;
+  T tr[4][4], xr[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      tr[a][b] = Tl[r0 + a][c0 + b];
+      xr[a][b] = (r0 + a == c0 + b) ? T(1) : T(0);
     }
-    __syncthreads();
-  }
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
-    for (int r = 0; r < NB; ++r) {
-      if (r < c) { X[r][c] = T(0); continue; }
-      T acc = (r == c) ? T(1) : T(0);
-      for (int p = c; p < r; ++p) acc -= Tl[r][p] * X[p][c];
-      X[r][c] = acc / Tl[r][r];
-    }
-  }
   __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    const int buf = j & 1;
+    if (j >= c0 && j < c0 + 4) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (c0 + b == j)
+#pragma unroll
+          for (int a = 0; a < 4; ++a) colbuf[buf][r0 + a] = tr[a][b];
+    }
+    __syncthreads();
+    T d = colbuf[buf][j];
+    if (!(d > T(0))) {
+      if (j < kb && threadIdx.x == 0 && *info == 0) *info = static_cast<int32_t>(k0 + j + 1);
+      d = T(1);
+    }
+    const T sd = sqrt(d), isd = T(1) / sd;
+    T lr[4], lc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      lr[a] = colbuf[buf][r0 + a] * isd;
+      lc[a] = colbuf[buf][c0 + a] * isd;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = r0 + a, l = c0 + b;
+        if (i > j && l > j && l <= i) tr[a][b] -= lr[a] * lc[b];
+      }
+    if (j >= r0 && j < r0 + 4) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (r0 + a == j)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            xr[a][b] *= isd;
+            rowbuf[buf][c0 + b] = xr[a][b];
+          }
+    }
+    __syncthreads();
+    T xj[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xj[b] = rowbuf[buf][c0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (r0 + a > j)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) xr[a][b] -= lr[a] * xj[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Linv[(r0 + a) * NB + c0 + b] = xr[a][b];
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ L,
                                                          T* __restrict__ Linv, int32_t* __restrict__ info) {
   __shared__ T Tl[NB][NB + 1];
-  __shared__ T X[NB][NB + 1];
+  __shared__ T colbuf[2][NB];
+  __shared__ T rowbuf[2][NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
   if (threadIdx.x == 0) *info = 0;
   for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
@@ -120,12 +177,8 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
     Tl[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
   }
   __syncthreads();
-  tile_factor_inverse<T>(Tl, X, kb, 0, info);
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    int r = idx / NB, c = idx % NB;
-    Linv[idx] = X[r][c];
-    if (r < kb && c < kb) L[r * n + c] = c <= r ? Tl[r][c] : T(0);
-  }
+  tile_factor_inverse<T>(Tl, Linv, kb, 0, info, colbuf, rowbuf);
+  (void)L;
 }
 
 // P = Araw Linv^T into LDS (rows beyond the matrix are zero)
@@ -230,15 +283,10 @@ __global__ void __launch_bounds__(256) chol_step_kernel(T* __restrict__ A, int64
     }
   __syncthreads();
   if (!last) return;
-  // factor the next diagonal tile and store it with its inverse
-  tile_factor_inverse<T>(Wk, Pj, kb, i0, info);
-  T* Lnext = Linv + (k + 1) * NB * NB;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    int r = idx / NB, c = idx % NB;
-    Lnext[idx] = Pj[r][c];
-    int64_t gr = i0 + r, gc = i0 + c;
-    if (gr < n && gc < n) L[gr * n + gc] = c <= r ? Wk[r][c] : T(0);
-  }
+  // factor the next diagonal tile and store the inverse of its factor
+  T (*colbuf)[NB] = reinterpret_cast<T (*)[NB]>(&Pi[0][0]);
+  T (*rowbuf)[NB] = reinterpret_cast<T (*)[NB]>(&Pj[0][0]);
+  tile_factor_inverse<T>(Wk, Linv + (k + 1) * NB * NB, kb, i0, info, colbuf, rowbuf);
 }
 
 template <typename T>
@@ -261,6 +309,7 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
                                                           int64_t n, T* __restrict__ b, int nrhs) {
   __shared__ T t[NB][4];
   __shared__ T red[16][NB][4];
+  __shared__ T Ls[NB][NB + 1];
   const int lane = threadIdx.x % PDIPC_WAVE, wave = threadIdx.x / PDIPC_WAVE;
   const int64_t nblk = (n + NB - 1) / NB;
   // forward: L y = b
@@ -285,12 +334,12 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
       if (lane == 0)
         for (int q = 0; q < 4; ++q) t[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] - s[q] : T(0);
     }
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Ls[idx / NB][idx % NB] = Linv[bk * NB * NB + idx];
     __syncthreads();
-    const T* Lk = Linv + bk * NB * NB;
     if (threadIdx.x < NB * 4) {
       const int r = threadIdx.x / 4, q = threadIdx.x % 4;
       T acc = T(0);
-      for (int c = 0; c <= r; ++c) acc += Lk[r * NB + c] * t[c][q];
+      for (int c = 0; c <= r; ++c) acc += Ls[r][c] * t[c][q];
       if (r < kb && q < nrhs) b[(k0 + r) * nrhs + q] = acc;
     }
     __syncthreads();
@@ -315,12 +364,12 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
       for (int w = 0; w < 16; ++w) acc += red[w][c][q];
       t[c][q] = (c < kb && q < nrhs) ? b[(k0 + c) * nrhs + q] - acc : T(0);
     }
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Ls[idx / NB][idx % NB] = Linv[bk * NB * NB + idx];
     __syncthreads();
-    const T* Lk = Linv + bk * NB * NB;
     if (threadIdx.x < NB * 4) {
       const int c = threadIdx.x / 4, q = threadIdx.x % 4;
       T acc = T(0);
-      for (int r = c; r < NB; ++r) acc += Lk[r * NB + c] * t[r][q];
+      for (int r = c; r < NB; ++r) acc += Ls[r][c] * t[r][q];
       if (c < kb && q < nrhs) b[(k0 + c) * nrhs + q] = acc;
     }
     __syncthreads();
@@ -333,86 +382,92 @@ void dense_chol_solve(const T* L, const T* Linv, int64_t n, T* b, int32_t nrhs, 
   chol_solve_kernel<T><<<1, 1024, 0, st>>>(L, Linv, n, b, nrhs);
 }
 
-// ---- Y = L^-1 by block columns: Y_jj = Linv_j, Y_ij = -Linv_i sum_{j<=p<i} L_ip Y_pj --
+// ---- Y = L^-1 by block diagonals ------------------------------------------------
+// Y_ii = Linv_i; for i - j = d >= 1: Y_ij = -Linv_i sum_{j <= p < i} L_ip Y_pj.
+// Launch d computes every block of diagonal d (one workgroup each) from the
+// diagonals already done; the strict upper blocks are zeroed by launch 0.
 template <typename T>
-__global__ void __launch_bounds__(256) lower_inverse_kernel(const T* __restrict__ L, const T* __restrict__ Linv,
-                                                            int64_t n, T* __restrict__ Y) {
+__global__ void __launch_bounds__(256) inv_diag_kernel(const T* __restrict__ L, const T* __restrict__ Linv, int64_t n,
+                                                       int64_t dd, T* __restrict__ Y) {
   extern __shared__ unsigned char smem_raw[];
   T (*Lt)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);
   T (*Yp)[NB + 1] = Lt + NB;
   T (*Acc)[NB + 1] = Yp + NB;
-  const int64_t bj = blockIdx.x;
-  const int64_t j0 = bj * NB;
-  const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
   const int64_t nblk = (n + NB - 1) / NB;
+  const int64_t bj = blockIdx.x, bi = bj + dd;
+  const int64_t i0 = bi * NB, j0 = bj * NB;
+  const int ib = static_cast<int>(n - i0 < NB ? n - i0 : NB);
+  const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int64_t idx = threadIdx.x; idx < j0 * jb; idx += blockDim.x) Y[(idx / jb) * n + j0 + idx % jb] = T(0);
-  for (int64_t bi = bj; bi < nblk; ++bi) {
-    const int64_t i0 = bi * NB;
-    const int ib = static_cast<int>(n - i0 < NB ? n - i0 : NB);
-    T acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-    for (int64_t bp = bj; bp < bi; ++bp) {
-      const int64_t p0 = bp * NB;
-      for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-        int r = idx / NB, c = idx % NB;
-        Lt[r][c] = (r < ib && p0 + c < n) ? L[(i0 + r) * n + p0 + c] : T(0);
-        Yp[r][c] = (p0 + r < n && c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
-      }
-      __syncthreads();
-      for (int p = 0; p < NB; ++p) {
-        T x[4], y[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          x[q] = Lt[ty + 16 * q][p];
-          y[q] = Yp[p][tx + 16 * q];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
-      }
-      __syncthreads();
+  if (dd == 0) {
+    // diagonal block and the zero block-row above it
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      int r = idx / NB, c = idx % NB;
+      if (r < ib && c < ib) Y[(i0 + r) * n + i0 + c] = Linv[bi * NB * NB + idx];
     }
-    // Acc = (i == j ? I : -acc), then Y_ij = Linv_i Acc
+    for (int64_t bq = bi + 1; bq < nblk; ++bq) {
+      const int64_t q0 = bq * NB;
+      const int qb = static_cast<int>(n - q0 < NB ? n - q0 : NB);
+      for (int idx = threadIdx.x; idx < ib * qb; idx += blockDim.x) Y[(i0 + idx / qb) * n + q0 + idx % qb] = T(0);
+    }
+    return;
+  }
+  T acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int r = ty + 16 * a, c = tx + 16 * b;
-        Acc[r][c] = (bi == bj) ? ((r == c) ? T(1) : T(0)) : -acc[a][b];
-      }
-    const T* Li = Linv + bi * NB * NB;
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Lt[idx / NB][idx % NB] = Li[idx];
+    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+  for (int64_t bp = bj; bp < bi; ++bp) {
+    const int64_t p0 = bp * NB;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      int r = idx / NB, c = idx % NB;
+      Lt[r][c] = (r < ib && p0 + c < n) ? L[(i0 + r) * n + p0 + c] : T(0);
+      Yp[r][c] = (p0 + r < n && c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
+    }
     __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
     for (int p = 0; p < NB; ++p) {
       T x[4], y[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         x[q] = Lt[ty + 16 * q][p];
-        y[q] = Acc[p][tx + 16 * q];
+        y[q] = Yp[p][tx + 16 * q];
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
     }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Acc[ty + 16 * a][tx + 16 * b] = -acc[a][b];
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Lt[idx / NB][idx % NB] = Linv[bi * NB * NB + idx];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+  for (int p = 0; p < NB; ++p) {
+    T x[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[q] = Lt[ty + 16 * q][p];
+      y[q] = Acc[p][tx + 16 * q];
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int r = ty + 16 * a, c = tx + 16 * b;
-        if (r < ib && c < jb) Y[(i0 + r) * n + j0 + c] = acc[a][b];
-      }
-    __syncthreads();
+      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int r = ty + 16 * a, c = tx + 16 * b;
+      if (r < ib && c < jb) Y[(i0 + r) * n + j0 + c] = acc[a][b];
+    }
 }
 
 template <typename T>
@@ -420,7 +475,8 @@ void dense_chol_inverse(const T* L, const T* Linv, int64_t n, T* Ainv, T* work, 
   if (n <= 0) return;
   const unsigned nblk = grid_for(n, NB);
   const size_t shm = sizeof(T) * 3 * NB * (NB + 1);
-  lower_inverse_kernel<T><<<nblk, 256, shm, st>>>(L, Linv, n, work);
+  for (unsigned dd = 0; dd < nblk; ++dd)
+    inv_diag_kernel<T><<<nblk - dd, 256, shm, st>>>(L, Linv, n, dd, work);
   dim3 grid(nblk, nblk);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
 }
@@ -454,6 +510,43 @@ __global__ void __launch_bounds__(256) dense_residual_kernel(const double* __res
 }
 void launch_dense_residual(const double* M, int64_t n, const double* b, const double* u, double* r, hipStream_t st) {
   if (n > 0) dense_residual_kernel<<<grid_for(n, 4), 256, 0, st>>>(M, n, b, u, r);
+}
+
+// ---- Jacobi-scaled FP32 copies for mixed-precision refinement --------------------
+__global__ void diag_scale_kernel(const double* __restrict__ M, int64_t n, double* __restrict__ sc) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double d = M[i * n + i];
+    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+  }
+}
+__global__ void scale_convert_matrix_kernel(const double* __restrict__ M, int64_t n, const double* __restrict__ sc,
+                                            float* __restrict__ out) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < n * n) out[idx] = static_cast<float>(sc[idx / n] * M[idx] * sc[idx % n]);
+}
+__global__ void scale_convert_vec_kernel(const double* __restrict__ r, int64_t n, const double* __restrict__ sc,
+                                         float* __restrict__ out) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = static_cast<float>(sc[i] * r[i]);
+}
+__global__ void scaled_accumulate_kernel(const float* __restrict__ y, int64_t n, const double* __restrict__ sc,
+                                         double* __restrict__ u) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) u[i] += sc[i] * static_cast<double>(y[i]);
+}
+
+void launch_jacobi_scaling(const double* M, int64_t n, double* sc, hipStream_t st) {
+  if (n > 0) diag_scale_kernel<<<grid_for(n, 256), 256, 0, st>>>(M, n, sc);
+}
+void launch_scale_convert_matrix(const double* M, int64_t n, const double* sc, float* out, hipStream_t st) {
+  if (n > 0) scale_convert_matrix_kernel<<<grid_for(n * n, 256), 256, 0, st>>>(M, n, sc, out);
+}
+void launch_scale_convert_vec(const double* r, int64_t n, const double* sc, float* out, hipStream_t st) {
+  if (n > 0) scale_convert_vec_kernel<<<grid_for(n, 256), 256, 0, st>>>(r, n, sc, out);
+}
+void launch_scaled_accumulate(const float* y, int64_t n, const double* sc, double* u, hipStream_t st) {
+  if (n > 0) scaled_accumulate_kernel<<<grid_for(n, 256), 256, 0, st>>>(y, n, sc, u);
 }
 
 template void dense_cholesky<double>(double*, int64_t, double*, double*, int32_t*, hipStream_t);

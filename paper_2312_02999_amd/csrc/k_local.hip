@@ -102,6 +102,52 @@ __device__ void nearest_rotation(const M3<T>& M, M3<T>& R) {
     for (int c = 0; c < 3; ++c) R(r, c) = u1[r] * v1[c] + u2[r] * v2[c] + u3[r] * v3[c];
 }
 
+// One FP64 Newton step on SO(3) toward the rotation maximising tr(R^T M):
+// with S0 = R0^T M, the optimum R0 Q has Q^T S0 symmetric; to first order
+// Q = exp([w]_x) with (tr(Sym) I - Sym) w = a(S0), Sym = sym(S0),
+// a(X) = (X32 - X23, X13 - X31, X21 - X12).  Convergence is quadratic, so an
+// FP32 rotation becomes FP64-accurate in one step.
+__device__ void refine_rotation(const M3<double>& M, M3<double>& R) {
+  M3<double> Rt;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Rt(r, c) = R(c, r);
+  M3<double> S = mul(Rt, M);
+  double av[3] = {S(2, 1) - S(1, 2), S(0, 2) - S(2, 0), S(1, 0) - S(0, 1)};
+  double s01 = 0.5 * (S(0, 1) + S(1, 0)), s02 = 0.5 * (S(0, 2) + S(2, 0)), s12 = 0.5 * (S(1, 2) + S(2, 1));
+  double tr = S(0, 0) + S(1, 1) + S(2, 2);
+  double b00 = tr - S(0, 0), b11 = tr - S(1, 1), b22 = tr - S(2, 2);
+  double b01 = -s01, b02 = -s02, b12 = -s12;
+  double c00 = b11 * b22 - b12 * b12, c01 = b02 * b12 - b01 * b22, c02 = b01 * b12 - b02 * b11;
+  double c11 = b00 * b22 - b02 * b02, c12 = b01 * b02 - b00 * b12, c22 = b00 * b11 - b01 * b01;
+  double det = b00 * c00 + b01 * c01 + b02 * c02;
+  if (!(fabs(det) > 0.0)) return;
+  double w[3] = {(c00 * av[0] + c01 * av[1] + c02 * av[2]) / det, (c01 * av[0] + c11 * av[1] + c12 * av[2]) / det,
+                 (c02 * av[0] + c12 * av[1] + c22 * av[2]) / det};
+  // Q = exp([w]_x) by Rodrigues' formula (exactly orthogonal in exact arithmetic)
+  double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  double th = sqrt(th2);
+  double A1, B1;
+  if (th < 1e-4) {
+    A1 = 1.0 - th2 / 6.0;
+    B1 = 0.5 - th2 / 24.0;
+  } else {
+    A1 = sin(th) / th;
+    B1 = (1.0 - cos(th)) / th2;
+  }
+  M3<double> K, K2, Q;
+  K(0, 0) = 0.0; K(0, 1) = -w[2]; K(0, 2) = w[1];
+  K(1, 0) = w[2]; K(1, 1) = 0.0; K(1, 2) = -w[0];
+  K(2, 0) = -w[1]; K(2, 1) = w[0]; K(2, 2) = 0.0;
+  K2 = mul(K, K);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Q(r, c) = (r == c ? 1.0 : 0.0) + A1 * K(r, c) + B1 * K2(r, c);
+  R = mul(R, Q);
+}
+
 struct TetStreams {
   const int32_t* tets;   // 4 x m
   const double* B;       // 9 x m, D_m^-1 row-major entries
@@ -153,6 +199,7 @@ __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t 
   M3<double> R;
 #pragma unroll
   for (int e = 0; e < 9; ++e) R.a[e] = static_cast<double>(Rt.a[e]);
+  if (sizeof(TP) < sizeof(double)) refine_rotation(M, R);
   M3<double> P = mul(R, A);
   double res[9];
   double e2 = 0.0;
@@ -223,6 +270,7 @@ __global__ void __launch_bounds__(256) trial_energy_kernel(TetStreams ts, int64_
   M3<double> R;
 #pragma unroll
   for (int e = 0; e < 9; ++e) R.a[e] = static_cast<double>(Rt.a[e]);
+  if (sizeof(TP) < sizeof(double)) refine_rotation(M, R);
   M3<double> P = mul(R, A);
   double e2 = 0.0;
 #pragma unroll

@@ -66,7 +66,9 @@ struct BroadPhaseBuffers {
   int32_t* e_id;
   uint64_t* e_key;
   int64_t ent_cap;      // capacity of each entry array
-  int32_t* q_count;     // nsv + nse + 1 per-query counts / offsets
+  int32_t* q_count;     // 27 (nsv + nse) + 1 per-(query, cell slot) counts / offsets
+  int32_t* tmpj;        // unsorted partner ids
+  int64_t tmp_cap;
   int32_t* d_totals;    // [0] pairs total
   void* scan_temp;
   void* red_temp;
@@ -122,7 +124,8 @@ struct Incidence {
   int32_t* cnt;         // n + 1
   int32_t* ptr;         // n + 1
   int32_t* cursor;      // n
-  int32_t* ent;         // 4 * cap pairs
+  int32_t* raw;         // 4 * cap pairs, unsorted fill
+  int32_t* ent;         // 4 * cap pairs, sorted per vertex
   int32_t* cflag;       // n + 1: 1 if free and touched
   int32_t* cidx;        // n + 1: exclusive scan of cflag (c index if flagged)
   int32_t* clist;       // n: c index -> sim vertex
@@ -205,7 +208,28 @@ template <typename T>
 void dense_chol_inverse(const T* L, const T* Linv, int64_t n, T* Ainv, T* work, hipStream_t st);
 void launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t st);
+// Jacobi scaling sc_i = 1/sqrt(M_ii); FP32 copies of S M S and S r; u += S y
+void launch_jacobi_scaling(const double* M, int64_t n, double* sc, hipStream_t st);
+void launch_scale_convert_matrix(const double* M, int64_t n, const double* sc, float* out, hipStream_t st);
+void launch_scale_convert_vec(const double* r, int64_t n, const double* sc, float* out, hipStream_t st);
+void launch_scaled_accumulate(const float* y, int64_t n, const double* sc, double* u, hipStream_t st);
 // r = b - M u  (dense, n x n row-major FP64), all vectors n
 void launch_dense_residual(const double* M, int64_t n, const double* b, const double* u, double* r, hipStream_t st);
+
+// ------------------------------------------------------------------ adjoint
+// out = K v on the free DOFs (true energy Hessian: PD term with the rotation
+// derivative + unprojected barrier Hessian); tetg: 12 x m scratch, pairbuf:
+// 12 x npairs scratch.
+void launch_hessvec(const LocalArgs& la, int32_t n, const int32_t* vt_ptr, const int32_t* vt_ent,
+                    const uint8_t* fixed, const double* x, const double* Rrot, const double* v, double* tetg,
+                    const PairList& pl, int32_t npairs, int32_t n_pt, const Incidence& inc, const ProxyDev& px,
+                    double dhat, double kappa, double* pairbuf, double* out, hipStream_t st);
+// dL/da per tet from the adjoint state lambda (n x 3)
+void launch_actuation_grad(const LocalArgs& la, const double* x, const double* Rrot, const double* R0,
+                           const double* lam, double* out, hipStream_t st);
+void launch_masked_mul(int64_t n, const double* a, const double* b, const uint8_t* fixed, double* out,
+                       hipStream_t st);
+// y = alpha x + beta y
+void launch_axpby(int64_t n3, double alpha, const double* x, double beta, double* y, hipStream_t st);
 
 }  // namespace pdipc

@@ -26,7 +26,7 @@
 
 namespace pdipc {
 
-static std::string g_last_init_error;
+static thread_local std::string g_last_init_error;
 
 #define HIPCHK(expr)                                                   \
   do {                                                                 \
@@ -45,13 +45,21 @@ struct SolverError {
   std::string msg;
 };
 
+// device bytes held by all DBufs of the calling thread's current solver
+static thread_local int64_t* g_bytes_counter = nullptr;
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   int64_t cap = 0;
+  int64_t* counter = nullptr;
   void ensure(int64_t count) {
     if (count <= cap) return;
-    if (p) HIPCHK(hipFree(p));
+    if (!counter) counter = g_bytes_counter;
+    if (p) {
+      HIPCHK(hipFree(p));
+      if (counter) *counter -= static_cast<int64_t>(sizeof(T)) * cap;
+    }
     p = nullptr;
     int64_t c = std::max<int64_t>(count, 1);
     if (hipMalloc(&p, sizeof(T) * c) != hipSuccess) {
@@ -60,20 +68,31 @@ struct DBuf {
       throw SolverError{PDIPC_E_NOMEM, "device allocation failed"};
     }
     cap = c;
+    if (counter) *counter += static_cast<int64_t>(sizeof(T)) * c;
   }
   void upload(const T* h, int64_t count, hipStream_t st) {
     ensure(count);
     if (count > 0) HIPCHK(hipMemcpyAsync(p, h, sizeof(T) * count, hipMemcpyHostToDevice, st));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      if (counter) *counter -= static_cast<int64_t>(sizeof(T)) * cap;
+    }
     p = nullptr;
     cap = 0;
   }
 };
 
+struct BytesScope {
+  int64_t* prev;
+  explicit BytesScope(int64_t* c) : prev(g_bytes_counter) { g_bytes_counter = c; }
+  ~BytesScope() { g_bytes_counter = prev; }
+};
+
 struct Solver {
   std::string err;
+  int64_t device_bytes = 0;
   pdipc_options opt{};
   hipStream_t st = nullptr;
   int32_t n = 0, m = 0, nsv = 0, nst = 0, nse = 0, n1 = 0, n2 = 0;
@@ -97,25 +116,27 @@ struct Solver {
   ProxyDev px{};
   BroadPhaseBuffers bb{};
   DBuf<double> vbox, tbox, ebox, params;
-  DBuf<int32_t> t_count, t_cursor, t_id, e_count, e_cursor, e_id, q_count, totals;
+  DBuf<int32_t> t_count, t_cursor, t_id, e_count, e_cursor, e_id, q_count, totals, tmpj;
   DBuf<uint64_t> t_key, e_key;
   DBuf<char> scan_tmp, red_tmp;
   DBuf<int32_t> act_type, act_i, act_j, act_v4, cand_type, cand_i, cand_j, cand_v4;
   PairList act{}, cand{};
   DBuf<double> b_energy, b_grad, b_U;
   BarrierOut bo{};
-  DBuf<int32_t> inc_cnt, inc_ptr, inc_cursor, inc_ent, inc_cflag, inc_cidx, inc_clist, inc_nc;
+  DBuf<int32_t> inc_cnt, inc_ptr, inc_cursor, inc_ent, inc_raw, inc_cflag, inc_cidx, inc_clist, inc_nc;
   Incidence inc{};
   // reduced system
   DBuf<int32_t> c_x2, info;
-  DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid, CsL, CsLi, ML, MLi;
+  DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid, CsL, CsLi, ML, MLi, scl;
+  int32_t refine_steps = 0, refine_fallbacks = 0;
   DBuf<float> Mf, uf, MLf, MLif;
   // swept candidates of the last step (x_prev -> x_prev + dx), valid for x on that path
   bool cand_valid = false;
   int32_t cand_n = 0, cand_pt = 0;
   DBuf<int32_t> cflagbuf, cposbuf;
-  // last converged state for the adjoint
-  int32_t last_npairs = 0, last_npt = 0;
+  // adjoint work vectors
+  DBuf<double> lam, res, zvec, pvec, kp, prod, pairbuf;
+  int32_t adjoint_iters = 0;
 
   // host helpers
   double* h_scal = nullptr;   // pinned readback
@@ -491,9 +512,10 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   const int64_t ent = 27LL * std::max(S->nst, S->nse) + 64;
   for (auto* b : {&S->t_count, &S->t_cursor, &S->e_count, &S->e_cursor}) b->ensure(T + 1);
   S->t_id.ensure(ent); S->e_id.ensure(ent); S->t_key.ensure(ent); S->e_key.ensure(ent);
-  S->q_count.ensure(static_cast<int64_t>(S->nsv) + S->nse + 1);
+  S->q_count.ensure(27LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1);
   S->totals.ensure(8);
-  const int64_t scan_n = std::max<int64_t>({T + 1, static_cast<int64_t>(S->nsv) + S->nse + 1, static_cast<int64_t>(n) + 1});
+  const int64_t scan_n = std::max<int64_t>({T + 1, 27LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1,
+                                            static_cast<int64_t>(n) + 1});
   S->scan_tmp.ensure(static_cast<int64_t>(scan_temp_bytes(scan_n)));
   S->red_tmp.ensure(static_cast<int64_t>(sum_temp_bytes(0)) + 4096);
   BroadPhaseBuffers& bb = S->bb;
@@ -502,6 +524,9 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   bb.t_count = S->t_count.p; bb.t_cursor = S->t_cursor.p; bb.t_id = S->t_id.p; bb.t_key = S->t_key.p;
   bb.e_count = S->e_count.p; bb.e_cursor = S->e_cursor.p; bb.e_id = S->e_id.p; bb.e_key = S->e_key.p;
   bb.ent_cap = ent; bb.q_count = S->q_count.p; bb.d_totals = S->totals.p;
+  S->tmpj.ensure(4LL * S->nsv + 1024);
+  bb.tmpj = S->tmpj.p;
+  bb.tmp_cap = S->tmpj.cap;
   bb.scan_temp = S->scan_tmp.p; bb.red_temp = S->red_tmp.p;
   for (auto* b : {&S->inc_cnt, &S->inc_ptr, &S->inc_cflag, &S->inc_cidx}) b->ensure(n + 1);
   S->inc_cursor.ensure(n);
@@ -531,7 +556,12 @@ static void pairs(Solver* S, bool active, const double* xx, const double* dxx, i
     int rc = find_pairs(S->px, S->bb, xx, dxx, S->opt.dhat, active, pl, npt, nee, S->st, &need);
     if (rc == 0) return;
     if (rc < 0) fail(PDIPC_E_HIP, "broad phase overflow");
-    grow_pairs(S, pl, ty, ii, jj, v4, need);
+    if (need > pl.cap) grow_pairs(S, pl, ty, ii, jj, v4, need);
+    if (need > S->bb.tmp_cap) {
+      S->tmpj.ensure(need + need / 2 + 256);
+      S->bb.tmpj = S->tmpj.p;
+      S->bb.tmp_cap = S->tmpj.cap;
+    }
   }
   fail(PDIPC_E_NOMEM, "pair list growth failed");
 }
@@ -560,11 +590,12 @@ static void ensure_pair_arrays(Solver* S, int64_t np) {
   if (S->b_energy.cap < cap) {
     int64_t c = cap + cap / 2 + 256;
     S->b_energy.ensure(c); S->b_grad.ensure(12 * c); S->b_U.ensure(60 * c); S->inc_ent.ensure(4 * c);
+    S->inc_raw.ensure(4 * c);
     S->wtmp.ensure(5 * c);
   }
   S->bo = BarrierOut{S->b_energy.p, S->b_grad.p, S->b_U.p};
-  S->inc = Incidence{S->inc_cnt.p, S->inc_ptr.p, S->inc_cursor.p, S->inc_ent.p, S->inc_cflag.p, S->inc_cidx.p,
-                     S->inc_clist.p, S->inc_nc.p};
+  S->inc = Incidence{S->inc_cnt.p, S->inc_ptr.p, S->inc_cursor.p, S->inc_raw.p, S->inc_ent.p, S->inc_cflag.p,
+                     S->inc_cidx.p, S->inc_clist.p, S->inc_nc.p};
 }
 
 static LocalArgs local_args(Solver* S) { return LocalArgs{S->m, S->tets.p, S->Bm.p, S->w.p, S->A.p}; }
@@ -652,26 +683,37 @@ static void global_step(Solver* S, const IterOut& io) {
     dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, st);
     launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
+    bool solved = false;
     if (S->opt.precision == PDIPC_MIXED_FP32) {
-      // FP32 factor of the reduced system, refined against FP64 residuals
+      // Jacobi-scaled FP32 factor, refined against FP64 residuals of the
+      // unscaled system; falls back to FP64 if refinement cannot converge.
       S->Mf.ensure(N3 * N3);
       S->MLf.ensure(N3 * N3);
       S->MLif.ensure(dense_linv_size(N3));
       S->uf.ensure(N3);
       S->resid.ensure(N3);
-      launch_convert_f64_f32(S->Mred.p, S->Mf.p, N3 * N3, st);
+      S->scl.ensure(N3);
+      launch_jacobi_scaling(S->Mred.p, N3, S->scl.p, st);
+      launch_scale_convert_matrix(S->Mred.p, N3, S->scl.p, S->Mf.p, st);
       dense_cholesky<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, st);
-      if (read_scalar_i(S, S->info.p + 1) != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD (FP32)");
-      launch_fill_f64(S->u.p, N3, 0.0, st);
-      HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
-      for (int it = 0; it < 4; ++it) {
-        launch_convert_f64_f32(S->resid.p, S->uf.p, N3, st);
-        dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
-        launch_convert_f32_f64(S->uf.p, S->vvec.p, N3, st);
-        launch_axpy_positions(N3, 1.0, S->vvec.p, S->u.p, st);
-        launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
+      if (read_scalar_i(S, S->info.p + 1) == 0) {
+        launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
+        const double bnorm = read_scalar_d(S, S->scal.p + 5);
+        launch_fill_f64(S->u.p, N3, 0.0, st);
+        HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
+        for (int it = 0; it < 10 && !solved; ++it) {
+          launch_scale_convert_vec(S->resid.p, N3, S->scl.p, S->uf.p, st);
+          dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
+          launch_scaled_accumulate(S->uf.p, N3, S->scl.p, S->u.p, st);
+          launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
+          launch_max_abs(S->resid.p, N3, S->scal.p + 6, S->red_tmp.p, st);
+          S->refine_steps++;
+          if (read_scalar_d(S, S->scal.p + 6) <= 1e-13 * bnorm) solved = true;
+        }
       }
-    } else {
+      if (!solved) S->refine_fallbacks++;
+    }
+    if (!solved) {
       {
         ScopedTimer tm(S, TK_REDUCED_CHOL);
         dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, st);
@@ -749,6 +791,8 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   int32_t rc = PDIPC_OK;
   const bool tol_mode = S->opt.tol > 0;
   double tms[5] = {0, 0, 0, 0, 0};
+  S->refine_steps = 0;
+  S->refine_fallbacks = 0;
   int it = 0;
   for (; it < S->opt.iters; ++it) {
     IterOut io;
@@ -783,6 +827,8 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
     }
   }
   fs.iters = it;
+  fs.refine_steps = S->refine_steps;
+  fs.refine_fallbacks = S->refine_fallbacks;
   if (tol_mode && it >= S->opt.iters && rc == PDIPC_OK) rc = PDIPC_W_NOT_CONVERGED;
   HIPCHK(hipMemcpyAsync(x_out, S->x.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -799,12 +845,81 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   return rc;
 }
 
+// Adjoint of the last frame: K lambda = dL/dx by conjugate gradients
+// preconditioned with the forward global step (H + projected barrier Hessian,
+// Eq. 7 and 11), then dL/da from lambda.
+static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
+  if (!S->have_solution) fail(PDIPC_E_INVALID, "no converged frame to differentiate");
+  if (!S->have_scalar) fail(PDIPC_E_INVALID, "the actuation was not set through pdipc_set_actuation_scalar");
+  hipStream_t st = S->st;
+  const int64_t n3 = 3LL * S->n;
+  IterOut io;
+  S->cand_valid = false;
+  assemble_gradient(S, true, io);                   // rotations, pairs, barrier factors at x*
+  const int32_t np = io.npt + io.nee;
+  S->lam.ensure(n3); S->res.ensure(n3); S->zvec.ensure(n3); S->pvec.ensure(n3); S->kp.ensure(n3);
+  S->prod.ensure(n3);
+  S->pairbuf.ensure(12LL * std::max(np, 1));
+  launch_fill_f64(S->lam.p, n3, 0.0, st);
+  launch_masked_mul(S->n, dLdx, dLdx, S->fixed.p, S->prod.p, st);   // |b|^2
+  launch_sum(S->prod.p, n3, S->scal.p + 3, S->red_tmp.p, st);
+  const double bn = std::sqrt(read_scalar_d(S, S->scal.p + 3));
+  if (bn == 0.0) {
+    launch_fill_f64(dLda, S->m, 0.0, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return PDIPC_OK;
+  }
+  // r = b (free DOFs only)
+  HIPCHK(hipMemcpyAsync(S->res.p, dLdx, sizeof(double) * n3, hipMemcpyDeviceToDevice, st));
+  launch_masked_mul(S->n, S->res.p, S->res.p, S->fixed.p, S->prod.p, st);
+  auto precond = [&](const double* r, double* z) {
+    launch_axpby(n3, -1.0, r, 0.0, S->g.p, st);     // g = -r  =>  dx = Hhat^-1 r
+    global_step(S, io);
+    HIPCHK(hipMemcpyAsync(z, S->dx.p, sizeof(double) * n3, hipMemcpyDeviceToDevice, st));
+  };
+  auto dot = [&](const double* a, const double* b) {
+    launch_masked_mul(S->n, a, b, S->fixed.p, S->prod.p, st);
+    launch_sum(S->prod.p, n3, S->scal.p + 4, S->red_tmp.p, st);
+    return read_scalar_d(S, S->scal.p + 4);
+  };
+  auto kvec = [&](const double* v, double* out) {
+    launch_hessvec(local_args(S), S->n, S->vt_ptr.p, S->vt_ent.p, S->fixed.p, S->x.p, S->Rtet.p, v, S->tetg.p,
+                   S->act, np, io.npt, S->inc, S->px, S->opt.dhat, S->opt.kappa, S->pairbuf.p, out, st);
+  };
+  precond(S->res.p, S->zvec.p);
+  HIPCHK(hipMemcpyAsync(S->pvec.p, S->zvec.p, sizeof(double) * n3, hipMemcpyDeviceToDevice, st));
+  double rz = dot(S->res.p, S->zvec.p);
+  int it = 0;
+  const int max_it = 500;
+  const double tol = 1e-12;
+  for (; it < max_it; ++it) {
+    kvec(S->pvec.p, S->kp.p);
+    const double pkp = dot(S->pvec.p, S->kp.p);
+    if (!(pkp > 0.0)) fail(PDIPC_E_NOT_SPD, "energy Hessian is not positive definite at the frame's state");
+    const double alpha = rz / pkp;
+    launch_axpby(n3, alpha, S->pvec.p, 1.0, S->lam.p, st);
+    launch_axpby(n3, -alpha, S->kp.p, 1.0, S->res.p, st);
+    const double rn = std::sqrt(dot(S->res.p, S->res.p));
+    if (rn <= tol * bn) { ++it; break; }
+    precond(S->res.p, S->zvec.p);
+    const double rz2 = dot(S->res.p, S->zvec.p);
+    launch_axpby(n3, 1.0, S->zvec.p, rz2 / rz, S->pvec.p, st);
+    rz = rz2;
+  }
+  S->adjoint_iters = it;
+  launch_actuation_grad(local_args(S), S->x.p, S->Rtet.p, S->R0.p, S->lam.p, dLda, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return it >= max_it ? PDIPC_W_NOT_CONVERGED : PDIPC_OK;
+}
+
 }  // namespace pdipc
 
 using namespace pdipc;
 
 template <typename F>
 static int32_t guarded(Solver* S, F&& fn) {
+  BytesScope scope(S ? &S->device_bytes : nullptr);
   try {
     return fn();
   } catch (const SolverError& e) {
@@ -893,8 +1008,14 @@ int32_t pdipc_solve_frame(void* h, const double* x_in, double* x_out, pdipc_fram
 int32_t pdipc_solve_frame_backward(void* h, const double* dL_dx, double* dL_da) {
   Solver* S = static_cast<Solver*>(h);
   if (!S || !dL_dx || !dL_da) return PDIPC_E_INVALID;
-  S->err = "backward pass not available in this build";
-  return PDIPC_E_INVALID;
+  return guarded(S, [&] { return do_backward(S, dL_dx, dL_da); });
+}
+
+int32_t pdipc_device_bytes(const void* h, int64_t* bytes) {
+  const Solver* S = static_cast<const Solver*>(h);
+  if (!S || !bytes) return PDIPC_E_INVALID;
+  *bytes = S->device_bytes;
+  return PDIPC_OK;
 }
 
 int32_t pdipc_get_sizes(const void* h, int64_t* n1, int64_t* n2, int64_t* nnz) {
@@ -912,9 +1033,9 @@ void pdipc_destroy(void* h) {
   if (S->st) (void)hipStreamSynchronize(S->st);
   DBuf<int32_t>* bi[] = {&S->tets, &S->vt_ptr, &S->vt_ent, &S->sv, &S->stri, &S->sedge, &S->node_c0, &S->node_s,
                          &S->node_r, &S->level_nodes, &S->frows, &S->fcol, &S->ext2vert, &S->vert2x2, &S->lvl_rows, &S->lvl_row_node, &S->t_count,
-                         &S->t_cursor, &S->t_id, &S->e_count, &S->e_cursor, &S->e_id, &S->q_count, &S->totals,
+                         &S->t_cursor, &S->t_id, &S->e_count, &S->e_cursor, &S->e_id, &S->q_count, &S->totals, &S->tmpj,
                          &S->act_type, &S->act_i, &S->act_j, &S->act_v4, &S->cand_type, &S->cand_i, &S->cand_j,
-                         &S->cand_v4, &S->inc_cnt, &S->inc_ptr, &S->inc_cursor, &S->inc_ent, &S->inc_cflag,
+                         &S->cand_v4, &S->inc_cnt, &S->inc_ptr, &S->inc_cursor, &S->inc_ent, &S->inc_raw, &S->inc_cflag,
                          &S->inc_cidx, &S->inc_clist, &S->inc_nc, &S->c_x2, &S->info, &S->cflagbuf, &S->cposbuf};
   for (auto* b : bi) b->release();
   DBuf<double>* bd[] = {&S->Bm, &S->w, &S->A, &S->a_s, &S->R0, &S->X, &S->x, &S->g, &S->dx, &S->tetg, &S->E0,
@@ -927,7 +1048,9 @@ void pdipc_destroy(void* h) {
   S->node_roff.release(); S->node_poff.release(); S->node_doff.release(); S->fptr.release();
   S->t_key.release(); S->e_key.release(); S->scan_tmp.release(); S->red_tmp.release();
   S->Mf.release(); S->uf.release(); S->MLf.release(); S->MLif.release();
-  S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release();
+  S->lam.release(); S->res.release(); S->zvec.release(); S->pvec.release(); S->kp.release(); S->prod.release();
+  S->pairbuf.release();
+  S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release(); S->scl.release();
   delete S;
 }
 
