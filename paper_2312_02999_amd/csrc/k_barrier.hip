@@ -454,23 +454,32 @@ __global__ void pair_ut_kernel(int32_t npairs, const int32_t* __restrict__ v4, c
   for (int c = 0; c < 5; ++c) w[static_cast<int64_t>(c) * npairs + k] = acc[c];
 }
 
-__global__ void bu_gather_kernel(int32_t nc, const int32_t* __restrict__ clist, const int32_t* __restrict__ ptr,
-                                 const int32_t* __restrict__ ent, const double* __restrict__ U,
-                                 const double* __restrict__ w, int32_t npairs, double* __restrict__ v) {
-  int32_t ca = blockIdx.x * blockDim.x + threadIdx.x;
+// v_a = sum over incident (pair k, local slot l) of U_{k,l} w_k: one wave per c
+// vertex, lanes over its incidence entries, then a fixed-order wave sum.
+__global__ void __launch_bounds__(256) bu_gather_kernel(int32_t nc, const int32_t* __restrict__ clist,
+                                                        const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
+                                                        const double* __restrict__ U, const double* __restrict__ w,
+                                                        int32_t npairs, double* __restrict__ v) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t ca = static_cast<int64_t>(blockIdx.x) * (256 / PDIPC_WAVE) + threadIdx.x / PDIPC_WAVE;
   if (ca >= nc) return;
-  int32_t va = clist[ca];
+  const int32_t va = clist[ca];
   double s[3] = {0, 0, 0};
-  for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
-    int32_t k = ent[t] >> 2, la = ent[t] & 3;
+  for (int32_t t = ptr[va] + lane; t < ptr[va + 1]; t += PDIPC_WAVE) {
+    const int32_t k = ent[t] >> 2, la = ent[t] & 3;
+    double wk[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) wk[c] = w[static_cast<int64_t>(c) * npairs + k];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 5; ++c)
-        s[r] += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] * w[static_cast<int64_t>(c) * npairs + k];
+      for (int c = 0; c < 5; ++c) s[r] += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] * wk[c];
   }
 #pragma unroll
-  for (int r = 0; r < 3; ++r) v[3 * static_cast<int64_t>(ca) + r] = s[r];
+  for (int r = 0; r < 3; ++r) s[r] = wave_sum(s[r]);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) v[3 * ca + r] = s[r];
 }
 
 void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, int32_t npairs, const BarrierOut& bo,
@@ -478,7 +487,7 @@ void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, i
   (void)fixed;
   if (nc <= 0) return;
   pair_ut_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(npairs, pl.v4, inc.cflag, inc.cidx, bo.U, u, wtmp);
-  bu_gather_kernel<<<grid_for(nc, 256), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, bo.U, wtmp, npairs, v);
+  bu_gather_kernel<<<grid_for(nc, 256 / PDIPC_WAVE), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, bo.U, wtmp, npairs, v);
 }
 
 }  // namespace pdipc

@@ -1,7 +1,8 @@
 // Dense symmetric-positive-definite kernels for the reduced contact system of
 // Eq. (11) and the inverse Schur complement Sigma^-1 (Section 3.2): blocked
-// right-looking Cholesky (64-wide panels), triangular solves, and the inverse
-// through L^-1 and a Gram product.  Row-major, lower triangle.
+// right-looking Cholesky (64-wide blocks, trailing updates on the matrix
+// cores), triangular solves, and the inverse through L^-1 and a Gram product.
+// Row-major, lower triangle.
 #include "common.h"
 #include "kernels.h"
 
@@ -76,271 +77,293 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
 }
 
 // ---- Cholesky -----------------------------------------------------------------
-// Right-looking with 64-wide blocks, one launch per block step.  Step k (k >= 0)
-// handles the trailing lower tiles (i, j), k < j <= i:
-//   P_i = A_ik Linv_k^T          (panel solve via the stored inverse of L_kk)
-//   A_ij -= P_i P_j^T            (trailing update)
-// the diagonal tile (i, i) also writes P_i into L, and tile (k+1, k+1), after
-// its last update, factors itself and stores the inverse of L_{k+1,k+1}.
-// A is the workspace (destroyed); the off-diagonal blocks of L and the
-// diagonal-block inverses are the outputs (the solves never need L_kk).
-// Ragged last blocks are padded with the identity.
+// Right-looking with 64-wide blocks.  Outputs: L (lower, row-major), its
+// transpose Lt (upper, row-major) and the reciprocals of the diagonal, dinv;
+// Lt and dinv share the auxiliary buffer (n*n + n entries).  A is the
+// workspace (its lower tiles are destroyed).  Per block step k:
+//   panel:  L_ik = A_ik L_kk^-T for every block row i > k (one wave per block
+//           row, forward substitution with the row held in registers);
+//   update: A_ij -= L_ik L_jk^T for k < j <= i (matrix cores, one workgroup
+//           per tile); the workgroup of tile (k+1, k+1) then factors it.
+// Diagonal tiles are factored by one wave: lane r keeps row r in registers,
+// step j broadcasts the pivot by readlane and column j through LDS.  Ragged
+// last blocks are padded with the identity.
 
-// Factor the 64x64 tile held in LDS (lower part; rows and columns beyond kb
-// are the identity) and write the inverse of its Cholesky factor to Linv
-// (global, 64 x 64 row-major).  256 threads; thread (ty, tx) keeps rows
-// 4ty..4ty+3 x columns 4tx..4tx+3 of the tile and of the inverse in
-// registers.  Step j broadcasts column j of the tile and row j of the
-// inverse through double-buffered LDS vectors:
-//   L[:, j] = T[:, j] / sqrt(T[j][j]);  T[i][l] -= L[i][j] L[l][j]  (i, l > j)
-//   X[j, :] /= L[j][j];                 X[i, :] -= L[i][j] X[j, :]  (i > j)
-// starting from X = I, which leaves X = L^-1 (forward elimination on I).
 template <typename T>
-__device__ void tile_factor_inverse(const T (*Tl)[NB + 1], T* __restrict__ Linv, int kb, int64_t k0,
-                                    int32_t* info, T (*colbuf)[NB], T (*rowbuf)[NB]) {
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  const int r0 = 4 * ty, c0 = 4 * tx;
-  T tr[4][4], xr[4][4];
+struct MfmaVec;
+template <>
+struct MfmaVec<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct MfmaVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// D (16x16) += A (16x4) B (4x16); lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 (l / 16) + q][l % 16] in element q.
+__device__ __forceinline__ MfmaVec<double>::type mfma16x16x4(double a, double b, MfmaVec<double>::type c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ MfmaVec<float>::type mfma16x16x4(float a, float b, MfmaVec<float>::type c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// 1/sqrt(d) for d > 0: hardware estimate, then Newton steps y <- y (3 - d y^2) / 2
+// (two for FP64, one for FP32; each squares the relative error).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float d) {
+  float y = __builtin_amdgcn_rsqf(d);
+  return y * (1.5f - 0.5f * d * y * y);
+}
+
+// Factor the 64x64 tile W (LDS, row-major, lower part used; rows and columns
+// beyond kb hold the identity) with the first wave of the workgroup; writes
+// rows/columns < kb of L and Lt at offset k0 and dinv.  A non-positive pivot
+// is replaced by 1 so that the factorisation completes, and the first such
+// column (global index + 1) goes to *info unless an earlier tile set it.
+// The unrolled loop is kept free of branches (failure is tracked by selects)
+// so that the row stays in registers; W is overwritten with the factor and
+// copied out afterwards.
+template <typename T>
+__device__ __forceinline__ void factor_diag_wave(T (*W)[NB + 1], int kb, int64_t k0, int64_t n, T* __restrict__ L,
+                                 T* __restrict__ Lt, T* __restrict__ dinv, int32_t* __restrict__ info,
+                                 T* __restrict__ colbuf) {
+  const int lane = threadIdx.x;
+  T a[NB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < NB; ++c) a[c] = W[lane][c];
+  T myinv = T(1);
+  int first_bad = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      tr[a][b] = Tl[r0 + a][c0 + b];
-      xr[a][b] = (r0 + a == c0 + b) ? T(1) : T(0);
-    }
-  __syncthreads();
   for (int j = 0; j < NB; ++j) {
-    const int buf = j & 1;
-    if (j >= c0 && j < c0 + 4) {
+    T d = read_lane(a[j], j);
+    const bool ok = d > T(0);
+    first_bad = (!ok && first_bad == 0 && j < kb) ? j + 1 : first_bad;
+    d = ok ? d : T(1);
+    const T isd = rsqrt_nr(d);
+    const T l = (lane == j) ? d * isd : a[j] * isd;
+    a[j] = l;
+    myinv = (lane == j) ? isd : myinv;
+    colbuf[lane] = l;
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (c0 + b == j)
-#pragma unroll
-          for (int a = 0; a < 4; ++a) colbuf[buf][r0 + a] = tr[a][b];
-    }
-    __syncthreads();
-    T d = colbuf[buf][j];
-    if (!(d > T(0))) {
-      if (j < kb && threadIdx.x == 0 && *info == 0) *info = static_cast<int32_t>(k0 + j + 1);
-      d = T(1);
-    }
-    const T sd = sqrt(d), isd = T(1) / sd;
-    T lr[4], lc[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      lr[a] = colbuf[buf][r0 + a] * isd;
-      lc[a] = colbuf[buf][c0 + a] * isd;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int i = r0 + a, l = c0 + b;
-        if (i > j && l > j && l <= i) tr[a][b] -= lr[a] * lc[b];
-      }
-    if (j >= r0 && j < r0 + 4) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (r0 + a == j)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            xr[a][b] *= isd;
-            rowbuf[buf][c0 + b] = xr[a][b];
-          }
-    }
-    __syncthreads();
-    T xj[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) xj[b] = rowbuf[buf][c0 + b];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      if (r0 + a > j)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) xr[a][b] -= lr[a] * xj[b];
+    for (int c = j + 1; c < NB; ++c) a[c] -= l * colbuf[c];
+    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) Linv[(r0 + a) * NB + c0 + b] = xr[a][b];
+  for (int c = 0; c < NB; ++c) W[lane][c] = a[c];
+  colbuf[lane] = myinv;
+  __builtin_amdgcn_wave_barrier();
+  if (first_bad != 0 && lane == 0 && *info == 0) *info = static_cast<int32_t>(k0 + first_bad);
+  for (int r = 0; r < kb; ++r) {
+    if (lane <= r) L[(k0 + r) * n + k0 + lane] = W[r][lane];
+    if (lane >= r && lane < kb) Lt[(k0 + r) * n + k0 + lane] = W[lane][r];
+  }
+  if (lane < kb) dinv[k0 + lane] = colbuf[lane];
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ L,
-                                                         T* __restrict__ Linv, int32_t* __restrict__ info) {
-  __shared__ T Tl[NB][NB + 1];
-  __shared__ T colbuf[2][NB];
-  __shared__ T rowbuf[2][NB];
+                                                         T* __restrict__ Lt, T* __restrict__ dinv,
+                                                         int32_t* __restrict__ info) {
+  __shared__ T W[NB][NB + 1];
+  __shared__ T colbuf[NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
   if (threadIdx.x == 0) *info = 0;
   for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    int r = idx / NB, c = idx % NB;
-    Tl[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
+    const int r = idx / NB, c = idx % NB;
+    W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
   }
   __syncthreads();
-  tile_factor_inverse<T>(Tl, Linv, kb, 0, info, colbuf, rowbuf);
-  (void)L;
+  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
 }
 
-// P = Araw Linv^T into LDS (rows beyond the matrix are zero)
+// v <- L_kk^-1 v for the register vector v (lane-private), with LkT[c][r] =
+// L_kk[r][c] and dk = 1 / diag(L_kk) in LDS.
 template <typename T>
-__device__ void panel_times_linvT(const T* __restrict__ A, int64_t n, int64_t r0, int64_t k0, const T (*Li)[NB + 1],
-                                  T (*Raw)[NB + 1], T (*P)[NB + 1]) {
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    int r = idx / NB, c = idx % NB;
-    int64_t gr = r0 + r, gc = k0 + c;
-    Raw[r][c] = (gr < n && gc < n) ? A[gr * n + gc] : T(0);
+__device__ __forceinline__ void forward_subst_regs(T v[NB], const T (*LkT)[NB + 1], const T* dk) {
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const T y = v[c] * dk[c];
+    v[c] = y;
+#pragma unroll
+    for (int r = c + 1; r < NB; ++r) v[r] -= y * LkT[c][r];
   }
-  __syncthreads();
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-  for (int p = 0; p < NB; ++p) {
-    T x[4], y[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      x[q] = Raw[ty + 16 * q][p];
-      y[q] = Li[tx + 16 * q][p];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) P[ty + 16 * a][tx + 16 * b] = acc[a][b];
-  __syncthreads();
 }
 
+// Panel of block column k: row gr of block row i solves L_kk p = A[gr, k-block]^T.
 template <typename T>
-__global__ void __launch_bounds__(256) chol_step_kernel(T* __restrict__ A, int64_t n, int64_t k, T* __restrict__ L,
-                                                        T* __restrict__ Linv, int32_t* __restrict__ info) {
+__global__ void __launch_bounds__(64) chol_panel_kernel(const T* __restrict__ A, int64_t n, int64_t k,
+                                                        T* __restrict__ L, T* __restrict__ Lt,
+                                                        const T* __restrict__ dinv) {
+  __shared__ T LkT[NB][NB + 1];
+  __shared__ T dk[NB];
+  const int lane = threadIdx.x;
+  const int64_t k0 = k * NB;
+  // L_kk is a full block (k < nblk - 1); its transpose is row block k of Lt
+  for (int c = 0; c < NB; ++c) LkT[c][lane] = (lane >= c) ? Lt[(k0 + c) * n + k0 + lane] : T(0);
+  dk[lane] = dinv[k0 + lane];
+  __syncthreads();
+  const int64_t gr = (k + 1 + blockIdx.x) * NB + lane;
+  if (gr >= n) return;
+  T v[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) v[c] = A[gr * n + k0 + c];
+  forward_subst_regs<T>(v, LkT, dk);
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    L[gr * n + k0 + c] = v[c];
+    Lt[(k0 + c) * n + gr] = v[c];
+  }
+}
+
+// Trailing update of tile (bi, bj), k < bj <= bi, on the matrix cores; the
+// workgroup of tile (k+1, k+1) factors it afterwards.
+template <typename T>
+__global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int64_t n, int64_t k,
+                                                          T* __restrict__ L, T* __restrict__ Lt,
+                                                          T* __restrict__ dinv, int32_t* __restrict__ info) {
   extern __shared__ unsigned char smem_raw[];
-  T (*Li)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);
-  T (*Pi)[NB + 1] = Li + NB;
-  T (*Pj)[NB + 1] = Pi + NB;
-  T (*Wk)[NB + 1] = Pj + NB;            // scratch: raw panel, then the tile
+  T (*Ta)[NB] = reinterpret_cast<T (*)[NB]>(smem_raw);          // Ta[p][r] = L[i0 + r][k0 + p]
+  T (*Tb)[NB] = Ta + NB;                                         // Tb[p][r] = L[j0 + r][k0 + p]
+  T (*W)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);   // reused for the tile to factor
+  __shared__ T colbuf[NB];
   const int64_t nblk = (n + NB - 1) / NB;
-  // tile index -> (i, j) with k < j <= i < nblk
   const int64_t m = nblk - k - 1;
   int64_t t = blockIdx.x, ii = 0;
   while (t >= m - ii) { t -= m - ii; ++ii; }
   const int64_t bj = k + 1 + ii, bi = bj + t;
   const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
-  const T* Lk = Linv + k * NB * NB;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Li[idx / NB][idx % NB] = Lk[idx];
-  __syncthreads();
-  panel_times_linvT<T>(A, n, i0, k0, Li, Wk, Pi);
-  if (bi != bj) panel_times_linvT<T>(A, n, j0, k0, Li, Wk, Pj);
-  T (*Q)[NB + 1] = (bi != bj) ? Pj : Pi;
-  if (bi == bj) {
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      int r = idx / NB, c = idx % NB;
-      int64_t gr = i0 + r, gc = k0 + c;
-      if (gr < n && gc < n) L[gr * n + gc] = Pi[r][c];
-    }
-  }
-  // trailing update of tile (bi, bj), kept in Wk
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-  for (int p = 0; p < NB; ++p) {
-    T x[4], y[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      x[q] = Pi[ty + 16 * q][p];
-      y[q] = Q[tx + 16 * q][p];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    const int p = idx / NB, r = idx % NB;
+    const T* row = Lt + (k0 + p) * n;
+    Ta[p][r] = (i0 + r < n) ? row[i0 + r] : T(0);
+    Tb[p][r] = (j0 + r < n) ? row[j0 + r] : T(0);
   }
   __syncthreads();
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int rb = 32 * (w / 2), cb = 32 * (w % 2);
+  const int lr = lane % 16, lk = lane / 16;
+  typename MfmaVec<T>::type acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+  for (int p0 = 0; p0 < NB; p0 += 4) {
+    const T a0 = Ta[p0 + lk][rb + lr], a1 = Ta[p0 + lk][rb + 16 + lr];
+    const T b0 = Tb[p0 + lk][cb + lr], b1 = Tb[p0 + lk][cb + 16 + lr];
+    acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
+    acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
+    acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
+    acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
+  }
   const bool last = (bi == k + 1) && (bj == k + 1);
-  const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
+  if (last) __syncthreads();      // Ta/Tb are overwritten by W below
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int r = ty + 16 * a, c = tx + 16 * b;
-      int64_t gr = i0 + r, gc = j0 + c;
-      T v;
-      if (gr < n && gc < n) {
-        v = A[gr * n + gc] - acc[a][b];
-        if (!last) A[gr * n + gc] = v;
-      } else {
-        v = (r == c) ? T(1) : T(0);
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = rb + 16 * x + 4 * lk + q, c = cb + 16 * y + lr;
+        const int64_t gr = i0 + r, gc = j0 + c;
+        if (gr < n && gc < n) {
+          const T v = A[gr * n + gc] - acc[x][y][q];
+          if (last) W[r][c] = v;
+          else A[gr * n + gc] = v;
+        } else if (last) {
+          W[r][c] = (r == c) ? T(1) : T(0);
+        }
       }
-      Wk[r][c] = v;
-    }
-  __syncthreads();
   if (!last) return;
-  // factor the next diagonal tile and store the inverse of its factor
-  T (*colbuf)[NB] = reinterpret_cast<T (*)[NB]>(&Pi[0][0]);
-  T (*rowbuf)[NB] = reinterpret_cast<T (*)[NB]>(&Pj[0][0]);
-  tile_factor_inverse<T>(Wk, Linv + (k + 1) * NB * NB, kb, i0, info, colbuf, rowbuf);
+  __syncthreads();
+  const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
+  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
 }
 
 template <typename T>
-void dense_cholesky(T* A, int64_t n, T* L, T* Linv, int32_t* d_info, hipStream_t st) {
+void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
   if (n <= 0) return;
+  T* Lt = aux;
+  T* dinv = aux + n * n;
   const int64_t nblk = (n + NB - 1) / NB;
-  launch_fill_i32(d_info, 1, 0, st);
-  // only the lower blocks of L are ever read: the upper part is left as is
-  chol_first_kernel<T><<<1, 256, 0, st>>>(A, n, L, Linv, d_info);
-  const size_t shm = sizeof(T) * 4 * NB * (NB + 1);
+  chol_first_kernel<T><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, d_info);
+  const size_t shm = sizeof(T) * 2 * NB * NB;
   for (int64_t k = 0; k + 1 < nblk; ++k) {
     const int64_t m = nblk - k - 1;
-    chol_step_kernel<T><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Linv, d_info);
+    chol_panel_kernel<T><<<static_cast<unsigned>(m), 64, 0, st>>>(A, n, k, L, Lt, dinv);
+    chol_update_kernel<T><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Lt, dinv, d_info);
   }
 }
 
-// ---- solves: one workgroup, blocked with the stored diagonal inverses ----------
+// ---- solves: one workgroup, diagonal blocks by one wave, the rest coalesced -----
 template <typename T>
-__global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ L, const T* __restrict__ Linv,
-                                                          int64_t n, T* __restrict__ b, int nrhs) {
-  __shared__ T t[NB][4];
-  __shared__ T red[16][NB][4];
-  __shared__ T Ls[NB][NB + 1];
-  const int lane = threadIdx.x % PDIPC_WAVE, wave = threadIdx.x / PDIPC_WAVE;
+__global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
+                                                          const T* __restrict__ dinv, int64_t n, T* __restrict__ b,
+                                                          int nrhs) {
+  __shared__ T Lk[NB][NB + 1];
+  __shared__ T ys[NB][4];
+  __shared__ T dk[NB];
+  const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t nblk = (n + NB - 1) / NB;
   // forward: L y = b
   for (int64_t bk = 0; bk < nblk; ++bk) {
     const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    for (int r = wave; r < NB; r += 16) {
-      T s[4] = {T(0), T(0), T(0), T(0)};
-      if (r < kb) {
-        const T* Lr = L + (k0 + r) * n;
-        for (int64_t c = lane; c < k0; c += PDIPC_WAVE) {
-          T v = Lr[c];
-          for (int q = 0; q < nrhs; ++q) s[q] += v * b[c * nrhs + q];
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      const int r = idx / NB, c = idx % NB;
+      Lk[r][c] = (r < kb && c <= r) ? L[(k0 + r) * n + k0 + c] : T(0);
+    }
+    if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
+    __syncthreads();
+    if (threadIdx.x < PDIPC_WAVE) {
+      T tq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tq[q] = (lane < kb && q < nrhs) ? b[(k0 + lane) * nrhs + q] : T(0);
+      for (int i = 0; i < kb; ++i) {
+        const T di = dk[i], lv = Lk[lane][i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < nrhs) {
+            const T y = read_lane(tq[q], i) * di;
+            if (lane == i) tq[q] = y;
+            else if (lane > i) tq[q] -= lv * y;
+          }
         }
       }
-      for (int q = 0; q < nrhs; ++q) {
-        T w = s[q];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, PDIPC_WAVE);
-        s[q] = w;
+      for (int q = 0; q < 4; ++q) {
+        ys[lane][q] = tq[q];
+        if (lane < kb && q < nrhs) b[(k0 + lane) * nrhs + q] = tq[q];
       }
-      if (lane == 0)
-        for (int q = 0; q < 4; ++q) t[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] - s[q] : T(0);
     }
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Ls[idx / NB][idx % NB] = Linv[bk * NB * NB + idx];
     __syncthreads();
-    if (threadIdx.x < NB * 4) {
-      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
-      T acc = T(0);
-      for (int c = 0; c <= r; ++c) acc += Ls[r][c] * t[c][q];
-      if (r < kb && q < nrhs) b[(k0 + r) * nrhs + q] = acc;
+    for (int64_t gr = k0 + kb + threadIdx.x; gr < n; gr += blockDim.x) {
+      T s[4] = {T(0), T(0), T(0), T(0)};
+      for (int c = 0; c < kb; ++c) {
+        const T l = Lt[(k0 + c) * n + gr];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += l * ys[c][q];
+      }
+      for (int q = 0; q < nrhs; ++q) b[gr * nrhs + q] -= s[q];
     }
     __syncthreads();
   }
@@ -348,135 +371,126 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
   for (int64_t bk = nblk - 1; bk >= 0; --bk) {
     const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    {
-      T s[4] = {T(0), T(0), T(0), T(0)};
-      if (lane < kb)
-        for (int64_t i = k0 + kb + wave; i < n; i += 16) {
-          T v = L[i * n + k0 + lane];
-          for (int q = 0; q < nrhs; ++q) s[q] += v * b[i * nrhs + q];
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      const int r = idx / NB, c = idx % NB;
+      Lk[r][c] = (r < kb && c <= r) ? L[(k0 + r) * n + k0 + c] : T(0);
+    }
+    if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
+    __syncthreads();
+    if (threadIdx.x < PDIPC_WAVE) {
+      T tq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tq[q] = (lane < kb && q < nrhs) ? b[(k0 + lane) * nrhs + q] : T(0);
+      for (int i = kb - 1; i >= 0; --i) {
+        const T di = dk[i], lv = Lk[i][lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < nrhs) {
+            const T x = read_lane(tq[q], i) * di;
+            if (lane == i) tq[q] = x;
+            else if (lane < i) tq[q] -= lv * x;
+          }
         }
-      for (int q = 0; q < 4; ++q) red[wave][lane][q] = s[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < NB * 4) {
-      const int c = threadIdx.x / 4, q = threadIdx.x % 4;
-      T acc = T(0);
-      for (int w = 0; w < 16; ++w) acc += red[w][c][q];
-      t[c][q] = (c < kb && q < nrhs) ? b[(k0 + c) * nrhs + q] - acc : T(0);
-    }
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Ls[idx / NB][idx % NB] = Linv[bk * NB * NB + idx];
-    __syncthreads();
-    if (threadIdx.x < NB * 4) {
-      const int c = threadIdx.x / 4, q = threadIdx.x % 4;
-      T acc = T(0);
-      for (int r = c; r < NB; ++r) acc += Ls[r][c] * t[r][q];
-      if (c < kb && q < nrhs) b[(k0 + c) * nrhs + q] = acc;
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T>
-void dense_chol_solve(const T* L, const T* Linv, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
-  if (n <= 0) return;
-  chol_solve_kernel<T><<<1, 1024, 0, st>>>(L, Linv, n, b, nrhs);
-}
-
-// ---- Y = L^-1 by block diagonals ------------------------------------------------
-// Y_ii = Linv_i; for i - j = d >= 1: Y_ij = -Linv_i sum_{j <= p < i} L_ip Y_pj.
-// Launch d computes every block of diagonal d (one workgroup each) from the
-// diagonals already done; the strict upper blocks are zeroed by launch 0.
-template <typename T>
-__global__ void __launch_bounds__(256) inv_diag_kernel(const T* __restrict__ L, const T* __restrict__ Linv, int64_t n,
-                                                       int64_t dd, T* __restrict__ Y) {
-  extern __shared__ unsigned char smem_raw[];
-  T (*Lt)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);
-  T (*Yp)[NB + 1] = Lt + NB;
-  T (*Acc)[NB + 1] = Yp + NB;
-  const int64_t nblk = (n + NB - 1) / NB;
-  const int64_t bj = blockIdx.x, bi = bj + dd;
-  const int64_t i0 = bi * NB, j0 = bj * NB;
-  const int ib = static_cast<int>(n - i0 < NB ? n - i0 : NB);
-  const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  if (dd == 0) {
-    // diagonal block and the zero block-row above it
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      int r = idx / NB, c = idx % NB;
-      if (r < ib && c < ib) Y[(i0 + r) * n + i0 + c] = Linv[bi * NB * NB + idx];
-    }
-    for (int64_t bq = bi + 1; bq < nblk; ++bq) {
-      const int64_t q0 = bq * NB;
-      const int qb = static_cast<int>(n - q0 < NB ? n - q0 : NB);
-      for (int idx = threadIdx.x; idx < ib * qb; idx += blockDim.x) Y[(i0 + idx / qb) * n + q0 + idx % qb] = T(0);
-    }
-    return;
-  }
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-  for (int64_t bp = bj; bp < bi; ++bp) {
-    const int64_t p0 = bp * NB;
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      int r = idx / NB, c = idx % NB;
-      Lt[r][c] = (r < ib && p0 + c < n) ? L[(i0 + r) * n + p0 + c] : T(0);
-      Yp[r][c] = (p0 + r < n && c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
-    }
-    __syncthreads();
-    for (int p = 0; p < NB; ++p) {
-      T x[4], y[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        x[q] = Lt[ty + 16 * q][p];
-        y[q] = Yp[p][tx + 16 * q];
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int q = 0; q < 4; ++q) {
+        ys[lane][q] = tq[q];
+        if (lane < kb && q < nrhs) b[(k0 + lane) * nrhs + q] = tq[q];
+      }
+    }
+    __syncthreads();
+    for (int64_t gc = threadIdx.x; gc < k0; gc += blockDim.x) {
+      T s[4] = {T(0), T(0), T(0), T(0)};
+      for (int c = 0; c < kb; ++c) {
+        const T l = L[(k0 + c) * n + gc];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+        for (int q = 0; q < 4; ++q) s[q] += l * ys[c][q];
+      }
+      for (int q = 0; q < nrhs; ++q) b[gc * nrhs + q] -= s[q];
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) Acc[ty + 16 * a][tx + 16 * b] = -acc[a][b];
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) Lt[idx / NB][idx % NB] = Linv[bi * NB * NB + idx];
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-  for (int p = 0; p < NB; ++p) {
-    T x[4], y[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      x[q] = Lt[ty + 16 * q][p];
-      y[q] = Acc[p][tx + 16 * q];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int r = ty + 16 * a, c = tx + 16 * b;
-      if (r < ib && c < jb) Y[(i0 + r) * n + j0 + c] = acc[a][b];
-    }
 }
 
 template <typename T>
-void dense_chol_inverse(const T* L, const T* Linv, int64_t n, T* Ainv, T* work, hipStream_t st) {
+void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
+  if (n <= 0) return;
+  chol_solve_kernel<T><<<1, 1024, 0, st>>>(L, aux, aux + n * n, n, b, nrhs);
+}
+
+// ---- Y = L^-1, one workgroup per 64-column block -------------------------------
+// Block row kk >= j of column block j: Y_kk,j = L_kk^-1 (delta_kj I - sum_{j<=p<kk}
+// L_kp Y_pj); the sum is staged through LDS, the diagonal solve is done by one
+// wave with each lane holding one column in registers.  Blocks above the
+// diagonal are zeroed.
+template <typename T>
+__global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
+                                                        const T* __restrict__ dinv, int64_t n, T* __restrict__ Y) {
+  __shared__ T Ls[NB][NB + 1];
+  __shared__ T Ys[NB][NB + 1];
+  __shared__ T Tm[NB][NB + 1];
+  __shared__ T dk[NB];
+  const int64_t nblk = (n + NB - 1) / NB;
+  const int64_t bj = blockIdx.x, j0 = bj * NB;
+  const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
+  for (int64_t r = threadIdx.x / NB; r < j0; r += blockDim.x / NB) {
+    const int c = threadIdx.x % NB;
+    if (c < jb) Y[r * n + j0 + c] = T(0);
+  }
+  const int tr = threadIdx.x / 4, tq = threadIdx.x % 4;     // row tr, columns 16 tq .. 16 tq + 15
+  for (int64_t bk = bj; bk < nblk; ++bk) {
+    const int64_t k0 = bk * NB;
+    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
+    T acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = (bk == bj && tr == 16 * tq + c) ? T(1) : T(0);
+    for (int64_t bp = bj; bp < bk; ++bp) {
+      const int64_t p0 = bp * NB;
+      for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+        const int r = idx / NB, c = idx % NB;
+        Ls[r][c] = (r < kb) ? L[(k0 + r) * n + p0 + c] : T(0);
+        Ys[r][c] = (c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
+      }
+      __syncthreads();
+      for (int s = 0; s < NB; ++s) {
+        const T l = Ls[tr][s];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] -= l * Ys[s][16 * tq + c];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Tm[tr][16 * tq + c] = acc[c];
+    // LkT[c][r] = L_kk[r][c] (reusing Ls), identity-padded
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      const int c = idx / NB, r = idx % NB;
+      Ls[c][r] = (r < kb && c < kb) ? (r >= c ? Lt[(k0 + c) * n + k0 + r] : T(0)) : (r == c ? T(1) : T(0));
+    }
+    if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
+    __syncthreads();
+    if (threadIdx.x < PDIPC_WAVE) {
+      const int c = threadIdx.x;
+      T v[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) v[r] = Tm[r][c];
+      forward_subst_regs<T>(v, Ls, dk);
+#pragma unroll
+      for (int r = 0; r < NB; ++r) Tm[r][c] = v[r];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      const int r = idx / NB, c = idx % NB;
+      if (r < kb && c < jb) Y[(k0 + r) * n + j0 + c] = Tm[r][c];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st) {
   if (n <= 0) return;
   const unsigned nblk = grid_for(n, NB);
-  const size_t shm = sizeof(T) * 3 * NB * (NB + 1);
-  for (unsigned dd = 0; dd < nblk; ++dd)
-    inv_diag_kernel<T><<<nblk - dd, 256, shm, st>>>(L, Linv, n, dd, work);
+  chol_linv_kernel<T><<<nblk, 256, 0, st>>>(L, aux, aux + n * n, n, work);
   dim3 grid(nblk, nblk);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
 }

@@ -280,27 +280,44 @@ void launch_cinv_times_zc(int32_t nc, const double* Cinv, const int32_t* c_x2, c
 }
 
 // z[j] -= sum_i S[c_x2[i]][j] v[i]   (S symmetric: the rows of c are its columns)
-__global__ void __launch_bounds__(FT) sigma_cols_kernel(int32_t n2, int32_t nc, const int32_t* __restrict__ c_x2,
-                                                        const double* __restrict__ S, const double* __restrict__ v,
-                                                        double* __restrict__ z) {
-  int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n2) return;
+// z_j -= sum_i Sigma^-1[c_i][j] v_i (Sigma^-1 symmetric, rows read coalesced
+// along j).  Block: 64 consecutive j (one per lane) x 16 waves, wave g takes
+// i = g, g + 16, ...; the 16 partial sums are added in wave order, so the
+// result does not depend on scheduling.
+constexpr int SC_WAVES = 16;
+__global__ void __launch_bounds__(SC_WAVES * PDIPC_WAVE) sigma_cols_kernel(int32_t n2, int32_t nc,
+                                                                        const int32_t* __restrict__ c_x2,
+                                                                        const double* __restrict__ S,
+                                                                        const double* __restrict__ v,
+                                                                        double* __restrict__ z) {
+  __shared__ double part[SC_WAVES][3][PDIPC_WAVE];
+  const int lane = threadIdx.x % PDIPC_WAVE, g = threadIdx.x / PDIPC_WAVE;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * PDIPC_WAVE + lane;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int32_t i = 0; i < nc; ++i) {
-    double c = S[static_cast<int64_t>(c_x2[i]) * n2 + j];
-    s0 += c * v[3 * i];
-    s1 += c * v[3 * i + 1];
-    s2 += c * v[3 * i + 2];
+  if (j < n2) {
+    for (int32_t i = g; i < nc; i += SC_WAVES) {
+      const double c = S[static_cast<int64_t>(c_x2[i]) * n2 + j];
+      s0 += c * v[3 * i];
+      s1 += c * v[3 * i + 1];
+      s2 += c * v[3 * i + 2];
+    }
   }
-  z[3 * j] -= s0;
-  z[3 * j + 1] -= s1;
-  z[3 * j + 2] -= s2;
+  part[g][0][lane] = s0;
+  part[g][1][lane] = s1;
+  part[g][2][lane] = s2;
+  __syncthreads();
+  if (g < 3 && j < n2) {
+    double acc = 0.0;
+    for (int w = 0; w < SC_WAVES; ++w) acc += part[w][g][lane];
+    z[3 * j + g] -= acc;
+  }
 }
 
 void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* z,
                               hipStream_t st) {
   if (nc > 0 && f.n2 > 0)
-    sigma_cols_kernel<<<grid_for(f.n2, FT), FT, 0, st>>>(f.n2, nc, c_x2, f.sigma_inv, v, z);
+    sigma_cols_kernel<<<grid_for(f.n2, PDIPC_WAVE), SC_WAVES * PDIPC_WAVE, 0, st>>>(f.n2, nc, c_x2, f.sigma_inv, v,
+                                                                                    z);
 }
 
 }  // namespace pdipc

@@ -6,7 +6,7 @@ namespace pdipc {
 
 namespace {
 constexpr int SCAN_T = 256;
-constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_T * SCAN_ITEMS;
 constexpr int RED_T = 256;
 constexpr int RED_BLOCKS = 512;
@@ -15,79 +15,70 @@ int64_t nblocks(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
-// Block-local exclusive scan; writes the block total to bsum[blockIdx].
-__global__ void __launch_bounds__(SCAN_T) scan_block_kernel(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                                                            int64_t n, int32_t* __restrict__ bsum) {
+// Exclusive scan in two launches: per-tile sums, then every tile adds the sums
+// of the tiles before it (read from the small bsum array) to its local scan.
+// The last tile also writes the total.  The input may alias the output: each
+// tile reads its inputs into registers before writing.
+__global__ void __launch_bounds__(SCAN_T) scan_reduce_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                             int32_t* __restrict__ bsum) {
+  __shared__ int32_t sh[SCAN_T / PDIPC_WAVE];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+  int32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t idx = base + k * SCAN_T + threadIdx.x;
+    acc += idx < n ? in[idx] : 0;
+  }
+  acc = wave_sum_i32(acc);
+  if (threadIdx.x % PDIPC_WAVE == 0) sh[threadIdx.x / PDIPC_WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < SCAN_T / PDIPC_WAVE; ++w) t += sh[w];
+    bsum[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(SCAN_T) scan_apply_kernel(const int32_t* in, int32_t* out, int64_t n,
+                                                            const int32_t* __restrict__ bsum, int32_t nb,
+                                                            int32_t* __restrict__ d_total) {
   __shared__ int32_t sh[SCAN_T];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  __shared__ int32_t wsum[SCAN_T / PDIPC_WAVE];
+  // offset of this tile: sum of the tile sums before it
+  int32_t off = 0;
+  for (int b = threadIdx.x; b < static_cast<int>(blockIdx.x); b += SCAN_T) off += bsum[b];
+  off = wave_sum_i32(off);
+  if (threadIdx.x % PDIPC_WAVE == 0) wsum[threadIdx.x / PDIPC_WAVE] = off;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + static_cast<int64_t>(threadIdx.x) * SCAN_ITEMS;
   int32_t v[SCAN_ITEMS];
   int32_t acc = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int64_t idx = base + k;
+    const int64_t idx = base + k;
     v[k] = idx < n ? in[idx] : 0;
     acc += v[k];
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
-  for (int off = 1; off < SCAN_T; off <<= 1) {
-    int32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+  int32_t tile_off = 0;
+  for (int w = 0; w < SCAN_T / PDIPC_WAVE; ++w) tile_off += wsum[w];
+  for (int o = 1; o < SCAN_T; o <<= 1) {
+    const int32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
     __syncthreads();
     sh[threadIdx.x] += t;
     __syncthreads();
   }
-  int32_t run = sh[threadIdx.x] - acc;          // exclusive prefix of this thread
+  int32_t run = tile_off + sh[threadIdx.x] - acc;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int64_t idx = base + k;
+    const int64_t idx = base + k;
     if (idx < n) out[idx] = run;
     run += v[k];
   }
-  if (threadIdx.x == SCAN_T - 1) bsum[blockIdx.x] = sh[SCAN_T - 1];
+  if (blockIdx.x == static_cast<unsigned>(nb - 1) && threadIdx.x == SCAN_T - 1) *d_total = tile_off + sh[SCAN_T - 1];
 }
 
-__global__ void scan_add_kernel(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ boff) {
-  int64_t idx = static_cast<int64_t>(blockIdx.x) * SCAN_T * SCAN_ITEMS + threadIdx.x;
-  int32_t add = boff[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    int64_t j = idx + k * SCAN_T;
-    if (j < n) out[j] += add;
-  }
-}
-
-__global__ void scan_total_kernel(const int32_t* __restrict__ in_last, const int32_t* __restrict__ out_last,
-                                  int32_t* d_total) {
-  *d_total = *in_last + *out_last;
-}
-
-size_t scan_temp_bytes(int64_t n) {
-  size_t b = 0;
-  int64_t m = n;
-  while (true) {
-    int64_t nb = nblocks(m);
-    b += align256(sizeof(int32_t) * (nb + 1)) * 2;
-    if (nb <= 1) break;
-    m = nb;
-  }
-  return b + 256;
-}
-
-static void scan_rec(const int32_t* in, int32_t* out, int64_t n, char* temp, hipStream_t st) {
-  int64_t nb = nblocks(n);
-  int32_t* bsum = reinterpret_cast<int32_t*>(temp);
-  int32_t* boff = reinterpret_cast<int32_t*>(temp + align256(sizeof(int32_t) * (nb + 1)));
-  char* next = temp + 2 * align256(sizeof(int32_t) * (nb + 1));
-  scan_block_kernel<<<static_cast<unsigned>(nb), SCAN_T, 0, st>>>(in, out, n, bsum);
-  if (nb > 1) {
-    scan_rec(bsum, boff, nb, next, st);
-    scan_add_kernel<<<static_cast<unsigned>(nb), SCAN_T, 0, st>>>(out, n, boff);
-  }
-}
-
-// The input may alias the output; the last input element is saved first so
-// the total stays correct.
-__global__ void copy_last_kernel(const int32_t* in, int64_t n, int32_t* dst) { *dst = in[n - 1]; }
+size_t scan_temp_bytes(int64_t n) { return align256(sizeof(int32_t) * (nblocks(n) + 1)) + 256; }
 
 void launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total, void* temp,
                            hipStream_t st) {
@@ -95,11 +86,10 @@ void launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* 
     launch_fill_i32(d_total, 1, 0, st);
     return;
   }
-  char* t = static_cast<char*>(temp);
-  int32_t* last = reinterpret_cast<int32_t*>(t);
-  copy_last_kernel<<<1, 1, 0, st>>>(in, n, last);
-  scan_rec(in, out, n, t + 256, st);
-  scan_total_kernel<<<1, 1, 0, st>>>(last, out + n - 1, d_total);
+  const int64_t nb = nblocks(n);
+  int32_t* bsum = static_cast<int32_t*>(temp);
+  scan_reduce_kernel<<<static_cast<unsigned>(nb), SCAN_T, 0, st>>>(in, n, bsum);
+  scan_apply_kernel<<<static_cast<unsigned>(nb), SCAN_T, 0, st>>>(in, out, n, bsum, static_cast<int32_t>(nb), d_total);
 }
 
 // ---- deterministic FP64 sums -------------------------------------------------
@@ -167,23 +157,25 @@ __global__ void __launch_bounds__(RED_T) minmax_partial_kernel(const double* __r
   }
 }
 
-__global__ void minmax_final_kernel(const double* __restrict__ part, int nparts, int mode, double* out) {
-  if (threadIdx.x != 0) return;
+// one wave: strided loads, then a wave reduction (min and max are order-free)
+__global__ void __launch_bounds__(PDIPC_WAVE) minmax_final_kernel(const double* __restrict__ part, int nparts,
+                                                                  int mode, double* out) {
   double r = mode == 0 ? 1.0 : 0.0;
-  for (int i = 0; i < nparts; ++i) r = mode == 0 ? fmin(r, part[i]) : fmax(r, part[i]);
-  *out = r;
+  for (int i = threadIdx.x; i < nparts; i += PDIPC_WAVE) r = mode == 0 ? fmin(r, part[i]) : fmax(r, part[i]);
+  r = mode == 0 ? wave_min(r) : wave_max(r);
+  if (threadIdx.x == 0) *out = r;
 }
 
 void launch_min_clamp1(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st) {
   double* part = static_cast<double*>(temp);
   minmax_partial_kernel<<<RED_BLOCKS, RED_T, 0, st>>>(in, n, 0, part);
-  minmax_final_kernel<<<1, 64, 0, st>>>(part, RED_BLOCKS, 0, d_out);
+  minmax_final_kernel<<<1, PDIPC_WAVE, 0, st>>>(part, RED_BLOCKS, 0, d_out);
 }
 
 void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st) {
   double* part = static_cast<double*>(temp);
   minmax_partial_kernel<<<RED_BLOCKS, RED_T, 0, st>>>(in, n, 1, part);
-  minmax_final_kernel<<<1, 64, 0, st>>>(part, RED_BLOCKS, 1, d_out);
+  minmax_final_kernel<<<1, PDIPC_WAVE, 0, st>>>(part, RED_BLOCKS, 1, d_out);
 }
 
 // ---- fills and updates ------------------------------------------------------
@@ -207,6 +199,18 @@ __global__ void count_nonfinite_kernel(const double* __restrict__ x, int64_t n, 
 void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStream_t st) {
   launch_fill_i32(d_out, 1, 0, st);
   if (n > 0) count_nonfinite_kernel<<<grid_for(n, 256), 256, 0, st>>>(x, n, d_out);
+}
+
+// *flag <- 1 if a and b differ anywhere in [0, n) (cleared first; every
+// writer stores the same value)
+__global__ void differ_kernel(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n,
+                              int32_t* __restrict__ flag) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && a[i] != b[i]) *flag = 1;
+}
+void launch_differ_i32(const int32_t* a, const int32_t* b, int64_t n, int32_t* d_flag, hipStream_t st) {
+  launch_fill_i32(d_flag, 1, 0, st);
+  if (n > 0) differ_kernel<<<grid_for(n, 256), 256, 0, st>>>(a, b, n, d_flag);
 }
 
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {

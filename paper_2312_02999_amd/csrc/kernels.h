@@ -41,6 +41,7 @@ void launch_axpy_positions(int64_t n3, double alpha, const double* dx, double* x
 void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
 // number of non-finite entries -> *d_out
 void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStream_t st);
+void launch_differ_i32(const int32_t* a, const int32_t* b, int64_t n, int32_t* d_flag, hipStream_t st);
 
 // ------------------------------------------------------------------- contact
 struct ProxyDev {
@@ -192,20 +193,20 @@ void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x
 void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
 
 // ---------------------------------------------------------------- dense SPD
-// Lower Cholesky of an n x n row-major SPD matrix A (full symmetric input,
-// destroyed).  Writes the lower blocks of L (n x n row-major; the strict
-// upper part is not written) and the inverse of every 64 x 64 diagonal block
-// (Linv: ceil(n/64) blocks of 64 x 64).  *d_info <- 0 ok, else 1 + the first
-// failing column.
-inline int64_t dense_linv_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
+// Lower Cholesky of an n x n row-major SPD matrix A (lower triangle read,
+// destroyed).  Writes the lower triangle of L (n x n row-major; the strict
+// upper part is not written) and, in aux (dense_aux_size(n) entries), the
+// transpose Lt (n x n) followed by 1 / diag(L) (n).  *d_info <- 0 ok, else
+// 1 + the first failing column.
+inline int64_t dense_aux_size(int64_t n) { return n * n + n + 64; }
 template <typename T>
-void dense_cholesky(T* A, int64_t n, T* L, T* Linv, int32_t* d_info, hipStream_t st);
+void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st);
 // Solve L L^T x = b in place (b: n x nrhs row-major, nrhs <= 4).
 template <typename T>
-void dense_chol_solve(const T* L, const T* Linv, int64_t n, T* b, int32_t nrhs, hipStream_t st);
+void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st);
 // Ainv = (L L^T)^-1 (full symmetric, row-major), work: n x n scratch
 template <typename T>
-void dense_chol_inverse(const T* L, const T* Linv, int64_t n, T* Ainv, T* work, hipStream_t st);
+void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st);
 void launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t st);
 // Jacobi scaling sc_i = 1/sqrt(M_ii); FP32 copies of S M S and S r; u += S y

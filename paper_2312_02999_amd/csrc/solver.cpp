@@ -134,6 +134,10 @@ struct Solver {
   bool cand_valid = false;
   int32_t cand_n = 0, cand_pt = 0;
   DBuf<int32_t> cflagbuf, cposbuf;
+  // C^-1 = ((Sigma_s^-1)_cc)^-1 depends only on the contact set c (Sigma_s^-1 is
+  // constant): it is kept while the flags of c are unchanged
+  DBuf<int32_t> prev_cflag;
+  bool cinv_valid = false;
   // adjoint work vectors
   DBuf<double> lam, res, zvec, pvec, kp, prod, pairbuf;
   int32_t adjoint_iters = 0;
@@ -472,7 +476,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
     sig.upload(hf.sigma.data(), static_cast<int64_t>(n2) * n2, st);
     wk.ensure(static_cast<int64_t>(n2) * n2);
     sl.ensure(static_cast<int64_t>(n2) * n2);
-    sli.ensure(dense_linv_size(n2));
+    sli.ensure(dense_aux_size(n2));
     dense_cholesky<double>(sig.p, n2, sl.p, sli.p, S->info.p, st);
     int32_t hinfo = 0;
     HIPCHK(hipMemcpyAsync(&hinfo, S->info.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -616,6 +620,7 @@ static int32_t read_scalar_i(Solver* S, const int32_t* dptr) {
 struct IterOut {
   int32_t npt = 0, nee = 0, nc = 0, ncand = 0, halvings = 0;
   bool ls_ok = true;
+  bool c_same = false;          // contact set equal to the one C^-1 was built for
   double alpha_m = 1.0, alpha = 0.0;
 };
 
@@ -645,7 +650,13 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
   }
   build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
   launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
-  io.nc = read_scalar_i(S, S->inc.d_nc);
+  if (S->cinv_valid) launch_differ_i32(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st);
+  int32_t h2[2] = {0, 1};
+  HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (S->cinv_valid ? 2 : 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(h2, S->h_scal, sizeof(int32_t) * (S->cinv_valid ? 2 : 1));
+  io.nc = h2[0];
+  io.c_same = S->cinv_valid && h2[1] == 0;
 }
 
 // Global step of Eq. (4) via Eq. (7) and (11): dx from g.
@@ -671,16 +682,21 @@ static void global_step(Solver* S, const IterOut& io) {
     S->work.ensure(static_cast<int64_t>(nc) * nc);
     S->Mred.ensure(N3 * N3);
     S->CsL.ensure(static_cast<int64_t>(nc) * nc);
-    S->CsLi.ensure(dense_linv_size(nc));
+    S->CsLi.ensure(dense_aux_size(nc));
     S->ML.ensure(N3 * N3);
-    S->MLi.ensure(dense_linv_size(N3));
+    S->MLi.ensure(dense_aux_size(N3));
     S->rhs.ensure(N3);
     S->u.ensure(N3);
     S->vvec.ensure(N3);
-    launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
-    launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, st);
-    dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p, st);
-    dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, st);
+    if (!io.c_same) {
+      launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
+      launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, st);
+      dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p, st);
+      dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, st);
+      S->prev_cflag.ensure(S->n + 1LL);
+      HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, st));
+      S->cinv_valid = true;
+    }
     launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
     bool solved = false;
@@ -689,7 +705,7 @@ static void global_step(Solver* S, const IterOut& io) {
       // unscaled system; falls back to FP64 if refinement cannot converge.
       S->Mf.ensure(N3 * N3);
       S->MLf.ensure(N3 * N3);
-      S->MLif.ensure(dense_linv_size(N3));
+      S->MLif.ensure(dense_aux_size(N3));
       S->uf.ensure(N3);
       S->resid.ensure(N3);
       S->scl.ensure(N3);
@@ -1051,6 +1067,7 @@ void pdipc_destroy(void* h) {
   S->lam.release(); S->res.release(); S->zvec.release(); S->pvec.release(); S->kp.release(); S->prod.release();
   S->pairbuf.release();
   S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release(); S->scl.release();
+  S->prev_cflag.release();
   delete S;
 }
 
@@ -1151,7 +1168,7 @@ int32_t pdipc_debug_dense(const double* A, int64_t n, double* b, int32_t nrhs, d
     int32_t hinfo = 0;
     if (precision == 0) {
       DBuf<double> W, L, Li, wk;
-      W.ensure(nn); L.ensure(nn); Li.ensure(dense_linv_size(n)); wk.ensure(nn);
+      W.ensure(nn); L.ensure(nn); Li.ensure(dense_aux_size(n)); wk.ensure(nn);
       HIPCHK(hipMemcpyAsync(W.p, A, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
       dense_cholesky<double>(W.p, n, L.p, Li.p, info.p, st);
       if (b && nrhs > 0) dense_chol_solve<double>(L.p, Li.p, n, b, nrhs, st);
@@ -1162,7 +1179,7 @@ int32_t pdipc_debug_dense(const double* A, int64_t n, double* b, int32_t nrhs, d
       W.release(); L.release(); Li.release(); wk.release();
     } else {
       DBuf<float> W, L, Li, wk, bf, invf;
-      W.ensure(nn); L.ensure(nn); Li.ensure(dense_linv_size(n)); wk.ensure(nn);
+      W.ensure(nn); L.ensure(nn); Li.ensure(dense_aux_size(n)); wk.ensure(nn);
       launch_convert_f64_f32(A, W.p, nn, st);
       dense_cholesky<float>(W.p, n, L.p, Li.p, info.p, st);
       if (b && nrhs > 0) {
