@@ -110,6 +110,62 @@ def cpu_baseline(sc, budget_s=20.0):
                       f"scaled to {sc.iters} iterations/frame ({sec_per_it:.2f} s/iteration)"}
 
 
+def run_adjoint(sc, n_targets=500, n_dirs=2, n_params=4, h_dir=1e-4, seed=1):
+    """Adjoint of a converged frame on the face mesh against central finite
+    differences of the same GPU solver (tolerance mode).  Targets are the
+    converged positions of seeded proxy vertices at 0.6 x the strength field;
+    the loss is taken at 0.8 x the field.  Finite differences run along seeded
+    random directions in actuation space (all tets at once) and along the
+    single tets with the largest gradient entries."""
+    import torch
+    from paper_2312_02999_amd import FP64, Solver
+    dev = "cuda"
+    S = Solver(sc, iters=1500, tol=1e-10, precision=FP64)
+    R = torch.from_numpy(np.ascontiguousarray(sc.act_R.reshape(-1, 9))).to(dev)
+    X = torch.from_numpy(np.ascontiguousarray(sc.X)).to(dev)
+    rng = np.random.default_rng(seed)
+    cand = np.setdiff1d(np.unique(sc.surf_tris), np.nonzero(sc.dirichlet)[0])
+    tv = torch.from_numpy(rng.choice(cand, min(n_targets, cand.size), replace=False)).to(dev)
+
+    def solve(a, x0):
+        S.set_actuation_scalar(torch.from_numpy(np.ascontiguousarray(a)).to(dev), R)
+        x, st = S.solve_frame(x0, stats=True)
+        return x, st
+
+    xt, st_t = solve(0.6 * sc.act_a, X)
+    a = 0.8 * sc.act_a
+    xs, st_s = solve(a, xt)
+    loss = lambda x: float(((x[tv] - xt[tv]) ** 2).sum())
+    L0 = loss(xs)
+    dLdx = torch.zeros_like(xs)
+    dLdx[tv] = 2.0 * (xs[tv] - xt[tv])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = S.solve_frame_backward(dLdx)
+    torch.cuda.synchronize()
+    ms_bwd = 1e3 * (time.perf_counter() - t0)
+    g = g.cpu().numpy()
+    errs = []
+    for k in range(n_dirs):
+        d = rng.standard_normal(sc.m)
+        fd = (loss(solve(a + h_dir * d, xs)[0]) - loss(solve(a - h_dir * d, xs)[0])) / (2 * h_dir)
+        errs.append(("dir", k, float(g @ d), fd))
+    top = np.argsort(-np.abs(g))[:n_params]
+    for i in top:
+        e = np.zeros(sc.m)
+        h = 1e-3
+        e[i] = h
+        fd = (loss(solve(a + e, xs)[0]) - loss(solve(a - e, xs)[0])) / (2 * h)
+        errs.append(("tet", int(i), float(g[i]), fd))
+    S.close()
+    rel = [abs(ad - fd) / max(abs(fd), 1e-300) for _, _, ad, fd in errs]
+    return {"metric": "adjoint of a converged frame: backward ms and agreement with finite differences",
+            "workload": f"{sc.n} vertices, {sc.m} tets, {sc.m} actuation parameters",
+            "backward_ms": round(ms_bwd, 2), "loss": L0, "iters_targets": st_t["iters"],
+            "iters_frame": st_s["iters"], "max_rel_err_fd": max(rel),
+            "checks": [{"kind": k, "index": i, "adjoint": ad, "fd": fd} for k, i, ad, fd in errs]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +175,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="profile one path only (the JSON line then lacks the other)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint on the workload and check it against finite differences")
+    ap.add_argument("--serving", type=int, default=0, metavar="REQUESTS",
+                    help="replay a Poisson stream of this many requests through the server instead")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver has no multi-GPU path); got --gpus {args.gpus}",
@@ -128,7 +190,16 @@ def main():
     import meshgen as mg
     from paper_2312_02999_amd import FP64, MIXED_FP32
 
+    if args.serving:
+        from paper_2312_02999_amd import serve
+        for prec in (MIXED_FP32, FP64):
+            rep = serve.run_serving(n_requests=args.serving, precision=prec)
+            print(json.dumps({"metric": "serving: request latency and frames/s", **rep}), flush=True)
+        return
     sc = mg.scene_by_name(args.workload)
+    if args.adjoint:
+        print(json.dumps(run_adjoint(sc)))
+        return
     if args.only:
         r = run_precision(sc, FP64 if args.only == "fp64" else MIXED_FP32, args.steps, args.warmup, K_LOCAL)
         r.pop("x_final")
@@ -166,6 +237,14 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # scale the counters of the solver's kernels to bytes
+        a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8}))
 
 
 if __name__ == "__main__":

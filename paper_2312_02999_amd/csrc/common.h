@@ -16,6 +16,12 @@ struct M3 {
 };
 
 template <typename T>
+__device__ __forceinline__ T det3(const M3<T>& A) {
+  return A(0, 0) * (A(1, 1) * A(2, 2) - A(1, 2) * A(2, 1)) - A(0, 1) * (A(1, 0) * A(2, 2) - A(1, 2) * A(2, 0)) +
+         A(0, 2) * (A(1, 0) * A(2, 1) - A(1, 1) * A(2, 0));
+}
+
+template <typename T>
 __device__ __forceinline__ M3<T> mul(const M3<T>& A, const M3<T>& B) {
   M3<T> C;
 #pragma unroll

@@ -244,6 +244,7 @@ __global__ void __launch_bounds__(256) add_pair_vec_kernel(int32_t nsv, const in
   int32_t v = sv[i];
   if (fixed[v]) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
   for (int32_t t = ptr[v]; t < ptr[v + 1]; ++t) {
     int32_t k = ent[t] >> 2, a = ent[t] & 3;
     s0 += pv[static_cast<int64_t>(3 * a) * npairs + k];

@@ -72,7 +72,12 @@ __device__ __forceinline__ void sym_eig_jacobi5(T A[5][5], T V[5][5]) {
   }
 }
 
-template <typename T>
+// Barrier energy, gradient and the factor U (12 x 5) of the projected
+// Hessian, H+ = U U^T.  Geometry, derivatives and the projected 5 x 5 matrix
+// are formed in T; the 5 x 5 eigen-decomposition runs in TE (FP32 in the
+// mixed path: the cancellation-prone geometry, e.g. nearly parallel edges,
+// stays in FP64).
+template <typename T, typename TE = T>
 __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, double kappa, double& energy,
                              double grad[12], double U[12][5]) {
   T P[4][3];
@@ -209,10 +214,19 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
       Ht[a][b] = sm;
       Ht[b][a] = sm;
     }
-  sym_eig_jacobi5<T>(Ht, V);
+  TE He[5][5], Ve[5][5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int b = 0; b < 5; ++b) He[a][b] = static_cast<TE>(Ht[a][b]);
+  sym_eig_jacobi5<TE>(He, Ve);
   T sq[5];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) sq[a] = Ht[a][a] > T(0) ? sqrt(Ht[a][a]) : T(0);
+  for (int a = 0; a < 5; ++a) {
+    sq[a] = He[a][a] > TE(0) ? sqrt(static_cast<T>(He[a][a])) : T(0);
+#pragma unroll
+    for (int b = 0; b < 5; ++b) V[a][b] = static_cast<T>(Ve[a][b]);
+  }
 #pragma unroll
   for (int i = 0; i < 12; ++i)
 #pragma unroll
@@ -224,26 +238,6 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
     }
 }
 
-// FP64 barrier energy and gradient only
-__device__ void pair_energy_grad(const double P[4][3], bool is_pt, double dhat, double kappa, double& energy,
-                                 double grad[12]) {
-  Feature<double> f;
-  pair_feature<double>(is_pt, P, f);
-  double q[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) q[r] += f.c[j] * P[j][r];
-  const double D = dot3(q, q), d = sqrt(D);
-  const double e = d - dhat, lg = log(d / dhat);
-  const double b1 = -2.0 * e * lg - e * e / d;
-  const double phi1 = kappa * b1 / (2.0 * d);
-  energy = -kappa * e * e * lg;
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) grad[3 * j + r] = phi1 * 2.0 * f.c[j] * q[r];
-}
 
 __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
                                                      const double* __restrict__ x, double dhat, double kappa,
@@ -256,9 +250,9 @@ __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__
   load_pair_rel(v4, x, P);
   double e, g[12], u[12][5];
   if (fp32) {
-    // FP32 Hessian factor; energy and gradient (which fix the equilibrium) in FP64
-    pair_barrier<float>(P, k < n_pt, dhat, kappa, e, g, u);
-    pair_energy_grad(P, k < n_pt, dhat, kappa, e, g);
+    // FP32 eigen-decomposition of the projected Hessian; everything else,
+    // including the energy and gradient that fix the equilibrium, in FP64
+    pair_barrier<double, float>(P, k < n_pt, dhat, kappa, e, g, u);
   } else {
     pair_barrier<double>(P, k < n_pt, dhat, kappa, e, g, u);
   }
@@ -345,32 +339,44 @@ void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyD
 }
 
 // g[v] += sum of pair gradient rows at v (pair-ascending order), free v only
-__global__ void add_barrier_grad_kernel(int32_t nsv, const int32_t* __restrict__ sv, const int32_t* __restrict__ ptr,
-                                        const int32_t* __restrict__ ent, const double* __restrict__ grad,
-                                        int32_t npairs, const uint8_t* __restrict__ fixed, double* __restrict__ g) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// g[v] += sum of the pair gradient rows at v over its incidence entries (free
+// proxy vertices only): one wave per vertex, lanes over entries, then a
+// fixed-order wave sum.
+__global__ void __launch_bounds__(256) add_barrier_grad_kernel(int32_t nsv, const int32_t* __restrict__ sv,
+                                                               const int32_t* __restrict__ ptr,
+                                                               const int32_t* __restrict__ ent,
+                                                               const double* __restrict__ grad, int32_t npairs,
+                                                               const uint8_t* __restrict__ fixed,
+                                                               double* __restrict__ g) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * (256 / PDIPC_WAVE) + threadIdx.x / PDIPC_WAVE;
   if (i >= nsv) return;
-  int32_t v = sv[i];
-  if (fixed[v]) return;
-  int32_t b = ptr[v], e = ptr[v + 1];
-  if (e == b) return;
+  const int32_t v = sv[i];
+  const int32_t b = ptr[v], e = ptr[v + 1];
+  if (fixed[v] || e == b) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int32_t t = b; t < e; ++t) {
-    int32_t k = ent[t] >> 2, a = ent[t] & 3;
+#pragma unroll 4
+  for (int32_t t = b + lane; t < e; t += PDIPC_WAVE) {
+    const int32_t k = ent[t] >> 2, a = ent[t] & 3;
     s0 += grad[static_cast<int64_t>(3 * a) * npairs + k];
     s1 += grad[static_cast<int64_t>(3 * a + 1) * npairs + k];
     s2 += grad[static_cast<int64_t>(3 * a + 2) * npairs + k];
   }
-  g[3 * v] += s0;
-  g[3 * v + 1] += s1;
-  g[3 * v + 2] += s2;
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    g[3 * v] += s0;
+    g[3 * v + 1] += s1;
+    g[3 * v + 2] += s2;
+  }
 }
 
 void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
                              const uint8_t* fixed, double* g, hipStream_t st) {
   if (npairs <= 0) return;
-  add_barrier_grad_kernel<<<grid_for(px.nsv, 256), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent, bo.grad, npairs,
-                                                                   fixed, g);
+  add_barrier_grad_kernel<<<grid_for(px.nsv, 256 / PDIPC_WAVE), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent,
+                                                                                bo.grad, npairs, fixed, g);
 }
 
 // ---- reduced contact system ----------------------------------------------------------
@@ -465,6 +471,7 @@ __global__ void __launch_bounds__(256) bu_gather_kernel(int32_t nc, const int32_
   if (ca >= nc) return;
   const int32_t va = clist[ca];
   double s[3] = {0, 0, 0};
+#pragma unroll 4
   for (int32_t t = ptr[va] + lane; t < ptr[va + 1]; t += PDIPC_WAVE) {
     const int32_t k = ent[t] >> 2, la = ent[t] & 3;
     double wk[5];

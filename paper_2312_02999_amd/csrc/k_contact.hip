@@ -458,11 +458,19 @@ void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* 
 }
 
 // ---- line-search barrier energies -------------------------------------------------
+// Barrier energy of every candidate at x (dx == nullptr) or at x + alpha dx with
+// alpha = ls[LS_ALPHA] (no-op once the line search is decided), optionally as
+// a difference from E0.
 __global__ void __launch_bounds__(BT) pair_energy_kernel(const int32_t* __restrict__ v4all, int32_t npairs,
                                                          int32_t n_pt, const double* __restrict__ x,
-                                                         const double* __restrict__ dx, double alpha, double dhat,
-                                                         double kappa, const double* __restrict__ E0,
-                                                         double* __restrict__ out) {
+                                                         const double* __restrict__ dx,
+                                                         const double* __restrict__ ls, double dhat, double kappa,
+                                                         const double* __restrict__ E0, double* __restrict__ out) {
+  double alpha = 0.0;
+  if (ls) {
+    if (ls[LS_STATE] != 0.0) return;
+    alpha = ls[LS_ALPHA];
+  }
   int32_t k = blockIdx.x * BT + threadIdx.x;
   if (k >= npairs) return;
   int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
@@ -477,10 +485,10 @@ __global__ void __launch_bounds__(BT) pair_energy_kernel(const int32_t* __restri
 }
 
 void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
-                                double alpha, double dhat, double kappa, const double* E0, double* out,
+                                const double* ls, double dhat, double kappa, const double* E0, double* out,
                                 hipStream_t st) {
   if (npairs <= 0) return;
-  pair_energy_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, alpha, dhat, kappa, E0, out);
+  pair_energy_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, ls, dhat, kappa, E0, out);
 }
 
 __global__ void __launch_bounds__(BT) pair_d2_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,

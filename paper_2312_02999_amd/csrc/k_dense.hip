@@ -78,8 +78,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
 
 // ---- Cholesky -----------------------------------------------------------------
 // Right-looking with 64-wide blocks.  Outputs: L (lower, row-major), its
-// transpose Lt (upper, row-major) and the reciprocals of the diagonal, dinv;
-// Lt and dinv share the auxiliary buffer (n*n + n entries).  A is the
+// transpose Lt (upper, row-major), the reciprocals of the diagonal, dinv, and
+// the inverses of the 64 x 64 diagonal blocks (for the solves); Lt, dinv and
+// the block inverses share the auxiliary buffer (dense_aux_size entries).  A is the
 // workspace (its lower tiles are destroyed).  Per block step k:
 //   panel:  L_ik = A_ik L_kk^-T for every block row i > k (one wave per block
 //           row, forward substitution with the row held in registers);
@@ -101,7 +102,13 @@ struct MfmaVec<float> {
 };
 
 // D (16x16) += A (16x4) B (4x16); lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16] and holds D[4 (l / 16) + q][l % 16] in element q.
+// B[l / 16][l % 16] and holds column l % 16 of D.  Element q of its result is
+// row 4 (l / 16) + q for the FP32 instruction and row l / 16 + 4 q for the
+// FP64 one (both checked on the device).
+template <typename T>
+__device__ __forceinline__ int mfma_row(int lk, int q) {
+  return sizeof(T) == 8 ? lk + 4 * q : 4 * lk + q;
+}
 __device__ __forceinline__ MfmaVec<double>::type mfma16x16x4(double a, double b, MfmaVec<double>::type c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -141,11 +148,12 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
 // The unrolled loop is kept free of branches (failure is tracked by selects)
 // so that the row stays in registers; W is overwritten with the factor and
 // copied out afterwards.
-template <typename T>
+template <typename T, int NB>
 __device__ __forceinline__ void factor_diag_wave(T (*W)[NB + 1], int kb, int64_t k0, int64_t n, T* __restrict__ L,
                                  T* __restrict__ Lt, T* __restrict__ dinv, int32_t* __restrict__ info,
                                  T* __restrict__ colbuf) {
   const int lane = threadIdx.x;
+  if (lane >= NB) return;
   T a[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) a[c] = W[lane][c];
@@ -179,7 +187,7 @@ __device__ __forceinline__ void factor_diag_wave(T (*W)[NB + 1], int kb, int64_t
   if (lane < kb) dinv[k0 + lane] = colbuf[lane];
 }
 
-template <typename T>
+template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ L,
                                                          T* __restrict__ Lt, T* __restrict__ dinv,
                                                          int32_t* __restrict__ info) {
@@ -187,17 +195,19 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
   __shared__ T colbuf[NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
   if (threadIdx.x == 0) *info = 0;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+  #pragma unroll
+  for (int it = 0; it < NB * NB / 256; ++it) {
+    const int idx = threadIdx.x + 256 * it;
     const int r = idx / NB, c = idx % NB;
     W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
   }
   __syncthreads();
-  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
+  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T, NB>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
 }
 
 // v <- L_kk^-1 v for the register vector v (lane-private), with LkT[c][r] =
 // L_kk[r][c] and dk = 1 / diag(L_kk) in LDS.
-template <typename T>
+template <typename T, int NB>
 __device__ __forceinline__ void forward_subst_regs(T v[NB], const T (*LkT)[NB + 1], const T* dk) {
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
@@ -209,7 +219,7 @@ __device__ __forceinline__ void forward_subst_regs(T v[NB], const T (*LkT)[NB + 
 }
 
 // Panel of block column k: row gr of block row i solves L_kk p = A[gr, k-block]^T.
-template <typename T>
+template <typename T, int NB>
 __global__ void __launch_bounds__(64) chol_panel_kernel(const T* __restrict__ A, int64_t n, int64_t k,
                                                         T* __restrict__ L, T* __restrict__ Lt,
                                                         const T* __restrict__ dinv) {
@@ -218,15 +228,18 @@ __global__ void __launch_bounds__(64) chol_panel_kernel(const T* __restrict__ A,
   const int lane = threadIdx.x;
   const int64_t k0 = k * NB;
   // L_kk is a full block (k < nblk - 1); its transpose is row block k of Lt
-  for (int c = 0; c < NB; ++c) LkT[c][lane] = (lane >= c) ? Lt[(k0 + c) * n + k0 + lane] : T(0);
-  dk[lane] = dinv[k0 + lane];
+  if (lane < NB) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) LkT[c][lane] = (lane >= c) ? Lt[(k0 + c) * n + k0 + lane] : T(0);
+    dk[lane] = dinv[k0 + lane];
+  }
   __syncthreads();
   const int64_t gr = (k + 1 + blockIdx.x) * NB + lane;
-  if (gr >= n) return;
+  if (lane >= NB || gr >= n) return;
   T v[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) v[c] = A[gr * n + k0 + c];
-  forward_subst_regs<T>(v, LkT, dk);
+  forward_subst_regs<T, NB>(v, LkT, dk);
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     L[gr * n + k0 + c] = v[c];
@@ -236,7 +249,7 @@ __global__ void __launch_bounds__(64) chol_panel_kernel(const T* __restrict__ A,
 
 // Trailing update of tile (bi, bj), k < bj <= bi, on the matrix cores; the
 // workgroup of tile (k+1, k+1) factors it afterwards.
-template <typename T>
+template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int64_t n, int64_t k,
                                                           T* __restrict__ L, T* __restrict__ Lt,
                                                           T* __restrict__ dinv, int32_t* __restrict__ info) {
@@ -251,115 +264,156 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   while (t >= m - ii) { t -= m - ii; ++ii; }
   const int64_t bj = k + 1 + ii, bi = bj + t;
   const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+  #pragma unroll
+  for (int it = 0; it < NB * NB / 256; ++it) {
+    const int idx = threadIdx.x + 256 * it;
     const int p = idx / NB, r = idx % NB;
     const T* row = Lt + (k0 + p) * n;
     Ta[p][r] = (i0 + r < n) ? row[i0 + r] : T(0);
     Tb[p][r] = (j0 + r < n) ? row[j0 + r] : T(0);
   }
   __syncthreads();
-  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
-  const int rb = 32 * (w / 2), cb = 32 * (w % 2);
-  const int lr = lane % 16, lk = lane / 16;
-  typename MfmaVec<T>::type acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
-#pragma unroll 4
-  for (int p0 = 0; p0 < NB; p0 += 4) {
-    const T a0 = Ta[p0 + lk][rb + lr], a1 = Ta[p0 + lk][rb + 16 + lr];
-    const T b0 = Tb[p0 + lk][cb + lr], b1 = Tb[p0 + lk][cb + 16 + lr];
-    acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
-    acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
-    acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
-    acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
-  }
   const bool last = (bi == k + 1) && (bj == k + 1);
-  if (last) __syncthreads();      // Ta/Tb are overwritten by W below
+  // write back A_ij - acc (or stage it in W for the factorisation)
+  auto put = [&](int r, int c, T acc_rc) {
+    const int64_t gr = i0 + r, gc = j0 + c;
+    if (gr < n && gc < n) {
+      const T v = A[gr * n + gc] - acc_rc;
+      if (last) W[r][c] = v;
+      else A[gr * n + gc] = v;
+    } else if (last) {
+      W[r][c] = (r == c) ? T(1) : T(0);
+    }
+  };
+  {
+    // matrix cores: wave w owns an NB/2 x NB/2 quadrant as TL x TL tiles of
+    // 16 x 16 (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64)
+    constexpr int TL = NB / 32;
+    const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+    const int rb = (NB / 2) * (w / 2), cb = (NB / 2) * (w % 2);
+    const int lr = lane % 16, lk = lane / 16;
+    typename MfmaVec<T>::type acc[TL][TL];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < TL; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < TL; ++y) acc[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+    for (int p0 = 0; p0 < NB; p0 += 4) {
+      T av[TL], bv[TL];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = rb + 16 * x + 4 * lk + q, c = cb + 16 * y + lr;
-        const int64_t gr = i0 + r, gc = j0 + c;
-        if (gr < n && gc < n) {
-          const T v = A[gr * n + gc] - acc[x][y][q];
-          if (last) W[r][c] = v;
-          else A[gr * n + gc] = v;
-        } else if (last) {
-          W[r][c] = (r == c) ? T(1) : T(0);
-        }
+      for (int x = 0; x < TL; ++x) {
+        av[x] = Ta[p0 + lk][rb + 16 * x + lr];
+        bv[x] = Tb[p0 + lk][cb + 16 * x + lr];
       }
+#pragma unroll
+      for (int x = 0; x < TL; ++x)
+#pragma unroll
+        for (int y = 0; y < TL; ++y) acc[x][y] = mfma16x16x4(av[x], bv[y], acc[x][y]);
+    }
+    if (last) __syncthreads();      // Ta/Tb are overwritten by W below
+#pragma unroll
+    for (int x = 0; x < TL; ++x)
+#pragma unroll
+      for (int y = 0; y < TL; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) put(rb + 16 * x + mfma_row<T>(lk, q), cb + 16 * y + lr, acc[x][y][q]);
+  }
   if (!last) return;
   __syncthreads();
   const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
-  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
+  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T, NB>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
+}
+
+
+// ---- inverses of the diagonal blocks (one wave per block, all blocks at once) --
+// Lane c holds column c of L_kk^-1 in registers and forms it by forward
+// substitution; rows/columns beyond the matrix are the identity.
+template <typename T, int NB>
+__global__ void __launch_bounds__(64) chol_diaginv_kernel(const T* __restrict__ Lt, const T* __restrict__ dinv,
+                                                          int64_t n, T* __restrict__ Dinv) {
+  __shared__ T LkT[NB][NB + 1];
+  __shared__ T dk[NB];
+  const int lane = threadIdx.x;
+  const int64_t k0 = static_cast<int64_t>(blockIdx.x) * NB;
+  const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
+  if (lane < NB) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      LkT[c][lane] = (c < kb && lane < kb) ? (lane >= c ? Lt[(k0 + c) * n + k0 + lane] : T(0)) : T(0);
+    dk[lane] = lane < kb ? dinv[k0 + lane] : T(1);
+  }
+  __syncthreads();
+  if (lane >= NB) return;
+  T v[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) v[r] = (r == lane) ? T(1) : T(0);
+  forward_subst_regs<T, NB>(v, LkT, dk);
+  T* D = Dinv + static_cast<int64_t>(blockIdx.x) * NB * NB;
+#pragma unroll
+  for (int r = 0; r < NB; ++r) D[r * NB + lane] = v[r];
+}
+
+// Block size: 32 keeps the serial chain of diagonal factorisations short for
+// the reduced systems of a few thousand unknowns; 64 feeds the matrix cores
+// better above that.  Factor, solves and inverse must agree on it.
+static int dense_block(int64_t n) { return n <= 2048 ? 32 : 64; }
+
+template <typename T, int NB>
+static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
+  T* Lt = aux;
+  T* dinv = aux + n * n;
+  const int64_t nblk = (n + NB - 1) / NB;
+  chol_first_kernel<T, NB><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, d_info);
+  const size_t shm = sizeof(T) * 2 * NB * NB;
+  for (int64_t k = 0; k + 1 < nblk; ++k) {
+    const int64_t m = nblk - k - 1;
+    chol_panel_kernel<T, NB><<<static_cast<unsigned>(m), 64, 0, st>>>(A, n, k, L, Lt, dinv);
+    chol_update_kernel<T, NB><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Lt, dinv,
+                                                                                         d_info);
+  }
+  chol_diaginv_kernel<T, NB><<<static_cast<unsigned>(nblk), 64, 0, st>>>(Lt, dinv, n, aux + n * n + n);
 }
 
 template <typename T>
 void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
   if (n <= 0) return;
-  T* Lt = aux;
-  T* dinv = aux + n * n;
-  const int64_t nblk = (n + NB - 1) / NB;
-  chol_first_kernel<T><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, d_info);
-  const size_t shm = sizeof(T) * 2 * NB * NB;
-  for (int64_t k = 0; k + 1 < nblk; ++k) {
-    const int64_t m = nblk - k - 1;
-    chol_panel_kernel<T><<<static_cast<unsigned>(m), 64, 0, st>>>(A, n, k, L, Lt, dinv);
-    chol_update_kernel<T><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Lt, dinv, d_info);
-  }
+  if (dense_block(n) == 32) dense_cholesky_nb<T, 32>(A, n, L, aux, d_info, st);
+  else dense_cholesky_nb<T, 64>(A, n, L, aux, d_info, st);
 }
 
-// ---- solves: one workgroup, diagonal blocks by one wave, the rest coalesced -----
-template <typename T>
-__global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
-                                                          const T* __restrict__ dinv, int64_t n, T* __restrict__ b,
+// ---- solves: one workgroup; diagonal blocks by their inverses, the rest coalesced
+template <typename T, int NB>
+__global__ void __launch_bounds__(512) chol_solve_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
+                                                          const T* __restrict__ Dinv, int64_t n, T* __restrict__ b,
                                                           int nrhs) {
-  __shared__ T Lk[NB][NB + 1];
+  __shared__ T Di[NB][NB + 1];
+  __shared__ T ts[NB][4];
   __shared__ T ys[NB][4];
-  __shared__ T dk[NB];
-  const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t nblk = (n + NB - 1) / NB;
   // forward: L y = b
   for (int64_t bk = 0; bk < nblk; ++bk) {
     const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      const int r = idx / NB, c = idx % NB;
-      Lk[r][c] = (r < kb && c <= r) ? L[(k0 + r) * n + k0 + c] : T(0);
+    const T* D = Dinv + bk * NB * NB;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += 512) Di[idx / NB][idx % NB] = D[idx];
+    if (threadIdx.x < NB * 4) {
+      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
+      ts[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] : T(0);
     }
-    if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
     __syncthreads();
-    if (threadIdx.x < PDIPC_WAVE) {
-      T tq[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) tq[q] = (lane < kb && q < nrhs) ? b[(k0 + lane) * nrhs + q] : T(0);
-      for (int i = 0; i < kb; ++i) {
-        const T di = dk[i], lv = Lk[lane][i];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q < nrhs) {
-            const T y = read_lane(tq[q], i) * di;
-            if (lane == i) tq[q] = y;
-            else if (lane > i) tq[q] -= lv * y;
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ys[lane][q] = tq[q];
-        if (lane < kb && q < nrhs) b[(k0 + lane) * nrhs + q] = tq[q];
-      }
+    if (threadIdx.x < NB * 4) {
+      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
+      T acc = T(0);
+      for (int c = 0; c <= r; ++c) acc += Di[r][c] * ts[c][q];
+      ys[r][q] = acc;
+      if (r < kb && q < nrhs) b[(k0 + r) * nrhs + q] = acc;
     }
     __syncthreads();
     for (int64_t gr = k0 + kb + threadIdx.x; gr < n; gr += blockDim.x) {
       T s[4] = {T(0), T(0), T(0), T(0)};
-      for (int c = 0; c < kb; ++c) {
-        const T l = Lt[(k0 + c) * n + gr];
+#pragma unroll 8
+      for (int c = 0; c < NB; ++c) {
+        const T l = c < kb ? Lt[(k0 + c) * n + gr] : T(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) s[q] += l * ys[c][q];
       }
@@ -371,38 +425,26 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
   for (int64_t bk = nblk - 1; bk >= 0; --bk) {
     const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-      const int r = idx / NB, c = idx % NB;
-      Lk[r][c] = (r < kb && c <= r) ? L[(k0 + r) * n + k0 + c] : T(0);
+    const T* D = Dinv + bk * NB * NB;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += 512) Di[idx / NB][idx % NB] = D[idx];
+    if (threadIdx.x < NB * 4) {
+      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
+      ts[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] : T(0);
     }
-    if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
     __syncthreads();
-    if (threadIdx.x < PDIPC_WAVE) {
-      T tq[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) tq[q] = (lane < kb && q < nrhs) ? b[(k0 + lane) * nrhs + q] : T(0);
-      for (int i = kb - 1; i >= 0; --i) {
-        const T di = dk[i], lv = Lk[i][lane];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q < nrhs) {
-            const T x = read_lane(tq[q], i) * di;
-            if (lane == i) tq[q] = x;
-            else if (lane < i) tq[q] -= lv * x;
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ys[lane][q] = tq[q];
-        if (lane < kb && q < nrhs) b[(k0 + lane) * nrhs + q] = tq[q];
-      }
+    if (threadIdx.x < NB * 4) {
+      const int c = threadIdx.x / 4, q = threadIdx.x % 4;
+      T acc = T(0);
+      for (int r = c; r < NB; ++r) acc += Di[r][c] * ts[r][q];
+      ys[c][q] = acc;
+      if (c < kb && q < nrhs) b[(k0 + c) * nrhs + q] = acc;
     }
     __syncthreads();
     for (int64_t gc = threadIdx.x; gc < k0; gc += blockDim.x) {
       T s[4] = {T(0), T(0), T(0), T(0)};
-      for (int c = 0; c < kb; ++c) {
-        const T l = L[(k0 + c) * n + gc];
+#pragma unroll 8
+      for (int c = 0; c < NB; ++c) {
+        const T l = c < kb ? L[(k0 + c) * n + gc] : T(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) s[q] += l * ys[c][q];
       }
@@ -415,7 +457,8 @@ __global__ void __launch_bounds__(1024) chol_solve_kernel(const T* __restrict__ 
 template <typename T>
 void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
   if (n <= 0) return;
-  chol_solve_kernel<T><<<1, 1024, 0, st>>>(L, aux, aux + n * n, n, b, nrhs);
+  if (dense_block(n) == 32) chol_solve_kernel<T, 32><<<1, 512, 0, st>>>(L, aux, aux + n * n + n, n, b, nrhs);
+  else chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(L, aux, aux + n * n + n, n, b, nrhs);
 }
 
 // ---- Y = L^-1, one workgroup per 64-column block -------------------------------
@@ -423,7 +466,7 @@ void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, h
 // L_kp Y_pj); the sum is staged through LDS, the diagonal solve is done by one
 // wave with each lane holding one column in registers.  Blocks above the
 // diagonal are zeroed.
-template <typename T>
+template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
                                                         const T* __restrict__ dinv, int64_t n, T* __restrict__ Y) {
   __shared__ T Ls[NB][NB + 1];
@@ -437,16 +480,19 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
     const int c = threadIdx.x % NB;
     if (c < jb) Y[r * n + j0 + c] = T(0);
   }
-  const int tr = threadIdx.x / 4, tq = threadIdx.x % 4;     // row tr, columns 16 tq .. 16 tq + 15
+  constexpr int TPR = 256 / NB, CPT = NB / TPR;               // threads per row, columns per thread
+  const int tr = threadIdx.x / TPR, tq = threadIdx.x % TPR;   // row tr, columns CPT tq .. CPT tq + CPT - 1
   for (int64_t bk = bj; bk < nblk; ++bk) {
     const int64_t k0 = bk * NB;
     const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    T acc[16];
+    T acc[CPT];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = (bk == bj && tr == 16 * tq + c) ? T(1) : T(0);
+    for (int c = 0; c < CPT; ++c) acc[c] = (bk == bj && tr == CPT * tq + c) ? T(1) : T(0);
     for (int64_t bp = bj; bp < bk; ++bp) {
       const int64_t p0 = bp * NB;
-      for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+      #pragma unroll
+      for (int it = 0; it < NB * NB / 256; ++it) {
+        const int idx = threadIdx.x + 256 * it;
         const int r = idx / NB, c = idx % NB;
         Ls[r][c] = (r < kb) ? L[(k0 + r) * n + p0 + c] : T(0);
         Ys[r][c] = (c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
@@ -455,30 +501,34 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
       for (int s = 0; s < NB; ++s) {
         const T l = Ls[tr][s];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] -= l * Ys[s][16 * tq + c];
+        for (int c = 0; c < CPT; ++c) acc[c] -= l * Ys[s][CPT * tq + c];
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Tm[tr][16 * tq + c] = acc[c];
+    for (int c = 0; c < CPT; ++c) Tm[tr][CPT * tq + c] = acc[c];
     // LkT[c][r] = L_kk[r][c] (reusing Ls), identity-padded
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    #pragma unroll
+      for (int it = 0; it < NB * NB / 256; ++it) {
+        const int idx = threadIdx.x + 256 * it;
       const int c = idx / NB, r = idx % NB;
       Ls[c][r] = (r < kb && c < kb) ? (r >= c ? Lt[(k0 + c) * n + k0 + r] : T(0)) : (r == c ? T(1) : T(0));
     }
     if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
     __syncthreads();
-    if (threadIdx.x < PDIPC_WAVE) {
+    if (threadIdx.x < NB) {
       const int c = threadIdx.x;
       T v[NB];
 #pragma unroll
       for (int r = 0; r < NB; ++r) v[r] = Tm[r][c];
-      forward_subst_regs<T>(v, Ls, dk);
+      forward_subst_regs<T, NB>(v, Ls, dk);
 #pragma unroll
       for (int r = 0; r < NB; ++r) Tm[r][c] = v[r];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+    #pragma unroll
+      for (int it = 0; it < NB * NB / 256; ++it) {
+        const int idx = threadIdx.x + 256 * it;
       const int r = idx / NB, c = idx % NB;
       if (r < kb && c < jb) Y[(k0 + r) * n + j0 + c] = Tm[r][c];
     }
@@ -489,9 +539,12 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
 template <typename T>
 void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st) {
   if (n <= 0) return;
-  const unsigned nblk = grid_for(n, NB);
-  chol_linv_kernel<T><<<nblk, 256, 0, st>>>(L, aux, aux + n * n, n, work);
-  dim3 grid(nblk, nblk);
+  if (dense_block(n) == 32)
+    chol_linv_kernel<T, 32><<<grid_for(n, 32), 256, 0, st>>>(L, aux, aux + n * n, n, work);
+  else
+    chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, aux, aux + n * n, n, work);
+  const unsigned g = grid_for(n, 64);
+  dim3 grid(g, g);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
 }
 

@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(FT) fwd_gather_kernel(FactorDev f, int32_t row
   if (k >= nrows) return;
   const int64_t row = f.lvl_rows[row0 + k];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int64_t e = f.fwd_ptr[row] + lane; e < f.fwd_ptr[row + 1]; e += PDIPC_WAVE) {
     int32_t c = f.fwd_col[e];
     double v = f.fwd_val[e];
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(FT) fwd_diag_kernel(FactorDev f, int32_t row0,
   const int32_t r = static_cast<int32_t>(row - c0);
   const double* D = f.dinv + f.node_dinv_off[J] + static_cast<int64_t>(r) * s;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int32_t c = lane; c <= r; c += PDIPC_WAVE) {
     double d = D[c];
     a0 += d * t[3 * (c0 + c)];
@@ -101,6 +103,7 @@ __global__ void __launch_bounds__(FT) fwd_x2_kernel(FactorDev f, const double* _
   if (q >= f.n2) return;
   const int64_t row = f.n1 + q;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int64_t e = f.fwd_ptr[row] + lane; e < f.fwd_ptr[row + 1]; e += PDIPC_WAVE) {
     int32_t c = f.fwd_col[e];
     double v = f.fwd_val[e];
@@ -136,6 +139,7 @@ __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double
   if (i >= n2) return;
   const double* Si = S + i * n2;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int64_t j = lane; j < n2; j += PDIPC_WAVE) {
     double v = Si[j];
     a0 += v * r[3 * j];
@@ -168,6 +172,7 @@ __global__ void __launch_bounds__(FT) bwd_gather_kernel(FactorDev f, int32_t row
   const double* P = f.panelT + f.node_panel_off[J] + static_cast<int64_t>(c) * r;
   const int32_t* R = f.rows + f.node_rows_off[J];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int32_t i = lane; i < r; i += PDIPC_WAVE) {
     double v = P[i];
     int64_t q = R[i];
@@ -195,6 +200,7 @@ __global__ void __launch_bounds__(FT) bwd_diag_kernel(FactorDev f, int32_t row0,
   const int32_t c = static_cast<int32_t>(col - c0);
   const double* DT = f.dinvT + f.node_dinv_off[J] + static_cast<int64_t>(c) * s;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int32_t rr = c + lane; rr < s; rr += PDIPC_WAVE) {
     double d = DT[rr];
     a0 += d * t[3 * (c0 + rr)];

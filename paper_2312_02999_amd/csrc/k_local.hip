@@ -148,6 +148,81 @@ __device__ void refine_rotation(const M3<double>& M, M3<double>& R) {
   R = mul(R, Q);
 }
 
+// Warm-started nearest rotation in FP64: Newton steps on SO(3) from R (the
+// rotation of the same tet at a nearby state).  With S = R^T M, the update
+// solves (tr(S) I - sym(S)) w = a(S) and applies R <- R cay(w), where the
+// Cayley map cay(w) = I + 2 ([v]x + [v]x^2) / (1 + |v|^2), v = w / 2, is
+// orthogonal and agrees with exp([w]x) to second order, so convergence stays
+// quadratic.  Returns false (R unusable) unless the iteration converged to the
+// maximiser of tr(R^T M): there tr(S) I - sym(S) is positive definite.
+__device__ __forceinline__ bool polar_warm(const M3<double>& M, M3<double>& R) {
+  // one Newton-Schulz step removes drift from orthogonality: R (3 I - R^T R) / 2
+  {
+    M3<double> RtR;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) RtR(i, j) = R(0, i) * R(0, j) + R(1, i) * R(1, j) + R(2, i) * R(2, j);
+    M3<double> Rn;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Rn(i, j) = 1.5 * R(i, j) - 0.5 * (R(i, 0) * RtR(0, j) + R(i, 1) * RtR(1, j) + R(i, 2) * RtR(2, j));
+    // the start must already be a rotation up to rounding drift
+    double dev = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dev = fmax(dev, fabs(RtR(i, j) - (i == j ? 1.0 : 0.0)));
+    if (!(dev < 1e-6) || !(det3(Rn) > 0.0)) return false;
+    R = Rn;
+  }
+  const double scale = fabs(M(0, 0)) + fabs(M(1, 1)) + fabs(M(2, 2)) + fabs(M(0, 1)) + fabs(M(1, 0)) +
+                       fabs(M(0, 2)) + fabs(M(2, 0)) + fabs(M(1, 2)) + fabs(M(2, 1));
+  if (!(scale > 0.0)) return false;
+  bool conv = false;
+  double b00 = 0, b11 = 0, b22 = 0, b01 = 0, b02 = 0, b12 = 0;
+#pragma unroll 1
+  for (int it = 0; it < 5; ++it) {
+    double S[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) S[i][j] = R(0, i) * M(0, j) + R(1, i) * M(1, j) + R(2, i) * M(2, j);
+    const double av[3] = {S[2][1] - S[1][2], S[0][2] - S[2][0], S[1][0] - S[0][1]};
+    const double tr = S[0][0] + S[1][1] + S[2][2];
+    b00 = tr - S[0][0]; b11 = tr - S[1][1]; b22 = tr - S[2][2];
+    b01 = -0.5 * (S[0][1] + S[1][0]); b02 = -0.5 * (S[0][2] + S[2][0]); b12 = -0.5 * (S[1][2] + S[2][1]);
+    const double c00 = b11 * b22 - b12 * b12, c01 = b02 * b12 - b01 * b22, c02 = b01 * b12 - b02 * b11;
+    const double c11 = b00 * b22 - b02 * b02, c12 = b01 * b02 - b00 * b12, c22 = b00 * b11 - b01 * b01;
+    const double det = b00 * c00 + b01 * c01 + b02 * c02;
+    if (!(det > 0.0)) return false;
+    const double id = 1.0 / det;
+    const double w0 = (c00 * av[0] + c01 * av[1] + c02 * av[2]) * id;
+    const double w1 = (c01 * av[0] + c11 * av[1] + c12 * av[2]) * id;
+    const double w2 = (c02 * av[0] + c12 * av[1] + c22 * av[2]) * id;
+    const double wn = fabs(w0) + fabs(w1) + fabs(w2);
+    if (!(wn < 1.0)) return false;                 // too far from the basin
+    const double v0 = 0.5 * w0, v1 = 0.5 * w1, v2 = 0.5 * w2;
+    const double f = 2.0 / (1.0 + v0 * v0 + v1 * v1 + v2 * v2);
+    M3<double> K, Q;
+    K(0, 0) = 0.0; K(0, 1) = -v2; K(0, 2) = v1;
+    K(1, 0) = v2; K(1, 1) = 0.0; K(1, 2) = -v0;
+    K(2, 0) = -v1; K(2, 1) = v0; K(2, 2) = 0.0;
+    M3<double> K2 = mul(K, K);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Q(i, j) = (i == j ? 1.0 : 0.0) + f * (K(i, j) + K2(i, j));
+    R = mul(R, Q);
+    if (wn < 1e-9) { conv = true; break; }         // the step just taken is below 1e-18 next
+  }
+  if (!conv || !(det3(R) > 0.5)) return false;
+  // maximiser test on the last system matrix: leading minors positive
+  return b00 > 0.0 && b00 * b11 - b01 * b01 > 0.0;
+}
+
 struct TetStreams {
   const int32_t* tets;   // 4 x m
   const double* B;       // 9 x m, D_m^-1 row-major entries
@@ -181,10 +256,31 @@ __device__ __forceinline__ void load_tet(const TetStreams& ts, int64_t m, int64_
 
 // Writes per tet: R (9 x m, optional), energy (m), gradient share (12 x m,
 // entry 3a + r for local vertex a, coordinate r).
+// Rotation of tet i at deformation M: warm-started FP64 Newton from Rwarm
+// (if given), else (or if that fails) Jacobi in TP, refined in FP64 when TP
+// is FP32.
+template <typename TP>
+__device__ __forceinline__ void tet_rotation(const M3<double>& M, const double* __restrict__ Rwarm, int64_t m,
+                                             int64_t i, M3<double>& R) {
+  if (Rwarm) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) R.a[e] = Rwarm[e * m + i];
+    if (polar_warm(M, R)) return;
+  }
+  M3<TP> Mt, Rt;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) Mt.a[e] = static_cast<TP>(M.a[e]);
+  nearest_rotation<TP>(Mt, Rt);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) R.a[e] = static_cast<double>(Rt.a[e]);
+  if (sizeof(TP) < sizeof(double)) refine_rotation(M, R);
+}
+
+// Rwarm may alias Rout (each thread reads its own tet before writing it).
 template <typename TP>
 __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t m, const double* __restrict__ x,
-                                                         double* __restrict__ Rout, double* __restrict__ energy,
-                                                         double* __restrict__ tetg) {
+                                                         const double* Rwarm, double* Rout,
+                                                         double* __restrict__ energy, double* __restrict__ tetg) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
   M3<double> F, A, Bm;
@@ -192,14 +288,8 @@ __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t 
   int32_t v[4];
   load_tet(ts, m, i, x, F, A, w, v, Bm);
   M3<double> M = mul(F, A);
-  M3<TP> Mt, Rt;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) Mt.a[e] = static_cast<TP>(M.a[e]);
-  nearest_rotation<TP>(Mt, Rt);
   M3<double> R;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) R.a[e] = static_cast<double>(Rt.a[e]);
-  if (sizeof(TP) < sizeof(double)) refine_rotation(M, R);
+  tet_rotation<TP>(M, Rwarm, m, i, R);
   M3<double> P = mul(R, A);
   double res[9];
   double e2 = 0.0;
@@ -232,11 +322,17 @@ __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t 
 }
 
 // Element energies at x + alpha dx (line-search trial), as differences from
-// the energies at x: out[i] = E_i(x + alpha dx) - E0[i].
+// the energies at x: out[i] = E_i(x + alpha dx) - E0[i].  alpha is ls[LS_ALPHA]
+// of the device line-search state; a decided search (ls[LS_STATE] != 0)
+// makes the launch a no-op.
 template <typename TP>
 __global__ void __launch_bounds__(256) trial_energy_kernel(TetStreams ts, int64_t m, const double* __restrict__ x,
-                                                           const double* __restrict__ dx, double alpha,
+                                                           const double* __restrict__ dx,
+                                                           const double* __restrict__ ls,
+                                                           const double* __restrict__ Rwarm,
                                                            const double* __restrict__ E0, double* __restrict__ dE) {
+  if (ls[LS_STATE] != 0.0) return;
+  const double alpha = ls[LS_ALPHA];
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
   int32_t v[4];
@@ -263,14 +359,8 @@ __global__ void __launch_bounds__(256) trial_energy_kernel(TetStreams ts, int64_
   A(1, 2) = A(2, 1) = a6[4];
   A(2, 0) = A(0, 2) = a6[5];
   M3<double> M = mul(F, A);
-  M3<TP> Mt, Rt;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) Mt.a[e] = static_cast<TP>(M.a[e]);
-  nearest_rotation<TP>(Mt, Rt);
   M3<double> R;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) R.a[e] = static_cast<double>(Rt.a[e]);
-  if (sizeof(TP) < sizeof(double)) refine_rotation(M, R);
+  tet_rotation<TP>(M, Rwarm, m, i, R);
   M3<double> P = mul(R, A);
   double e2 = 0.0;
 #pragma unroll
@@ -292,6 +382,7 @@ __global__ void __launch_bounds__(256) gather_vertex_grad_kernel(int32_t n, int6
   if (v >= n) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (!fixed[v]) {
+#pragma unroll 4
     for (int32_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
       int32_t ent = vt_ent[e];
       int64_t t = ent >> 2;
@@ -336,24 +427,34 @@ __global__ void actuation_transpose_kernel(int64_t m, const double* __restrict__
 }
 
 // ---- launchers --------------------------------------------------------------
-void launch_local_step(const LocalArgs& la, const double* x, double* Rout, double* energy, double* tetg,
-                       bool fp32, hipStream_t st) {
+void launch_local_step(const LocalArgs& la, const double* x, const double* Rwarm, double* Rout, double* energy,
+                       double* tetg, bool fp32, hipStream_t st) {
   TetStreams ts{la.tets, la.B, la.w, la.A};
   unsigned g = grid_for(la.m, 256);
   if (fp32)
-    local_step_kernel<float><<<g, 256, 0, st>>>(ts, la.m, x, Rout, energy, tetg);
+    local_step_kernel<float><<<g, 256, 0, st>>>(ts, la.m, x, Rwarm, Rout, energy, tetg);
   else
-    local_step_kernel<double><<<g, 256, 0, st>>>(ts, la.m, x, Rout, energy, tetg);
+    local_step_kernel<double><<<g, 256, 0, st>>>(ts, la.m, x, Rwarm, Rout, energy, tetg);
 }
 
-void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, double alpha, const double* E0,
-                         double* dE, bool fp32, hipStream_t st) {
+void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, const double* ls,
+                         const double* Rwarm, const double* E0, double* dE, bool fp32, hipStream_t st) {
   TetStreams ts{la.tets, la.B, la.w, la.A};
   unsigned g = grid_for(la.m, 256);
   if (fp32)
-    trial_energy_kernel<float><<<g, 256, 0, st>>>(ts, la.m, x, dx, alpha, E0, dE);
+    trial_energy_kernel<float><<<g, 256, 0, st>>>(ts, la.m, x, dx, ls, Rwarm, E0, dE);
   else
-    trial_energy_kernel<double><<<g, 256, 0, st>>>(ts, la.m, x, dx, alpha, E0, dE);
+    trial_energy_kernel<double><<<g, 256, 0, st>>>(ts, la.m, x, dx, ls, Rwarm, E0, dE);
+}
+
+__global__ void identity_rotations_kernel(int64_t m, double* __restrict__ R) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) R[e * m + i] = (e % 4 == 0) ? 1.0 : 0.0;
+}
+void launch_identity_rotations(int64_t m, double* R, hipStream_t st) {
+  if (m > 0) identity_rotations_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, R);
 }
 
 void launch_gather_vertex_grad(int32_t n, int64_t m, const int32_t* vt_ptr, const int32_t* vt_ent,

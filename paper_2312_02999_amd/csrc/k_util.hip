@@ -108,7 +108,9 @@ __device__ double block_sum(double v) {
 
 __global__ void __launch_bounds__(RED_T) sum_partial_kernel(const double* __restrict__ a, int64_t na,
                                                             const double* __restrict__ b, int64_t nb,
+                                                            const double* __restrict__ ls,
                                                             double* __restrict__ part) {
+  if (ls && ls[LS_STATE] != 0.0) return;
   double acc = 0.0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * RED_T;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * RED_T + threadIdx.x; i < na; i += stride) acc += a[i];
@@ -118,7 +120,8 @@ __global__ void __launch_bounds__(RED_T) sum_partial_kernel(const double* __rest
 }
 
 __global__ void __launch_bounds__(RED_T) sum_final_kernel(const double* __restrict__ part, int nparts,
-                                                          double* __restrict__ out) {
+                                                          const double* __restrict__ ls, double* __restrict__ out) {
+  if (ls && ls[LS_STATE] != 0.0) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += RED_T) acc += part[i];
   double s = block_sum(acc);
@@ -128,14 +131,14 @@ __global__ void __launch_bounds__(RED_T) sum_final_kernel(const double* __restri
 size_t sum_temp_bytes(int64_t) { return sizeof(double) * RED_BLOCKS + 256; }
 
 void launch_sum2(const double* a, int64_t na, const double* b, int64_t nb, double* d_out, void* temp,
-                 hipStream_t st) {
+                 hipStream_t st, const double* ls) {
   double* part = static_cast<double*>(temp);
-  sum_partial_kernel<<<RED_BLOCKS, RED_T, 0, st>>>(a, na, b, nb, part);
-  sum_final_kernel<<<1, RED_T, 0, st>>>(part, RED_BLOCKS, d_out);
+  sum_partial_kernel<<<RED_BLOCKS, RED_T, 0, st>>>(a, na, b, nb, ls, part);
+  sum_final_kernel<<<1, RED_T, 0, st>>>(part, RED_BLOCKS, ls, d_out);
 }
 
 void launch_sum(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st) {
-  launch_sum2(in, n, nullptr, 0, d_out, temp, st);
+  launch_sum2(in, n, nullptr, 0, d_out, temp, st, nullptr);
 }
 
 // ---- order-free min / max -----------------------------------------------------
@@ -190,6 +193,42 @@ __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
 __global__ void axpy_kernel(int64_t n, double alpha, const double* __restrict__ dx, double* __restrict__ x) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) x[i] = x[i] + alpha * dx[i];
+}
+
+// ---- device line-search state (Section 2.2 back-tracking; see kernels.h) ---------
+__global__ void ls_init_kernel(double* ls, const double* __restrict__ alpha_m) {
+  ls[LS_ALPHA] = *alpha_m;
+  ls[LS_STATE] = 0.0;
+  ls[LS_HALVINGS] = 0.0;
+  ls[LS_ALPHA_M] = *alpha_m;
+}
+// accept when the energy change of the current trial is <= 0; otherwise halve,
+// and give up (state -1) after max_halvings halvings
+__global__ void ls_decide_kernel(double* ls, const double* __restrict__ dE, int32_t max_halvings) {
+  if (ls[LS_STATE] != 0.0) return;
+  ls[LS_DE] = *dE;
+  if (*dE <= 0.0) {
+    ls[LS_STATE] = 1.0;
+  } else if (ls[LS_HALVINGS] >= max_halvings) {
+    ls[LS_STATE] = -1.0;
+  } else {
+    ls[LS_HALVINGS] += 1.0;
+    ls[LS_ALPHA] *= 0.5;
+  }
+}
+__global__ void axpy_ls_kernel(int64_t n, const double* __restrict__ ls, const double* __restrict__ dx,
+                               double* __restrict__ x) {
+  if (ls[LS_STATE] != 1.0) return;
+  const double alpha = ls[LS_ALPHA];
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = x[i] + alpha * dx[i];
+}
+void launch_ls_init(double* ls, const double* alpha_m, hipStream_t st) { ls_init_kernel<<<1, 1, 0, st>>>(ls, alpha_m); }
+void launch_ls_decide(double* ls, const double* dE, int32_t max_halvings, hipStream_t st) {
+  ls_decide_kernel<<<1, 1, 0, st>>>(ls, dE, max_halvings);
+}
+void launch_axpy_ls(int64_t n3, const double* ls, const double* dx, double* x, hipStream_t st) {
+  if (n3 > 0) axpy_ls_kernel<<<grid_for(n3, 256), 256, 0, st>>>(n3, ls, dx, x);
 }
 
 __global__ void count_nonfinite_kernel(const double* __restrict__ x, int64_t n, int32_t* __restrict__ out) {

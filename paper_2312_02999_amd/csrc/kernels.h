@@ -14,10 +14,12 @@ struct LocalArgs {
   const double* w;      // m
   const double* A;      // 6 x m
 };
-void launch_local_step(const LocalArgs& la, const double* x, double* Rout, double* energy, double* tetg, bool fp32,
-                       hipStream_t st);
-void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, double alpha, const double* E0,
-                         double* dE, bool fp32, hipStream_t st);
+// Rwarm (optional, may alias Rout): rotations at a nearby state to start from
+void launch_local_step(const LocalArgs& la, const double* x, const double* Rwarm, double* Rout, double* energy,
+                       double* tetg, bool fp32, hipStream_t st);
+void launch_identity_rotations(int64_t m, double* R, hipStream_t st);
+void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, const double* ls,
+                         const double* Rwarm, const double* E0, double* dE, bool fp32, hipStream_t st);
 void launch_gather_vertex_grad(int32_t n, int64_t m, const int32_t* vt_ptr, const int32_t* vt_ent,
                                const double* tetg, const uint8_t* fixed, double* g, hipStream_t st);
 void launch_actuation_scalar(int64_t m, const double* a, const double* R, double* A, hipStream_t st);
@@ -32,7 +34,14 @@ void launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* 
 size_t sum_temp_bytes(int64_t n);
 void launch_sum(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
 void launch_sum2(const double* a, int64_t na, const double* b, int64_t nb, double* d_out, void* temp,
-                 hipStream_t st);
+                 hipStream_t st, const double* ls = nullptr);
+// Device line-search state: a few doubles, indexed as below.  Trial kernels
+// read alpha from it and do nothing once the state is decided (1 accepted,
+// -1 failed), so several trials can be queued without reading anything back.
+enum { LS_ALPHA = 0, LS_STATE = 1, LS_HALVINGS = 2, LS_ALPHA_M = 3, LS_DE = 4, LS_SIZE = 8 };
+void launch_ls_init(double* ls, const double* alpha_m, hipStream_t st);
+void launch_ls_decide(double* ls, const double* dE, int32_t max_halvings, hipStream_t st);
+void launch_axpy_ls(int64_t n3, const double* ls, const double* dx, double* x, hipStream_t st);
 // min of n doubles (>= 0 entries) into *d_out, 1.0 if n == 0 (exact: min is order-free)
 void launch_min_clamp1(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
@@ -102,7 +111,7 @@ void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* 
 // kappa * b(d) per candidate at x + alpha dx (alpha = 0 allowed); pairs at
 // d >= dhat give 0.
 void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
-                                double alpha, double dhat, double kappa, const double* E0, double* out,
+                                const double* ls, double dhat, double kappa, const double* E0, double* out,
                                 hipStream_t st);
 // smallest pair distance (for the intersection check); -> d_out
 void launch_pair_min_dist2(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double* d2_out,
@@ -196,9 +205,9 @@ void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, in
 // Lower Cholesky of an n x n row-major SPD matrix A (lower triangle read,
 // destroyed).  Writes the lower triangle of L (n x n row-major; the strict
 // upper part is not written) and, in aux (dense_aux_size(n) entries), the
-// transpose Lt (n x n) followed by 1 / diag(L) (n).  *d_info <- 0 ok, else
-// 1 + the first failing column.
-inline int64_t dense_aux_size(int64_t n) { return n * n + n + 64; }
+// transpose Lt (n x n), 1 / diag(L) (n) and the inverses of the 64 x 64
+// diagonal blocks.  *d_info <- 0 ok, else 1 + the first failing column.
+inline int64_t dense_aux_size(int64_t n) { return n * n + n + ((n + 63) / 64) * 64 * 64 + 64; }
 template <typename T>
 void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st);
 // Solve L L^T x = b in place (b: n x nrhs row-major, nrhs <= 4).

@@ -138,6 +138,9 @@ struct Solver {
   // constant): it is kept while the flags of c are unchanged
   DBuf<int32_t> prev_cflag;
   bool cinv_valid = false;
+  // device line-search state; factor statuses still to be checked
+  DBuf<double> lsbuf;
+  bool check_info_m = false, check_info_cs = false;
   // adjoint work vectors
   DBuf<double> lam, res, zvec, pvec, kp, prod, pairbuf;
   int32_t adjoint_iters = 0;
@@ -385,7 +388,9 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   S->E0.ensure(m);
   S->dE.ensure(m);
   S->Rtet.ensure(9LL * m);
+  launch_identity_rotations(m, S->Rtet.p, st);
   S->scal.ensure(16);
+  S->lsbuf.ensure(LS_SIZE);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
 
   // ---- factor upload ---------------------------------------------------------------------------
@@ -630,7 +635,7 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
   hipStream_t st = S->st;
   {
     ScopedTimer tm(S, TK_LOCAL);
-    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st);
+    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st);
   }
   launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
   if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee);
@@ -691,7 +696,8 @@ static void global_step(Solver* S, const IterOut& io) {
     if (!io.c_same) {
       launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
       launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, st);
-      dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p, st);
+      dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p + 3, st);
+      S->check_info_cs = true;
       dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, st);
       S->prev_cflag.ensure(S->n + 1LL);
       HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, st));
@@ -702,7 +708,9 @@ static void global_step(Solver* S, const IterOut& io) {
     bool solved = false;
     if (S->opt.precision == PDIPC_MIXED_FP32) {
       // Jacobi-scaled FP32 factor, refined against FP64 residuals of the
-      // unscaled system; falls back to FP64 if refinement cannot converge.
+      // unscaled system: a few steps are queued without readback, then the
+      // residual is checked once; more steps (checked each time) or an FP64
+      // refactorisation follow only if needed.
       S->Mf.ensure(N3 * N3);
       S->MLf.ensure(N3 * N3);
       S->MLif.ensure(dense_aux_size(N3));
@@ -712,20 +720,31 @@ static void global_step(Solver* S, const IterOut& io) {
       launch_jacobi_scaling(S->Mred.p, N3, S->scl.p, st);
       launch_scale_convert_matrix(S->Mred.p, N3, S->scl.p, S->Mf.p, st);
       dense_cholesky<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, st);
-      if (read_scalar_i(S, S->info.p + 1) == 0) {
-        launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
-        const double bnorm = read_scalar_d(S, S->scal.p + 5);
-        launch_fill_f64(S->u.p, N3, 0.0, st);
-        HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
-        for (int it = 0; it < 10 && !solved; ++it) {
-          launch_scale_convert_vec(S->resid.p, N3, S->scl.p, S->uf.p, st);
-          dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
-          launch_scaled_accumulate(S->uf.p, N3, S->scl.p, S->u.p, st);
-          launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
-          launch_max_abs(S->resid.p, N3, S->scal.p + 6, S->red_tmp.p, st);
-          S->refine_steps++;
-          if (read_scalar_d(S, S->scal.p + 6) <= 1e-13 * bnorm) solved = true;
-        }
+      launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
+      launch_fill_f64(S->u.p, N3, 0.0, st);
+      HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
+      auto refine_step = [&]() {
+        launch_scale_convert_vec(S->resid.p, N3, S->scl.p, S->uf.p, st);
+        dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
+        launch_scaled_accumulate(S->uf.p, N3, S->scl.p, S->u.p, st);
+        launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
+        launch_max_abs(S->resid.p, N3, S->scal.p + 6, S->red_tmp.p, st);
+        S->refine_steps++;
+      };
+      constexpr int kQueued = 2, kMaxSteps = 10;
+      for (int it = 0; it < kQueued; ++it) refine_step();
+      int done = kQueued;
+      while (true) {
+        HIPCHK(hipMemcpyAsync(S->h_scal, S->scal.p + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(S->h_scal + 2, S->info.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int32_t finfo = 0;
+        std::memcpy(&finfo, S->h_scal + 2, sizeof(int32_t));
+        if (finfo != 0) break;
+        if (S->h_scal[1] <= 1e-13 * S->h_scal[0]) { solved = true; break; }
+        if (done >= kMaxSteps) break;
+        refine_step();
+        ++done;
       }
       if (!solved) S->refine_fallbacks++;
     }
@@ -734,7 +753,8 @@ static void global_step(Solver* S, const IterOut& io) {
         ScopedTimer tm(S, TK_REDUCED_CHOL);
         dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, st);
       }
-      if (read_scalar_i(S, S->info.p) != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
+      // the factor's status is read back with the line-search state
+      S->check_info_m = true;
       HIPCHK(hipMemcpyAsync(S->u.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
       dense_chol_solve<double>(S->ML.p, S->MLi.p, N3, S->u.p, 1, st);
     }
@@ -746,6 +766,19 @@ static void global_step(Solver* S, const IterOut& io) {
     launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
   }
   launch_unpack(f, S->n, S->solvec.p, S->dx.p, st);
+}
+
+// Statuses of the reduced factorisations queued since the last check.
+static void check_factor_status(Solver* S) {
+  if (!S->check_info_m && !S->check_info_cs) return;
+  int32_t hinfo[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(S->h_scal, S->info.p, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, S->st));
+  HIPCHK(hipStreamSynchronize(S->st));
+  std::memcpy(hinfo, S->h_scal, sizeof(hinfo));
+  const bool bad_m = S->check_info_m && hinfo[0] != 0, bad_cs = S->check_info_cs && hinfo[3] != 0;
+  S->check_info_m = S->check_info_cs = false;
+  if (bad_m) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
+  if (bad_cs) fail(PDIPC_E_NOT_SPD, "contact block of the inverse Schur complement not SPD");
 }
 
 // CCD bound and back-tracking line search; updates x.
@@ -767,29 +800,46 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
     launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p, st);
   }
   launch_min_clamp1(S->tpair.p, ncand, S->scal.p, S->red_tmp.p, st);
-  io.alpha_m = read_scalar_d(S, S->scal.p);
-  launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, nullptr, 0.0, S->opt.dhat, S->opt.kappa, nullptr, S->bE0.p, st);
-  double alpha = io.alpha_m;
-  io.ls_ok = false;
-  int h = 0;
-  for (; h <= S->opt.ls_max_halvings; ++h) {
+  launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, nullptr, nullptr, S->opt.dhat, S->opt.kappa, nullptr,
+                             S->bE0.p, st);
+  // back-tracking line search on the device: trials read alpha from the state
+  // and become no-ops once it is decided; two are queued, then one readback
+  double* ls = S->lsbuf.p;
+  launch_ls_init(ls, S->scal.p, st);
+  auto trial = [&]() {
     {
       ScopedTimer tm(S, TK_TRIAL);
-      launch_trial_energy(local_args(S), S->x.p, S->dx.p, alpha, S->E0.p, S->dE.p, fp32, st);
+      launch_trial_energy(local_args(S), S->x.p, S->dx.p, ls, S->Rtet.p, S->E0.p, S->dE.p, fp32, st);
     }
-    launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, alpha, S->opt.dhat, S->opt.kappa, S->bE0.p,
+    launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, ls, S->opt.dhat, S->opt.kappa, S->bE0.p,
                                S->bdE.p, st);
-    launch_sum2(S->dE.p, S->m, S->bdE.p, ncand, S->scal.p + 1, S->red_tmp.p, st);
-    double dEtot = read_scalar_d(S, S->scal.p + 1);
-    if (dEtot <= 0.0) {
-      io.ls_ok = true;
-      break;
-    }
-    alpha *= 0.5;
+    launch_sum2(S->dE.p, S->m, S->bdE.p, ncand, S->scal.p + 1, S->red_tmp.p, st, ls);
+    launch_ls_decide(ls, S->scal.p + 1, S->opt.ls_max_halvings, st);
+  };
+  const int queued = std::min(2, S->opt.ls_max_halvings + 1);
+  for (int h = 0; h < queued; ++h) trial();
+  double hls[LS_SIZE];
+  int32_t hinfo[4] = {0, 0, 0, 0};
+  auto readback = [&]() {
+    HIPCHK(hipMemcpyAsync(S->h_scal, ls, sizeof(double) * LS_SIZE, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(S->h_scal + LS_SIZE, S->info.p, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(hls, S->h_scal, sizeof(double) * LS_SIZE);
+    std::memcpy(hinfo, S->h_scal + LS_SIZE, sizeof(int32_t) * 4);
+  };
+  readback();
+  if (S->check_info_m && hinfo[0] != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
+  if (S->check_info_cs && hinfo[3] != 0) fail(PDIPC_E_NOT_SPD, "contact block of the inverse Schur complement not SPD");
+  S->check_info_m = S->check_info_cs = false;
+  while (hls[LS_STATE] == 0.0) {
+    trial();
+    readback();
   }
-  io.halvings = h;
-  io.alpha = io.ls_ok ? alpha : 0.0;
-  if (apply && io.alpha > 0.0) launch_axpy_positions(3LL * S->n, io.alpha, S->dx.p, S->x.p, st);
+  io.alpha_m = hls[LS_ALPHA_M];
+  io.halvings = static_cast<int32_t>(hls[LS_HALVINGS]);
+  io.ls_ok = hls[LS_STATE] == 1.0;
+  io.alpha = io.ls_ok ? hls[LS_ALPHA] : 0.0;
+  if (apply && io.alpha > 0.0) launch_axpy_ls(3LL * S->n, ls, S->dx.p, S->x.p, st);
 }
 
 static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdipc_frame_stats* stats) {
@@ -799,6 +849,10 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipMemcpyAsync(S->x.p, x_in, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
   S->cand_valid = false;
+  S->check_info_m = S->check_info_cs = false;
+  // the local steps of a frame start from the identity, so a frame does not
+  // depend on earlier calls
+  launch_identity_rotations(S->m, S->Rtet.p, st);
   launch_count_nonfinite(S->x.p, 3LL * S->n, S->info.p + 2, st);
   if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite input state");
   pdipc_frame_stats fs{};
@@ -838,7 +892,8 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
     fs.alpha_min = std::min(fs.alpha_min, io.alpha);
     if (tol_mode) {
       launch_max_abs(S->dx.p, 3LL * S->n, S->scal.p + 2, S->red_tmp.p, st);
-      double step = read_scalar_d(S, S->scal.p + 2) * io.alpha;
+      // converged when the full direction (before the line search) is small
+      double step = read_scalar_d(S, S->scal.p + 2);
       if (step <= S->opt.tol) { ++it; break; }
     }
   }
@@ -871,6 +926,7 @@ static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
   const int64_t n3 = 3LL * S->n;
   IterOut io;
   S->cand_valid = false;
+  launch_identity_rotations(S->m, S->Rtet.p, st);   // same rotations whatever ran before
   assemble_gradient(S, true, io);                   // rotations, pairs, barrier factors at x*
   const int32_t np = io.npt + io.nee;
   S->lam.ensure(n3); S->res.ensure(n3); S->zvec.ensure(n3); S->pvec.ensure(n3); S->kp.ensure(n3);
@@ -923,6 +979,7 @@ static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
     rz = rz2;
   }
   S->adjoint_iters = it;
+  check_factor_status(S);
   launch_actuation_grad(local_args(S), S->x.p, S->Rtet.p, S->R0.p, S->lam.p, dLda, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
@@ -1068,6 +1125,7 @@ void pdipc_destroy(void* h) {
   S->pairbuf.release();
   S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release(); S->scl.release();
   S->prev_cflag.release();
+  S->lsbuf.release();
   delete S;
 }
 
@@ -1094,7 +1152,8 @@ int32_t pdipc_debug_local(void* h, const double* x, double* R, double* energies,
   return guarded(S, [&] {
     if (!S->have_actuation) fail(PDIPC_E_INVALID, "no actuation set");
     const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
-    launch_local_step(local_args(S), x, S->Rtet.p, S->E0.p, S->tetg.p, fp32, S->st);
+    launch_identity_rotations(S->m, S->Rtet.p, S->st);
+    launch_local_step(local_args(S), x, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, S->st);
     launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, S->st);
     if (R) {
       // SoA 9 x m -> m x 9 through the host (debug path)
@@ -1143,6 +1202,7 @@ int32_t pdipc_debug_step(void* h, const double* x, double* dx, double* alpha_m, 
     if (!S->have_actuation) fail(PDIPC_E_INVALID, "no actuation set");
     HIPCHK(hipMemcpyAsync(S->x.p, x, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
     S->cand_valid = false;
+    launch_identity_rotations(S->m, S->Rtet.p, S->st);
     IterOut io;
     assemble_gradient(S, true, io);
     global_step(S, io);

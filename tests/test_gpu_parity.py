@@ -134,7 +134,7 @@ def test_frame_c1_first_frame():
     assert err < 1e-9, err
 
 
-@pytest.mark.parametrize("n", [5, 64, 130, 257, 700])
+@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2100])
 def test_dense_spd_kernels(n):
     """Cholesky, solve and inverse against numpy at ragged multi-tile sizes."""
     from paper_2312_02999_amd import dense_spd
@@ -169,7 +169,9 @@ def test_mixed_precision_converged_frame():
     a = 0.8 * sc.act_a
     xs = _polished_equilibrium(prob, sc, a)
     assert ocontact.constraint_set(xs, prob.prox, prob.dhat).size > 0
-    S = _solver(sc, iters=4000, tol=1e-13, precision=MIXED_FP32)
+    # tolerance on the full direction: below ~1e-12 the energy differences of
+    # the line search reach rounding and steps stop shortening the distance
+    S = _solver(sc, iters=4000, tol=1e-11, precision=MIXED_FP32)
     S.set_actuation_scalar(_t(a), _t(sc.act_R.reshape(-1, 9)))
     xg, st = S.solve_frame(_t(sc.X), stats=True)
     diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
