@@ -82,10 +82,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
 // the inverses of the 64 x 64 diagonal blocks (for the solves); Lt, dinv and
 // the block inverses share the auxiliary buffer (dense_aux_size entries).  A is the
 // workspace (its lower tiles are destroyed).  Per block step k:
-//   panel:  L_ik = A_ik L_kk^-T for every block row i > k (one wave per block
-//           row, forward substitution with the row held in registers);
-//   update: A_ij -= L_ik L_jk^T for k < j <= i (matrix cores, one workgroup
-//           per tile); the workgroup of tile (k+1, k+1) then factors it.
+//   one launch, one workgroup per trailing tile (i, j), k < j <= i: the
+//   panels L_ik = A_ik L_kk^-T and L_jk by forward substitution (one row per
+//   lane, in registers), then A_ij -= L_ik L_jk^T on the matrix cores; the
+//   workgroups of column k+1 store the panels, and the workgroup of tile
+//   (k+1, k+1) factors it.
 // Diagonal tiles are factored by one wave: lane r keeps row r in registers,
 // step j broadcasts the pivot by readlane and column j through LDS.  Ragged
 // last blocks are padded with the identity.
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
   __shared__ T colbuf[NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
   if (threadIdx.x == 0) *info = 0;
-  #pragma unroll
+#pragma unroll
   for (int it = 0; it < NB * NB / 256; ++it) {
     const int idx = threadIdx.x + 256 * it;
     const int r = idx / NB, c = idx % NB;
@@ -218,37 +219,9 @@ __device__ __forceinline__ void forward_subst_regs(T v[NB], const T (*LkT)[NB + 
   }
 }
 
-// Panel of block column k: row gr of block row i solves L_kk p = A[gr, k-block]^T.
-template <typename T, int NB>
-__global__ void __launch_bounds__(64) chol_panel_kernel(const T* __restrict__ A, int64_t n, int64_t k,
-                                                        T* __restrict__ L, T* __restrict__ Lt,
-                                                        const T* __restrict__ dinv) {
-  __shared__ T LkT[NB][NB + 1];
-  __shared__ T dk[NB];
-  const int lane = threadIdx.x;
-  const int64_t k0 = k * NB;
-  // L_kk is a full block (k < nblk - 1); its transpose is row block k of Lt
-  if (lane < NB) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c) LkT[c][lane] = (lane >= c) ? Lt[(k0 + c) * n + k0 + lane] : T(0);
-    dk[lane] = dinv[k0 + lane];
-  }
-  __syncthreads();
-  const int64_t gr = (k + 1 + blockIdx.x) * NB + lane;
-  if (lane >= NB || gr >= n) return;
-  T v[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) v[c] = A[gr * n + k0 + c];
-  forward_subst_regs<T, NB>(v, LkT, dk);
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    L[gr * n + k0 + c] = v[c];
-    Lt[(k0 + c) * n + gr] = v[c];
-  }
-}
-
-// Trailing update of tile (bi, bj), k < bj <= bi, on the matrix cores; the
-// workgroup of tile (k+1, k+1) factors it afterwards.
+// Block step k for tile (bi, bj), k < bj <= bi: panels by substitution, the
+// trailing update on the matrix cores; the workgroup of tile (k+1, k+1)
+// factors it afterwards.
 template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int64_t n, int64_t k,
                                                           T* __restrict__ L, T* __restrict__ Lt,
@@ -258,21 +231,55 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   T (*Tb)[NB] = Ta + NB;                                         // Tb[p][r] = L[j0 + r][k0 + p]
   T (*W)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);   // reused for the tile to factor
   __shared__ T colbuf[NB];
+  __shared__ T LkT[NB][NB + 1];
+  __shared__ T dk[NB];
   const int64_t nblk = (n + NB - 1) / NB;
   const int64_t m = nblk - k - 1;
   int64_t t = blockIdx.x, ii = 0;
   while (t >= m - ii) { t -= m - ii; ++ii; }
   const int64_t bj = k + 1 + ii, bi = bj + t;
   const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
-  #pragma unroll
+  // panels of block rows bi and bj: L_bk = A_bk L_kk^-T by substitution (wave 0
+  // for bi, wave 1 for bj), one row per lane, staged transposed for the
+  // matrix cores; the workgroups of the first trailing column store them
+#pragma unroll
   for (int it = 0; it < NB * NB / 256; ++it) {
     const int idx = threadIdx.x + 256 * it;
-    const int p = idx / NB, r = idx % NB;
-    const T* row = Lt + (k0 + p) * n;
-    Ta[p][r] = (i0 + r < n) ? row[i0 + r] : T(0);
-    Tb[p][r] = (j0 + r < n) ? row[j0 + r] : T(0);
+    const int c = idx / NB, r = idx % NB;
+    LkT[c][r] = (r >= c) ? Lt[(k0 + c) * n + k0 + r] : T(0);     // L_kk is a full block (k < nblk - 1)
+  }
+  if (threadIdx.x < NB) dk[threadIdx.x] = dinv[k0 + threadIdx.x];
+  __syncthreads();
+  {
+    const int w = threadIdx.x / PDIPC_WAVE, lane = threadIdx.x % PDIPC_WAVE;
+    if ((w == 0 || (w == 1 && bi != bj)) && lane < NB) {
+      const int64_t r0 = (w == 0) ? i0 : j0;
+      const int64_t gr = r0 + lane;
+      T v[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[c] = (gr < n) ? A[gr * n + k0 + c] : T(0);
+      forward_subst_regs<T, NB>(v, LkT, dk);
+      T (*Tx)[NB] = (w == 0) ? Ta : Tb;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) Tx[c][lane] = v[c];
+      if (bj == k + 1 && w == 0 && gr < n) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          L[gr * n + k0 + c] = v[c];
+          Lt[(k0 + c) * n + gr] = v[c];
+        }
+      }
+    }
   }
   __syncthreads();
+  if (bi == bj) {
+#pragma unroll
+    for (int it = 0; it < NB * NB / 256; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      Tb[idx / NB][idx % NB] = Ta[idx / NB][idx % NB];
+    }
+    __syncthreads();
+  }
   const bool last = (bi == k + 1) && (bj == k + 1);
   // write back A_ij - acc (or stage it in W for the factorisation)
   auto put = [&](int r, int c, T acc_rc) {
@@ -367,7 +374,6 @@ static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hi
   const size_t shm = sizeof(T) * 2 * NB * NB;
   for (int64_t k = 0; k + 1 < nblk; ++k) {
     const int64_t m = nblk - k - 1;
-    chol_panel_kernel<T, NB><<<static_cast<unsigned>(m), 64, 0, st>>>(A, n, k, L, Lt, dinv);
     chol_update_kernel<T, NB><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Lt, dinv,
                                                                                          d_info);
   }
@@ -490,7 +496,7 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
     for (int c = 0; c < CPT; ++c) acc[c] = (bk == bj && tr == CPT * tq + c) ? T(1) : T(0);
     for (int64_t bp = bj; bp < bk; ++bp) {
       const int64_t p0 = bp * NB;
-      #pragma unroll
+#pragma unroll
       for (int it = 0; it < NB * NB / 256; ++it) {
         const int idx = threadIdx.x + 256 * it;
         const int r = idx / NB, c = idx % NB;
@@ -508,7 +514,7 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
 #pragma unroll
     for (int c = 0; c < CPT; ++c) Tm[tr][CPT * tq + c] = acc[c];
     // LkT[c][r] = L_kk[r][c] (reusing Ls), identity-padded
-    #pragma unroll
+#pragma unroll
       for (int it = 0; it < NB * NB / 256; ++it) {
         const int idx = threadIdx.x + 256 * it;
       const int c = idx / NB, r = idx % NB;
@@ -526,7 +532,7 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
       for (int r = 0; r < NB; ++r) Tm[r][c] = v[r];
     }
     __syncthreads();
-    #pragma unroll
+#pragma unroll
       for (int it = 0; it < NB * NB / 256; ++it) {
         const int idx = threadIdx.x + 256 * it;
       const int r = idx / NB, c = idx % NB;

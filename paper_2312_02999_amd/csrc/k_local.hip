@@ -3,6 +3,8 @@
 // energy (w_i/2)||F_i - R_i A_i||^2 and the element's share of
 // sum_i w_i G_i^T (G_i x - p_i).  One thread per tet; per-tet data are SoA
 // streams (coalesced), vertex positions are gathered as xyz triples.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -428,13 +430,16 @@ __global__ void actuation_transpose_kernel(int64_t m, const double* __restrict__
 
 // ---- launchers --------------------------------------------------------------
 void launch_local_step(const LocalArgs& la, const double* x, const double* Rwarm, double* Rout, double* energy,
-                       double* tetg, bool fp32, hipStream_t st) {
+                       double* tetg, bool fp32, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
   TetStreams ts{la.tets, la.B, la.w, la.A};
-  unsigned g = grid_for(la.m, 256);
+  const dim3 g(grid_for(la.m, 256)), b(256);
+  // with events: the runtime stamps them at the dispatch's own start and end
   if (fp32)
-    local_step_kernel<float><<<g, 256, 0, st>>>(ts, la.m, x, Rwarm, Rout, energy, tetg);
+    hipExtLaunchKernelGGL(local_step_kernel<float>, g, b, 0, st, ev_start, ev_stop, 0, ts, la.m, x, Rwarm, Rout,
+                          energy, tetg);
   else
-    local_step_kernel<double><<<g, 256, 0, st>>>(ts, la.m, x, Rwarm, Rout, energy, tetg);
+    hipExtLaunchKernelGGL(local_step_kernel<double>, g, b, 0, st, ev_start, ev_stop, 0, ts, la.m, x, Rwarm, Rout,
+                          energy, tetg);
 }
 
 void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, const double* ls,

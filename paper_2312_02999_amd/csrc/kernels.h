@@ -15,8 +15,10 @@ struct LocalArgs {
   const double* A;      // 6 x m
 };
 // Rwarm (optional, may alias Rout): rotations at a nearby state to start from
+// ev_start / ev_stop (optional): events stamped at the kernel's start and end
 void launch_local_step(const LocalArgs& la, const double* x, const double* Rwarm, double* Rout, double* energy,
-                       double* tetg, bool fp32, hipStream_t st);
+                       double* tetg, bool fp32, hipStream_t st, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
 void launch_identity_rotations(int64_t m, double* R, hipStream_t st);
 void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, const double* ls,
                          const double* Rwarm, const double* E0, double* dE, bool fp32, hipStream_t st);

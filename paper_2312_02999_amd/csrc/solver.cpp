@@ -187,6 +187,21 @@ struct ScopedTimer {
   }
 };
 
+// A start/stop event pair for a launch that stamps them itself (extended
+// launch): the elapsed time is the kernel's own duration.
+static bool timer_events(Solver* S, int which, hipEvent_t* e0, hipEvent_t* e1) {
+  if (S->timer_which != which) return false;
+  while (S->ev_pool.size() < S->ev_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    S->ev_pool.push_back(e);
+  }
+  *e0 = S->ev_pool[S->ev_used];
+  *e1 = S->ev_pool[S->ev_used + 1];
+  S->ev_used += 2;
+  return true;
+}
+
 static void harvest_timer(Solver* S) {
   for (size_t k = 0; k + 1 < S->ev_used; k += 2) {
     float ms = 0.f;
@@ -634,8 +649,9 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
   const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
   hipStream_t st = S->st;
   {
-    ScopedTimer tm(S, TK_LOCAL);
-    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_events(S, TK_LOCAL, &e0, &e1);
+    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st, e0, e1);
   }
   launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
   if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee);
