@@ -430,9 +430,60 @@ __global__ void __launch_bounds__(256) add_bcheck_kernel(int32_t nc, const int32
   }
 }
 
+// Row block a of M = C^-1 + B_check in one pass (reduced systems up to
+// RB_LDS_N unknowns): one wave per contact vertex accumulates its three rows
+// of B_check in LDS, entry by entry in incidence order (deterministic), then
+// writes the rows with the C^-1 = C_s^-1 (x) I3 part added.
+constexpr int RB_LDS_N = 2048;
+__global__ void __launch_bounds__(64) assemble_rows_kernel(int32_t nc, const double* __restrict__ Cinv,
+                                                           const int32_t* __restrict__ clist,
+                                                           const int32_t* __restrict__ ptr,
+                                                           const int32_t* __restrict__ ent,
+                                                           const int32_t* __restrict__ v4,
+                                                           const int32_t* __restrict__ cflag,
+                                                           const int32_t* __restrict__ cidx,
+                                                           const double* __restrict__ U, int32_t npairs,
+                                                           double* __restrict__ M) {
+  extern __shared__ unsigned char smem_raw[];
+  double* R = reinterpret_cast<double*>(smem_raw);     // 3 x N
+  const int lane = threadIdx.x;
+  const int64_t ca = blockIdx.x;
+  const int64_t N = 3 * static_cast<int64_t>(nc);
+  for (int64_t i = lane; i < 3 * N; i += PDIPC_WAVE) R[i] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  const int32_t va = clist[ca];
+  const int lb = lane / 9, r = (lane % 9) / 3, sc = lane % 3;
+  const bool active = lane < 36;
+#pragma unroll 4
+  for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
+    const int32_t k = ent[t] >> 2, la = ent[t] & 3;
+    const int32_t vb = active ? v4[4 * k + lb] : 0;
+    const bool use = active && cflag[vb];
+    double acc = 0.0;
+    if (use) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c)
+        acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
+               U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
+      R[r * N + 3 * static_cast<int64_t>(cidx[vb]) + sc] += acc;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int rr = 0; rr < 3; ++rr)
+    for (int64_t col = lane; col < N; col += PDIPC_WAVE) {
+      const double kron = (col % 3 == rr) ? Cinv[ca * nc + col / 3] : 0.0;
+      M[(3 * ca + rr) * N + col] = kron + R[rr * N + col];
+    }
+}
+
 void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairList& pl,
                              int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st) {
   int64_t N = 3 * static_cast<int64_t>(nc);
+  if (N <= RB_LDS_N) {
+    assemble_rows_kernel<<<static_cast<unsigned>(nc), 64, sizeof(double) * 3 * N, st>>>(
+        nc, Cinv, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx, bo.U, npairs, M);
+    return;
+  }
   fill_kron_kernel<<<grid_for(N * N, 256), 256, 0, st>>>(nc, Cinv, M);
   add_bcheck_kernel<<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx,
                                                       bo.U, npairs, M);

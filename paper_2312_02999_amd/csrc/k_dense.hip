@@ -460,29 +460,119 @@ __global__ void __launch_bounds__(512) chol_solve_kernel(const T* __restrict__ L
   }
 }
 
+// Single right-hand side with the whole vector in LDS (up to SOLVE_LDS_BYTES):
+// the block steps then read only L, Lt and the diagonal-block inverses from
+// memory, and the next block inverse is fetched while the rows below update.
+constexpr int SOLVE_LDS_BYTES = 48 * 1024;
+template <typename T, int NB>
+__global__ void __launch_bounds__(512) chol_solve1_lds_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
+                                                              const T* __restrict__ Dinv, int64_t n,
+                                                              T* __restrict__ b) {
+  extern __shared__ unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  __shared__ T Di[2][NB][NB + 1];
+  __shared__ T ys[NB];
+  constexpr int DPT = NB * NB / 512 > 0 ? NB * NB / 512 : 1;   // block-inverse entries per thread
+  const int nblk = static_cast<int>((n + NB - 1) / NB);
+  for (int64_t i = threadIdx.x; i < n; i += 512) xs[i] = b[i];
+  auto fetch = [&](int bk, T reg[DPT]) {
+    const T* D = Dinv + static_cast<int64_t>(bk) * NB * NB;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int idx = threadIdx.x + 512 * q;
+      reg[q] = idx < NB * NB ? D[idx] : T(0);
+    }
+  };
+  auto put = [&](int buf, const T reg[DPT]) {
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int idx = threadIdx.x + 512 * q;
+      if (idx < NB * NB) Di[buf][idx / NB][idx % NB] = reg[q];
+    }
+  };
+  T reg[DPT];
+  // forward: L y = b
+  fetch(0, reg);
+  put(0, reg);
+  __syncthreads();
+  for (int bk = 0; bk < nblk; ++bk) {
+    const int64_t k0 = static_cast<int64_t>(bk) * NB;
+    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
+    const int cur = bk & 1;
+    if (threadIdx.x < NB) {
+      const int r = threadIdx.x;
+      T acc = T(0);
+      for (int c = 0; c <= r; ++c) acc += Di[cur][r][c] * (c < kb ? xs[k0 + c] : T(0));
+      ys[r] = acc;
+    }
+    if (bk + 1 < nblk) fetch(bk + 1, reg);
+    __syncthreads();
+    if (threadIdx.x < kb) xs[k0 + threadIdx.x] = ys[threadIdx.x];
+    for (int64_t gr = k0 + kb + threadIdx.x; gr < n; gr += 512) {
+      T sacc = T(0);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) sacc += (c < kb ? Lt[(k0 + c) * n + gr] : T(0)) * ys[c];
+      xs[gr] -= sacc;
+    }
+    if (bk + 1 < nblk) put(cur ^ 1, reg);
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  fetch(nblk - 1, reg);
+  put((nblk - 1) & 1, reg);
+  __syncthreads();
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int64_t k0 = static_cast<int64_t>(bk) * NB;
+    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
+    const int cur = bk & 1;
+    if (threadIdx.x < NB) {
+      const int c = threadIdx.x;
+      T acc = T(0);
+      for (int r = c; r < NB; ++r) acc += Di[cur][r][c] * (r < kb ? xs[k0 + r] : T(0));
+      ys[c] = acc;
+    }
+    if (bk > 0) fetch(bk - 1, reg);
+    __syncthreads();
+    if (threadIdx.x < kb) xs[k0 + threadIdx.x] = ys[threadIdx.x];
+    for (int64_t gc = threadIdx.x; gc < k0; gc += 512) {
+      T sacc = T(0);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) sacc += (c < kb ? L[(k0 + c) * n + gc] : T(0)) * ys[c];
+      xs[gc] -= sacc;
+    }
+    if (bk > 0) put(cur ^ 1, reg);
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < n; i += 512) b[i] = xs[i];
+}
+
 template <typename T>
 void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
   if (n <= 0) return;
-  if (dense_block(n) == 32) chol_solve_kernel<T, 32><<<1, 512, 0, st>>>(L, aux, aux + n * n + n, n, b, nrhs);
-  else chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(L, aux, aux + n * n + n, n, b, nrhs);
+  const T* Dinv = aux + n * n + n;
+  const size_t xs_bytes = sizeof(T) * static_cast<size_t>(n);
+  if (nrhs == 1 && dense_block(n) == 32 && xs_bytes <= static_cast<size_t>(SOLVE_LDS_BYTES)) {
+    chol_solve1_lds_kernel<T, 32><<<1, 512, xs_bytes, st>>>(L, aux, Dinv, n, b);
+    return;
+  }
+  if (dense_block(n) == 32) chol_solve_kernel<T, 32><<<1, 512, 0, st>>>(L, aux, Dinv, n, b, nrhs);
+  else chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(L, aux, Dinv, n, b, nrhs);
 }
 
-// ---- Y = L^-1, one workgroup per 64-column block -------------------------------
+// ---- Y = L^-1, one workgroup per column block ----------------------------------
 // Block row kk >= j of column block j: Y_kk,j = L_kk^-1 (delta_kj I - sum_{j<=p<kk}
-// L_kp Y_pj); the sum is staged through LDS, the diagonal solve is done by one
-// wave with each lane holding one column in registers.  Blocks above the
-// diagonal are zeroed.
+// L_kp Y_pj); the sum is staged through LDS and L_kk^-1 is the stored
+// inverse of the diagonal block.  Blocks above the diagonal are zeroed.
 template <typename T, int NB>
-__global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
-                                                        const T* __restrict__ dinv, int64_t n, T* __restrict__ Y) {
+__global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                        int64_t n, T* __restrict__ Y) {
   __shared__ T Ls[NB][NB + 1];
   __shared__ T Ys[NB][NB + 1];
   __shared__ T Tm[NB][NB + 1];
-  __shared__ T dk[NB];
   const int64_t nblk = (n + NB - 1) / NB;
   const int64_t bj = blockIdx.x, j0 = bj * NB;
   const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
-  for (int64_t r = threadIdx.x / NB; r < j0; r += blockDim.x / NB) {
+  for (int64_t r = threadIdx.x / NB; r < j0; r += 256 / NB) {
     const int c = threadIdx.x % NB;
     if (c < jb) Y[r * n + j0 + c] = T(0);
   }
@@ -511,33 +601,28 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
       }
       __syncthreads();
     }
+    // Y_kj = Dinv_k (delta_kj I - sum_p L_kp Y_pj): Tm holds the bracket, Ls
+    // the inverse of the diagonal block (identity-padded beyond the matrix)
 #pragma unroll
     for (int c = 0; c < CPT; ++c) Tm[tr][CPT * tq + c] = acc[c];
-    // LkT[c][r] = L_kk[r][c] (reusing Ls), identity-padded
+    const T* D = Dinv + bk * NB * NB;
 #pragma unroll
-      for (int it = 0; it < NB * NB / 256; ++it) {
-        const int idx = threadIdx.x + 256 * it;
-      const int c = idx / NB, r = idx % NB;
-      Ls[c][r] = (r < kb && c < kb) ? (r >= c ? Lt[(k0 + c) * n + k0 + r] : T(0)) : (r == c ? T(1) : T(0));
-    }
-    if (threadIdx.x < NB) dk[threadIdx.x] = threadIdx.x < kb ? dinv[k0 + threadIdx.x] : T(1);
-    __syncthreads();
-    if (threadIdx.x < NB) {
-      const int c = threadIdx.x;
-      T v[NB];
-#pragma unroll
-      for (int r = 0; r < NB; ++r) v[r] = Tm[r][c];
-      forward_subst_regs<T, NB>(v, Ls, dk);
-#pragma unroll
-      for (int r = 0; r < NB; ++r) Tm[r][c] = v[r];
+    for (int it = 0; it < NB * NB / 256; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      Ls[idx / NB][idx % NB] = D[idx];
     }
     __syncthreads();
+    T out[CPT];
 #pragma unroll
-      for (int it = 0; it < NB * NB / 256; ++it) {
-        const int idx = threadIdx.x + 256 * it;
-      const int r = idx / NB, c = idx % NB;
-      if (r < kb && c < jb) Y[(k0 + r) * n + j0 + c] = Tm[r][c];
+    for (int c = 0; c < CPT; ++c) out[c] = T(0);
+    for (int s = 0; s <= tr; ++s) {
+      const T d = Ls[tr][s];
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) out[c] += d * Tm[s][CPT * tq + c];
     }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (tr < kb && CPT * tq + c < jb) Y[(k0 + tr) * n + j0 + CPT * tq + c] = out[c];
     __syncthreads();
   }
 }
@@ -545,10 +630,11 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
 template <typename T>
 void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st) {
   if (n <= 0) return;
+  const T* Dinv = aux + n * n + n;
   if (dense_block(n) == 32)
-    chol_linv_kernel<T, 32><<<grid_for(n, 32), 256, 0, st>>>(L, aux, aux + n * n, n, work);
+    chol_linv_kernel<T, 32><<<grid_for(n, 32), 256, 0, st>>>(L, Dinv, n, work);
   else
-    chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, aux, aux + n * n, n, work);
+    chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, Dinv, n, work);
   const unsigned g = grid_for(n, 64);
   dim3 grid(g, g);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);

@@ -149,6 +149,10 @@ struct Solver {
   double* h_scal = nullptr;   // pinned readback
   // optional HIP-event timer around every launch of one kernel family
   int32_t timer_which = -1;
+  // second stream (default priority) for the reduced contact system, which
+  // runs concurrently with the sweeps of the global step
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   double timer_ms = 0.0;
@@ -156,6 +160,9 @@ struct Solver {
 
   ~Solver() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     if (h_scal) (void)hipHostFree(h_scal);
     if (st) (void)hipStreamSynchronize(st);
   }
@@ -171,7 +178,9 @@ enum TimerKernel { TK_LOCAL = 0, TK_SIGMA_GEMV = 1, TK_FWD = 2, TK_BWD = 3, TK_B
 struct ScopedTimer {
   Solver* S;
   bool on;
-  ScopedTimer(Solver* s, int which) : S(s), on(s->timer_which == which) {
+  hipStream_t stream;
+  ScopedTimer(Solver* s, int which, hipStream_t sx = nullptr)
+      : S(s), on(s->timer_which == which), stream(sx ? sx : s->st) {
     if (on) record();
   }
   ~ScopedTimer() {
@@ -183,7 +192,7 @@ struct ScopedTimer {
       if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
       S->ev_pool.push_back(e);
     }
-    (void)hipEventRecord(S->ev_pool[S->ev_used++], S->st);
+    (void)hipEventRecord(S->ev_pool[S->ev_used++], stream);
   }
 };
 
@@ -406,6 +415,9 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   launch_identity_rotations(m, S->Rtet.p, st);
   S->scal.ensure(16);
   S->lsbuf.ensure(LS_SIZE);
+  HIPCHK(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
 
   // ---- factor upload ---------------------------------------------------------------------------
@@ -686,17 +698,9 @@ static void global_step(Solver* S, const IterOut& io) {
   FactorDev& f = S->fd;
   const int32_t np = io.npt + io.nee, nc = io.nc;
   const int64_t n1x3 = 3LL * f.n1;
-  launch_pack_rhs(f, S->g.p, S->bvec.p, st);
-  {
-    ScopedTimer tm(S, TK_FWD);
-    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
-  }
-  {
-    ScopedTimer tm(S, TK_SIGMA_GEMV);
-    launch_sigma_gemv(f, S->yvec.p + n1x3, S->solvec.p + n1x3, st);
-  }
+  const bool mixed = S->opt.precision == PDIPC_MIXED_FP32;
+  const int64_t N3 = 3LL * nc;
   if (nc > 0) {
-    const int64_t N3 = 3LL * nc;
     S->c_x2.ensure(nc);
     S->Cs.ensure(static_cast<int64_t>(nc) * nc);
     S->Cinv.ensure(static_cast<int64_t>(nc) * nc);
@@ -709,33 +713,59 @@ static void global_step(Solver* S, const IterOut& io) {
     S->rhs.ensure(N3);
     S->u.ensure(N3);
     S->vvec.ensure(N3);
-    if (!io.c_same) {
-      launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
-      launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, st);
-      dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p + 3, st);
-      S->check_info_cs = true;
-      dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, st);
-      S->prev_cflag.ensure(S->n + 1LL);
-      HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, st));
-      S->cinv_valid = true;
-    }
-    launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
-    launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
-    bool solved = false;
-    if (S->opt.precision == PDIPC_MIXED_FP32) {
-      // Jacobi-scaled FP32 factor, refined against FP64 residuals of the
-      // unscaled system: a few steps are queued without readback, then the
-      // residual is checked once; more steps (checked each time) or an FP64
-      // refactorisation follow only if needed.
+    if (mixed) {
       S->Mf.ensure(N3 * N3);
       S->MLf.ensure(N3 * N3);
       S->MLif.ensure(dense_aux_size(N3));
       S->uf.ensure(N3);
       S->resid.ensure(N3);
       S->scl.ensure(N3);
-      launch_jacobi_scaling(S->Mred.p, N3, S->scl.p, st);
-      launch_scale_convert_matrix(S->Mred.p, N3, S->scl.p, S->Mf.p, st);
-      dense_cholesky<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, st);
+    }
+    // The reduced system depends only on the contact terms and C^-1: build and
+    // factor it on the side stream while the sweeps run on the main stream.
+    hipStream_t sd = S->side;
+    HIPCHK(hipEventRecord(S->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(sd, S->ev_fork, 0));
+    if (!io.c_same) {
+      launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, sd);
+      launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, sd);
+      dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p + 3, sd);
+      S->check_info_cs = true;
+      dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, sd);
+      S->prev_cflag.ensure(S->n + 1LL);
+      HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, sd));
+      S->cinv_valid = true;
+    }
+    launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, sd);
+    if (mixed) {
+      // Jacobi-scaled FP32 copy and its factor (refined against FP64 below)
+      launch_jacobi_scaling(S->Mred.p, N3, S->scl.p, sd);
+      launch_scale_convert_matrix(S->Mred.p, N3, S->scl.p, S->Mf.p, sd);
+      dense_cholesky<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, sd);
+    } else {
+      ScopedTimer tm(S, TK_REDUCED_CHOL, sd);
+      dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, sd);
+      S->check_info_m = true;           // read back with the line-search state
+    }
+    HIPCHK(hipEventRecord(S->ev_join, sd));
+  }
+  launch_pack_rhs(f, S->g.p, S->bvec.p, st);
+  {
+    ScopedTimer tm(S, TK_FWD);
+    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
+  }
+  {
+    ScopedTimer tm(S, TK_SIGMA_GEMV);
+    launch_sigma_gemv(f, S->yvec.p + n1x3, S->solvec.p + n1x3, st);
+  }
+  if (nc > 0) {
+    HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
+    launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
+    bool solved = !mixed, fallback = false;
+    if (mixed) {
+      // refined against FP64 residuals of the unscaled system: a few steps are
+      // queued without readback, then the residual is checked once; more steps
+      // (checked each time) or an FP64 refactorisation follow only if needed
       launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
       launch_fill_f64(S->u.p, N3, 0.0, st);
       HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
@@ -762,15 +792,17 @@ static void global_step(Solver* S, const IterOut& io) {
         refine_step();
         ++done;
       }
-      if (!solved) S->refine_fallbacks++;
-    }
-    if (!solved) {
-      {
-        ScopedTimer tm(S, TK_REDUCED_CHOL);
-        dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, st);
+      if (!solved) {
+        S->refine_fallbacks++;
+        fallback = true;
+        {
+          ScopedTimer tm(S, TK_REDUCED_CHOL);
+          dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, st);
+        }
+        S->check_info_m = true;
       }
-      // the factor's status is read back with the line-search state
-      S->check_info_m = true;
+    }
+    if (!mixed || fallback) {
       HIPCHK(hipMemcpyAsync(S->u.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
       dense_chol_solve<double>(S->ML.p, S->MLi.p, N3, S->u.p, 1, st);
     }

@@ -148,6 +148,9 @@ def test_dense_spd_kernels(n):
     assert np.abs(inv.cpu().numpy() - np.linalg.inv(A)).max() < 1e-10 * np.abs(np.linalg.inv(A)).max()
     xf, _ = dense_spd(_t(A), _t(b), precision=1)
     assert np.abs(xf.cpu().numpy() - xr).max() < 1e-3 * max(1.0, np.abs(xr).max())
+    # single right-hand side (the solver's case)
+    x1, _ = dense_spd(_t(A), _t(b[:, 0]))
+    assert np.abs(x1.cpu().numpy() - xr[:, 0]).max() < 1e-10 * max(1.0, np.abs(xr).max())
 
 
 def test_dense_spd_rejects_indefinite():
