@@ -77,16 +77,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t
 }
 
 // ---- Cholesky -----------------------------------------------------------------
-// Right-looking with 64-wide blocks.  Outputs: L (lower, row-major), its
+// Right-looking, blocked (NB = 32 or 64).  Outputs: L (lower, row-major), its
 // transpose Lt (upper, row-major), the reciprocals of the diagonal, dinv, and
-// the inverses of the 64 x 64 diagonal blocks (for the solves); Lt, dinv and
-// the block inverses share the auxiliary buffer (dense_aux_size entries).  A is the
-// workspace (its lower tiles are destroyed).  Per block step k:
-//   one launch, one workgroup per trailing tile (i, j), k < j <= i: the
-//   panels L_ik = A_ik L_kk^-T and L_jk by forward substitution (one row per
-//   lane, in registers), then A_ij -= L_ik L_jk^T on the matrix cores; the
-//   workgroups of column k+1 store the panels, and the workgroup of tile
-//   (k+1, k+1) factors it.
+// the inverses of the diagonal blocks L_kk^-1 (for the panels and the solves);
+// Lt, dinv and the block inverses share the auxiliary buffer (dense_aux_size
+// entries).  A is the workspace (its lower tiles are destroyed).  Per block
+// step k: one launch, one workgroup per trailing tile (i, j), k < j <= i: the
+// panels L_ik = A_ik (L_kk^-1)^T and L_jk, then A_ij -= L_ik L_jk^T, both on the
+// matrix cores; the workgroups of column k+1 store the panels, and the
+// workgroup of tile (k+1, k+1) factors and inverts it.
 // Diagonal tiles are factored by one wave: lane r keeps row r in registers,
 // step j broadcasts the pivot by readlane and column j through LDS.  Ragged
 // last blocks are padded with the identity.
@@ -188,12 +187,96 @@ __device__ __forceinline__ void factor_diag_wave(T (*W)[NB + 1], int kb, int64_t
   if (lane < kb) dinv[k0 + lane] = colbuf[lane];
 }
 
+// Lane c of the first wave forms column c of L_kk^-1 from the factor left in W
+// (row-major, lower part) and the reciprocal diagonal dk by forward
+// substitution, and stores the inverse row-major to D.  Padded rows/columns
+// hold the identity, so the inverse is the identity there too.
+template <typename T, int NB>
+__device__ __forceinline__ void invert_diag_wave(const T (*W)[NB + 1], const T* dk, T* __restrict__ D) {
+  const int lane = threadIdx.x;
+  if (lane >= NB) return;
+  T v[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) v[r] = (r == lane) ? T(1) : T(0);
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const T y = v[c] * dk[c];
+    v[c] = y;
+#pragma unroll
+    for (int r = c + 1; r < NB; ++r) v[r] -= y * W[r][c];
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r) D[r * NB + lane] = v[r];
+}
+
+// NB = 32: the 32-lane rows of the tile leave the upper half of the wave idle,
+// so lanes 32 + c carry column c of the identity through the same steps: with
+// the column of L broadcast for the trailing update they forward-substitute
+// it, and end holding column c of L_kk^-1.  The factor goes to W (rows), the
+// inverse to X, 1 / diag(L_kk) to dk; same pivot rules as factor_diag_wave.
+template <typename T>
+__device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int kb, int64_t k0,
+                                                     int32_t* __restrict__ info, T* colbuf, T* dk) {
+  const int lane = threadIdx.x;
+  const int rr = lane & 31;
+  const bool rowlane = lane < 32;
+  T a[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) a[c] = rowlane ? W[rr][c] : (c == rr ? T(1) : T(0));
+  T myinv = T(1);
+  int first_bad = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    T d = read_lane(a[j], j);
+    const bool ok = d > T(0);
+    first_bad = (!ok && first_bad == 0 && j < kb) ? j + 1 : first_bad;
+    d = ok ? d : T(1);
+    const T isd = rsqrt_nr(d);
+    const T l = (lane == j) ? d * isd : a[j] * isd;
+    a[j] = l;
+    myinv = (lane == j) ? isd : myinv;
+    colbuf[lane] = l;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = j + 1; c < 32; ++c) a[c] -= l * colbuf[c];
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (rowlane) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) W[rr][c] = a[c];
+    dk[rr] = myinv;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) X[r][rr] = a[r];
+  }
+  if (first_bad != 0 && lane == 0 && *info == 0) *info = static_cast<int32_t>(k0 + first_bad);
+}
+
+// Stores a factored and inverted 32 x 32 diagonal block with the whole
+// workgroup (coalesced): L and Lt (rows/columns < kb), dinv, the inverse D.
+template <typename T>
+__device__ __forceinline__ void store_diag32(const T (*W)[33], const T (*X)[33], const T* dk, int kb, int64_t k0,
+                                             int64_t n, T* __restrict__ L, T* __restrict__ Lt,
+                                             T* __restrict__ dinv, T* __restrict__ D) {
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    const int r = idx / 32, c = idx % 32;
+    if (r < kb && c <= r) L[(k0 + r) * n + k0 + c] = W[r][c];
+    if (c < kb && c >= r) Lt[(k0 + r) * n + k0 + c] = W[c][r];
+    D[idx] = X[r][c];
+  }
+  if (threadIdx.x < kb) dinv[k0 + threadIdx.x] = dk[threadIdx.x];
+}
+
 template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ L,
                                                          T* __restrict__ Lt, T* __restrict__ dinv,
-                                                         int32_t* __restrict__ info) {
+                                                         T* __restrict__ Dinv, int32_t* __restrict__ info) {
   __shared__ T W[NB][NB + 1];
-  __shared__ T colbuf[NB];
+  __shared__ T X[NB == 32 ? 32 : 1][33];
+  __shared__ T colbuf[PDIPC_WAVE];
+  __shared__ T dk[NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
   if (threadIdx.x == 0) *info = 0;
 #pragma unroll
@@ -203,102 +286,122 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
     W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
   }
   __syncthreads();
-  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T, NB>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
-}
-
-// v <- L_kk^-1 v for the register vector v (lane-private), with LkT[c][r] =
-// L_kk[r][c] and dk = 1 / diag(L_kk) in LDS.
-template <typename T, int NB>
-__device__ __forceinline__ void forward_subst_regs(T v[NB], const T (*LkT)[NB + 1], const T* dk) {
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    const T y = v[c] * dk[c];
-    v[c] = y;
-#pragma unroll
-    for (int r = c + 1; r < NB; ++r) v[r] -= y * LkT[c][r];
+  if constexpr (NB == 32) {
+    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, colbuf, dk);
+    __syncthreads();
+    store_diag32<T>(W, X, dk, kb, 0, n, L, Lt, dinv, Dinv);
+  } else if (threadIdx.x < PDIPC_WAVE) {
+    factor_diag_wave<T, NB>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
+    invert_diag_wave<T, NB>(W, colbuf, Dinv);
   }
 }
 
-// Block step k for tile (bi, bj), k < bj <= bi: panels by substitution, the
-// trailing update on the matrix cores; the workgroup of tile (k+1, k+1)
-// factors it afterwards.
+// Block step k for tile (bi, bj), k < bj <= bi.  The panels L_bk = A_bk
+// L_kk^-T are products with the stored inverse of the diagonal block (matrix
+// cores), the trailing update A_ij -= L_ik L_jk^T too; the workgroups of the
+// first trailing column store the panels (coalesced), and the workgroup of
+// tile (k+1, k+1) factors and inverts it afterwards.  The tile to update is
+// loaded together with the panel operands.
 template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int64_t n, int64_t k,
                                                           T* __restrict__ L, T* __restrict__ Lt,
-                                                          T* __restrict__ dinv, int32_t* __restrict__ info) {
+                                                          T* __restrict__ dinv, T* __restrict__ Dinv,
+                                                          int32_t* __restrict__ info) {
   extern __shared__ unsigned char smem_raw[];
-  T (*Ta)[NB] = reinterpret_cast<T (*)[NB]>(smem_raw);          // Ta[p][r] = L[i0 + r][k0 + p]
-  T (*Tb)[NB] = Ta + NB;                                         // Tb[p][r] = L[j0 + r][k0 + p]
-  T (*W)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);   // reused for the tile to factor
-  __shared__ T colbuf[NB];
-  __shared__ T LkT[NB][NB + 1];
+  T (*Ds)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);  // Ds[p][q] = (L_kk^-1)[p][q]
+  T (*Ai)[NB + 1] = Ds + NB;                                     // Ai[r][q] = A[i0 + r][k0 + q]
+  T (*Aj)[NB + 1] = Ai + NB;
+  T (*Ta)[NB + 1] = Ai;   // then Ta[p][r] = L[i0 + r][k0 + p]
+  T (*Tb)[NB + 1] = Aj;
+  T (*W)[NB + 1] = Ds;    // then the tile to factor
+  __shared__ T colbuf[PDIPC_WAVE];
   __shared__ T dk[NB];
+  constexpr int TL = NB / 32;
   const int64_t nblk = (n + NB - 1) / NB;
   const int64_t m = nblk - k - 1;
   int64_t t = blockIdx.x, ii = 0;
   while (t >= m - ii) { t -= m - ii; ++ii; }
   const int64_t bj = k + 1 + ii, bi = bj + t;
   const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
-  // panels of block rows bi and bj: L_bk = A_bk L_kk^-T by substitution (wave 0
-  // for bi, wave 1 for bj), one row per lane, staged transposed for the
-  // matrix cores; the workgroups of the first trailing column store them
-#pragma unroll
-  for (int it = 0; it < NB * NB / 256; ++it) {
-    const int idx = threadIdx.x + 256 * it;
-    const int c = idx / NB, r = idx % NB;
-    LkT[c][r] = (r >= c) ? Lt[(k0 + c) * n + k0 + r] : T(0);     // L_kk is a full block (k < nblk - 1)
-  }
-  if (threadIdx.x < NB) dk[threadIdx.x] = dinv[k0 + threadIdx.x];
-  __syncthreads();
+  const bool same = bi == bj;
+  const bool last = (bi == k + 1) && same;
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int rb = (NB / 2) * (w / 2), cb = (NB / 2) * (w % 2);
+  const int lr = lane % 16, lk = lane / 16;
   {
-    const int w = threadIdx.x / PDIPC_WAVE, lane = threadIdx.x % PDIPC_WAVE;
-    if ((w == 0 || (w == 1 && bi != bj)) && lane < NB) {
-      const int64_t r0 = (w == 0) ? i0 : j0;
-      const int64_t gr = r0 + lane;
-      T v[NB];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) v[c] = (gr < n) ? A[gr * n + k0 + c] : T(0);
-      forward_subst_regs<T, NB>(v, LkT, dk);
-      T (*Tx)[NB] = (w == 0) ? Ta : Tb;
-#pragma unroll
-      for (int c = 0; c < NB; ++c) Tx[c][lane] = v[c];
-      if (bj == k + 1 && w == 0 && gr < n) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          L[gr * n + k0 + c] = v[c];
-          Lt[(k0 + c) * n + gr] = v[c];
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (bi == bj) {
+    const T* D = Dinv + k * NB * NB;
 #pragma unroll
     for (int it = 0; it < NB * NB / 256; ++it) {
       const int idx = threadIdx.x + 256 * it;
-      Tb[idx / NB][idx % NB] = Ta[idx / NB][idx % NB];
+      const int r = idx / NB, c = idx % NB;
+      Ds[r][c] = D[idx];
+      Ai[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);
+      if (!same) Aj[r][c] = (j0 + r < n) ? A[(j0 + r) * n + k0 + c] : T(0);
     }
-    __syncthreads();
   }
-  const bool last = (bi == k + 1) && (bj == k + 1);
-  // write back A_ij - acc (or stage it in W for the factorisation)
-  auto put = [&](int r, int c, T acc_rc) {
-    const int64_t gr = i0 + r, gc = j0 + c;
-    if (gr < n && gc < n) {
-      const T v = A[gr * n + gc] - acc_rc;
-      if (last) W[r][c] = v;
-      else A[gr * n + gc] = v;
-    } else if (last) {
-      W[r][c] = (r == c) ? T(1) : T(0);
-    }
-  };
+  T pre[TL][TL][4];
+#pragma unroll
+  for (int x = 0; x < TL; ++x)
+#pragma unroll
+    for (int y = 0; y < TL; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gr = i0 + rb + 16 * x + mfma_row<T>(lk, q), gc = j0 + cb + 16 * y + lr;
+        pre[x][y][q] = (gr < n && gc < n) ? A[gr * n + gc] : T(0);
+      }
+  __syncthreads();
   {
-    // matrix cores: wave w owns an NB/2 x NB/2 quadrant as TL x TL tiles of
-    // 16 x 16 (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64)
-    constexpr int TL = NB / 32;
-    const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
-    const int rb = (NB / 2) * (w / 2), cb = (NB / 2) * (w % 2);
-    const int lr = lane % 16, lk = lane / 16;
+    // panels on the matrix cores: wave w owns an NB/2 x NB/2 quadrant
+    typename MfmaVec<T>::type pi[TL][TL], pj[TL][TL];
+#pragma unroll
+    for (int x = 0; x < TL; ++x)
+#pragma unroll
+      for (int y = 0; y < TL; ++y) {
+        pi[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
+        pj[x][y] = pi[x][y];
+      }
+#pragma unroll
+    for (int q0 = 0; q0 < NB; q0 += 4) {
+      T ai[TL], aj[TL], bd[TL];
+#pragma unroll
+      for (int x = 0; x < TL; ++x) {
+        ai[x] = Ai[rb + 16 * x + lr][q0 + lk];
+        aj[x] = Aj[rb + 16 * x + lr][q0 + lk];
+        bd[x] = Ds[cb + 16 * x + lr][q0 + lk];
+      }
+#pragma unroll
+      for (int x = 0; x < TL; ++x)
+#pragma unroll
+        for (int y = 0; y < TL; ++y) {
+          pi[x][y] = mfma16x16x4(ai[x], bd[y], pi[x][y]);
+          if (!same) pj[x][y] = mfma16x16x4(aj[x], bd[y], pj[x][y]);
+        }
+    }
+    __syncthreads();      // Ai/Aj become the transposed panels
+#pragma unroll
+    for (int x = 0; x < TL; ++x)
+#pragma unroll
+      for (int y = 0; y < TL; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rb + 16 * x + mfma_row<T>(lk, q), p = cb + 16 * y + lr;
+          Ta[p][r] = pi[x][y][q];
+          if (!same) Tb[p][r] = pj[x][y][q];
+        }
+  }
+  __syncthreads();
+  T (*Tbs)[NB + 1] = same ? Ta : Tb;
+  if (bj == k + 1) {
+#pragma unroll
+    for (int it = 0; it < NB * NB / 256; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      const int r = idx / NB, p = idx % NB;
+      if (i0 + r < n) L[(i0 + r) * n + k0 + p] = Ta[p][r];
+      const int p2 = idx / NB, r2 = idx % NB;
+      if (i0 + r2 < n) Lt[(k0 + p2) * n + i0 + r2] = Ta[p2][r2];
+    }
+  }
+  {
     typename MfmaVec<T>::type acc[TL][TL];
 #pragma unroll
     for (int x = 0; x < TL; ++x)
@@ -310,55 +413,40 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
 #pragma unroll
       for (int x = 0; x < TL; ++x) {
         av[x] = Ta[p0 + lk][rb + 16 * x + lr];
-        bv[x] = Tb[p0 + lk][cb + 16 * x + lr];
+        bv[x] = Tbs[p0 + lk][cb + 16 * x + lr];
       }
 #pragma unroll
       for (int x = 0; x < TL; ++x)
 #pragma unroll
         for (int y = 0; y < TL; ++y) acc[x][y] = mfma16x16x4(av[x], bv[y], acc[x][y]);
     }
-    if (last) __syncthreads();      // Ta/Tb are overwritten by W below
 #pragma unroll
     for (int x = 0; x < TL; ++x)
 #pragma unroll
       for (int y = 0; y < TL; ++y)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) put(rb + 16 * x + mfma_row<T>(lk, q), cb + 16 * y + lr, acc[x][y][q]);
+        for (int q = 0; q < 4; ++q) {
+          const int r = rb + 16 * x + mfma_row<T>(lk, q), c = cb + 16 * y + lr;
+          const int64_t gr = i0 + r, gc = j0 + c;
+          const T v = pre[x][y][q] - acc[x][y][q];
+          if (last) W[r][c] = (gr < n && gc < n) ? v : (r == c ? T(1) : T(0));
+          else if (gr < n && gc < n) A[gr * n + gc] = v;
+        }
   }
   if (!last) return;
   __syncthreads();
   const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
-  if (threadIdx.x < PDIPC_WAVE) factor_diag_wave<T, NB>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
-}
-
-
-// ---- inverses of the diagonal blocks (one wave per block, all blocks at once) --
-// Lane c holds column c of L_kk^-1 in registers and forms it by forward
-// substitution; rows/columns beyond the matrix are the identity.
-template <typename T, int NB>
-__global__ void __launch_bounds__(64) chol_diaginv_kernel(const T* __restrict__ Lt, const T* __restrict__ dinv,
-                                                          int64_t n, T* __restrict__ Dinv) {
-  __shared__ T LkT[NB][NB + 1];
-  __shared__ T dk[NB];
-  const int lane = threadIdx.x;
-  const int64_t k0 = static_cast<int64_t>(blockIdx.x) * NB;
-  const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-  if (lane < NB) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-      LkT[c][lane] = (c < kb && lane < kb) ? (lane >= c ? Lt[(k0 + c) * n + k0 + lane] : T(0)) : T(0);
-    dk[lane] = lane < kb ? dinv[k0 + lane] : T(1);
+  if constexpr (NB == 32) {
+    T (*X)[33] = Ai;      // the panels are consumed
+    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, i0, info, colbuf, dk);
+    __syncthreads();
+    store_diag32<T>(W, X, dk, kb, i0, n, L, Lt, dinv, Dinv + (k + 1) * NB * NB);
+  } else if (threadIdx.x < PDIPC_WAVE) {
+    factor_diag_wave<T, NB>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
+    invert_diag_wave<T, NB>(W, colbuf, Dinv + (k + 1) * NB * NB);
   }
-  __syncthreads();
-  if (lane >= NB) return;
-  T v[NB];
-#pragma unroll
-  for (int r = 0; r < NB; ++r) v[r] = (r == lane) ? T(1) : T(0);
-  forward_subst_regs<T, NB>(v, LkT, dk);
-  T* D = Dinv + static_cast<int64_t>(blockIdx.x) * NB * NB;
-#pragma unroll
-  for (int r = 0; r < NB; ++r) D[r * NB + lane] = v[r];
 }
+
 
 // Block size: 32 keeps the serial chain of diagonal factorisations short for
 // the reduced systems of a few thousand unknowns; 64 feeds the matrix cores
@@ -369,15 +457,15 @@ template <typename T, int NB>
 static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
   T* Lt = aux;
   T* dinv = aux + n * n;
+  T* Dinv = aux + n * n + n;
   const int64_t nblk = (n + NB - 1) / NB;
-  chol_first_kernel<T, NB><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, d_info);
-  const size_t shm = sizeof(T) * 2 * NB * NB;
+  chol_first_kernel<T, NB><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, Dinv, d_info);
+  const size_t shm = sizeof(T) * 3 * NB * (NB + 1);
   for (int64_t k = 0; k + 1 < nblk; ++k) {
     const int64_t m = nblk - k - 1;
     chol_update_kernel<T, NB><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Lt, dinv,
-                                                                                         d_info);
+                                                                                         Dinv, d_info);
   }
-  chol_diaginv_kernel<T, NB><<<static_cast<unsigned>(nblk), 64, 0, st>>>(Lt, dinv, n, aux + n * n + n);
 }
 
 template <typename T>
