@@ -211,9 +211,11 @@ __device__ __forceinline__ void invert_diag_wave(const T (*W)[NB + 1], const T* 
 
 // NB = 32: the 32-lane rows of the tile leave the upper half of the wave idle,
 // so lanes 32 + c carry column c of the identity through the same steps: with
-// the column of L broadcast for the trailing update they forward-substitute
-// it, and end holding column c of L_kk^-1.  The factor goes to W (rows), the
-// inverse to X, 1 / diag(L_kk) to dk; same pivot rules as factor_diag_wave.
+// the column of L broadcast for the trailing update (FP64: readlane into
+// scalar registers; FP32: through LDS, measured faster there) they
+// forward-substitute it, and end holding
+// column c of L_kk^-1.  The inverse goes to X and 1 / diag(L_kk) to dk (the
+// factor itself is not kept); same pivot rules as factor_diag_wave.
 template <typename T>
 __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int kb, int64_t k0,
                                                      int32_t* __restrict__ info, T* colbuf, T* dk) {
@@ -235,15 +237,18 @@ __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int
     const T l = (lane == j) ? d * isd : a[j] * isd;
     a[j] = l;
     myinv = (lane == j) ? isd : myinv;
-    colbuf[lane] = l;
-    __builtin_amdgcn_wave_barrier();
+    if constexpr (sizeof(T) == 8) {
 #pragma unroll
-    for (int c = j + 1; c < 32; ++c) a[c] -= l * colbuf[c];
-    __builtin_amdgcn_wave_barrier();
+      for (int c = j + 1; c < 32; ++c) a[c] -= l * read_lane(l, c);
+    } else {
+      colbuf[lane] = l;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int c = j + 1; c < 32; ++c) a[c] -= l * colbuf[c];
+      __builtin_amdgcn_wave_barrier();
+    }
   }
   if (rowlane) {
-#pragma unroll
-    for (int c = 0; c < 32; ++c) W[rr][c] = a[c];
     dk[rr] = myinv;
   } else {
 #pragma unroll
@@ -252,21 +257,136 @@ __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int
   if (first_bad != 0 && lane == 0 && *info == 0) *info = static_cast<int32_t>(k0 + first_bad);
 }
 
-// Stores a factored and inverted 32 x 32 diagonal block with the whole
-// workgroup (coalesced): L and Lt (rows/columns < kb), dinv, the inverse D.
+// Stores 1 / diag(L_kk) and the inverse D of a factored 32 x 32 diagonal block
+// with the whole workgroup (coalesced).
 template <typename T>
-__device__ __forceinline__ void store_diag32(const T (*W)[33], const T (*X)[33], const T* dk, int kb, int64_t k0,
-                                             int64_t n, T* __restrict__ L, T* __restrict__ Lt,
+__device__ __forceinline__ void store_diag32(const T (*X)[33], const T* dk, int kb, int64_t k0,
                                              T* __restrict__ dinv, T* __restrict__ D) {
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     const int idx = threadIdx.x + 256 * it;
-    const int r = idx / 32, c = idx % 32;
-    if (r < kb && c <= r) L[(k0 + r) * n + k0 + c] = W[r][c];
-    if (c < kb && c >= r) Lt[(k0 + r) * n + k0 + c] = W[c][r];
-    D[idx] = X[r][c];
+    D[idx] = X[idx / 32][idx % 32];
   }
   if (threadIdx.x < kb) dinv[k0 + threadIdx.x] = dk[threadIdx.x];
+}
+
+// ---- L^-1 along the factorisation (NB = 32) ----------------------------------
+// The substitution L Y = I runs block by block with the factor: Y_kj =
+// L_kk^-1 B_kj, then B_ij -= L_ik Y_kj for i > k, starting from B = I.  The
+// working blocks B_ij (i > j) live in the strictly upper blocks of A, which the
+// factorisation never touches: B_ij[r][c] at A[(j0 + c) n + i0 + r].  Block
+// step k adds one workgroup per tile (i, j), i > k >= j: it forms L_ik =
+// A_ik (L_kk^-1)^T as the trailing tiles do, Y_kj (B_kk = I, so Y_kk = L_kk^-1
+// and B_ik starts from zero), and the update, all on the matrix cores; the
+// tiles of block row k + 1 store Y_kj to F (row-major) and Yt (transposed).
+// The last block row follows in a launch of its own.
+template <typename T>
+__device__ __forceinline__ void rhs_tile_step(T* __restrict__ A, int64_t n, int64_t k, int64_t t,
+                                              T* __restrict__ F, T* __restrict__ Yt,
+                                              const T* __restrict__ Dinv, unsigned char* smem_raw) {
+  constexpr int NB = 32;
+  T (*Ds)[NB + 1] = reinterpret_cast<T (*)[NB + 1]>(smem_raw);  // L_kk^-1
+  T (*Ai)[NB + 1] = Ds + NB;                                     // A_ik, then Ta[p][r] = L_ik[r][p]
+  T (*Bk)[NB + 1] = Ai + NB;                                     // B_kj, then Y_kj
+  T (*Ta)[NB + 1] = Ai;
+  T (*Yl)[NB + 1] = Bk;
+  const int64_t bi = k + 1 + t / (k + 1), bj = t % (k + 1);
+  const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
+  const bool diag = bj == k;
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int rb = 16 * (w / 2), cb = 16 * (w % 2);
+  const int lr = lane % 16, lk = lane / 16;
+  const T* D = Dinv + k * NB * NB;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    const int r = idx / NB, c = idx % NB;
+    Ds[r][c] = D[idx];
+    Ai[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);
+    if (!diag) Bk[c][r] = A[(j0 + r) * n + k0 + c];       // B_kj[c][r]; block k is full
+  }
+  T pre[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rb + mfma_row<T>(lk, q), c = cb + lr;
+    pre[q] = (!diag && i0 + r < n) ? A[(j0 + c) * n + i0 + r] : T(0);
+  }
+  __syncthreads();
+  typename MfmaVec<T>::type pm = {T(0), T(0), T(0), T(0)}, ym = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int q0 = 0; q0 < NB; q0 += 4) {
+    pm = mfma16x16x4(Ai[rb + lr][q0 + lk], Ds[cb + lr][q0 + lk], pm);
+    if (!diag) ym = mfma16x16x4(Ds[rb + lr][q0 + lk], Bk[q0 + lk][cb + lr], ym);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rb + mfma_row<T>(lk, q);
+    Ta[cb + lr][r] = pm[q];
+    if (!diag) Yl[r][cb + lr] = ym[q];
+  }
+  __syncthreads();
+  T (*Yk)[NB + 1] = diag ? Ds : Yl;
+  if (bi == k + 1) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      F[(k0 + idx / NB) * n + j0 + idx % NB] = Yk[idx / NB][idx % NB];
+      Yt[(j0 + idx / NB) * n + k0 + idx % NB] = Yk[idx % NB][idx / NB];
+    }
+  }
+  typename MfmaVec<T>::type acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int p0 = 0; p0 < NB; p0 += 4) acc = mfma16x16x4(Ta[p0 + lk][rb + lr], Yk[p0 + lk][cb + lr], acc);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rb + mfma_row<T>(lk, q), c = cb + lr;
+    if (i0 + r < n) A[(j0 + c) * n + i0 + r] = pre[q] - acc[q];
+  }
+}
+
+// Last block row of L^-1: Y_lj = L_ll^-1 B_lj (Y_ll = L_ll^-1), one workgroup
+// per block column j.
+template <typename T>
+__global__ void __launch_bounds__(256) chol_lastrow_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ F,
+                                                           T* __restrict__ Yt, const T* __restrict__ Dinv) {
+  constexpr int NB = 32;
+  __shared__ T Ds[NB][NB + 1];
+  __shared__ T Bl[NB][NB + 1];
+  __shared__ T Yl[NB][NB + 1];
+  const int64_t nblk = (n + NB - 1) / NB, last = nblk - 1;
+  const int64_t bj = blockIdx.x, i0 = last * NB, j0 = bj * NB;
+  const int kb = static_cast<int>(n - i0);
+  const bool diag = bj == last;
+  const T* D = Dinv + last * NB * NB;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    Ds[idx / NB][idx % NB] = D[idx];
+    const int r = idx % NB, c = idx / NB;
+    Bl[r][c] = (!diag && r < kb) ? A[(j0 + c) * n + i0 + r] : T(0);
+  }
+  __syncthreads();
+  if (!diag) {
+    const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+    const int rb = 16 * (w / 2), cb = 16 * (w % 2);
+    const int lr = lane % 16, lk = lane / 16;
+    typename MfmaVec<T>::type ym = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int q0 = 0; q0 < NB; q0 += 4) ym = mfma16x16x4(Ds[rb + lr][q0 + lk], Bl[q0 + lk][cb + lr], ym);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Yl[rb + mfma_row<T>(lk, q)][cb + lr] = ym[q];
+  }
+  __syncthreads();
+  T (*Yk)[NB + 1] = diag ? Ds : Yl;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    const int p = idx / NB, c = idx % NB;
+    if (p < kb && (!diag || c < kb)) F[(i0 + p) * n + j0 + c] = Yk[p][c];
+    const int c2 = idx / NB, p2 = idx % NB;
+    if (p2 < kb && (!diag || c2 < kb)) Yt[(j0 + c2) * n + i0 + p2] = Yk[p2][c2];
+  }
 }
 
 template <typename T, int NB>
@@ -289,7 +409,7 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
   if constexpr (NB == 32) {
     if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, colbuf, dk);
     __syncthreads();
-    store_diag32<T>(W, X, dk, kb, 0, n, L, Lt, dinv, Dinv);
+    store_diag32<T>(X, dk, kb, 0, dinv, Dinv);
   } else if (threadIdx.x < PDIPC_WAVE) {
     factor_diag_wave<T, NB>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
     invert_diag_wave<T, NB>(W, colbuf, Dinv);
@@ -320,6 +440,12 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   const int64_t nblk = (n + NB - 1) / NB;
   const int64_t m = nblk - k - 1;
   int64_t t = blockIdx.x, ii = 0;
+  if constexpr (NB == 32) {
+    if (t >= m * (m + 1) / 2) {
+      rhs_tile_step<T>(A, n, k, t - m * (m + 1) / 2, L, Lt, Dinv, smem_raw);
+      return;
+    }
+  }
   while (t >= m - ii) { t -= m - ii; ++ii; }
   const int64_t bj = k + 1 + ii, bi = bj + t;
   const int64_t k0 = k * NB, i0 = bi * NB, j0 = bj * NB;
@@ -391,7 +517,7 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   }
   __syncthreads();
   T (*Tbs)[NB + 1] = same ? Ta : Tb;
-  if (bj == k + 1) {
+  if (NB != 32 && bj == k + 1) {
 #pragma unroll
     for (int it = 0; it < NB * NB / 256; ++it) {
       const int idx = threadIdx.x + 256 * it;
@@ -440,7 +566,7 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
     T (*X)[33] = Ai;      // the panels are consumed
     if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, i0, info, colbuf, dk);
     __syncthreads();
-    store_diag32<T>(W, X, dk, kb, i0, n, L, Lt, dinv, Dinv + (k + 1) * NB * NB);
+    store_diag32<T>(X, dk, kb, i0, dinv, Dinv + (k + 1) * NB * NB);
   } else if (threadIdx.x < PDIPC_WAVE) {
     factor_diag_wave<T, NB>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
     invert_diag_wave<T, NB>(W, colbuf, Dinv + (k + 1) * NB * NB);
@@ -463,9 +589,10 @@ static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hi
   const size_t shm = sizeof(T) * 3 * NB * (NB + 1);
   for (int64_t k = 0; k + 1 < nblk; ++k) {
     const int64_t m = nblk - k - 1;
-    chol_update_kernel<T, NB><<<static_cast<unsigned>(m * (m + 1) / 2), 256, shm, st>>>(A, n, k, L, Lt, dinv,
-                                                                                         Dinv, d_info);
+    const int64_t tiles = m * (m + 1) / 2 + (NB == 32 ? m * (k + 1) : 0);
+    chol_update_kernel<T, NB><<<static_cast<unsigned>(tiles), 256, shm, st>>>(A, n, k, L, Lt, dinv, Dinv, d_info);
   }
+  if (NB == 32) chol_lastrow_kernel<T><<<static_cast<unsigned>(nblk), 256, 0, st>>>(A, n, L, Lt, Dinv);
 }
 
 template <typename T>
@@ -548,103 +675,53 @@ __global__ void __launch_bounds__(512) chol_solve_kernel(const T* __restrict__ L
   }
 }
 
-// Single right-hand side with the whole vector in LDS (up to SOLVE_LDS_BYTES):
-// the block steps then read only L, Lt and the diagonal-block inverses from
-// memory, and the next block inverse is fetched while the rows below update.
-constexpr int SOLVE_LDS_BYTES = 48 * 1024;
-template <typename T, int NB>
-__global__ void __launch_bounds__(512) chol_solve1_lds_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
-                                                              const T* __restrict__ Dinv, int64_t n,
-                                                              T* __restrict__ b) {
-  extern __shared__ unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);
-  __shared__ T Di[2][NB][NB + 1];
-  __shared__ T ys[NB];
-  constexpr int DPT = NB * NB / 512 > 0 ? NB * NB / 512 : 1;   // block-inverse entries per thread
-  const int nblk = static_cast<int>((n + NB - 1) / NB);
-  for (int64_t i = threadIdx.x; i < n; i += 512) xs[i] = b[i];
-  auto fetch = [&](int bk, T reg[DPT]) {
-    const T* D = Dinv + static_cast<int64_t>(bk) * NB * NB;
+// Row-major triangular matrix times nrhs <= 4 vectors (n x nrhs row-major):
+// y_r = sum over the columns c <= r (LOWER) or c >= r of M[r][c] x_c.  One
+// wave per row, coalesced along the row.
+template <typename T, bool LOWER>
+__global__ void __launch_bounds__(256) tri_gemv_kernel(const T* __restrict__ M, int64_t n, const T* __restrict__ x,
+                                                       T* __restrict__ y, int nrhs) {
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  if (row >= n) return;
+  const int64_t c0 = LOWER ? 0 : row, c1 = LOWER ? row + 1 : n;
+  const T* Mr = M + row * n;
+  T s[4] = {T(0), T(0), T(0), T(0)};
+  if (nrhs == 1) {
+    for (int64_t c = c0 + lane; c < c1; c += PDIPC_WAVE) s[0] += Mr[c] * x[c];
+  } else {
+    for (int64_t c = c0 + lane; c < c1; c += PDIPC_WAVE) {
+      const T m = Mr[c];
 #pragma unroll
-    for (int q = 0; q < DPT; ++q) {
-      const int idx = threadIdx.x + 512 * q;
-      reg[q] = idx < NB * NB ? D[idx] : T(0);
+      for (int q = 0; q < 4; ++q)
+        if (q < nrhs) s[q] += m * x[c * nrhs + q];
     }
-  };
-  auto put = [&](int buf, const T reg[DPT]) {
-#pragma unroll
-    for (int q = 0; q < DPT; ++q) {
-      const int idx = threadIdx.x + 512 * q;
-      if (idx < NB * NB) Di[buf][idx / NB][idx % NB] = reg[q];
-    }
-  };
-  T reg[DPT];
-  // forward: L y = b
-  fetch(0, reg);
-  put(0, reg);
-  __syncthreads();
-  for (int bk = 0; bk < nblk; ++bk) {
-    const int64_t k0 = static_cast<int64_t>(bk) * NB;
-    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    const int cur = bk & 1;
-    if (threadIdx.x < NB) {
-      const int r = threadIdx.x;
-      T acc = T(0);
-      for (int c = 0; c <= r; ++c) acc += Di[cur][r][c] * (c < kb ? xs[k0 + c] : T(0));
-      ys[r] = acc;
-    }
-    if (bk + 1 < nblk) fetch(bk + 1, reg);
-    __syncthreads();
-    if (threadIdx.x < kb) xs[k0 + threadIdx.x] = ys[threadIdx.x];
-    for (int64_t gr = k0 + kb + threadIdx.x; gr < n; gr += 512) {
-      T sacc = T(0);
-#pragma unroll
-      for (int c = 0; c < NB; ++c) sacc += (c < kb ? Lt[(k0 + c) * n + gr] : T(0)) * ys[c];
-      xs[gr] -= sacc;
-    }
-    if (bk + 1 < nblk) put(cur ^ 1, reg);
-    __syncthreads();
   }
-  // backward: L^T x = y
-  fetch(nblk - 1, reg);
-  put((nblk - 1) & 1, reg);
-  __syncthreads();
-  for (int bk = nblk - 1; bk >= 0; --bk) {
-    const int64_t k0 = static_cast<int64_t>(bk) * NB;
-    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    const int cur = bk & 1;
-    if (threadIdx.x < NB) {
-      const int c = threadIdx.x;
-      T acc = T(0);
-      for (int r = c; r < NB; ++r) acc += Di[cur][r][c] * (r < kb ? xs[k0 + r] : T(0));
-      ys[c] = acc;
-    }
-    if (bk > 0) fetch(bk - 1, reg);
-    __syncthreads();
-    if (threadIdx.x < kb) xs[k0 + threadIdx.x] = ys[threadIdx.x];
-    for (int64_t gc = threadIdx.x; gc < k0; gc += 512) {
-      T sacc = T(0);
 #pragma unroll
-      for (int c = 0; c < NB; ++c) sacc += (c < kb ? L[(k0 + c) * n + gc] : T(0)) * ys[c];
-      xs[gc] -= sacc;
-    }
-    if (bk > 0) put(cur ^ 1, reg);
-    __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int off = PDIPC_WAVE / 2; off > 0; off /= 2) s[q] += __shfl_xor(s[q], off, PDIPC_WAVE);
   }
-  for (int64_t i = threadIdx.x; i < n; i += 512) b[i] = xs[i];
+  if (lane < nrhs) {
+    T v = s[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) v = (lane == q) ? s[q] : v;
+    y[row * nrhs + lane] = v;
+  }
 }
 
 template <typename T>
-void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
+void dense_chol_solve(const T* L, T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
   if (n <= 0) return;
-  const T* Dinv = aux + n * n + n;
-  const size_t xs_bytes = sizeof(T) * static_cast<size_t>(n);
-  if (nrhs == 1 && dense_block(n) == 32 && xs_bytes <= static_cast<size_t>(SOLVE_LDS_BYTES)) {
-    chol_solve1_lds_kernel<T, 32><<<1, 512, xs_bytes, st>>>(L, aux, Dinv, n, b);
+  if (dense_block(n) == 32) {
+    // x = Y^T (Y b) with Y = L^-1 (F, row-major) and Y^T (aux)
+    T* z = aux + dense_tmp_offset(n);
+    const unsigned g = static_cast<unsigned>((n + 3) / 4);
+    tri_gemv_kernel<T, true><<<g, 256, 0, st>>>(L, n, b, z, nrhs);
+    tri_gemv_kernel<T, false><<<g, 256, 0, st>>>(aux, n, z, b, nrhs);
     return;
   }
-  if (dense_block(n) == 32) chol_solve_kernel<T, 32><<<1, 512, 0, st>>>(L, aux, Dinv, n, b, nrhs);
-  else chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(L, aux, Dinv, n, b, nrhs);
+  chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(L, aux, aux + n * n + n, n, b, nrhs);
 }
 
 // ---- Y = L^-1, one workgroup per column block ----------------------------------
@@ -715,14 +792,22 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
   }
 }
 
+// work = lower part of F with zeros above (Y = L^-1 for NB = 32)
+template <typename T>
+__global__ void lower_copy_kernel(const T* __restrict__ F, int64_t n, T* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  out[i] = (i % n <= i / n) ? F[i] : T(0);
+}
+
 template <typename T>
 void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st) {
   if (n <= 0) return;
-  const T* Dinv = aux + n * n + n;
-  if (dense_block(n) == 32)
-    chol_linv_kernel<T, 32><<<grid_for(n, 32), 256, 0, st>>>(L, Dinv, n, work);
-  else
-    chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, Dinv, n, work);
+  if (dense_block(n) == 32) {
+    lower_copy_kernel<T><<<grid_for(n * n, 256), 256, 0, st>>>(L, n, work);
+  } else {
+    chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, aux + n * n + n, n, work);
+  }
   const unsigned g = grid_for(n, 64);
   dim3 grid(g, g);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
@@ -798,8 +883,8 @@ void launch_scaled_accumulate(const float* y, int64_t n, const double* sc, doubl
 
 template void dense_cholesky<double>(double*, int64_t, double*, double*, int32_t*, hipStream_t);
 template void dense_cholesky<float>(float*, int64_t, float*, float*, int32_t*, hipStream_t);
-template void dense_chol_solve<double>(const double*, const double*, int64_t, double*, int32_t, hipStream_t);
-template void dense_chol_solve<float>(const float*, const float*, int64_t, float*, int32_t, hipStream_t);
+template void dense_chol_solve<double>(const double*, double*, int64_t, double*, int32_t, hipStream_t);
+template void dense_chol_solve<float>(const float*, float*, int64_t, float*, int32_t, hipStream_t);
 template void dense_chol_inverse<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
 template void dense_chol_inverse<float>(const float*, const float*, int64_t, float*, float*, hipStream_t);
 

@@ -204,20 +204,25 @@ void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x
 void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
 
 // ---------------------------------------------------------------- dense SPD
-// Lower Cholesky of an n x n row-major SPD matrix A (lower triangle read,
-// destroyed).  Writes the lower triangle of L (n x n row-major; the strict
-// upper part is not written) and, in aux (dense_aux_size(n) entries), the
-// transpose Lt (n x n), 1 / diag(L) (n) and the inverses of the 64 x 64
-// diagonal blocks.  *d_info <- 0 ok, else 1 + the first failing column.
-inline int64_t dense_aux_size(int64_t n) { return n * n + n + ((n + 63) / 64) * 64 * 64 + 64; }
+// Lower Cholesky of an n x n row-major SPD matrix A (destroyed: lower tiles by
+// the factorisation, strictly upper blocks as workspace).  With 32-wide blocks
+// (n <= 2048) F receives L^-1 (lower triangle, row-major) and aux its
+// transpose; with 64-wide blocks F receives L (lower triangle) and aux its
+// transpose Lt.  aux (dense_aux_size(n) entries) then holds 1 / diag(L) (n),
+// the inverses of the diagonal blocks and solve scratch (4 n).  The strict
+// upper part of F is not written.  *d_info <- 0 ok, else 1 + the first
+// failing column.
+inline int64_t dense_blocks_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
+inline int64_t dense_tmp_offset(int64_t n) { return n * n + n + dense_blocks_size(n); }
+inline int64_t dense_aux_size(int64_t n) { return dense_tmp_offset(n) + 4 * n + 64; }
 template <typename T>
-void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st);
+void dense_cholesky(T* A, int64_t n, T* F, T* aux, int32_t* d_info, hipStream_t st);
 // Solve L L^T x = b in place (b: n x nrhs row-major, nrhs <= 4).
 template <typename T>
-void dense_chol_solve(const T* L, const T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st);
+void dense_chol_solve(const T* F, T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st);
 // Ainv = (L L^T)^-1 (full symmetric, row-major), work: n x n scratch
 template <typename T>
-void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st);
+void dense_chol_inverse(const T* F, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st);
 void launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t st);
 // Jacobi scaling sc_i = 1/sqrt(M_ii); FP32 copies of S M S and S r; u += S y
