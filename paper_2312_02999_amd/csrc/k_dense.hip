@@ -792,6 +792,115 @@ __global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L,
   }
 }
 
+bool dense_has_inverse(int64_t n) { return n > 0 && dense_block(n) == 32; }
+
+template <typename T>
+__global__ void copy_vec_kernel(const T* __restrict__ in, int64_t n, T* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+// Single right-hand side into a separate output: x = Y^T (Y b) for 32-wide
+// blocks, else a copy and the in-place block solve.
+template <typename T>
+void dense_chol_solve_into(const T* F, T* aux, int64_t n, const T* b, T* x, hipStream_t st) {
+  if (n <= 0) return;
+  if (dense_block(n) == 32) {
+    T* z = aux + dense_tmp_offset(n);
+    const unsigned g = static_cast<unsigned>((n + 3) / 4);
+    tri_gemv_kernel<T, true><<<g, 256, 0, st>>>(F, n, b, z, 1);
+    tri_gemv_kernel<T, false><<<g, 256, 0, st>>>(aux, n, z, x, 1);
+    return;
+  }
+  copy_vec_kernel<T><<<grid_for(n, 256), 256, 0, st>>>(b, n, x);
+  chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(F, aux, aux + n * n + n, n, x, 1);
+}
+
+// ---- iterative refinement on an FP32 inverse factor (32-wide blocks) ---------
+// Step s: r_s = rhs - M u_s in FP64 (u_0 = 0), res[s] = max |r_s|; unless
+// res[s] <= tol res[0], u_{s+1} = u_s + S Y^T Y S r_s with the FP32 factor of
+// S M S.  Every kernel of a step returns at once when the previous residual
+// already met the tolerance, so several steps are queued without a readback
+// (res must start at zero).
+__device__ __forceinline__ bool refined(const double* res, int s, double tol) {
+  return res[s] <= tol * res[0];
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = PDIPC_WAVE / 2; off > 0; off /= 2) v += __shfl_xor(v, off, PDIPC_WAVE);
+  return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int off = PDIPC_WAVE / 2; off > 0; off /= 2) v += __shfl_xor(v, off, PDIPC_WAVE);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) refine_residual_kernel(const double* __restrict__ M, int64_t n,
+                                                              const double* __restrict__ rhs,
+                                                              const double* __restrict__ u,
+                                                              const double* __restrict__ sc, float* __restrict__ out,
+                                                              double* __restrict__ res, int s, double tol) {
+  if (s > 0 && refined(res, s - 1, tol)) return;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  if (row >= n) return;
+  double acc = 0.0;
+  if (s > 0) {
+    const double* Mr = M + row * n;
+    for (int64_t c = lane; c < n; c += PDIPC_WAVE) acc += Mr[c] * u[c];
+    acc = wave_sum_d(acc);
+  }
+  if (lane == 0) {
+    const double r = rhs[row] - acc;
+    out[row] = static_cast<float>(sc[row] * r);
+    atomicMax(reinterpret_cast<unsigned long long*>(res + s), static_cast<unsigned long long>(__double_as_longlong(fabs(r))));
+  }
+}
+
+__global__ void __launch_bounds__(256) refine_lower_kernel(const float* __restrict__ Y, int64_t n,
+                                                           const float* __restrict__ r, float* __restrict__ z,
+                                                           const double* __restrict__ res, int s, double tol) {
+  if (refined(res, s, tol)) return;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  if (row >= n) return;
+  const float* Yr = Y + row * n;
+  float acc = 0.0f;
+  for (int64_t c = lane; c <= row; c += PDIPC_WAVE) acc += Yr[c] * r[c];
+  acc = wave_sum_f(acc);
+  if (lane == 0) z[row] = acc;
+}
+
+__global__ void __launch_bounds__(256) refine_upper_kernel(const float* __restrict__ Yt, int64_t n,
+                                                           const float* __restrict__ z, const double* __restrict__ sc,
+                                                           double* __restrict__ u, const double* __restrict__ res,
+                                                           int s, double tol) {
+  if (refined(res, s, tol)) return;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  if (row >= n) return;
+  const float* Yr = Yt + row * n;
+  float acc = 0.0f;
+  for (int64_t c = row + lane; c < n; c += PDIPC_WAVE) acc += Yr[c] * z[c];
+  acc = wave_sum_f(acc);
+  if (lane == 0) u[row] += sc[row] * static_cast<double>(acc);
+}
+
+void launch_refine_residual(const double* M, int64_t n, const double* rhs, const double* u, const double* sc,
+                            float* r32, double* res, int s, double tol, hipStream_t st) {
+  if (n > 0)
+    refine_residual_kernel<<<static_cast<unsigned>((n + 3) / 4), 256, 0, st>>>(M, n, rhs, u, sc, r32, res, s, tol);
+}
+void launch_refine_correct(const float* F, float* aux, int64_t n, const float* r32, const double* sc, double* u,
+                           const double* res, int s, double tol, hipStream_t st) {
+  if (n <= 0) return;
+  float* z = aux + dense_tmp_offset(n);
+  const unsigned g = static_cast<unsigned>((n + 3) / 4);
+  refine_lower_kernel<<<g, 256, 0, st>>>(F, n, r32, z, res, s, tol);
+  refine_upper_kernel<<<g, 256, 0, st>>>(aux, n, z, sc, u, res, s, tol);
+}
+
 // work = lower part of F with zeros above (Y = L^-1 for NB = 32)
 template <typename T>
 __global__ void lower_copy_kernel(const T* __restrict__ F, int64_t n, T* __restrict__ out) {
@@ -885,6 +994,8 @@ template void dense_cholesky<double>(double*, int64_t, double*, double*, int32_t
 template void dense_cholesky<float>(float*, int64_t, float*, float*, int32_t*, hipStream_t);
 template void dense_chol_solve<double>(const double*, double*, int64_t, double*, int32_t, hipStream_t);
 template void dense_chol_solve<float>(const float*, float*, int64_t, float*, int32_t, hipStream_t);
+template void dense_chol_solve_into<double>(const double*, double*, int64_t, const double*, double*, hipStream_t);
+template void dense_chol_solve_into<float>(const float*, float*, int64_t, const float*, float*, hipStream_t);
 template void dense_chol_inverse<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
 template void dense_chol_inverse<float>(const float*, const float*, int64_t, float*, float*, hipStream_t);
 

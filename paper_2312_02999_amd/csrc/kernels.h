@@ -220,6 +220,20 @@ void dense_cholesky(T* A, int64_t n, T* F, T* aux, int32_t* d_info, hipStream_t 
 // Solve L L^T x = b in place (b: n x nrhs row-major, nrhs <= 4).
 template <typename T>
 void dense_chol_solve(const T* F, T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st);
+// Single right-hand side, b -> x (no aliasing).
+template <typename T>
+void dense_chol_solve_into(const T* F, T* aux, int64_t n, const T* b, T* x, hipStream_t st);
+// True when dense_cholesky leaves L^-1 in F (32-wide blocks).
+bool dense_has_inverse(int64_t n);
+// Iterative refinement of M u = rhs with the FP32 inverse factor (F, aux) of
+// S M S, S = diag(sc): step s computes r_s = rhs - M u_s (u_0 = 0) in FP64,
+// res[s] = max |r_s| and r32 = float(S r_s) (launch_refine_residual), then
+// u += S Y^T Y r32 (launch_refine_correct).  Kernels of a step do nothing once
+// an earlier res met res <= tol res[0]; res (>= steps + 1 entries) starts at 0.
+void launch_refine_residual(const double* M, int64_t n, const double* rhs, const double* u, const double* sc,
+                            float* r32, double* res, int s, double tol, hipStream_t st);
+void launch_refine_correct(const float* F, float* aux, int64_t n, const float* r32, const double* sc, double* u,
+                           const double* res, int s, double tol, hipStream_t st);
 // Ainv = (L L^T)^-1 (full symmetric, row-major), work: n x n scratch
 template <typename T>
 void dense_chol_inverse(const T* F, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st);

@@ -61,7 +61,9 @@ struct DBuf {
       if (counter) *counter -= static_cast<int64_t>(sizeof(T)) * cap;
     }
     p = nullptr;
-    int64_t c = std::max<int64_t>(count, 1);
+    // regrowth is geometric: sizes that creep up over a frame (contact counts)
+    // would otherwise free and reallocate, and hipFree waits for the device
+    int64_t c = std::max<int64_t>(count, cap > 0 ? cap + cap / 2 : 1);
     if (hipMalloc(&p, sizeof(T) * c) != hipSuccess) {
       p = nullptr;
       cap = 0;
@@ -140,6 +142,7 @@ struct Solver {
   bool cinv_valid = false;
   // device line-search state; factor statuses still to be checked
   DBuf<double> lsbuf;
+  DBuf<double> refres;        // refinement residual maxima
   bool check_info_m = false, check_info_cs = false;
   // adjoint work vectors
   DBuf<double> lam, res, zvec, pvec, kp, prod, pairbuf;
@@ -649,15 +652,32 @@ static int32_t read_scalar_i(Solver* S, const int32_t* dptr) {
   return v;
 }
 
+struct IterOut;
+static void finish_readback(Solver* S, IterOut& io);
+
 struct IterOut {
   int32_t npt = 0, nee = 0, nc = 0, ncand = 0, halvings = 0;
   bool ls_ok = true;
   bool c_same = false;          // contact set equal to the one C^-1 was built for
+  bool nc_pending = false;      // n_c (and c_same) still in flight to h_scal
+  bool nc_with_same = false;    // the readback carries the c_same flag
   double alpha_m = 1.0, alpha = 0.0;
 };
 
+static void finish_readback(Solver* S, IterOut& io) {
+  if (!io.nc_pending) return;
+  HIPCHK(hipEventSynchronize(S->ev_fork));
+  int32_t h2[2] = {0, 1};
+  std::memcpy(h2, S->h_scal, sizeof(int32_t) * (io.nc_with_same ? 2 : 1));
+  io.nc = h2[0];
+  io.c_same = io.nc_with_same && h2[1] == 0;
+  io.nc_pending = false;
+}
+
 // Local step + constraint set + barrier + gradient; returns pair counts, n_c.
-static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
+// With defer, n_c is left in flight (the fork event marks its copy) and
+// global_step collects it after queueing the sweeps, which need only g.
+static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool defer = false) {
   const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
   hipStream_t st = S->st;
   {
@@ -684,21 +704,115 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io) {
   build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
   launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
   if (S->cinv_valid) launch_differ_i32(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st);
-  int32_t h2[2] = {0, 1};
-  HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (S->cinv_valid ? 2 : 1), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  std::memcpy(h2, S->h_scal, sizeof(int32_t) * (S->cinv_valid ? 2 : 1));
-  io.nc = h2[0];
-  io.c_same = S->cinv_valid && h2[1] == 0;
+  io.nc_with_same = S->cinv_valid;
+  HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (io.nc_with_same ? 2 : 1), hipMemcpyDeviceToHost,
+                        st));
+  HIPCHK(hipEventRecord(S->ev_fork, st));
+  io.nc_pending = true;
+  if (!defer) finish_readback(S, io);
+}
+
+// Mixed path: M u = rhs by iterative refinement with the FP32 factor of the
+// Jacobi-scaled M against FP64 residuals, to max|r| <= 1e-13 max|rhs|; false
+// if the FP32 factor failed or the steps ran out (then the FP64 factor is
+// used).  With the FP32 inverse factor, three steps and the following residual
+// are queued and read back once; steps after convergence do nothing.
+static constexpr double kRefineTol = 1e-13;
+static constexpr int kRefineMaxSteps = 10;
+
+static bool refine_on_inverse(Solver* S, int64_t N3) {
+  hipStream_t st = S->st;
+  constexpr int kQueued = 3;
+  S->refres.ensure(kRefineMaxSteps + 2);
+  launch_fill_f64(S->refres.p, kRefineMaxSteps + 2, 0.0, st);
+  launch_fill_f64(S->u.p, N3, 0.0, st);
+  auto residual = [&](int s) {
+    launch_refine_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->scl.p, S->uf.p, S->refres.p, s, kRefineTol, st);
+  };
+  auto correct = [&](int s) {
+    launch_refine_correct(S->MLf.p, S->MLif.p, N3, S->uf.p, S->scl.p, S->u.p, S->refres.p, s, kRefineTol, st);
+  };
+  for (int s = 0; s < kQueued; ++s) {
+    residual(s);
+    correct(s);
+  }
+  int s = kQueued;
+  residual(s);
+  while (true) {
+    HIPCHK(hipMemcpyAsync(S->h_scal, S->refres.p, sizeof(double) * (s + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(S->h_scal + 12, S->info.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t finfo = 0;
+    std::memcpy(&finfo, S->h_scal + 12, sizeof(int32_t));
+    if (finfo != 0) return false;
+    for (int i = 0; i <= s; ++i)
+      if (S->h_scal[i] <= kRefineTol * S->h_scal[0]) {
+        S->refine_steps += i;
+        return true;
+      }
+    if (s >= kRefineMaxSteps) {
+      S->refine_steps += s;
+      return false;
+    }
+    correct(s);
+    ++s;
+    residual(s);
+  }
+}
+
+// Same refinement with a blocked FP32 factor (reduced systems above 2048
+// unknowns): one step is a scaled FP32 solve, an FP64 residual and its norm.
+static bool refine_on_blocks(Solver* S, int64_t N3) {
+  hipStream_t st = S->st;
+  launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
+  launch_fill_f64(S->u.p, N3, 0.0, st);
+  HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
+  auto refine_step = [&]() {
+    launch_scale_convert_vec(S->resid.p, N3, S->scl.p, S->uf.p, st);
+    dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
+    launch_scaled_accumulate(S->uf.p, N3, S->scl.p, S->u.p, st);
+    launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
+    launch_max_abs(S->resid.p, N3, S->scal.p + 6, S->red_tmp.p, st);
+    S->refine_steps++;
+  };
+  constexpr int kQueued = 2;
+  for (int it = 0; it < kQueued; ++it) refine_step();
+  int done = kQueued;
+  while (true) {
+    HIPCHK(hipMemcpyAsync(S->h_scal, S->scal.p + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(S->h_scal + 2, S->info.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t finfo = 0;
+    std::memcpy(&finfo, S->h_scal + 2, sizeof(int32_t));
+    if (finfo != 0) return false;
+    if (S->h_scal[1] <= kRefineTol * S->h_scal[0]) return true;
+    if (done >= kRefineMaxSteps) return false;
+    refine_step();
+    ++done;
+  }
 }
 
 // Global step of Eq. (4) via Eq. (7) and (11): dx from g.
-static void global_step(Solver* S, const IterOut& io) {
+static void global_step(Solver* S, IterOut& io) {
   hipStream_t st = S->st;
   FactorDev& f = S->fd;
-  const int32_t np = io.npt + io.nee, nc = io.nc;
   const int64_t n1x3 = 3LL * f.n1;
   const bool mixed = S->opt.precision == PDIPC_MIXED_FP32;
+  // the side stream below starts from the fork event: everything queued on
+  // the main stream before this step (the contact terms, C^-1's last users)
+  if (!io.nc_pending) HIPCHK(hipEventRecord(S->ev_fork, st));
+  // Eq. (7) forward part needs only g: queue it before waiting for n_c
+  launch_pack_rhs(f, S->g.p, S->bvec.p, st);
+  {
+    ScopedTimer tm(S, TK_FWD);
+    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
+  }
+  {
+    ScopedTimer tm(S, TK_SIGMA_GEMV);
+    launch_sigma_gemv(f, S->yvec.p + n1x3, S->solvec.p + n1x3, st);
+  }
+  finish_readback(S, io);
+  const int32_t np = io.npt + io.nee, nc = io.nc;
   const int64_t N3 = 3LL * nc;
   if (nc > 0) {
     S->c_x2.ensure(nc);
@@ -724,7 +838,6 @@ static void global_step(Solver* S, const IterOut& io) {
     // The reduced system depends only on the contact terms and C^-1: build and
     // factor it on the side stream while the sweeps run on the main stream.
     hipStream_t sd = S->side;
-    HIPCHK(hipEventRecord(S->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(sd, S->ev_fork, 0));
     if (!io.c_same) {
       launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, sd);
@@ -748,50 +861,11 @@ static void global_step(Solver* S, const IterOut& io) {
       S->check_info_m = true;           // read back with the line-search state
     }
     HIPCHK(hipEventRecord(S->ev_join, sd));
-  }
-  launch_pack_rhs(f, S->g.p, S->bvec.p, st);
-  {
-    ScopedTimer tm(S, TK_FWD);
-    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
-  }
-  {
-    ScopedTimer tm(S, TK_SIGMA_GEMV);
-    launch_sigma_gemv(f, S->yvec.p + n1x3, S->solvec.p + n1x3, st);
-  }
-  if (nc > 0) {
     HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
-    bool solved = !mixed, fallback = false;
+    bool fallback = false;
     if (mixed) {
-      // refined against FP64 residuals of the unscaled system: a few steps are
-      // queued without readback, then the residual is checked once; more steps
-      // (checked each time) or an FP64 refactorisation follow only if needed
-      launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
-      launch_fill_f64(S->u.p, N3, 0.0, st);
-      HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
-      auto refine_step = [&]() {
-        launch_scale_convert_vec(S->resid.p, N3, S->scl.p, S->uf.p, st);
-        dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
-        launch_scaled_accumulate(S->uf.p, N3, S->scl.p, S->u.p, st);
-        launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
-        launch_max_abs(S->resid.p, N3, S->scal.p + 6, S->red_tmp.p, st);
-        S->refine_steps++;
-      };
-      constexpr int kQueued = 2, kMaxSteps = 10;
-      for (int it = 0; it < kQueued; ++it) refine_step();
-      int done = kQueued;
-      while (true) {
-        HIPCHK(hipMemcpyAsync(S->h_scal, S->scal.p + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(S->h_scal + 2, S->info.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        int32_t finfo = 0;
-        std::memcpy(&finfo, S->h_scal + 2, sizeof(int32_t));
-        if (finfo != 0) break;
-        if (S->h_scal[1] <= 1e-13 * S->h_scal[0]) { solved = true; break; }
-        if (done >= kMaxSteps) break;
-        refine_step();
-        ++done;
-      }
+      const bool solved = dense_has_inverse(N3) ? refine_on_inverse(S, N3) : refine_on_blocks(S, N3);
       if (!solved) {
         S->refine_fallbacks++;
         fallback = true;
@@ -802,10 +876,7 @@ static void global_step(Solver* S, const IterOut& io) {
         S->check_info_m = true;
       }
     }
-    if (!mixed || fallback) {
-      HIPCHK(hipMemcpyAsync(S->u.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
-      dense_chol_solve<double>(S->ML.p, S->MLi.p, N3, S->u.p, 1, st);
-    }
+    if (!mixed || fallback) dense_chol_solve_into<double>(S->ML.p, S->MLi.p, N3, S->rhs.p, S->u.p, st);
     launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
     launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
   }
@@ -915,7 +986,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   for (; it < S->opt.iters; ++it) {
     IterOut io;
     auto a = std::chrono::steady_clock::now();
-    assemble_gradient(S, it == 0, io);
+    assemble_gradient(S, it == 0, io, /*defer=*/true);
     auto b = std::chrono::steady_clock::now();
     global_step(S, io);
     if (stats) HIPCHK(hipStreamSynchronize(st));
@@ -1174,6 +1245,7 @@ void pdipc_destroy(void* h) {
   S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release(); S->scl.release();
   S->prev_cflag.release();
   S->lsbuf.release();
+  S->refres.release();
   delete S;
 }
 
