@@ -37,8 +37,10 @@ __device__ __forceinline__ int32_t cell_of(double c, double o, double h) {
 }
 // A box never spans more than 3 cells per axis (cell size >= largest extent
 // gives at most 2); the clamp bounds every loop even for corrupt input.
+// The cell size exceeds every (padded) box extent, so a finite box spans at
+// most two cells per axis; the clamp only bounds non-finite input.
 __device__ __forceinline__ int32_t clamp_hi(int32_t lo, int32_t hi) {
-  return hi < lo ? lo : (hi > lo + 2 ? lo + 2 : hi);
+  return hi < lo ? lo : (hi > lo + 1 ? lo + 1 : hi);
 }
 }  // namespace
 
@@ -178,8 +180,8 @@ __device__ __forceinline__ bool box_overlap(const double* a, const double* b, do
          a[2] <= b[5] + dhat && b[2] <= a[5] + dhat;
 }
 
-// Visit the accepted partners of query q inside cell slot `slot` (0..26) of
-// its (at most 3 x 3 x 3) cell range; call emit(partner).
+// Visit the accepted partners of query q inside cell slot `slot` (0..7) of
+// its (at most 2 x 2 x 2) cell range; call emit(partner).
 template <typename Emit>
 __device__ void visit_slot(const QueryArgs& qa, int64_t q, int slot, Emit emit) {
   const ProxyDev& px = qa.px;
@@ -203,7 +205,7 @@ __device__ void visit_slot(const QueryArgs& qa, int64_t q, int slot, Emit emit) 
     ql[r] = cell_of(qb[r] - pad, o[r], h);
     qu[r] = clamp_hi(ql[r], cell_of(qb[3 + r] + pad, o[r], h));
   }
-  const int32_t i = ql[0] + slot % 3, j = ql[1] + (slot / 3) % 3, k = ql[2] + slot / 9;
+  const int32_t i = ql[0] + (slot & 1), j = ql[1] + ((slot >> 1) & 1), k = ql[2] + (slot >> 2);
   if (i > qu[0] || j > qu[1] || k > qu[2]) return;
   const int32_t* start = is_pt ? qa.t_start : qa.e_start;
   const int32_t* ids = is_pt ? qa.t_id : qa.e_id;
@@ -240,7 +242,7 @@ __device__ void visit_slot(const QueryArgs& qa, int64_t q, int slot, Emit emit) 
 }
 
 constexpr int QT = 256;
-constexpr int SLOTS = 27;
+constexpr int SLOTS = 8;
 
 __global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;

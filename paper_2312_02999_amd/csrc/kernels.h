@@ -78,7 +78,7 @@ struct BroadPhaseBuffers {
   int32_t* e_id;
   uint64_t* e_key;
   int64_t ent_cap;      // capacity of each entry array
-  int32_t* q_count;     // 27 (nsv + nse) + 1 per-(query, cell slot) counts / offsets
+  int32_t* q_count;     // 8 (nsv + nse) + 1 per-(query, cell slot) counts / offsets
   int32_t* tmpj;        // unsorted partner ids
   int64_t tmp_cap;
   int32_t* d_totals;    // [0] pairs total

@@ -548,12 +548,12 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   int bits = 10;
   while ((1LL << bits) < 4LL * (S->nst + S->nse) && bits < 28) ++bits;
   const int64_t T = 1LL << bits;
-  const int64_t ent = 27LL * std::max(S->nst, S->nse) + 64;
+  const int64_t ent = 8LL * std::max(S->nst, S->nse) + 64;
   for (auto* b : {&S->t_count, &S->t_cursor, &S->e_count, &S->e_cursor}) b->ensure(T + 1);
   S->t_id.ensure(ent); S->e_id.ensure(ent); S->t_key.ensure(ent); S->e_key.ensure(ent);
-  S->q_count.ensure(27LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1);
+  S->q_count.ensure(8LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1);
   S->totals.ensure(8);
-  const int64_t scan_n = std::max<int64_t>({T + 1, 27LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1,
+  const int64_t scan_n = std::max<int64_t>({T + 1, 8LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1,
                                             static_cast<int64_t>(n) + 1});
   S->scan_tmp.ensure(static_cast<int64_t>(scan_temp_bytes(scan_n)));
   S->red_tmp.ensure(static_cast<int64_t>(sum_temp_bytes(0)) + 4096);
