@@ -26,6 +26,11 @@ K_LOCAL, K_SIGMA_GEMV, K_FWD, K_BWD, K_BARRIER, K_TRIAL, K_RED_CHOL = 0, 1, 2, 3
 HBM_PEAK_GBS = 8000.0
 
 
+def progress(msg: str) -> None:
+    """One line per finished stage on stderr (stdout carries the JSON)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def local_step_bytes(n: int, m: int) -> int:
     """Algorithmic bytes of one local-step launch (FP64 streams).
 
@@ -41,6 +46,7 @@ def run_precision(sc, precision, steps, warmup, timer_kernel):
     import torch
     from paper_2312_02999_amd import Solver
     S = Solver(sc, iters=sc.iters, precision=precision)
+    progress(f"solver ready ({'mixed' if precision else 'fp64'})")
     dev = "cuda"
     R = torch.from_numpy(np.ascontiguousarray(sc.act_R.reshape(-1, 9))).to(dev)
     seq = [torch.from_numpy(np.ascontiguousarray(sc.actuation_at((t + 1) / sc.frames))).to(dev)
@@ -52,6 +58,7 @@ def run_precision(sc, precision, steps, warmup, timer_kernel):
         S.set_actuation_scalar(seq[min(t, len(seq) - 1)])
         x = S.solve_frame(x)
         t += 1
+    progress("warm-up frames done")
     S.kernel_timer(timer_kernel)
     lat = []
     x_start, t_start = x.clone(), t
@@ -65,6 +72,7 @@ def run_precision(sc, precision, steps, warmup, timer_kernel):
         t += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    progress(f"{steps} timed frames in {wall:.2f} s")
     k_ms, k_count = S.kernel_timer(-1)
     # counters and per-stage times from an untimed replay of the same frames
     # (stage timing synchronises after the global step)
@@ -201,10 +209,12 @@ def main():
     if args.serving:
         from paper_2312_02999_amd import serve
         for prec in (MIXED_FP32, FP64):
+            progress(f"serving {args.serving} requests ({'mixed' if prec else 'fp64'})")
             rep = serve.run_serving(n_requests=args.serving, precision=prec)
             print(json.dumps({"metric": "serving: request latency and frames/s", **rep}), flush=True)
         return
     sc = mg.scene_by_name(args.workload)
+    progress(f"scene {args.workload} generated (n={sc.n}, m={sc.m})")
     if args.adjoint:
         print(json.dumps(run_adjoint(sc)))
         return
@@ -227,6 +237,8 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": fp64["kernel_launches"],
             "algorithmic_bytes": nbytes}
+    if not args.no_cpu_baseline:
+        progress("oracle baseline sample")
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc)
     out = {
         "metric": "PD+IPC frames/s on 50k-vert mesh, mixed vs FP64 GPU; p50/p99 latency",

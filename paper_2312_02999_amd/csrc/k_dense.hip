@@ -222,6 +222,9 @@ __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int
   const int lane = threadIdx.x;
   const int rr = lane & 31;
   const bool rowlane = lane < 32;
+  // the serial chain of the whole factorisation runs here: win instruction
+  // issue against the other workgroups sharing this compute unit
+  __builtin_amdgcn_s_setprio(3);
   T a[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) a[c] = rowlane ? W[rr][c] : (c == rr ? T(1) : T(0));
@@ -255,6 +258,7 @@ __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int
     for (int r = 0; r < 32; ++r) X[r][rr] = a[r];
   }
   if (first_bad != 0 && lane == 0 && *info == 0) *info = static_cast<int32_t>(k0 + first_bad);
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // Stores 1 / diag(L_kk) and the inverse D of a factored 32 x 32 diagonal block
