@@ -209,56 +209,96 @@ __device__ __forceinline__ void invert_diag_wave(const T (*W)[NB + 1], const T* 
   for (int r = 0; r < NB; ++r) D[r * NB + lane] = v[r];
 }
 
-// NB = 32: the 32-lane rows of the tile leave the upper half of the wave idle,
-// so lanes 32 + c carry column c of the identity through the same steps: with
-// the column of L broadcast for the trailing update (FP64: readlane into
-// scalar registers; FP32: through LDS, measured faster there) they
-// forward-substitute it, and end holding
-// column c of L_kk^-1.  The inverse goes to X and 1 / diag(L_kk) to dk (the
-// factor itself is not kept); same pivot rules as factor_diag_wave.
+// Factor and invert the 16 x 16 block W[o..o+16)[o..o+16) of a 32-wide
+// diagonal tile with one wave.  Lanes 0-15 hold its rows; lanes 32-47 carry
+// the identity through the same steps (the column of L is broadcast by
+// readlane into scalar registers) and so forward-substitute it, ending with
+// column c of the block's inverse in lane 32 + c.  The inverse goes to Xs,
+// 1 / diag to dk[o..o+16); a non-positive pivot is replaced by 1 and the
+// first such column (tile index + 1, below kb) is kept in first_bad.  The
+// unrolled loop is kept free of branches so that the row stays in registers.
 template <typename T>
-__device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int kb, int64_t k0,
-                                                     int32_t* __restrict__ info, T* colbuf, T* dk) {
+__device__ __forceinline__ void factor_invert16(const T (*W)[33], int o, T (*Xs)[17], T* dk, int kb,
+                                                int& first_bad) {
   const int lane = threadIdx.x;
-  const int rr = lane & 31;
-  const bool rowlane = lane < 32;
-  // the serial chain of the whole factorisation runs here: win instruction
-  // issue against the other workgroups sharing this compute unit
-  __builtin_amdgcn_s_setprio(3);
-  T a[32];
+  const int rr = lane & 15;
+  const bool rowlane = lane < 16;
+  T a[16];
 #pragma unroll
-  for (int c = 0; c < 32; ++c) a[c] = rowlane ? W[rr][c] : (c == rr ? T(1) : T(0));
+  for (int c = 0; c < 16; ++c) a[c] = rowlane ? W[o + rr][o + c] : (c == rr ? T(1) : T(0));
   T myinv = T(1);
-  int first_bad = 0;
 #pragma unroll
-  for (int j = 0; j < 32; ++j) {
+  for (int j = 0; j < 16; ++j) {
     T d = read_lane(a[j], j);
     const bool ok = d > T(0);
-    first_bad = (!ok && first_bad == 0 && j < kb) ? j + 1 : first_bad;
+    first_bad = (!ok && first_bad == 0 && o + j < kb) ? o + j + 1 : first_bad;
     d = ok ? d : T(1);
     const T isd = rsqrt_nr(d);
     const T l = (lane == j) ? d * isd : a[j] * isd;
     a[j] = l;
     myinv = (lane == j) ? isd : myinv;
-    if constexpr (sizeof(T) == 8) {
 #pragma unroll
-      for (int c = j + 1; c < 32; ++c) a[c] -= l * read_lane(l, c);
-    } else {
-      colbuf[lane] = l;
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int c = j + 1; c < 32; ++c) a[c] -= l * colbuf[c];
-      __builtin_amdgcn_wave_barrier();
-    }
+    for (int c = j + 1; c < 16; ++c) a[c] -= l * read_lane(l, c);
   }
   if (rowlane) {
-    dk[rr] = myinv;
-  } else {
+    dk[o + rr] = myinv;
+  } else if (lane >= 32 && lane < 48) {
 #pragma unroll
-    for (int r = 0; r < 32; ++r) X[r][rr] = a[r];
+    for (int r = 0; r < 16; ++r) Xs[r][rr] = a[r];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// NB = 32 diagonal tile, factored and inverted by one wave as 2 x 2 blocks of
+// 16: L11 (and L11^-1) as above, L21 = A21 L11^-T and A22 -= L21 L21^T on the
+// matrix cores, L22 (and L22^-1), then (L^-1)_21 = -L22^-1 L21 L11^-1.  The
+// tile W is overwritten; X receives L_kk^-1 (32 x 33), dk 1 / diag(L_kk);
+// S is scratch for three 16 x 17 blocks.  The factor itself is not kept.
+template <typename T>
+__device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int kb, int64_t k0,
+                                                     int32_t* __restrict__ info, T (*S)[17], T* dk) {
+  const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
+  T (*X11)[17] = S;
+  T (*X22)[17] = S + 16;
+  T (*Tm)[17] = S + 32;
+  typedef typename MfmaVec<T>::type V;
+  int first_bad = 0;
+  factor_invert16<T>(W, 0, X11, dk, kb, first_bad);
+  V acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int q0 = 0; q0 < 16; q0 += 4) acc = mfma16x16x4(W[16 + lr][q0 + lk], X11[lr][q0 + lk], acc);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) W[16 + mfma_row<T>(lk, q)][lr] = acc[q];        // L21
+  __builtin_amdgcn_wave_barrier();
+  V upd = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int p0 = 0; p0 < 16; p0 += 4) {
+    const T v = W[16 + lr][p0 + lk];
+    upd = mfma16x16x4(v, v, upd);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) W[16 + mfma_row<T>(lk, q)][16 + lr] -= upd[q];
+  __builtin_amdgcn_wave_barrier();
+  factor_invert16<T>(W, 16, X22, dk, kb, first_bad);
+  V t = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int p0 = 0; p0 < 16; p0 += 4) t = mfma16x16x4(W[16 + lr][p0 + lk], X11[p0 + lk][lr], t);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Tm[mfma_row<T>(lk, q)][lr] = t[q];
+  __builtin_amdgcn_wave_barrier();
+  V x21 = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int p0 = 0; p0 < 16; p0 += 4) x21 = mfma16x16x4(X22[lr][p0 + lk], Tm[p0 + lk][lr], x21);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = mfma_row<T>(lk, q);
+    X[16 + r][lr] = -x21[q];
+    X[r][lr] = X11[r][lr];
+    X[r][16 + lr] = T(0);
+    X[16 + r][16 + lr] = X22[r][lr];
   }
   if (first_bad != 0 && lane == 0 && *info == 0) *info = static_cast<int32_t>(k0 + first_bad);
-  __builtin_amdgcn_s_setprio(0);
 }
 
 // Stores 1 / diag(L_kk) and the inverse D of a factored 32 x 32 diagonal block
@@ -399,6 +439,7 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
                                                          T* __restrict__ Dinv, int32_t* __restrict__ info) {
   __shared__ T W[NB][NB + 1];
   __shared__ T X[NB == 32 ? 32 : 1][33];
+  __shared__ T Sc[NB == 32 ? 48 : 1][17];
   __shared__ T colbuf[PDIPC_WAVE];
   __shared__ T dk[NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
@@ -411,7 +452,7 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
   }
   __syncthreads();
   if constexpr (NB == 32) {
-    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, colbuf, dk);
+    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, Sc, dk);
     __syncthreads();
     store_diag32<T>(X, dk, kb, 0, dinv, Dinv);
   } else if (threadIdx.x < PDIPC_WAVE) {
@@ -568,7 +609,8 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
   if constexpr (NB == 32) {
     T (*X)[33] = Ai;      // the panels are consumed
-    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, i0, info, colbuf, dk);
+    T (*Sc)[17] = reinterpret_cast<T (*)[17]>(&Aj[0][0]);
+    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, i0, info, Sc, dk);
     __syncthreads();
     store_diag32<T>(X, dk, kb, i0, dinv, Dinv + (k + 1) * NB * NB);
   } else if (threadIdx.x < PDIPC_WAVE) {
@@ -905,22 +947,59 @@ void launch_refine_correct(const float* F, float* aux, int64_t n, const float* r
   refine_upper_kernel<<<g, 256, 0, st>>>(aux, n, z, sc, u, res, s, tol);
 }
 
-// work = lower part of F with zeros above (Y = L^-1 for NB = 32)
+// (L L^T)^-1 = Y^T Y = Yt Yt^T with Yt = Y^T (row-major, upper triangle and
+// diagonal blocks valid) for 32-wide blocks: one workgroup per 32 x 32 tile
+// (i, j), i >= j, summing over the column blocks p >= i of Yt on the matrix
+// cores, and writing the tile and its mirror.
 template <typename T>
-__global__ void lower_copy_kernel(const T* __restrict__ F, int64_t n, T* __restrict__ out) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n * n) return;
-  out[i] = (i % n <= i / n) ? F[i] : T(0);
+__global__ void __launch_bounds__(256) yty_kernel(const T* __restrict__ Yt, int64_t n, T* __restrict__ C) {
+  constexpr int NB = 32;
+  __shared__ T As[NB][NB + 1];
+  __shared__ T Bs[NB][NB + 1];
+  __shared__ T Cs[NB][NB + 1];
+  const int64_t nblk = (n + NB - 1) / NB;
+  int64_t t = blockIdx.x, bi = 0;
+  while (t > bi) { t -= bi + 1; ++bi; }
+  const int64_t bj = t, i0 = bi * NB, j0 = bj * NB;
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int rb = 16 * (w / 2), cb = 16 * (w % 2);
+  const int lr = lane % 16, lk = lane / 16;
+  typename MfmaVec<T>::type acc = {T(0), T(0), T(0), T(0)};
+  for (int64_t pb = bi; pb < nblk; ++pb) {
+    const int64_t p0 = pb * NB;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      const int r = idx / NB, c = idx % NB;
+      As[r][c] = (i0 + r < n && p0 + c < n) ? Yt[(i0 + r) * n + p0 + c] : T(0);
+      Bs[r][c] = (j0 + r < n && p0 + c < n) ? Yt[(j0 + r) * n + p0 + c] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q0 = 0; q0 < NB; q0 += 4) acc = mfma16x16x4(As[rb + lr][q0 + lk], Bs[cb + lr][q0 + lk], acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Cs[rb + mfma_row<T>(lk, q)][cb + lr] = acc[q];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    const int r = idx / NB, c = idx % NB;
+    if (i0 + r < n && j0 + c < n) C[(i0 + r) * n + j0 + c] = Cs[r][c];
+    if (bi != bj && j0 + r < n && i0 + c < n) C[(j0 + r) * n + i0 + c] = Cs[c][r];
+  }
 }
 
 template <typename T>
 void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st) {
   if (n <= 0) return;
   if (dense_block(n) == 32) {
-    lower_copy_kernel<T><<<grid_for(n * n, 256), 256, 0, st>>>(L, n, work);
-  } else {
-    chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, aux + n * n + n, n, work);
+    const int64_t nb = (n + 31) / 32;
+    yty_kernel<T><<<static_cast<unsigned>(nb * (nb + 1) / 2), 256, 0, st>>>(aux, n, Ainv);
+    return;
   }
+  chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, aux + n * n + n, n, work);
   const unsigned g = grid_for(n, 64);
   dim3 grid(g, g);
   gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
