@@ -25,6 +25,22 @@ K_LOCAL, K_SIGMA_GEMV, K_FWD, K_BWD, K_BARRIER, K_TRIAL, K_RED_CHOL = 0, 1, 2, 3
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per local-step launch on face50k from two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy
+# of known size; valid only for the kernel source they were taken on
+# (profiles/local_step_kernel_face50k_pmc.md).
+LOCAL_STEP_TRAFFIC = {"workload": "face50k", "source_sha256_prefix": "80fd166d7c8e6d27", "bytes": 111204647}
+
+
+def measured_traffic(workload: str):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2312_02999_amd", "csrc", "k_local.hip")
+    with open(path, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    t = LOCAL_STEP_TRAFFIC
+    ok = workload == t["workload"] and digest == t["source_sha256_prefix"]
+    return t["bytes"] if ok else None
+
 
 def progress(msg: str) -> None:
     """One line per finished stage on stderr (stdout carries the JSON)."""
@@ -234,7 +250,8 @@ def main():
     # avg_launch_us: events stamped by the dispatch itself (extended launch) on
     # the solver's stream, every local-step launch of the timed FP64 frames
     roof = {"bound": "hbm", "kernel": "local_step_kernel<double>", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.workload),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": fp64["kernel_launches"],
             "algorithmic_bytes": nbytes}
     if not args.no_cpu_baseline:
