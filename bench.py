@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy
 # of known size; valid only for the kernel source they were taken on
 # (profiles/local_step_kernel_face50k_pmc.md).
-LOCAL_STEP_TRAFFIC = {"workload": "face50k", "source_sha256_prefix": "80fd166d7c8e6d27", "bytes": 111204647}
+LOCAL_STEP_TRAFFIC = {"workload": "face50k", "source_sha256_prefix": "e0e0ef2c8732ebba", "bytes": 103253281}
 
 
 def measured_traffic(workload: str):

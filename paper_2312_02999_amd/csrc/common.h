@@ -70,6 +70,17 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin;
+// this bijection of the block index gives each XCD one contiguous range of
+// logical blocks, so neighbouring elements (which share vertices) meet in the
+// same L2.
+constexpr int PDIPC_XCDS = 8;
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t q = nb / PDIPC_XCDS, r = nb % PDIPC_XCDS, x = b % PDIPC_XCDS, j = b / PDIPC_XCDS;
+  return x * q + (x < r ? x : r) + j;
+}
+
 inline unsigned grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return static_cast<unsigned>(g < 1 ? 1 : g);

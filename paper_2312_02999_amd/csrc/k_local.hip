@@ -283,7 +283,7 @@ template <typename TP>
 __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t m, const double* __restrict__ x,
                                                          const double* Rwarm, double* Rout,
                                                          double* __restrict__ energy, double* __restrict__ tetg) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= m) return;
   M3<double> F, A, Bm;
   double w;
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(256) trial_energy_kernel(TetStreams ts, int64_
                                                            const double* __restrict__ E0, double* __restrict__ dE) {
   if (ls[LS_STATE] != 0.0) return;
   const double alpha = ls[LS_ALPHA];
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= m) return;
   int32_t v[4];
 #pragma unroll
@@ -380,8 +380,9 @@ __global__ void __launch_bounds__(256) gather_vertex_grad_kernel(int32_t n, int6
                                                                  const double* __restrict__ tetg,
                                                                  const uint8_t* __restrict__ fixed,
                                                                  double* __restrict__ g) {
-  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  const int64_t vv = xcd_block() * blockDim.x + threadIdx.x;
+  if (vv >= n) return;
+  const int32_t v = static_cast<int32_t>(vv);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (!fixed[v]) {
 #pragma unroll 4
