@@ -180,86 +180,125 @@ __device__ __forceinline__ bool box_overlap(const double* a, const double* b, do
          a[2] <= b[5] + dhat && b[2] <= a[5] + dhat;
 }
 
-// Visit the accepted partners of query q inside cell slot `slot` (0..7) of
-// its (at most 2 x 2 x 2) cell range; call emit(partner).
-template <typename Emit>
-__device__ void visit_slot(const QueryArgs& qa, int64_t q, int slot, Emit emit) {
-  const ProxyDev& px = qa.px;
-  const bool is_pt = q < px.nsv;
+// One wave per query.  The query's box spans at most 2 x 2 x 2 cells; for
+// each, the lanes test the cell's hash bucket 64 entries at a time (buckets
+// are short but several dozen long where the mesh is dense, so a serial scan
+// would be a long chain of dependent loads).  A pair is reported only in the
+// first cell both boxes share, so each appears once.
+struct QueryCtx {
+  bool is_pt;
   const double* qb;
-  int32_t qv[2] = {0, 0};
-  if (is_pt) {
-    qb = qa.vbox + 6 * q;
-    qv[0] = px.sv[q];
-  } else {
-    int64_t e = q - px.nsv;
-    qb = qa.ebox + 6 * e;
-    qv[0] = px.se[2 * e];
-    qv[1] = px.se[2 * e + 1];
-  }
-  const double o[3] = {qa.params[0], qa.params[1], qa.params[2]};
-  const double h = qa.params[3], pad = qa.params[4];
+  int32_t qv[2];
   int32_t ql[3], qu[3];
+  double o[3], h;
+};
+
+__device__ __forceinline__ QueryCtx query_ctx(const QueryArgs& qa, int64_t q) {
+  const ProxyDev& px = qa.px;
+  QueryCtx c;
+  c.is_pt = q < px.nsv;
+  c.qv[0] = c.qv[1] = 0;
+  if (c.is_pt) {
+    c.qb = qa.vbox + 6 * q;
+    c.qv[0] = px.sv[q];
+  } else {
+    const int64_t e = q - px.nsv;
+    c.qb = qa.ebox + 6 * e;
+    c.qv[0] = px.se[2 * e];
+    c.qv[1] = px.se[2 * e + 1];
+  }
+  c.o[0] = qa.params[0]; c.o[1] = qa.params[1]; c.o[2] = qa.params[2];
+  c.h = qa.params[3];
+  const double pad = qa.params[4];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    ql[r] = cell_of(qb[r] - pad, o[r], h);
-    qu[r] = clamp_hi(ql[r], cell_of(qb[3 + r] + pad, o[r], h));
+    c.ql[r] = cell_of(c.qb[r] - pad, c.o[r], c.h);
+    c.qu[r] = clamp_hi(c.ql[r], cell_of(c.qb[3 + r] + pad, c.o[r], c.h));
   }
-  const int32_t i = ql[0] + (slot & 1), j = ql[1] + ((slot >> 1) & 1), k = ql[2] + (slot >> 2);
-  if (i > qu[0] || j > qu[1] || k > qu[2]) return;
-  const int32_t* start = is_pt ? qa.t_start : qa.e_start;
-  const int32_t* ids = is_pt ? qa.t_id : qa.e_id;
-  const uint64_t* keys = is_pt ? qa.t_key : qa.e_key;
-  const double* pbox = is_pt ? qa.tbox : qa.ebox;
-  const uint32_t hh = cell_hash(i, j, k, qa.mask);
-  const uint64_t key = cell_key(i, j, k);
-  for (int32_t s = start[hh]; s < start[hh + 1]; ++s) {
-    if (keys[s] != key) continue;
-    int32_t p = ids[s];
-    if (!is_pt && p <= q - px.nsv) continue;
-    const double* b = pbox + 6 * static_cast<int64_t>(p);
-    int32_t pl0 = cell_of(b[0], o[0], h), pl1 = cell_of(b[1], o[1], h), pl2 = cell_of(b[2], o[2], h);
-    if (max(ql[0], pl0) != i || max(ql[1], pl1) != j || max(ql[2], pl2) != k) continue;
-    if (!box_overlap(qb, b, qa.dhat)) continue;
-    int32_t v4[4];
-    if (is_pt) {
-      int32_t t0 = px.st[3 * p], t1 = px.st[3 * p + 1], t2 = px.st[3 * p + 2];
-      if (qv[0] == t0 || qv[0] == t1 || qv[0] == t2) continue;
-      v4[0] = qv[0]; v4[1] = t0; v4[2] = t1; v4[3] = t2;
-    } else {
-      int32_t b0 = px.se[2 * p], b1 = px.se[2 * p + 1];
-      if (qv[0] == b0 || qv[0] == b1 || qv[1] == b0 || qv[1] == b1) continue;
-      v4[0] = qv[0]; v4[1] = qv[1]; v4[2] = b0; v4[3] = b1;
-    }
-    if (qa.dist) {
-      double P[4][3];
-      load_pair_rel(v4, qa.x, P);
-      double d2 = pair_dist2<double>(is_pt, P);
-      if (!(d2 < qa.dhat * qa.dhat)) continue;
-    }
-    emit(p);
+  return c;
+}
+
+// Partner of bucket entry s in cell (i, j, k) if the pair is accepted, else -1.
+__device__ __forceinline__ int32_t query_test(const QueryArgs& qa, const QueryCtx& c, int64_t q, int32_t s,
+                                              uint64_t key, int32_t i, int32_t j, int32_t k) {
+  const ProxyDev& px = qa.px;
+  const int32_t* ids = c.is_pt ? qa.t_id : qa.e_id;
+  const uint64_t* keys = c.is_pt ? qa.t_key : qa.e_key;
+  const double* pbox = c.is_pt ? qa.tbox : qa.ebox;
+  if (keys[s] != key) return -1;
+  const int32_t p = ids[s];
+  if (!c.is_pt && p <= q - px.nsv) return -1;
+  const double* b = pbox + 6 * static_cast<int64_t>(p);
+  const int32_t pl0 = cell_of(b[0], c.o[0], c.h), pl1 = cell_of(b[1], c.o[1], c.h), pl2 = cell_of(b[2], c.o[2], c.h);
+  if (max(c.ql[0], pl0) != i || max(c.ql[1], pl1) != j || max(c.ql[2], pl2) != k) return -1;
+  if (!box_overlap(c.qb, b, qa.dhat)) return -1;
+  int32_t v4[4];
+  if (c.is_pt) {
+    const int32_t t0 = px.st[3 * p], t1 = px.st[3 * p + 1], t2 = px.st[3 * p + 2];
+    if (c.qv[0] == t0 || c.qv[0] == t1 || c.qv[0] == t2) return -1;
+    v4[0] = c.qv[0]; v4[1] = t0; v4[2] = t1; v4[3] = t2;
+  } else {
+    const int32_t b0 = px.se[2 * p], b1 = px.se[2 * p + 1];
+    if (c.qv[0] == b0 || c.qv[0] == b1 || c.qv[1] == b0 || c.qv[1] == b1) return -1;
+    v4[0] = c.qv[0]; v4[1] = c.qv[1]; v4[2] = b0; v4[3] = b1;
   }
+  if (qa.dist) {
+    double P[4][3];
+    load_pair_rel(v4, qa.x, P);
+    const double d2 = pair_dist2<double>(c.is_pt, P);
+    if (!(d2 < qa.dhat * qa.dhat)) return -1;
+  }
+  return p;
+}
+
+// Walk the query's cells with the whole wave; emit(partner, rank) for every
+// accepted partner (rank: its position among the wave's accepted partners so
+// far); returns the count.
+template <typename Emit>
+__device__ __forceinline__ int32_t query_wave(const QueryArgs& qa, int64_t q, Emit emit) {
+  const int lane = threadIdx.x % PDIPC_WAVE;
+  const QueryCtx c = query_ctx(qa, q);
+  const int32_t* start = c.is_pt ? qa.t_start : qa.e_start;
+  int32_t total = 0;
+  for (int slot = 0; slot < 8; ++slot) {
+    const int32_t i = c.ql[0] + (slot & 1), j = c.ql[1] + ((slot >> 1) & 1), k = c.ql[2] + (slot >> 2);
+    if (i > c.qu[0] || j > c.qu[1] || k > c.qu[2]) continue;      // uniform across the wave
+    const uint32_t hh = cell_hash(i, j, k, qa.mask);
+    const uint64_t key = cell_key(i, j, k);
+    const int32_t s0 = start[hh], s1 = start[hh + 1];
+    for (int32_t base = s0; base < s1; base += PDIPC_WAVE) {
+      const int32_t s = base + lane;
+      const int32_t p = s < s1 ? query_test(qa, c, q, s, key, i, j, k) : -1;
+      const uint64_t m = __ballot(p >= 0);
+      if (p >= 0) {
+        const int32_t below = static_cast<int32_t>(
+            __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
+        emit(p, total + below);
+      }
+      total += static_cast<int32_t>(__popcll(m));
+    }
+  }
+  return total;
 }
 
 constexpr int QT = 256;
-constexpr int SLOTS = 8;
+constexpr int QW = QT / PDIPC_WAVE;   // queries per workgroup
 
 __global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * QW + threadIdx.x / PDIPC_WAVE;
   const int64_t nq = static_cast<int64_t>(qa.px.nsv) + qa.px.nse;
-  if (t >= nq * SLOTS) return;
-  int32_t c = 0;
-  visit_slot(qa, t / SLOTS, static_cast<int>(t % SLOTS), [&](int32_t) { ++c; });
-  qcount[t] = c;
+  if (q >= nq) return;
+  const int32_t c = query_wave(qa, q, [&](int32_t, int32_t) {});
+  if (threadIdx.x % PDIPC_WAVE == 0) qcount[q] = c;
 }
 
 __global__ void __launch_bounds__(QT) query_fill_kernel(QueryArgs qa, const int32_t* __restrict__ qoff,
                                                         int32_t* __restrict__ tmpj) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * QT + threadIdx.x;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * QW + threadIdx.x / PDIPC_WAVE;
   const int64_t nq = static_cast<int64_t>(qa.px.nsv) + qa.px.nse;
-  if (t >= nq * SLOTS) return;
-  int32_t c = qoff[t];
-  visit_slot(qa, t / SLOTS, static_cast<int>(t % SLOTS), [&](int32_t p) { tmpj[c++] = p; });
+  if (q >= nq) return;
+  const int32_t b = qoff[q];
+  query_wave(qa, q, [&](int32_t p, int32_t r) { tmpj[b + r] = p; });
 }
 
 // one wave per query: rank its partners (unique ids) and emit sorted pairs
@@ -271,7 +310,7 @@ __global__ void __launch_bounds__(256) query_emit_kernel(ProxyDev px, const int3
   const int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
   const int64_t nq = static_cast<int64_t>(px.nsv) + px.nse;
   if (q >= nq) return;
-  const int32_t b = qoff[q * SLOTS], e = qoff[q * SLOTS + SLOTS], cnt = e - b;
+  const int32_t b = qoff[q], e = qoff[q + 1], cnt = e - b;
   const bool is_pt = q < px.nsv;
   const int32_t qi = is_pt ? px.sv[q] : static_cast<int32_t>(q - px.nsv);
   for (int32_t a = lane; a < cnt; a += PDIPC_WAVE) {
@@ -297,7 +336,7 @@ __global__ void __launch_bounds__(256) query_emit_kernel(ProxyDev px, const int3
 }
 
 __global__ void pt_total_kernel(const int32_t* __restrict__ qoff, int32_t nsv, int32_t* __restrict__ out) {
-  *out = qoff[static_cast<int64_t>(nsv) * SLOTS];
+  *out = qoff[nsv];
 }
 
 int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x, const double* dx, double dhat,
@@ -305,7 +344,7 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
                int64_t* needed) {
   const int64_t total = static_cast<int64_t>(px.nsv) + px.nst + px.nse;
   const int64_t nq = static_cast<int64_t>(px.nsv) + px.nse;
-  const int64_t nslots = nq * SLOTS;
+
   *needed = 0;
   if (px.nsv == 0 || (px.nst == 0 && px.nse == 0)) {
     *n_pt = 0;
@@ -332,9 +371,9 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
 
   QueryArgs qa{px, x, bb.vbox, bb.tbox, bb.ebox, bb.params, mask, bb.t_count, bb.t_id, bb.t_key,
                bb.e_count, bb.e_id, bb.e_key, dhat, distance_filter};
-  launch_fill_i32(bb.q_count + nslots, 1, 0, st);     // sentinel slot of the scan
-  query_count_kernel<<<grid_for(nslots, QT), QT, 0, st>>>(qa, bb.q_count);
-  launch_exclusive_scan(bb.q_count, bb.q_count, nslots + 1, bb.d_totals, bb.scan_temp, st);
+  launch_fill_i32(bb.q_count + nq, 1, 0, st);     // sentinel slot of the scan
+  query_count_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count);
+  launch_exclusive_scan(bb.q_count, bb.q_count, nq + 1, bb.d_totals, bb.scan_temp, st);
   pt_total_kernel<<<1, 1, 0, st>>>(bb.q_count, px.nsv, bb.d_totals + 1);
   int32_t h_tot[4];
   hipMemcpyAsync(h_tot, bb.d_totals, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
@@ -348,7 +387,7 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
   *n_pt = h_tot[1];
   *n_ee = npairs - h_tot[1];
   if (npairs > 0) {
-    query_fill_kernel<<<grid_for(nslots, QT), QT, 0, st>>>(qa, bb.q_count, bb.tmpj);
+    query_fill_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count, bb.tmpj);
     query_emit_kernel<<<grid_for(nq, 4), 256, 0, st>>>(px, bb.q_count, bb.tmpj, out.type, out.i, out.j, out.v4);
   }
   return 0;
