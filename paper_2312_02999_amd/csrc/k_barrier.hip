@@ -329,8 +329,10 @@ void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyD
                      Incidence& inc, void* scan_temp, hipStream_t st) {
   launch_fill_i32(inc.cnt, n + 1, 0, st);
   if (npairs > 0) inc_count_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cnt);
-  launch_exclusive_scan(inc.cnt, inc.ptr, n + 1, inc.d_nc, scan_temp, st);
-  hipMemcpyAsync(inc.cursor, inc.ptr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
+  {
+    const ScanJob job{inc.cnt, inc.ptr, n + 1, inc.d_nc, inc.cursor, -1, nullptr};   // cursor: copy of ptr
+    launch_exclusive_scans(&job, 1, scan_temp, st);
+  }
   if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.raw);
   if (npairs > 0) inc_sort_kernel<<<grid_for(px.nsv, 4), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.raw, inc.ent);
   cflag_kernel<<<grid_for(n + 1, 256), 256, 0, st>>>(n, inc.ptr, fixed, inc.cflag);

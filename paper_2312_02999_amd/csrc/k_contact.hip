@@ -118,29 +118,44 @@ __global__ void __launch_bounds__(BT) grid_params_partial(ProxyDev px, const dou
   }
 }
 
-__global__ void grid_params_final(const double* __restrict__ part, int nparts, double pad, double* params) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(64) grid_params_final(const double* __restrict__ part, int nparts, double pad,
+                                                        double* params) {
+  // one wave: lane i folds partials i, i + 64, ...
   double mn[3] = {INFINITY, INFINITY, INFINITY}, ext = 0.0;
-  for (int i = 0; i < nparts; ++i) {
+  for (int i = threadIdx.x; i < nparts; i += PDIPC_WAVE) {
+#pragma unroll
     for (int r = 0; r < 3; ++r) mn[r] = fmin(mn[r], part[4 * i + r]);
     ext = fmax(ext, part[4 * i + 3]);
   }
-  double h = ext * (1.0 + 1e-6) + 1e-12;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) mn[r] = wave_min(mn[r]);
+  ext = wave_max(ext);
+  if (threadIdx.x != 0) return;
+  const double h = ext * (1.0 + 1e-6) + 1e-12;
   for (int r = 0; r < 3; ++r) params[r] = mn[r] - h;
   params[3] = h;
   params[4] = pad;
 }
 
 // ---- table build ---------------------------------------------------------------
+// Triangles (g < nt) and edges in one launch: each primitive goes into the
+// hash bucket of every cell its box spans (at most 2 x 2 x 2).
 template <bool FILL>
-__global__ void __launch_bounds__(BT) insert_kernel(int32_t nprim, const double* __restrict__ box,
+__global__ void __launch_bounds__(BT) insert_kernel(int32_t nt, int32_t ne, const double* __restrict__ tbox,
+                                                    const double* __restrict__ ebox,
                                                     const double* __restrict__ params, uint32_t mask,
-                                                    int32_t* __restrict__ count, int32_t* __restrict__ ids,
-                                                    uint64_t* __restrict__ keys) {
-  int32_t p = blockIdx.x * BT + threadIdx.x;
-  if (p >= nprim) return;
+                                                    int32_t* __restrict__ tcount, int32_t* __restrict__ tids,
+                                                    uint64_t* __restrict__ tkeys, int32_t* __restrict__ ecount,
+                                                    int32_t* __restrict__ eids, uint64_t* __restrict__ ekeys) {
+  const int32_t g = blockIdx.x * BT + threadIdx.x;
+  if (g >= nt + ne) return;
+  const bool tri = g < nt;
+  const int32_t p = tri ? g : g - nt;
+  int32_t* count = tri ? tcount : ecount;
+  int32_t* ids = tri ? tids : eids;
+  uint64_t* keys = tri ? tkeys : ekeys;
   const double o0 = params[0], o1 = params[1], o2 = params[2], h = params[3];
-  const double* b = box + 6 * static_cast<int64_t>(p);
+  const double* b = (tri ? tbox : ebox) + 6 * static_cast<int64_t>(p);
   int32_t l0 = cell_of(b[0], o0, h), l1 = cell_of(b[1], o1, h), l2 = cell_of(b[2], o2, h);
   int32_t u0 = clamp_hi(l0, cell_of(b[3], o0, h)), u1 = clamp_hi(l1, cell_of(b[4], o1, h)),
           u2 = clamp_hi(l2, cell_of(b[5], o2, h));
@@ -287,6 +302,7 @@ constexpr int QW = QT / PDIPC_WAVE;   // queries per workgroup
 __global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * QW + threadIdx.x / PDIPC_WAVE;
   const int64_t nq = static_cast<int64_t>(qa.px.nsv) + qa.px.nse;
+  if (blockIdx.x == 0 && threadIdx.x == 0) qcount[nq] = 0;     // sentinel of the scan
   if (q >= nq) return;
   const int32_t c = query_wave(qa, q, [&](int32_t, int32_t) {});
   if (threadIdx.x % PDIPC_WAVE == 0) qcount[q] = c;
@@ -335,10 +351,6 @@ __global__ void __launch_bounds__(256) query_emit_kernel(ProxyDev px, const int3
   }
 }
 
-__global__ void pt_total_kernel(const int32_t* __restrict__ qoff, int32_t nsv, int32_t* __restrict__ out) {
-  *out = qoff[nsv];
-}
-
 int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x, const double* dx, double dhat,
                bool distance_filter, PairList& out, int32_t* n_pt, int32_t* n_ee, hipStream_t st,
                int64_t* needed) {
@@ -358,23 +370,27 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
   grid_params_final<<<1, 64, 0, st>>>(part, 64, pad, bb.params);
   const uint32_t T = 1u << bb.table_bits;
   const uint32_t mask = T - 1;
-  launch_fill_i32(bb.t_count, T + 1, 0, st);
-  launch_fill_i32(bb.e_count, T + 1, 0, st);
-  if (px.nst) insert_kernel<false><<<grid_for(px.nst, BT), BT, 0, st>>>(px.nst, bb.tbox, bb.params, mask, bb.t_count, nullptr, nullptr);
-  if (px.nse) insert_kernel<false><<<grid_for(px.nse, BT), BT, 0, st>>>(px.nse, bb.ebox, bb.params, mask, bb.e_count, nullptr, nullptr);
-  launch_exclusive_scan(bb.t_count, bb.t_count, T + 1, bb.d_totals + 2, bb.scan_temp, st);
-  launch_exclusive_scan(bb.e_count, bb.e_count, T + 1, bb.d_totals + 3, bb.scan_temp, st);
-  hipMemcpyAsync(bb.t_cursor, bb.t_count, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToDevice, st);
-  hipMemcpyAsync(bb.e_cursor, bb.e_count, sizeof(int32_t) * (T + 1), hipMemcpyDeviceToDevice, st);
-  if (px.nst) insert_kernel<true><<<grid_for(px.nst, BT), BT, 0, st>>>(px.nst, bb.tbox, bb.params, mask, bb.t_cursor, bb.t_id, bb.t_key);
-  if (px.nse) insert_kernel<true><<<grid_for(px.nse, BT), BT, 0, st>>>(px.nse, bb.ebox, bb.params, mask, bb.e_cursor, bb.e_id, bb.e_key);
+  launch_fill2_i32(bb.t_count, T + 1, bb.e_count, T + 1, 0, st);
+  const int32_t nte = px.nst + px.nse;
+  insert_kernel<false><<<grid_for(nte, BT), BT, 0, st>>>(px.nst, px.nse, bb.tbox, bb.ebox, bb.params, mask, bb.t_count,
+                                                         nullptr, nullptr, bb.e_count, nullptr, nullptr);
+  {
+    // bucket starts, with copies as the fill cursors
+    const ScanJob jobs[2] = {{bb.t_count, bb.t_count, T + 1, bb.d_totals + 2, bb.t_cursor, -1, nullptr},
+                             {bb.e_count, bb.e_count, T + 1, bb.d_totals + 3, bb.e_cursor, -1, nullptr}};
+    launch_exclusive_scans(jobs, 2, bb.scan_temp, st);
+  }
+  insert_kernel<true><<<grid_for(nte, BT), BT, 0, st>>>(px.nst, px.nse, bb.tbox, bb.ebox, bb.params, mask, bb.t_cursor,
+                                                        bb.t_id, bb.t_key, bb.e_cursor, bb.e_id, bb.e_key);
 
   QueryArgs qa{px, x, bb.vbox, bb.tbox, bb.ebox, bb.params, mask, bb.t_count, bb.t_id, bb.t_key,
                bb.e_count, bb.e_id, bb.e_key, dhat, distance_filter};
-  launch_fill_i32(bb.q_count + nq, 1, 0, st);     // sentinel slot of the scan
   query_count_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count);
-  launch_exclusive_scan(bb.q_count, bb.q_count, nq + 1, bb.d_totals, bb.scan_temp, st);
-  pt_total_kernel<<<1, 1, 0, st>>>(bb.q_count, px.nsv, bb.d_totals + 1);
+  {
+    // per-query offsets; the offset of the first edge query is the PT count
+    const ScanJob job{bb.q_count, bb.q_count, nq + 1, bb.d_totals, nullptr, px.nsv, bb.d_totals + 1};
+    launch_exclusive_scans(&job, 1, bb.scan_temp, st);
+  }
   int32_t h_tot[4];
   hipMemcpyAsync(h_tot, bb.d_totals, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);

@@ -15,53 +15,63 @@ int64_t nblocks(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
-// Exclusive scan in two launches: per-tile sums, then every tile adds the sums
-// of the tiles before it (read from the small bsum array) to its local scan.
-// The last tile also writes the total.  The input may alias the output: each
-// tile reads its inputs into registers before writing.
-__global__ void __launch_bounds__(SCAN_T) scan_reduce_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                             int32_t* __restrict__ bsum) {
+// Exclusive scans in two launches: per-tile sums, then every tile adds the
+// sums of the tiles before it (read from the small bsum array) to its local
+// scan.  Up to two independent arrays share the launches (their tiles follow
+// each other in the grid).  The last tile of an array writes its total; a
+// tile may also copy its output to a second array and hand over the scanned
+// value at one index.  The input may alias the output: each tile reads its
+// inputs into registers before writing.
+__device__ __forceinline__ int scan_job_index(const ScanJobs& js, int64_t b) { return b < js.nb0 ? 0 : 1; }
+
+__global__ void __launch_bounds__(SCAN_T) scan_reduce_kernel(ScanJobs js, int32_t* __restrict__ bsum) {
   __shared__ int32_t sh[SCAN_T / PDIPC_WAVE];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+  const int w = scan_job_index(js, blockIdx.x);
+  const ScanJob& J = js.j[w];
+  const int64_t tile = w ? blockIdx.x - js.nb0 : blockIdx.x;
+  const int64_t base = tile * SCAN_TILE;
   int32_t acc = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t idx = base + k * SCAN_T + threadIdx.x;
-    acc += idx < n ? in[idx] : 0;
+    acc += idx < J.n ? J.in[idx] : 0;
   }
   acc = wave_sum_i32(acc);
   if (threadIdx.x % PDIPC_WAVE == 0) sh[threadIdx.x / PDIPC_WAVE] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     int32_t t = 0;
-    for (int w = 0; w < SCAN_T / PDIPC_WAVE; ++w) t += sh[w];
+    for (int v = 0; v < SCAN_T / PDIPC_WAVE; ++v) t += sh[v];
     bsum[blockIdx.x] = t;
   }
 }
 
-__global__ void __launch_bounds__(SCAN_T) scan_apply_kernel(const int32_t* in, int32_t* out, int64_t n,
-                                                            const int32_t* __restrict__ bsum, int32_t nb,
-                                                            int32_t* __restrict__ d_total) {
+__global__ void __launch_bounds__(SCAN_T) scan_apply_kernel(ScanJobs js, const int32_t* __restrict__ bsum) {
   __shared__ int32_t sh[SCAN_T];
   __shared__ int32_t wsum[SCAN_T / PDIPC_WAVE];
-  // offset of this tile: sum of the tile sums before it
+  const int w = scan_job_index(js, blockIdx.x);
+  const ScanJob& J = js.j[w];
+  const int64_t first = w ? js.nb0 : 0;
+  const int64_t tile = blockIdx.x - first;
+  const int64_t ntiles = (J.n + SCAN_TILE - 1) / SCAN_TILE;
+  // offset of this tile: sum of the tile sums before it (same array)
   int32_t off = 0;
-  for (int b = threadIdx.x; b < static_cast<int>(blockIdx.x); b += SCAN_T) off += bsum[b];
+  for (int64_t b = first + threadIdx.x; b < static_cast<int64_t>(blockIdx.x); b += SCAN_T) off += bsum[b];
   off = wave_sum_i32(off);
   if (threadIdx.x % PDIPC_WAVE == 0) wsum[threadIdx.x / PDIPC_WAVE] = off;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + static_cast<int64_t>(threadIdx.x) * SCAN_ITEMS;
+  const int64_t base = tile * SCAN_TILE + static_cast<int64_t>(threadIdx.x) * SCAN_ITEMS;
   int32_t v[SCAN_ITEMS];
   int32_t acc = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t idx = base + k;
-    v[k] = idx < n ? in[idx] : 0;
+    v[k] = idx < J.n ? J.in[idx] : 0;
     acc += v[k];
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
   int32_t tile_off = 0;
-  for (int w = 0; w < SCAN_T / PDIPC_WAVE; ++w) tile_off += wsum[w];
+  for (int q = 0; q < SCAN_T / PDIPC_WAVE; ++q) tile_off += wsum[q];
   for (int o = 1; o < SCAN_T; o <<= 1) {
     const int32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
     __syncthreads();
@@ -72,24 +82,43 @@ __global__ void __launch_bounds__(SCAN_T) scan_apply_kernel(const int32_t* in, i
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t idx = base + k;
-    if (idx < n) out[idx] = run;
+    if (idx < J.n) {
+      J.out[idx] = run;
+      if (J.copy) J.copy[idx] = run;
+      if (idx == J.pick && J.pick_out) *J.pick_out = run;
+    }
     run += v[k];
   }
-  if (blockIdx.x == static_cast<unsigned>(nb - 1) && threadIdx.x == SCAN_T - 1) *d_total = tile_off + sh[SCAN_T - 1];
+  if (tile == ntiles - 1 && threadIdx.x == SCAN_T - 1) *J.d_total = tile_off + sh[SCAN_T - 1];
 }
 
-size_t scan_temp_bytes(int64_t n) { return align256(sizeof(int32_t) * (nblocks(n) + 1)) + 256; }
+size_t scan_temp_bytes(int64_t n) { return align256(sizeof(int32_t) * (2 * nblocks(n) + 2)) + 256; }
+
+void launch_exclusive_scans(const ScanJob* jobs, int njobs, void* temp, hipStream_t st) {
+  ScanJobs js{};
+  int64_t nbt = 0;
+  int k = 0;
+  for (int q = 0; q < njobs; ++q) {
+    if (jobs[q].n <= 0) {
+      launch_fill_i32(jobs[q].d_total, 1, 0, st);
+      continue;
+    }
+    js.j[k] = jobs[q];
+    if (k == 0) js.nb0 = nblocks(jobs[q].n);
+    nbt += nblocks(jobs[q].n);
+    ++k;
+  }
+  if (k == 0) return;
+  if (k == 1) js.j[1] = js.j[0];
+  int32_t* bsum = static_cast<int32_t*>(temp);
+  scan_reduce_kernel<<<static_cast<unsigned>(nbt), SCAN_T, 0, st>>>(js, bsum);
+  scan_apply_kernel<<<static_cast<unsigned>(nbt), SCAN_T, 0, st>>>(js, bsum);
+}
 
 void launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total, void* temp,
                            hipStream_t st) {
-  if (n <= 0) {
-    launch_fill_i32(d_total, 1, 0, st);
-    return;
-  }
-  const int64_t nb = nblocks(n);
-  int32_t* bsum = static_cast<int32_t*>(temp);
-  scan_reduce_kernel<<<static_cast<unsigned>(nb), SCAN_T, 0, st>>>(in, n, bsum);
-  scan_apply_kernel<<<static_cast<unsigned>(nb), SCAN_T, 0, st>>>(in, out, n, bsum, static_cast<int32_t>(nb), d_total);
+  ScanJob j{in, out, n, d_total, nullptr, -1, nullptr};
+  launch_exclusive_scans(&j, 1, temp, st);
 }
 
 // ---- deterministic FP64 sums -------------------------------------------------
@@ -254,6 +283,14 @@ void launch_differ_i32(const int32_t* a, const int32_t* b, int64_t n, int32_t* d
 
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   if (n > 0) fill_i32_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
+}
+__global__ void fill2_i32_kernel(int32_t* a, int64_t na, int32_t* b, int64_t nb, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < na) a[i] = v;
+  else if (i < na + nb) b[i - na] = v;
+}
+void launch_fill2_i32(int32_t* a, int64_t na, int32_t* b, int64_t nb, int32_t v, hipStream_t st) {
+  if (na + nb > 0) fill2_i32_kernel<<<grid_for(na + nb, 256), 256, 0, st>>>(a, na, b, nb, v);
 }
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
   if (n > 0) fill_f64_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n, v);

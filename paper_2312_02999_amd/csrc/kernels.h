@@ -28,8 +28,25 @@ void launch_actuation_scalar(int64_t m, const double* a, const double* R, double
 void launch_actuation_transpose(int64_t m, const double* Ain, double* A, hipStream_t st);
 
 // ------------------------------------------------------------------- utility
-// exclusive scan of n int32 into out (out may alias in); total -> *d_total
+// exclusive scan of n int32 into out (out may alias in); total -> *d_total.
+// A job may also write a copy of the output and hand over the scanned value
+// at index pick; two jobs share one pair of launches (temp sized by
+// scan_temp_bytes of the larger n).
+struct ScanJob {
+  const int32_t* in;
+  int32_t* out;
+  int64_t n;
+  int32_t* d_total;
+  int32_t* copy;       // optional second output
+  int64_t pick;        // index whose scanned value goes to *pick_out (optional)
+  int32_t* pick_out;
+};
+struct ScanJobs {
+  ScanJob j[2];
+  int64_t nb0;         // tiles of the first job
+};
 size_t scan_temp_bytes(int64_t n);
+void launch_exclusive_scans(const ScanJob* jobs, int njobs, void* temp, hipStream_t st);
 void launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total, void* temp,
                            hipStream_t st);
 // deterministic sum of n doubles into *d_out (fixed blocked order)
@@ -47,6 +64,8 @@ void launch_axpy_ls(int64_t n3, const double* ls, const double* dx, double* x, h
 // min of n doubles (>= 0 entries) into *d_out, 1.0 if n == 0 (exact: min is order-free)
 void launch_min_clamp1(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+// two int32 arrays filled with v in one launch
+void launch_fill2_i32(int32_t* a, int64_t na, int32_t* b, int64_t nb, int32_t v, hipStream_t st);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 void launch_axpy_positions(int64_t n3, double alpha, const double* dx, double* x, hipStream_t st);
 void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);

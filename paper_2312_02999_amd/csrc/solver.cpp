@@ -568,7 +568,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   bb.tmp_cap = S->tmpj.cap;
   bb.scan_temp = S->scan_tmp.p; bb.red_temp = S->red_tmp.p;
   for (auto* b : {&S->inc_cnt, &S->inc_ptr, &S->inc_cflag, &S->inc_cidx}) b->ensure(n + 1);
-  S->inc_cursor.ensure(n);
+  S->inc_cursor.ensure(n + 1);
   S->inc_clist.ensure(n);
   S->inc_nc.ensure(2);
   HIPCHK(hipStreamSynchronize(st));
