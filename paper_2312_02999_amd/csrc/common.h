@@ -81,6 +81,15 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Minimum over a 256-thread block (wave butterflies, then the four waves).
+// Every thread calls it; all hold the result.
+__device__ __forceinline__ double block256_min(double v, double* sh4) {
+  v = wave_min(v);
+  if (threadIdx.x % PDIPC_WAVE == 0) sh4[threadIdx.x / PDIPC_WAVE] = v;
+  __syncthreads();
+  return fmin(fmin(sh4[0], sh4[1]), fmin(sh4[2], sh4[3]));
+}
+
 inline unsigned grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return static_cast<unsigned>(g < 1 ? 1 : g);

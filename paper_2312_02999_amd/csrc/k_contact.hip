@@ -468,11 +468,10 @@ int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const do
 }
 
 // ---- CCD: conservative advancement ---------------------------------------------
-__global__ void __launch_bounds__(BT) ccd_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
-                                                 const double* __restrict__ x, const double* __restrict__ dx,
-                                                 double eta, int32_t steps, double* __restrict__ tout) {
-  int32_t k = blockIdx.x * BT + threadIdx.x;
-  if (k >= npairs) return;
+// Conservative bound of one swept candidate.
+__device__ __forceinline__ double ccd_pair(const int32_t* __restrict__ v4all, int32_t k, int32_t n_pt,
+                                           const double* __restrict__ x, const double* __restrict__ dx, double eta,
+                                           int32_t steps) {
   const bool is_pt = k < n_pt;
   int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
   double P[4][3];
@@ -505,13 +504,29 @@ __global__ void __launch_bounds__(BT) ccd_kernel(const int32_t* __restrict__ v4a
       t = fmin(1.0, t + fmax(0.0, dt - g) / l);
     }
   }
-  tout[k] = t;
+  return t;
 }
 
-void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
-                int32_t steps, double* t_out, hipStream_t st) {
-  if (npairs <= 0) return;
-  ccd_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, eta, steps, t_out);
+// One thread per candidate; each block also writes the minimum of its bounds
+// (the step bound alpha_m is the minimum over the blocks).
+__global__ void __launch_bounds__(BT) ccd_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
+                                                 const double* __restrict__ x, const double* __restrict__ dx,
+                                                 double eta, int32_t steps, double* __restrict__ tout,
+                                                 double* __restrict__ part) {
+  __shared__ double sh4[4];
+  const int32_t k = blockIdx.x * BT + threadIdx.x;
+  const double t = k < npairs ? ccd_pair(v4all, k, n_pt, x, dx, eta, steps) : 1.0;
+  if (k < npairs) tout[k] = t;
+  const double mn = block256_min(t, sh4);
+  if (threadIdx.x == 0) part[blockIdx.x] = mn;
+}
+
+int launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
+               int32_t steps, double* t_out, double* part, hipStream_t st) {
+  if (npairs <= 0) return 0;
+  const unsigned g = grid_for(npairs, BT);
+  ccd_kernel<<<g, BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, eta, steps, t_out, part);
+  return static_cast<int>(g);
 }
 
 // ---- line-search barrier energies -------------------------------------------------

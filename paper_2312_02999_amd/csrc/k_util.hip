@@ -225,25 +225,16 @@ __global__ void axpy_kernel(int64_t n, double alpha, const double* __restrict__ 
 }
 
 // ---- device line-search state (Section 2.2 back-tracking; see kernels.h) ---------
-__global__ void ls_init_kernel(double* ls, const double* __restrict__ alpha_m) {
-  ls[LS_ALPHA] = *alpha_m;
+// alpha_m = min(1, minimum over the CCD blocks' minima); one wave
+__global__ void __launch_bounds__(PDIPC_WAVE) ls_init_kernel(double* ls, const double* __restrict__ part, int nparts) {
+  double a = 1.0;
+  for (int i = threadIdx.x; i < nparts; i += PDIPC_WAVE) a = fmin(a, part[i]);
+  a = wave_min(a);
+  if (threadIdx.x != 0) return;
+  ls[LS_ALPHA] = a;
   ls[LS_STATE] = 0.0;
   ls[LS_HALVINGS] = 0.0;
-  ls[LS_ALPHA_M] = *alpha_m;
-}
-// accept when the energy change of the current trial is <= 0; otherwise halve,
-// and give up (state -1) after max_halvings halvings
-__global__ void ls_decide_kernel(double* ls, const double* __restrict__ dE, int32_t max_halvings) {
-  if (ls[LS_STATE] != 0.0) return;
-  ls[LS_DE] = *dE;
-  if (*dE <= 0.0) {
-    ls[LS_STATE] = 1.0;
-  } else if (ls[LS_HALVINGS] >= max_halvings) {
-    ls[LS_STATE] = -1.0;
-  } else {
-    ls[LS_HALVINGS] += 1.0;
-    ls[LS_ALPHA] *= 0.5;
-  }
+  ls[LS_ALPHA_M] = a;
 }
 __global__ void axpy_ls_kernel(int64_t n, const double* __restrict__ ls, const double* __restrict__ dx,
                                double* __restrict__ x) {
@@ -252,9 +243,35 @@ __global__ void axpy_ls_kernel(int64_t n, const double* __restrict__ ls, const d
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) x[i] = x[i] + alpha * dx[i];
 }
-void launch_ls_init(double* ls, const double* alpha_m, hipStream_t st) { ls_init_kernel<<<1, 1, 0, st>>>(ls, alpha_m); }
-void launch_ls_decide(double* ls, const double* dE, int32_t max_halvings, hipStream_t st) {
-  ls_decide_kernel<<<1, 1, 0, st>>>(ls, dE, max_halvings);
+void launch_ls_init(double* ls, const double* part, int nparts, hipStream_t st) {
+  ls_init_kernel<<<1, PDIPC_WAVE, 0, st>>>(ls, part, nparts);
+}
+// dE of a trial: the second stage of launch_sum2 (the same partials and the
+// same block reduction as sum_final_kernel), then the decision: accept when
+// dE <= 0; otherwise halve alpha, and give up (state -1) after max_halvings
+// halvings.
+__global__ void __launch_bounds__(RED_T) ls_final_decide_kernel(double* ls, const double* __restrict__ part,
+                                                                int nparts, int32_t max_halvings) {
+  if (ls[LS_STATE] != 0.0) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += RED_T) acc += part[i];
+  const double dE = block_sum(acc);
+  if (threadIdx.x != 0) return;
+  ls[LS_DE] = dE;
+  if (dE <= 0.0) {
+    ls[LS_STATE] = 1.0;
+  } else if (ls[LS_HALVINGS] >= max_halvings) {
+    ls[LS_STATE] = -1.0;
+  } else {
+    ls[LS_HALVINGS] += 1.0;
+    ls[LS_ALPHA] *= 0.5;
+  }
+}
+void launch_sum2_decide(const double* a, int64_t na, const double* b, int64_t nb, double* ls, void* temp,
+                        int32_t max_halvings, hipStream_t st) {
+  double* part = static_cast<double*>(temp);
+  sum_partial_kernel<<<RED_BLOCKS, RED_T, 0, st>>>(a, na, b, nb, ls, part);
+  ls_final_decide_kernel<<<1, RED_T, 0, st>>>(ls, part, RED_BLOCKS, max_halvings);
 }
 void launch_axpy_ls(int64_t n3, const double* ls, const double* dx, double* x, hipStream_t st) {
   if (n3 > 0) axpy_ls_kernel<<<grid_for(n3, 256), 256, 0, st>>>(n3, ls, dx, x);

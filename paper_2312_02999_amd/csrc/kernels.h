@@ -20,8 +20,8 @@ void launch_local_step(const LocalArgs& la, const double* x, const double* Rwarm
                        double* tetg, bool fp32, hipStream_t st, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr);
 void launch_identity_rotations(int64_t m, double* R, hipStream_t st);
-void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, const double* ls,
-                         const double* Rwarm, const double* E0, double* dE, bool fp32, hipStream_t st);
+void launch_trial_energy(const LocalArgs& la, const double* x, const double* dx, const double* ls, const double* Rwarm,
+                         const double* E0, double* dE, bool fp32, hipStream_t st);
 void launch_gather_vertex_grad(int32_t n, int64_t m, const int32_t* vt_ptr, const int32_t* vt_ent,
                                const double* tetg, const uint8_t* fixed, double* g, hipStream_t st);
 void launch_actuation_scalar(int64_t m, const double* a, const double* R, double* A, hipStream_t st);
@@ -58,8 +58,12 @@ void launch_sum2(const double* a, int64_t na, const double* b, int64_t nb, doubl
 // read alpha from it and do nothing once the state is decided (1 accepted,
 // -1 failed), so several trials can be queued without reading anything back.
 enum { LS_ALPHA = 0, LS_STATE = 1, LS_HALVINGS = 2, LS_ALPHA_M = 3, LS_DE = 4, LS_SIZE = 8 };
-void launch_ls_init(double* ls, const double* alpha_m, hipStream_t st);
-void launch_ls_decide(double* ls, const double* dE, int32_t max_halvings, hipStream_t st);
+// alpha_m = min(1, the CCD blocks' minima); starts the search
+void launch_ls_init(double* ls, const double* part, int nparts, hipStream_t st);
+// dE of a trial = the deterministic sum of a (elements) and b (pairs), as
+// launch_sum2; then accept / halve / give up
+void launch_sum2_decide(const double* a, int64_t na, const double* b, int64_t nb, double* ls, void* temp,
+                        int32_t max_halvings, hipStream_t st);
 void launch_axpy_ls(int64_t n3, const double* ls, const double* dx, double* x, hipStream_t st);
 // min of n doubles (>= 0 entries) into *d_out, 1.0 if n == 0 (exact: min is order-free)
 void launch_min_clamp1(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
@@ -127,8 +131,9 @@ int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const do
                   hipStream_t st, int64_t* needed);
 
 // CCD: t_k per candidate pair (conservative advancement), then alpha_m.
-void launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
-                int32_t steps, double* t_out, hipStream_t st);
+// per-candidate bounds t_out and per-block minima part; returns the blocks
+int launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
+               int32_t steps, double* t_out, double* part, hipStream_t st);
 // kappa * b(d) per candidate at x + alpha dx (alpha = 0 allowed); pairs at
 // d >= dhat give 0.
 void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,

@@ -143,6 +143,7 @@ struct Solver {
   // device line-search state; factor statuses still to be checked
   DBuf<double> lsbuf;
   DBuf<double> refres;        // refinement residual maxima
+  DBuf<double> ccd_part;      // per-block minima of the CCD bounds
   bool check_info_m = false, check_info_cs = false;
   // adjoint work vectors
   DBuf<double> lam, res, zvec, pvec, kp, prod, pairbuf;
@@ -914,17 +915,19 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   S->tpair.ensure(std::max(ncand, 1));
   S->bE0.ensure(std::max(ncand, 1));
   S->bdE.ensure(std::max(ncand, 1));
+  S->ccd_part.ensure(std::max<int64_t>((ncand + 255) / 256, 1));
+  int nccd = 0;
   {
     ScopedTimer tm(S, TK_CCD);
-    launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p, st);
+    nccd = launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p,
+                      S->ccd_part.p, st);
   }
-  launch_min_clamp1(S->tpair.p, ncand, S->scal.p, S->red_tmp.p, st);
   launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, nullptr, nullptr, S->opt.dhat, S->opt.kappa, nullptr,
                              S->bE0.p, st);
   // back-tracking line search on the device: trials read alpha from the state
   // and become no-ops once it is decided; two are queued, then one readback
   double* ls = S->lsbuf.p;
-  launch_ls_init(ls, S->scal.p, st);
+  launch_ls_init(ls, S->ccd_part.p, nccd, st);
   auto trial = [&]() {
     {
       ScopedTimer tm(S, TK_TRIAL);
@@ -932,8 +935,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
     }
     launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, ls, S->opt.dhat, S->opt.kappa, S->bE0.p,
                                S->bdE.p, st);
-    launch_sum2(S->dE.p, S->m, S->bdE.p, ncand, S->scal.p + 1, S->red_tmp.p, st, ls);
-    launch_ls_decide(ls, S->scal.p + 1, S->opt.ls_max_halvings, st);
+    launch_sum2_decide(S->dE.p, S->m, S->bdE.p, ncand, ls, S->red_tmp.p, S->opt.ls_max_halvings, st);
   };
   const int queued = std::min(2, S->opt.ls_max_halvings + 1);
   for (int h = 0; h < queued; ++h) trial();
@@ -1246,6 +1248,7 @@ void pdipc_destroy(void* h) {
   S->prev_cflag.release();
   S->lsbuf.release();
   S->refres.release();
+  S->ccd_part.release();
   delete S;
 }
 
