@@ -110,6 +110,9 @@ def run_precision(sc, precision, steps, warmup, timer_kernel):
         "ls_failures": sum(s["ls_failures"] for s in stats),
         "refine_steps": sum(s["refine_steps"] for s in stats),
         "refine_fallbacks": sum(s["refine_fallbacks"] for s in stats),
+        "cinv_rebuilds": sum(s["cinv_rebuilds"] for s in stats),
+        "c_delta_max": max(s["c_delta_max"] for s in stats),
+        "c_delta_sum": sum(s["c_delta_sum"] for s in stats),
         "stage_ms": {k: float(np.mean([s[k] for s in stats])) for k in ("ms_ipc", "ms_gstep", "ms_ls", "ms_misc")},
         "x_final": x.cpu().numpy(),
     }
@@ -268,7 +271,9 @@ def main():
         "p50_ms": round(mixed["p50_ms"], 3), "p99_ms": round(mixed["p99_ms"], 3),
         "fp64": {"value": round(fp64["fps"], 3), "ms_per_step": round(fp64["ms_per_frame"], 3),
                  "p50_ms": round(fp64["p50_ms"], 3), "p99_ms": round(fp64["p99_ms"], 3),
-                 "stage_ms": fp64["stage_ms"], "n_c_max": fp64["n_c_max"], "ls_failures": fp64["ls_failures"]},
+                 "stage_ms": fp64["stage_ms"], "n_c_max": fp64["n_c_max"], "ls_failures": fp64["ls_failures"],
+                 "cinv_rebuilds": fp64["cinv_rebuilds"], "c_delta_max": fp64["c_delta_max"],
+                 "c_delta_sum": fp64["c_delta_sum"]},
         "mixed": {"stage_ms": mixed["stage_ms"], "n_c_max": mixed["n_c_max"], "ls_failures": mixed["ls_failures"],
                   "refine_steps": mixed["refine_steps"], "refine_fallbacks": mixed["refine_fallbacks"],
                   "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},

@@ -98,10 +98,13 @@ typedef struct {
  * columns: IPC (constraint set + barrier derivatives), G-Step (global solve),
  * CCD, LS (line search), Misc (local step, assembly, bookkeeping).
  * refine_steps / refine_fallbacks: mixed-precision refinement solves and the
- * iterations whose reduced system fell back to the FP64 factor. */
+ * iterations whose reduced system fell back to the FP64 factor.
+ * cinv_rebuilds: iterations whose contact set c differed from the previous
+ * one (C^-1 recomputed); c_delta_max / c_delta_sum: vertices that entered or
+ * left c at those iterations (largest, total). */
 typedef struct {
   int32_t iters, n_pt, n_ee, n_c, ls_halvings, ls_failures, refine_steps;
-  int32_t n_candidates, refine_fallbacks;
+  int32_t n_candidates, refine_fallbacks, cinv_rebuilds, c_delta_max, c_delta_sum;
   double alpha_m_min, alpha_min, energy, grad_inf;
   double ms_ipc, ms_gstep, ms_ccd, ms_ls, ms_misc, ms_total;
 } pdipc_frame_stats;

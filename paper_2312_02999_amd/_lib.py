@@ -46,7 +46,9 @@ class Options(C.Structure):
 class FrameStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_pt", C.c_int32), ("n_ee", C.c_int32), ("n_c", C.c_int32),
                 ("ls_halvings", C.c_int32), ("ls_failures", C.c_int32), ("refine_steps", C.c_int32),
-                ("n_candidates", C.c_int32), ("refine_fallbacks", C.c_int32), ("alpha_m_min", C.c_double), ("alpha_min", C.c_double),
+                ("n_candidates", C.c_int32), ("refine_fallbacks", C.c_int32), ("cinv_rebuilds", C.c_int32),
+                ("c_delta_max", C.c_int32), ("c_delta_sum", C.c_int32), ("alpha_m_min", C.c_double),
+                ("alpha_min", C.c_double),
                 ("energy", C.c_double), ("grad_inf", C.c_double), ("ms_ipc", C.c_double),
                 ("ms_gstep", C.c_double), ("ms_ccd", C.c_double), ("ms_ls", C.c_double),
                 ("ms_misc", C.c_double), ("ms_total", C.c_double)]

@@ -391,7 +391,7 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
     const ScanJob job{bb.q_count, bb.q_count, nq + 1, bb.d_totals, nullptr, px.nsv, bb.d_totals + 1};
     launch_exclusive_scans(&job, 1, bb.scan_temp, st);
   }
-  int32_t h_tot[4];
+  int32_t* h_tot = bb.h_totals;
   hipMemcpyAsync(h_tot, bb.d_totals, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
   const int32_t npairs = h_tot[0];
@@ -438,13 +438,9 @@ __global__ void __launch_bounds__(BT) compact_pairs_kernel(PairList src, int32_t
   for (int a = 0; a < 4; ++a) dst.v4[4 * o + a] = src.v4[4 * k + a];
 }
 
-__global__ void pt_count_kernel(const int32_t* __restrict__ pos, int32_t n_pt, int32_t* __restrict__ out) {
-  *out = pos[n_pt];
-}
-
 int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const double* x, double dhat, PairList& out,
-                  int32_t* flag, int32_t* pos, int32_t* d_tot, void* scan_temp, int32_t* n_pt, int32_t* n_ee,
-                  hipStream_t st, int64_t* needed) {
+                  int32_t* flag, int32_t* pos, int32_t* d_tot, int32_t* h_tot, void* scan_temp, int32_t* n_pt,
+                  int32_t* n_ee, hipStream_t st, int64_t* needed) {
   *needed = 0;
   if (ncand <= 0) {
     *n_pt = 0;
@@ -452,9 +448,12 @@ int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const do
     return 0;
   }
   active_flag_kernel<<<grid_for(ncand + 1, BT), BT, 0, st>>>(cand.v4, ncand, cand_pt, x, dhat, flag);
-  launch_exclusive_scan(flag, pos, ncand + 1, d_tot, scan_temp, st);
-  pt_count_kernel<<<1, 1, 0, st>>>(pos, cand_pt, d_tot + 1);
-  int32_t h[2];
+  {
+    // active positions; the position of the first EE candidate is the PT count
+    const ScanJob job{flag, pos, ncand + 1, d_tot, nullptr, cand_pt, d_tot + 1};
+    launch_exclusive_scans(&job, 1, scan_temp, st);
+  }
+  int32_t* h = h_tot;
   hipMemcpyAsync(h, d_tot, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
   if (h[0] > out.cap) {

@@ -286,16 +286,24 @@ void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStrea
   if (n > 0) count_nonfinite_kernel<<<grid_for(n, 256), 256, 0, st>>>(x, n, d_out);
 }
 
-// *flag <- 1 if a and b differ anywhere in [0, n) (cleared first; every
-// writer stores the same value)
-__global__ void differ_kernel(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n,
-                              int32_t* __restrict__ flag) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n && a[i] != b[i]) *flag = 1;
+// Change of a flag set: out[0] = 1 if any entry differs, out[1] = entries set
+// before and cleared now, out[2] = entries set now and not before (wave
+// ballots, one integer atomic per wave).
+__global__ void __launch_bounds__(256) set_delta_kernel(const int32_t* __restrict__ cur,
+                                                        const int32_t* __restrict__ prev, int64_t n,
+                                                        int32_t* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool p = i < n && prev[i] != 0, c = i < n && cur[i] != 0;
+  const uint64_t mr = __ballot(p && !c), ma = __ballot(c && !p);
+  if (threadIdx.x % PDIPC_WAVE == 0 && (mr | ma) != 0) {
+    out[0] = 1;
+    if (mr) atomicAdd(out + 1, static_cast<int32_t>(__popcll(mr)));
+    if (ma) atomicAdd(out + 2, static_cast<int32_t>(__popcll(ma)));
+  }
 }
-void launch_differ_i32(const int32_t* a, const int32_t* b, int64_t n, int32_t* d_flag, hipStream_t st) {
-  launch_fill_i32(d_flag, 1, 0, st);
-  if (n > 0) differ_kernel<<<grid_for(n, 256), 256, 0, st>>>(a, b, n, d_flag);
+void launch_set_delta(const int32_t* cur, const int32_t* prev, int64_t n, int32_t* d_out3, hipStream_t st) {
+  launch_fill_i32(d_out3, 3, 0, st);
+  if (n > 0) set_delta_kernel<<<grid_for(n, 256), 256, 0, st>>>(cur, prev, n, d_out3);
 }
 
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {

@@ -75,7 +75,9 @@ void launch_axpy_positions(int64_t n3, double alpha, const double* dx, double* x
 void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
 // number of non-finite entries -> *d_out
 void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStream_t st);
-void launch_differ_i32(const int32_t* a, const int32_t* b, int64_t n, int32_t* d_flag, hipStream_t st);
+// out[0] = any entry of cur and prev differs (as flags), out[1] = set in prev
+// only, out[2] = set in cur only
+void launch_set_delta(const int32_t* cur, const int32_t* prev, int64_t n, int32_t* d_out3, hipStream_t st);
 
 // ------------------------------------------------------------------- contact
 struct ProxyDev {
@@ -101,10 +103,11 @@ struct BroadPhaseBuffers {
   int32_t* e_id;
   uint64_t* e_key;
   int64_t ent_cap;      // capacity of each entry array
-  int32_t* q_count;     // 8 (nsv + nse) + 1 per-(query, cell slot) counts / offsets
+  int32_t* q_count;     // nsv + nse + 1 per-query counts / offsets
   int32_t* tmpj;        // unsorted partner ids
   int64_t tmp_cap;
   int32_t* d_totals;    // [0] pairs total
+  int32_t* h_totals;    // pinned host copy of d_totals (4 entries)
   void* scan_temp;
   void* red_temp;
 };
@@ -126,9 +129,10 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
 
 // Constraint set at x as the pairs of a (sorted) candidate list with squared
 // distance below dhat^2; order preserved.  flag, pos: ncand + 1 ints.
+// h_tot: pinned host memory for the two counts read back
 int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const double* x, double dhat, PairList& out,
-                  int32_t* flag, int32_t* pos, int32_t* d_tot, void* scan_temp, int32_t* n_pt, int32_t* n_ee,
-                  hipStream_t st, int64_t* needed);
+                  int32_t* flag, int32_t* pos, int32_t* d_tot, int32_t* h_tot, void* scan_temp, int32_t* n_pt,
+                  int32_t* n_ee, hipStream_t st, int64_t* needed);
 
 // CCD: t_k per candidate pair (conservative advancement), then alpha_m.
 // per-candidate bounds t_out and per-block minima part; returns the blocks

@@ -131,6 +131,7 @@ struct Solver {
   DBuf<int32_t> c_x2, info;
   DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid, CsL, CsLi, ML, MLi, scl;
   int32_t refine_steps = 0, refine_fallbacks = 0;
+  int32_t cinv_rebuilds = 0, c_delta_max = 0, c_delta_sum = 0;
   DBuf<float> Mf, uf, MLf, MLif;
   // swept candidates of the last step (x_prev -> x_prev + dx), valid for x on that path
   bool cand_valid = false;
@@ -151,6 +152,7 @@ struct Solver {
 
   // host helpers
   double* h_scal = nullptr;   // pinned readback
+  int32_t* h_counts = nullptr;   // pinned readback of pair counts (8)
   // optional HIP-event timer around every launch of one kernel family
   int32_t timer_which = -1;
   // second stream (default priority) for the reduced contact system, which
@@ -168,6 +170,7 @@ struct Solver {
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
     if (h_scal) (void)hipHostFree(h_scal);
+    if (h_counts) (void)hipHostFree(h_counts);
     if (st) (void)hipStreamSynchronize(st);
   }
 };
@@ -423,6 +426,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   HIPCHK(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_counts), 8 * sizeof(int32_t), hipHostMallocDefault));
 
   // ---- factor upload ---------------------------------------------------------------------------
   const int32_t nn = static_cast<int32_t>(hf.nodes.size());
@@ -563,7 +567,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   bb.table_bits = bits;
   bb.t_count = S->t_count.p; bb.t_cursor = S->t_cursor.p; bb.t_id = S->t_id.p; bb.t_key = S->t_key.p;
   bb.e_count = S->e_count.p; bb.e_cursor = S->e_cursor.p; bb.e_id = S->e_id.p; bb.e_key = S->e_key.p;
-  bb.ent_cap = ent; bb.q_count = S->q_count.p; bb.d_totals = S->totals.p;
+  bb.ent_cap = ent; bb.q_count = S->q_count.p; bb.d_totals = S->totals.p; bb.h_totals = S->h_counts;
   S->tmpj.ensure(4LL * S->nsv + 1024);
   bb.tmpj = S->tmpj.p;
   bb.tmp_cap = S->tmpj.cap;
@@ -571,7 +575,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   for (auto* b : {&S->inc_cnt, &S->inc_ptr, &S->inc_cflag, &S->inc_cidx}) b->ensure(n + 1);
   S->inc_cursor.ensure(n + 1);
   S->inc_clist.ensure(n);
-  S->inc_nc.ensure(2);
+  S->inc_nc.ensure(4);
   HIPCHK(hipStreamSynchronize(st));
   return PDIPC_OK;
 }
@@ -618,7 +622,7 @@ static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee) {
   for (int attempt = 0; attempt < 3; ++attempt) {
     int64_t need = 0;
     int rc = filter_active(S->cand, S->cand_n, S->cand_pt, S->x.p, S->opt.dhat, pl, S->cflagbuf.p, S->cposbuf.p,
-                           S->totals.p + 4, S->scan_tmp.p, npt, nee, S->st, &need);
+                           S->totals.p + 4, S->h_counts + 4, S->scan_tmp.p, npt, nee, S->st, &need);
     if (rc == 0) return;
     grow_pairs(S, pl, S->act_type, S->act_i, S->act_j, S->act_v4, need);
   }
@@ -662,16 +666,19 @@ struct IterOut {
   bool c_same = false;          // contact set equal to the one C^-1 was built for
   bool nc_pending = false;      // n_c (and c_same) still in flight to h_scal
   bool nc_with_same = false;    // the readback carries the c_same flag
+  int32_t c_removed = 0, c_added = 0;   // vertices that left / entered c
   double alpha_m = 1.0, alpha = 0.0;
 };
 
 static void finish_readback(Solver* S, IterOut& io) {
   if (!io.nc_pending) return;
   HIPCHK(hipEventSynchronize(S->ev_fork));
-  int32_t h2[2] = {0, 1};
-  std::memcpy(h2, S->h_scal, sizeof(int32_t) * (io.nc_with_same ? 2 : 1));
-  io.nc = h2[0];
-  io.c_same = io.nc_with_same && h2[1] == 0;
+  int32_t h4[4] = {0, 1, 0, 0};
+  std::memcpy(h4, S->h_scal, sizeof(int32_t) * (io.nc_with_same ? 4 : 1));
+  io.nc = h4[0];
+  io.c_same = io.nc_with_same && h4[1] == 0;
+  io.c_removed = io.nc_with_same ? h4[2] : 0;
+  io.c_added = io.nc_with_same ? h4[3] : h4[0];
   io.nc_pending = false;
 }
 
@@ -704,9 +711,9 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
   }
   build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
   launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
-  if (S->cinv_valid) launch_differ_i32(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st);
+  if (S->cinv_valid) launch_set_delta(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st);
   io.nc_with_same = S->cinv_valid;
-  HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (io.nc_with_same ? 2 : 1), hipMemcpyDeviceToHost,
+  HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (io.nc_with_same ? 4 : 1), hipMemcpyDeviceToHost,
                         st));
   HIPCHK(hipEventRecord(S->ev_fork, st));
   io.nc_pending = true;
@@ -841,6 +848,12 @@ static void global_step(Solver* S, IterOut& io) {
     hipStream_t sd = S->side;
     HIPCHK(hipStreamWaitEvent(sd, S->ev_fork, 0));
     if (!io.c_same) {
+      if (io.nc_with_same) {
+        const int32_t delta = io.c_removed + io.c_added;
+        S->cinv_rebuilds++;
+        S->c_delta_sum += delta;
+        S->c_delta_max = std::max(S->c_delta_max, delta);
+      }
       launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, sd);
       launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, sd);
       dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p + 3, sd);
@@ -984,6 +997,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   double tms[5] = {0, 0, 0, 0, 0};
   S->refine_steps = 0;
   S->refine_fallbacks = 0;
+  S->cinv_rebuilds = S->c_delta_max = S->c_delta_sum = 0;
   int it = 0;
   for (; it < S->opt.iters; ++it) {
     IterOut io;
@@ -1021,6 +1035,9 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   fs.iters = it;
   fs.refine_steps = S->refine_steps;
   fs.refine_fallbacks = S->refine_fallbacks;
+  fs.cinv_rebuilds = S->cinv_rebuilds;
+  fs.c_delta_max = S->c_delta_max;
+  fs.c_delta_sum = S->c_delta_sum;
   if (tol_mode && it >= S->opt.iters && rc == PDIPC_OK) rc = PDIPC_W_NOT_CONVERGED;
   HIPCHK(hipMemcpyAsync(x_out, S->x.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
