@@ -82,6 +82,9 @@ typedef struct {
  *  ccd_eta         CCD target gap as a fraction of the current distance
  *  ccd_steps       conservative-advancement steps per pair
  *  ls_max_halvings line-search halvings before giving up (alpha = 0)
+ *  cinv_updates_max  when at most 32 vertices leave and 32 enter the contact
+ *                  set, C^-1 is updated in place of rebuilt, up to this many
+ *                  times in a row (0 = always rebuild)
  *  stream          hipStream_t to order work on (NULL = default stream)
  */
 typedef struct {
@@ -90,7 +93,7 @@ typedef struct {
   double tol;
   int32_t precision;
   double ccd_eta;
-  int32_t ccd_steps, ls_max_halvings;
+  int32_t ccd_steps, ls_max_halvings, cinv_updates_max;
   void* stream;
 } pdipc_options;
 
@@ -101,10 +104,11 @@ typedef struct {
  * iterations whose reduced system fell back to the FP64 factor.
  * cinv_rebuilds: iterations whose contact set c differed from the previous
  * one (C^-1 recomputed); c_delta_max / c_delta_sum: vertices that entered or
- * left c at those iterations (largest, total). */
+ * left c at those iterations (largest, total); cinv_updates: those of them
+ * served by the incremental update of C^-1. */
 typedef struct {
   int32_t iters, n_pt, n_ee, n_c, ls_halvings, ls_failures, refine_steps;
-  int32_t n_candidates, refine_fallbacks, cinv_rebuilds, c_delta_max, c_delta_sum;
+  int32_t n_candidates, refine_fallbacks, cinv_rebuilds, c_delta_max, c_delta_sum, cinv_updates;
   double alpha_m_min, alpha_min, energy, grad_inf;
   double ms_ipc, ms_gstep, ms_ccd, ms_ls, ms_misc, ms_total;
 } pdipc_frame_stats;
@@ -151,7 +155,8 @@ int32_t pdipc_get_sizes(const void* solver, int64_t* n1, int64_t* n2, int64_t* f
 /* Measurement tap: read and reset the HIP-event timer, then arm it for the
  * kernel family `which` (-1 = off): 0 local step, 1 Sigma^-1 GEMV, 2 lower
  * sweep, 3 upper sweep, 4 barrier, 5 line-search energies, 6 reduced
- * Cholesky, 8 CCD.  Events are recorded on the solver's stream around every
+ * Cholesky, 8 CCD, 9 incremental C^-1 update, 10 full C^-1
+ * rebuild (Cholesky and inverse of the contact block).  Events are recorded on the solver's stream around every
  * launch of that family during pdipc_solve_frame; *total_ms and *launches
  * (host, nullable) return what was accumulated since the previous call. */
 int32_t pdipc_kernel_timer(void* solver, int32_t which, double* total_ms, int64_t* launches);

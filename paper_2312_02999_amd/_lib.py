@@ -40,14 +40,15 @@ class MeshDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("dhat", C.c_double), ("kappa", C.c_double), ("iters", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("ccd_eta", C.c_double), ("ccd_steps", C.c_int32),
-                ("ls_max_halvings", C.c_int32), ("stream", C.c_void_p)]
+                ("ls_max_halvings", C.c_int32), ("cinv_updates_max", C.c_int32), ("stream", C.c_void_p)]
 
 
 class FrameStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_pt", C.c_int32), ("n_ee", C.c_int32), ("n_c", C.c_int32),
                 ("ls_halvings", C.c_int32), ("ls_failures", C.c_int32), ("refine_steps", C.c_int32),
                 ("n_candidates", C.c_int32), ("refine_fallbacks", C.c_int32), ("cinv_rebuilds", C.c_int32),
-                ("c_delta_max", C.c_int32), ("c_delta_sum", C.c_int32), ("alpha_m_min", C.c_double),
+                ("c_delta_max", C.c_int32), ("c_delta_sum", C.c_int32), ("cinv_updates", C.c_int32),
+                ("alpha_m_min", C.c_double),
                 ("alpha_min", C.c_double),
                 ("energy", C.c_double), ("grad_inf", C.c_double), ("ms_ipc", C.c_double),
                 ("ms_gstep", C.c_double), ("ms_ccd", C.c_double), ("ms_ls", C.c_double),

@@ -76,8 +76,10 @@ void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipS
 // number of non-finite entries -> *d_out
 void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStream_t st);
 // out[0] = any entry of cur and prev differs (as flags), out[1] = set in prev
-// only, out[2] = set in cur only
-void launch_set_delta(const int32_t* cur, const int32_t* prev, int64_t n, int32_t* d_out3, hipStream_t st);
+// only, out[2] = set in cur only; with lists, up to cap indices of each of the
+// two kinds go to rem_ids / add_ids (unordered)
+void launch_set_delta(const int32_t* cur, const int32_t* prev, int64_t n, int32_t* d_out3, hipStream_t st,
+                      int32_t* rem_ids = nullptr, int32_t* add_ids = nullptr, int32_t cap = 0);
 
 // ------------------------------------------------------------------- contact
 struct ProxyDev {
@@ -265,6 +267,35 @@ void launch_refine_correct(const float* F, float* aux, int64_t n, const float* r
 // Ainv = (L L^T)^-1 (full symmetric, row-major), work: n x n scratch
 template <typename T>
 void dense_chol_inverse(const T* F, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st);
+// C^-1 after a small change of the contact set c (at most 32 vertices leave and
+// at most 32 enter; at least one is kept): the previous inverse Ci (order of
+// the previous c, nold x nold) is downdated for the leaving vertices and
+// bordered with the entering ones (Schur complement against Sigma^-1), giving
+// out (nc x nc, order of the new c).  rem_ids / add_ids hold the r leaving and
+// a entering vertices in any order (launch_set_delta's lists); pflag/pidx are
+// the previous contact flags and ranks, cflag/cidx the current ones.  A
+// non-positive pivot of the two small SPD inverses sets *info (zeroed first).
+struct CinvLists {
+  int32_t* kept_old;   // nk: previous index of the k-th kept vertex
+  int32_t* kept_x2;    // nk: its index among the rows of Sigma^-1
+  int32_t* rem_old;    // r: previous index of the leaving vertices (by id)
+  int32_t* add_x2;     // a: Sigma^-1 index of the entering vertices (by id)
+  int32_t* kind;       // nc: k >= 0 kept rank k, -1 - q entering vertex q
+};
+struct CinvUpdateArgs {
+  int32_t n, nold, nc, r, a, n2;
+  const int32_t *cflag, *cidx, *pflag, *pidx, *vert2x2;
+  const int32_t *rem_ids, *add_ids;
+  int32_t* info;
+  CinvLists L;
+  const double* Ci;                  // previous inverse
+  const double* Si;                  // Sigma^-1 (n2 x n2)
+  double *Sm, *Sinv;                 // a x a, 32 x 32
+  double *T, *W, *V;                 // nk x r, nk x a, nk x a
+  double* CK;                        // nk x nk
+  double* out;                       // nc x nc
+};
+void launch_cinv_update(const CinvUpdateArgs& u, hipStream_t st);
 void launch_convert_f64_f32(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_convert_f32_f64(const float* in, double* out, int64_t n, hipStream_t st);
 // Jacobi scaling sc_i = 1/sqrt(M_ii); FP32 copies of S M S and S r; u += S y

@@ -131,7 +131,7 @@ struct Solver {
   DBuf<int32_t> c_x2, info;
   DBuf<double> Cs, Cinv, work, Mred, rhs, u, vvec, wtmp, resid, CsL, CsLi, ML, MLi, scl;
   int32_t refine_steps = 0, refine_fallbacks = 0;
-  int32_t cinv_rebuilds = 0, c_delta_max = 0, c_delta_sum = 0;
+  int32_t cinv_rebuilds = 0, c_delta_max = 0, c_delta_sum = 0, cinv_updates = 0;
   DBuf<float> Mf, uf, MLf, MLif;
   // swept candidates of the last step (x_prev -> x_prev + dx), valid for x on that path
   bool cand_valid = false;
@@ -141,6 +141,12 @@ struct Solver {
   // constant): it is kept while the flags of c are unchanged
   DBuf<int32_t> prev_cflag;
   bool cinv_valid = false;
+  // incremental update of C^-1: ranks of the previous c, its size, updates
+  // since the last full rebuild, and the work buffers
+  DBuf<int32_t> prev_cidx, cupd_i, cset_ids;
+  DBuf<double> Cinv_next, cupd_d;
+  int32_t nc_prev = 0, cinv_since_full = 0;
+  bool cinv_incr_ok = false;
   // device line-search state; factor statuses still to be checked
   DBuf<double> lsbuf;
   DBuf<double> refres;        // refinement residual maxima
@@ -180,7 +186,7 @@ static void fail(int code, const std::string& msg) { throw SolverError{code, msg
 
 // Kernel families that the event timer can bracket.
 enum TimerKernel { TK_LOCAL = 0, TK_SIGMA_GEMV = 1, TK_FWD = 2, TK_BWD = 3, TK_BARRIER = 4, TK_TRIAL = 5,
-                   TK_REDUCED_CHOL = 6, TK_PAIRS = 7, TK_CCD = 8 };
+                   TK_REDUCED_CHOL = 6, TK_PAIRS = 7, TK_CCD = 8, TK_CINV_UPDATE = 9, TK_CINV_FULL = 10 };
 
 struct ScopedTimer {
   Solver* S;
@@ -237,6 +243,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   const int32_t n = md->n_verts, m = md->n_tets;
   if (n <= 0 || m <= 0 || !md->rest_pos || !md->tets || !md->dirichlet) fail(PDIPC_E_INVALID, "empty mesh");
   if (!(op->dhat > 0) || !(op->kappa > 0) || op->iters <= 0 || op->ccd_steps <= 0 || op->ls_max_halvings < 0 ||
+      op->cinv_updates_max < 0 ||
       !(op->ccd_eta > 0 && op->ccd_eta < 1))
     fail(PDIPC_E_INVALID, "bad options");
   if (op->precision != PDIPC_FP64 && op->precision != PDIPC_MIXED_FP32) fail(PDIPC_E_INVALID, "bad precision");
@@ -682,6 +689,19 @@ static void finish_readback(Solver* S, IterOut& io) {
   io.nc_pending = false;
 }
 
+// Most vertices that may leave (and, separately, enter) c for an incremental
+// update of C^-1 in place of a rebuild.
+static constexpr int32_t kCinvMaxDelta = 32;
+
+// Start of a frame (or of another pass over one state): C^-1 is kept only if
+// it came from a full rebuild, a function of its contact set alone, and the
+// first change of the set is a full rebuild too, so that what a pass computes
+// does not depend on earlier calls.
+static void cinv_begin_pass(Solver* S) {
+  if (S->cinv_since_full > 0) S->cinv_valid = false;
+  S->cinv_incr_ok = false;
+}
+
 // Local step + constraint set + barrier + gradient; returns pair counts, n_c.
 // With defer, n_c is left in flight (the fork event marks its copy) and
 // global_step collects it after queueing the sweeps, which need only g.
@@ -711,7 +731,16 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
   }
   build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
   launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
-  if (S->cinv_valid) launch_set_delta(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st);
+  if (S->cinv_valid) {
+    // the vertices that left / entered c are listed for the incremental update
+    int32_t* ids = nullptr;
+    if (S->opt.cinv_updates_max > 0) {
+      S->cset_ids.ensure(2 * kCinvMaxDelta);
+      ids = S->cset_ids.p;
+    }
+    launch_set_delta(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st, ids,
+                     ids ? ids + kCinvMaxDelta : nullptr, kCinvMaxDelta);
+  }
   io.nc_with_same = S->cinv_valid;
   HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (io.nc_with_same ? 4 : 1), hipMemcpyDeviceToHost,
                         st));
@@ -825,7 +854,6 @@ static void global_step(Solver* S, IterOut& io) {
   if (nc > 0) {
     S->c_x2.ensure(nc);
     S->Cs.ensure(static_cast<int64_t>(nc) * nc);
-    S->Cinv.ensure(static_cast<int64_t>(nc) * nc);
     S->work.ensure(static_cast<int64_t>(nc) * nc);
     S->Mred.ensure(N3 * N3);
     S->CsL.ensure(static_cast<int64_t>(nc) * nc);
@@ -848,6 +876,10 @@ static void global_step(Solver* S, IterOut& io) {
     hipStream_t sd = S->side;
     HIPCHK(hipStreamWaitEvent(sd, S->ev_fork, 0));
     if (!io.c_same) {
+      const int32_t nk = nc - io.c_added;
+      const bool incremental = io.nc_with_same && S->cinv_incr_ok && S->cinv_since_full < S->opt.cinv_updates_max &&
+                               io.c_removed <= kCinvMaxDelta && io.c_added <= kCinvMaxDelta && nk >= 1 &&
+                               nk == S->nc_prev - io.c_removed;
       if (io.nc_with_same) {
         const int32_t delta = io.c_removed + io.c_added;
         S->cinv_rebuilds++;
@@ -855,14 +887,57 @@ static void global_step(Solver* S, IterOut& io) {
         S->c_delta_max = std::max(S->c_delta_max, delta);
       }
       launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, sd);
-      launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, sd);
-      dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p + 3, sd);
+      if (incremental) {
+        ScopedTimer tm(S, TK_CINV_UPDATE, sd);
+        const int32_t r = io.c_removed, a = io.c_added;
+        S->cupd_i.ensure(2LL * nk + 2 * kCinvMaxDelta + nc);
+        S->cupd_d.ensure(32 * 32 + a * a + static_cast<int64_t>(nk) * (r + 2 * a + nk));
+        S->Cinv_next.ensure(static_cast<int64_t>(nc) * nc);
+        CinvUpdateArgs u{};
+        u.n = S->n; u.nold = S->nc_prev; u.nc = nc; u.r = r; u.a = a; u.n2 = f.n2;
+        u.cflag = S->inc.cflag; u.cidx = S->inc.cidx; u.pflag = S->prev_cflag.p; u.pidx = S->prev_cidx.p;
+        u.vert2x2 = S->vert2x2.p;
+        u.rem_ids = S->cset_ids.p;
+        u.add_ids = S->cset_ids.p + kCinvMaxDelta;
+        int32_t* ip = S->cupd_i.p;
+        u.L.kept_old = ip; ip += nk;
+        u.L.kept_x2 = ip; ip += nk;
+        u.L.rem_old = ip; ip += kCinvMaxDelta;
+        u.L.add_x2 = ip; ip += kCinvMaxDelta;
+        u.L.kind = ip;
+        u.info = S->info.p + 3;
+        u.Ci = S->Cinv.p;
+        u.Si = f.sigma_inv;
+        double* dp = S->cupd_d.p;
+        u.Sinv = dp; dp += 32 * 32;
+        u.Sm = dp; dp += a * a;
+        u.T = dp; dp += static_cast<int64_t>(nk) * r;
+        u.W = dp; dp += static_cast<int64_t>(nk) * a;
+        u.V = dp; dp += static_cast<int64_t>(nk) * a;
+        u.CK = dp;
+        u.out = S->Cinv_next.p;
+        launch_cinv_update(u, sd);
+        std::swap(S->Cinv, S->Cinv_next);
+        S->cinv_updates++;
+        S->cinv_since_full++;
+      } else {
+        ScopedTimer tm(S, TK_CINV_FULL, sd);
+        S->Cinv.ensure(static_cast<int64_t>(nc) * nc);
+        launch_gather_cc(f, nc, S->c_x2.p, S->Cs.p, sd);
+        dense_cholesky<double>(S->Cs.p, nc, S->CsL.p, S->CsLi.p, S->info.p + 3, sd);
+        dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, sd);
+        S->cinv_since_full = 0;
+      }
       S->check_info_cs = true;
-      dense_chol_inverse<double>(S->CsL.p, S->CsLi.p, nc, S->Cinv.p, S->work.p, sd);
       S->prev_cflag.ensure(S->n + 1LL);
+      S->prev_cidx.ensure(S->n + 1LL);
       HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, sd));
+      HIPCHK(hipMemcpyAsync(S->prev_cidx.p, S->inc.cidx, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, sd));
+      S->nc_prev = nc;
       S->cinv_valid = true;
+      io.c_same = true;                 // later solves with this io reuse it
     }
+    S->cinv_incr_ok = true;
     launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, sd);
     if (mixed) {
       // Jacobi-scaled FP32 copy and its factor (refined against FP64 below)
@@ -987,6 +1062,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   // the local steps of a frame start from the identity, so a frame does not
   // depend on earlier calls
   launch_identity_rotations(S->m, S->Rtet.p, st);
+  cinv_begin_pass(S);
   launch_count_nonfinite(S->x.p, 3LL * S->n, S->info.p + 2, st);
   if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite input state");
   pdipc_frame_stats fs{};
@@ -997,7 +1073,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   double tms[5] = {0, 0, 0, 0, 0};
   S->refine_steps = 0;
   S->refine_fallbacks = 0;
-  S->cinv_rebuilds = S->c_delta_max = S->c_delta_sum = 0;
+  S->cinv_rebuilds = S->c_delta_max = S->c_delta_sum = S->cinv_updates = 0;
   int it = 0;
   for (; it < S->opt.iters; ++it) {
     IterOut io;
@@ -1038,6 +1114,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   fs.cinv_rebuilds = S->cinv_rebuilds;
   fs.c_delta_max = S->c_delta_max;
   fs.c_delta_sum = S->c_delta_sum;
+  fs.cinv_updates = S->cinv_updates;
   if (tol_mode && it >= S->opt.iters && rc == PDIPC_OK) rc = PDIPC_W_NOT_CONVERGED;
   HIPCHK(hipMemcpyAsync(x_out, S->x.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1065,6 +1142,7 @@ static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
   IterOut io;
   S->cand_valid = false;
   launch_identity_rotations(S->m, S->Rtet.p, st);   // same rotations whatever ran before
+  cinv_begin_pass(S);
   assemble_gradient(S, true, io);                   // rotations, pairs, barrier factors at x*
   const int32_t np = io.npt + io.nee;
   S->lam.ensure(n3); S->res.ensure(n3); S->zvec.ensure(n3); S->pvec.ensure(n3); S->kp.ensure(n3);
@@ -1160,6 +1238,7 @@ void pdipc_default_options(pdipc_options* o) {
   o->ccd_eta = 0.1;
   o->ccd_steps = 16;
   o->ls_max_halvings = 20;
+  o->cinv_updates_max = 16;
   o->stream = nullptr;
 }
 
@@ -1263,6 +1342,7 @@ void pdipc_destroy(void* h) {
   S->pairbuf.release();
   S->CsL.release(); S->CsLi.release(); S->ML.release(); S->MLi.release(); S->scl.release();
   S->prev_cflag.release();
+  S->prev_cidx.release(); S->cupd_i.release(); S->Cinv_next.release(); S->cupd_d.release(); S->cset_ids.release();
   S->lsbuf.release();
   S->refres.release();
   S->ccd_part.release();
@@ -1343,6 +1423,7 @@ int32_t pdipc_debug_step(void* h, const double* x, double* dx, double* alpha_m, 
     HIPCHK(hipMemcpyAsync(S->x.p, x, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
     S->cand_valid = false;
     launch_identity_rotations(S->m, S->Rtet.p, S->st);
+    cinv_begin_pass(S);
     IterOut io;
     assemble_gradient(S, true, io);
     global_step(S, io);

@@ -207,6 +207,40 @@ def test_mixed_precision_fixed_iterations_face():
     assert worst < 1e-6, worst
 
 
+@pytest.mark.parametrize("name", ["slabs", "face5k"])
+def test_incremental_cinv_matches_rebuild(name):
+    """C^-1 = ((Sigma^-1)_cc)^-1 downdated for vertices leaving c and bordered
+    with those entering (Schur complement) against full rebuilds at every
+    change of c, over the whole frame sequence (FP64)."""
+    sc = mg.scene_by_name(name)
+    Sf = _solver(sc, iters=sc.iters, cinv_updates_max=0)
+    Si = _solver(sc, iters=sc.iters)
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    xf = xi = _t(sc.X)
+    R = _t(sc.act_R.reshape(-1, 9))
+    worst, updates, changes, ncmax = 0.0, 0, 0, 0
+    for t in range(sc.frames):
+        a = _t(sc.actuation_at((t + 1) / sc.frames))
+        Sf.set_actuation_scalar(a, R)
+        Si.set_actuation_scalar(a, R)
+        xf, sf = Sf.solve_frame(xf, stats=True)
+        xi, si = Si.solve_frame(xi, stats=True)
+        assert sf["cinv_updates"] == 0
+        updates += si["cinv_updates"]
+        changes += si["cinv_rebuilds"]
+        ncmax = max(ncmax, si["n_c"])
+        worst = max(worst, np.abs(xi.cpu().numpy() - xf.cpu().numpy()).max() / diag)
+    print(f"incremental C^-1 {name}: {updates} updates of {changes} changes, n_c max {ncmax}, worst {worst:.3e}")
+    assert updates > 0
+    assert worst < 1e-9, worst
+    # a frame still does not depend on earlier calls
+    Si.set_actuation_scalar(_t(sc.actuation_at(1.0)), R)
+    x0 = xi.clone()
+    a1 = Si.solve_frame(x0).cpu().numpy()
+    a2 = Si.solve_frame(x0).cpu().numpy()
+    assert np.array_equal(a1, a2)
+
+
 def test_frame_is_bitwise_repeatable():
     """No floating-point atomics on the path: two runs give identical bits."""
     sc = mg.slabs(0)
