@@ -77,14 +77,19 @@ typedef struct {
  *  dhat, kappa     barrier threshold d_0 and stiffness (Eq. 3)
  *  iters           iterations per frame (fixed mode) or cap (tolerance mode)
  *  tol             > 0: stop when max |alpha dx| <= tol; <= 0: fixed iters
- *  precision       PDIPC_FP64 or PDIPC_MIXED_FP32 (FP32 local/barrier passes and
- *                  FP32 reduced system, refined against FP64 residuals)
+ *  precision       PDIPC_FP64 or PDIPC_MIXED_FP32 (FP32 local/barrier passes and,
+ *                  from fp32_reduced_min unknowns on, an FP32 factor of the
+ *                  reduced system refined against FP64 residuals)
  *  ccd_eta         CCD target gap as a fraction of the current distance
  *  ccd_steps       conservative-advancement steps per pair
  *  ls_max_halvings line-search halvings before giving up (alpha = 0)
  *  cinv_updates_max  when at most 32 vertices leave and 32 enter the contact
  *                  set, C^-1 is updated in place of rebuilt, up to this many
  *                  times in a row (0 = always rebuild)
+ *  fp32_reduced_min  mixed precision: smallest reduced system (3 n_c unknowns)
+ *                  solved with the refined FP32 factor; smaller ones, whose
+ *                  factorisation is bound by its sequence of block steps
+ *                  rather than by arithmetic, use the FP64 factor
  *  stream          hipStream_t to order work on (NULL = default stream)
  */
 typedef struct {
@@ -93,7 +98,7 @@ typedef struct {
   double tol;
   int32_t precision;
   double ccd_eta;
-  int32_t ccd_steps, ls_max_halvings, cinv_updates_max;
+  int32_t ccd_steps, ls_max_halvings, cinv_updates_max, fp32_reduced_min;
   void* stream;
 } pdipc_options;
 

@@ -119,16 +119,19 @@ __global__ void __launch_bounds__(FT) fwd_x2_kernel(FactorDev f, const double* _
   }
 }
 
-void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st) {
+void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st, int level_begin,
+                          int level_end) {
   // t lives after y in the same allocation (caller provides 2 * 3 * N)
   double* tbuf = y + 3 * static_cast<int64_t>(f.n1 + f.n2);
-  for (int L = 0; L < f.nlevels; ++L) {
+  const bool to_end = level_end < 0;
+  if (to_end || level_end > f.nlevels) level_end = f.nlevels;
+  for (int L = level_begin > 0 ? level_begin : 0; L < level_end; ++L) {
     const int32_t r0 = f.h_lvl_row_ptr[L], nr = f.h_lvl_row_ptr[L + 1] - r0;
     if (nr <= 0) continue;
     fwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, b, y, tbuf);
     fwd_diag_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, tbuf, y);
   }
-  if (f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f, b, y);
+  if (to_end && f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f, b, y);
 }
 
 // z = Sigma^-1 r, r and z are n2 x 3 (x2 part of the extended vectors)

@@ -207,7 +207,10 @@ struct FactorDev {
 // b (ext, 3) = -g at ext2vert
 void launch_pack_rhs(const FactorDev& f, const double* g, double* b, hipStream_t st);
 // forward sweep: y (ext, 3); rows of x2 get r2 - L21 y1 (no diagonal solve)
-void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st);
+// (levels [level_begin, level_end) of the x1 sweep; level_end < 0: to the end,
+// then the x2 rows)
+void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st, int level_begin = 0,
+                          int level_end = -1);
 // z = Sigma^-1 r (n2 x 3)
 void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream_t st);
 // backward sweep: sol[0, n1) from y and sol[n1, n1 + n2) (already set)

@@ -243,7 +243,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   const int32_t n = md->n_verts, m = md->n_tets;
   if (n <= 0 || m <= 0 || !md->rest_pos || !md->tets || !md->dirichlet) fail(PDIPC_E_INVALID, "empty mesh");
   if (!(op->dhat > 0) || !(op->kappa > 0) || op->iters <= 0 || op->ccd_steps <= 0 || op->ls_max_halvings < 0 ||
-      op->cinv_updates_max < 0 ||
+      op->cinv_updates_max < 0 || op->fp32_reduced_min < 0 ||
       !(op->ccd_eta > 0 && op->ccd_eta < 1))
     fail(PDIPC_E_INVALID, "bad options");
   if (op->precision != PDIPC_FP64 && op->precision != PDIPC_MIXED_FP32) fail(PDIPC_E_INVALID, "bad precision");
@@ -689,6 +689,9 @@ static void finish_readback(Solver* S, IterOut& io) {
   io.nc_pending = false;
 }
 
+// Levels of the lower sweep queued before the host waits for n_c.
+static constexpr int kFwdLevelsBeforeFork = 3;
+
 // Most vertices that may leave (and, separately, enter) c for an incremental
 // update of C^-1 in place of a rebuild.
 static constexpr int32_t kCinvMaxDelta = 32;
@@ -834,23 +837,32 @@ static void global_step(Solver* S, IterOut& io) {
   hipStream_t st = S->st;
   FactorDev& f = S->fd;
   const int64_t n1x3 = 3LL * f.n1;
-  const bool mixed = S->opt.precision == PDIPC_MIXED_FP32;
+  const bool mixed_prec = S->opt.precision == PDIPC_MIXED_FP32;
   // the side stream below starts from the fork event: everything queued on
   // the main stream before this step (the contact terms, C^-1's last users)
   if (!io.nc_pending) HIPCHK(hipEventRecord(S->ev_fork, st));
-  // Eq. (7) forward part needs only g: queue it before waiting for n_c
+  // Eq. (7) forward part needs only g.  Its first levels are queued before
+  // waiting for n_c, so that the main stream stays busy while the host queues
+  // the side stream's work; the rest follows that.
   launch_pack_rhs(f, S->g.p, S->bvec.p, st);
+  const int split = std::min(kFwdLevelsBeforeFork, f.nlevels);
   {
     ScopedTimer tm(S, TK_FWD);
-    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
+    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st, 0, split);
   }
-  {
+  auto rest_of_forward = [&]() {
+    {
+      ScopedTimer tm(S, TK_FWD);
+      launch_forward_sweep(f, S->bvec.p, S->yvec.p, st, split, -1);
+    }
     ScopedTimer tm(S, TK_SIGMA_GEMV);
     launch_sigma_gemv(f, S->yvec.p + n1x3, S->solvec.p + n1x3, st);
-  }
+  };
   finish_readback(S, io);
   const int32_t np = io.npt + io.nee, nc = io.nc;
   const int64_t N3 = 3LL * nc;
+  // FP32 factor of the reduced system with FP64 refinement, or the FP64 factor
+  const bool mixed = mixed_prec && N3 >= S->opt.fp32_reduced_min;
   if (nc > 0) {
     S->c_x2.ensure(nc);
     S->Cs.ensure(static_cast<int64_t>(nc) * nc);
@@ -950,6 +962,7 @@ static void global_step(Solver* S, IterOut& io) {
       S->check_info_m = true;           // read back with the line-search state
     }
     HIPCHK(hipEventRecord(S->ev_join, sd));
+    rest_of_forward();
     HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
     bool fallback = false;
@@ -968,6 +981,8 @@ static void global_step(Solver* S, IterOut& io) {
     if (!mixed || fallback) dense_chol_solve_into<double>(S->ML.p, S->MLi.p, N3, S->rhs.p, S->u.p, st);
     launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
     launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
+  } else {
+    rest_of_forward();
   }
   {
     ScopedTimer tm(S, TK_BWD);
@@ -1239,6 +1254,7 @@ void pdipc_default_options(pdipc_options* o) {
   o->ccd_steps = 16;
   o->ls_max_halvings = 20;
   o->cinv_updates_max = 16;
+  o->fp32_reduced_min = 2049;
   o->stream = nullptr;
 }
 

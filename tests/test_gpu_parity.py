@@ -161,9 +161,11 @@ def test_dense_spd_rejects_indefinite():
         dense_spd(_t(A), _t(np.ones((70, 1))))
 
 
-def test_mixed_precision_converged_frame():
-    """FP32 local/barrier passes + FP32 reduced system refined against FP64
-    residuals reach the same equilibrium as the oracle: the frame is run to a
+@pytest.mark.parametrize("fp32_reduced_min", [0, 2049])
+def test_mixed_precision_converged_frame(fp32_reduced_min):
+    """FP32 local/barrier passes + the reduced system (FP32 factor refined
+    against FP64 residuals, or the FP64 factor below fp32_reduced_min
+    unknowns) reach the same equilibrium as the oracle: the frame is run to a
     step tolerance from rest and compared with the oracle's Newton-polished
     equilibrium (relative to the rest bounding-box diagonal)."""
     from paper_2312_02999_amd import MIXED_FP32
@@ -174,7 +176,7 @@ def test_mixed_precision_converged_frame():
     assert ocontact.constraint_set(xs, prob.prox, prob.dhat).size > 0
     # tolerance on the full direction: below ~1e-12 the energy differences of
     # the line search reach rounding and steps stop shortening the distance
-    S = _solver(sc, iters=4000, tol=1e-11, precision=MIXED_FP32)
+    S = _solver(sc, iters=4000, tol=1e-11, precision=MIXED_FP32, fp32_reduced_min=fp32_reduced_min)
     S.set_actuation_scalar(_t(a), _t(sc.act_R.reshape(-1, 9)))
     xg, st = S.solve_frame(_t(sc.X), stats=True)
     diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
@@ -182,6 +184,7 @@ def test_mixed_precision_converged_frame():
     print(f"mixed converged: iters {st['iters']} n_c {st['n_c']} err {err:.3e} refine {st['refine_steps']} "
           f"fallbacks {st['refine_fallbacks']}")
     assert st["n_c"] > 0 and st["iters"] < 4000
+    assert (st["refine_steps"] > 0) == (fp32_reduced_min == 0)
     assert err < 1e-8, err
 
 
