@@ -433,46 +433,67 @@ __global__ void __launch_bounds__(256) add_bcheck_kernel(int32_t nc, const int32
 }
 
 // Row block a of M = C^-1 + B_check in one pass (reduced systems up to
-// RB_LDS_N unknowns): one wave per contact vertex accumulates its three rows
-// of B_check in LDS, entry by entry in incidence order (deterministic), then
-// writes the rows with the C^-1 = C_s^-1 (x) I3 part added.
+// RB_LDS_N unknowns): one workgroup per contact vertex.  The 36 products of
+// each incidence entry (3 rows x 4 pair vertices x 3 columns) are formed by
+// all threads, RB_CHUNK entries at a time, and staged in LDS with their target
+// column; one wave then adds them to the three rows (LDS) entry by entry in
+// incidence order (deterministic), and the rows are written with the
+// C^-1 = C_s^-1 (x) I3 part added.
 constexpr int RB_LDS_N = 2048;
-__global__ void __launch_bounds__(64) assemble_rows_kernel(int32_t nc, const double* __restrict__ Cinv,
-                                                           const int32_t* __restrict__ clist,
-                                                           const int32_t* __restrict__ ptr,
-                                                           const int32_t* __restrict__ ent,
-                                                           const int32_t* __restrict__ v4,
-                                                           const int32_t* __restrict__ cflag,
-                                                           const int32_t* __restrict__ cidx,
-                                                           const double* __restrict__ U, int32_t npairs,
-                                                           double* __restrict__ M) {
+constexpr int RB_CHUNK = 7;                 // 7 x 36 products per pass of 256 threads
+__global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const double* __restrict__ Cinv,
+                                                            const int32_t* __restrict__ clist,
+                                                            const int32_t* __restrict__ ptr,
+                                                            const int32_t* __restrict__ ent,
+                                                            const int32_t* __restrict__ v4,
+                                                            const int32_t* __restrict__ cflag,
+                                                            const int32_t* __restrict__ cidx,
+                                                            const double* __restrict__ U, int32_t npairs,
+                                                            double* __restrict__ M) {
   extern __shared__ unsigned char smem_raw[];
   double* R = reinterpret_cast<double*>(smem_raw);     // 3 x N
-  const int lane = threadIdx.x;
+  __shared__ double P[RB_CHUNK * 36];
+  __shared__ int32_t Q[RB_CHUNK * 36];
+  const int tid = threadIdx.x;
   const int64_t ca = blockIdx.x;
   const int64_t N = 3 * static_cast<int64_t>(nc);
-  for (int64_t i = lane; i < 3 * N; i += PDIPC_WAVE) R[i] = 0.0;
-  __builtin_amdgcn_wave_barrier();
+  for (int64_t i = tid; i < 3 * N; i += blockDim.x) R[i] = 0.0;
   const int32_t va = clist[ca];
-  const int lb = lane / 9, r = (lane % 9) / 3, sc = lane % 3;
-  const bool active = lane < 36;
-#pragma unroll 4
-  for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
-    const int32_t k = ent[t] >> 2, la = ent[t] & 3;
-    const int32_t vb = active ? v4[4 * k + lb] : 0;
-    const bool use = active && cflag[vb];
-    double acc = 0.0;
-    if (use) {
+  const int32_t t0 = ptr[va], t1 = ptr[va + 1];
+  const int e = tid / 36, l36 = tid % 36;
+  const int lb = l36 / 9, r = (l36 % 9) / 3, sc = l36 % 3;
+  for (int32_t tc = t0; tc < t1; tc += RB_CHUNK) {
+    if (e < RB_CHUNK) {
+      const int32_t t = tc + e;
+      double acc = 0.0;
+      int32_t q = -1;
+      if (t < t1) {
+        const int32_t k = ent[t] >> 2, la = ent[t] & 3;
+        const int32_t vb = v4[4 * k + lb];
+        if (cflag[vb]) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c)
-        acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
-               U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
-      R[r * N + 3 * static_cast<int64_t>(cidx[vb]) + sc] += acc;
+          for (int c = 0; c < 5; ++c)
+            acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
+                   U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
+          q = static_cast<int32_t>(r * N + 3 * static_cast<int64_t>(cidx[vb]) + sc);
+        }
+      }
+      P[tid] = acc;
+      Q[tid] = q;
     }
+    __syncthreads();
+    if (tid < 36) {
+      const int ne = min(RB_CHUNK, t1 - tc);
+      for (int ee = 0; ee < ne; ++ee) {
+        const int32_t q = Q[ee * 36 + tid];
+        if (q >= 0) R[q] += P[ee * 36 + tid];
+      }
+    }
+    __syncthreads();
   }
-  __builtin_amdgcn_wave_barrier();
+  if (t0 >= t1) __syncthreads();               // R zeroed by every thread
   for (int rr = 0; rr < 3; ++rr)
-    for (int64_t col = lane; col < N; col += PDIPC_WAVE) {
+    for (int64_t col = tid; col < N; col += blockDim.x) {
       const double kron = (col % 3 == rr) ? Cinv[ca * nc + col / 3] : 0.0;
       M[(3 * ca + rr) * N + col] = kron + R[rr * N + col];
     }
@@ -482,7 +503,7 @@ void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& in
                              int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st) {
   int64_t N = 3 * static_cast<int64_t>(nc);
   if (N <= RB_LDS_N) {
-    assemble_rows_kernel<<<static_cast<unsigned>(nc), 64, sizeof(double) * 3 * N, st>>>(
+    assemble_rows_kernel<<<static_cast<unsigned>(nc), 256, sizeof(double) * 3 * N, st>>>(
         nc, Cinv, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx, bo.U, npairs, M);
     return;
   }

@@ -164,7 +164,7 @@ struct Solver {
   // second stream (default priority) for the reduced contact system, which
   // runs concurrently with the sweeps of the global step
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_cinv = nullptr;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   double timer_ms = 0.0;
@@ -174,6 +174,7 @@ struct Solver {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_cinv) (void)hipEventDestroy(ev_cinv);
     if (side) (void)hipStreamDestroy(side);
     if (h_scal) (void)hipHostFree(h_scal);
     if (h_counts) (void)hipHostFree(h_counts);
@@ -432,6 +433,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   HIPCHK(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&S->ev_cinv, hipEventDisableTiming));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_counts), 8 * sizeof(int32_t), hipHostMallocDefault));
 
@@ -950,6 +952,7 @@ static void global_step(Solver* S, IterOut& io) {
       io.c_same = true;                 // later solves with this io reuse it
     }
     S->cinv_incr_ok = true;
+    HIPCHK(hipEventRecord(S->ev_cinv, sd));          // C^-1 and c_x2 ready
     launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, sd);
     if (mixed) {
       // Jacobi-scaled FP32 copy and its factor (refined against FP64 below)
@@ -963,8 +966,9 @@ static void global_step(Solver* S, IterOut& io) {
     }
     HIPCHK(hipEventRecord(S->ev_join, sd));
     rest_of_forward();
-    HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
+    HIPCHK(hipStreamWaitEvent(st, S->ev_cinv, 0));
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
+    HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
     bool fallback = false;
     if (mixed) {
       const bool solved = dense_has_inverse(N3) ? refine_on_inverse(S, N3) : refine_on_blocks(S, N3);
