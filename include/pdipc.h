@@ -86,6 +86,12 @@ typedef struct {
  *  cinv_updates_max  when at most 32 vertices leave and 32 enter the contact
  *                  set, C^-1 is updated in place of rebuilt, up to this many
  *                  times in a row (0 = always rebuild)
+ *  hinv_rows_mb    device memory (MiB) allowed for the rows x2 of H_s^-1
+ *                  (n2 x (n1 + n2) FP64, built at init with one backward sweep
+ *                  per three rows).  With them the contact correction of the
+ *                  global step is one product over all rows, and the backward
+ *                  sweep runs on the uncorrected step while the reduced system
+ *                  is factored; 0 = off (correct x2, then sweep)
  *  fp32_reduced_min  mixed precision: smallest reduced system (3 n_c unknowns)
  *                  solved with the refined FP32 factor; smaller ones, whose
  *                  factorisation is bound by its sequence of block steps
@@ -98,7 +104,7 @@ typedef struct {
   double tol;
   int32_t precision;
   double ccd_eta;
-  int32_t ccd_steps, ls_max_halvings, cinv_updates_max, fp32_reduced_min;
+  int32_t ccd_steps, ls_max_halvings, cinv_updates_max, fp32_reduced_min, hinv_rows_mb;
   void* stream;
 } pdipc_options;
 

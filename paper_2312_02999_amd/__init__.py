@@ -43,7 +43,7 @@ class Solver:
     def __init__(self, scene=None, *, X=None, tets=None, dirichlet=None, surf_tris=None, region=None,
                  youngs=1e4, poisson=0.45, dhat=5e-4, kappa=1e3, iters=30, tol=0.0, precision=FP64,
                  ccd_eta=0.1, ccd_steps=16, ls_max_halvings=20, cinv_updates_max=16,
-                 fp32_reduced_min=2049, device="cuda", stream=None):
+                 fp32_reduced_min=2049, hinv_rows_mb=4096, device="cuda", stream=None):
         if scene is not None:
             X, tets, dirichlet, surf_tris = scene.X, scene.tets, scene.dirichlet, scene.surf_tris
             region = scene.region
@@ -63,7 +63,7 @@ class Solver:
         self.stream = st
         op = Options(float(dhat), float(kappa), int(iters), float(tol), int(precision), float(ccd_eta),
                      int(ccd_steps), int(ls_max_halvings), int(cinv_updates_max),
-                     int(fp32_reduced_min), C.c_void_p(st.cuda_stream))
+                     int(fp32_reduced_min), int(hinv_rows_mb), C.c_void_p(st.cuda_stream))
         h = C.c_void_p()
         check(lib().pdipc_init_mesh(C.byref(md), C.byref(op), C.byref(h)), None)
         self._h = h

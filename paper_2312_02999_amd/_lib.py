@@ -41,7 +41,7 @@ class Options(C.Structure):
     _fields_ = [("dhat", C.c_double), ("kappa", C.c_double), ("iters", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("ccd_eta", C.c_double), ("ccd_steps", C.c_int32),
                 ("ls_max_halvings", C.c_int32), ("cinv_updates_max", C.c_int32),
-                ("fp32_reduced_min", C.c_int32), ("stream", C.c_void_p)]
+                ("fp32_reduced_min", C.c_int32), ("hinv_rows_mb", C.c_int32), ("stream", C.c_void_p)]
 
 
 class FrameStats(C.Structure):

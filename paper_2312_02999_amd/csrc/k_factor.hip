@@ -288,24 +288,25 @@ void launch_cinv_times_zc(int32_t nc, const double* Cinv, const int32_t* c_x2, c
   if (nc > 0) cinv_zc_kernel<<<grid_for(nc, FT / PDIPC_WAVE), FT, 0, st>>>(nc, Cinv, c_x2, z, out);
 }
 
-// z[j] -= sum_i S[c_x2[i]][j] v[i]   (S symmetric: the rows of c are its columns)
-// z_j -= sum_i Sigma^-1[c_i][j] v_i (Sigma^-1 symmetric, rows read coalesced
-// along j).  Block: 64 consecutive j (one per lane) x 16 waves, wave g takes
-// i = g, g + 16, ...; the 16 partial sums are added in wave order, so the
-// result does not depend on scheduling.
+// z_j -= sum_i S[c_i][j] v_i over n_out outputs, S row-major with leading
+// dimension ld (for Sigma^-1, symmetric, the rows of c are its columns; for
+// the stored rows x2 of H_s^-1 they are those columns by symmetry of H_s^-1).
+// Rows are read coalesced along j.  Block: 64 consecutive j (one per lane) x
+// 16 waves, wave g takes i = g, g + 16, ...; the 16 partial sums are added in
+// wave order, so the result does not depend on scheduling.
 constexpr int SC_WAVES = 16;
-__global__ void __launch_bounds__(SC_WAVES * PDIPC_WAVE) sigma_cols_kernel(int32_t n2, int32_t nc,
-                                                                        const int32_t* __restrict__ c_x2,
-                                                                        const double* __restrict__ S,
-                                                                        const double* __restrict__ v,
-                                                                        double* __restrict__ z) {
+__global__ void __launch_bounds__(SC_WAVES * PDIPC_WAVE) rows_update_kernel(int64_t n_out, int64_t ld, int32_t nc,
+                                                                         const int32_t* __restrict__ c_x2,
+                                                                         const double* __restrict__ S,
+                                                                         const double* __restrict__ v,
+                                                                         double* __restrict__ z) {
   __shared__ double part[SC_WAVES][3][PDIPC_WAVE];
   const int lane = threadIdx.x % PDIPC_WAVE, g = threadIdx.x / PDIPC_WAVE;
   const int64_t j = static_cast<int64_t>(blockIdx.x) * PDIPC_WAVE + lane;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (j < n2) {
+  if (j < n_out) {
     for (int32_t i = g; i < nc; i += SC_WAVES) {
-      const double c = S[static_cast<int64_t>(c_x2[i]) * n2 + j];
+      const double c = S[static_cast<int64_t>(c_x2[i]) * ld + j];
       s0 += c * v[3 * i];
       s1 += c * v[3 * i + 1];
       s2 += c * v[3 * i + 2];
@@ -315,7 +316,7 @@ __global__ void __launch_bounds__(SC_WAVES * PDIPC_WAVE) sigma_cols_kernel(int32
   part[g][1][lane] = s1;
   part[g][2][lane] = s2;
   __syncthreads();
-  if (g < 3 && j < n2) {
+  if (g < 3 && j < n_out) {
     double acc = 0.0;
     for (int w = 0; w < SC_WAVES; ++w) acc += part[w][g][lane];
     z[3 * j + g] -= acc;
@@ -325,8 +326,52 @@ __global__ void __launch_bounds__(SC_WAVES * PDIPC_WAVE) sigma_cols_kernel(int32
 void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* z,
                               hipStream_t st) {
   if (nc > 0 && f.n2 > 0)
-    sigma_cols_kernel<<<grid_for(f.n2, PDIPC_WAVE), SC_WAVES * PDIPC_WAVE, 0, st>>>(f.n2, nc, c_x2, f.sigma_inv, v,
-                                                                                    z);
+    rows_update_kernel<<<grid_for(f.n2, PDIPC_WAVE), SC_WAVES * PDIPC_WAVE, 0, st>>>(f.n2, f.n2, nc, c_x2,
+                                                                                     f.sigma_inv, v, z);
+}
+
+void launch_hinv_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* sol,
+                             hipStream_t st) {
+  const int64_t N = static_cast<int64_t>(f.n1) + f.n2;
+  if (nc > 0 && f.n2 > 0)
+    rows_update_kernel<<<grid_for(N, PDIPC_WAVE), SC_WAVES * PDIPC_WAVE, 0, st>>>(N, N, nc, c_x2, f.hinv_x2, v,
+                                                                                  sol);
+}
+
+// sol's x2 rows = columns q0, q0 + 1, q0 + 2 of Sigma^-1 (one per right-hand side)
+__global__ void hinv_fill_x2_kernel(int32_t n1, int32_t n2, int32_t q0, const double* __restrict__ Si,
+                                    double* __restrict__ sol) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= 3LL * n2) return;
+  const int64_t j = idx / 3;
+  const int r = static_cast<int>(idx % 3);
+  const int32_t q = q0 + r;
+  sol[3 * (n1 + j) + r] = q < n2 ? Si[static_cast<int64_t>(q) * n2 + j] : 0.0;
+}
+
+// K[q][p] for the three columns of the batch: x1 part from the sweep, x2 part
+// from Sigma^-1 (row q, by symmetry)
+__global__ void hinv_store_rows_kernel(int32_t n1, int32_t n2, int32_t q0, const double* __restrict__ sol,
+                                       const double* __restrict__ Si, double* __restrict__ K) {
+  const int64_t N = static_cast<int64_t>(n1) + n2;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= 3 * N) return;
+  const int r = static_cast<int>(idx / N);
+  const int64_t p = idx % N;
+  const int32_t q = q0 + r;
+  if (q >= n2) return;
+  K[static_cast<int64_t>(q) * N + p] = p < n1 ? sol[3 * p + r] : Si[static_cast<int64_t>(q) * n2 + (p - n1)];
+}
+
+void launch_build_hinv_rows(const FactorDev& f, double* y, double* sol, double* K, hipStream_t st) {
+  const int64_t N = static_cast<int64_t>(f.n1) + f.n2;
+  if (f.n2 <= 0) return;
+  launch_fill_f64(y, 3 * N, 0.0, st);
+  for (int32_t q0 = 0; q0 < f.n2; q0 += 3) {
+    hinv_fill_x2_kernel<<<grid_for(3LL * f.n2, 256), 256, 0, st>>>(f.n1, f.n2, q0, f.sigma_inv, sol);
+    launch_backward_sweep(f, y, sol, st);
+    hinv_store_rows_kernel<<<grid_for(3 * N, 256), 256, 0, st>>>(f.n1, f.n2, q0, sol, f.sigma_inv, K);
+  }
 }
 
 }  // namespace pdipc

@@ -202,6 +202,7 @@ struct FactorDev {
   const int32_t* fwd_col;
   const double* fwd_val;
   const double* sigma_inv;         // n2 x n2 row-major
+  const double* hinv_x2;           // n2 x (n1 + n2) row-major: rows x2 of H_s^-1 (extended order), or null
   const int32_t* ext2vert;         // n1 + n2: sim vertex of each extended index
 };
 // b (ext, 3) = -g at ext2vert
@@ -233,6 +234,15 @@ void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, i
 // z -= Sigma^-1[:, c] v   (n2 x 3)
 void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* z,
                               hipStream_t st);
+// sol -= H_s^-1[:, c] v over all n1 + n2 extended rows (3 RHS), from the
+// stored rows x2 of H_s^-1 (f.hinv_x2)
+void launch_hinv_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* sol,
+                             hipStream_t st);
+// Rows x2 of H_s^-1 into K (n2 x (n1 + n2)): column q of Sigma^-1 is the x2
+// part of H_s^-1 e_q, and the backward sweep with y1 = 0 gives its x1 part,
+// -H11^-1 H12 Sigma^-1 e_q; three columns per sweep.  y and sol are the
+// sweep's work vectors (3 (n1 + n2) and 6 (n1 + n2)); y is left zero.
+void launch_build_hinv_rows(const FactorDev& f, double* y, double* sol, double* K, hipStream_t st);
 // c index -> x2 index
 void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
 

@@ -110,7 +110,7 @@ struct Solver {
   // factor
   DBuf<int32_t> node_c0, node_s, node_r, level_nodes, frows, fcol, ext2vert, vert2x2, lvl_rows, lvl_row_node;
   DBuf<int64_t> node_roff, node_poff, node_doff, fptr;
-  DBuf<double> panelT, dinv, dinvT, fval, sigma_inv;
+  DBuf<double> panelT, dinv, dinvT, fval, sigma_inv, hinv_x2;
   std::vector<int32_t> h_level_ptr, h_level_maxs, h_level_maxr, h_lvl_row_ptr;
   FactorDev fd{};
   DBuf<double> bvec, yvec, solvec;
@@ -244,7 +244,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   const int32_t n = md->n_verts, m = md->n_tets;
   if (n <= 0 || m <= 0 || !md->rest_pos || !md->tets || !md->dirichlet) fail(PDIPC_E_INVALID, "empty mesh");
   if (!(op->dhat > 0) || !(op->kappa > 0) || op->iters <= 0 || op->ccd_steps <= 0 || op->ls_max_halvings < 0 ||
-      op->cinv_updates_max < 0 || op->fp32_reduced_min < 0 ||
+      op->cinv_updates_max < 0 || op->fp32_reduced_min < 0 || op->hinv_rows_mb < 0 ||
       !(op->ccd_eta > 0 && op->ccd_eta < 1))
     fail(PDIPC_E_INVALID, "bad options");
   if (op->precision != PDIPC_FP64 && op->precision != PDIPC_MIXED_FP32) fail(PDIPC_E_INVALID, "bad precision");
@@ -552,6 +552,15 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   f.rows = S->frows.p; f.panelT = S->panelT.p; f.dinv = S->dinv.p; f.dinvT = S->dinvT.p;
   f.fwd_ptr = S->fptr.p; f.fwd_col = S->fcol.p; f.fwd_val = S->fval.p;
   f.sigma_inv = S->sigma_inv.p; f.ext2vert = S->ext2vert.p;
+  f.hinv_x2 = nullptr;
+  // rows x2 of H_s^-1 (contact correction as one product), within the budget
+  if (n2 > 0 && static_cast<int64_t>(n2) * N * 8 <= static_cast<int64_t>(op->hinv_rows_mb) << 20) {
+    S->hinv_x2.ensure(static_cast<int64_t>(n2) * N);
+    launch_build_hinv_rows(f, S->yvec.p, S->solvec.p, S->hinv_x2.p, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    f.hinv_x2 = S->hinv_x2.p;
+  }
 
   // ---- contact buffers ---------------------------------------------------------------------------------
   S->px = ProxyDev{S->nsv, S->nst, S->nse, S->sv.p, S->stri.p, S->sedge.p};
@@ -690,6 +699,11 @@ static void finish_readback(Solver* S, IterOut& io) {
   io.c_added = io.nc_with_same ? h4[3] : h4[0];
   io.nc_pending = false;
 }
+
+// Largest product (bytes of H_s^-1 rows read) for the contact correction by
+// the stored rows; beyond it the backward sweep after the x2 correction is
+// cheaper.
+static constexpr int64_t kHinvColsBytes = 512LL << 20;
 
 // Levels of the lower sweep queued before the host waits for n_c.
 static constexpr int kFwdLevelsBeforeFork = 3;
@@ -865,6 +879,12 @@ static void global_step(Solver* S, IterOut& io) {
   const int64_t N3 = 3LL * nc;
   // FP32 factor of the reduced system with FP64 refinement, or the FP64 factor
   const bool mixed = mixed_prec && N3 >= S->opt.fp32_reduced_min;
+  // Contact correction from the stored rows of H_s^-1: the backward sweep then
+  // runs on the uncorrected step, before the join, and the correction of all
+  // rows is one product after it (taken while that product reads less than
+  // kHinvColsBytes; else x2 is corrected first and the sweep follows).
+  const int64_t Next = static_cast<int64_t>(f.n1) + f.n2;
+  const bool hinv_path = f.hinv_x2 && nc > 0 && static_cast<int64_t>(nc) * Next * 8 <= kHinvColsBytes;
   if (nc > 0) {
     S->c_x2.ensure(nc);
     S->Cs.ensure(static_cast<int64_t>(nc) * nc);
@@ -966,6 +986,10 @@ static void global_step(Solver* S, IterOut& io) {
     }
     HIPCHK(hipEventRecord(S->ev_join, sd));
     rest_of_forward();
+    if (hinv_path) {
+      ScopedTimer tm(S, TK_BWD);
+      launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
+    }
     HIPCHK(hipStreamWaitEvent(st, S->ev_cinv, 0));
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
     HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
@@ -984,11 +1008,12 @@ static void global_step(Solver* S, IterOut& io) {
     }
     if (!mixed || fallback) dense_chol_solve_into<double>(S->ML.p, S->MLi.p, N3, S->rhs.p, S->u.p, st);
     launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
-    launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
+    if (hinv_path) launch_hinv_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p, st);
+    else launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
   } else {
     rest_of_forward();
   }
-  {
+  if (!hinv_path) {
     ScopedTimer tm(S, TK_BWD);
     launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
   }
@@ -1259,6 +1284,7 @@ void pdipc_default_options(pdipc_options* o) {
   o->ls_max_halvings = 20;
   o->cinv_updates_max = 16;
   o->fp32_reduced_min = 2049;
+  o->hinv_rows_mb = 4096;
   o->stream = nullptr;
 }
 
@@ -1350,7 +1376,7 @@ void pdipc_destroy(void* h) {
   for (auto* b : bi) b->release();
   DBuf<double>* bd[] = {&S->Bm, &S->w, &S->A, &S->a_s, &S->R0, &S->X, &S->x, &S->g, &S->dx, &S->tetg, &S->E0,
                         &S->dE, &S->Rtet, &S->tpair, &S->bE0, &S->bdE, &S->scal, &S->panelT, &S->dinv, &S->dinvT,
-                        &S->fval, &S->sigma_inv, &S->bvec, &S->yvec, &S->solvec, &S->vbox, &S->tbox, &S->ebox,
+                        &S->fval, &S->sigma_inv, &S->hinv_x2, &S->bvec, &S->yvec, &S->solvec, &S->vbox, &S->tbox, &S->ebox,
                         &S->params, &S->b_energy, &S->b_grad, &S->b_U, &S->Cs, &S->Cinv, &S->work, &S->Mred,
                         &S->rhs, &S->u, &S->vvec, &S->wtmp, &S->resid};
   for (auto* b : bd) b->release();

@@ -45,7 +45,11 @@ def estimate_bytes(scene) -> int:
     n2 = int(np.sum((scene.region == 1) & (scene.dirichlet == 0)))
     per_tet = 8 * (9 + 1 + 6 + 12 + 9 + 4) + 4 * 8
     factor = 16 * 40 * n          # supernodal panels, forward copy and inverses
-    return int(m * per_tet + n * 200 + 8 * n2 * n2 + factor + (64 << 20))
+    n_free = int(np.sum(scene.dirichlet == 0))
+    hinv = 8 * n2 * n_free        # rows x2 of H_s^-1, kept within the solver's default 4096 MiB
+    if hinv > (4096 << 20):
+        hinv = 0
+    return int(m * per_tet + n * 200 + 8 * n2 * n2 + hinv + factor + (64 << 20))
 
 
 class Server:

@@ -244,6 +244,32 @@ def test_incremental_cinv_matches_rebuild(name):
     assert np.array_equal(a1, a2)
 
 
+@pytest.mark.parametrize("name", ["slabs", "face5k"])
+def test_contact_correction_by_hinv_rows(name):
+    """The contact correction as one product with the stored rows x2 of
+    H_s^-1 (backward sweep on the uncorrected step) against correcting x2 with
+    Sigma^-1 and sweeping afterwards, over the whole frame sequence (FP64)."""
+    sc = mg.scene_by_name(name)
+    Ss = _solver(sc, iters=sc.iters, hinv_rows_mb=0)
+    Sh = _solver(sc, iters=sc.iters)
+    assert Sh.device_bytes() > Ss.device_bytes()          # the rows were built
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    xs = xh = _t(sc.X)
+    R = _t(sc.act_R.reshape(-1, 9))
+    worst, ncmax = 0.0, 0
+    for t in range(sc.frames):
+        a = _t(sc.actuation_at((t + 1) / sc.frames))
+        Ss.set_actuation_scalar(a, R)
+        Sh.set_actuation_scalar(a, R)
+        xs = Ss.solve_frame(xs)
+        xh, st = Sh.solve_frame(xh, stats=True)
+        ncmax = max(ncmax, st["n_c"])
+        worst = max(worst, np.abs(xh.cpu().numpy() - xs.cpu().numpy()).max() / diag)
+    print(f"H^-1 rows vs sweep {name}: n_c max {ncmax}, worst {worst:.3e}")
+    assert ncmax > 0
+    assert worst < 1e-9, worst
+
+
 def test_frame_is_bitwise_repeatable():
     """No floating-point atomics on the path: two runs give identical bits."""
     sc = mg.slabs(0)
