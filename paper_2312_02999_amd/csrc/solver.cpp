@@ -721,18 +721,14 @@ static void cinv_begin_pass(Solver* S) {
   S->cinv_incr_ok = false;
 }
 
-// Local step + constraint set + barrier + gradient; returns pair counts, n_c.
-// With defer, n_c is left in flight (the fork event marks its copy) and
-// global_step collects it after queueing the sweeps, which need only g.
+// Constraint set + barrier + local step + gradient; returns pair counts, n_c.
+// The contact terms go first: the fork event follows them, so the reduced
+// system (second stream) builds while the local step runs.  With defer, n_c
+// is left in flight (the fork event marks its copy) and global_step collects
+// it after queueing the first sweep levels, which need only g.
 static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool defer = false) {
   const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
   hipStream_t st = S->st;
-  {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    timer_events(S, TK_LOCAL, &e0, &e1);
-    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st, e0, e1);
-  }
-  launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
   if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee);
   else pairs(S, true, S->x.p, nullptr, &io.npt, &io.nee);
   const int32_t np = io.npt + io.nee;
@@ -749,7 +745,6 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
     launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->opt.kappa, fp32, S->bo, st);
   }
   build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
-  launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
   if (S->cinv_valid) {
     // the vertices that left / entered c are listed for the incremental update
     int32_t* ids = nullptr;
@@ -765,6 +760,13 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
                         st));
   HIPCHK(hipEventRecord(S->ev_fork, st));
   io.nc_pending = true;
+  {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_events(S, TK_LOCAL, &e0, &e1);
+    launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st, e0, e1);
+  }
+  launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
+  launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
   if (!defer) finish_readback(S, io);
 }
 
