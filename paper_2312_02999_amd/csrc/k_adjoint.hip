@@ -102,11 +102,15 @@ __global__ void __launch_bounds__(AT) pd_hessvec_kernel(LocalArgs la, const doub
     g[3][c] = Bm(2, c);
     g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
   }
+  double sh[12];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int r = 0; r < 3; ++r)
-      tetg[(3 * a + r) * m + i] = w * (res[3 * r] * g[a][0] + res[3 * r + 1] * g[a][1] + res[3 * r + 2] * g[a][2]);
+      sh[3 * a + r] = w * (res[3 * r] * g[a][0] + res[3 * r + 1] * g[a][1] + res[3 * r + 2] * g[a][2]);
+  double2* out = reinterpret_cast<double2*>(tetg + 12 * i);      // m x 12 records, as the local step
+#pragma unroll
+  for (int q = 0; q < 6; ++q) out[q] = make_double2(sh[2 * q], sh[2 * q + 1]);
 }
 
 // Per pair: true barrier Hessian times the pair's local 12-vector of v.

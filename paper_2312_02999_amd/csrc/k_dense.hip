@@ -625,27 +625,45 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
 // better above that.  Factor, solves and inverse must agree on it.
 static int dense_block(int64_t n) { return n <= 2048 ? 32 : 64; }
 
+// Launches [p0, p1) of the factorisation: launch 0 is the first diagonal
+// block, launch 1 + k the block step k, and (NB = 32) the last launch forms
+// the last block row of L^-1.
 template <typename T, int NB>
-static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
+static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st, int64_t p0,
+                              int64_t p1) {
   T* Lt = aux;
   T* dinv = aux + n * n;
   T* Dinv = aux + n * n + n;
   const int64_t nblk = (n + NB - 1) / NB;
-  chol_first_kernel<T, NB><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, Dinv, d_info);
+  if (p0 <= 0 && p1 > 0) chol_first_kernel<T, NB><<<1, 256, 0, st>>>(A, n, L, Lt, dinv, Dinv, d_info);
   const size_t shm = sizeof(T) * 3 * NB * (NB + 1);
   for (int64_t k = 0; k + 1 < nblk; ++k) {
+    if (1 + k < p0 || 1 + k >= p1) continue;
     const int64_t m = nblk - k - 1;
     const int64_t tiles = m * (m + 1) / 2 + (NB == 32 ? m * (k + 1) : 0);
     chol_update_kernel<T, NB><<<static_cast<unsigned>(tiles), 256, shm, st>>>(A, n, k, L, Lt, dinv, Dinv, d_info);
   }
-  if (NB == 32) chol_lastrow_kernel<T><<<static_cast<unsigned>(nblk), 256, 0, st>>>(A, n, L, Lt, Dinv);
+  if (NB == 32 && nblk >= p0 && nblk < p1)
+    chol_lastrow_kernel<T><<<static_cast<unsigned>(nblk), 256, 0, st>>>(A, n, L, Lt, Dinv);
+}
+
+int64_t dense_cholesky_launches(int64_t n) {
+  if (n <= 0) return 0;
+  const int nb = dense_block(n);
+  const int64_t nblk = (n + nb - 1) / nb;
+  return nb == 32 ? nblk + 1 : nblk;
+}
+
+template <typename T>
+void dense_cholesky_range(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st, int64_t p0, int64_t p1) {
+  if (n <= 0) return;
+  if (dense_block(n) == 32) dense_cholesky_nb<T, 32>(A, n, L, aux, d_info, st, p0, p1);
+  else dense_cholesky_nb<T, 64>(A, n, L, aux, d_info, st, p0, p1);
 }
 
 template <typename T>
 void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
-  if (n <= 0) return;
-  if (dense_block(n) == 32) dense_cholesky_nb<T, 32>(A, n, L, aux, d_info, st);
-  else dense_cholesky_nb<T, 64>(A, n, L, aux, d_info, st);
+  dense_cholesky_range<T>(A, n, L, aux, d_info, st, 0, dense_cholesky_launches(n));
 }
 
 // ---- solves: one workgroup; diagonal blocks by their inverses, the rest coalesced
@@ -1301,6 +1319,9 @@ void launch_scaled_accumulate(const float* y, int64_t n, const double* sc, doubl
 
 template void dense_cholesky<double>(double*, int64_t, double*, double*, int32_t*, hipStream_t);
 template void dense_cholesky<float>(float*, int64_t, float*, float*, int32_t*, hipStream_t);
+template void dense_cholesky_range<double>(double*, int64_t, double*, double*, int32_t*, hipStream_t, int64_t,
+                                           int64_t);
+template void dense_cholesky_range<float>(float*, int64_t, float*, float*, int32_t*, hipStream_t, int64_t, int64_t);
 template void dense_chol_solve<double>(const double*, double*, int64_t, double*, int32_t, hipStream_t);
 template void dense_chol_solve<float>(const float*, float*, int64_t, float*, int32_t, hipStream_t);
 template void dense_chol_solve_into<double>(const double*, double*, int64_t, const double*, double*, hipStream_t);

@@ -134,31 +134,46 @@ void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStr
   if (to_end && f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f, b, y);
 }
 
-// z = Sigma^-1 r, r and z are n2 x 3 (x2 part of the extended vectors)
+// z = Sigma^-1 r, r and z are n2 x 3 (x2 part of the extended vectors).  One
+// wave per two rows: two independent row streams per lane keep more loads in
+// flight, and each r entry serves both rows.  Per row, the lane-strided
+// partial sums and the wave sum are as for one row per wave.
 __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double* __restrict__ S,
                                                         const double* __restrict__ r, double* __restrict__ z) {
   const int lane = threadIdx.x % PDIPC_WAVE;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
-  if (i >= n2) return;
-  const double* Si = S + i * n2;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const int64_t i0 = 2 * (static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE);
+  if (i0 >= n2) return;
+  const bool two = i0 + 1 < n2;
+  const double* S0 = S + i0 * n2;
+  const double* S1 = two ? S0 + n2 : S0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
 #pragma unroll 4
   for (int64_t j = lane; j < n2; j += PDIPC_WAVE) {
-    double v = Si[j];
-    a0 += v * r[3 * j];
-    a1 += v * r[3 * j + 1];
-    a2 += v * r[3 * j + 2];
+    const double v0 = S0[j], v1 = S1[j];
+    const double r0 = r[3 * j], r1 = r[3 * j + 1], r2 = r[3 * j + 2];
+    a0 += v0 * r0;
+    a1 += v0 * r1;
+    a2 += v0 * r2;
+    b0 += v1 * r0;
+    b1 += v1 * r1;
+    b2 += v1 * r2;
   }
   wave_sum3(a0, a1, a2);
+  wave_sum3(b0, b1, b2);
   if (lane == 0) {
-    z[3 * i] = a0;
-    z[3 * i + 1] = a1;
-    z[3 * i + 2] = a2;
+    z[3 * i0] = a0;
+    z[3 * i0 + 1] = a1;
+    z[3 * i0 + 2] = a2;
+    if (two) {
+      z[3 * i0 + 3] = b0;
+      z[3 * i0 + 4] = b1;
+      z[3 * i0 + 5] = b2;
+    }
   }
 }
 
 void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream_t st) {
-  if (f.n2 > 0) sigma_gemv_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
+  if (f.n2 > 0) sigma_gemv_kernel<<<grid_for((f.n2 + 1) / 2, WPB), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
 }
 
 // s_c = y_c - sum_i panelT_J[c][i] sol[R_J[i]]

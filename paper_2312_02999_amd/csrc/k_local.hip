@@ -256,8 +256,9 @@ __device__ __forceinline__ void load_tet(const TetStreams& ts, int64_t m, int64_
   w = ts.w[i];
 }
 
-// Writes per tet: R (9 x m, optional), energy (m), gradient share (12 x m,
-// entry 3a + r for local vertex a, coordinate r).
+// Writes per tet: R (9 x m, optional), energy (m), gradient share (m x 12,
+// one 96-byte record per tet, entry 3a + r for local vertex a, coordinate r,
+// so that the per-vertex gather reads one cache line per incident corner).
 // Rotation of tet i at deformation M: warm-started FP64 Newton from Rwarm
 // (if given), else (or if that fails) Jacobi in TP, refined in FP64 when TP
 // is FP32.
@@ -283,29 +284,30 @@ template <typename TP>
 __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t m, const double* __restrict__ x,
                                                          const double* Rwarm, double* Rout,
                                                          double* __restrict__ energy, double* __restrict__ tetg) {
-  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  M3<double> F, A, Bm;
-  double w;
-  int32_t v[4];
-  load_tet(ts, m, i, x, F, A, w, v, Bm);
-  M3<double> M = mul(F, A);
-  M3<double> R;
-  tet_rotation<TP>(M, Rwarm, m, i, R);
-  M3<double> P = mul(R, A);
-  double res[9];
-  double e2 = 0.0;
+  const int64_t blk = xcd_block();
+  const int64_t i = blk * blockDim.x + threadIdx.x;
+  double sh[12];
+  if (i < m) {
+    M3<double> F, A, Bm;
+    double w;
+    int32_t v[4];
+    load_tet(ts, m, i, x, F, A, w, v, Bm);
+    M3<double> M = mul(F, A);
+    M3<double> R;
+    tet_rotation<TP>(M, Rwarm, m, i, R);
+    M3<double> P = mul(R, A);
+    double res[9];
+    double e2 = 0.0;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    res[e] = F.a[e] - P.a[e];
-    e2 += res[e] * res[e];
-  }
-  energy[i] = 0.5 * w * e2;
-  if (Rout) {
+    for (int e = 0; e < 9; ++e) {
+      res[e] = F.a[e] - P.a[e];
+      e2 += res[e] * res[e];
+    }
+    energy[i] = 0.5 * w * e2;
+    if (Rout) {
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Rout[e * m + i] = R.a[e];
-  }
-  if (tetg) {
+      for (int e = 0; e < 9; ++e) Rout[e * m + i] = R.a[e];
+    }
     // g_a = row (a-1) of B for a >= 1, g_0 = -(sum of rows); share_a = w * res * g_a
     double g[4][3];
 #pragma unroll
@@ -319,7 +321,26 @@ __global__ void __launch_bounds__(256) local_step_kernel(TetStreams ts, int64_t 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        tetg[(3 * a + r) * m + i] = w * (res[3 * r] * g[a][0] + res[3 * r + 1] * g[a][1] + res[3 * r + 2] * g[a][2]);
+        sh[3 * a + r] = w * (res[3 * r] * g[a][0] + res[3 * r + 1] * g[a][1] + res[3 * r + 2] * g[a][2]);
+  }
+  if (tetg) {
+    // the block's 256 records are contiguous: stage them in LDS (row pitch 13
+    // against bank conflicts) and store them with consecutive lanes on
+    // consecutive words
+    __shared__ double stage[256 * 13];
+    if (i < m) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) stage[threadIdx.x * 13 + q] = sh[q];
+    }
+    __syncthreads();
+    const int64_t base = blk * blockDim.x;
+    const int64_t nval = 12 * (m - base < 256 ? m - base : 256);
+    double* out = tetg + 12 * base;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const int e = k * 256 + threadIdx.x;
+      if (e < nval) out[e] = stage[(e / 12) * 13 + e % 12];
+    }
   }
 }
 
@@ -388,11 +409,10 @@ __global__ void __launch_bounds__(256) gather_vertex_grad_kernel(int32_t n, int6
 #pragma unroll 4
     for (int32_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
       int32_t ent = vt_ent[e];
-      int64_t t = ent >> 2;
-      int a = ent & 3;
-      s0 += tetg[(3 * a + 0) * m + t];
-      s1 += tetg[(3 * a + 1) * m + t];
-      s2 += tetg[(3 * a + 2) * m + t];
+      const double* sh = tetg + 12 * static_cast<int64_t>(ent >> 2) + 3 * (ent & 3);
+      s0 += sh[0];
+      s1 += sh[1];
+      s2 += sh[2];
     }
   }
   g[3 * v] = s0;

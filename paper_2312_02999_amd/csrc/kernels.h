@@ -14,7 +14,8 @@ struct LocalArgs {
   const double* w;      // m
   const double* A;      // 6 x m
 };
-// Rwarm (optional, may alias Rout): rotations at a nearby state to start from
+// Rwarm (optional, may alias Rout): rotations at a nearby state to start from;
+// tetg: per-tet gradient shares, m x 12 (entry 3a + r: local vertex a, coordinate r)
 // ev_start / ev_stop (optional): events stamped at the kernel's start and end
 void launch_local_step(const LocalArgs& la, const double* x, const double* Rwarm, double* Rout, double* energy,
                        double* tetg, bool fp32, hipStream_t st, hipEvent_t ev_start = nullptr,
@@ -260,6 +261,12 @@ inline int64_t dense_tmp_offset(int64_t n) { return n * n + n + dense_blocks_siz
 inline int64_t dense_aux_size(int64_t n) { return dense_tmp_offset(n) + 4 * n + 64; }
 template <typename T>
 void dense_cholesky(T* A, int64_t n, T* F, T* aux, int32_t* d_info, hipStream_t st);
+// The same factorisation queued in parts: its launches are numbered
+// 0 .. dense_cholesky_launches(n) - 1 and dense_cholesky_range queues
+// [p0, p1) of them, so that a caller can interleave other streams' launches.
+int64_t dense_cholesky_launches(int64_t n);
+template <typename T>
+void dense_cholesky_range(T* A, int64_t n, T* F, T* aux, int32_t* d_info, hipStream_t st, int64_t p0, int64_t p1);
 // Solve L L^T x = b in place (b: n x nrhs row-major, nrhs <= 4).
 template <typename T>
 void dense_chol_solve(const T* F, T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st);

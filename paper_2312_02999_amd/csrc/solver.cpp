@@ -705,6 +705,10 @@ static void finish_readback(Solver* S, IterOut& io) {
 // cheaper.
 static constexpr int64_t kHinvColsBytes = 512LL << 20;
 
+// Launches of the reduced factorisation queued before the rest of the main
+// stream's forward sweep.
+static constexpr int64_t kFactorLaunchesFirst = 10;
+
 // Levels of the lower sweep queued before the host waits for n_c.
 static constexpr int kFwdLevelsBeforeFork = 3;
 
@@ -976,18 +980,25 @@ static void global_step(Solver* S, IterOut& io) {
     S->cinv_incr_ok = true;
     HIPCHK(hipEventRecord(S->ev_cinv, sd));          // C^-1 and c_x2 ready
     launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, sd);
+    // The factorisation is queued in two parts with the rest of the main
+    // stream's sweep between them, so that neither stream waits for the host.
+    const int64_t nlaunch = dense_cholesky_launches(N3);
+    const int64_t first_part = std::min<int64_t>(nlaunch, kFactorLaunchesFirst);
     if (mixed) {
       // Jacobi-scaled FP32 copy and its factor (refined against FP64 below)
       launch_jacobi_scaling(S->Mred.p, N3, S->scl.p, sd);
       launch_scale_convert_matrix(S->Mred.p, N3, S->scl.p, S->Mf.p, sd);
-      dense_cholesky<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, sd);
+      dense_cholesky_range<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, sd, 0, first_part);
+      rest_of_forward();
+      dense_cholesky_range<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, sd, first_part, nlaunch);
     } else {
       ScopedTimer tm(S, TK_REDUCED_CHOL, sd);
-      dense_cholesky<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, sd);
+      dense_cholesky_range<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, sd, 0, first_part);
+      rest_of_forward();
+      dense_cholesky_range<double>(S->Mred.p, N3, S->ML.p, S->MLi.p, S->info.p, sd, first_part, nlaunch);
       S->check_info_m = true;           // read back with the line-search state
     }
     HIPCHK(hipEventRecord(S->ev_join, sd));
-    rest_of_forward();
     if (hinv_path) {
       ScopedTimer tm(S, TK_BWD);
       launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
