@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy
 # of known size; valid only for the kernel source they were taken on
 # (profiles/local_step_kernel_face50k_pmc.md).
-LOCAL_STEP_TRAFFIC = {"workload": "face50k", "source_sha256_prefix": "e0e0ef2c8732ebba", "bytes": 103253281}
+LOCAL_STEP_TRAFFIC = {"workload": "face50k", "source_sha256_prefix": "54fa61f8b0518b46", "bytes": 103978783}
 
 
 def measured_traffic(workload: str):
