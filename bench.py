@@ -100,12 +100,13 @@ def run_precision(sc, precision, steps, warmup, timer_kernel):
         stats.append(st)
         t += 1
     sizes = S.sizes()
+    dev_bytes = S.device_bytes()
     S.close()
     lat_ms = np.array(lat) * 1e3
     return {
         "fps": steps / wall, "ms_per_frame": 1e3 * wall / steps,
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-        "kernel_ms_total": k_ms, "kernel_launches": k_count, "sizes": sizes,
+        "kernel_ms_total": k_ms, "kernel_launches": k_count, "sizes": sizes, "device_bytes": dev_bytes,
         "n_c_max": max(s["n_c"] for s in stats), "n_pt_last": stats[-1]["n_pt"], "n_ee_last": stats[-1]["n_ee"],
         "ls_failures": sum(s["ls_failures"] for s in stats),
         "refine_steps": sum(s["refine_steps"] for s in stats),
@@ -273,7 +274,7 @@ def main():
                  "p50_ms": round(fp64["p50_ms"], 3), "p99_ms": round(fp64["p99_ms"], 3),
                  "stage_ms": fp64["stage_ms"], "n_c_max": fp64["n_c_max"], "ls_failures": fp64["ls_failures"],
                  "cinv_rebuilds": fp64["cinv_rebuilds"], "c_delta_max": fp64["c_delta_max"],
-                 "c_delta_sum": fp64["c_delta_sum"]},
+                 "c_delta_sum": fp64["c_delta_sum"], "device_bytes": fp64["device_bytes"]},
         "mixed": {"stage_ms": mixed["stage_ms"], "n_c_max": mixed["n_c_max"], "ls_failures": mixed["ls_failures"],
                   "refine_steps": mixed["refine_steps"], "refine_fallbacks": mixed["refine_fallbacks"],
                   "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},

@@ -320,6 +320,7 @@ __global__ void __launch_bounds__(SC_WAVES * PDIPC_WAVE) rows_update_kernel(int6
   const int64_t j = static_cast<int64_t>(blockIdx.x) * PDIPC_WAVE + lane;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (j < n_out) {
+#pragma unroll 4
     for (int32_t i = g; i < nc; i += SC_WAVES) {
       const double c = S[static_cast<int64_t>(c_x2[i]) * ld + j];
       s0 += c * v[3 * i];
