@@ -135,20 +135,21 @@ void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStr
 }
 
 // z = Sigma^-1 r, r and z are n2 x 3 (x2 part of the extended vectors).  One
-// wave per two rows: two independent row streams per lane keep more loads in
-// flight, and each r entry serves both rows.  Per row, the lane-strided
-// partial sums and the wave sum are as for one row per wave.
+// workgroup per two rows, its four waves over interleaved quarters of the
+// columns: two row streams per lane and four waves per row pair keep enough
+// loads in flight to stream the matrix, and each r entry serves both rows.
+// The four wave partials are added in wave order (deterministic).
 __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double* __restrict__ S,
                                                         const double* __restrict__ r, double* __restrict__ z) {
-  const int lane = threadIdx.x % PDIPC_WAVE;
-  const int64_t i0 = 2 * (static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE);
-  if (i0 >= n2) return;
+  __shared__ double part[WPB][6];
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int64_t i0 = 2 * static_cast<int64_t>(blockIdx.x);
   const bool two = i0 + 1 < n2;
   const double* S0 = S + i0 * n2;
   const double* S1 = two ? S0 + n2 : S0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
 #pragma unroll 4
-  for (int64_t j = lane; j < n2; j += PDIPC_WAVE) {
+  for (int64_t j = w * PDIPC_WAVE + lane; j < n2; j += FT) {
     const double v0 = S0[j], v1 = S1[j];
     const double r0 = r[3 * j], r1 = r[3 * j + 1], r2 = r[3 * j + 2];
     a0 += v0 * r0;
@@ -161,19 +162,19 @@ __global__ void __launch_bounds__(FT) sigma_gemv_kernel(int32_t n2, const double
   wave_sum3(a0, a1, a2);
   wave_sum3(b0, b1, b2);
   if (lane == 0) {
-    z[3 * i0] = a0;
-    z[3 * i0 + 1] = a1;
-    z[3 * i0 + 2] = a2;
-    if (two) {
-      z[3 * i0 + 3] = b0;
-      z[3 * i0 + 4] = b1;
-      z[3 * i0 + 5] = b2;
-    }
+    part[w][0] = a0; part[w][1] = a1; part[w][2] = a2;
+    part[w][3] = b0; part[w][4] = b1; part[w][5] = b2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6 && (threadIdx.x < 3 || two)) {
+    double acc = 0.0;
+    for (int q = 0; q < WPB; ++q) acc += part[q][threadIdx.x];
+    z[3 * i0 + threadIdx.x] = acc;
   }
 }
 
 void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream_t st) {
-  if (f.n2 > 0) sigma_gemv_kernel<<<grid_for((f.n2 + 1) / 2, WPB), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
+  if (f.n2 > 0) sigma_gemv_kernel<<<static_cast<unsigned>((f.n2 + 1) / 2), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
 }
 
 // s_c = y_c - sum_i panelT_J[c][i] sol[R_J[i]]
