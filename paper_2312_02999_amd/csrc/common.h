@@ -81,6 +81,12 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Number of set bits of a wave mask below the calling lane.
+__device__ __forceinline__ int32_t lanes_below(uint64_t m) {
+  return static_cast<int32_t>(
+      __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
+}
+
 // Minimum over a 256-thread block (wave butterflies, then the four waves).
 // Every thread calls it; all hold the result.
 __device__ __forceinline__ double block256_min(double v, double* sh4) {

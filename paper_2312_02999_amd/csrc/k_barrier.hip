@@ -310,12 +310,39 @@ __global__ void __launch_bounds__(256) inc_sort_kernel(int32_t nsv, const int32_
   }
 }
 
-// cflag[v] = 1 for a free vertex touched by at least one pair
-__global__ void cflag_kernel(int32_t n, const int32_t* __restrict__ ptr, const uint8_t* __restrict__ fixed,
-                             int32_t* __restrict__ cflag) {
-  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v > n) return;
-  cflag[v] = (v < n && ptr[v + 1] > ptr[v] && !fixed[v]) ? 1 : 0;
+// cflag[v] = 1 for a free vertex touched by at least one pair (from the
+// entry counts).  With prev, the change against prev as well: out[0] = 1 if
+// any flag differs, out[1] / out[2] = vertices that left / entered (wave
+// ballots, one integer atomic per wave), and the first cap of each kind listed
+// (in no particular order).
+__global__ void __launch_bounds__(256) cflag_kernel(int32_t n, const int32_t* __restrict__ cnt,
+                                                    const uint8_t* __restrict__ fixed, int32_t* __restrict__ cflag,
+                                                    const int32_t* __restrict__ prev, int32_t* __restrict__ out,
+                                                    int32_t* __restrict__ rem_ids, int32_t* __restrict__ add_ids,
+                                                    int32_t cap) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool c = v < n && cnt[v] > 0 && !fixed[v];
+  if (v <= n) cflag[v] = c ? 1 : 0;
+  if (!prev) return;
+  const bool p = v <= n && prev[v] != 0;
+  const uint64_t mr = __ballot(p && !c), ma = __ballot(c && !p);
+  if ((mr | ma) == 0) return;
+  int32_t br = 0, ba = 0;
+  if (threadIdx.x % PDIPC_WAVE == 0) {
+    out[0] = 1;
+    if (mr) br = atomicAdd(out + 1, static_cast<int32_t>(__popcll(mr)));
+    if (ma) ba = atomicAdd(out + 2, static_cast<int32_t>(__popcll(ma)));
+  }
+  if (!rem_ids) return;
+  br = __shfl(br, 0, PDIPC_WAVE);
+  ba = __shfl(ba, 0, PDIPC_WAVE);
+  if (p && !c) {
+    const int32_t slot = br + lanes_below(mr);
+    if (slot < cap) rem_ids[slot] = static_cast<int32_t>(v);
+  } else if (c && !p) {
+    const int32_t slot = ba + lanes_below(ma);
+    if (slot < cap) add_ids[slot] = static_cast<int32_t>(v);
+  }
 }
 
 __global__ void clist_kernel(int32_t n, const int32_t* __restrict__ cflag, const int32_t* __restrict__ cidx,
@@ -326,17 +353,21 @@ __global__ void clist_kernel(int32_t n, const int32_t* __restrict__ cflag, const
 }
 
 void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyDev& px, const uint8_t* fixed,
-                     Incidence& inc, void* scan_temp, hipStream_t st) {
-  launch_fill_i32(inc.cnt, n + 1, 0, st);
+                     Incidence& inc, void* scan_temp, hipStream_t st, const int32_t* prev_cflag, int32_t* rem_ids,
+                     int32_t* add_ids, int32_t cap) {
+  // counts and (with prev_cflag) the three change counters start at zero
+  launch_fill2_i32(inc.cnt, n + 1LL, inc.d_nc + 1, prev_cflag ? 3 : 0, 0, st);
   if (npairs > 0) inc_count_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cnt);
+  cflag_kernel<<<grid_for(n + 1LL, 256), 256, 0, st>>>(n, inc.cnt, fixed, inc.cflag, prev_cflag, inc.d_nc + 1,
+                                                        rem_ids, add_ids, cap);
   {
-    const ScanJob job{inc.cnt, inc.ptr, n + 1, inc.d_nc, inc.cursor, -1, nullptr};   // cursor: copy of ptr
-    launch_exclusive_scans(&job, 1, scan_temp, st);
+    // entry offsets (cursor: a copy of them) and c ranks in the same two launches
+    const ScanJob jobs[2] = {{inc.cnt, inc.ptr, n + 1LL, inc.d_nc + 4, inc.cursor, -1, nullptr},
+                             {inc.cflag, inc.cidx, n + 1LL, inc.d_nc, nullptr, -1, nullptr}};
+    launch_exclusive_scans(jobs, 2, scan_temp, st);
   }
   if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.raw);
   if (npairs > 0) inc_sort_kernel<<<grid_for(px.nsv, 4), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.raw, inc.ent);
-  cflag_kernel<<<grid_for(n + 1, 256), 256, 0, st>>>(n, inc.ptr, fixed, inc.cflag);
-  launch_exclusive_scan(inc.cflag, inc.cidx, n + 1, inc.d_nc, scan_temp, st);
   clist_kernel<<<grid_for(n, 256), 256, 0, st>>>(n, inc.cflag, inc.cidx, inc.clist);
 }
 

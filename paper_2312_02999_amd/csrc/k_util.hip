@@ -286,45 +286,6 @@ void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStrea
   if (n > 0) count_nonfinite_kernel<<<grid_for(n, 256), 256, 0, st>>>(x, n, d_out);
 }
 
-// Change of a flag set: out[0] = 1 if any entry differs, out[1] = entries set
-// before and cleared now, out[2] = entries set now and not before (wave
-// ballots, one integer atomic per wave).  With lists, the first cap indices of
-// each kind are also written (in no particular order).
-__device__ __forceinline__ int32_t lanes_below(uint64_t m) {
-  return static_cast<int32_t>(
-      __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
-}
-__global__ void __launch_bounds__(256) set_delta_kernel(const int32_t* __restrict__ cur,
-                                                        const int32_t* __restrict__ prev, int64_t n,
-                                                        int32_t* __restrict__ out, int32_t* __restrict__ rem_ids,
-                                                        int32_t* __restrict__ add_ids, int32_t cap) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const bool p = i < n && prev[i] != 0, c = i < n && cur[i] != 0;
-  const uint64_t mr = __ballot(p && !c), ma = __ballot(c && !p);
-  if ((mr | ma) == 0) return;
-  int32_t br = 0, ba = 0;
-  if (threadIdx.x % PDIPC_WAVE == 0) {
-    out[0] = 1;
-    if (mr) br = atomicAdd(out + 1, static_cast<int32_t>(__popcll(mr)));
-    if (ma) ba = atomicAdd(out + 2, static_cast<int32_t>(__popcll(ma)));
-  }
-  if (!rem_ids) return;
-  br = __shfl(br, 0, PDIPC_WAVE);
-  ba = __shfl(ba, 0, PDIPC_WAVE);
-  if (p && !c) {
-    const int32_t slot = br + lanes_below(mr);
-    if (slot < cap) rem_ids[slot] = static_cast<int32_t>(i);
-  } else if (c && !p) {
-    const int32_t slot = ba + lanes_below(ma);
-    if (slot < cap) add_ids[slot] = static_cast<int32_t>(i);
-  }
-}
-void launch_set_delta(const int32_t* cur, const int32_t* prev, int64_t n, int32_t* d_out3, hipStream_t st,
-                      int32_t* rem_ids, int32_t* add_ids, int32_t cap) {
-  launch_fill_i32(d_out3, 3, 0, st);
-  if (n > 0) set_delta_kernel<<<grid_for(n, 256), 256, 0, st>>>(cur, prev, n, d_out3, rem_ids, add_ids, cap);
-}
-
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   if (n > 0) fill_i32_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n, v);
 }

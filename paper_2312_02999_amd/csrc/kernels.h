@@ -76,12 +76,6 @@ void launch_axpy_positions(int64_t n3, double alpha, const double* dx, double* x
 void launch_max_abs(const double* in, int64_t n, double* d_out, void* temp, hipStream_t st);
 // number of non-finite entries -> *d_out
 void launch_count_nonfinite(const double* x, int64_t n, int32_t* d_out, hipStream_t st);
-// out[0] = any entry of cur and prev differs (as flags), out[1] = set in prev
-// only, out[2] = set in cur only; with lists, up to cap indices of each of the
-// two kinds go to rem_ids / add_ids (unordered)
-void launch_set_delta(const int32_t* cur, const int32_t* prev, int64_t n, int32_t* d_out3, hipStream_t st,
-                      int32_t* rem_ids = nullptr, int32_t* add_ids = nullptr, int32_t cap = 0);
-
 // ------------------------------------------------------------------- contact
 struct ProxyDev {
   int32_t nsv, nst, nse;
@@ -172,10 +166,15 @@ struct Incidence {
   int32_t* cflag;       // n + 1: 1 if free and touched
   int32_t* cidx;        // n + 1: exclusive scan of cflag (c index if flagged)
   int32_t* clist;       // n: c index -> sim vertex
-  int32_t* d_nc;        // device total
+  int32_t* d_nc;        // 5: n_c, then the change of c (any, left, entered), then the entry total
 };
+// Incidence lists, contact flags, ranks and list of c.  With prev_cflag (the
+// flags of an earlier c, n + 1 entries), d_nc[1..3] also receive the change
+// of c (any flag differs, vertices that left, vertices that entered) and, with
+// ids, up to cap of the leaving / entering vertices go to rem_ids / add_ids.
 void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyDev& px, const uint8_t* fixed,
-                     Incidence& inc, void* scan_temp, hipStream_t st);
+                     Incidence& inc, void* scan_temp, hipStream_t st, const int32_t* prev_cflag = nullptr,
+                     int32_t* rem_ids = nullptr, int32_t* add_ids = nullptr, int32_t cap = 0);
 void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
                              const uint8_t* fixed, double* g, hipStream_t st);
 
@@ -292,7 +291,7 @@ void dense_chol_inverse(const T* F, const T* aux, int64_t n, T* Ainv, T* work, h
 // the previous c, nold x nold) is downdated for the leaving vertices and
 // bordered with the entering ones (Schur complement against Sigma^-1), giving
 // out (nc x nc, order of the new c).  rem_ids / add_ids hold the r leaving and
-// a entering vertices in any order (launch_set_delta's lists); pflag/pidx are
+// a entering vertices in any order (build_incidence's lists); pflag/pidx are
 // the previous contact flags and ranks, cflag/cidx the current ones.  A
 // non-positive pivot of the two small SPD inverses sets *info (zeroed first).
 struct CinvLists {

@@ -593,7 +593,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   for (auto* b : {&S->inc_cnt, &S->inc_ptr, &S->inc_cflag, &S->inc_cidx}) b->ensure(n + 1);
   S->inc_cursor.ensure(n + 1);
   S->inc_clist.ensure(n);
-  S->inc_nc.ensure(4);
+  S->inc_nc.ensure(8);
   HIPCHK(hipStreamSynchronize(st));
   return PDIPC_OK;
 }
@@ -748,16 +748,17 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
     ScopedTimer tm(S, TK_BARRIER);
     launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->opt.kappa, fp32, S->bo, st);
   }
-  build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
-  if (S->cinv_valid) {
-    // the vertices that left / entered c are listed for the incremental update
+  {
+    // against the c of the current C^-1: the change of c, and the vertices
+    // that left / entered it listed for the incremental update
     int32_t* ids = nullptr;
-    if (S->opt.cinv_updates_max > 0) {
+    if (S->cinv_valid && S->opt.cinv_updates_max > 0) {
       S->cset_ids.ensure(2 * kCinvMaxDelta);
       ids = S->cset_ids.p;
     }
-    launch_set_delta(S->inc.cflag, S->prev_cflag.p, S->n + 1LL, S->inc.d_nc + 1, st, ids,
-                     ids ? ids + kCinvMaxDelta : nullptr, kCinvMaxDelta);
+    build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st,
+                    S->cinv_valid ? S->prev_cflag.p : nullptr, ids, ids ? ids + kCinvMaxDelta : nullptr,
+                    kCinvMaxDelta);
   }
   io.nc_with_same = S->cinv_valid;
   HIPCHK(hipMemcpyAsync(S->h_scal, S->inc.d_nc, sizeof(int32_t) * (io.nc_with_same ? 4 : 1), hipMemcpyDeviceToHost,
