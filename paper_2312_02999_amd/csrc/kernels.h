@@ -132,9 +132,11 @@ int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const do
                   int32_t* n_ee, hipStream_t st, int64_t* needed);
 
 // CCD: t_k per candidate pair (conservative advancement), then alpha_m.
-// per-candidate bounds t_out and per-block minima part; returns the blocks
+// per-candidate bounds t_out and per-block minima part; returns the blocks.
+// With e0, also each candidate's barrier energy at x (kappa b(d), 0 beyond dhat).
 int launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
-               int32_t steps, double* t_out, double* part, hipStream_t st);
+               int32_t steps, double* t_out, double* part, hipStream_t st, double dhat = 0.0, double kappa = 0.0,
+               double* e0 = nullptr);
 // kappa * b(d) per candidate at x + alpha dx (alpha = 0 allowed); pairs at
 // d >= dhat give 0.
 void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
@@ -216,7 +218,8 @@ void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStr
 void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream_t st);
 // backward sweep: sol[0, n1) from y and sol[n1, n1 + n2) (already set)
 void launch_backward_sweep(const FactorDev& f, const double* y, double* sol, hipStream_t st);
-// dx (n x 3) from sol (ext): zero elsewhere
+// dx (n x 3) from sol (ext) at the free vertices; the fixed vertices' entries
+// are not written (the caller keeps them zero)
 void launch_unpack(const FactorDev& f, int32_t n, const double* sol, double* dx, hipStream_t st);
 
 // ------------------------------------------------- reduced contact system

@@ -423,6 +423,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   S->stri.upload(tris.data(), 3LL * F, st);
   S->sedge.upload(sev.data(), static_cast<int64_t>(sev.size()), st);
   for (auto* b : {&S->x, &S->g, &S->dx}) b->ensure(3LL * n);
+  launch_fill_f64(S->dx.p, 3LL * n, 0.0, st);      // the fixed vertices' entries stay zero
   S->tetg.ensure(12LL * m);
   S->E0.ensure(m);
   S->dE.ensure(m);
@@ -1065,11 +1066,10 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   int nccd = 0;
   {
     ScopedTimer tm(S, TK_CCD);
+    // with the candidates' barrier energies at x, the line search's reference
     nccd = launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p,
-                      S->ccd_part.p, st);
+                      S->ccd_part.p, st, S->opt.dhat, S->opt.kappa, S->bE0.p);
   }
-  launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, nullptr, nullptr, S->opt.dhat, S->opt.kappa, nullptr,
-                             S->bE0.p, st);
   // back-tracking line search on the device: trials read alpha from the state
   // and become no-ops once it is decided; two are queued, then one readback
   double* ls = S->lsbuf.p;
