@@ -28,13 +28,14 @@ void launch_pack_rhs(const FactorDev& f, const double* g, double* b, hipStream_t
   if (N > 0) pack_rhs_kernel<<<grid_for(N, 256), 256, 0, st>>>(N, f.ext2vert, g, b);
 }
 
-// Level-scheduled sweeps.  Every level runs two launches per direction, one
-// wavefront per row (lower sweep) or column (upper sweep) of that level's
-// supernodes, lanes over the reduction dimension (coalesced):
-//   lower  t_rho = b_rho - sum_e L[rho, e] y_e     (CSR row of the factor)
-//          y_J   = Dinv_J t_J                      (row-major Dinv)
-//   upper  s_c   = y_c - sum_i L[R_i, c] x_{R_i}   (transposed panel)
-//          x_J   = Dinv_J^T s_J                    (row-major Dinv^T)
+// Level-scheduled sweeps with W_J = L[R(J), cols(J)] Dinv_J in place of the
+// panels, so that a level is one launch: one wavefront per row (lower sweep)
+// or column (upper sweep) of that level's supernodes, lanes over the
+// reduction dimension (coalesced):
+//   lower  t_rho = b_rho - sum_e W[rho, e] t_e     (CSR rows of W), per level
+//          y_J   = Dinv_J t_J                      (all blocks, one launch)
+//   upper  z_J   = Dinv_J^T y_J                    (all blocks, one launch)
+//          x_c   = z_c - sum_i W[R_i, c] x_{R_i}   (transposed W), per level
 namespace {
 constexpr int WPB = FT / PDIPC_WAVE;   // waves per block
 }
@@ -46,8 +47,7 @@ __device__ __forceinline__ void wave_sum3(double& a0, double& a1, double& a2) {
 }
 
 __global__ void __launch_bounds__(FT) fwd_gather_kernel(FactorDev f, int32_t row0, int32_t nrows,
-                                                        const double* __restrict__ b, const double* __restrict__ y,
-                                                        double* __restrict__ out) {
+                                                        const double* __restrict__ b, double* t) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
   if (k >= nrows) return;
@@ -57,15 +57,15 @@ __global__ void __launch_bounds__(FT) fwd_gather_kernel(FactorDev f, int32_t row
   for (int64_t e = f.fwd_ptr[row] + lane; e < f.fwd_ptr[row + 1]; e += PDIPC_WAVE) {
     int32_t c = f.fwd_col[e];
     double v = f.fwd_val[e];
-    a0 += v * y[3 * c];
-    a1 += v * y[3 * c + 1];
-    a2 += v * y[3 * c + 2];
+    a0 += v * t[3 * c];
+    a1 += v * t[3 * c + 1];
+    a2 += v * t[3 * c + 2];
   }
   wave_sum3(a0, a1, a2);
   if (lane == 0) {
-    out[3 * row] = b[3 * row] - a0;
-    out[3 * row + 1] = b[3 * row + 1] - a1;
-    out[3 * row + 2] = b[3 * row + 2] - a2;
+    t[3 * row] = b[3 * row] - a0;
+    t[3 * row + 1] = b[3 * row + 1] - a1;
+    t[3 * row + 2] = b[3 * row + 2] - a2;
   }
 }
 
@@ -96,8 +96,9 @@ __global__ void __launch_bounds__(FT) fwd_diag_kernel(FactorDev f, int32_t row0,
   }
 }
 
-// rows of x2: y2 = r2 - L21 y1
-__global__ void __launch_bounds__(FT) fwd_x2_kernel(FactorDev f, const double* __restrict__ b, double* __restrict__ y) {
+// rows of x2: y2 = r2 - L21 y1 = r2 - sum over x1 nodes of W_J[x2 rows] t_J
+__global__ void __launch_bounds__(FT) fwd_x2_kernel(FactorDev f, const double* __restrict__ b,
+                                                    const double* __restrict__ t, double* __restrict__ y) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t q = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
   if (q >= f.n2) return;
@@ -107,9 +108,9 @@ __global__ void __launch_bounds__(FT) fwd_x2_kernel(FactorDev f, const double* _
   for (int64_t e = f.fwd_ptr[row] + lane; e < f.fwd_ptr[row + 1]; e += PDIPC_WAVE) {
     int32_t c = f.fwd_col[e];
     double v = f.fwd_val[e];
-    a0 += v * y[3 * c];
-    a1 += v * y[3 * c + 1];
-    a2 += v * y[3 * c + 2];
+    a0 += v * t[3 * c];
+    a1 += v * t[3 * c + 1];
+    a2 += v * t[3 * c + 2];
   }
   wave_sum3(a0, a1, a2);
   if (lane == 0) {
@@ -128,10 +129,12 @@ void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStr
   for (int L = level_begin > 0 ? level_begin : 0; L < level_end; ++L) {
     const int32_t r0 = f.h_lvl_row_ptr[L], nr = f.h_lvl_row_ptr[L + 1] - r0;
     if (nr <= 0) continue;
-    fwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, b, y, tbuf);
-    fwd_diag_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, tbuf, y);
+    fwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, b, tbuf);
   }
-  if (to_end && f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f, b, y);
+  if (!to_end) return;
+  // every diagonal block at once: y_J = Dinv_J t_J, then the x2 rows from t
+  if (f.n1 > 0) fwd_diag_kernel<<<grid_for(f.n1, WPB), FT, 0, st>>>(f, 0, f.n1, tbuf, y);
+  if (f.n2 > 0) fwd_x2_kernel<<<grid_for(f.n2, WPB), FT, 0, st>>>(f, b, tbuf, y);
 }
 
 // z = Sigma^-1 r, r and z are n2 x 3 (x2 part of the extended vectors).  One
@@ -177,10 +180,8 @@ void launch_sigma_gemv(const FactorDev& f, const double* r, double* z, hipStream
   if (f.n2 > 0) sigma_gemv_kernel<<<static_cast<unsigned>((f.n2 + 1) / 2), FT, 0, st>>>(f.n2, f.sigma_inv, r, z);
 }
 
-// s_c = y_c - sum_i panelT_J[c][i] sol[R_J[i]]
-__global__ void __launch_bounds__(FT) bwd_gather_kernel(FactorDev f, int32_t row0, int32_t nrows,
-                                                        const double* __restrict__ y, const double* __restrict__ sol,
-                                                        double* __restrict__ out) {
+// x_c = z_c - sum_i W_J^T[c][i] x[R_J[i]], z_c in sol already (z = Dinv^T y)
+__global__ void __launch_bounds__(FT) bwd_gather_kernel(FactorDev f, int32_t row0, int32_t nrows, double* sol) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * WPB + threadIdx.x / PDIPC_WAVE;
   if (k >= nrows) return;
@@ -201,13 +202,12 @@ __global__ void __launch_bounds__(FT) bwd_gather_kernel(FactorDev f, int32_t row
   }
   wave_sum3(a0, a1, a2);
   if (lane == 0) {
-    out[3 * col] = y[3 * col] - a0;
-    out[3 * col + 1] = y[3 * col + 1] - a1;
-    out[3 * col + 2] = y[3 * col + 2] - a2;
+    sol[3 * col] -= a0;
+    sol[3 * col + 1] -= a1;
+    sol[3 * col + 2] -= a2;
   }
 }
 
-// x_c = sum_{r >= c} Dinv_J[r][c] s_{c0 + r} = sum_r DinvT_J[c][r] s_{c0 + r}
 __global__ void __launch_bounds__(FT) bwd_diag_kernel(FactorDev f, int32_t row0, int32_t nrows,
                                                       const double* __restrict__ t, double* __restrict__ sol) {
   const int lane = threadIdx.x % PDIPC_WAVE;
@@ -235,12 +235,12 @@ __global__ void __launch_bounds__(FT) bwd_diag_kernel(FactorDev f, int32_t row0,
 }
 
 void launch_backward_sweep(const FactorDev& f, const double* y, double* sol, hipStream_t st) {
-  double* tbuf = sol + 3 * static_cast<int64_t>(f.n1 + f.n2);
+  // every diagonal block first: z_J = Dinv_J^T y_J into the x1 rows of sol
+  if (f.n1 > 0) bwd_diag_kernel<<<grid_for(f.n1, WPB), FT, 0, st>>>(f, 0, f.n1, y, sol);
   for (int L = f.nlevels - 1; L >= 0; --L) {
     const int32_t r0 = f.h_lvl_row_ptr[L], nr = f.h_lvl_row_ptr[L + 1] - r0;
     if (nr <= 0) continue;
-    bwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, y, sol, tbuf);
-    bwd_diag_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, tbuf, sol);
+    bwd_gather_kernel<<<grid_for(nr, WPB), FT, 0, st>>>(f, r0, nr, sol);
   }
 }
 
@@ -258,6 +258,33 @@ void launch_unpack(const FactorDev& f, int32_t n, const double* sol, double* dx,
   (void)n;
   int32_t N = f.n1 + f.n2;
   if (N > 0) unpack_kernel<<<grid_for(N, 256), 256, 0, st>>>(N, f.ext2vert, sol, dx);
+}
+
+// W_J = P_J Dinv_J per supernode (P_J = L[R(J), cols(J)], r x s row-major;
+// Dinv_J lower triangular, s x s row-major): one workgroup per node.
+__global__ void __launch_bounds__(256) panel_dinv_kernel(const int32_t* __restrict__ node_s,
+                                                         const int32_t* __restrict__ node_r,
+                                                         const int64_t* __restrict__ poff,
+                                                         const int64_t* __restrict__ doff,
+                                                         const double* __restrict__ P,
+                                                         const double* __restrict__ D, double* __restrict__ W) {
+  const int32_t J = blockIdx.x;
+  const int32_t s = node_s[J], r = node_r[J];
+  const double* PJ = P + poff[J];
+  const double* DJ = D + doff[J];
+  double* WJ = W + poff[J];
+  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(r) * s; e += blockDim.x) {
+    const int64_t i = e / s;
+    const int32_t c = static_cast<int32_t>(e % s);
+    double acc = 0.0;
+    for (int32_t k = c; k < s; ++k) acc += PJ[i * s + k] * DJ[static_cast<int64_t>(k) * s + c];
+    WJ[e] = acc;
+  }
+}
+
+void launch_panel_times_dinv(int32_t nnodes, const int32_t* node_s, const int32_t* node_r, const int64_t* poff,
+                             const int64_t* doff, const double* P, const double* D, double* W, hipStream_t st) {
+  if (nnodes > 0) panel_dinv_kernel<<<static_cast<unsigned>(nnodes), 256, 0, st>>>(node_s, node_r, poff, doff, P, D, W);
 }
 
 // ---- reduced contact system helpers ---------------------------------------------

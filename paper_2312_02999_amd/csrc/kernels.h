@@ -209,7 +209,12 @@ struct FactorDev {
 };
 // b (ext, 3) = -g at ext2vert
 void launch_pack_rhs(const FactorDev& f, const double* g, double* b, hipStream_t st);
-// forward sweep: y (ext, 3); rows of x2 get r2 - L21 y1 (no diagonal solve)
+// W_J = L[R(J), cols(J)] Dinv_J per supernode, in the panel layout (init)
+void launch_panel_times_dinv(int32_t nnodes, const int32_t* node_s, const int32_t* node_r, const int64_t* poff,
+                             const int64_t* doff, const double* P, const double* D, double* W, hipStream_t st);
+// forward sweep: y (ext, 3); rows of x2 get r2 - L21 y1 (no diagonal solve).
+// The sweeps read W (f.fwd_val by rows, f.panelT transposed) in place of the
+// panels; levels carry t, and the diagonal blocks go in one launch.
 // (levels [level_begin, level_end) of the x1 sweep; level_end < 0: to the end,
 // then the x2 rows)
 void launch_forward_sweep(const FactorDev& f, const double* b, double* y, hipStream_t st, int level_begin = 0,

@@ -476,15 +476,6 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
     }
     S->h_lvl_row_ptr[L + 1] = static_cast<int32_t>(lrows.size());
   }
-  // transposed panels (s x r row-major) for the upper sweep
-  std::vector<double> pT(hf.panel.size());
-  for (int32_t J = 0; J < nn; ++J) {
-    const int s_ = ss[J], r_ = rr[J];
-    const double* P = hf.panel.data() + po[J];
-    double* Q = pT.data() + po[J];
-    for (int i = 0; i < r_; ++i)
-      for (int c = 0; c < s_; ++c) Q[static_cast<int64_t>(c) * r_ + i] = P[static_cast<int64_t>(i) * s_ + c];
-  }
   std::vector<double> dT(hf.dinv.size());
   for (int32_t J = 0; J < nn; ++J) {
     const int s = ss[J];
@@ -504,14 +495,55 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   S->node_doff.upload(dof.data(), nn, st);
   S->level_nodes.upload(lev_nodes.data(), nn, st);
   S->frows.upload(hf.rows.data(), static_cast<int64_t>(hf.rows.size()), st);
-  S->panelT.upload(pT.data(), static_cast<int64_t>(pT.size()), st);
   S->lvl_rows.upload(lrows.data(), static_cast<int64_t>(lrows.size()), st);
   S->lvl_row_node.upload(lnode.data(), static_cast<int64_t>(lnode.size()), st);
   S->dinv.upload(hf.dinv.data(), static_cast<int64_t>(hf.dinv.size()), st);
   S->dinvT.upload(dT.data(), static_cast<int64_t>(dT.size()), st);
   S->fptr.upload(hf.fwd_ptr.data(), static_cast<int64_t>(hf.fwd_ptr.size()), st);
   S->fcol.upload(hf.fwd_col.data(), static_cast<int64_t>(hf.fwd_col.size()), st);
-  S->fval.upload(hf.fwd_val.data(), static_cast<int64_t>(hf.fwd_val.size()), st);
+  {
+    // The sweeps use W_J = L_{R(J),J} Dinv_J in place of the panels: the lower
+    // sweep then carries t (before the diagonal blocks) from level to level,
+    // t_J = b_J - sum over descendants K of W_K[J rows] t_K, and applies every
+    // Dinv_J in one launch at the end; the upper sweep applies every Dinv_J^T
+    // first and then needs one launch per level, x_J = z_J - W_J^T x_R.
+    std::vector<double> pw(hf.panel.size());
+    if (!pw.empty()) {
+      DBuf<double> pan, out;
+      pan.upload(hf.panel.data(), static_cast<int64_t>(pw.size()), st);
+      out.ensure(static_cast<int64_t>(pw.size()));
+      launch_panel_times_dinv(nn, S->node_s.p, S->node_r.p, S->node_poff.p, S->node_doff.p, pan.p, S->dinv.p, out.p,
+                              st);
+      HIPCHK(hipMemcpyAsync(pw.data(), out.p, sizeof(double) * pw.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      pan.release();
+      out.release();
+    }
+    // transposed (s x r row-major per node) for the upper sweep
+    std::vector<double> pT(pw.size());
+    for (int32_t J = 0; J < nn; ++J) {
+      const int s_ = ss[J], r_ = rr[J];
+      const double* P = pw.data() + po[J];
+      double* Q = pT.data() + po[J];
+      for (int i = 0; i < r_; ++i)
+        for (int c = 0; c < s_; ++c) Q[static_cast<int64_t>(c) * r_ + i] = P[static_cast<int64_t>(i) * s_ + c];
+    }
+    S->panelT.upload(pT.data(), static_cast<int64_t>(pT.size()), st);
+    // by rows for the lower sweep, in the order of the row copy of the panels
+    std::vector<double> fv(hf.fwd_val.size());
+    std::vector<int64_t> cur(hf.fwd_ptr.begin(), hf.fwd_ptr.end() - 1);
+    for (int32_t J = 0; J < nn; ++J) {
+      const int s_ = ss[J], r_ = rr[J];
+      const double* P = pw.data() + po[J];
+      const int32_t* R = hf.rows.data() + ro[J];
+      for (int i = 0; i < r_; ++i) {
+        int64_t& q = cur[R[i]];
+        for (int k = 0; k < s_; ++k) fv[q++] = P[static_cast<int64_t>(i) * s_ + k];
+      }
+    }
+    S->fval.upload(fv.data(), static_cast<int64_t>(fv.size()), st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
   S->ext2vert.upload(e2v.data(), N, st);
   S->vert2x2.upload(v2x2.data(), n, st);
   S->bvec.ensure(3LL * std::max(N, 1));
