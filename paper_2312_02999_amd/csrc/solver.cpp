@@ -948,6 +948,7 @@ static void global_step(Solver* S, IterOut& io) {
     // The reduced system depends only on the contact terms and C^-1: build and
     // factor it on the side stream while the sweeps run on the main stream.
     hipStream_t sd = S->side;
+    bool keep_flags = false;
     HIPCHK(hipStreamWaitEvent(sd, S->ev_fork, 0));
     if (!io.c_same) {
       const int32_t nk = nc - io.c_added;
@@ -1005,8 +1006,7 @@ static void global_step(Solver* S, IterOut& io) {
       S->check_info_cs = true;
       S->prev_cflag.ensure(S->n + 1LL);
       S->prev_cidx.ensure(S->n + 1LL);
-      HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, sd));
-      HIPCHK(hipMemcpyAsync(S->prev_cidx.p, S->inc.cidx, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, sd));
+      keep_flags = true;                // copied on the main stream once C^-1 is ready
       S->nc_prev = nc;
       S->cinv_valid = true;
       io.c_same = true;                 // later solves with this io reuse it
@@ -1039,6 +1039,12 @@ static void global_step(Solver* S, IterOut& io) {
     }
     HIPCHK(hipStreamWaitEvent(st, S->ev_cinv, 0));
     launch_cinv_times_zc(nc, S->Cinv.p, S->c_x2.p, S->solvec.p + n1x3, S->rhs.p, st);
+    if (keep_flags) {
+      // the flags and ranks of the c that C^-1 now belongs to (the update has
+      // read the previous ones: it precedes the C^-1 event)
+      HIPCHK(hipMemcpyAsync(S->prev_cflag.p, S->inc.cflag, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(S->prev_cidx.p, S->inc.cidx, sizeof(int32_t) * (S->n + 1LL), hipMemcpyDeviceToDevice, st));
+    }
     HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
     bool fallback = false;
     if (mixed) {
