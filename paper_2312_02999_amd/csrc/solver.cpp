@@ -961,7 +961,9 @@ static void global_step(Solver* S, IterOut& io) {
         S->c_delta_sum += delta;
         S->c_delta_max = std::max(S->c_delta_max, delta);
       }
-      launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, sd);
+      // c -> rows of Sigma^-1: on the main stream when only the main stream
+      // reads them (the update takes its indices from the vertex map itself)
+      launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, incremental ? st : sd);
       if (incremental) {
         ScopedTimer tm(S, TK_CINV_UPDATE, sd);
         const int32_t r = io.c_removed, a = io.c_added;
@@ -1123,6 +1125,9 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   };
   const int queued = std::min(2, S->opt.ls_max_halvings + 1);
   for (int h = 0; h < queued; ++h) trial();
+  // x += alpha dx is applied by the device once the search has accepted, so it
+  // is queued before the readback; a search still open repeats it below
+  if (apply) launch_axpy_ls(3LL * S->n, ls, S->dx.p, S->x.p, st);
   double hls[LS_SIZE];
   int32_t hinfo[4] = {0, 0, 0, 0};
   auto readback = [&]() {
@@ -1136,7 +1141,9 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   if (S->check_info_m && hinfo[0] != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
   if (S->check_info_cs && hinfo[3] != 0) fail(PDIPC_E_NOT_SPD, "contact block of the inverse Schur complement not SPD");
   S->check_info_m = S->check_info_cs = false;
+  bool reopened = false;
   while (hls[LS_STATE] == 0.0) {
+    reopened = true;
     trial();
     readback();
   }
@@ -1144,7 +1151,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   io.halvings = static_cast<int32_t>(hls[LS_HALVINGS]);
   io.ls_ok = hls[LS_STATE] == 1.0;
   io.alpha = io.ls_ok ? hls[LS_ALPHA] : 0.0;
-  if (apply && io.alpha > 0.0) launch_axpy_ls(3LL * S->n, ls, S->dx.p, S->x.p, st);
+  if (apply && reopened && io.alpha > 0.0) launch_axpy_ls(3LL * S->n, ls, S->dx.p, S->x.p, st);
 }
 
 static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdipc_frame_stats* stats) {
