@@ -1111,7 +1111,9 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
                       S->ccd_part.p, st, S->opt.dhat, S->opt.kappa, S->bE0.p);
   }
   // back-tracking line search on the device: trials read alpha from the state
-  // and become no-ops once it is decided; two are queued, then one readback
+  // and become no-ops once it is decided; one is queued, then one readback
+  // (the first trial is accepted in nearly every iteration: 4 halvings in 240
+  // on the 50k face, so a second queued trial costs more than its round trip)
   double* ls = S->lsbuf.p;
   launch_ls_init(ls, S->ccd_part.p, nccd, st);
   auto trial = [&]() {
@@ -1123,7 +1125,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
                                S->bdE.p, st);
     launch_sum2_decide(S->dE.p, S->m, S->bdE.p, ncand, ls, S->red_tmp.p, S->opt.ls_max_halvings, st);
   };
-  const int queued = std::min(2, S->opt.ls_max_halvings + 1);
+  const int queued = 1;
   for (int h = 0; h < queued; ++h) trial();
   // x += alpha dx is applied by the device once the search has accepted, so it
   // is queued before the readback; a search still open repeats it below
