@@ -528,7 +528,136 @@ def test_frames_stay_intersection_free_and_energy_decreases():
         r = solver.frame(prob, x, A, iters=8, trace=True)
         for rec in r.trace:
             assert 0 < rec.alpha <= rec.alpha_m <= 1
+        # the total energy never increases along the iterates (line search on
+        # E_hat, Algorithm 1), counted over every pair, active or not
+        E = [_total_energy(prob, rec.x, A) for rec in r.trace] + [_total_energy(prob, r.x, A)]
+        assert all(E[k + 1] <= E[k] + 1e-14 * abs(E[k]) for k in range(len(E) - 1)), E
+        assert E[-1] < E[0]
         x = r.x
         dmin = contact.min_distance(x, prob.prox)
         assert dmin > 0
     assert max(r.n_pt) > 0
+
+
+# --------------------------------------------------------------------------
+# swept candidates, line-search barrier term, energy decrease (Algorithm 1)
+# --------------------------------------------------------------------------
+def _brute_swept(x0, x1, prox, margin):
+    """Swept-box pairs by explicit loops over every pair of primitives.
+
+    A vertex moving linearly from x0 to x1 stays inside the box spanned by its
+    two end positions, so a primitive's swept box is the box of all of its
+    corners at both ends.  Two boxes overlap with the margin when every axis
+    interval, widened by the margin, intersects.
+    """
+    def box(ids):
+        pts = [x0[i] for i in ids] + [x1[i] for i in ids]
+        lo = [min(p[a] for p in pts) for a in range(3)]
+        hi = [max(p[a] for p in pts) for a in range(3)]
+        return lo, hi
+
+    def overlap(b1, b2):
+        return all(b1[0][a] <= b2[1][a] + margin and b2[0][a] <= b1[1][a] + margin for a in range(3))
+
+    pt, ee = [], []
+    for v in prox.verts:
+        bv = box([v])
+        for f, tri in enumerate(prox.tris):
+            if v not in tri and overlap(bv, box(tri)):
+                pt.append((v, f))
+    E = prox.edges
+    for i in range(len(E)):
+        for j in range(i + 1, len(E)):
+            if not set(E[i]) & set(E[j]) and overlap(box(E[i]), box(E[j])):
+                ee.append((i, j))
+    return np.array(pt, np.int64).reshape(-1, 2), np.array(ee, np.int64).reshape(-1, 2)
+
+
+def test_swept_candidates_equal_brute_force_enumeration():
+    sc = mg.slabs(0, nx=3, ny=3, nz=1, gap=1e-3)
+    prox = contact.make_proxy(sc.surf_tris)
+    rng = np.random.default_rng(11)
+    x0 = sc.X + rng.uniform(-1e-4, 1e-4, sc.X.shape)
+    dx = rng.standard_normal(sc.X.shape) * 6e-4
+    dx[sc.X[:, 2] > 0.0105, 2] -= 1.5e-3             # upper face sweeps through the gap
+    pt, ee = contact.candidates(x0, x0 + dx, prox, DHAT)
+    bpt, bee = _brute_swept(x0, x0 + dx, prox, DHAT)
+    assert len(pt) > 0 and len(ee) > 0
+    assert np.array_equal(pt, bpt) and np.array_equal(ee, bee)
+
+
+def test_swept_candidates_hold_a_pair_that_meets_only_mid_sweep():
+    """A point passing straight through a triangle: apart by more than dhat at
+    both ends of the motion, at distance 0 half-way.  Only a box over the
+    whole motion (not over either end state) contains that pair."""
+    tri = np.array([[0.0, 0.0, 0.0], [1e-2, 0.0, 0.0], [0.0, 1e-2, 0.0]])
+    p0, p1 = np.array([-4e-3, 2e-3, 4e-3]), np.array([8e-3, 2e-3, -4e-3])
+    x0 = np.vstack([tri, p0])
+    x1 = np.vstack([tri, p1])
+    prox = contact.Proxy(verts=np.array([3]), tris=np.array([[0, 1, 2]]), edges=np.zeros((0, 2), np.int64))
+    for xa, xb in ((x0, x0), (x1, x1)):
+        assert len(contact.candidates(xa, xb, prox, DHAT)[0]) == 0
+    pt, _ = contact.candidates(x0, x1, prox, DHAT)
+    assert pt.tolist() == [[3, 0]]
+    # the distance along the motion does drop to zero half-way
+    mid = 0.5 * (x0 + x1)
+    assert geo.point_triangle(mid[3], *tri)[0][0] < 1e-30
+
+
+def test_swept_candidates_contain_every_pair_that_comes_within_dhat():
+    """Completeness, the property the step bound and the line search rely on:
+    every pair whose distance drops below dhat anywhere along the linear
+    motion (dense sampling of the motion) is a candidate."""
+    sc = mg.slabs(2, nx=3, ny=3, nz=1, gap=1e-3)
+    prox = contact.make_proxy(sc.surf_tris)
+    rng = np.random.default_rng(5)
+    x0 = sc.X + rng.uniform(-1e-4, 1e-4, sc.X.shape)
+    dx = rng.standard_normal(sc.X.shape) * 3e-4
+    dx[sc.X[:, 2] > 0.0105, 2] -= 9e-4
+    pt, ee = contact.candidates(x0, x0 + dx, prox, DHAT)
+    have_pt = {tuple(r) for r in pt.tolist()}
+    have_ee = {tuple(r) for r in ee.tolist()}
+    apt, aee = contact.candidates(x0, x0, prox, 1.0)   # every non-incident pair
+    dmin = np.full(len(apt) + len(aee), np.inf)
+    for s in np.linspace(0.0, 1.0, 201):
+        dmin = np.minimum(dmin, contact.pair_distances(x0 + s * dx, prox, apt, aee)[0])
+    close = dmin < DHAT * DHAT
+    npt = len(apt)
+    assert close[:npt].sum() > 0 and close[npt:].sum() > 0
+    assert all(tuple(r) in have_pt for r in apt[close[:npt]].tolist())
+    assert all(tuple(r) in have_ee for r in aee[close[npt:]].tolist())
+
+
+def _total_energy(prob, x, A):
+    """E_hat(x) = sum_i (w_i/2)||F_i - R_i A_i||^2 + kappa sum_k b(d_k) over every
+    non-incident pair (pairs at d >= dhat contribute 0)."""
+    F = local.deformation_gradients(x, prob.tets, prob.B)
+    Ee = local.element_energies(F, A, prob.w).sum()
+    cs = contact.constraint_set(x, prob.prox, prob.dhat)
+    Eb = prob.kappa * barrier.barrier(np.sqrt(cs.d2), prob.dhat).sum()
+    return Ee + Eb
+
+
+def test_line_search_counts_pairs_that_enter_dhat_along_the_step():
+    """A step that lowers the elastic energy but brings pairs that are not yet
+    active to a small gap: the barrier differences over the swept candidates
+    must reject the CCD bound (a search over the active set alone, or over
+    the elastic energy alone, would accept it)."""
+    sc = mg.slabs(0, nx=3, ny=3, nz=1, gap=1e-3)
+    prob = solver.setup_scene(sc)
+    A = fem.actuation_matrices(sc.act_a, sc.act_R)
+    x = sc.X.copy()
+    assert contact.constraint_set(x, prob.prox, prob.dhat).size == 0
+    dx = np.zeros_like(x)
+    low_face_of_upper = np.isclose(sc.X[:, 2], 0.01 + 1e-3)
+    dx[low_face_of_upper, 2] = -8.5e-4               # gap 1 mm -> 0.15 mm
+    alpha_m, spt, see = ccd.step_bound(x, dx, prob.prox, prob.dhat)
+    assert alpha_m == 1.0                            # 0.15 mm is above the CCD target 0.1 mm
+    F0 = local.deformation_gradients(x, prob.tets, prob.B)
+    F1 = local.deformation_gradients(x + dx, prob.tets, prob.B)
+    dE_elastic = local.element_energies(F1, A, prob.w).sum() - local.element_energies(F0, A, prob.w).sum()
+    assert dE_elastic < 0
+    assert _total_energy(prob, x + dx, A) > _total_energy(prob, x, A)
+    alpha, halvings, ok = solver.line_search(prob, x, dx, A, alpha_m, spt, see)
+    assert ok and halvings >= 1 and alpha < alpha_m
+    assert _total_energy(prob, x + alpha * dx, A) <= _total_energy(prob, x, A)
