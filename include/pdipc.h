@@ -47,18 +47,36 @@ enum { PDIPC_FP64 = 0, PDIPC_MIXED_FP32 = 1 };
 
 /*
  * Mesh description (Section 2 of the paper: tetrahedral simulation mesh,
- * embedded collision proxy s = W x, manually marked collision region x2).
- * All pointers are host memory and are only read during pdipc_init_mesh.
+ * embedded collision proxy s = W x of Section 3.1, manually marked collision
+ * region x2 of Eq. 6).  All pointers are host memory and are only read during
+ * pdipc_init_mesh; the library copies what it keeps.
  *  rest_pos    n_verts x 3   rest positions X [m]
  *  tets        n_tets x 4    vertex ids; every tet must have det[X1-X0,
  *                            X2-X0, X3-X0] > 0 (else PDIPC_E_DEGENERATE)
- *  dirichlet   n_verts       1 = vertex fixed at its rest position (needs at
- *                            least one, else the PD matrix is singular)
- *  surf_tris   n_surf_tris x 3  proxy triangles as simulation vertex ids (the
- *                            proxy is embedded by selection: W picks vertices)
+ *  dirichlet   n_verts       1 = vertex fixed at its rest position; at least
+ *                            one is needed (else PDIPC_E_NOT_SPD: the PD
+ *                            matrix of Eq. 2 would be singular)
+ *  n_surf_verts, W_rowptr, W_col, W_val
+ *                            the proxy vertices s = W x as a CSR matrix of
+ *                            n_surf_verts rows over the n_verts simulation
+ *                            vertices (W_rowptr: n_surf_verts + 1 entries,
+ *                            W_col: column ids, W_val: weights, NULL = every
+ *                            row has one entry of weight 1).  Rows must have
+ *                            non-negative weights that sum to 1 within 1e-12
+ *                            and distinct columns (else PDIPC_E_INVALID).
+ *                            This build embeds the proxy by selection: every
+ *                            row must pick one vertex with weight 1; a row
+ *                            that interpolates several vertices is rejected
+ *                            with PDIPC_E_INVALID.
+ *                            W_rowptr = NULL: no W; surf_tris then holds
+ *                            simulation vertex ids directly.
+ *  n_surf_tris, surf_tris    proxy triangles, n_surf_tris x 3 ids of proxy
+ *                            vertices (rows of W), or of simulation vertices
+ *                            when W_rowptr is NULL
  *  region      n_verts or NULL  1 = collision-aware vertex (block x2 of Eq. 6);
- *                            NULL = the free vertices of the proxy.  Every free
- *                            proxy vertex must be marked (else PDIPC_E_INVALID).
+ *                            NULL = the free vertices the proxy uses.  Every
+ *                            free proxy vertex must be marked (else
+ *                            PDIPC_E_INVALID).
  *  youngs, poisson           element weight w_i = 2 mu V_i, mu = E/(2(1+nu))
  */
 typedef struct {
@@ -70,6 +88,10 @@ typedef struct {
   const int32_t* surf_tris;
   const uint8_t* region;
   double youngs, poisson;
+  int32_t n_surf_verts;
+  const int32_t* W_rowptr;
+  const int32_t* W_col;
+  const double* W_val;
 } pdipc_mesh_desc;
 
 /*
@@ -109,8 +131,14 @@ typedef struct {
 } pdipc_options;
 
 /* Per-frame statistics (host).  Stage times follow the paper's Table 1
- * columns: IPC (constraint set + barrier derivatives), G-Step (global solve),
- * CCD, LS (line search), Misc (local step, assembly, bookkeeping).
+ * columns, measured with HIP events at the stage boundaries of every
+ * iteration on the solver's stream (the reduced system's second stream is
+ * inside G-Step, which waits for it): IPC (constraint set, barrier
+ * derivatives and their incidence), Misc (local step, gradient assembly, and
+ * the frame's own copies and checks), G-Step (global solve), CCD (swept
+ * candidates and the step bound), LS (line search and update).
+ * near_ties: candidates whose distance was within 1e-10 dhat of dhat when the
+ * constraint set was formed (membership there can follow rounding).
  * refine_steps / refine_fallbacks: mixed-precision refinement solves and the
  * iterations whose reduced system fell back to the FP64 factor.
  * cinv_rebuilds: iterations whose contact set c differed from the previous
@@ -120,6 +148,7 @@ typedef struct {
 typedef struct {
   int32_t iters, n_pt, n_ee, n_c, ls_halvings, ls_failures, refine_steps;
   int32_t n_candidates, refine_fallbacks, cinv_rebuilds, c_delta_max, c_delta_sum, cinv_updates;
+  int32_t near_ties, pcg_iters;
   double alpha_m_min, alpha_min, energy, grad_inf;
   double ms_ipc, ms_gstep, ms_ccd, ms_ls, ms_misc, ms_total;
 } pdipc_frame_stats;
@@ -163,54 +192,11 @@ int32_t pdipc_device_bytes(const void* solver, int64_t* bytes);
 /* Sizes of the blocks after init: n1, n2 of Eq. (6) and nnz of the factor. */
 int32_t pdipc_get_sizes(const void* solver, int64_t* n1, int64_t* n2, int64_t* factor_nnz);
 
-/* Measurement tap: read and reset the HIP-event timer, then arm it for the
- * kernel family `which` (-1 = off): 0 local step, 1 Sigma^-1 GEMV, 2 lower
- * sweep, 3 upper sweep, 4 barrier, 5 line-search energies, 6 reduced
- * Cholesky, 8 CCD, 9 incremental C^-1 update, 10 full C^-1
- * rebuild (Cholesky and inverse of the contact block).  Events are recorded on the solver's stream around every
- * launch of that family during pdipc_solve_frame; *total_ms and *launches
- * (host, nullable) return what was accumulated since the previous call. */
-int32_t pdipc_kernel_timer(void* solver, int32_t which, double* total_ms, int64_t* launches);
-
 /* Release everything the solver owns. NULL is allowed. */
 void pdipc_destroy(void* solver);
 
 /* Last error message of a handle (or of the last failed init if NULL). */
 const char* pdipc_last_error(const void* solver);
-
-/* ---- debug / parity taps (device pointers, sizes from pdipc_get_sizes) ----
- * pdipc_debug_local: run only the local step at x (device n x 3): writes
- *   R (device m x 9 row-major) and element energies (device m), and the PD
- *   gradient sum_i w_i G_i^T (G_i x - p_i) (device n x 3, zero at fixed).
- * pdipc_debug_contacts: constraint set at x: writes up to cap pairs as
- *   (type, i, j) int32 triples into pairs (device), returns the count in
- *   *count (host).  type 0 = point-triangle (sim vertex, proxy triangle),
- *   type 1 = edge-edge (edge, edge) with edges sorted (lo, hi).
- * pdipc_debug_step: one full iteration from x; writes dx (device n x 3) and
- *   the host scalars alpha_m, alpha. */
-int32_t pdipc_debug_local(void* solver, const double* x, double* R, double* energies, double* grad);
-int32_t pdipc_debug_contacts(void* solver, const double* x, int32_t* pairs, int32_t cap, int32_t* count);
-int32_t pdipc_debug_step(void* solver, const double* x, double* dx, double* alpha_m, double* alpha);
-
-/* Dense SPD kernels on caller data (test tap, default stream): factor the
- * device matrix A (n x n row-major, symmetric positive definite; not
- * modified), solve A x = b in place for b (device n x nrhs, nrhs <= 4, may
- * be NULL) and write A^-1 to Ainv (device n x n, may be NULL).  precision 1
- * runs the FP32 kernels on a rounded copy.  PDIPC_E_NOT_SPD on a non-positive
- * pivot. */
-int32_t pdipc_debug_dense(const double* A, int64_t n, double* b, int32_t nrhs, double* Ainv, int32_t precision);
-
-/* Host-only check of the set-up factorization (no device work, usable
- * without a GPU).  Input: the scalar PD matrix over free vertices in
- * extended order (x1 block [0, n1) with coordinates coords1 (n1 x 3), then
- * x2 block) as full-pattern CSR (ptr: n1 + n2 + 1 int64, col int32, val);
- * leaf = nested-dissection leaf size.  Solves H x = b (host vectors of
- * n1 + n2) through the supernodal factor and a dense host Cholesky of the
- * Schur complement, writes Sigma_s (n2 x n2 row-major, host) and the factor
- * size.  b/x/sigma_out/nnz_out may be NULL to skip. */
-int32_t pdipc_debug_host_factor(int32_t n1, int32_t n2, const double* coords1, const int64_t* ptr,
-                                const int32_t* col, const double* val, int32_t leaf, const double* b, double* x,
-                                double* sigma_out, int64_t* nnz_out);
 
 #ifdef __cplusplus
 }

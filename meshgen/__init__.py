@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "Scene", "hex_grid_tets", "boundary_faces", "unique_edges",
     "random_rotations", "slabs", "face_like", "ramp", "keyframe_sequence",
-    "scene_by_name",
+    "scene_by_name", "closed_slit_state",
 ]
 
 
@@ -72,6 +72,24 @@ class Scene:
     def actuation_at(self, t: float) -> np.ndarray:
         """Strength field at ramp fraction t in [0, 1]."""
         return (float(t) * self.act_a).astype(np.float64)
+
+    def sequence(self) -> list:
+        """Per-frame strength fields of the scene's animation: from rest
+        through its keyframe fields (piecewise linear, ``frames`` frames in
+        all, spread evenly over the segments), or the plain ramp of ``act_a``
+        when it has no keyframes."""
+        keys = self.meta.get("keyframes") or []
+        if not keys:
+            return [self.actuation_at((t + 1) / self.frames) for t in range(self.frames)]
+        fields = [np.zeros_like(self.act_a)] + list(keys)
+        bounds = np.linspace(0, self.frames, len(fields)).round().astype(int)
+        seq = []
+        for k in range(len(fields) - 1):
+            n_seg = bounds[k + 1] - bounds[k]
+            for s in range(n_seg):
+                w = (s + 1) / n_seg
+                seq.append((1 - w) * fields[k] + w * fields[k + 1])
+        return seq
 
 
 # --------------------------------------------------------------------------
@@ -236,18 +254,41 @@ def _ellipsoid_normal(P, axes):
     return n / np.linalg.norm(n, axis=-1, keepdims=True)
 
 
+def graded_nodes(lo: float, hi: float, n: int, centers=(), ratio: float = 1.0, band: float = 1.0) -> np.ndarray:
+    """n + 1 grid nodes on [lo, hi] whose spacing is ``ratio`` times finer
+    near each of ``centers`` than far from them: node k sits where the
+    integral of the density 1 + (ratio - 1) max_c exp(-((u - c) / band)^2)
+    reaches k / n of its total.  ratio = 1 gives the uniform grid."""
+    if ratio == 1.0 or not len(centers):
+        return np.linspace(lo, hi, n + 1)
+    u = np.linspace(lo, hi, 40001)
+    bump = np.max([np.exp(-((u - c) / band) ** 2) for c in centers], axis=0)
+    rho = 1.0 + (ratio - 1.0) * bump
+    cum = np.concatenate([[0.0], np.cumsum(0.5 * (rho[1:] + rho[:-1]) * np.diff(u))])
+    nodes = np.interp(np.linspace(0.0, cum[-1], n + 1), cum, u)
+    nodes[0], nodes[-1] = lo, hi
+    return nodes
+
+
 def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int = 0,
               axes=(0.10, 0.12, 0.06), thickness: float = 0.02,
               theta_max: float = 1.2, phi_max: float = 1.2,
               slits=(("mouth", 0.0, -0.35, 0.06),), region_radius: float = 0.025,
               fix_radius: float = 0.03, n_bumps: int = 8, a_cap: float = 0.35,
-              bump_height: float = 0.6, frames: int = 10, iters: int = 30) -> Scene:
+              bump_height: float = 0.6, frames: int = 10, iters: int = 30,
+              grade=(1.0, 1.0, 1.0, 1.0), keyframes: int = 0) -> Scene:
     """Half-ellipsoidal shell of n_theta x n_phi x n_layers hexes.
 
     The outer surface is the ellipsoid with semi-axes ``axes``; layers step
-    inward along the outer normal to ``thickness``.  Each slit
+    inward along the outer normal to ``thickness``.  The (theta, phi) grid is
+    graded toward the slits: ``grade = (ratio_theta, band_theta, ratio_phi,
+    band_phi)`` makes cells ratio times finer within about band (radians) of
+    the slit centres (see ``graded_nodes``).  Each slit
     (name, theta_c, phi_c, length) removes one row of hexes through the whole
-    thickness over ``length`` of outer arc, leaving a slot of one cell height.
+    thickness over ``length`` of outer arc (the columns whose centres lie
+    within length / 2 of the slit centre), leaving a slot of one cell height.
+    ``keyframes`` > 0 adds that many further seeded strength fields (same
+    bump recipe) to ``meta["keyframes"]`` for ``Scene.sequence``.
     Fixed vertices: the inner surface farther than ``fix_radius`` from every
     slit, plus the whole rim of the parameter domain.  The collision-aware
     region is every free vertex of a tet whose centroid lies within
@@ -258,8 +299,9 @@ def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int
     """
     rng = np.random.default_rng(seed)
     nvt, nvp, nvl = n_theta + 1, n_phi + 1, n_layers + 1
-    th = np.linspace(-theta_max, theta_max, nvt)
-    ph = np.linspace(-phi_max, phi_max, nvp)
+    r_th, b_th, r_ph, b_ph = grade
+    th = graded_nodes(-theta_max, theta_max, n_theta, [sl[1] for sl in slits], r_th, b_th)
+    ph = graded_nodes(-phi_max, phi_max, n_phi, [sl[2] for sl in slits], r_ph, b_ph)
     # vertex (i, j, k): i along theta, j along phi, k through thickness
     TT, PP = np.meshgrid(th, ph, indexing="ij")          # (nvt, nvp)
     outer = _ellipsoid_point(TT, PP, axes)               # (nvt, nvp, 3)
@@ -270,17 +312,20 @@ def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int
     X = V.transpose(2, 1, 0, 3).reshape(-1, 3)
     keep = np.ones((n_theta, n_phi, n_layers), dtype=bool)
     slit_info = []
-    dth = th[1] - th[0]
     for name, th_c, ph_c, length in slits:
         jrow = int(np.argmin(np.abs(0.5 * (ph[:-1] + ph[1:]) - ph_c)))
-        # outer arc length per theta step at this latitude (approx.)
+        # outer arc length along theta at this latitude; columns whose centre
+        # lies within length / 2 of the slit centre are removed
         phi_mid = 0.5 * (ph[jrow] + ph[jrow + 1])
-        p0 = _ellipsoid_point(np.array(th_c), np.array(phi_mid), axes)
-        p1 = _ellipsoid_point(np.array(th_c + dth), np.array(phi_mid), axes)
-        step = float(np.linalg.norm(p1 - p0))
-        half = max(1, int(round(0.5 * length / step)))
-        ic = int(np.argmin(np.abs(0.5 * (th[:-1] + th[1:]) - th_c)))
-        i0, i1 = max(1, ic - half + 1), min(n_theta - 1, ic + half + 1)
+        P = _ellipsoid_point(th, np.full_like(th, phi_mid), axes)
+        arc = np.concatenate([[0.0], np.cumsum(np.linalg.norm(np.diff(P, axis=0), axis=1))])
+        mid = 0.5 * (arc[1:] + arc[:-1])
+        s_c = float(np.interp(th_c, th, arc))
+        cols = np.nonzero(np.abs(mid - s_c) < 0.5 * length)[0]
+        cols = cols[(cols >= 1) & (cols <= n_theta - 2)]
+        if cols.size == 0:
+            cols = np.array([int(np.argmin(np.abs(mid - s_c)))])
+        i0, i1 = int(cols[0]), int(cols[-1]) + 1
         keep[i0:i1, jrow, :] = False
         a_pt = _ellipsoid_point(np.array(th[i0]), np.array(phi_mid), axes)
         b_pt = _ellipsoid_point(np.array(th[i1]), np.array(phi_mid), axes)
@@ -306,32 +351,42 @@ def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int
     used = np.zeros(full_ijk.shape[0], dtype=bool)
     used[hex_grid_tets(n_theta, n_phi, n_layers, keep).reshape(-1)] = True
     ijk = full_ijk[used]
-    dslit = dist_to_slits(X)
+    # distances to a slit are lateral: measured from each vertex's counterpart
+    # on the outer surface (layers step along the outer normal), so the whole
+    # depth of a slit wall is as close to the slit as its outer edge
+    Xo = outer[ijk[:, 0], ijk[:, 1]]
+    dslit = dist_to_slits(Xo)
     inner = ijk[:, 2] == n_layers
     rim = (ijk[:, 0] == 0) | (ijk[:, 0] == n_theta) | (ijk[:, 1] == 0) | (ijk[:, 1] == n_phi)
     dirichlet = ((inner & (dslit > fix_radius)) | rim).astype(np.uint8)
 
     cent = X[tets].mean(axis=1)
-    in_region = dist_to_slits(cent) < region_radius
+    in_region = dist_to_slits(Xo[tets].mean(axis=1)) < region_radius
     faces, owner = boundary_faces(tets)
     surf = faces[in_region[owner]].astype(np.int32)
     region = np.zeros(X.shape[0], dtype=np.uint8)
     region[np.unique(tets[in_region].reshape(-1))] = 1
     region[dirichlet == 1] = 0
 
-    # actuation: Gaussian bumps near each slit, contracting along the normal
+    # actuation: Gaussian bumps near each slit, contracting along the normal;
+    # the scene's field and each keyframe field draw their own bumps
     m = tets.shape[0]
-    act = np.zeros(m)
-    for s in slit_info:
-        mid = 0.5 * (s["a"] + s["b"])
-        for _ in range(n_bumps):
-            off = rng.uniform(-1.0, 1.0, 3)
-            off *= rng.uniform(0.0, 0.04) / max(np.linalg.norm(off), 1e-12)
-            mu = mid + off
-            sig = rng.uniform(0.01, 0.03)
-            hgt = bump_height * rng.uniform(0.5, 1.0)
-            act += hgt * np.exp(-np.sum((cent - mu) ** 2, axis=1) / (2 * sig * sig))
-    act_a = np.minimum(a_cap, act)
+
+    def bump_field(g):
+        act = np.zeros(m)
+        for s in slit_info:
+            mid = 0.5 * (s["a"] + s["b"])
+            for _ in range(n_bumps):
+                off = g.uniform(-1.0, 1.0, 3)
+                off *= g.uniform(0.0, 0.04) / max(np.linalg.norm(off), 1e-12)
+                mu = mid + off
+                sig = g.uniform(0.01, 0.03)
+                hgt = bump_height * g.uniform(0.5, 1.0)
+                act += hgt * np.exp(-np.sum((cent - mu) ** 2, axis=1) / (2 * sig * sig))
+        return np.minimum(a_cap, act)
+
+    act_a = bump_field(rng)
+    keys = [bump_field(np.random.default_rng([seed, 1000 + k])) for k in range(keyframes)]
     # local frame: first axis = outward shell normal at the tet centroid
     n_c = _ellipsoid_normal(cent * 0 + _project_to_outer(cent, axes), axes)
     up = np.where(np.abs(n_c[:, 1:2]) < 0.9, np.array([[0.0, 1.0, 0.0]]),
@@ -343,7 +398,8 @@ def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int
     return Scene(name=f"face_{n_theta}x{n_phi}x{n_layers}_s{seed}", X=X,
                  tets=tets.astype(np.int32), dirichlet=dirichlet, region=region,
                  surf_tris=surf, act_a=act_a, act_R=act_R, frames=frames, iters=iters,
-                 meta={"seed": seed, "slits": [(s["name"], s["row"], s["cols"]) for s in slit_info]})
+                 meta={"seed": seed, "slits": [(s["name"], s["row"], s["cols"]) for s in slit_info],
+                       "ijk": ijk.astype(np.int32), "keyframes": keys})
 
 
 def _project_to_outer(P, axes):
@@ -351,6 +407,43 @@ def _project_to_outer(P, axes):
     a, b, c = axes
     s = np.sqrt((P[:, 0] / a) ** 2 + (P[:, 1] / b) ** 2 + (P[:, 2] / c) ** 2)
     return P / s[:, None]
+
+
+def closed_slit_state(scene: Scene, gap: float, seed: int = 0, jitter: float = 0.0,
+                      falloff_rows: int = 6) -> np.ndarray:
+    """A contact state of a face-like scene made by moving material, not by
+    solving: the upper wall of every slit is carried toward the lower wall
+    until the walls are ``gap`` apart in the middle of the slit.
+
+    For a vertex on grid row j >= row + 1 of a slit (row = the removed hex
+    row) and on one of the slit's columns, the displacement is
+    s(i) w(j) (1 - gap / h) (X(i, row, k) - X(i, row + 1, k)), with h the
+    wall distance at that column and layer, s(i) a smooth bump that is 1 in the
+    middle of the slit and 0 at its ends, and w(j) falling linearly from 1 on
+    the wall to 0 ``falloff_rows`` rows above it.  Fixed vertices do not move.
+    ``jitter`` adds a seeded uniform perturbation to the moved vertices.
+    """
+    ijk = scene.meta["ijk"]
+    key = {tuple(v): q for q, v in enumerate(ijk.tolist())}
+    x = scene.X.copy()
+    rng = np.random.default_rng(seed)
+    for _, row, (i0, i1) in scene.meta["slits"]:
+        for q, (i, j, k) in enumerate(ijk.tolist()):
+            if j < row + 1 or not (i0 <= i <= i1) or scene.dirichlet[q]:
+                continue
+            lo, up = key.get((i, row, k)), key.get((i, row + 1, k))
+            if lo is None or up is None:
+                continue
+            d = scene.X[lo] - scene.X[up]
+            h = float(np.linalg.norm(d))
+            u = (i - i0) / max(i1 - i0, 1)
+            s_i = np.sin(np.pi * u) ** 2
+            w_j = max(0.0, 1.0 - (j - row - 1) / falloff_rows)
+            x[q] += s_i * w_j * (1.0 - gap / h) * d
+    if jitter > 0:
+        moved = np.any(x != scene.X, axis=1)
+        x[moved] += rng.uniform(-jitter, jitter, (int(moved.sum()), 3))
+    return x
 
 
 # --------------------------------------------------------------------------
@@ -375,24 +468,45 @@ def keyframe_sequence(fields: list[np.ndarray], per_segment: int) -> list[np.nda
 # --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
-def scene_by_name(name: str, seed: int = 0) -> Scene:
-    """Named workloads: 'slabs', 'face50k', 'face250k', 'face5k', 'face20k', 'face100k', 'tiny'."""
+# Grading of the face-like grids toward the slits (cells 5x finer along the
+# slit and 3x across it near the slit centres), and the number of layers
+# through the 2 cm shell: together they put about 2% of the vertices on the
+# slit walls of the 50k face, the contact level its workload calls for.
+FACE_GRADE = (5.0, 0.3, 3.0, 0.2)
+FACE_LAYERS = 10
+# Peak bump height of the actuation fields (before the 0.35 cap), tuned once
+# per workload so that the slits close; the values are frozen here.
+FACE_BUMP = {"face5k": 0.6, "face20k": 0.6, "face50k": 0.6, "face100k": 0.6, "face250k": 0.6}
+THREE_SLITS = (("mouth", 0.0, -0.35, 0.06), ("eye_l", -0.45, 0.35, 0.035), ("eye_r", 0.45, 0.35, 0.035))
+
+
+def scene_by_name(name: str, seed: int = 0, bump_height: float | None = None) -> Scene:
+    """Named workloads: 'slabs', 'tiny', 'face5k', 'face20k', 'face50k',
+    'face100k', 'face250k'.
+
+    face50k: 96 x 48 x 10 graded hexes (n = 52 283, m = 273 240), mouth slit,
+    collision region within 3 cm of the slit (n2 = 3684 free proxy vertices),
+    a 50-frame animation from rest through 4 keyframe fields, 30 iterations
+    per frame.  face250k: 190 x 125 x 10 (n = 264 726), mouth and two eyelid
+    slits, region within 1.2 cm (n2 = 12 096), 60 frames through 4 keyframes,
+    40 iterations per frame.  face5k/20k/100k: the serving sizes, 10-frame
+    ramps of one field.
+    """
     if name == "slabs":
         return slabs(seed=seed)
     if name == "tiny":
         return slabs(seed=seed, nx=3, ny=3, nz=1, gap=1.0e-3, frames=3, iters=10)
+    grids = {"face5k": (30, 14), "face20k": (60, 30), "face50k": (96, 48), "face100k": (136, 68),
+             "face250k": (190, 125)}
+    if name not in grids:
+        raise KeyError(name)
+    nt, nph = grids[name]
+    h = FACE_BUMP[name] if bump_height is None else bump_height
+    kw = dict(seed=seed, n_layers=FACE_LAYERS, grade=FACE_GRADE, region_radius=0.03, bump_height=h)
     if name == "face50k":
-        return face_like(101, 101, 4, seed=seed)
-    if name == "face5k":
-        return face_like(31, 31, 4, seed=seed)
-    if name == "face20k":
-        return face_like(62, 62, 4, seed=seed)
-    if name == "face100k":
-        return face_like(140, 140, 4, seed=seed)
+        kw.update(frames=50, keyframes=4)
     if name == "face250k":
         # region radius 1.2 cm keeps the dense inverse Schur complement at
-        # n2 ~ 14k (1.5 GB); 2.5 cm would give n2 ~ 54k (23 GB)
-        return face_like(229, 229, 4, seed=seed, iters=40, frames=60, region_radius=0.012,
-                         slits=(("mouth", 0.0, -0.35, 0.06), ("eye_l", -0.45, 0.35, 0.035),
-                                ("eye_r", 0.45, 0.35, 0.035)))
-    raise KeyError(name)
+        # n2 ~ 12k (1.2 GB)
+        kw.update(iters=40, frames=60, keyframes=4, region_radius=0.012, slits=THREE_SLITS)
+    return face_like(nt, nph, **kw)

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FrameStats, MeshDesc, Options, PdipcError, check, lib
+from ._lib import FrameStats, IterTrace, MeshDesc, Options, PdipcError, check, lib
 
 __all__ = ["Solver", "PdipcError", "FP64", "MIXED_FP32", "host_factor_solve", "actuation_rows", "PDIPCFrame",
            "dense_spd"]
@@ -43,7 +43,7 @@ class Solver:
     def __init__(self, scene=None, *, X=None, tets=None, dirichlet=None, surf_tris=None, region=None,
                  youngs=1e4, poisson=0.45, dhat=5e-4, kappa=1e3, iters=30, tol=0.0, precision=FP64,
                  ccd_eta=0.1, ccd_steps=16, ls_max_halvings=20, cinv_updates_max=16,
-                 fp32_reduced_min=2049, hinv_rows_mb=4096, device="cuda", stream=None):
+                 fp32_reduced_min=2049, hinv_rows_mb=4096, device="cuda", stream=None, W=None):
         if scene is not None:
             X, tets, dirichlet, surf_tris = scene.X, scene.tets, scene.dirichlet, scene.surf_tris
             region = scene.region
@@ -58,6 +58,16 @@ class Solver:
         md = MeshDesc(self.n, self.m, self._X.ctypes.data, self._tets.ctypes.data, self._dir.ctypes.data,
                       self._tris.shape[0], self._tris.ctypes.data if self._tris.size else None,
                       self._reg.ctypes.data if self._reg is not None else None, float(youngs), float(poisson))
+        if W is not None:
+            # proxy embedding s = W x as CSR (rowptr, col, val or None); the
+            # triangles then index proxy vertices (rows of W)
+            rowptr, col, val = W
+            self._W = (np.ascontiguousarray(rowptr, dtype=np.int32), np.ascontiguousarray(col, dtype=np.int32),
+                       None if val is None else np.ascontiguousarray(val, dtype=np.float64))
+            md.n_surf_verts = self._W[0].size - 1
+            md.W_rowptr = self._W[0].ctypes.data
+            md.W_col = self._W[1].ctypes.data
+            md.W_val = self._W[2].ctypes.data if self._W[2] is not None else None
         with torch.cuda.device(self.device):
             st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = st
@@ -134,6 +144,14 @@ class Solver:
         buf = torch.empty(max(k, 1) * 3, dtype=torch.int32, device=self.device)
         check(lib().pdipc_debug_contacts(self._h, _dev(x, (self.n, 3)), buf.data_ptr(), k, C.byref(cnt)), self._h)
         return buf[: 3 * k].reshape(k, 3).cpu().numpy()
+
+    def trace(self):
+        """Per-iteration records of the last frame (list of dicts)."""
+        cnt = C.c_int32()
+        check(lib().pdipc_debug_trace(self._h, None, 0, C.byref(cnt)), self._h)
+        buf = (IterTrace * max(cnt.value, 1))()
+        check(lib().pdipc_debug_trace(self._h, buf, cnt.value, C.byref(cnt)), self._h)
+        return [buf[i].as_dict() for i in range(cnt.value)]
 
     def debug_step(self, x: torch.Tensor):
         dx = torch.empty(self.n, 3, dtype=torch.float64, device=self.device)

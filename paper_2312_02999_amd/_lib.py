@@ -27,6 +27,7 @@ EXPORTS = [
     "pdipc_solve_frame", "pdipc_solve_frame_backward", "pdipc_get_sizes", "pdipc_destroy",
     "pdipc_last_error", "pdipc_debug_local", "pdipc_debug_contacts", "pdipc_debug_step",
     "pdipc_debug_host_factor", "pdipc_kernel_timer", "pdipc_debug_dense", "pdipc_device_bytes",
+    "pdipc_debug_trace",
 ]
 
 
@@ -34,7 +35,8 @@ class MeshDesc(C.Structure):
     _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("rest_pos", C.c_void_p),
                 ("tets", C.c_void_p), ("dirichlet", C.c_void_p), ("n_surf_tris", C.c_int32),
                 ("surf_tris", C.c_void_p), ("region", C.c_void_p), ("youngs", C.c_double),
-                ("poisson", C.c_double)]
+                ("poisson", C.c_double), ("n_surf_verts", C.c_int32), ("W_rowptr", C.c_void_p),
+                ("W_col", C.c_void_p), ("W_val", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -49,11 +51,21 @@ class FrameStats(C.Structure):
                 ("ls_halvings", C.c_int32), ("ls_failures", C.c_int32), ("refine_steps", C.c_int32),
                 ("n_candidates", C.c_int32), ("refine_fallbacks", C.c_int32), ("cinv_rebuilds", C.c_int32),
                 ("c_delta_max", C.c_int32), ("c_delta_sum", C.c_int32), ("cinv_updates", C.c_int32),
+                ("near_ties", C.c_int32), ("pcg_iters", C.c_int32),
                 ("alpha_m_min", C.c_double),
                 ("alpha_min", C.c_double),
                 ("energy", C.c_double), ("grad_inf", C.c_double), ("ms_ipc", C.c_double),
                 ("ms_gstep", C.c_double), ("ms_ccd", C.c_double), ("ms_ls", C.c_double),
                 ("ms_misc", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IterTrace(C.Structure):
+    _fields_ = [("n_pt", C.c_int32), ("n_ee", C.c_int32), ("n_c", C.c_int32), ("n_candidates", C.c_int32),
+                ("ls_halvings", C.c_int32), ("ls_ok", C.c_int32), ("near_ties", C.c_int32),
+                ("refine_steps", C.c_int32), ("alpha_m", C.c_double), ("alpha", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,6 +116,8 @@ def lib():
     L.pdipc_debug_dense.restype = i32
     L.pdipc_device_bytes.argtypes = [vp, C.POINTER(i64)]
     L.pdipc_device_bytes.restype = i32
+    L.pdipc_debug_trace.argtypes = [vp, C.POINTER(IterTrace), i32, C.POINTER(i32)]
+    L.pdipc_debug_trace.restype = i32
     _lib = L
     return L
 

@@ -22,6 +22,10 @@ SOURCES = ["k_local.hip", "k_util.hip", "k_contact.hip", "k_barrier.hip", "k_fac
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wno-unused-result",
           "-I", os.path.join(HERE, "..", "include")]
+# Sources whose floating point decides a discrete result (constraint-set
+# membership, the closest feature of a pair): every product and sum rounded on
+# its own, so that the decision follows the written formula bit for bit.
+NO_CONTRACT = {"k_contact.hip", "k_barrier.hip"}
 
 
 def _hipcc() -> str:
@@ -35,7 +39,8 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [_hipcc(), "-x", "hip", *COMMON, *DEVICE_FLAGS, "-c", path, "-o", obj]
+        extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+        cmd = [_hipcc(), "-x", "hip", *COMMON, *DEVICE_FLAGS, *extra, "-c", path, "-o", obj]
     else:
         cmd = [_hipcc(), *COMMON, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -11,8 +11,14 @@
 // Degenerate systems (|n|^2 <= 1e-12 |e1|^2 |e2|^2) skip the interior
 // candidate; for parallel segments the minimum is at an endpoint anyway.
 //
-// Inputs are local points relative to a reference point (taken in FP64 by
-// the caller), so the squared distance keeps its relative accuracy.
+// Decisions (d^2 < dhat^2 for the constraint set, the intersection check)
+// take the points in absolute FP64 coordinates (load_pair_abs) and evaluate
+// every product and sum separately rounded, in the order written here (the
+// files that hold them are built without floating-point contraction), so
+// that the same positions give the same squared distance, bit for bit, as a
+// plain evaluation of these formulas.  The barrier derivatives take points
+// relative to the pair's first point (load_pair_rel), which keeps the
+// relative accuracy of FP32 evaluations.
 #pragma once
 #include "common.h"
 
@@ -31,6 +37,8 @@ struct Feature {
   T d2;
 };
 
+// Closest point of the closed segment [a, b] to p: q = a + t (b - a) with t
+// clamped to [0, 1]; d2 = |p - q|^2.
 template <typename T>
 __device__ __forceinline__ T seg_param(const T* p, const T* a, const T* b, T& d2) {
   T ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
@@ -38,8 +46,9 @@ __device__ __forceinline__ T seg_param(const T* p, const T* a, const T* b, T& d2
   T L2 = dot3(ab, ab);
   T t = L2 > T(0) ? dot3(ap, ab) / L2 : T(0);
   t = fmin(fmax(t, T(0)), T(1));
-  T q[3] = {ap[0] - t * ab[0], ap[1] - t * ab[1], ap[2] - t * ab[2]};
-  d2 = dot3(q, q);
+  T q[3] = {a[0] + t * ab[0], a[1] + t * ab[1], a[2] + t * ab[2]};
+  T r[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+  d2 = dot3(r, r);
   return t;
 }
 
@@ -169,6 +178,14 @@ __device__ __forceinline__ T pair_dist2(bool is_pt, const T P[4][3]) {
   Feature<T> f;
   pair_feature(is_pt, P, f);
   return f.d2;
+}
+
+// Load the 4 points of a pair in absolute coordinates (decisions).
+__device__ __forceinline__ void load_pair_abs(const int32_t* v4, const double* __restrict__ x, double P[4][3]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) P[k][r] = x[3 * v4[k] + r];
 }
 
 // Load the 4 points of a pair relative to its first point (FP64 difference).

@@ -259,7 +259,7 @@ __device__ __forceinline__ int32_t query_test(const QueryArgs& qa, const QueryCt
   }
   if (qa.dist) {
     double P[4][3];
-    load_pair_rel(v4, qa.x, P);
+    load_pair_abs(v4, qa.x, P);
     const double d2 = pair_dist2<double>(c.is_pt, P);
     if (!(d2 < qa.dhat * qa.dhat)) return -1;
   }
@@ -413,17 +413,24 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
 // Candidates swept over x_prev -> x_prev + dx contain every pair within dhat at
 // any x_prev + alpha dx, alpha in [0, 1]; filtering them by the exact distance
 // at the new iterate gives the same sorted set as a fresh broad phase.
+// Near ties: candidates with |d - dhat| below kNearTie dhat, where a rounding
+// difference in the positions could flip membership (|d^2 - dhat^2| is about
+// 2 dhat |d - dhat|); counted with integer atomics for the frame statistics.
+constexpr double kNearTie = 1e-10;
+
 __global__ void __launch_bounds__(BT) active_flag_kernel(const int32_t* __restrict__ v4all, int32_t npairs,
                                                          int32_t n_pt, const double* __restrict__ x, double dhat,
-                                                         int32_t* __restrict__ flag) {
+                                                         int32_t* __restrict__ flag, int32_t* __restrict__ near) {
   int32_t k = blockIdx.x * BT + threadIdx.x;
   if (k > npairs) return;
   if (k == npairs) { flag[k] = 0; return; }
   int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
   double P[4][3];
-  load_pair_rel(v4, x, P);
+  load_pair_abs(v4, x, P);
   double d2 = pair_dist2<double>(k < n_pt, P);
-  flag[k] = d2 < dhat * dhat ? 1 : 0;
+  const double dh2 = dhat * dhat;
+  flag[k] = d2 < dh2 ? 1 : 0;
+  if (fabs(d2 - dh2) < 2.0 * kNearTie * dh2) atomicAdd(near, 1);
 }
 
 __global__ void __launch_bounds__(BT) compact_pairs_kernel(PairList src, int32_t npairs, const int32_t* __restrict__ flag,
@@ -440,21 +447,23 @@ __global__ void __launch_bounds__(BT) compact_pairs_kernel(PairList src, int32_t
 
 int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const double* x, double dhat, PairList& out,
                   int32_t* flag, int32_t* pos, int32_t* d_tot, int32_t* h_tot, void* scan_temp, int32_t* n_pt,
-                  int32_t* n_ee, hipStream_t st, int64_t* needed) {
+                  int32_t* n_ee, hipStream_t st, int64_t* needed, int32_t* near_ties) {
   *needed = 0;
+  if (near_ties) *near_ties = 0;
   if (ncand <= 0) {
     *n_pt = 0;
     *n_ee = 0;
     return 0;
   }
-  active_flag_kernel<<<grid_for(ncand + 1, BT), BT, 0, st>>>(cand.v4, ncand, cand_pt, x, dhat, flag);
+  launch_fill_i32(d_tot + 2, 1, 0, st);
+  active_flag_kernel<<<grid_for(ncand + 1, BT), BT, 0, st>>>(cand.v4, ncand, cand_pt, x, dhat, flag, d_tot + 2);
   {
     // active positions; the position of the first EE candidate is the PT count
     const ScanJob job{flag, pos, ncand + 1, d_tot, nullptr, cand_pt, d_tot + 1};
     launch_exclusive_scans(&job, 1, scan_temp, st);
   }
   int32_t* h = h_tot;
-  hipMemcpyAsync(h, d_tot, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st);
+  hipMemcpyAsync(h, d_tot, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
   if (h[0] > out.cap) {
     *needed = h[0];
@@ -462,6 +471,7 @@ int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const do
   }
   *n_pt = h[1];
   *n_ee = h[0] - h[1];
+  if (near_ties) *near_ties = h[2];
   if (h[0] > 0) compact_pairs_kernel<<<grid_for(ncand, BT), BT, 0, st>>>(cand, ncand, flag, pos, out);
   return 0;
 }
@@ -583,7 +593,7 @@ __global__ void __launch_bounds__(BT) pair_d2_kernel(const int32_t* __restrict__
   if (k >= npairs) return;
   int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
   double P[4][3];
-  load_pair_rel(v4, x, P);
+  load_pair_abs(v4, x, P);
   out[k] = pair_dist2<double>(k < n_pt, P);
 }
 

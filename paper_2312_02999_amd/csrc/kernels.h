@@ -129,7 +129,7 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
 // h_tot: pinned host memory for the two counts read back
 int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const double* x, double dhat, PairList& out,
                   int32_t* flag, int32_t* pos, int32_t* d_tot, int32_t* h_tot, void* scan_temp, int32_t* n_pt,
-                  int32_t* n_ee, hipStream_t st, int64_t* needed);
+                  int32_t* n_ee, hipStream_t st, int64_t* needed, int32_t* near_ties);
 
 // CCD: t_k per candidate pair (conservative advancement), then alpha_m.
 // per-candidate bounds t_out and per-block minima part; returns the blocks.

@@ -10,6 +10,7 @@
 // All state stays in device memory; the host reads back only the pair
 // counts, n_c, the factorization status, alpha_m and the line-search sign.
 #include "../../include/pdipc.h"
+#include "../../include/pdipc_debug.h"
 
 #include <hip/hip_runtime.h>
 
@@ -169,9 +170,19 @@ struct Solver {
   size_t ev_used = 0;
   double timer_ms = 0.0;
   int64_t timer_count = 0;
+  // Table 1 stage boundaries of one iteration on the main stream (recorded
+  // while a frame collects statistics): start, IPC done (constraint set,
+  // barrier, incidence), local step and gradient done (Misc), global step
+  // done, CCD done, line search done
+  hipEvent_t sev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool stage_on = false;
+  // per-iteration record of the last frame (pdipc_debug_trace)
+  std::vector<pdipc_iter_trace> trace;
 
   ~Solver() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : sev)
+      if (e) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_cinv) (void)hipEventDestroy(ev_cinv);
@@ -223,6 +234,10 @@ static bool timer_events(Solver* S, int which, hipEvent_t* e0, hipEvent_t* e1) {
   *e1 = S->ev_pool[S->ev_used + 1];
   S->ev_used += 2;
   return true;
+}
+
+static void stage_mark(Solver* S, int k) {
+  if (S->stage_on) HIPCHK(hipEventRecord(S->sev[k], S->st));
 }
 
 static void harvest_timer(Solver* S) {
@@ -309,6 +324,39 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   const int32_t F = md->n_surf_tris;
   if (F < 0 || (F > 0 && !md->surf_tris)) fail(PDIPC_E_INVALID, "bad proxy triangles");
   std::vector<int32_t> tris(md->surf_tris, md->surf_tris + 3LL * std::max(F, 0));
+  if (md->W_rowptr) {
+    // s = W x (Section 3.1): validate the CSR rows, then resolve the
+    // triangles' proxy-vertex ids to the simulation vertices W selects
+    const int32_t ns = md->n_surf_verts;
+    if (ns <= 0 || !md->W_col || md->W_rowptr[0] != 0) fail(PDIPC_E_INVALID, "bad proxy embedding W");
+    std::vector<int32_t> pick(ns), seen(n, -1);
+    for (int32_t r = 0; r < ns; ++r) {
+      const int32_t b = md->W_rowptr[r], e = md->W_rowptr[r + 1];
+      if (e <= b) fail(PDIPC_E_INVALID, "empty row in the proxy embedding W");
+      double sum = 0.0;
+      for (int32_t k = b; k < e; ++k) {
+        const int32_t c = md->W_col[k];
+        const double wv = md->W_val ? md->W_val[k] : 1.0;
+        if (c < 0 || c >= n) fail(PDIPC_E_INVALID, "proxy embedding W column out of range");
+        if (!(wv >= 0.0) || !std::isfinite(wv)) fail(PDIPC_E_INVALID, "negative or non-finite weight in W");
+        for (int32_t k2 = b; k2 < k; ++k2)
+          if (md->W_col[k2] == c) fail(PDIPC_E_INVALID, "repeated column in a row of W");
+        sum += wv;
+      }
+      if (!(std::fabs(sum - 1.0) <= 1e-12)) fail(PDIPC_E_INVALID, "a row of W does not sum to 1");
+      if (e - b != 1)
+        fail(PDIPC_E_INVALID, "proxy vertex " + std::to_string(r) +
+                                  " interpolates several vertices: only embedding by selection is supported");
+      const int32_t c = md->W_col[b];
+      if (seen[c] >= 0) fail(PDIPC_E_INVALID, "two proxy vertices select the same simulation vertex");
+      seen[c] = r;
+      pick[r] = c;
+    }
+    for (int32_t& v : tris) {
+      if (v < 0 || v >= ns) fail(PDIPC_E_INVALID, "proxy triangle index out of range");
+      v = pick[v];
+    }
+  }
   for (int32_t v : tris)
     if (v < 0 || v >= n) fail(PDIPC_E_INVALID, "proxy triangle index out of range");
   for (int32_t f = 0; f < F; ++f)
@@ -435,6 +483,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   HIPCHK(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S->ev_cinv, hipEventDisableTiming));
+  for (hipEvent_t& e : S->sev) HIPCHK(hipEventCreate(&e));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_counts), 8 * sizeof(int32_t), hipHostMallocDefault));
 
@@ -663,7 +712,7 @@ static void pairs(Solver* S, bool active, const double* xx, const double* dxx, i
 
 // Constraint set from the previous step's swept candidates (same sorted set as
 // a fresh broad phase at any point of that step).
-static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee) {
+static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee, int32_t* near_ties) {
   PairList& pl = S->act;
   if (pl.cap == 0) grow_pairs(S, pl, S->act_type, S->act_i, S->act_j, S->act_v4, 4LL * S->nsv + 1024);
   S->cflagbuf.ensure(S->cand_n + 1);
@@ -673,7 +722,7 @@ static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee) {
   for (int attempt = 0; attempt < 3; ++attempt) {
     int64_t need = 0;
     int rc = filter_active(S->cand, S->cand_n, S->cand_pt, S->x.p, S->opt.dhat, pl, S->cflagbuf.p, S->cposbuf.p,
-                           S->totals.p + 4, S->h_counts + 4, S->scan_tmp.p, npt, nee, S->st, &need);
+                           S->totals.p + 4, S->h_counts + 4, S->scan_tmp.p, npt, nee, S->st, &need, near_ties);
     if (rc == 0) return;
     grow_pairs(S, pl, S->act_type, S->act_i, S->act_j, S->act_v4, need);
   }
@@ -712,7 +761,7 @@ struct IterOut;
 static void finish_readback(Solver* S, IterOut& io);
 
 struct IterOut {
-  int32_t npt = 0, nee = 0, nc = 0, ncand = 0, halvings = 0;
+  int32_t npt = 0, nee = 0, nc = 0, ncand = 0, halvings = 0, near_ties = 0;
   bool ls_ok = true;
   bool c_same = false;          // contact set equal to the one C^-1 was built for
   bool nc_pending = false;      // n_c (and c_same) still in flight to h_scal
@@ -766,7 +815,7 @@ static void cinv_begin_pass(Solver* S) {
 static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool defer = false) {
   const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
   hipStream_t st = S->st;
-  if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee);
+  if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee, &io.near_ties);
   else pairs(S, true, S->x.p, nullptr, &io.npt, &io.nee);
   const int32_t np = io.npt + io.nee;
   ensure_pair_arrays(S, np);
@@ -798,6 +847,7 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
                         st));
   HIPCHK(hipEventRecord(S->ev_fork, st));
   io.nc_pending = true;
+  stage_mark(S, 1);
   {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_events(S, TK_LOCAL, &e0, &e1);
@@ -805,6 +855,7 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
   }
   launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
   launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
+  stage_mark(S, 2);
   if (!defer) finish_readback(S, io);
 }
 
@@ -1114,6 +1165,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   // and become no-ops once it is decided; one is queued, then one readback
   // (the first trial is accepted in nearly every iteration: 4 halvings in 240
   // on the 50k face, so a second queued trial costs more than its round trip)
+  stage_mark(S, 4);
   double* ls = S->lsbuf.p;
   launch_ls_init(ls, S->ccd_part.p, nccd, st);
   auto trial = [&]() {
@@ -1139,6 +1191,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
     std::memcpy(hls, S->h_scal, sizeof(double) * LS_SIZE);
     std::memcpy(hinfo, S->h_scal + LS_SIZE, sizeof(int32_t) * 4);
   };
+  stage_mark(S, 5);
   readback();
   if (S->check_info_m && hinfo[0] != 0) fail(PDIPC_E_NOT_SPD, "reduced contact system not SPD");
   if (S->check_info_cs && hinfo[3] != 0) fail(PDIPC_E_NOT_SPD, "contact block of the inverse Schur complement not SPD");
@@ -1154,6 +1207,10 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   io.ls_ok = hls[LS_STATE] == 1.0;
   io.alpha = io.ls_ok ? hls[LS_ALPHA] : 0.0;
   if (apply && reopened && io.alpha > 0.0) launch_axpy_ls(3LL * S->n, ls, S->dx.p, S->x.p, st);
+  if (reopened && S->stage_on) {
+    stage_mark(S, 5);
+    HIPCHK(hipEventSynchronize(S->sev[5]));
+  }
 }
 
 static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdipc_frame_stats* stats) {
@@ -1176,24 +1233,38 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   int32_t rc = PDIPC_OK;
   const bool tol_mode = S->opt.tol > 0;
   double tms[5] = {0, 0, 0, 0, 0};
+  S->stage_on = stats != nullptr;
+  S->trace.clear();
   S->refine_steps = 0;
   S->refine_fallbacks = 0;
   S->cinv_rebuilds = S->c_delta_max = S->c_delta_sum = S->cinv_updates = 0;
   int it = 0;
   for (; it < S->opt.iters; ++it) {
     IterOut io;
-    auto a = std::chrono::steady_clock::now();
+    const int32_t refine_before = S->refine_steps;
+    stage_mark(S, 0);
     assemble_gradient(S, it == 0, io, /*defer=*/true);
-    auto b = std::chrono::steady_clock::now();
     global_step(S, io);
-    if (stats) HIPCHK(hipStreamSynchronize(st));
-    auto c = std::chrono::steady_clock::now();
+    stage_mark(S, 3);
     step_and_search(S, io, true);
-    auto d = std::chrono::steady_clock::now();
-    tms[0] += std::chrono::duration<double, std::milli>(b - a).count();
-    tms[1] += std::chrono::duration<double, std::milli>(c - b).count();
-    tms[3] += std::chrono::duration<double, std::milli>(d - c).count();
+    if (S->stage_on) {
+      // the line-search readback has synchronised past every stage event
+      for (int k = 0; k < 5; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, S->sev[k], S->sev[k + 1]));
+        tms[k] += ms;
+      }
+    }
     HIPCHK(hipGetLastError());
+    {
+      pdipc_iter_trace tr{};
+      tr.n_pt = io.npt; tr.n_ee = io.nee; tr.n_c = io.nc; tr.n_candidates = io.ncand;
+      tr.ls_halvings = io.halvings; tr.ls_ok = io.ls_ok ? 1 : 0; tr.near_ties = io.near_ties;
+      tr.refine_steps = S->refine_steps - refine_before;
+      tr.alpha_m = io.alpha_m; tr.alpha = io.alpha;
+      S->trace.push_back(tr);
+    }
+    fs.near_ties += io.near_ties;
     if (S->timer_which >= 0) {
       HIPCHK(hipStreamSynchronize(st));
       harvest_timer(S);
@@ -1225,12 +1296,16 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
   HIPCHK(hipStreamSynchronize(st));
   S->have_solution = true;
   auto t1 = std::chrono::steady_clock::now();
+  S->stage_on = false;
   if (stats) {
+    // Table 1 columns: IPC, Misc (local step, gradient assembly and the
+    // frame's own copies and checks), G-Step, CCD, LS
     fs.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     fs.ms_ipc = tms[0];
-    fs.ms_gstep = tms[1];
-    fs.ms_ls = tms[3];
-    fs.ms_misc = fs.ms_total - tms[0] - tms[1] - tms[3];
+    fs.ms_gstep = tms[2];
+    fs.ms_ccd = tms[3];
+    fs.ms_ls = tms[4];
+    fs.ms_misc = fs.ms_total - tms[0] - tms[2] - tms[3] - tms[4];
     *stats = fs;
   }
   return rc;
@@ -1373,6 +1448,8 @@ int32_t pdipc_set_actuation(void* h, const double* A) {
   Solver* S = static_cast<Solver*>(h);
   if (!S || !A) return PDIPC_E_INVALID;
   return guarded(S, [&] {
+    launch_count_nonfinite(A, 6LL * S->m, S->info.p + 2, S->st);
+    if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite actuation");
     launch_actuation_transpose(S->m, A, S->A.p, S->st);
     HIPCHK(hipStreamSynchronize(S->st));
     S->have_actuation = true;
@@ -1386,6 +1463,12 @@ int32_t pdipc_set_actuation_scalar(void* h, const double* a, const double* R) {
   if (!S || !a) return PDIPC_E_INVALID;
   return guarded(S, [&] {
     if (!R && !S->have_scalar) fail(PDIPC_E_INVALID, "no actuation frames given yet");
+    launch_count_nonfinite(a, S->m, S->info.p + 2, S->st);
+    if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite actuation strength");
+    if (R) {
+      launch_count_nonfinite(R, 9LL * S->m, S->info.p + 2, S->st);
+      if (read_scalar_i(S, S->info.p + 2) != 0) fail(PDIPC_E_INVALID, "non-finite actuation frame");
+    }
     HIPCHK(hipMemcpyAsync(S->a_s.p, a, sizeof(double) * S->m, hipMemcpyDeviceToDevice, S->st));
     if (R) HIPCHK(hipMemcpyAsync(S->R0.p, R, sizeof(double) * 9 * S->m, hipMemcpyDeviceToDevice, S->st));
     launch_actuation_scalar(S->m, S->a_s.p, S->R0.p, S->A.p, S->st);
@@ -1465,6 +1548,15 @@ int32_t pdipc_kernel_timer(void* h, int32_t which, double* total_ms, int64_t* la
   S->timer_ms = 0.0;
   S->timer_count = 0;
   S->ev_used = 0;
+  return PDIPC_OK;
+}
+
+int32_t pdipc_debug_trace(const void* h, pdipc_iter_trace* out, int32_t cap, int32_t* count) {
+  const Solver* S = static_cast<const Solver*>(h);
+  if (!S || cap < 0 || (cap > 0 && !out)) return PDIPC_E_INVALID;
+  const int32_t k = static_cast<int32_t>(S->trace.size());
+  for (int32_t i = 0; i < std::min(k, cap); ++i) out[i] = S->trace[i];
+  if (count) *count = k;
   return PDIPC_OK;
 }
 

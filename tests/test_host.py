@@ -23,7 +23,8 @@ def _lib_or_skip():
 def test_library_exports_every_header_symbol():
     _lib = _lib_or_skip()
     L = _lib.lib()
-    header = open(os.path.join(ROOT, "include", "pdipc.h")).read()
+    import glob
+    header = "".join(open(h).read() for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     names = set(re.findall(r"\b(pdipc_[a-z_]+)\s*\(", header))
     assert names, "no declarations parsed"
     for nm in sorted(names):
@@ -89,3 +90,94 @@ def test_host_factor_rejects_singular_matrix():
     coords = np.stack([np.arange(n), np.zeros(n), np.zeros(n)], axis=1).astype(float)
     with pytest.raises(PdipcError):
         host_factor_solve(n, 0, coords, L.indptr, L.indices, L.data, np.ones(n), leaf=8)
+
+
+# --------------------------------------------------------------------------
+# pdipc_init_mesh validation through the C ABI (host checks that run before
+# any device work, so they need no GPU)
+# --------------------------------------------------------------------------
+def _init_rc(sc, *, tets=None, dirichlet=None, W=None, tris=None, opt_edit=None):
+    import ctypes as C
+    _lib = _lib_or_skip()
+    L = _lib.lib()
+    X = np.ascontiguousarray(sc.X, dtype=np.float64)
+    T = np.ascontiguousarray(sc.tets if tets is None else tets, dtype=np.int32)
+    D = np.ascontiguousarray(sc.dirichlet if dirichlet is None else dirichlet, dtype=np.uint8)
+    F = np.ascontiguousarray(sc.surf_tris if tris is None else tris, dtype=np.int32)
+    md = _lib.MeshDesc(X.shape[0], T.shape[0], X.ctypes.data, T.ctypes.data, D.ctypes.data, F.shape[0],
+                       F.ctypes.data, None, sc.youngs, sc.poisson)
+    keep = []
+    if W is not None:
+        rp, col, val = (np.ascontiguousarray(W[0], dtype=np.int32), np.ascontiguousarray(W[1], dtype=np.int32),
+                        None if W[2] is None else np.ascontiguousarray(W[2], dtype=np.float64))
+        keep += [rp, col, val]
+        md.n_surf_verts, md.W_rowptr, md.W_col = rp.size - 1, rp.ctypes.data, col.ctypes.data
+        md.W_val = val.ctypes.data if val is not None else None
+    op = _lib.Options()
+    L.pdipc_default_options(C.byref(op))
+    if opt_edit:
+        opt_edit(op)
+    h = C.c_void_p()
+    rc = L.pdipc_init_mesh(C.byref(md), C.byref(op), C.byref(h))
+    msg = L.pdipc_last_error(None).decode()
+    assert rc < 0 and not h.value, (rc, msg)      # only failing inputs here: nothing was allocated
+    return rc, msg
+
+
+def test_init_rejects_inverted_rest_tet():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    T = sc.tets.copy()
+    T[3, [1, 2]] = T[3, [2, 1]]
+    rc, msg = _init_rc(sc, tets=T)
+    assert rc == -2 and "tet 3" in msg            # PDIPC_E_DEGENERATE
+
+
+def test_init_rejects_mesh_without_fixed_vertex():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    rc, msg = _init_rc(sc, dirichlet=np.zeros(sc.n, np.uint8))
+    assert rc == -3 and "singular" in msg         # PDIPC_E_NOT_SPD
+
+
+def test_init_rejects_bad_options_and_indices():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    def neg_dhat(op):
+        op.dhat = -1.0
+    assert _init_rc(sc, opt_edit=neg_dhat)[0] == -1
+    T = sc.tets.copy()
+    T[0, 0] = sc.n
+    assert _init_rc(sc, tets=T)[0] == -1
+
+
+def _selection_W(sc):
+    """Proxy vertices = sorted vertex ids of the proxy triangles, W = selection."""
+    sv = np.unique(sc.surf_tris)
+    local = np.searchsorted(sv, sc.surf_tris)
+    return sv, local
+
+
+def test_init_validates_the_proxy_embedding():
+    sc = mg.slabs(0, nx=2, ny=2, nz=1)
+    sv, local = _selection_W(sc)
+    k = sv.size
+    rp = np.arange(k + 1)
+    # a row whose weights do not sum to 1
+    val = np.ones(k)
+    val[2] = 0.9
+    rc, msg = _init_rc(sc, W=(rp, sv, val), tris=local)
+    assert rc == -1 and "sum to 1" in msg
+    # a row interpolating two vertices (barycentric embedding)
+    rp2 = np.concatenate([[0, 2], np.arange(2, k + 1) + 1])
+    col2 = np.concatenate([[sv[0], sv[0] + 1], sv[1:]])
+    val2 = np.concatenate([[0.5, 0.5], np.ones(k - 1)])
+    rc, msg = _init_rc(sc, W=(rp2, col2, val2), tris=local)
+    assert rc == -1 and "selection" in msg
+    # negative weight, column out of range, triangle index beyond the rows
+    val3 = np.ones(k)
+    val3[1] = -0.0 - 1e-3
+    assert _init_rc(sc, W=(rp, sv, val3), tris=local)[0] == -1
+    col4 = sv.copy()
+    col4[0] = sc.n
+    assert _init_rc(sc, W=(rp, col4, None), tris=local)[0] == -1
+    bad = local.copy()
+    bad[0, 0] = k
+    assert _init_rc(sc, W=(rp, sv, None), tris=bad)[0] == -1
