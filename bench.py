@@ -24,12 +24,14 @@ sys.path.insert(0, ROOT)
 K_LOCAL, K_SIGMA_GEMV, K_FWD, K_BWD, K_BARRIER, K_TRIAL, K_RED_CHOL = 0, 1, 2, 3, 4, 5, 6
 
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of MI355X (TFLOP/s) by the reduced factor's type
+MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}
 
-# HBM bytes per local-step launch on face50k from two rocprofv3 counter passes
+# HBM bytes per local-step launch from two rocprofv3 counter passes
 # (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy
-# of known size; valid only for the kernel source they were taken on
-# (profiles/local_step_kernel_face50k_pmc.md).
-LOCAL_STEP_TRAFFIC = {"workload": "face50k", "source_sha256_prefix": "54fa61f8b0518b46", "bytes": 103978783}
+# of known size; valid only for the workload and kernel source they were taken
+# on (profiles/local_step_kernel_face50k_pmc.md).
+LOCAL_STEP_TRAFFIC = {"workload": "face50k-r1", "source_sha256_prefix": "54fa61f8b0518b46", "bytes": 103978783}
 
 
 def measured_traffic(workload: str):
@@ -48,83 +50,157 @@ def progress(msg: str) -> None:
 
 
 def local_step_bytes(n: int, m: int) -> int:
-    """Algorithmic bytes of one local-step launch (FP64 streams).
+    """Algorithmic bytes of one local-step (or line-search trial) launch.
 
-    Per tet: 4 int32 indices, 9 D_m^-1 + 1 weight + 6 actuation doubles in;
-    9 rotation + 1 energy + 12 gradient-share doubles out.  Per vertex: one
-    xyz triple read once.
+    Per tet: 4 int32 indices, 9 D_m^-1 + 1 weight + 6 actuation doubles read
+    once (144 B).  Per vertex: one xyz triple in and one out (48 B: x and the
+    gradient, or x and the step for a trial).
     """
-    per_tet = 4 * 4 + (9 + 1 + 6) * 8 + (9 + 1 + 12) * 8
-    return m * per_tet + n * 24
+    return m * (4 * 4 + (9 + 1 + 6) * 8) + n * 48
 
 
-def run_precision(sc, precision, steps, warmup, timer_kernel):
+# families timed in replays of the timed frames, with what one timer interval
+# covers: "launch" = one kernel launch, "sweep" = one whole triangular sweep,
+# "factor" = one factorisation of the reduced system
+TIMED_FAMILIES = [("local_step_kernel", K_LOCAL), ("trial_energy_kernel", K_TRIAL),
+                  ("forward sweep (Eq. 7, L1^-1)", K_FWD), ("backward sweep (Eq. 7, L1^-T)", K_BWD),
+                  ("sigma_gemv_kernel", K_SIGMA_GEMV), ("reduced Cholesky (Eq. 11 system)", K_RED_CHOL),
+                  ("barrier_kernel", K_BARRIER)]
+
+
+def run_precision(sc, precision, steps, warmup):
     import torch
     from paper_2312_02999_amd import Solver
+    seq_np = sc.sequence()
+    if warmup + steps > len(seq_np):
+        print(f"warmup + steps = {warmup + steps} exceeds the {len(seq_np)}-frame actuation sequence "
+              f"of this workload: every timed frame must change actuation", file=sys.stderr)
+        sys.exit(2)
     S = Solver(sc, iters=sc.iters, precision=precision)
     progress(f"solver ready ({'mixed' if precision else 'fp64'})")
     dev = "cuda"
     R = torch.from_numpy(np.ascontiguousarray(sc.act_R.reshape(-1, 9))).to(dev)
-    seq = [torch.from_numpy(np.ascontiguousarray(sc.actuation_at((t + 1) / sc.frames))).to(dev)
-           for t in range(sc.frames)]
+    seq = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq_np]
     x = torch.from_numpy(np.ascontiguousarray(sc.X)).to(dev)
     S.set_actuation_scalar(seq[0], R)
-    t = 0
-    for _ in range(warmup):
-        S.set_actuation_scalar(seq[min(t, len(seq) - 1)])
+    for t in range(warmup):
+        S.set_actuation_scalar(seq[t])
         x = S.solve_frame(x)
-        t += 1
     progress("warm-up frames done")
-    S.kernel_timer(timer_kernel)
     lat = []
-    x_start, t_start = x.clone(), t
+    x_start = x.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        S.set_actuation_scalar(seq[min(t, len(seq) - 1)])
+    for t in range(warmup, warmup + steps):
+        S.set_actuation_scalar(seq[t])
         a = time.perf_counter()
         x = S.solve_frame(x)
         lat.append(time.perf_counter() - a)
-        t += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     progress(f"{steps} timed frames in {wall:.2f} s")
-    k_ms, k_count = S.kernel_timer(-1)
-    # counters and per-stage times from an untimed replay of the same frames
-    # (stage timing synchronises after the global step)
-    stats = []
-    xs, t = x_start, t_start
-    for _ in range(steps):
-        S.set_actuation_scalar(seq[min(t, len(seq) - 1)])
-        xs, st = S.solve_frame(xs, stats=True)
-        stats.append(st)
-        t += 1
+
+    def replay(with_stats):
+        xs, out = x_start, []
+        for t in range(warmup, warmup + steps):
+            S.set_actuation_scalar(seq[t])
+            if with_stats:
+                xs, st = S.solve_frame(xs, stats=True)
+                out.append((st, S.trace()))
+            else:
+                xs = S.solve_frame(xs)
+        return xs, out
+
+    # counters, per-iteration records and Table 1 stage times from an untimed
+    # replay of the same frames (stage timing synchronises at stage ends)
+    x_replay, stats = replay(True)
+    same = bool(torch.equal(x_replay, x))
+    # per-kernel-family durations: one more replay per family with the
+    # library's HIP-event timer around that family's launches
+    fam = {}
+    for name, k in TIMED_FAMILIES:
+        S.kernel_timer(k)
+        replay(False)
+        ms, cnt = S.kernel_timer(-1)
+        fam[name] = (ms, cnt)
+    progress("replays done")
     sizes = S.sizes()
     dev_bytes = S.device_bytes()
     S.close()
     lat_ms = np.array(lat) * 1e3
+    its = [tr for _, trs in stats for tr in trs]
+    nc_frames = [st["n_c"] for st, _ in stats]
     return {
         "fps": steps / wall, "ms_per_frame": 1e3 * wall / steps,
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-        "kernel_ms_total": k_ms, "kernel_launches": k_count, "sizes": sizes, "device_bytes": dev_bytes,
-        "n_c_max": max(s["n_c"] for s in stats), "n_pt_last": stats[-1]["n_pt"], "n_ee_last": stats[-1]["n_ee"],
-        "ls_failures": sum(s["ls_failures"] for s in stats),
-        "refine_steps": sum(s["refine_steps"] for s in stats),
-        "refine_fallbacks": sum(s["refine_fallbacks"] for s in stats),
-        "cinv_rebuilds": sum(s["cinv_rebuilds"] for s in stats),
-        "c_delta_max": max(s["c_delta_max"] for s in stats),
-        "c_delta_sum": sum(s["c_delta_sum"] for s in stats),
-        "stage_ms": {k: float(np.mean([s[k] for s in stats])) for k in ("ms_ipc", "ms_gstep", "ms_ls", "ms_misc")},
+        "families": fam, "iters_total": len(its), "sizes": sizes, "device_bytes": dev_bytes,
+        "replay_bitwise_equal": same,
+        "n_c_max": int(max(nc_frames)), "n_c_mean": float(np.mean([tr["n_c"] for tr in its])),
+        "contact_iters": int(sum(1 for tr in its if tr["n_c"] > 0)),
+        "reduced_flops": float(sum((3.0 * tr["n_c"]) ** 3 / 3.0 for tr in its if tr["n_c"] > 0)),
+        "pairs_max": int(max(tr["n_pt"] + tr["n_ee"] for tr in its)),
+        "ls_failures": sum(st["ls_failures"] for st, _ in stats),
+        "refine_steps": sum(st["refine_steps"] for st, _ in stats),
+        "refine_fallbacks": sum(st["refine_fallbacks"] for st, _ in stats),
+        "cinv_rebuilds": sum(st["cinv_rebuilds"] for st, _ in stats),
+        "near_ties": sum(st["near_ties"] for st, _ in stats),
+        "stage_ms": {k: round(float(np.mean([st[k] for st, _ in stats])), 3)
+                     for k in ("ms_ipc", "ms_gstep", "ms_ccd", "ms_ls", "ms_misc")},
         "x_final": x.cpu().numpy(),
     }
 
 
-def cpu_baseline(sc, budget_s=20.0):
+def rooflines(sc, r, reduced_type):
+    """One roofline entry per timed kernel family: algorithmic work per timer
+    interval over its mean duration."""
+    n2 = r["sizes"]["n2"]
+    nnz = r["sizes"]["factor_nnz"]
+    out = []
+    for name, (ms, cnt) in r["families"].items():
+        if cnt == 0 or ms <= 0:
+            continue
+        avg_s = ms * 1e-3 / cnt
+        e = {"kernel": name, "intervals": cnt, "total_ms": round(ms, 3), "avg_us": round(avg_s * 1e6, 2)}
+        if name in ("local_step_kernel", "trial_energy_kernel"):
+            work = local_step_bytes(sc.n, sc.m)
+            e.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, work_per_interval=work,
+                     work_unit="B", per_unit="144 B/tet + 48 B/vertex")
+            e["achieved"] = work / avg_s / 1e9
+        elif name.startswith("forward sweep") or name.startswith("backward sweep"):
+            # the forward sweep is timed in two parts per iteration
+            per_it = ms * 1e-3 / max(r["iters_total"], 1)
+            work = 12 * nnz
+            e.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, work_per_interval=work, work_unit="B",
+                     per_unit="12 B per factor nonzero (value + index), 3 right-hand sides per read",
+                     avg_us=round(per_it * 1e6, 2), intervals=r["iters_total"])
+            e["achieved"] = work / per_it / 1e9
+        elif name == "sigma_gemv_kernel":
+            work = 8 * n2 * (n2 + 1) // 2
+            e.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, work_per_interval=work, work_unit="B",
+                     per_unit="8 B per entry of the packed symmetric n2 x n2 inverse Schur complement")
+            e["achieved"] = work / avg_s / 1e9
+        elif name.startswith("reduced Cholesky"):
+            flops_per = r["reduced_flops"] / max(cnt, 1)
+            e.update(bound="mfma", unit="TFLOP/s", peak=MFMA_PEAK_TFS[reduced_type],
+                     work_per_interval=flops_per, work_unit="flop", per_unit="(3 n_c)^3 / 3 per factorisation",
+                     dtype=reduced_type)
+            e["achieved"] = flops_per / avg_s / 1e12
+        else:
+            e.update(bound="alu")
+        if "achieved" in e:
+            e["achieved"] = round(e["achieved"], 3)
+            e["frac"] = round(e["achieved"] / e["peak"], 4)
+        out.append(e)
+    return out
+
+
+def cpu_baseline(sc, a, budget_s=20.0):
     """The oracle (as it stands) on a bounded sample: whole Algorithm-1
-    iterations from the rest state at full actuation until ~budget_s."""
+    iterations from the rest state at the actuation ``a`` of the first timed
+    frame, until ~budget_s (at most 4 iterations)."""
     from oracle import fem, solver as osolver
     prob = osolver.setup_scene(sc)
-    A = fem.actuation_matrices(sc.act_a, sc.act_R)
+    A = fem.actuation_matrices(a, sc.act_R)
     x = sc.X.copy()
     c0 = os.times()
     t0 = time.perf_counter()
@@ -142,7 +218,8 @@ def cpu_baseline(sc, budget_s=20.0):
     # thread; SuperLU does not)
     return {"value": 1.0 / (sec_per_it * sc.iters), "unit": "frames/s", "cores": round(busy / wall, 2),
             "kind": "oracle", "host_cpus": os.cpu_count(),
-            "sample": f"{its} oracle iteration(s) of the {sc.n}-vertex workload from rest at full actuation, "
+            "sample": f"{its} oracle iteration(s) of the {sc.n}-vertex workload from rest at the first timed frame's "
+                      f"actuation, "
                       f"scaled to {sc.iters} iterations/frame ({sec_per_it:.2f} s/iteration)"}
 
 
@@ -202,11 +279,21 @@ def run_adjoint(sc, n_targets=500, n_dirs=2, n_params=4, h_dir=1e-4, seed=1):
             "checks": [{"kind": k, "index": i, "adjoint": ad, "fd": fd} for k, i, ad, fd in errs]}
 
 
+def summary(r):
+    keys = ("n_c_max", "n_c_mean", "contact_iters", "iters_total", "pairs_max", "ls_failures", "refine_steps",
+            "refine_fallbacks", "cinv_rebuilds", "near_ties", "stage_ms", "replay_bitwise_equal", "device_bytes")
+    out = {"value": round(r["fps"], 3), "ms_per_step": round(r["ms_per_frame"], 3),
+           "p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3)}
+    out.update({k: r[k] for k in keys})
+    out["n_c_mean"] = round(out["n_c_mean"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="face50k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
@@ -239,46 +326,48 @@ def main():
         print(json.dumps(run_adjoint(sc)))
         return
     if args.only:
-        r = run_precision(sc, FP64 if args.only == "fp64" else MIXED_FP32, args.steps, args.warmup, K_LOCAL)
+        prec = FP64 if args.only == "fp64" else MIXED_FP32
+        r = run_precision(sc, prec, args.steps, args.warmup)
         r.pop("x_final")
-        print(json.dumps({"only": args.only, **r}))
+        out = {"only": args.only, **summary(r), "rooflines": rooflines(sc, r, "f64")}
+        print(json.dumps(out))
         return
-    fp64 = run_precision(sc, FP64, args.steps, args.warmup, K_LOCAL)
-    mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup, K_LOCAL)
+    fp64 = run_precision(sc, FP64, args.steps, args.warmup)
+    mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup)
     diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
     mixed_vs_fp64 = float(np.abs(mixed["x_final"] - fp64["x_final"]).max() / diag)
-
-    avg_ms = fp64["kernel_ms_total"] / max(fp64["kernel_launches"], 1)
-    nbytes = local_step_bytes(sc.n, sc.m)
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    # avg_launch_us: events stamped by the dispatch itself (extended launch) on
-    # the solver's stream, every local-step launch of the timed FP64 frames
-    roof = {"bound": "hbm", "kernel": "local_step_kernel<double>", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload),
-            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": fp64["kernel_launches"],
-            "algorithmic_bytes": nbytes}
+    # the mixed path factors the reduced system in FP32 from 2049 unknowns on
+    red_type = "f32" if 3 * mixed["n_c_mean"] >= 2049 else "f64"
+    roofs_fp64 = rooflines(sc, fp64, "f64")
+    roofs_mixed = rooflines(sc, mixed, red_type)
+    # the headline's roofline: the mixed path's kernel family with the most
+    # time in the timed frames
+    dom = max(roofs_mixed, key=lambda e: e["total_ms"])
+    roof = {"bound": dom["bound"], "kernel": dom["kernel"], "achieved": dom.get("achieved"),
+            "peak": dom.get("peak"), "unit": dom.get("unit"), "frac": dom.get("frac"),
+            "traffic": measured_traffic(args.workload) if dom["kernel"] == "local_step_kernel" else None,
+            "avg_us": dom["avg_us"], "intervals": dom["intervals"],
+            "work_per_interval": dom.get("work_per_interval"), "per_unit": dom.get("per_unit")}
     if not args.no_cpu_baseline:
         progress("oracle baseline sample")
-    cpu = None if args.no_cpu_baseline else cpu_baseline(sc)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(sc, sc.sequence()[args.warmup])
+    seq_len = len(sc.sequence())
     out = {
         "metric": "PD+IPC frames/s on 50k-vert mesh, mixed vs FP64 GPU; p50/p99 latency",
         "value": round(mixed["fps"], 3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(mixed["ms_per_frame"], 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
         "config": {"workload": f"{args.workload}: face-like shell n={sc.n} m={sc.m}, {sc.iters} iterations/frame, "
-                               f"{sc.frames}-frame actuation ramp",
-                   "n1": fp64["sizes"]["n1"], "n2": fp64["sizes"]["n2"], "factor_nnz": fp64["sizes"]["factor_nnz"]},
+                               f"frames {args.warmup}..{args.warmup + args.steps - 1} of a {seq_len}-frame "
+                               f"keyframed actuation sequence (every timed frame changes actuation)",
+                   "n": sc.n, "m": sc.m, "n1": fp64["sizes"]["n1"], "n2": fp64["sizes"]["n2"],
+                   "factor_nnz": fp64["sizes"]["factor_nnz"],
+                   "contact_frac_max": round(mixed["n_c_max"] / sc.n, 4)},
         "p50_ms": round(mixed["p50_ms"], 3), "p99_ms": round(mixed["p99_ms"], 3),
-        "fp64": {"value": round(fp64["fps"], 3), "ms_per_step": round(fp64["ms_per_frame"], 3),
-                 "p50_ms": round(fp64["p50_ms"], 3), "p99_ms": round(fp64["p99_ms"], 3),
-                 "stage_ms": fp64["stage_ms"], "n_c_max": fp64["n_c_max"], "ls_failures": fp64["ls_failures"],
-                 "cinv_rebuilds": fp64["cinv_rebuilds"], "c_delta_max": fp64["c_delta_max"],
-                 "c_delta_sum": fp64["c_delta_sum"], "device_bytes": fp64["device_bytes"]},
-        "mixed": {"stage_ms": mixed["stage_ms"], "n_c_max": mixed["n_c_max"], "ls_failures": mixed["ls_failures"],
-                  "refine_steps": mixed["refine_steps"], "refine_fallbacks": mixed["refine_fallbacks"],
-                  "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},
+        "fp64": summary(fp64),
+        "mixed": {**summary(mixed), "reduced_factor_type": red_type, "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},
         "roofline": roof,
+        "rooflines": {"mixed": roofs_mixed, "fp64": roofs_fp64},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -1075,6 +1075,7 @@ static void global_step(Solver* S, IterOut& io) {
       // Jacobi-scaled FP32 copy and its factor (refined against FP64 below)
       launch_jacobi_scaling(S->Mred.p, N3, S->scl.p, sd);
       launch_scale_convert_matrix(S->Mred.p, N3, S->scl.p, S->Mf.p, sd);
+      ScopedTimer tm(S, TK_REDUCED_CHOL, sd);
       dense_cholesky_range<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, sd, 0, first_part);
       rest_of_forward();
       dense_cholesky_range<float>(S->Mf.p, N3, S->MLf.p, S->MLif.p, S->info.p + 1, sd, first_part, nlaunch);
