@@ -195,8 +195,37 @@ int32_t pdipc_get_sizes(const void* solver, int64_t* n1, int64_t* n2, int64_t* f
 /* Release everything the solver owns. NULL is allowed. */
 void pdipc_destroy(void* solver);
 
-/* Last error message of a handle (or of the last failed init if NULL). */
+/* Last error message of a handle (or, for NULL, of the last failed
+ * pdipc_init_mesh or pdipc_dense_spd_noalloc call of this thread). */
 const char* pdipc_last_error(const void* solver);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call the allocator): the dense SPD
+ * factorisation, solve and inverse of the reduced contact system, on caller
+ * data, with no allocation of any kind.  Every work buffer lives in one
+ * file-scope device array of the library (about 26 MB per device, held until
+ * the process ends), which limits the order to n <= 1024.
+ *  A       device, n x n float64 row-major, symmetric positive definite
+ *          (lower triangle read); not modified
+ *  b       device, n x nrhs float64 row-major, solved in place (A x = b);
+ *          may be NULL when nrhs = 0.  0 <= nrhs <= 4
+ *  Ainv    device, n x n float64, receives A^-1 (full); may be NULL
+ *  precision  PDIPC_FP64, or PDIPC_MIXED_FP32 (factor, solve and inverse in
+ *          FP32 on a rounded copy; results widened to float64)
+ *  info    device int32 (caller-owned): 0, or 1 + the first column whose
+ *          pivot was not positive (the outputs are then not meaningful)
+ *  stream  hipStream_t the work is queued on (NULL = default stream)
+ * The call only queues work: it returns without waiting, and info is valid
+ * once the stream has reached it.  All calls on one device share the array,
+ * which keeps the last call's contents: calls that overlap on one device (on
+ * different streams or host threads) race and must be serialised by the
+ * caller.  Errors: PDIPC_E_INVALID for n < 1 or n > 1024, a bad nrhs,
+ * precision or NULL pointer (nothing queued); PDIPC_E_HIP when the array's
+ * address or a launch fails.  Same results as pdipc_debug_dense.
+ */
+int32_t pdipc_dense_spd_noalloc(const double* A, int64_t n, double* b, int32_t nrhs, double* Ainv,
+                                int32_t precision, int32_t* info, void* stream);
 
 #ifdef __cplusplus
 }

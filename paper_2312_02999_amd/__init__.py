@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import FrameStats, IterTrace, MeshDesc, Options, PdipcError, check, lib
 
 __all__ = ["Solver", "PdipcError", "FP64", "MIXED_FP32", "host_factor_solve", "actuation_rows", "PDIPCFrame",
-           "dense_spd"]
+           "dense_spd", "dense_spd_noalloc"]
 
 FP64, MIXED_FP32 = 0, 1
 
@@ -189,6 +189,24 @@ def dense_spd(A: torch.Tensor, b: torch.Tensor | None = None, inverse: bool = Fa
     check(lib().pdipc_debug_dense(_dev(A, (n, n)), n, _dev(x) if x is not None else None, nrhs,
                                   _dev(inv) if inv is not None else None, int(precision)), None)
     return x, inv
+
+
+def dense_spd_noalloc(A: torch.Tensor, b: torch.Tensor | None = None, inverse: bool = False,
+                      precision: int = FP64, stream=None):
+    """pdipc_dense_spd_noalloc on device data: returns (x or None, A^-1 or
+    None, info).  The library allocates nothing; the output tensors here are
+    the caller's.  The work is queued on ``stream`` (default: the current
+    stream); info (a one-element int32 device tensor) is 0 on success."""
+    n = A.shape[0]
+    x = None if b is None else b.clone().contiguous()
+    nrhs = 0 if x is None else (1 if x.dim() == 1 else x.shape[1])
+    inv = torch.empty_like(A) if inverse else None
+    info = torch.empty(1, dtype=torch.int32, device=A.device)
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    check(lib().pdipc_dense_spd_noalloc(_dev(A, (n, n)), n, _dev(x) if x is not None else None, nrhs,
+                                        _dev(inv) if inv is not None else None, int(precision), info.data_ptr(),
+                                        C.c_void_p(st.cuda_stream)), None)
+    return x, inv, info
 
 
 def host_factor_solve(n1: int, n2: int, coords1, ptr, col, val, b=None, leaf: int = 96):

@@ -27,7 +27,7 @@ EXPORTS = [
     "pdipc_solve_frame", "pdipc_solve_frame_backward", "pdipc_get_sizes", "pdipc_destroy",
     "pdipc_last_error", "pdipc_debug_local", "pdipc_debug_contacts", "pdipc_debug_step",
     "pdipc_debug_host_factor", "pdipc_kernel_timer", "pdipc_debug_dense", "pdipc_device_bytes",
-    "pdipc_debug_trace",
+    "pdipc_debug_trace", "pdipc_dense_spd_noalloc",
 ]
 
 
@@ -100,6 +100,8 @@ def lib():
     L.pdipc_get_sizes.restype = i32
     L.pdipc_destroy.argtypes = [vp]
     L.pdipc_destroy.restype = None
+    L.pdipc_dense_spd_noalloc.argtypes = [dp, i64, dp, i32, dp, i32, vp, vp]
+    L.pdipc_dense_spd_noalloc.restype = i32
     L.pdipc_last_error.argtypes = [vp]
     L.pdipc_last_error.restype = C.c_char_p
     L.pdipc_debug_local.argtypes = [vp, dp, dp, dp, dp]

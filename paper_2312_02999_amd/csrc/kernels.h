@@ -254,6 +254,9 @@ void launch_build_hinv_rows(const FactorDev& f, double* y, double* sol, double* 
 // c index -> x2 index
 void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
 
+// Message returned by pdipc_last_error(NULL) (this thread).
+void set_last_error(const char* msg);
+
 // ---------------------------------------------------------------- dense SPD
 // Lower Cholesky of an n x n row-major SPD matrix A (destroyed: lower tiles by
 // the factorisation, strictly upper blocks as workspace).  With 32-wide blocks
@@ -263,9 +266,9 @@ void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, in
 // the inverses of the diagonal blocks and solve scratch (4 n).  The strict
 // upper part of F is not written.  *d_info <- 0 ok, else 1 + the first
 // failing column.
-inline int64_t dense_blocks_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
-inline int64_t dense_tmp_offset(int64_t n) { return n * n + n + dense_blocks_size(n); }
-inline int64_t dense_aux_size(int64_t n) { return dense_tmp_offset(n) + 4 * n + 64; }
+constexpr int64_t dense_blocks_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
+constexpr int64_t dense_tmp_offset(int64_t n) { return n * n + n + dense_blocks_size(n); }
+constexpr int64_t dense_aux_size(int64_t n) { return dense_tmp_offset(n) + 4 * n + 64; }
 template <typename T>
 void dense_cholesky(T* A, int64_t n, T* F, T* aux, int32_t* d_info, hipStream_t st);
 // The same factorisation queued in parts: its launches are numbered

@@ -29,6 +29,8 @@ namespace pdipc {
 
 static thread_local std::string g_last_init_error;
 
+void set_last_error(const char* msg) { g_last_init_error = msg; }
+
 #define HIPCHK(expr)                                                   \
   do {                                                                 \
     hipError_t e_ = (expr);                                            \
