@@ -45,6 +45,19 @@ enum {
 
 enum { PDIPC_FP64 = 0, PDIPC_MIXED_FP32 = 1 };
 
+/* Global step (Table 1 configurations with collision):
+ *  PDIPC_GSTEP_SCHUR_WOODBURY  the constant factor, the Schur complement of
+ *                              Eq. (6)-(8) and the low-rank update of Eq. (11)
+ *                              (the method; default)
+ *  PDIPC_GSTEP_PCG             conjugate gradients on (H + kappa B) dx = -g
+ *                              preconditioned by the constant factor L L^T = H
+ *                              (Eq. 5, the paper's baseline); FP64 only
+ *  PDIPC_GSTEP_SCHUR           the Schur complement alone (Section 3.1): the
+ *                              dense Sigma + B_22 (3 n2 unknowns) factored every
+ *                              iteration; FP64 only
+ * All three solve the same system; they differ in cost. */
+enum { PDIPC_GSTEP_SCHUR_WOODBURY = 0, PDIPC_GSTEP_PCG = 1, PDIPC_GSTEP_SCHUR = 2 };
+
 /*
  * Mesh description (Section 2 of the paper: tetrahedral simulation mesh,
  * embedded collision proxy s = W x of Section 3.1, manually marked collision
@@ -119,6 +132,9 @@ typedef struct {
  *                  factorisation is bound by its sequence of block steps
  *                  rather than by arithmetic, use the FP64 factor
  *  stream          hipStream_t to order work on (NULL = default stream)
+ *  global_method   PDIPC_GSTEP_* (above)
+ *  cg_tol, cg_max_iters  PDIPC_GSTEP_PCG: stop when |r| <= cg_tol |g| over the
+ *                  free DOFs, or after cg_max_iters products
  */
 typedef struct {
   double dhat, kappa;
@@ -128,6 +144,9 @@ typedef struct {
   double ccd_eta;
   int32_t ccd_steps, ls_max_halvings, cinv_updates_max, fp32_reduced_min, hinv_rows_mb;
   void* stream;
+  int32_t global_method;
+  double cg_tol;
+  int32_t cg_max_iters;
 } pdipc_options;
 
 /* Per-frame statistics (host).  Stage times follow the paper's Table 1
@@ -144,7 +163,8 @@ typedef struct {
  * cinv_rebuilds: iterations whose contact set c differed from the previous
  * one (C^-1 recomputed); c_delta_max / c_delta_sum: vertices that entered or
  * left c at those iterations (largest, total); cinv_updates: those of them
- * served by the incremental update of C^-1. */
+ * served by the incremental update of C^-1.  pcg_iters: products of the
+ * conjugate-gradient global step over the frame (PDIPC_GSTEP_PCG). */
 typedef struct {
   int32_t iters, n_pt, n_ee, n_c, ls_halvings, ls_failures, refine_steps;
   int32_t n_candidates, refine_fallbacks, cinv_rebuilds, c_delta_max, c_delta_sum, cinv_updates;
@@ -154,7 +174,8 @@ typedef struct {
 } pdipc_frame_stats;
 
 /* Fill *opt with defaults: dhat 5e-4, kappa 1e3, 30 iters, fixed mode, FP64,
- * eta 0.1, 16 CCD steps, 20 halvings, default stream. */
+ * eta 0.1, 16 CCD steps, 20 halvings, default stream, the Schur-complement and
+ * low-rank-update global step (CG: tolerance 1e-12, at most 2000 products). */
 void pdipc_default_options(pdipc_options* opt);
 
 /* Build a solver: validate the mesh, precompute per-tet data, assemble the

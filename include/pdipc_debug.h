@@ -20,9 +20,10 @@ extern "C" {
  * pair counts of the constraint set, affected vertices n_c (Eq. 9), swept
  * candidates of the CCD step, line-search halvings and outcome, near ties of
  * the constraint set, refinement solves of the reduced system, and the step
- * bound alpha_m and accepted step alpha. */
+ * bound alpha_m and accepted step alpha; cg_iters: products of the conjugate-gradient
+ * global step (PDIPC_GSTEP_PCG). */
 typedef struct {
-  int32_t n_pt, n_ee, n_c, n_candidates, ls_halvings, ls_ok, near_ties, refine_steps;
+  int32_t n_pt, n_ee, n_c, n_candidates, ls_halvings, ls_ok, near_ties, refine_steps, cg_iters;
   double alpha_m, alpha;
 } pdipc_iter_trace;
 

@@ -290,10 +290,10 @@ def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int
     ``keyframes`` > 0 adds that many further seeded strength fields (same
     bump recipe) to ``meta["keyframes"]`` for ``Scene.sequence``.
     Fixed vertices: the inner surface farther than ``fix_radius`` from every
-    slit, plus the whole rim of the parameter domain.  The collision-aware
-    region is every free vertex of a tet whose centroid lies within
-    ``region_radius`` of a slit; the proxy is the boundary triangles of those
-    tets.  Actuation: a sum of ``n_bumps`` Gaussian bumps per slit, capped at
+    slit, plus the whole rim of the parameter domain.  The proxy is the
+    boundary triangles of the tets whose centroid lies within
+    ``region_radius`` of a slit; the collision-aware block x2 is the free
+    vertices of those triangles (the vertices that embed the proxy).  Actuation: a sum of ``n_bumps`` Gaussian bumps per slit, capped at
     ``a_cap``, contracting along the local shell normal (so the skin grows
     in-plane and the slots close).
     """
@@ -364,8 +364,9 @@ def face_like(n_theta: int = 101, n_phi: int = 101, n_layers: int = 4, seed: int
     in_region = dist_to_slits(Xo[tets].mean(axis=1)) < region_radius
     faces, owner = boundary_faces(tets)
     surf = faces[in_region[owner]].astype(np.int32)
+    # the collision-aware block x2: the free vertices that carry the proxy
     region = np.zeros(X.shape[0], dtype=np.uint8)
-    region[np.unique(tets[in_region].reshape(-1))] = 1
+    region[np.unique(surf)] = 1
     region[dirichlet == 1] = 0
 
     # actuation: Gaussian bumps near each slit, contracting along the normal;

@@ -15,9 +15,13 @@ from . import _lib
 from ._lib import FrameStats, IterTrace, MeshDesc, Options, PdipcError, check, lib
 
 __all__ = ["Solver", "PdipcError", "FP64", "MIXED_FP32", "host_factor_solve", "actuation_rows", "PDIPCFrame",
-           "dense_spd", "dense_spd_noalloc"]
+           "dense_spd", "dense_spd_noalloc", "GSTEP_SCHUR_WOODBURY", "GSTEP_PCG",
+           "GSTEP_SCHUR"]
 
 FP64, MIXED_FP32 = 0, 1
+# global steps (Table 1): Schur complement + low-rank update (the method), the
+# conjugate-gradient baseline, the Schur complement alone
+GSTEP_SCHUR_WOODBURY, GSTEP_PCG, GSTEP_SCHUR = 0, 1, 2
 
 
 def _dev(t: torch.Tensor, shape=None) -> int:
@@ -43,7 +47,8 @@ class Solver:
     def __init__(self, scene=None, *, X=None, tets=None, dirichlet=None, surf_tris=None, region=None,
                  youngs=1e4, poisson=0.45, dhat=5e-4, kappa=1e3, iters=30, tol=0.0, precision=FP64,
                  ccd_eta=0.1, ccd_steps=16, ls_max_halvings=20, cinv_updates_max=16,
-                 fp32_reduced_min=2049, hinv_rows_mb=4096, device="cuda", stream=None, W=None):
+                 fp32_reduced_min=2049, hinv_rows_mb=4096, device="cuda", stream=None, W=None,
+                 global_method=0, cg_tol=1e-12, cg_max_iters=2000):
         if scene is not None:
             X, tets, dirichlet, surf_tris = scene.X, scene.tets, scene.dirichlet, scene.surf_tris
             region = scene.region
@@ -73,7 +78,8 @@ class Solver:
         self.stream = st
         op = Options(float(dhat), float(kappa), int(iters), float(tol), int(precision), float(ccd_eta),
                      int(ccd_steps), int(ls_max_halvings), int(cinv_updates_max),
-                     int(fp32_reduced_min), int(hinv_rows_mb), C.c_void_p(st.cuda_stream))
+                     int(fp32_reduced_min), int(hinv_rows_mb), C.c_void_p(st.cuda_stream), int(global_method),
+                     float(cg_tol), int(cg_max_iters))
         h = C.c_void_p()
         check(lib().pdipc_init_mesh(C.byref(md), C.byref(op), C.byref(h)), None)
         self._h = h

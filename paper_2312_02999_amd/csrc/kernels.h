@@ -254,6 +254,23 @@ void launch_build_hinv_rows(const FactorDev& f, double* y, double* sol, double* 
 // c index -> x2 index
 void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, int32_t* c_x2, hipStream_t st);
 
+// ---------------------------------------- comparison global steps (Table 1)
+// out = H v (per-tet shares into tetg, m x 12, gathered per free vertex)
+void launch_pd_matvec(const LocalArgs& la, int32_t n, const int32_t* vt_ptr, const int32_t* vt_ent,
+                      const uint8_t* fixed, const double* v, double* tetg, double* out, hipStream_t st);
+// vc (nc x 3) = v at the contact vertices; out at the contact vertices += vc
+void launch_gather_c(int32_t nc, const int32_t* clist, const double* v, double* vc, hipStream_t st);
+void launch_scatter_add_c(int32_t nc, const int32_t* clist, const double* vc, double* out, hipStream_t st);
+// CG updates with device scalars: x += a p, r -= a q (a = sc[num] / sc[den]);
+// p = z + b p (b = sc[num] / sc[den])
+void launch_cg_step(int64_t n3, const double* sc, int num, int den, const double* p, const double* q, double* x,
+                    double* r, hipStream_t st);
+void launch_cg_dir(int64_t n3, const double* sc, int num, int den, const double* z, double* p, hipStream_t st);
+// out (3 n2 square, vertex-major) = S (x) I3; out[x2 rows/cols of c] += Bc (3 nc square)
+void launch_kron_i3(int32_t n2, const double* S, double* out, hipStream_t st);
+void launch_scatter_block(int32_t nc, const int32_t* c_x2, const double* Bc, int32_t n2, double* out,
+                          hipStream_t st);
+
 // Message returned by pdipc_last_error(NULL) (this thread).
 void set_last_error(const char* msg);
 

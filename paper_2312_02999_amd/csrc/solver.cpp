@@ -157,6 +157,10 @@ struct Solver {
   bool check_info_m = false, check_info_cs = false;
   // adjoint work vectors
   DBuf<double> lam, res, zvec, pvec, kp, prod, pairbuf;
+  // comparison global steps: CG vectors and device scalars; the dense
+  // Sigma-hat, its factor and Sigma_s (kept only for the Schur-only step)
+  DBuf<double> cg_r, cg_z, cg_p, cg_q, cg_t, cg_sc, cg_pc, cg_vc;
+  DBuf<double> shat, shat_L, shat_aux, sigma_s;
   int32_t adjoint_iters = 0;
 
   // host helpers
@@ -265,6 +269,13 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
       !(op->ccd_eta > 0 && op->ccd_eta < 1))
     fail(PDIPC_E_INVALID, "bad options");
   if (op->precision != PDIPC_FP64 && op->precision != PDIPC_MIXED_FP32) fail(PDIPC_E_INVALID, "bad precision");
+  if (op->global_method != PDIPC_GSTEP_SCHUR_WOODBURY && op->global_method != PDIPC_GSTEP_PCG &&
+      op->global_method != PDIPC_GSTEP_SCHUR)
+    fail(PDIPC_E_INVALID, "bad global_method");
+  if (op->global_method != PDIPC_GSTEP_SCHUR_WOODBURY && op->precision != PDIPC_FP64)
+    fail(PDIPC_E_INVALID, "the comparison global steps run in FP64 only");
+  if (op->global_method == PDIPC_GSTEP_PCG && (!(op->cg_tol > 0) || op->cg_max_iters <= 0))
+    fail(PDIPC_E_INVALID, "bad CG options");
   if (!(md->youngs > 0) || !(md->poisson > -1 && md->poisson < 0.5)) fail(PDIPC_E_INVALID, "bad material");
   S->n = n;
   S->m = m;
@@ -600,13 +611,14 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   S->bvec.ensure(3LL * std::max(N, 1));
   S->yvec.ensure(6LL * std::max(N, 1));
   S->solvec.ensure(6LL * std::max(N, 1));
-  S->info.ensure(4);
+  S->info.ensure(8);
 
   // ---- Sigma^-1 on the device: Cholesky of Sigma_s, then L^-T L^-1 ---------------------------
   S->sigma_inv.ensure(std::max<int64_t>(1, static_cast<int64_t>(n2) * n2));
   if (n2 > 0) {
     DBuf<double> sig, wk, sl, sli;
     sig.upload(hf.sigma.data(), static_cast<int64_t>(n2) * n2, st);
+    if (op->global_method == PDIPC_GSTEP_SCHUR) S->sigma_s.upload(hf.sigma.data(), static_cast<int64_t>(n2) * n2, st);
     wk.ensure(static_cast<int64_t>(n2) * n2);
     sl.ensure(static_cast<int64_t>(n2) * n2);
     sli.ensure(dense_aux_size(n2));
@@ -769,6 +781,7 @@ struct IterOut {
   bool nc_pending = false;      // n_c (and c_same) still in flight to h_scal
   bool nc_with_same = false;    // the readback carries the c_same flag
   int32_t c_removed = 0, c_added = 0;   // vertices that left / entered c
+  int32_t cg_iters = 0;                 // products of the CG baseline's step
   double alpha_m = 1.0, alpha = 0.0;
 };
 
@@ -1129,6 +1142,142 @@ static void global_step(Solver* S, IterOut& io) {
   launch_unpack(f, S->n, S->solvec.p, S->dx.p, st);
 }
 
+// ---- comparison configurations of Table 1 -------------------------------------
+// z = H^-1 r through the constant factor with no contact (Eq. 7 with c empty):
+// lower sweep, Sigma^-1, upper sweep.  z is written at the free vertices only.
+static void pd_factor_solve(Solver* S, const double* r, double* z) {
+  hipStream_t st = S->st;
+  FactorDev& f = S->fd;
+  const int64_t n3 = 3LL * S->n;
+  // the right-hand side of the factor solve is -g: pass g = -r
+  launch_axpby(n3, -1.0, r, 0.0, S->cg_t.p, st);
+  launch_pack_rhs(f, S->cg_t.p, S->bvec.p, st);
+  {
+    ScopedTimer tm(S, TK_FWD);
+    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
+  }
+  {
+    ScopedTimer tm(S, TK_SIGMA_GEMV);
+    launch_sigma_gemv(f, S->yvec.p + 3LL * f.n1, S->solvec.p + 3LL * f.n1, st);
+  }
+  {
+    ScopedTimer tm(S, TK_BWD);
+    launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
+  }
+  launch_unpack(f, S->n, S->solvec.p, z, st);
+}
+
+// Global step of the conjugate-gradient baseline (Eq. 5): CG on
+// (H + kappa B) dx = -g, preconditioned by L L^T = H.  Stops when
+// |r| <= cg_tol |g| (free DOFs) or after cg_max_iters products.
+static void global_step_pcg(Solver* S, IterOut& io) {
+  hipStream_t st = S->st;
+  finish_readback(S, io);
+  const int32_t np = io.npt + io.nee, nc = io.nc;
+  const int64_t n3 = 3LL * S->n;
+  for (DBuf<double>* b : {&S->cg_r, &S->cg_z, &S->cg_p, &S->cg_q, &S->cg_t}) b->ensure(n3);
+  S->cg_sc.ensure(8);
+  if (nc > 0) {
+    S->cg_pc.ensure(3LL * nc);
+    S->cg_vc.ensure(3LL * nc);
+  }
+  // the preconditioner writes z at the free vertices only: the rest stays 0
+  launch_fill_f64(S->cg_z.p, n3, 0.0, st);
+  launch_fill_f64(S->dx.p, n3, 0.0, st);
+  launch_axpby(n3, -1.0, S->g.p, 0.0, S->cg_r.p, st);            // r = b = -g
+  auto dot = [&](const double* a, const double* b, int slot) {
+    launch_masked_mul(S->n, a, b, S->fixed.p, S->prod.p, st);
+    launch_sum(S->prod.p, n3, S->cg_sc.p + slot, S->red_tmp.p, st);
+  };
+  auto apply = [&](const double* p, double* q) {                 // q = (H + kappa B) p
+    launch_pd_matvec(local_args(S), S->n, S->vt_ptr.p, S->vt_ent.p, S->fixed.p, p, S->tetg.p, q, st);
+    if (nc > 0 && np > 0) {
+      launch_gather_c(nc, S->inc.clist, p, S->cg_pc.p, st);
+      launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->cg_pc.p, S->wtmp.p, S->cg_vc.p, st);
+      launch_scatter_add_c(nc, S->inc.clist, S->cg_vc.p, q, st);
+    }
+  };
+  S->prod.ensure(n3);
+  dot(S->cg_r.p, S->cg_r.p, 0);
+  const double bn = std::sqrt(read_scalar_d(S, S->cg_sc.p + 0));
+  int it = 0;
+  if (bn > 0.0) {
+    const double tol = S->opt.cg_tol * bn;
+    pd_factor_solve(S, S->cg_r.p, S->cg_z.p);
+    HIPCHK(hipMemcpyAsync(S->cg_p.p, S->cg_z.p, sizeof(double) * n3, hipMemcpyDeviceToDevice, st));
+    int rz = 1, rz_new = 4;
+    dot(S->cg_r.p, S->cg_z.p, rz);
+    while (it < S->opt.cg_max_iters) {
+      apply(S->cg_p.p, S->cg_q.p);
+      dot(S->cg_p.p, S->cg_q.p, 2);
+      launch_cg_step(n3, S->cg_sc.p, rz, 2, S->cg_p.p, S->cg_q.p, S->dx.p, S->cg_r.p, st);
+      ++it;
+      dot(S->cg_r.p, S->cg_r.p, 3);
+      if (std::sqrt(read_scalar_d(S, S->cg_sc.p + 3)) <= tol) break;
+      pd_factor_solve(S, S->cg_r.p, S->cg_z.p);
+      dot(S->cg_r.p, S->cg_z.p, rz_new);
+      launch_cg_dir(n3, S->cg_sc.p, rz_new, rz, S->cg_z.p, S->cg_p.p, st);
+      std::swap(rz, rz_new);
+    }
+  }
+  io.cg_iters = it;
+}
+
+// Global step with the Schur complement only (Section 3.1): the lower sweep
+// gives y1 and r2, the dense Sigma-hat = Sigma_s (x) I3 + kappa B_22 (3 n2
+// unknowns) is assembled and factored every iteration, dx2 = Sigma-hat^-1 r2,
+// and the upper sweep gives dx1 (Eq. 7 with Sigma-hat in place of Sigma).
+static void global_step_schur(Solver* S, IterOut& io) {
+  hipStream_t st = S->st;
+  FactorDev& f = S->fd;
+  finish_readback(S, io);
+  const int32_t np = io.npt + io.nee, nc = io.nc;
+  const int64_t n1x3 = 3LL * f.n1, N2 = 3LL * f.n2;
+  launch_pack_rhs(f, S->g.p, S->bvec.p, st);
+  {
+    ScopedTimer tm(S, TK_FWD);
+    launch_forward_sweep(f, S->bvec.p, S->yvec.p, st);
+  }
+  if (N2 > 0) {
+    S->shat.ensure(N2 * N2);
+    S->shat_L.ensure(N2 * N2);
+    S->shat_aux.ensure(dense_aux_size(N2));
+    launch_kron_i3(f.n2, S->sigma_s.p, S->shat.p, st);
+    if (nc > 0 && np > 0) {
+      // kappa B on the contact vertices (3 n_c square, from the pair factors),
+      // added at their x2 rows and columns
+      S->Cs.ensure(static_cast<int64_t>(nc) * nc);
+      S->Mred.ensure(9LL * nc * nc);
+      S->c_x2.ensure(nc);
+      launch_fill_f64(S->Cs.p, static_cast<int64_t>(nc) * nc, 0.0, st);
+      launch_assemble_reduced(nc, S->Cs.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
+      launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
+      launch_scatter_block(nc, S->c_x2.p, S->Mred.p, f.n2, S->shat.p, st);
+    }
+    {
+      ScopedTimer tm(S, TK_REDUCED_CHOL);
+      dense_cholesky<double>(S->shat.p, N2, S->shat_L.p, S->shat_aux.p, S->info.p + 4, st);
+    }
+    if (read_scalar_i(S, S->info.p + 4) != 0) fail(PDIPC_E_NOT_SPD, "Schur complement with contact not SPD");
+    // r2 (n2 x 3, vertex-major) -> dx2 in the x2 part of the solution
+    HIPCHK(hipMemcpyAsync(S->solvec.p + n1x3, S->yvec.p + n1x3, sizeof(double) * N2, hipMemcpyDeviceToDevice, st));
+    dense_chol_solve<double>(S->shat_L.p, S->shat_aux.p, N2, S->solvec.p + n1x3, 1, st);
+  }
+  {
+    ScopedTimer tm(S, TK_BWD);
+    launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
+  }
+  launch_unpack(f, S->n, S->solvec.p, S->dx.p, st);
+}
+
+static void global_step_method(Solver* S, IterOut& io) {
+  switch (S->opt.global_method) {
+    case PDIPC_GSTEP_PCG: global_step_pcg(S, io); break;
+    case PDIPC_GSTEP_SCHUR: global_step_schur(S, io); break;
+    default: global_step(S, io); break;
+  }
+}
+
 // Statuses of the reduced factorisations queued since the last check.
 static void check_factor_status(Solver* S) {
   if (!S->check_info_m && !S->check_info_cs) return;
@@ -1247,7 +1396,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
     const int32_t refine_before = S->refine_steps;
     stage_mark(S, 0);
     assemble_gradient(S, it == 0, io, /*defer=*/true);
-    global_step(S, io);
+    global_step_method(S, io);
     stage_mark(S, 3);
     step_and_search(S, io, true);
     if (S->stage_on) {
@@ -1264,10 +1413,12 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
       tr.n_pt = io.npt; tr.n_ee = io.nee; tr.n_c = io.nc; tr.n_candidates = io.ncand;
       tr.ls_halvings = io.halvings; tr.ls_ok = io.ls_ok ? 1 : 0; tr.near_ties = io.near_ties;
       tr.refine_steps = S->refine_steps - refine_before;
+      tr.cg_iters = io.cg_iters;
       tr.alpha_m = io.alpha_m; tr.alpha = io.alpha;
       S->trace.push_back(tr);
     }
     fs.near_ties += io.near_ties;
+    fs.pcg_iters += io.cg_iters;
     if (S->timer_which >= 0) {
       HIPCHK(hipStreamSynchronize(st));
       harvest_timer(S);
@@ -1425,6 +1576,9 @@ void pdipc_default_options(pdipc_options* o) {
   o->fp32_reduced_min = 2049;
   o->hinv_rows_mb = 4096;
   o->stream = nullptr;
+  o->global_method = PDIPC_GSTEP_SCHUR_WOODBURY;
+  o->cg_tol = 1e-12;
+  o->cg_max_iters = 2000;
 }
 
 int32_t pdipc_init_mesh(const pdipc_mesh_desc* mesh, const pdipc_options* opt, void** out) {
@@ -1628,7 +1782,7 @@ int32_t pdipc_debug_step(void* h, const double* x, double* dx, double* alpha_m, 
     cinv_begin_pass(S);
     IterOut io;
     assemble_gradient(S, true, io);
-    global_step(S, io);
+    global_step_method(S, io);
     step_and_search(S, io, false);
     if (dx) HIPCHK(hipMemcpyAsync(dx, S->dx.p, sizeof(double) * 3 * S->n, hipMemcpyDeviceToDevice, S->st));
     HIPCHK(hipStreamSynchronize(S->st));

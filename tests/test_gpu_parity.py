@@ -514,3 +514,79 @@ def test_nonfinite_actuation_is_rejected():
     # a valid actuation afterwards still works
     _set_act(S, sc, 0.5)
     S.solve_frame(_t(sc.X))
+
+
+# --------------------------------------------------------------------------
+# comparison global steps of Table 1: the CG baseline (Eq. 5) and the Schur
+# complement alone (Section 3.1) solve the same system as the method
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("method", ["pcg", "schur"])
+def test_comparison_global_steps_single_iteration_c1(method):
+    """One iteration from a pressed C1 state: dx of the CG baseline (to its
+    residual tolerance 1e-13) and of the Schur-only step against the oracle's
+    sparse LU, alpha_m and alpha too (1e-9)."""
+    from paper_2312_02999_amd import GSTEP_PCG, GSTEP_SCHUR
+    sc = mg.slabs(0)
+    gm = GSTEP_PCG if method == "pcg" else GSTEP_SCHUR
+    S = _solver(sc, global_method=gm, cg_tol=1e-13)
+    A = _set_act(S, sc, 0.4)
+    x = _pressed(sc, 8e-4, seed=1)
+    dx, am, al = S.debug_step(_t(x))
+    prob = osolver.setup_scene(sc)
+    _, rec, _ = osolver.iteration(prob, x, A)
+    err = np.abs(dx.cpu().numpy() - rec.dx).max() / np.abs(rec.dx).max()
+    print(f"{method} single iteration C1: dx err {err:.3e} n_c {len(np.unique(rec.cs.pt))} "
+          f"alpha_m {am} / {rec.alpha_m}")
+    assert err < 1e-9, err
+    assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
+    assert abs(al - rec.alpha) <= 1e-9 * max(1.0, rec.alpha)
+
+
+@pytest.mark.parametrize("method", ["pcg", "schur"])
+def test_comparison_global_steps_frames_match_oracle(method):
+    """The tiny scene's frames and C1's first frame with each comparison step:
+    positions within 1e-9 of the bounding-box diagonal of the oracle's, the
+    CG iteration count reported per iteration."""
+    from paper_2312_02999_amd import GSTEP_PCG, GSTEP_SCHUR
+    gm = GSTEP_PCG if method == "pcg" else GSTEP_SCHUR
+    for name in ("tiny", "slabs"):
+        sc = mg.scene_by_name(name)
+        S = _solver(sc, iters=sc.iters, global_method=gm, cg_tol=1e-13)
+        prob = osolver.setup_scene(sc)
+        x = sc.X.copy()
+        xg = _t(x)
+        diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+        frames = sc.frames if name == "tiny" else 1
+        for t in range(frames):
+            A = _set_act(S, sc, (t + 1) / sc.frames)
+            xg, st = S.solve_frame(xg, stats=True)
+            r = osolver.frame(prob, x, A, iters=sc.iters)
+            x = r.x
+            err = np.abs(xg.cpu().numpy() - x).max() / diag
+            print(f"{method} {name} frame {t}: err {err:.3e} n_c {st['n_c']} cg products {st['pcg_iters']}")
+            assert err < 1e-9, (name, t, err)
+            if method == "pcg":
+                assert st["pcg_iters"] > 0
+                assert sum(tr["cg_iters"] for tr in S.trace()) == st["pcg_iters"]
+        S.close()
+
+
+def test_comparison_global_steps_face5k_closed_slit():
+    """face5k with its slit closed by moving material: one iteration of each
+    global step gives the same dx as the oracle (1e-9 of max |dx|)."""
+    from paper_2312_02999_amd import GSTEP_PCG, GSTEP_SCHUR, GSTEP_SCHUR_WOODBURY, Solver
+    sc = mg.scene_by_name("face5k")
+    x = mg.closed_slit_state(sc, 3e-4, seed=1, jitter=2e-5)
+    prob = osolver.setup_scene(sc)
+    A = ofem.actuation_matrices(0.5 * sc.act_a, sc.act_R)
+    _, rec, _ = osolver.iteration(prob, x, A)
+    assert len(rec.cs.pt) + len(rec.cs.ee) > 50
+    for gm in (GSTEP_SCHUR_WOODBURY, GSTEP_PCG, GSTEP_SCHUR):
+        S = Solver(sc, global_method=gm, cg_tol=1e-13)
+        S.set_actuation_scalar(_t(0.5 * sc.act_a), _t(sc.act_R.reshape(-1, 9)))
+        dx, am, al = S.debug_step(_t(x))
+        err = np.abs(dx.cpu().numpy() - rec.dx).max() / np.abs(rec.dx).max()
+        print(f"face5k closed slit, global step {gm}: dx err {err:.3e} alpha_m {am} / {rec.alpha_m}")
+        S.close()
+        assert err < 1e-9, (gm, err)
+        assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
