@@ -12,70 +12,6 @@ namespace {
 constexpr int NB = 64;
 }
 
-// ---- tiled GEMM: C = beta C + alpha op(A) op(B), 64x64 tiles, K chunks of 16 ----
-template <typename T, bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A,
-                                                   int64_t lda, const T* __restrict__ B, int64_t ldb, T beta,
-                                                   T* __restrict__ C, int64_t ldc, int lower_only) {
-  const int64_t ti = blockIdx.y, tj = blockIdx.x;
-  if (lower_only && tj > ti) return;
-  __shared__ T As[16][64 + 1];
-  __shared__ T Bs[16][64 + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-  const int64_t i0 = ti * 64, j0 = tj * 64;
-  T pa[4], pb[4];
-  auto fetch = [&](int64_t k0) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int idx = threadIdx.x + 256 * u;
-      int kk = idx / 64, r = idx % 64;
-      int64_t gi = i0 + r, gk = k0 + kk, gj = j0 + r;
-      pa[u] = (gi < M && gk < K) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : T(0);
-      pb[u] = (gj < N && gk < K) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : T(0);
-    }
-  };
-  fetch(0);
-  for (int64_t k0 = 0; k0 < K; k0 += 16) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int idx = threadIdx.x + 256 * u;
-      As[idx / 64][idx % 64] = pa[u];
-      Bs[idx / 64][idx % 64] = pb[u];
-    }
-    __syncthreads();
-    if (k0 + 16 < K) fetch(k0 + 16);
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty + 16 * q];
-        b[q] = Bs[kk][tx + 16 * q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int64_t gi = i0 + ty + 16 * p, gj = j0 + tx + 16 * q;
-      if (gi < M && gj < N && (!lower_only || gj <= gi)) {
-        T old = beta == T(0) ? T(0) : C[gi * ldc + gj];
-        C[gi * ldc + gj] = beta * old + alpha * acc[p][q];
-      }
-    }
-}
-
 // ---- Cholesky -----------------------------------------------------------------
 // Right-looking, blocked (NB = 32 or 64).  Outputs: L (lower, row-major), its
 // transpose Lt (upper, row-major), the reciprocals of the diagonal, dinv, and
@@ -140,75 +76,6 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
   return y * (1.5f - 0.5f * d * y * y);
 }
 
-// Factor the 64x64 tile W (LDS, row-major, lower part used; rows and columns
-// beyond kb hold the identity) with the first wave of the workgroup; writes
-// rows/columns < kb of L and Lt at offset k0 and dinv.  A non-positive pivot
-// is replaced by 1 so that the factorisation completes, and the first such
-// column (global index + 1) goes to *info unless an earlier tile set it.
-// The unrolled loop is kept free of branches (failure is tracked by selects)
-// so that the row stays in registers; W is overwritten with the factor and
-// copied out afterwards.
-template <typename T, int NB>
-__device__ __forceinline__ void factor_diag_wave(T (*W)[NB + 1], int kb, int64_t k0, int64_t n, T* __restrict__ L,
-                                 T* __restrict__ Lt, T* __restrict__ dinv, int32_t* __restrict__ info,
-                                 T* __restrict__ colbuf) {
-  const int lane = threadIdx.x;
-  if (lane >= NB) return;
-  T a[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) a[c] = W[lane][c];
-  T myinv = T(1);
-  int first_bad = 0;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    T d = read_lane(a[j], j);
-    const bool ok = d > T(0);
-    first_bad = (!ok && first_bad == 0 && j < kb) ? j + 1 : first_bad;
-    d = ok ? d : T(1);
-    const T isd = rsqrt_nr(d);
-    const T l = (lane == j) ? d * isd : a[j] * isd;
-    a[j] = l;
-    myinv = (lane == j) ? isd : myinv;
-    colbuf[lane] = l;
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int c = j + 1; c < NB; ++c) a[c] -= l * colbuf[c];
-    __builtin_amdgcn_wave_barrier();
-  }
-#pragma unroll
-  for (int c = 0; c < NB; ++c) W[lane][c] = a[c];
-  colbuf[lane] = myinv;
-  __builtin_amdgcn_wave_barrier();
-  if (first_bad != 0 && lane == 0 && *info == 0) *info = static_cast<int32_t>(k0 + first_bad);
-  for (int r = 0; r < kb; ++r) {
-    if (lane <= r) L[(k0 + r) * n + k0 + lane] = W[r][lane];
-    if (lane >= r && lane < kb) Lt[(k0 + r) * n + k0 + lane] = W[lane][r];
-  }
-  if (lane < kb) dinv[k0 + lane] = colbuf[lane];
-}
-
-// Lane c of the first wave forms column c of L_kk^-1 from the factor left in W
-// (row-major, lower part) and the reciprocal diagonal dk by forward
-// substitution, and stores the inverse row-major to D.  Padded rows/columns
-// hold the identity, so the inverse is the identity there too.
-template <typename T, int NB>
-__device__ __forceinline__ void invert_diag_wave(const T (*W)[NB + 1], const T* dk, T* __restrict__ D) {
-  const int lane = threadIdx.x;
-  if (lane >= NB) return;
-  T v[NB];
-#pragma unroll
-  for (int r = 0; r < NB; ++r) v[r] = (r == lane) ? T(1) : T(0);
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    const T y = v[c] * dk[c];
-    v[c] = y;
-#pragma unroll
-    for (int r = c + 1; r < NB; ++r) v[r] -= y * W[r][c];
-  }
-#pragma unroll
-  for (int r = 0; r < NB; ++r) D[r * NB + lane] = v[r];
-}
-
 // Factor and invert the 16 x 16 block W[o..o+16)[o..o+16) of a 32-wide
 // diagonal tile with one wave.  Lanes 0-15 hold its rows; lanes 32-47 carry
 // the identity through the same steps (the column of L is broadcast by
@@ -217,8 +84,8 @@ __device__ __forceinline__ void invert_diag_wave(const T (*W)[NB + 1], const T* 
 // 1 / diag to dk[o..o+16); a non-positive pivot is replaced by 1 and the
 // first such column (tile index + 1, below kb) is kept in first_bad.  The
 // unrolled loop is kept free of branches so that the row stays in registers.
-template <typename T>
-__device__ __forceinline__ void factor_invert16(const T (*W)[33], int o, T (*Xs)[17], T* dk, int kb,
+template <typename T, int LD = 33>
+__device__ __forceinline__ void factor_invert16(const T (*W)[LD], int o, T (*Xs)[17], T* dk, int kb,
                                                 int& first_bad) {
   const int lane = threadIdx.x;
   const int rr = lane & 15;
@@ -254,8 +121,8 @@ __device__ __forceinline__ void factor_invert16(const T (*W)[33], int o, T (*Xs)
 // matrix cores, L22 (and L22^-1), then (L^-1)_21 = -L22^-1 L21 L11^-1.  The
 // tile W is overwritten; X receives L_kk^-1 (32 x 33), dk 1 / diag(L_kk);
 // S is scratch for three 16 x 17 blocks.  The factor itself is not kept.
-template <typename T>
-__device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int kb, int64_t k0,
+template <typename T, int LD = 33>
+__device__ __forceinline__ void factor_invert_wave32(T (*W)[LD], T (*X)[LD], int kb, int64_t k0,
                                                      int32_t* __restrict__ info, T (*S)[17], T* dk) {
   const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
   T (*X11)[17] = S;
@@ -263,7 +130,7 @@ __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int
   T (*Tm)[17] = S + 32;
   typedef typename MfmaVec<T>::type V;
   int first_bad = 0;
-  factor_invert16<T>(W, 0, X11, dk, kb, first_bad);
+  factor_invert16<T, LD>(W, 0, X11, dk, kb, first_bad);
   V acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int q0 = 0; q0 < 16; q0 += 4) acc = mfma16x16x4(W[16 + lr][q0 + lk], X11[lr][q0 + lk], acc);
@@ -280,7 +147,7 @@ __device__ __forceinline__ void factor_invert_wave32(T (*W)[33], T (*X)[33], int
 #pragma unroll
   for (int q = 0; q < 4; ++q) W[16 + mfma_row<T>(lk, q)][16 + lr] -= upd[q];
   __builtin_amdgcn_wave_barrier();
-  factor_invert16<T>(W, 16, X22, dk, kb, first_bad);
+  factor_invert16<T, LD>(W, 16, X22, dk, kb, first_bad);
   V t = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int p0 = 0; p0 < 16; p0 += 4) t = mfma16x16x4(W[16 + lr][p0 + lk], X11[p0 + lk][lr], t);
@@ -437,10 +304,10 @@ template <typename T, int NB>
 __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ L,
                                                          T* __restrict__ Lt, T* __restrict__ dinv,
                                                          T* __restrict__ Dinv, int32_t* __restrict__ info) {
+  static_assert(NB == 32, "32-wide blocks");
   __shared__ T W[NB][NB + 1];
-  __shared__ T X[NB == 32 ? 32 : 1][33];
-  __shared__ T Sc[NB == 32 ? 48 : 1][17];
-  __shared__ T colbuf[PDIPC_WAVE];
+  __shared__ T X[32][33];
+  __shared__ T Sc[48][17];
   __shared__ T dk[NB];
   const int kb = static_cast<int>(n < NB ? n : NB);
   if (threadIdx.x == 0) *info = 0;
@@ -451,14 +318,9 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
     W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
   }
   __syncthreads();
-  if constexpr (NB == 32) {
-    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, Sc, dk);
-    __syncthreads();
-    store_diag32<T>(X, dk, kb, 0, dinv, Dinv);
-  } else if (threadIdx.x < PDIPC_WAVE) {
-    factor_diag_wave<T, NB>(W, kb, 0, n, L, Lt, dinv, info, colbuf);
-    invert_diag_wave<T, NB>(W, colbuf, Dinv);
-  }
+  if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, Sc, dk);
+  __syncthreads();
+  store_diag32<T>(X, dk, kb, 0, dinv, Dinv);
 }
 
 // Block step k for tile (bi, bj), k < bj <= bi.  The panels L_bk = A_bk
@@ -479,17 +341,15 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   T (*Ta)[NB + 1] = Ai;   // then Ta[p][r] = L[i0 + r][k0 + p]
   T (*Tb)[NB + 1] = Aj;
   T (*W)[NB + 1] = Ds;    // then the tile to factor
-  __shared__ T colbuf[PDIPC_WAVE];
   __shared__ T dk[NB];
   constexpr int TL = NB / 32;
   const int64_t nblk = (n + NB - 1) / NB;
   const int64_t m = nblk - k - 1;
   int64_t t = blockIdx.x, ii = 0;
-  if constexpr (NB == 32) {
-    if (t >= m * (m + 1) / 2) {
-      rhs_tile_step<T>(A, n, k, t - m * (m + 1) / 2, L, Lt, Dinv, smem_raw);
-      return;
-    }
+  static_assert(NB == 32, "32-wide blocks");
+  if (t >= m * (m + 1) / 2) {
+    rhs_tile_step<T>(A, n, k, t - m * (m + 1) / 2, L, Lt, Dinv, smem_raw);
+    return;
   }
   while (t >= m - ii) { t -= m - ii; ++ii; }
   const int64_t bj = k + 1 + ii, bi = bj + t;
@@ -562,16 +422,6 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   }
   __syncthreads();
   T (*Tbs)[NB + 1] = same ? Ta : Tb;
-  if (NB != 32 && bj == k + 1) {
-#pragma unroll
-    for (int it = 0; it < NB * NB / 256; ++it) {
-      const int idx = threadIdx.x + 256 * it;
-      const int r = idx / NB, p = idx % NB;
-      if (i0 + r < n) L[(i0 + r) * n + k0 + p] = Ta[p][r];
-      const int p2 = idx / NB, r2 = idx % NB;
-      if (i0 + r2 < n) Lt[(k0 + p2) * n + i0 + r2] = Ta[p2][r2];
-    }
-  }
   {
     typename MfmaVec<T>::type acc[TL][TL];
 #pragma unroll
@@ -607,30 +457,336 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   if (!last) return;
   __syncthreads();
   const int kb = static_cast<int>(n - i0 < NB ? n - i0 : NB);
-  if constexpr (NB == 32) {
-    T (*X)[33] = Ai;      // the panels are consumed
-    T (*Sc)[17] = reinterpret_cast<T (*)[17]>(&Aj[0][0]);
-    if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, i0, info, Sc, dk);
-    __syncthreads();
-    store_diag32<T>(X, dk, kb, i0, dinv, Dinv + (k + 1) * NB * NB);
-  } else if (threadIdx.x < PDIPC_WAVE) {
-    factor_diag_wave<T, NB>(W, kb, i0, n, L, Lt, dinv, info, colbuf);
-    invert_diag_wave<T, NB>(W, colbuf, Dinv + (k + 1) * NB * NB);
-  }
+  T (*X)[33] = Ai;      // the panels are consumed
+  T (*Sc)[17] = reinterpret_cast<T (*)[17]>(&Aj[0][0]);
+  if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, i0, info, Sc, dk);
+  __syncthreads();
+  store_diag32<T>(X, dk, kb, i0, dinv, Dinv + (k + 1) * NB * NB);
 }
 
 
-// Block size: 32 keeps the serial chain of diagonal factorisations short for
-// the reduced systems of a few thousand unknowns; 64 feeds the matrix cores
-// better above that.  Factor, solves and inverse must agree on it.
-static int dense_block(int64_t n) { return n <= 2048 ? 32 : 64; }
+// ---- 64-wide blocked Cholesky with L^-1, two launches per block step ---------
+// For the reduced systems of a few thousand unknowns.  Block step k:
+//  panel launch: L_ik = A_ik (L_kk^-1)^T for every row block i > k (each panel
+//    once, on the matrix cores, stored over A_ik), and the row k of
+//    Y = L^-1: Y_kj = L_kk^-1 B_kj (Y_kk = L_kk^-1), stored to F and Yt;
+//  update launch: A_ij -= L_ik L_jk^T for the trailing tiles and
+//    B_ij -= L_ik Y_kj for i > k >= j (the substitution L Y = I, B = I at the
+//    start, B_ij kept transposed in the strictly upper block (j, i) of A);
+//    the workgroup of tile (k+1, k+1) then factors and inverts it.
+// The 64 x 64 diagonal blocks are factored and inverted by one workgroup as
+// 2 x 2 blocks of 32 (each by one wave, as above), the coupling blocks on the
+// matrix cores.  Outputs as the 32-wide path: F = Y (lower), aux = Yt, then
+// 1 / diag(L), the diagonal-block inverses (64 x 64 each) and solve scratch.
+namespace {
+constexpr int NB6 = 64;
+constexpr int LD6 = NB6 + 1;
+}
 
-// Launches [p0, p1) of the factorisation: launch 0 is the first diagonal
-// block, launch 1 + k the block step k, and (NB = 32) the last launch forms
-// the last block row of L^-1.
-template <typename T, int NB>
-static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st, int64_t p0,
+// Each wave owns a 32 x 32 quadrant (2 x 2 MFMA blocks of 16) of a 64 x 64
+// product acc += op(As) op(Bs) over 64 terms: element (r, p) of the left
+// operand is As[r][p] (As[p][r] when TA), element (p, c) of the right one is
+// Bs[c][p] when TB, else Bs[p][c].
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void tile_gemm64(const T (*As)[LD6], const T (*Bs)[LD6],
+                                            typename MfmaVec<T>::type acc[2][2]) {
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int rb = 32 * (w / 2), cb = 32 * (w % 2), lr = lane % 16, lk = lane / 16;
+#pragma unroll 4
+  for (int p0 = 0; p0 < NB6; p0 += 4) {
+    const int p = p0 + lk;
+    T a[2], b[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int r = rb + 16 * x + lr, c = cb + 16 * x + lr;
+      a[x] = TA ? As[p][r] : As[r][p];
+      b[x] = TB ? Bs[c][p] : Bs[p][c];
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(a[x], b[y], acc[x][y]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_acc(typename MfmaVec<T>::type acc[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
+}
+
+// Row and column of element q of block (x, y) of the calling lane's quadrant.
+template <typename T>
+__device__ __forceinline__ void quad_pos(int x, int y, int q, int& r, int& c) {
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  r = 32 * (w / 2) + 16 * x + mfma_row<T>(lane / 16, q);
+  c = 32 * (w % 2) + 16 * y + lane % 16;
+}
+
+// 32 x 32 x 32 product on the matrix cores by all four waves (one 16 x 16
+// block each): out[r][c] = s * sum_p a(r, p) b(p, c) with a(r, p) = A[r][p]
+// and b(p, c) = Bt[c][p] (BT) or B[p][c]; operands and result are 32 x 32
+// sub-blocks of LDS arrays with row stride LD6.
+template <typename T, bool BT>
+__device__ __forceinline__ void gemm32_lds(const T (*A)[LD6], const T (*B)[LD6], T (*out)[LD6], T s, bool accumulate) {
+  const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
+  const int rb = 16 * (w / 2), cb = 16 * (w % 2), lr = lane % 16, lk = lane / 16;
+  typename MfmaVec<T>::type acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int p0 = 0; p0 < 32; p0 += 4) {
+    const int p = p0 + lk;
+    acc = mfma16x16x4(A[rb + lr][p], BT ? B[cb + lr][p] : B[p][cb + lr], acc);
+  }
+  __syncthreads();     // operands may alias the output
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rb + mfma_row<T>(lk, q), c = cb + lr;
+    out[r][c] = (accumulate ? out[r][c] : T(0)) + s * acc[q];
+  }
+  __syncthreads();
+}
+
+// Factor and invert the 64 x 64 tile W (LDS, symmetric, identity beyond kb)
+// with a workgroup of four waves: L11 and L11^-1 (wave 0), L21 = A21 L11^-T,
+// A22 -= L21 L21^T, L22 and L22^-1 (wave 0), (L^-1)_21 = -L22^-1 L21 L11^-1.
+// X receives L^-1 (64 x 64, zero above the diagonal), dk 1 / diag(L); W is
+// destroyed.  The 32-wide factorisations take their scratch from parts of W
+// and X that are free at the time, and L21 X11 goes where A22 was.
+template <typename T>
+__device__ void factor_invert_wg64(T (*W)[LD6], T (*X)[LD6], int kb, int64_t k0, int32_t* __restrict__ info,
+                                   T* dk) {
+  const int kb1 = kb < 32 ? kb : 32, kb2 = kb > 32 ? kb - 32 : 0;
+  T (*W21)[LD6] = reinterpret_cast<T (*)[LD6]>(&W[32][0]);
+  T (*W22)[LD6] = reinterpret_cast<T (*)[LD6]>(&W[32][32]);
+  T (*X22)[LD6] = reinterpret_cast<T (*)[LD6]>(&X[32][32]);
+  T (*X21)[LD6] = reinterpret_cast<T (*)[LD6]>(&X[32][0]);
+  // scratch of the first 32-wide factorisation: rows 32.. of X (still free)
+  if (threadIdx.x < PDIPC_WAVE)
+    factor_invert_wave32<T, LD6>(W, X, kb1, k0, info, reinterpret_cast<T (*)[17]>(&X[32][0]), dk);
+  __syncthreads();
+  gemm32_lds<T, true>(W21, X, W21, T(1), false);            // L21 = A21 X11^T
+  gemm32_lds<T, true>(W21, W21, W22, T(-1), true);          // A22 -= L21 L21^T
+  // scratch of the second: the first block of W (consumed)
+  if (threadIdx.x < PDIPC_WAVE)
+    factor_invert_wave32<T, LD6>(W22, X22, kb2, k0 + 32, info, reinterpret_cast<T (*)[17]>(&W[0][0]), dk + 32);
+  __syncthreads();
+  gemm32_lds<T, false>(W21, X, W22, T(1), false);           // L21 X11 (where A22 was)
+  gemm32_lds<T, false>(X22, W22, X21, T(-1), false);        // X21 = -X22 L21 X11
+  for (int idx = threadIdx.x; idx < 32 * 32; idx += blockDim.x) X[idx / 32][32 + idx % 32] = T(0);
+  __syncthreads();
+}
+
+// Block 0: factor and invert the first diagonal block.
+template <typename T>
+__global__ void __launch_bounds__(256) chol64_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ dinv,
+                                                           T* __restrict__ Dinv, int32_t* __restrict__ info) {
+  __shared__ T W[NB6][LD6];
+  __shared__ T X[NB6][LD6];
+  __shared__ T dk[NB6];
+  const int kb = static_cast<int>(n < NB6 ? n : NB6);
+  if (threadIdx.x == 0) *info = 0;
+  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
+    const int r = idx / NB6, c = idx % NB6;
+    W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
+  }
+  __syncthreads();
+  factor_invert_wg64<T>(W, X, kb, 0, info, dk);
+  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) Dinv[idx] = X[idx / NB6][idx % NB6];
+  if (threadIdx.x < kb) dinv[threadIdx.x] = dk[threadIdx.x];
+}
+
+// Panel launch of block step k: workgroups t < m form L_ik (i = k + 1 + t);
+// the others form Y_kj, j = t - m.
+template <typename T>
+__global__ void __launch_bounds__(256) chol64_panel_kernel(T* __restrict__ A, int64_t n, int64_t k,
+                                                           T* __restrict__ F, T* __restrict__ Yt,
+                                                           const T* __restrict__ Dinv) {
+  __shared__ T Ds[NB6][LD6];
+  __shared__ T Bs[NB6][LD6];
+  const int64_t nblk = (n + NB6 - 1) / NB6, m = nblk - k - 1;
+  const int64_t t = blockIdx.x, k0 = k * NB6;
+  const int kb = static_cast<int>(n - k0 < NB6 ? n - k0 : NB6);
+  const T* D = Dinv + k * NB6 * NB6;
+  typename MfmaVec<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  if (t < m) {
+    const int64_t i0 = (k + 1 + t) * NB6;
+    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
+      const int r = idx / NB6, c = idx % NB6;
+      Ds[r][c] = D[idx];
+      Bs[r][c] = (i0 + r < n && c < kb) ? A[(i0 + r) * n + k0 + c] : T(0);
+    }
+    __syncthreads();
+    tile_gemm64<T, false, true>(Bs, Ds, acc);        // L_ik[r][c] = sum_p A_ik[r][p] D[c][p]
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int r, c;
+          quad_pos<T>(x, y, q, r, c);
+          if (i0 + r < n && c < kb) A[(i0 + r) * n + k0 + c] = acc[x][y][q];
+        }
+    return;
+  }
+  const int64_t j = t - m, j0 = j * NB6;
+  if (j == k) {
+    // Y_kk = L_kk^-1
+    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
+      const int r = idx / NB6, c = idx % NB6;
+      if (r < kb && c < kb) {
+        F[(k0 + r) * n + k0 + c] = D[r * NB6 + c];
+        Yt[(k0 + c) * n + k0 + r] = D[r * NB6 + c];
+      }
+    }
+    return;
+  }
+  // Y_kj = L_kk^-1 B_kj, B_kj[p][c] kept at A[(j0 + c) n + k0 + p]
+  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
+    const int r = idx / NB6, c = idx % NB6;
+    Ds[r][c] = D[idx];
+    Bs[c][r] = (r < kb) ? A[(j0 + c) * n + k0 + r] : T(0);      // Bs[c][p] = B_kj[p][c]
+  }
+  __syncthreads();
+  tile_gemm64<T, false, true>(Ds, Bs, acc);          // Y[r][c] = sum_p D[r][p] B[p][c]
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int r, c;
+        quad_pos<T>(x, y, q, r, c);
+        if (r < kb) {
+          F[(k0 + r) * n + j0 + c] = acc[x][y][q];
+          Yt[(j0 + c) * n + k0 + r] = acc[x][y][q];
+        }
+      }
+}
+
+// Update launch of block step k: trailing tiles (bi, bj), k < bj <= bi,
+// then the tiles (bi, bj), bi > k >= bj, of the substitution.
+template <typename T>
+__global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, int64_t n, int64_t k,
+                                                            const T* __restrict__ F, T* __restrict__ dinv,
+                                                            T* __restrict__ Dinv, int32_t* __restrict__ info) {
+  __shared__ T Li[NB6][LD6];
+  __shared__ T Lj[NB6][LD6];
+  __shared__ T dk[NB6];
+  const int64_t nblk = (n + NB6 - 1) / NB6, m = nblk - k - 1;
+  const int64_t k0 = k * NB6;
+  int64_t t = blockIdx.x;
+  typename MfmaVec<T>::type acc[2][2];
+  zero_acc<T>(acc);
+  T pre[2][2][4];
+  if (t < m * (m + 1) / 2) {
+    int64_t ii = 0;
+    while (t >= m - ii) { t -= m - ii; ++ii; }
+    const int64_t bj = k + 1 + ii, bi = bj + t, i0 = bi * NB6, j0 = bj * NB6;
+    const bool diag_next = bi == k + 1 && bj == k + 1;
+    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
+      const int r = idx / NB6, c = idx % NB6;
+      Li[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);
+      Lj[r][c] = (j0 + r < n) ? A[(j0 + r) * n + k0 + c] : T(0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int r, c;
+          quad_pos<T>(x, y, q, r, c);
+          pre[x][y][q] = (i0 + r < n && j0 + c < n) ? A[(i0 + r) * n + j0 + c] : T(0);
+        }
+    __syncthreads();
+    tile_gemm64<T, false, true>(Li, Lj, acc);        // sum_p L_ik[r][p] L_jk[c][p]
+    if (!diag_next) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int r, c;
+            quad_pos<T>(x, y, q, r, c);
+            if (i0 + r < n && j0 + c < n) A[(i0 + r) * n + j0 + c] = pre[x][y][q] - acc[x][y][q];
+          }
+      return;
+    }
+    // the next diagonal block: factor and invert it (identity beyond n)
+    __syncthreads();
+    T (*W)[LD6] = Li;
+    T (*X)[LD6] = Lj;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int r, c;
+          quad_pos<T>(x, y, q, r, c);
+          W[r][c] = (i0 + r < n && j0 + c < n) ? pre[x][y][q] - acc[x][y][q] : (r == c ? T(1) : T(0));
+        }
+    __syncthreads();
+    const int kb = static_cast<int>(n - i0 < NB6 ? n - i0 : NB6);
+    factor_invert_wg64<T>(W, X, kb, i0, info, dk);
+    T* D = Dinv + (k + 1) * NB6 * NB6;
+    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) D[idx] = X[idx / NB6][idx % NB6];
+    if (threadIdx.x < kb) dinv[i0 + threadIdx.x] = dk[threadIdx.x];
+    return;
+  }
+  // B_ij -= L_ik Y_kj, B_ij[r][c] kept at A[(j0 + c) n + i0 + r]; B_ik starts at 0
+  t -= m * (m + 1) / 2;
+  const int64_t bi = k + 1 + t / (k + 1), bj = t % (k + 1), i0 = bi * NB6, j0 = bj * NB6;
+  const int kb = static_cast<int>(n - k0 < NB6 ? n - k0 : NB6);     // k < bi, so block k is full
+  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
+    const int r = idx / NB6, c = idx % NB6;
+    Li[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);      // L_ik
+    Lj[r][c] = (r < kb) ? F[(k0 + r) * n + j0 + c] : T(0);          // Y_kj[p = r][c]
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int r, c;
+        quad_pos<T>(x, y, q, r, c);
+        pre[x][y][q] = (bj < k && i0 + r < n) ? A[(j0 + c) * n + i0 + r] : T(0);
+      }
+  __syncthreads();
+  tile_gemm64<T, false, false>(Li, Lj, acc);         // sum_p L_ik[r][p] Y_kj[p][c]
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int r, c;
+        quad_pos<T>(x, y, q, r, c);
+        if (i0 + r < n) A[(j0 + c) * n + i0 + r] = pre[x][y][q] - acc[x][y][q];
+      }
+}
+
+// Block size: 32 below kDense64Min unknowns, where the chain of block steps
+// is short and one launch per step wins; 64 above, where each panel is formed
+// once and the trailing tiles need a single product (two launches per step).
+// Both leave L^-1 (F) and its transpose (aux), so solves and the inverse are
+// the same products.
+static constexpr int64_t kDense64Min = 2049;
+static int dense_block(int64_t n) { return n < kDense64Min ? 32 : 64; }
+
+// Launches [p0, p1) of the 32-wide factorisation: launch 0 is the first
+// diagonal block, launch 1 + k the block step k, the last one forms the last
+// block row of L^-1.
+template <typename T>
+static void dense_cholesky_32(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st, int64_t p0,
                               int64_t p1) {
+  constexpr int NB = 32;
   T* Lt = aux;
   T* dinv = aux + n * n;
   T* Dinv = aux + n * n + n;
@@ -640,103 +796,51 @@ static void dense_cholesky_nb(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hi
   for (int64_t k = 0; k + 1 < nblk; ++k) {
     if (1 + k < p0 || 1 + k >= p1) continue;
     const int64_t m = nblk - k - 1;
-    const int64_t tiles = m * (m + 1) / 2 + (NB == 32 ? m * (k + 1) : 0);
+    const int64_t tiles = m * (m + 1) / 2 + m * (k + 1);
     chol_update_kernel<T, NB><<<static_cast<unsigned>(tiles), 256, shm, st>>>(A, n, k, L, Lt, dinv, Dinv, d_info);
   }
-  if (NB == 32 && nblk >= p0 && nblk < p1)
+  if (nblk >= p0 && nblk < p1)
     chol_lastrow_kernel<T><<<static_cast<unsigned>(nblk), 256, 0, st>>>(A, n, L, Lt, Dinv);
+}
+
+// Launches [p0, p1) of the 64-wide factorisation: launch 0 is the first
+// diagonal block, then per block step k the panel launch (1 + 2k) and, but
+// for the last step, the update launch (2 + 2k).
+template <typename T>
+static void dense_cholesky_64(T* A, int64_t n, T* F, T* aux, int32_t* d_info, hipStream_t st, int64_t p0,
+                              int64_t p1) {
+  T* Yt = aux;
+  T* dinv = aux + n * n;
+  T* Dinv = aux + n * n + n;
+  const int64_t nblk = (n + NB6 - 1) / NB6;
+  auto in = [&](int64_t l) { return l >= p0 && l < p1; };
+  if (in(0)) chol64_first_kernel<T><<<1, 256, 0, st>>>(A, n, dinv, Dinv, d_info);
+  for (int64_t k = 0; k < nblk; ++k) {
+    const int64_t m = nblk - k - 1;
+    if (in(1 + 2 * k))
+      chol64_panel_kernel<T><<<static_cast<unsigned>(m + k + 1), 256, 0, st>>>(A, n, k, F, Yt, Dinv);
+    if (m > 0 && in(2 + 2 * k))
+      chol64_update_kernel<T><<<static_cast<unsigned>(m * (m + 1) / 2 + m * (k + 1)), 256, 0, st>>>(
+          A, n, k, F, dinv, Dinv, d_info);
+  }
 }
 
 int64_t dense_cholesky_launches(int64_t n) {
   if (n <= 0) return 0;
-  const int nb = dense_block(n);
-  const int64_t nblk = (n + nb - 1) / nb;
-  return nb == 32 ? nblk + 1 : nblk;
+  if (dense_block(n) == 32) return (n + 31) / 32 + 1;
+  return 2 * ((n + NB6 - 1) / NB6);
 }
 
 template <typename T>
 void dense_cholesky_range(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st, int64_t p0, int64_t p1) {
   if (n <= 0) return;
-  if (dense_block(n) == 32) dense_cholesky_nb<T, 32>(A, n, L, aux, d_info, st, p0, p1);
-  else dense_cholesky_nb<T, 64>(A, n, L, aux, d_info, st, p0, p1);
+  if (dense_block(n) == 32) dense_cholesky_32<T>(A, n, L, aux, d_info, st, p0, p1);
+  else dense_cholesky_64<T>(A, n, L, aux, d_info, st, p0, p1);
 }
 
 template <typename T>
 void dense_cholesky(T* A, int64_t n, T* L, T* aux, int32_t* d_info, hipStream_t st) {
   dense_cholesky_range<T>(A, n, L, aux, d_info, st, 0, dense_cholesky_launches(n));
-}
-
-// ---- solves: one workgroup; diagonal blocks by their inverses, the rest coalesced
-template <typename T, int NB>
-__global__ void __launch_bounds__(512) chol_solve_kernel(const T* __restrict__ L, const T* __restrict__ Lt,
-                                                          const T* __restrict__ Dinv, int64_t n, T* __restrict__ b,
-                                                          int nrhs) {
-  __shared__ T Di[NB][NB + 1];
-  __shared__ T ts[NB][4];
-  __shared__ T ys[NB][4];
-  const int64_t nblk = (n + NB - 1) / NB;
-  // forward: L y = b
-  for (int64_t bk = 0; bk < nblk; ++bk) {
-    const int64_t k0 = bk * NB;
-    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    const T* D = Dinv + bk * NB * NB;
-    for (int idx = threadIdx.x; idx < NB * NB; idx += 512) Di[idx / NB][idx % NB] = D[idx];
-    if (threadIdx.x < NB * 4) {
-      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
-      ts[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] : T(0);
-    }
-    __syncthreads();
-    if (threadIdx.x < NB * 4) {
-      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
-      T acc = T(0);
-      for (int c = 0; c <= r; ++c) acc += Di[r][c] * ts[c][q];
-      ys[r][q] = acc;
-      if (r < kb && q < nrhs) b[(k0 + r) * nrhs + q] = acc;
-    }
-    __syncthreads();
-    for (int64_t gr = k0 + kb + threadIdx.x; gr < n; gr += blockDim.x) {
-      T s[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 8
-      for (int c = 0; c < NB; ++c) {
-        const T l = c < kb ? Lt[(k0 + c) * n + gr] : T(0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += l * ys[c][q];
-      }
-      for (int q = 0; q < nrhs; ++q) b[gr * nrhs + q] -= s[q];
-    }
-    __syncthreads();
-  }
-  // backward: L^T x = y
-  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
-    const int64_t k0 = bk * NB;
-    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    const T* D = Dinv + bk * NB * NB;
-    for (int idx = threadIdx.x; idx < NB * NB; idx += 512) Di[idx / NB][idx % NB] = D[idx];
-    if (threadIdx.x < NB * 4) {
-      const int r = threadIdx.x / 4, q = threadIdx.x % 4;
-      ts[r][q] = (r < kb && q < nrhs) ? b[(k0 + r) * nrhs + q] : T(0);
-    }
-    __syncthreads();
-    if (threadIdx.x < NB * 4) {
-      const int c = threadIdx.x / 4, q = threadIdx.x % 4;
-      T acc = T(0);
-      for (int r = c; r < NB; ++r) acc += Di[r][c] * ts[r][q];
-      ys[c][q] = acc;
-      if (c < kb && q < nrhs) b[(k0 + c) * nrhs + q] = acc;
-    }
-    __syncthreads();
-    for (int64_t gc = threadIdx.x; gc < k0; gc += blockDim.x) {
-      T s[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 8
-      for (int c = 0; c < NB; ++c) {
-        const T l = c < kb ? L[(k0 + c) * n + gc] : T(0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += l * ys[c][q];
-      }
-      for (int q = 0; q < nrhs; ++q) b[gc * nrhs + q] -= s[q];
-    }
-    __syncthreads();
-  }
 }
 
 // Row-major triangular matrix times nrhs <= 4 vectors (n x nrhs row-major):
@@ -774,110 +878,25 @@ __global__ void __launch_bounds__(256) tri_gemv_kernel(const T* __restrict__ M, 
   }
 }
 
+// x = Y^T (Y b) with Y = L^-1 (F, row-major) and Y^T (aux): two triangular
+// products over all workgroups, for either block size.
 template <typename T>
 void dense_chol_solve(const T* L, T* aux, int64_t n, T* b, int32_t nrhs, hipStream_t st) {
   if (n <= 0) return;
-  if (dense_block(n) == 32) {
-    // x = Y^T (Y b) with Y = L^-1 (F, row-major) and Y^T (aux)
-    T* z = aux + dense_tmp_offset(n);
-    const unsigned g = static_cast<unsigned>((n + 3) / 4);
-    tri_gemv_kernel<T, true><<<g, 256, 0, st>>>(L, n, b, z, nrhs);
-    tri_gemv_kernel<T, false><<<g, 256, 0, st>>>(aux, n, z, b, nrhs);
-    return;
-  }
-  chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(L, aux, aux + n * n + n, n, b, nrhs);
+  T* z = aux + dense_tmp_offset(n);
+  const unsigned g = static_cast<unsigned>((n + 3) / 4);
+  tri_gemv_kernel<T, true><<<g, 256, 0, st>>>(L, n, b, z, nrhs);
+  tri_gemv_kernel<T, false><<<g, 256, 0, st>>>(aux, n, z, b, nrhs);
 }
 
-// ---- Y = L^-1, one workgroup per column block ----------------------------------
-// Block row kk >= j of column block j: Y_kk,j = L_kk^-1 (delta_kj I - sum_{j<=p<kk}
-// L_kp Y_pj); the sum is staged through LDS and L_kk^-1 is the stored
-// inverse of the diagonal block.  Blocks above the diagonal are zeroed.
-template <typename T, int NB>
-__global__ void __launch_bounds__(256) chol_linv_kernel(const T* __restrict__ L, const T* __restrict__ Dinv,
-                                                        int64_t n, T* __restrict__ Y) {
-  __shared__ T Ls[NB][NB + 1];
-  __shared__ T Ys[NB][NB + 1];
-  __shared__ T Tm[NB][NB + 1];
-  const int64_t nblk = (n + NB - 1) / NB;
-  const int64_t bj = blockIdx.x, j0 = bj * NB;
-  const int jb = static_cast<int>(n - j0 < NB ? n - j0 : NB);
-  for (int64_t r = threadIdx.x / NB; r < j0; r += 256 / NB) {
-    const int c = threadIdx.x % NB;
-    if (c < jb) Y[r * n + j0 + c] = T(0);
-  }
-  constexpr int TPR = 256 / NB, CPT = NB / TPR;               // threads per row, columns per thread
-  const int tr = threadIdx.x / TPR, tq = threadIdx.x % TPR;   // row tr, columns CPT tq .. CPT tq + CPT - 1
-  for (int64_t bk = bj; bk < nblk; ++bk) {
-    const int64_t k0 = bk * NB;
-    const int kb = static_cast<int>(n - k0 < NB ? n - k0 : NB);
-    T acc[CPT];
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) acc[c] = (bk == bj && tr == CPT * tq + c) ? T(1) : T(0);
-    for (int64_t bp = bj; bp < bk; ++bp) {
-      const int64_t p0 = bp * NB;
-#pragma unroll
-      for (int it = 0; it < NB * NB / 256; ++it) {
-        const int idx = threadIdx.x + 256 * it;
-        const int r = idx / NB, c = idx % NB;
-        Ls[r][c] = (r < kb) ? L[(k0 + r) * n + p0 + c] : T(0);
-        Ys[r][c] = (c < jb) ? Y[(p0 + r) * n + j0 + c] : T(0);
-      }
-      __syncthreads();
-      for (int s = 0; s < NB; ++s) {
-        const T l = Ls[tr][s];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) acc[c] -= l * Ys[s][CPT * tq + c];
-      }
-      __syncthreads();
-    }
-    // Y_kj = Dinv_k (delta_kj I - sum_p L_kp Y_pj): Tm holds the bracket, Ls
-    // the inverse of the diagonal block (identity-padded beyond the matrix)
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) Tm[tr][CPT * tq + c] = acc[c];
-    const T* D = Dinv + bk * NB * NB;
-#pragma unroll
-    for (int it = 0; it < NB * NB / 256; ++it) {
-      const int idx = threadIdx.x + 256 * it;
-      Ls[idx / NB][idx % NB] = D[idx];
-    }
-    __syncthreads();
-    T out[CPT];
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) out[c] = T(0);
-    for (int s = 0; s <= tr; ++s) {
-      const T d = Ls[tr][s];
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) out[c] += d * Tm[s][CPT * tq + c];
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c)
-      if (tr < kb && CPT * tq + c < jb) Y[(k0 + tr) * n + j0 + CPT * tq + c] = out[c];
-    __syncthreads();
-  }
-}
-
-bool dense_has_inverse(int64_t n) { return n > 0 && dense_block(n) == 32; }
-
-template <typename T>
-__global__ void copy_vec_kernel(const T* __restrict__ in, int64_t n, T* __restrict__ out) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = in[i];
-}
-
-// Single right-hand side into a separate output: x = Y^T (Y b) for 32-wide
-// blocks, else a copy and the in-place block solve.
+// Single right-hand side into a separate output.
 template <typename T>
 void dense_chol_solve_into(const T* F, T* aux, int64_t n, const T* b, T* x, hipStream_t st) {
   if (n <= 0) return;
-  if (dense_block(n) == 32) {
-    T* z = aux + dense_tmp_offset(n);
-    const unsigned g = static_cast<unsigned>((n + 3) / 4);
-    tri_gemv_kernel<T, true><<<g, 256, 0, st>>>(F, n, b, z, 1);
-    tri_gemv_kernel<T, false><<<g, 256, 0, st>>>(aux, n, z, x, 1);
-    return;
-  }
-  copy_vec_kernel<T><<<grid_for(n, 256), 256, 0, st>>>(b, n, x);
-  chol_solve_kernel<T, 64><<<1, 512, 0, st>>>(F, aux, aux + n * n + n, n, x, 1);
+  T* z = aux + dense_tmp_offset(n);
+  const unsigned g = static_cast<unsigned>((n + 3) / 4);
+  tri_gemv_kernel<T, true><<<g, 256, 0, st>>>(F, n, b, z, 1);
+  tri_gemv_kernel<T, false><<<g, 256, 0, st>>>(aux, n, z, x, 1);
 }
 
 // ---- iterative refinement on an FP32 inverse factor (32-wide blocks) ---------
@@ -1011,16 +1030,11 @@ __global__ void __launch_bounds__(256) yty_kernel(const T* __restrict__ Yt, int6
 
 template <typename T>
 void dense_chol_inverse(const T* L, const T* aux, int64_t n, T* Ainv, T* work, hipStream_t st) {
+  (void)L;
+  (void)work;
   if (n <= 0) return;
-  if (dense_block(n) == 32) {
-    const int64_t nb = (n + 31) / 32;
-    yty_kernel<T><<<static_cast<unsigned>(nb * (nb + 1) / 2), 256, 0, st>>>(aux, n, Ainv);
-    return;
-  }
-  chol_linv_kernel<T, 64><<<grid_for(n, 64), 256, 0, st>>>(L, aux + n * n + n, n, work);
-  const unsigned g = grid_for(n, 64);
-  dim3 grid(g, g);
-  gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(n, n, n, T(1), work, n, work, n, T(0), Ainv, n, 0);
+  const int64_t nb = (n + 31) / 32;
+  yty_kernel<T><<<static_cast<unsigned>(nb * (nb + 1) / 2), 256, 0, st>>>(aux, n, Ainv);
 }
 
 // ---- C^-1 after a small change of the contact set ---------------------------

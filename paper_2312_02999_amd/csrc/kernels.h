@@ -276,13 +276,12 @@ void set_last_error(const char* msg);
 
 // ---------------------------------------------------------------- dense SPD
 // Lower Cholesky of an n x n row-major SPD matrix A (destroyed: lower tiles by
-// the factorisation, strictly upper blocks as workspace).  With 32-wide blocks
-// (n <= 2048) F receives L^-1 (lower triangle, row-major) and aux its
-// transpose; with 64-wide blocks F receives L (lower triangle) and aux its
-// transpose Lt.  aux (dense_aux_size(n) entries) then holds 1 / diag(L) (n),
-// the inverses of the diagonal blocks and solve scratch (4 n).  The strict
-// upper part of F is not written.  *d_info <- 0 ok, else 1 + the first
-// failing column.
+// the factorisation, strictly upper blocks as workspace), 32-wide blocks up to
+// 2048 unknowns and 64-wide above.  F receives L^-1 (lower triangle,
+// row-major) and aux its transpose; aux (dense_aux_size(n) entries) then holds
+// 1 / diag(L) (n), the inverses of the diagonal blocks and solve scratch
+// (4 n).  The factor L itself is not kept, and the strict upper part of F is
+// not written.  *d_info <- 0 ok, else 1 + the first failing column.
 constexpr int64_t dense_blocks_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
 constexpr int64_t dense_tmp_offset(int64_t n) { return n * n + n + dense_blocks_size(n); }
 constexpr int64_t dense_aux_size(int64_t n) { return dense_tmp_offset(n) + 4 * n + 64; }
@@ -300,8 +299,6 @@ void dense_chol_solve(const T* F, T* aux, int64_t n, T* b, int32_t nrhs, hipStre
 // Single right-hand side, b -> x (no aliasing).
 template <typename T>
 void dense_chol_solve_into(const T* F, T* aux, int64_t n, const T* b, T* x, hipStream_t st);
-// True when dense_cholesky leaves L^-1 in F (32-wide blocks).
-bool dense_has_inverse(int64_t n);
 // Iterative refinement of M u = rhs with the FP32 inverse factor (F, aux) of
 // S M S, S = diag(sc): step s computes r_s = rhs - M u_s (u_0 = 0) in FP64,
 // res[s] = max |r_s| and r32 = float(S r_s) (launch_refine_residual), then

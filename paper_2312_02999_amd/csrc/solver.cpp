@@ -922,38 +922,6 @@ static bool refine_on_inverse(Solver* S, int64_t N3) {
   }
 }
 
-// Same refinement with a blocked FP32 factor (reduced systems above 2048
-// unknowns): one step is a scaled FP32 solve, an FP64 residual and its norm.
-static bool refine_on_blocks(Solver* S, int64_t N3) {
-  hipStream_t st = S->st;
-  launch_max_abs(S->rhs.p, N3, S->scal.p + 5, S->red_tmp.p, st);
-  launch_fill_f64(S->u.p, N3, 0.0, st);
-  HIPCHK(hipMemcpyAsync(S->resid.p, S->rhs.p, sizeof(double) * N3, hipMemcpyDeviceToDevice, st));
-  auto refine_step = [&]() {
-    launch_scale_convert_vec(S->resid.p, N3, S->scl.p, S->uf.p, st);
-    dense_chol_solve<float>(S->MLf.p, S->MLif.p, N3, S->uf.p, 1, st);
-    launch_scaled_accumulate(S->uf.p, N3, S->scl.p, S->u.p, st);
-    launch_dense_residual(S->Mred.p, N3, S->rhs.p, S->u.p, S->resid.p, st);
-    launch_max_abs(S->resid.p, N3, S->scal.p + 6, S->red_tmp.p, st);
-    S->refine_steps++;
-  };
-  constexpr int kQueued = 2;
-  for (int it = 0; it < kQueued; ++it) refine_step();
-  int done = kQueued;
-  while (true) {
-    HIPCHK(hipMemcpyAsync(S->h_scal, S->scal.p + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(S->h_scal + 2, S->info.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    int32_t finfo = 0;
-    std::memcpy(&finfo, S->h_scal + 2, sizeof(int32_t));
-    if (finfo != 0) return false;
-    if (S->h_scal[1] <= kRefineTol * S->h_scal[0]) return true;
-    if (done >= kRefineMaxSteps) return false;
-    refine_step();
-    ++done;
-  }
-}
-
 // Global step of Eq. (4) via Eq. (7) and (11): dx from g.
 static void global_step(Solver* S, IterOut& io) {
   hipStream_t st = S->st;
@@ -1117,7 +1085,7 @@ static void global_step(Solver* S, IterOut& io) {
     HIPCHK(hipStreamWaitEvent(st, S->ev_join, 0));
     bool fallback = false;
     if (mixed) {
-      const bool solved = dense_has_inverse(N3) ? refine_on_inverse(S, N3) : refine_on_blocks(S, N3);
+      const bool solved = refine_on_inverse(S, N3);
       if (!solved) {
         S->refine_fallbacks++;
         fallback = true;

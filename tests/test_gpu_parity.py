@@ -120,9 +120,10 @@ def test_frames_tiny_scene():
         assert err < 1e-9, (t, err)
 
 
-@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2100])
+@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2048, 2049, 2100, 3001])
 def test_dense_spd_kernels(n):
-    """Cholesky, solve and inverse against numpy at ragged multi-tile sizes."""
+    """Cholesky, solve and inverse against numpy at ragged multi-tile sizes,
+    on both sides of the switch from 32- to 64-wide blocks (2049)."""
     from paper_2312_02999_amd import dense_spd
     rng = np.random.default_rng(n)
     G = rng.standard_normal((n, n))
@@ -139,12 +140,13 @@ def test_dense_spd_kernels(n):
     assert np.abs(x1.cpu().numpy() - xr[:, 0]).max() < 1e-10 * max(1.0, np.abs(xr).max())
 
 
-def test_dense_spd_rejects_indefinite():
+@pytest.mark.parametrize("n,bad", [(70, 66), (2100, 2070), (2100, 40)])
+def test_dense_spd_rejects_indefinite(n, bad):
     from paper_2312_02999_amd import dense_spd, PdipcError
-    A = np.eye(70)
-    A[66, 66] = -1.0
+    A = np.eye(n)
+    A[bad, bad] = -1.0
     with pytest.raises(PdipcError):
-        dense_spd(_t(A), _t(np.ones((70, 1))))
+        dense_spd(_t(A), _t(np.ones((n, 1))))
 
 
 @pytest.mark.parametrize("fp32_reduced_min", [0, 2049])
