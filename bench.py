@@ -68,7 +68,7 @@ TIMED_FAMILIES = [("local_step_kernel", K_LOCAL), ("trial_energy_kernel", K_TRIA
                   ("barrier_kernel", K_BARRIER)]
 
 
-def run_precision(sc, precision, steps, warmup):
+def run_precision(sc, precision, steps, warmup, families=True, **solver_kw):
     import torch
     from paper_2312_02999_amd import Solver
     seq_np = sc.sequence()
@@ -76,8 +76,8 @@ def run_precision(sc, precision, steps, warmup):
         print(f"warmup + steps = {warmup + steps} exceeds the {len(seq_np)}-frame actuation sequence "
               f"of this workload: every timed frame must change actuation", file=sys.stderr)
         sys.exit(2)
-    S = Solver(sc, iters=sc.iters, precision=precision)
-    progress(f"solver ready ({'mixed' if precision else 'fp64'})")
+    S = Solver(sc, iters=sc.iters, precision=precision, **solver_kw)
+    progress(f"solver ready ({'mixed' if precision else 'fp64'}{' ' + str(solver_kw) if solver_kw else ''})")
     dev = "cuda"
     R = torch.from_numpy(np.ascontiguousarray(sc.act_R.reshape(-1, 9))).to(dev)
     seq = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in seq_np]
@@ -118,7 +118,7 @@ def run_precision(sc, precision, steps, warmup):
     # per-kernel-family durations: one more replay per family with the
     # library's HIP-event timer around that family's launches
     fam = {}
-    for name, k in TIMED_FAMILIES:
+    for name, k in (TIMED_FAMILIES if families else []):
         S.kernel_timer(k)
         replay(False)
         ms, cnt = S.kernel_timer(-1)
@@ -144,6 +144,7 @@ def run_precision(sc, precision, steps, warmup):
         "refine_fallbacks": sum(st["refine_fallbacks"] for st, _ in stats),
         "cinv_rebuilds": sum(st["cinv_rebuilds"] for st, _ in stats),
         "near_ties": sum(st["near_ties"] for st, _ in stats),
+        "cg_products": sum(st["pcg_iters"] for st, _ in stats),
         "stage_ms": {k: round(float(np.mean([st[k] for st, _ in stats])), 3)
                      for k in ("ms_ipc", "ms_gstep", "ms_ccd", "ms_ls", "ms_misc")},
         "x_final": x.cpu().numpy(),
@@ -279,6 +280,28 @@ def run_adjoint(sc, n_targets=500, n_dirs=2, n_params=4, h_dir=1e-4, seed=1):
             "checks": [{"kind": k, "index": i, "adjoint": ad, "fd": fd} for k, i, ad, fd in errs]}
 
 
+def run_table1(sc, steps, warmup, kappa0):
+    """The paper's Table 1 configurations with collision on this workload, all
+    FP64: the method (Schur complement and low-rank update), the Schur
+    complement alone and the conjugate-gradient baseline, at kappa and at
+    10 kappa (the paper states that 10x kappa nearly doubles the CG cost and
+    leaves the direct step unchanged).  Per-stage times per frame (Table 1
+    columns) and CG products per iteration."""
+    from paper_2312_02999_amd import FP64, GSTEP_PCG, GSTEP_SCHUR, GSTEP_SCHUR_WOODBURY
+    rows = []
+    for kappa in (kappa0, 10.0 * kappa0):
+        for name, gm in (("schur+low-rank update (the method)", GSTEP_SCHUR_WOODBURY),
+                         ("schur complement only", GSTEP_SCHUR), ("PCG baseline (Eq. 5)", GSTEP_PCG)):
+            r = run_precision(sc, FP64, steps, warmup, families=False, global_method=gm, kappa=kappa)
+            rows.append({"config": name, "kappa": kappa, "frames_per_s": round(r["fps"], 3),
+                         "ms_per_frame": round(r["ms_per_frame"], 2), "stage_ms": r["stage_ms"],
+                         "n_c_mean": round(r["n_c_mean"], 1), "n_c_max": r["n_c_max"],
+                         "cg_products_per_iteration": round(r["cg_products"] / max(r["iters_total"], 1), 1),
+                         "ls_failures": r["ls_failures"]})
+            progress(f"table 1: {name} at kappa {kappa:g} done")
+    return rows
+
+
 def summary(r):
     keys = ("n_c_max", "n_c_mean", "contact_iters", "iters_total", "pairs_max", "ls_failures", "refine_steps",
             "refine_fallbacks", "cinv_rebuilds", "near_ties", "stage_ms", "replay_bitwise_equal", "device_bytes")
@@ -302,6 +325,10 @@ def main():
                     help="time the adjoint on the workload and check it against finite differences")
     ap.add_argument("--serving", type=int, default=0, metavar="REQUESTS",
                     help="replay a Poisson stream of this many requests through the server instead")
+    ap.add_argument("--table1", action="store_true",
+                    help="time the Table 1 global-step configurations at kappa and 10 kappa instead")
+    ap.add_argument("--fp32-reduced-min", type=int, default=None,
+                    help="mixed path: smallest reduced system solved with the refined FP32 factor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -325,19 +352,32 @@ def main():
     if args.adjoint:
         print(json.dumps(run_adjoint(sc)))
         return
+    if args.table1:
+        rows = run_table1(sc, args.steps, args.warmup, sc.kappa)
+        print(json.dumps({"metric": "Table 1 global-step configurations: frames/s and stage ms per frame",
+                          "workload": f"{args.workload}: n={sc.n} m={sc.m}, {sc.iters} iterations/frame, frames "
+                                      f"{args.warmup}..{args.warmup + args.steps - 1} of the keyframed sequence",
+                          "rows": rows}))
+        return
+    mixed_kw = {} if args.fp32_reduced_min is None else {"fp32_reduced_min": args.fp32_reduced_min}
     if args.only:
         prec = FP64 if args.only == "fp64" else MIXED_FP32
-        r = run_precision(sc, prec, args.steps, args.warmup)
+        r = run_precision(sc, prec, args.steps, args.warmup, **(mixed_kw if prec == MIXED_FP32 else {}))
         r.pop("x_final")
         out = {"only": args.only, **summary(r), "rooflines": rooflines(sc, r, "f64")}
         print(json.dumps(out))
         return
     fp64 = run_precision(sc, FP64, args.steps, args.warmup)
-    mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup)
+    mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup, **mixed_kw)
+    # the mixed path with the FP32 reduced factor (refined against FP64
+    # residuals) from 2049 unknowns on, for comparison with the default
+    mixed32 = run_precision(sc, MIXED_FP32, args.steps, args.warmup, families=False, fp32_reduced_min=2049)
     diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
     mixed_vs_fp64 = float(np.abs(mixed["x_final"] - fp64["x_final"]).max() / diag)
-    # the mixed path factors the reduced system in FP32 from 2049 unknowns on
-    red_type = "f32" if 3 * mixed["n_c_mean"] >= 2049 else "f64"
+    # the mixed path factors the reduced system in FP32 from fp32_reduced_min
+    # unknowns on (library default 8192)
+    thr = 8192 if args.fp32_reduced_min is None else args.fp32_reduced_min
+    red_type = "f32" if 3 * mixed["n_c_mean"] >= thr else "f64"
     roofs_fp64 = rooflines(sc, fp64, "f64")
     roofs_mixed = rooflines(sc, mixed, red_type)
     # the headline's roofline: the mixed path's kernel family with the most
@@ -366,6 +406,8 @@ def main():
         "p50_ms": round(mixed["p50_ms"], 3), "p99_ms": round(mixed["p99_ms"], 3),
         "fp64": summary(fp64),
         "mixed": {**summary(mixed), "reduced_factor_type": red_type, "max_rel_pos_diff_vs_fp64": mixed_vs_fp64},
+        "mixed_fp32_reduced_from_2049": {**summary(mixed32),
+                                         "max_rel_pos_diff_vs_fp64": float(np.abs(mixed32["x_final"] - fp64["x_final"]).max() / diag)},
         "roofline": roof,
         "rooflines": {"mixed": roofs_mixed, "fp64": roofs_fp64},
         "cpu_baseline": cpu,

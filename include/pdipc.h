@@ -128,13 +128,28 @@ typedef struct {
  *                  sweep runs on the uncorrected step while the reduced system
  *                  is factored; 0 = off (correct x2, then sweep)
  *  fp32_reduced_min  mixed precision: smallest reduced system (3 n_c unknowns)
- *                  solved with the refined FP32 factor; smaller ones, whose
- *                  factorisation is bound by its sequence of block steps
- *                  rather than by arithmetic, use the FP64 factor
+ *                  solved with the refined FP32 factor (default 8192); smaller
+ *                  ones use the FP64 factor.  Up to a few thousand unknowns
+ *                  the factorisation is bound by its sequence of block steps,
+ *                  not by arithmetic, so the FP32 factor saves little there
+ *                  and its refinement (and FP64 refactorisation when FP32
+ *                  breaks down) costs more
  *  stream          hipStream_t to order work on (NULL = default stream)
  *  global_method   PDIPC_GSTEP_* (above)
  *  cg_tol, cg_max_iters  PDIPC_GSTEP_PCG: stop when |r| <= cg_tol |g| over the
  *                  free DOFs, or after cg_max_iters products
+ *  barrier_form    0: IPC's b(d) = -(d - dhat)^2 ln(d / dhat) on the distance
+ *                  d (Eq. 3 as read); 1: the same function of the squared
+ *                  distance d^2 with threshold dhat^2.  Both select the same
+ *                  pairs (d < dhat)
+ *  kappa_adapt     0: kappa fixed; 1: IPC-style adaptive stiffness (Section 4
+ *                  mentions it): at the start of a frame with pairs, kappa =
+ *                  -(g_E . g_b) / (g_b . g_b) clamped to [kappa, 100 kappa] (g_E
+ *                  the elastic gradient, g_b that of the unit barrier); later,
+ *                  kappa doubles (up to 100 kappa) at an iteration whose
+ *                  smallest squared pair distance is below 1e-9 l^2 (l: rest
+ *                  bounding-box diagonal) and below the previous iteration's.
+ *                  The adjoint uses the last iteration's kappa.
  */
 typedef struct {
   double dhat, kappa;
@@ -147,6 +162,7 @@ typedef struct {
   int32_t global_method;
   double cg_tol;
   int32_t cg_max_iters;
+  int32_t barrier_form, kappa_adapt;
 } pdipc_options;
 
 /* Per-frame statistics (host).  Stage times follow the paper's Table 1
@@ -175,7 +191,8 @@ typedef struct {
 
 /* Fill *opt with defaults: dhat 5e-4, kappa 1e3, 30 iters, fixed mode, FP64,
  * eta 0.1, 16 CCD steps, 20 halvings, default stream, the Schur-complement and
- * low-rank-update global step (CG: tolerance 1e-12, at most 2000 products). */
+ * low-rank-update global step (CG: tolerance 1e-12, at most 2000 products),
+ * barrier form 0, fixed kappa. */
 void pdipc_default_options(pdipc_options* opt);
 
 /* Build a solver: validate the mesh, precompute per-tet data, assemble the

@@ -21,10 +21,11 @@ extern "C" {
  * candidates of the CCD step, line-search halvings and outcome, near ties of
  * the constraint set, refinement solves of the reduced system, and the step
  * bound alpha_m and accepted step alpha; cg_iters: products of the conjugate-gradient
- * global step (PDIPC_GSTEP_PCG). */
+ * global step (PDIPC_GSTEP_PCG); kappa: the barrier stiffness of the
+ * iteration. */
 typedef struct {
   int32_t n_pt, n_ee, n_c, n_candidates, ls_halvings, ls_ok, near_ties, refine_steps, cg_iters;
-  double alpha_m, alpha;
+  double alpha_m, alpha, kappa;
 } pdipc_iter_trace;
 
 /* Copy up to cap iteration records of the last frame into out (host); the

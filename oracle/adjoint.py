@@ -63,7 +63,7 @@ def energy_hessian(prob, x, a, R0):
     cs = contact.constraint_set(x, prob.prox, prob.dhat)
     if cs.size:
         X4 = contact.pair_points(x, prob.prox, cs.pt, cs.ee)
-        _, _, Hp = barrier.pair_derivatives(X4, cs.kind, cs.idx, prob.dhat, prob.kappa)
+        _, _, Hp = barrier.pair_derivatives(X4, cs.kind, cs.idx, prob.dhat, prob.kappa, prob.barrier_form)
         V4 = contact.pair_vertices(prob.prox, cs.pt, cs.ee)
         pd = (3 * V4[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
         rows.append(np.repeat(pd, 12, axis=1).reshape(-1))

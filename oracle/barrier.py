@@ -5,7 +5,11 @@ Oracle module (test infrastructure only).
 Readings:
 * b(d) = -(d - dhat)^2 ln(d / dhat) for 0 < d < dhat, else 0 -- the barrier of
   Incremental Potential Contact on the unsigned distance d (the paper only
-  says "logarithm-like", active below the threshold d_0 = dhat).
+  says "logarithm-like", active below the threshold d_0 = dhat).  This is
+  form 0.  Form 1 is the same function of the squared distance D = d^2 with
+  threshold dhat^2: b(D) = -(D - dhat^2)^2 ln(D / dhat^2) for D < dhat^2 (the
+  squared-distance variant used by IPC implementations).  Both vanish with
+  their first two derivatives at the threshold and select the same pairs.
 * B(x) = kappa * sum_k b(d_k(x)) (Eq. 3).
 * "PositiveDefinite" (Algorithm 1) is read as: per pair, eigen-decompose the
   12 x 12 Hessian and clamp negative eigenvalues to zero.
@@ -24,18 +28,30 @@ from torch.func import grad, hessian, vmap
 from . import geometry as geo
 
 
-def barrier(d, dhat):
-    """b(d) for an array of distances (numpy)."""
+def barrier(d, dhat, form: int = 0):
+    """b for an array of distances d (numpy): b(d) (form 0) or b(d^2) with
+    threshold dhat^2 (form 1)."""
     d = np.asarray(d, dtype=np.float64)
     out = np.zeros_like(d)
     act = (d > 0) & (d < dhat)
     dd = d[act]
-    out[act] = -((dd - dhat) ** 2) * np.log(dd / dhat)
+    if form == 0:
+        out[act] = -((dd - dhat) ** 2) * np.log(dd / dhat)
+    else:
+        D, Dh = dd * dd, dhat * dhat
+        out[act] = -((D - Dh) ** 2) * np.log(D / Dh)
     return out
 
 
 def _b_torch(d, dhat):
     return -((d - dhat) ** 2) * torch.log(d / dhat)
+
+
+def _b_of_sqdist(D, dhat, form):
+    """The barrier as a function of the squared distance D (torch)."""
+    if form == 0:
+        return _b_torch(torch.sqrt(D), dhat)
+    return _b_torch(D, dhat * dhat)
 
 
 def _sqdist(kind: int, P):
@@ -75,12 +91,12 @@ def _make_sqdist_fn(kd, sel):
     return f
 
 
-def _make_barrier_fn(kd, sel, dhat, kappa):
+def _make_barrier_fn(kd, sel, dhat, kappa, form=0):
     sel = list(sel)
 
     def f(x12):
         D = _sqdist(kd, x12.reshape(4, 3)[sel])
-        return kappa * _b_torch(torch.sqrt(D), dhat)
+        return kappa * _b_of_sqdist(D, dhat, form)
     return f
 
 
@@ -92,11 +108,12 @@ def _groups(kind, idx):
     return {k: np.asarray(v) for k, v in groups.items()}
 
 
-def pair_derivatives(X4: np.ndarray, kind: np.ndarray, idx: np.ndarray, dhat: float, kappa: float):
+def pair_derivatives(X4: np.ndarray, kind: np.ndarray, idx: np.ndarray, dhat: float, kappa: float,
+                     form: int = 0):
     """kappa b, its gradient (k, 12) and Hessian (k, 12, 12) for active pairs.
 
     X4 (k, 4, 3): the four points of each pair in local order.  All pairs
-    must satisfy 0 < d < dhat.
+    must satisfy 0 < d < dhat.  form: 0 = b(d), 1 = b(d^2) (see above).
     """
     k = X4.shape[0]
     E = np.zeros(k)
@@ -104,7 +121,7 @@ def pair_derivatives(X4: np.ndarray, kind: np.ndarray, idx: np.ndarray, dhat: fl
     H = np.zeros((k, 12, 12))
     for (kd, sel), rows in _groups(kind, idx).items():
         Xt = torch.from_numpy(np.ascontiguousarray(X4[rows].reshape(len(rows), 12)))
-        f = _make_barrier_fn(kd, sel, dhat, kappa)
+        f = _make_barrier_fn(kd, sel, dhat, kappa, form)
         E[rows] = vmap(f)(Xt).numpy()
         G[rows] = vmap(grad(f))(Xt).numpy()
         H[rows] = vmap(hessian(f))(Xt).numpy()

@@ -18,7 +18,17 @@ Readings:
   pairs entering the threshold along the step are counted;
 * "while not converged" = a fixed number of iterations, or, in tolerance
   mode, until max |alpha dx| <= tol;
-* fixed (Dirichlet) vertices stay at their rest positions and carry no DOFs.
+* fixed (Dirichlet) vertices stay at their rest positions and carry no DOFs;
+* adaptive barrier stiffness (optional; the paper says only that IPC
+  initialises kappa from the average stiffness and adjusts it adaptively): at
+  the start of a frame, if the constraint set at x_t is not empty, kappa is the
+  value that best balances the elastic and barrier gradients,
+  argmin_k |g_E + k g_b|^2 = -(g_E . g_b) / (g_b . g_b) over the free DOFs
+  (g_E the PD gradient, g_b the gradient of sum_k b(d_k)), clamped to
+  [kappa_0, 100 kappa_0]; else kappa_0.  At each later iteration, when the
+  smallest squared distance of the constraint set falls below 1e-9 l^2 (l the
+  rest bounding-box diagonal) and below its value at the previous iteration,
+  kappa doubles, up to 100 kappa_0.  Every frame starts again from kappa_0.
 """
 from __future__ import annotations
 
@@ -44,13 +54,16 @@ class Problem:
     free: np.ndarray
     dhat: float
     kappa: float
+    barrier_form: int = 0
+    kappa_adapt: bool = False
 
     @property
     def n(self):
         return self.X.shape[0]
 
 
-def setup(X, tets, dirichlet, surf_tris, youngs, poisson, dhat, kappa) -> Problem:
+def setup(X, tets, dirichlet, surf_tris, youngs, poisson, dhat, kappa, barrier_form=0,
+          kappa_adapt=False) -> Problem:
     X = np.asarray(X, dtype=np.float64)
     tets = np.asarray(tets, dtype=np.int64)
     _, B, V = fem.rest_data(X, tets)
@@ -59,12 +72,13 @@ def setup(X, tets, dirichlet, surf_tris, youngs, poisson, dhat, kappa) -> Proble
     H = fem.assemble_H(X.shape[0], tets, G, w)
     free = fem.free_dofs(dirichlet)
     return Problem(X=X, tets=tets, dirichlet=np.asarray(dirichlet), prox=contact.make_proxy(surf_tris),
-                   B=B, V=V, w=w, G=G, H=H, free=free, dhat=float(dhat), kappa=float(kappa))
+                   B=B, V=V, w=w, G=G, H=H, free=free, dhat=float(dhat), kappa=float(kappa),
+                   barrier_form=int(barrier_form), kappa_adapt=bool(kappa_adapt))
 
 
-def setup_scene(scene) -> Problem:
+def setup_scene(scene, barrier_form=0, kappa_adapt=False) -> Problem:
     return setup(scene.X, scene.tets, scene.dirichlet, scene.surf_tris, scene.youngs,
-                 scene.poisson, scene.dhat, scene.kappa)
+                 scene.poisson, scene.dhat, scene.kappa, barrier_form, kappa_adapt)
 
 
 def pd_gradient(prob: Problem, F: np.ndarray, P: np.ndarray) -> np.ndarray:
@@ -81,13 +95,14 @@ def pair_dofs(prob: Problem, cs: contact.ConstraintSet) -> np.ndarray:
     return (3 * V4[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
 
 
-def barrier_terms(prob: Problem, x: np.ndarray, cs: contact.ConstraintSet):
+def barrier_terms(prob: Problem, x: np.ndarray, cs: contact.ConstraintSet, kappa: float | None = None):
     """(energy, gradient (3n), PSD-projected Hessian (sparse 3n x 3n), raw pieces)."""
+    kappa = prob.kappa if kappa is None else kappa
     n3 = 3 * prob.n
     if cs.size == 0:
         return 0.0, np.zeros(n3), sp.csc_matrix((n3, n3)), (np.zeros(0), np.zeros((0, 12)), np.zeros((0, 12, 12)))
     X4 = contact.pair_points(x, prob.prox, cs.pt, cs.ee)
-    E, Gp, Hp = barrier.pair_derivatives(X4, cs.kind, cs.idx, prob.dhat, prob.kappa)
+    E, Gp, Hp = barrier.pair_derivatives(X4, cs.kind, cs.idx, prob.dhat, kappa, prob.barrier_form)
     Hp = barrier.project_psd(Hp)
     dofs = pair_dofs(prob, cs)
     g = np.zeros(n3)
@@ -98,21 +113,22 @@ def barrier_terms(prob: Problem, x: np.ndarray, cs: contact.ConstraintSet):
     return float(E.sum()), g, Bm, (E, Gp, Hp)
 
 
-def total_energy_terms(prob: Problem, x, A, pt, ee):
+def total_energy_terms(prob: Problem, x, A, pt, ee, kappa: float | None = None):
     """Per-element PD energies and per-candidate barrier energies at x."""
+    kappa = prob.kappa if kappa is None else kappa
     F = local.deformation_gradients(x, prob.tets, prob.B)
     Ee = local.element_energies(F, A, prob.w)
     d2, _, _ = contact.pair_distances(x, prob.prox, pt, ee)
-    Eb = prob.kappa * barrier.barrier(np.sqrt(d2), prob.dhat)
+    Eb = kappa * barrier.barrier(np.sqrt(d2), prob.dhat, prob.barrier_form)
     return Ee, Eb
 
 
-def line_search(prob: Problem, x, dx, A, alpha_m, pt, ee, max_halvings=20):
+def line_search(prob: Problem, x, dx, A, alpha_m, pt, ee, max_halvings=20, kappa: float | None = None):
     """Back-tracking from alpha_m on the energy difference; returns (alpha, halvings, ok)."""
-    Ee0, Eb0 = total_energy_terms(prob, x, A, pt, ee)
+    Ee0, Eb0 = total_energy_terms(prob, x, A, pt, ee, kappa)
     alpha = alpha_m
     for h in range(max_halvings + 1):
-        Ee1, Eb1 = total_energy_terms(prob, x + alpha * dx, A, pt, ee)
+        Ee1, Eb1 = total_energy_terms(prob, x + alpha * dx, A, pt, ee, kappa)
         dE = np.sum(Ee1 - Ee0) + np.sum(Eb1 - Eb0)
         if dE <= 0:
             return alpha, h, True
@@ -136,6 +152,7 @@ class IterRecord:
     halvings: int
     swept_pt: np.ndarray
     swept_ee: np.ndarray
+    kappa: float = 0.0
 
 
 @dataclass
@@ -149,6 +166,7 @@ class FrameResult:
     n_c: list = field(default_factory=list)
     ls_failed: int = 0
     trace: list = field(default_factory=list)
+    kappa: list = field(default_factory=list)
 
 
 def affected_vertices(prob: Problem, cs: contact.ConstraintSet) -> np.ndarray:
@@ -160,14 +178,30 @@ def affected_vertices(prob: Problem, cs: contact.ConstraintSet) -> np.ndarray:
     return v[prob.dirichlet[v] == 0]
 
 
-def iteration(prob: Problem, x: np.ndarray, A: np.ndarray, max_halvings=20):
+def balanced_kappa(prob: Problem, x: np.ndarray, A: np.ndarray, cs: contact.ConstraintSet) -> float:
+    """argmin_k |g_E + k g_b|^2 over the free DOFs (g_b: the gradient of the
+    unit-stiffness barrier), clamped to [kappa_0, 100 kappa_0]; kappa_0 with no
+    pair."""
+    if cs.size == 0:
+        return prob.kappa
+    F = local.deformation_gradients(x, prob.tets, prob.B)
+    _, P = local.projections(F, A)
+    gE = pd_gradient(prob, F, P)[prob.free]
+    gb = barrier_terms(prob, x, cs, kappa=1.0)[1][prob.free]
+    bb = float(gb @ gb)
+    k = -float(gE @ gb) / bb if bb > 0 else prob.kappa
+    return min(max(k, prob.kappa), 100.0 * prob.kappa)
+
+
+def iteration(prob: Problem, x: np.ndarray, A: np.ndarray, max_halvings=20, kappa: float | None = None):
     """One pass of the Algorithm 1 loop body. Returns (x_new, IterRecord)."""
+    kappa = prob.kappa if kappa is None else kappa
     F = local.deformation_gradients(x, prob.tets, prob.B)
     R, P = local.projections(F, A)
     cs = contact.constraint_set(x, prob.prox, prob.dhat)
     if cs.size and np.any(cs.d2 <= 0):
         raise ValueError("state is not intersection-free")
-    _, gB, Bm, (pE, pg, pH) = barrier_terms(prob, x, cs)
+    _, gB, Bm, (pE, pg, pH) = barrier_terms(prob, x, cs, kappa)
     g = pd_gradient(prob, F, P) + gB
     f = prob.free
     K = (prob.H + Bm).tocsc()[f][:, f]
@@ -176,10 +210,10 @@ def iteration(prob: Problem, x: np.ndarray, A: np.ndarray, max_halvings=20):
     dx[f] = dxf
     dx = dx.reshape(-1, 3)
     alpha_m, spt, see = ccd.step_bound(x, dx, prob.prox, prob.dhat)
-    alpha, h, ok = line_search(prob, x, dx, A, alpha_m, spt, see, max_halvings)
+    alpha, h, ok = line_search(prob, x, dx, A, alpha_m, spt, see, max_halvings, kappa)
     rec = IterRecord(x=x.copy(), R=R, P=P, cs=cs, pair_E=pE, pair_g=pg, pair_H=pH,
                      g=g, dx=dx, alpha_m=alpha_m, alpha=alpha, halvings=h,
-                     swept_pt=spt, swept_ee=see)
+                     swept_pt=spt, swept_ee=see, kappa=kappa)
     return x + alpha * dx, rec, ok
 
 
@@ -189,8 +223,20 @@ def frame(prob: Problem, x_t: np.ndarray, A: np.ndarray, iters: int = 30, tol: f
     x = np.array(x_t, dtype=np.float64, copy=True)
     res = FrameResult(x=x, iters=0)
     n_it = max_iters if tol is not None else iters
+    kappa = prob.kappa
+    eps_d2 = 1e-9 * float(np.sum((prob.X.max(0) - prob.X.min(0)) ** 2))
+    d2_prev = np.inf
     for k in range(n_it):
-        x_new, rec, ok = iteration(prob, x, A, max_halvings)
+        if prob.kappa_adapt:
+            cs = contact.constraint_set(x, prob.prox, prob.dhat)
+            d2_min = float(cs.d2.min()) if cs.size else np.inf
+            if k == 0:
+                kappa = balanced_kappa(prob, x, A, cs)
+            elif d2_min < eps_d2 and d2_min < d2_prev:
+                kappa = min(2.0 * kappa, 100.0 * prob.kappa)
+            d2_prev = d2_min
+        res.kappa.append(kappa)
+        x_new, rec, ok = iteration(prob, x, A, max_halvings, kappa)
         res.alpha_m.append(rec.alpha_m)
         res.alpha.append(rec.alpha)
         res.n_pt.append(len(rec.cs.pt))

@@ -45,14 +45,20 @@ class Solver:
     """
 
     def __init__(self, scene=None, *, X=None, tets=None, dirichlet=None, surf_tris=None, region=None,
-                 youngs=1e4, poisson=0.45, dhat=5e-4, kappa=1e3, iters=30, tol=0.0, precision=FP64,
+                 youngs=None, poisson=None, dhat=None, kappa=None, iters=30, tol=0.0, precision=FP64,
                  ccd_eta=0.1, ccd_steps=16, ls_max_halvings=20, cinv_updates_max=16,
-                 fp32_reduced_min=2049, hinv_rows_mb=4096, device="cuda", stream=None, W=None,
-                 global_method=0, cg_tol=1e-12, cg_max_iters=2000):
+                 fp32_reduced_min=8192, hinv_rows_mb=4096, device="cuda", stream=None, W=None,
+                 global_method=0, cg_tol=1e-12, cg_max_iters=2000, barrier_form=0, kappa_adapt=False):
+        # material and barrier parameters: explicit arguments, else the
+        # scene's, else E = 1e4, nu = 0.45, dhat = 5e-4, kappa = 1e3
+        defaults = {"youngs": 1e4, "poisson": 0.45, "dhat": 5e-4, "kappa": 1e3}
+        given = {"youngs": youngs, "poisson": poisson, "dhat": dhat, "kappa": kappa}
         if scene is not None:
             X, tets, dirichlet, surf_tris = scene.X, scene.tets, scene.dirichlet, scene.surf_tris
             region = scene.region
-            youngs, poisson, dhat, kappa = scene.youngs, scene.poisson, scene.dhat, scene.kappa
+            defaults = {k: getattr(scene, k) for k in defaults}
+        youngs, poisson, dhat, kappa = (given[k] if given[k] is not None else defaults[k]
+                                        for k in ("youngs", "poisson", "dhat", "kappa"))
         self.device = torch.device(device)
         self._X = np.ascontiguousarray(X, dtype=np.float64)
         self._tets = np.ascontiguousarray(tets, dtype=np.int32)
@@ -79,7 +85,7 @@ class Solver:
         op = Options(float(dhat), float(kappa), int(iters), float(tol), int(precision), float(ccd_eta),
                      int(ccd_steps), int(ls_max_halvings), int(cinv_updates_max),
                      int(fp32_reduced_min), int(hinv_rows_mb), C.c_void_p(st.cuda_stream), int(global_method),
-                     float(cg_tol), int(cg_max_iters))
+                     float(cg_tol), int(cg_max_iters), int(barrier_form), int(bool(kappa_adapt)))
         h = C.c_void_p()
         check(lib().pdipc_init_mesh(C.byref(md), C.byref(op), C.byref(h)), None)
         self._h = h

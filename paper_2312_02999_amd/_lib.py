@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("ccd_eta", C.c_double), ("ccd_steps", C.c_int32),
                 ("ls_max_halvings", C.c_int32), ("cinv_updates_max", C.c_int32),
                 ("fp32_reduced_min", C.c_int32), ("hinv_rows_mb", C.c_int32), ("stream", C.c_void_p),
-                ("global_method", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iters", C.c_int32)]
+                ("global_method", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iters", C.c_int32),
+                ("barrier_form", C.c_int32), ("kappa_adapt", C.c_int32)]
 
 
 class FrameStats(C.Structure):
@@ -66,7 +67,8 @@ class FrameStats(C.Structure):
 class IterTrace(C.Structure):
     _fields_ = [("n_pt", C.c_int32), ("n_ee", C.c_int32), ("n_c", C.c_int32), ("n_candidates", C.c_int32),
                 ("ls_halvings", C.c_int32), ("ls_ok", C.c_int32), ("near_ties", C.c_int32),
-                ("refine_steps", C.c_int32), ("cg_iters", C.c_int32), ("alpha_m", C.c_double), ("alpha", C.c_double)]
+                ("refine_steps", C.c_int32), ("cg_iters", C.c_int32), ("alpha_m", C.c_double), ("alpha", C.c_double),
+                ("kappa", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

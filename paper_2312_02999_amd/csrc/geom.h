@@ -211,12 +211,38 @@ __device__ __forceinline__ void load_pair_rel_step(const int32_t* v4, const doub
     for (int r = 0; r < 3; ++r) P[k][r] = q[k][r] - q[0][r];
 }
 
-// IPC barrier b(d) = -(d - dhat)^2 ln(d / dhat) on 0 < d < dhat and its first
-// two derivatives in d.
-__device__ __forceinline__ double barrier_b(double d, double dhat) {
-  if (!(d < dhat)) return 0.0;
-  double e = d - dhat;
-  return -e * e * log(d / dhat);
+// Barrier of a pair at squared distance D (0 < D < dhat^2), the energy
+// kappa b and its first two derivatives in D (phi1 = dE/dD, phi2 = d2E/dD2):
+// form 0 is IPC's b(d) = -(d - dhat)^2 ln(d / dhat) on d = sqrt(D); form 1 is
+// the same function of D with threshold dhat^2, -(D - dhat^2)^2 ln(D / dhat^2).
+template <typename T>
+__device__ __forceinline__ void barrier_of_D(T D, T dhat, T kappa, int form, T& e, T& phi1, T& phi2) {
+  if (form == 0) {
+    const T d = sqrt(D);
+    const T u = d - dhat, lg = log(d / dhat);
+    const T b1 = -T(2) * u * lg - u * u / d;
+    const T b2 = -T(2) * lg - T(4) * u / d + u * u / (d * d);
+    e = -kappa * u * u * lg;
+    phi1 = kappa * b1 / (T(2) * d);
+    phi2 = kappa * (b2 - b1 / d) / (T(4) * D);
+  } else {
+    const T Dh = dhat * dhat;
+    const T u = D - Dh, lg = log(D / Dh);
+    e = -kappa * u * u * lg;
+    phi1 = kappa * (-T(2) * u * lg - u * u / D);
+    phi2 = kappa * (-T(2) * lg - T(4) * u / D + u * u / (D * D));
+  }
+}
+
+// b at squared distance D (0 < D), zero from the threshold on.
+__device__ __forceinline__ double barrier_b_of_D(double D, double dhat, int form) {
+  if (!(D < dhat * dhat)) return 0.0;
+  if (form == 0) {
+    const double d = sqrt(D), u = d - dhat;
+    return -u * u * log(d / dhat);
+  }
+  const double Dh = dhat * dhat, u = D - Dh;
+  return -u * u * log(D / Dh);
 }
 
 }  // namespace pdipc

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(AT) pd_hessvec_kernel(LocalArgs la, const doub
 __global__ void __launch_bounds__(64) barrier_hessvec_kernel(const int32_t* __restrict__ v4all, int32_t npairs,
                                                              int32_t n_pt, const double* __restrict__ x,
                                                              const double* __restrict__ v, double dhat, double kappa,
-                                                             double* __restrict__ out) {
+                                                             int form, double* __restrict__ out) {
   int32_t k = blockIdx.x * 64 + threadIdx.x;
   if (k >= npairs) return;
   int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
@@ -134,12 +134,9 @@ __global__ void __launch_bounds__(64) barrier_hessvec_kernel(const int32_t* __re
       Dk[0][r] += f.dcdb[0][j] * P[j][r];
       Dk[1][r] += f.dcdb[1][j] * P[j][r];
     }
-  const double D = dot3(q, q), d = sqrt(D);
-  const double e = d - dhat, lg = log(d / dhat);
-  const double b1 = -2.0 * e * lg - e * e / d;
-  const double b2 = -2.0 * lg - 4.0 * e / d + e * e / (d * d);
-  const double phi1 = kappa * b1 / (2.0 * d);
-  const double phi2 = kappa * (b2 - b1 / d) / (4.0 * D);
+  const double D = dot3(q, q);
+  double eb, phi1, phi2;
+  barrier_of_D<double>(D, dhat, kappa, form, eb, phi1, phi2);
   double vl[12];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -263,11 +260,12 @@ __global__ void __launch_bounds__(256) add_pair_vec_kernel(int32_t nsv, const in
 void launch_hessvec(const LocalArgs& la, int32_t n, const int32_t* vt_ptr, const int32_t* vt_ent,
                     const uint8_t* fixed, const double* x, const double* Rrot, const double* v, double* tetg,
                     const PairList& pl, int32_t npairs, int32_t n_pt, const Incidence& inc, const ProxyDev& px,
-                    double dhat, double kappa, double* pairbuf, double* out, hipStream_t st) {
+                    double dhat, double kappa, int form, double* pairbuf, double* out, hipStream_t st) {
   pd_hessvec_kernel<<<grid_for(la.m, AT), AT, 0, st>>>(la, x, Rrot, v, tetg);
   launch_gather_vertex_grad(n, la.m, vt_ptr, vt_ent, tetg, fixed, out, st);
   if (npairs > 0) {
-    barrier_hessvec_kernel<<<grid_for(npairs, 64), 64, 0, st>>>(pl.v4, npairs, n_pt, x, v, dhat, kappa, pairbuf);
+    barrier_hessvec_kernel<<<grid_for(npairs, 64), 64, 0, st>>>(pl.v4, npairs, n_pt, x, v, dhat, kappa, form,
+                                                                  pairbuf);
     add_pair_vec_kernel<<<grid_for(px.nsv, 256), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent, pairbuf, npairs,
                                                               fixed, out);
   }

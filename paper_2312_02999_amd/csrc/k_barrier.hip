@@ -78,7 +78,7 @@ __device__ __forceinline__ void sym_eig_jacobi5(T A[5][5], T V[5][5]) {
 // mixed path: the cancellation-prone geometry, e.g. nearly parallel edges,
 // stays in FP64).
 template <typename T, typename TE = T>
-__device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, double kappa, double& energy,
+__device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, double kappa, int form, double& energy,
                              double grad[12], double U[12][5]) {
   T P[4][3];
 #pragma unroll
@@ -97,17 +97,9 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
       Dk[1][r] += f.dcdb[1][j] * P[j][r];
     }
   const T D = dot3(q, q);
-  const T d = sqrt(D);
-  const T th = static_cast<T>(dhat);
-  const T e = d - th;
-  const T lg = log(d / th);
-  const T b0 = -e * e * lg;
-  const T b1 = -T(2) * e * lg - e * e / d;
-  const T b2 = -T(2) * lg - T(4) * e / d + e * e / (d * d);
-  const T kap = static_cast<T>(kappa);
-  const T phi1 = kap * b1 / (T(2) * d);
-  const T phi2 = kap * (b2 - b1 / d) / (T(4) * D);
-  energy = static_cast<double>(kap * b0);
+  T eb, phi1, phi2;
+  barrier_of_D<T>(D, static_cast<T>(dhat), static_cast<T>(kappa), form, eb, phi1, phi2);
+  energy = static_cast<double>(eb);
   T gD[12];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -241,7 +233,7 @@ __device__ void pair_barrier(const double Pd[4][3], bool is_pt, double dhat, dou
 
 __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,
                                                      const double* __restrict__ x, double dhat, double kappa,
-                                                     bool fp32, double* __restrict__ energy,
+                                                     int form, bool fp32, double* __restrict__ energy,
                                                      double* __restrict__ grad, double* __restrict__ U) {
   int32_t k = blockIdx.x * BT + threadIdx.x;
   if (k >= npairs) return;
@@ -252,9 +244,9 @@ __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__
   if (fp32) {
     // FP32 eigen-decomposition of the projected Hessian; everything else,
     // including the energy and gradient that fix the equilibrium, in FP64
-    pair_barrier<double, float>(P, k < n_pt, dhat, kappa, e, g, u);
+    pair_barrier<double, float>(P, k < n_pt, dhat, kappa, form, e, g, u);
   } else {
-    pair_barrier<double>(P, k < n_pt, dhat, kappa, e, g, u);
+    pair_barrier<double>(P, k < n_pt, dhat, kappa, form, e, g, u);
   }
   energy[k] = e;
 #pragma unroll
@@ -266,9 +258,9 @@ __global__ void __launch_bounds__(BT) barrier_kernel(const int32_t* __restrict__
 }
 
 void launch_barrier(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double dhat, double kappa,
-                    bool fp32, BarrierOut& bo, hipStream_t st) {
+                    int form, bool fp32, BarrierOut& bo, hipStream_t st) {
   if (npairs <= 0) return;
-  barrier_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dhat, kappa, fp32, bo.energy,
+  barrier_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dhat, kappa, form, fp32, bo.energy,
                                                        bo.grad, bo.U);
 }
 

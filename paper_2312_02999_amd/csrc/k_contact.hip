@@ -520,7 +520,7 @@ __device__ __forceinline__ double ccd_pair(const int32_t* __restrict__ v4all, in
 // (the step bound alpha_m is the minimum over the blocks).
 __device__ __forceinline__ double pair_energy_at(const int32_t* __restrict__ v4all, int32_t k, int32_t n_pt,
                                                   const double* __restrict__ x, const double* __restrict__ dx,
-                                                  double alpha, double dhat, double kappa);
+                                                  double alpha, double dhat, double kappa, int form);
 
 // With e0 (optional), each candidate's barrier energy at x as well (the line
 // search's reference values).
@@ -528,23 +528,24 @@ __global__ void __launch_bounds__(BT) ccd_kernel(const int32_t* __restrict__ v4a
                                                  const double* __restrict__ x, const double* __restrict__ dx,
                                                  double eta, int32_t steps, double* __restrict__ tout,
                                                  double* __restrict__ part, double dhat, double kappa,
-                                                 double* __restrict__ e0) {
+                                                 int form, double* __restrict__ e0) {
   __shared__ double sh4[4];
   const int32_t k = blockIdx.x * BT + threadIdx.x;
   const double t = k < npairs ? ccd_pair(v4all, k, n_pt, x, dx, eta, steps) : 1.0;
   if (k < npairs) {
     tout[k] = t;
-    if (e0) e0[k] = pair_energy_at(v4all, k, n_pt, x, nullptr, 0.0, dhat, kappa);
+    if (e0) e0[k] = pair_energy_at(v4all, k, n_pt, x, nullptr, 0.0, dhat, kappa, form);
   }
   const double mn = block256_min(t, sh4);
   if (threadIdx.x == 0) part[blockIdx.x] = mn;
 }
 
 int launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
-               int32_t steps, double* t_out, double* part, hipStream_t st, double dhat, double kappa, double* e0) {
+               int32_t steps, double* t_out, double* part, hipStream_t st, double dhat, double kappa, int form,
+               double* e0) {
   if (npairs <= 0) return 0;
   const unsigned g = grid_for(npairs, BT);
-  ccd_kernel<<<g, BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, eta, steps, t_out, part, dhat, kappa, e0);
+  ccd_kernel<<<g, BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, eta, steps, t_out, part, dhat, kappa, form, e0);
   return static_cast<int>(g);
 }
 
@@ -556,7 +557,8 @@ __global__ void __launch_bounds__(BT) pair_energy_kernel(const int32_t* __restri
                                                          int32_t n_pt, const double* __restrict__ x,
                                                          const double* __restrict__ dx,
                                                          const double* __restrict__ ls, double dhat, double kappa,
-                                                         const double* __restrict__ E0, double* __restrict__ out) {
+                                                         int form, const double* __restrict__ E0,
+                                                         double* __restrict__ out) {
   double alpha = 0.0;
   if (ls) {
     if (ls[LS_STATE] != 0.0) return;
@@ -564,27 +566,28 @@ __global__ void __launch_bounds__(BT) pair_energy_kernel(const int32_t* __restri
   }
   int32_t k = blockIdx.x * BT + threadIdx.x;
   if (k >= npairs) return;
-  const double e = pair_energy_at(v4all, k, n_pt, x, dx, alpha, dhat, kappa);
+  const double e = pair_energy_at(v4all, k, n_pt, x, dx, alpha, dhat, kappa, form);
   out[k] = E0 ? e - E0[k] : e;
 }
 
 __device__ __forceinline__ double pair_energy_at(const int32_t* __restrict__ v4all, int32_t k, int32_t n_pt,
                                                   const double* __restrict__ x, const double* __restrict__ dx,
-                                                  double alpha, double dhat, double kappa) {
+                                                  double alpha, double dhat, double kappa, int form) {
   int32_t v4[4] = {v4all[4 * k], v4all[4 * k + 1], v4all[4 * k + 2], v4all[4 * k + 3]};
   double P[4][3];
   if (dx) load_pair_rel_step(v4, x, dx, alpha, P);
   else load_pair_rel(v4, x, P);
   double d2 = pair_dist2<double>(k < n_pt, P);
   if (!(d2 > 0.0)) return INFINITY;
-  return d2 < dhat * dhat ? kappa * barrier_b(sqrt(d2), dhat) : 0.0;
+  return kappa * barrier_b_of_D(d2, dhat, form);
 }
 
 void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
-                                const double* ls, double dhat, double kappa, const double* E0, double* out,
+                                const double* ls, double dhat, double kappa, int form, const double* E0, double* out,
                                 hipStream_t st) {
   if (npairs <= 0) return;
-  pair_energy_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, ls, dhat, kappa, E0, out);
+  pair_energy_kernel<<<grid_for(npairs, BT), BT, 0, st>>>(pl.v4, npairs, n_pt, x, dx, ls, dhat, kappa, form, E0,
+                                                          out);
 }
 
 __global__ void __launch_bounds__(BT) pair_d2_kernel(const int32_t* __restrict__ v4all, int32_t npairs, int32_t n_pt,

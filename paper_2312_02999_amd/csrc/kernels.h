@@ -133,14 +133,15 @@ int filter_active(const PairList& cand, int32_t ncand, int32_t cand_pt, const do
 
 // CCD: t_k per candidate pair (conservative advancement), then alpha_m.
 // per-candidate bounds t_out and per-block minima part; returns the blocks.
-// With e0, also each candidate's barrier energy at x (kappa b(d), 0 beyond dhat).
+// With e0, also each candidate's barrier energy at x (kappa b, 0 beyond dhat;
+// barrier form as barrier_of_D).
 int launch_ccd(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx, double eta,
                int32_t steps, double* t_out, double* part, hipStream_t st, double dhat = 0.0, double kappa = 0.0,
-               double* e0 = nullptr);
-// kappa * b(d) per candidate at x + alpha dx (alpha = 0 allowed); pairs at
+               int form = 0, double* e0 = nullptr);
+// kappa * b per candidate at x + alpha dx (alpha = 0 allowed); pairs at
 // d >= dhat give 0.
 void launch_pair_barrier_energy(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, const double* dx,
-                                const double* ls, double dhat, double kappa, const double* E0, double* out,
+                                const double* ls, double dhat, double kappa, int form, const double* E0, double* out,
                                 hipStream_t st);
 // smallest pair distance (for the intersection check); -> d_out
 void launch_pair_min_dist2(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double* d2_out,
@@ -155,7 +156,7 @@ struct BarrierOut {
   double* U;            // 60 x npairs (SoA, entry 5 r + k)
 };
 void launch_barrier(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double dhat, double kappa,
-                    bool fp32, BarrierOut& bo, hipStream_t st);
+                    int form, bool fp32, BarrierOut& bo, hipStream_t st);
 
 // vertex -> (pair, local) incidence (sorted), per-vertex gradient add,
 // affected-set map.  inc_ptr: n + 1, inc_ent: 4 * npairs.
@@ -357,7 +358,7 @@ void launch_dense_residual(const double* M, int64_t n, const double* b, const do
 void launch_hessvec(const LocalArgs& la, int32_t n, const int32_t* vt_ptr, const int32_t* vt_ent,
                     const uint8_t* fixed, const double* x, const double* Rrot, const double* v, double* tetg,
                     const PairList& pl, int32_t npairs, int32_t n_pt, const Incidence& inc, const ProxyDev& px,
-                    double dhat, double kappa, double* pairbuf, double* out, hipStream_t st);
+                    double dhat, double kappa, int form, double* pairbuf, double* out, hipStream_t st);
 // dL/da per tet from the adjoint state lambda (n x 3)
 void launch_actuation_grad(const LocalArgs& la, const double* x, const double* Rrot, const double* R0,
                            const double* lam, double* out, hipStream_t st);

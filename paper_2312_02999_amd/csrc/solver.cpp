@@ -161,6 +161,12 @@ struct Solver {
   // Sigma-hat, its factor and Sigma_s (kept only for the Schur-only step)
   DBuf<double> cg_r, cg_z, cg_p, cg_q, cg_t, cg_sc, cg_pc, cg_vc;
   DBuf<double> shat, shat_L, shat_aux, sigma_s;
+  // barrier stiffness of the current iteration (kappa_0, or the adaptive
+  // value); smallest squared pair distance of the previous iteration and the
+  // threshold 1e-9 l^2 (l: rest bounding-box diagonal) of the adaptive rule;
+  // work arrays of the balancing gradients
+  double kappa = 0.0, d2min_prev = 0.0, eps_d2 = 0.0;
+  DBuf<double> ka_gE, ka_gb, ka_R;
   int32_t adjoint_iters = 0;
 
   // host helpers
@@ -276,12 +282,27 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
     fail(PDIPC_E_INVALID, "the comparison global steps run in FP64 only");
   if (op->global_method == PDIPC_GSTEP_PCG && (!(op->cg_tol > 0) || op->cg_max_iters <= 0))
     fail(PDIPC_E_INVALID, "bad CG options");
+  if (op->barrier_form != 0 && op->barrier_form != 1) fail(PDIPC_E_INVALID, "bad barrier_form");
+  if (op->kappa_adapt != 0 && op->kappa_adapt != 1) fail(PDIPC_E_INVALID, "bad kappa_adapt");
+  S->kappa = op->kappa;
   if (!(md->youngs > 0) || !(md->poisson > -1 && md->poisson < 0.5)) fail(PDIPC_E_INVALID, "bad material");
   S->n = n;
   S->m = m;
   const double* X = md->rest_pos;
   for (int64_t i = 0; i < 3LL * n; ++i)
     if (!std::isfinite(X[i])) fail(PDIPC_E_INVALID, "non-finite rest position");
+  {
+    // squared rest bounding-box diagonal, for the adaptive-stiffness threshold
+    double lo[3] = {X[0], X[1], X[2]}, hi[3] = {X[0], X[1], X[2]};
+    for (int32_t v = 0; v < n; ++v)
+      for (int r = 0; r < 3; ++r) {
+        lo[r] = std::min(lo[r], X[3 * v + r]);
+        hi[r] = std::max(hi[r], X[3 * v + r]);
+      }
+    double l2 = 0.0;
+    for (int r = 0; r < 3; ++r) l2 += (hi[r] - lo[r]) * (hi[r] - lo[r]);
+    S->eps_d2 = 1e-9 * l2;
+  }
   for (int64_t i = 0; i < 4LL * m; ++i)
     if (md->tets[i] < 0 || md->tets[i] >= n) fail(PDIPC_E_INVALID, "tet index out of range");
   int nfixed = 0;
@@ -783,6 +804,7 @@ struct IterOut {
   int32_t c_removed = 0, c_added = 0;   // vertices that left / entered c
   int32_t cg_iters = 0;                 // products of the CG baseline's step
   double alpha_m = 1.0, alpha = 0.0;
+  double kappa = 0.0;                   // barrier stiffness of the iteration
 };
 
 static void finish_readback(Solver* S, IterOut& io) {
@@ -822,6 +844,51 @@ static void cinv_begin_pass(Solver* S) {
   S->cinv_incr_ok = false;
 }
 
+// Adaptive barrier stiffness (IPC's scheme as read here).  At the start of a
+// frame with active pairs, kappa = argmin_k |g_E + k g_b|^2 = -(g_E . g_b) /
+// (g_b . g_b) over the free DOFs (g_E: PD gradient, g_b: gradient of the
+// unit-stiffness barrier), clamped to [kappa_0, 100 kappa_0]; kappa_0
+// without pairs.  At later iterations kappa doubles (up to 100 kappa_0) when
+// the smallest squared pair distance is below 1e-9 l^2 and below its value
+// at the previous iteration.
+static double balanced_kappa(Solver* S, int32_t npt, int32_t np) {
+  hipStream_t st = S->st;
+  const int64_t n3 = 3LL * S->n;
+  S->ka_gE.ensure(n3);
+  S->ka_gb.ensure(n3);
+  S->ka_R.ensure(9LL * S->m);
+  S->prod.ensure(n3);
+  launch_barrier(S->act, np, npt, S->x.p, S->opt.dhat, 1.0, S->opt.barrier_form, false, S->bo, st);
+  build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
+  launch_fill_f64(S->ka_gb.p, n3, 0.0, st);
+  launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->ka_gb.p, st);
+  // PD gradient at x from the frame's starting rotations (kept unchanged)
+  launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->ka_R.p, S->E0.p, S->tetg.p, false, st);
+  launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->ka_gE.p, st);
+  launch_masked_mul(S->n, S->ka_gE.p, S->ka_gb.p, S->fixed.p, S->prod.p, st);
+  launch_sum(S->prod.p, n3, S->scal.p + 5, S->red_tmp.p, st);
+  launch_masked_mul(S->n, S->ka_gb.p, S->ka_gb.p, S->fixed.p, S->prod.p, st);
+  launch_sum(S->prod.p, n3, S->scal.p + 6, S->red_tmp.p, st);
+  HIPCHK(hipMemcpyAsync(S->h_scal, S->scal.p + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double eb = S->h_scal[0], bb = S->h_scal[1];
+  const double k = bb > 0.0 ? -eb / bb : S->opt.kappa;
+  return std::min(std::max(k, S->opt.kappa), 100.0 * S->opt.kappa);
+}
+
+static void adapt_kappa(Solver* S, bool frame_start, int32_t npt, int32_t np) {
+  double d2min = INFINITY;
+  if (np > 0) {
+    S->tpair.ensure(np);
+    launch_pair_min_dist2(S->act, np, npt, S->x.p, S->tpair.p, S->st);
+    launch_min_clamp1(S->tpair.p, np, S->scal.p, S->red_tmp.p, S->st);
+    d2min = read_scalar_d(S, S->scal.p);
+  }
+  if (frame_start) S->kappa = np > 0 ? balanced_kappa(S, npt, np) : S->opt.kappa;
+  else if (d2min < S->eps_d2 && d2min < S->d2min_prev) S->kappa = std::min(2.0 * S->kappa, 100.0 * S->opt.kappa);
+  S->d2min_prev = d2min;
+}
+
 // Constraint set + barrier + local step + gradient; returns pair counts, n_c.
 // The contact terms go first: the fork event follows them, so the reduced
 // system (second stream) builds while the local step runs.  With defer, n_c
@@ -841,9 +908,11 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
     double dmin2 = read_scalar_d(S, S->scal.p);
     if (!(dmin2 > 0.0)) fail(PDIPC_E_INTERSECTING, "input state has a contact pair at distance 0");
   }
+  if (S->opt.kappa_adapt) adapt_kappa(S, first_check, io.npt, np);
+  io.kappa = S->kappa;
   {
     ScopedTimer tm(S, TK_BARRIER);
-    launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->opt.kappa, fp32, S->bo, st);
+    launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->kappa, S->opt.barrier_form, fp32, S->bo, st);
   }
   {
     // against the c of the current C^-1: the change of c, and the vertices
@@ -1279,7 +1348,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
     ScopedTimer tm(S, TK_CCD);
     // with the candidates' barrier energies at x, the line search's reference
     nccd = launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p,
-                      S->ccd_part.p, st, S->opt.dhat, S->opt.kappa, S->bE0.p);
+                      S->ccd_part.p, st, S->opt.dhat, S->kappa, S->opt.barrier_form, S->bE0.p);
   }
   // back-tracking line search on the device: trials read alpha from the state
   // and become no-ops once it is decided; one is queued, then one readback
@@ -1293,8 +1362,8 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
       ScopedTimer tm(S, TK_TRIAL);
       launch_trial_energy(local_args(S), S->x.p, S->dx.p, ls, S->Rtet.p, S->E0.p, S->dE.p, fp32, st);
     }
-    launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, ls, S->opt.dhat, S->opt.kappa, S->bE0.p,
-                               S->bdE.p, st);
+    launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, ls, S->opt.dhat, S->kappa, S->opt.barrier_form,
+                               S->bE0.p, S->bdE.p, st);
     launch_sum2_decide(S->dE.p, S->m, S->bdE.p, ncand, ls, S->red_tmp.p, S->opt.ls_max_halvings, st);
   };
   const int queued = 1;
@@ -1382,7 +1451,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
       tr.ls_halvings = io.halvings; tr.ls_ok = io.ls_ok ? 1 : 0; tr.near_ties = io.near_ties;
       tr.refine_steps = S->refine_steps - refine_before;
       tr.cg_iters = io.cg_iters;
-      tr.alpha_m = io.alpha_m; tr.alpha = io.alpha;
+      tr.alpha_m = io.alpha_m; tr.alpha = io.alpha; tr.kappa = io.kappa;
       S->trace.push_back(tr);
     }
     fs.near_ties += io.near_ties;
@@ -1445,7 +1514,11 @@ static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
   S->cand_valid = false;
   launch_identity_rotations(S->m, S->Rtet.p, st);   // same rotations whatever ran before
   cinv_begin_pass(S);
+  // the energy of the last frame: its final barrier stiffness, not a new balance
+  const int32_t adapt = S->opt.kappa_adapt;
+  S->opt.kappa_adapt = 0;
   assemble_gradient(S, true, io);                   // rotations, pairs, barrier factors at x*
+  S->opt.kappa_adapt = adapt;
   const int32_t np = io.npt + io.nee;
   S->lam.ensure(n3); S->res.ensure(n3); S->zvec.ensure(n3); S->pvec.ensure(n3); S->kp.ensure(n3);
   S->prod.ensure(n3);
@@ -1474,7 +1547,8 @@ static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
   };
   auto kvec = [&](const double* v, double* out) {
     launch_hessvec(local_args(S), S->n, S->vt_ptr.p, S->vt_ent.p, S->fixed.p, S->x.p, S->Rtet.p, v, S->tetg.p,
-                   S->act, np, io.npt, S->inc, S->px, S->opt.dhat, S->opt.kappa, S->pairbuf.p, out, st);
+                   S->act, np, io.npt, S->inc, S->px, S->opt.dhat, S->kappa, S->opt.barrier_form, S->pairbuf.p,
+                   out, st);
   };
   precond(S->res.p, S->zvec.p);
   HIPCHK(hipMemcpyAsync(S->pvec.p, S->zvec.p, sizeof(double) * n3, hipMemcpyDeviceToDevice, st));
@@ -1541,12 +1615,14 @@ void pdipc_default_options(pdipc_options* o) {
   o->ccd_steps = 16;
   o->ls_max_halvings = 20;
   o->cinv_updates_max = 16;
-  o->fp32_reduced_min = 2049;
+  o->fp32_reduced_min = 8192;
   o->hinv_rows_mb = 4096;
   o->stream = nullptr;
   o->global_method = PDIPC_GSTEP_SCHUR_WOODBURY;
   o->cg_tol = 1e-12;
   o->cg_max_iters = 2000;
+  o->barrier_form = 0;
+  o->kappa_adapt = 0;
 }
 
 int32_t pdipc_init_mesh(const pdipc_mesh_desc* mesh, const pdipc_options* opt, void** out) {

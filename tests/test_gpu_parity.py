@@ -592,3 +592,66 @@ def test_comparison_global_steps_face5k_closed_slit():
         S.close()
         assert err < 1e-9, (gm, err)
         assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
+
+
+# --------------------------------------------------------------------------
+# IPC refinements: the squared-distance barrier and the adaptive stiffness,
+# each against the oracle run with the same option
+# --------------------------------------------------------------------------
+def test_squared_barrier_single_iteration_and_frames():
+    """Barrier form 1 (b of the squared distance): one iteration from a
+    pressed C1 state (dx, alpha_m, alpha within 1e-9) and the tiny scene's
+    frames (positions within 1e-9 of the bounding-box diagonal)."""
+    sc = mg.slabs(0)
+    S = _solver(sc, barrier_form=1)
+    A = _set_act(S, sc, 0.4)
+    x = _pressed(sc, 8e-4, seed=1)
+    dx, am, al = S.debug_step(_t(x))
+    prob = osolver.setup_scene(sc, barrier_form=1)
+    _, rec, _ = osolver.iteration(prob, x, A)
+    err = np.abs(dx.cpu().numpy() - rec.dx).max() / np.abs(rec.dx).max()
+    print(f"squared barrier, C1 iteration: dx err {err:.3e} alpha_m {am} / {rec.alpha_m}")
+    assert err < 1e-9, err
+    assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
+    assert abs(al - rec.alpha) <= 1e-9 * max(1.0, rec.alpha)
+    S.close()
+    sc = mg.scene_by_name("tiny")
+    S = _solver(sc, iters=sc.iters, barrier_form=1)
+    prob = osolver.setup_scene(sc, barrier_form=1)
+    x = sc.X.copy()
+    xg = _t(x)
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    for t in range(sc.frames):
+        A = _set_act(S, sc, (t + 1) / sc.frames)
+        xg, st = S.solve_frame(xg, stats=True)
+        x = osolver.frame(prob, x, A, iters=sc.iters).x
+        err = np.abs(xg.cpu().numpy() - x).max() / diag
+        print(f"squared barrier, tiny frame {t}: err {err:.3e} n_c {st['n_c']}")
+        assert err < 1e-9, (t, err)
+
+
+def test_adaptive_kappa_matches_oracle():
+    """Adaptive stiffness from a pressed slab state with a soft kappa_0: the
+    per-iteration kappa (balanced at the start, doubled when the smallest
+    squared distance shrinks below 1e-9 l^2) equals the oracle's, and the
+    positions after the frame are within 1e-9 of the bounding-box diagonal."""
+    sc = mg.slabs(0, nx=4, ny=4, nz=2, gap=1e-3)
+    sc.kappa = 0.01
+    x = sc.X.copy()
+    top = sc.X[:, 2].max()
+    x[sc.X[:, 2] > 0.5 * top, 2] -= 9.5e-4
+    rng = np.random.default_rng(3)
+    x += rng.uniform(-5e-5, 5e-5, x.shape) * (sc.dirichlet[:, None] == 0)
+    prob = osolver.setup_scene(sc, kappa_adapt=True)
+    A = ofem.actuation_matrices(sc.act_a, sc.act_R)
+    ref = osolver.frame(prob, x, A, iters=10)
+    S = _solver(sc, iters=10, kappa_adapt=True)
+    S.set_actuation_scalar(_t(sc.act_a), _t(sc.act_R.reshape(-1, 9)))
+    xg = S.solve_frame(_t(x))
+    kg = [tr["kappa"] for tr in S.trace()]
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    err = np.abs(xg.cpu().numpy() - ref.x).max() / diag
+    print(f"adaptive kappa: gpu {kg} oracle {ref.kappa} err {err:.3e}")
+    assert len(set(ref.kappa)) >= 3          # balanced start and at least one doubling
+    assert np.allclose(kg, ref.kappa, rtol=1e-12, atol=0)
+    assert err < 1e-9, err

@@ -661,3 +661,160 @@ def test_line_search_counts_pairs_that_enter_dhat_along_the_step():
     alpha, halvings, ok = solver.line_search(prob, x, dx, A, alpha_m, spt, see)
     assert ok and halvings >= 1 and alpha < alpha_m
     assert _total_energy(prob, x + alpha * dx, A) <= _total_energy(prob, x, A)
+
+
+# --------------------------------------------------------------------------
+# IPC refinements: squared-distance barrier (form 1) and adaptive stiffness
+# --------------------------------------------------------------------------
+def _c0(D):
+    """b(D) = -(D - Dh)^2 ln(D / Dh) and its D-derivatives, written out."""
+    Dh = DHAT * DHAT
+    return -((D - Dh) ** 2) * np.log(D / Dh)
+
+
+def _c1(D):
+    Dh = DHAT * DHAT
+    return -2 * (D - Dh) * np.log(D / Dh) - (D - Dh) ** 2 / D
+
+
+def _c2(D):
+    Dh = DHAT * DHAT
+    return -2 * np.log(D / Dh) - 4 * (D - Dh) / D + (D - Dh) ** 2 / D ** 2
+
+
+def test_squared_barrier_vanishes_smoothly_and_selects_the_same_pairs():
+    Dh = DHAT * DHAT
+    assert barrier.barrier(np.array([DHAT, 2 * DHAT]), DHAT, form=1).max() == 0
+    assert np.isclose(_c1(Dh), 0) and np.isclose(_c2(Dh), 0)
+    d = np.array([1e-6, 1e-4, 4.9e-4])
+    assert np.all(barrier.barrier(d, DHAT, form=1) > 0)
+    assert np.allclose(barrier.barrier(d, DHAT, form=1), _c0(d * d), rtol=1e-13)
+    # the written-out derivatives against central differences of b(D)
+    for D in (1e-9, 1e-8, 1e-7):
+        h = 1e-4 * D
+        assert np.isclose((_c0(D + h) - _c0(D - h)) / (2 * h), _c1(D), rtol=1e-6)
+        assert np.isclose((_c1(D + h) - _c1(D - h)) / (2 * h), _c2(D), rtol=1e-6)
+
+
+def test_squared_barrier_single_point_triangle_closed_form():
+    """Point at height h over a triangle interior, D = h^2: grad_p =
+    kappa b'(D) 2 h n, Hess_pp = kappa (4 h^2 b''(D) + 2 b'(D)) n n^T."""
+    h = 2e-4
+    D = h * h
+    tri = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.0]])
+    X4 = np.concatenate([np.array([[0.002, 0.003, h]]), tri])[None]
+    d2, kind, idx = geo.point_triangle(X4[:, 0], X4[:, 1], X4[:, 2], X4[:, 3])
+    E, G, H = barrier.pair_derivatives(X4, kind, idx, DHAT, KAPPA, form=1)
+    n = np.array([0, 0, 1.0])
+    assert np.isclose(E[0], KAPPA * _c0(D), rtol=1e-12)
+    assert np.allclose(G[0, :3], KAPPA * _c1(D) * 2 * h * n, rtol=1e-10)
+    assert np.allclose(G[0].reshape(4, 3).sum(axis=0), 0, atol=1e-9 * np.abs(G).max())
+    Hnn = KAPPA * (4 * D * _c2(D) + 2 * _c1(D))
+    assert np.allclose(H[0, :3, :3], Hnn * np.outer(n, n), rtol=1e-9, atol=1e-9 * abs(Hnn))
+
+
+@pytest.mark.parametrize("is_pt", [True, False])
+def test_squared_barrier_gradient_against_finite_differences(is_pt):
+    rng = np.random.default_rng(21 if is_pt else 22)
+    checked = 0
+    while checked < 4:
+        base = rng.uniform(-0.005, 0.005, (3, 3))
+        if is_pt:
+            nrm = np.cross(base[1] - base[0], base[2] - base[0])
+            p = base.mean(axis=0) + nrm / np.linalg.norm(nrm) * rng.uniform(1e-4, 4e-4)
+            X4 = np.concatenate([p[None], base])[None]
+            f = geo.point_triangle
+        else:
+            mid = 0.5 * (base[0] + base[1])
+            dirb, off = rng.standard_normal(3), rng.standard_normal(3)
+            dirb /= np.linalg.norm(dirb)
+            off /= np.linalg.norm(off)
+            X4 = np.stack([base[0], base[1], mid + 3e-4 * off - 0.004 * dirb, mid + 3e-4 * off + 0.004 * dirb])[None]
+            f = geo.edge_edge
+        d2, kind, idx = f(X4[:, 0], X4[:, 1], X4[:, 2], X4[:, 3])
+        if not (5e-5 < np.sqrt(d2[0]) < 4.5e-4):
+            continue
+        _, G, _ = barrier.pair_derivatives(X4, kind, idx, DHAT, KAPPA, form=1)
+
+        def energy(y):
+            Y = y.reshape(1, 4, 3)
+            return KAPPA * _c0(f(Y[:, 0], Y[:, 1], Y[:, 2], Y[:, 3])[0][0])
+        x = X4.reshape(-1)
+        eps = 1e-9
+        g_fd = np.array([(energy(x + eps * e) - energy(x - eps * e)) / (2 * eps) for e in np.eye(12)])
+        assert np.allclose(G[0], g_fd, rtol=2e-4, atol=2e-4 * np.abs(G[0]).max())
+        checked += 1
+
+
+def _pressed_slabs(depth, seed=0, amp=5e-5, kappa=None):
+    sc = mg.slabs(0, nx=4, ny=4, nz=2, gap=1e-3)
+    if kappa is not None:
+        sc.kappa = kappa
+    x = sc.X.copy()
+    top = sc.X[:, 2].max()
+    x[sc.X[:, 2] > 0.5 * top, 2] -= depth
+    rng = np.random.default_rng(seed)
+    x += rng.uniform(-amp, amp, x.shape) * (sc.dirichlet[:, None] == 0)
+    return sc, x
+
+
+def test_balanced_kappa_minimises_the_gradient_residual():
+    """The frame-start stiffness is the minimiser of |g_E + k g_b| over k in
+    [kappa_0, 100 kappa_0]: checked against a dense scan of k (a soft kappa_0
+    so that the minimiser lies inside the interval)."""
+    sc, x = _pressed_slabs(9.5e-4, seed=3, kappa=0.01)
+    prob = solver.setup_scene(sc, kappa_adapt=True)
+    A = fem.actuation_matrices(sc.act_a, sc.act_R)
+    cs = contact.constraint_set(x, prob.prox, prob.dhat)
+    assert cs.size > 0
+    k_star = solver.balanced_kappa(prob, x, A, cs)
+    F = local.deformation_gradients(x, prob.tets, prob.B)
+    _, P = local.projections(F, A)
+    gE = solver.pd_gradient(prob, F, P)[prob.free]
+    gb = solver.barrier_terms(prob, x, cs, kappa=1.0)[1][prob.free]
+    ks = np.linspace(prob.kappa, 100 * prob.kappa, 100001)
+    k_scan = ks[int(np.argmin([np.linalg.norm(gE + k * gb) for k in ks]))]
+    assert prob.kappa < k_star < 100 * prob.kappa
+    assert abs(k_star - k_scan) <= ks[1] - ks[0]
+
+
+def test_adaptive_kappa_follows_its_rule_and_stays_fixed_without_contact():
+    """Without pairs the stiffness stays kappa_0; from a pressed state with a
+    soft kappa_0 it starts at the balanced value and doubles exactly at the
+    iterations whose smallest squared distance falls below 1e-9 l^2 and
+    below the previous one (at least once here)."""
+    sc = mg.slabs(0, nx=4, ny=4, nz=2, gap=0.02)
+    prob = solver.setup_scene(sc, kappa_adapt=True)
+    A = fem.actuation_matrices(0.3 * sc.act_a, sc.act_R)
+    r = solver.frame(prob, sc.X, A, iters=5)
+    assert r.kappa == [prob.kappa] * 5
+    sc, x = _pressed_slabs(9.5e-4, seed=3, kappa=0.01)
+    prob = solver.setup_scene(sc, kappa_adapt=True)
+    A = fem.actuation_matrices(sc.act_a, sc.act_R)
+    r = solver.frame(prob, x, A, iters=10, trace=True)
+    eps = 1e-9 * float(np.sum((prob.X.max(0) - prob.X.min(0)) ** 2))
+    k0 = solver.balanced_kappa(prob, x, A, contact.constraint_set(x, prob.prox, prob.dhat))
+    assert r.kappa[0] == k0 and k0 > prob.kappa
+    d2 = [float(rec.cs.d2.min()) if rec.cs.size else np.inf for rec in r.trace]
+    doublings = 0
+    for k in range(1, len(r.kappa)):
+        doubled = d2[k] < eps and d2[k] < d2[k - 1]
+        expect = min(2 * r.kappa[k - 1], 100 * prob.kappa) if doubled else r.kappa[k - 1]
+        assert r.kappa[k] == expect, (k, d2[k], r.kappa)
+        assert r.trace[k].kappa == r.kappa[k]
+        doublings += doubled
+    assert doublings >= 1
+    # with the stiffness fixed between doublings the total energy still
+    # decreases at every accepted step
+    for k in range(len(r.trace) - 1):
+        if r.kappa[k + 1] == r.kappa[k]:
+            e0 = _energy_at_kappa(prob, r.trace[k].x, A, r.kappa[k])
+            e1 = _energy_at_kappa(prob, r.trace[k + 1].x, A, r.kappa[k])
+            assert e1 <= e0 + 1e-12 * abs(e0)
+
+
+def _energy_at_kappa(prob, x, A, kappa):
+    F = local.deformation_gradients(x, prob.tets, prob.B)
+    Ee = local.element_energies(F, A, prob.w)
+    cs = contact.constraint_set(x, prob.prox, prob.dhat)
+    return float(Ee.sum()) + kappa * float(barrier.barrier(np.sqrt(cs.d2), prob.dhat, prob.barrier_form).sum())
