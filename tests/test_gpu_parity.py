@@ -653,5 +653,11 @@ def test_adaptive_kappa_matches_oracle():
     err = np.abs(xg.cpu().numpy() - ref.x).max() / diag
     print(f"adaptive kappa: gpu {kg} oracle {ref.kappa} err {err:.3e}")
     assert len(set(ref.kappa)) >= 3          # balanced start and at least one doubling
-    assert np.allclose(kg, ref.kappa, rtol=1e-12, atol=0)
+    # the same doublings at the same iterations (exact ratios), and the
+    # balanced start within the FP64 bar: it is a ratio of dot products of the
+    # elastic gradient, whose rounding is amplified by cancellation near
+    # equilibrium (GPU and oracle sum in different orders)
+    assert [kg[k + 1] / kg[k] for k in range(len(kg) - 1)] == \
+        [ref.kappa[k + 1] / ref.kappa[k] for k in range(len(kg) - 1)]
+    assert np.allclose(kg, ref.kappa, rtol=1e-9, atol=0)
     assert err < 1e-9, err
