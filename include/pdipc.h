@@ -75,21 +75,23 @@ enum { PDIPC_GSTEP_SCHUR_WOODBURY = 0, PDIPC_GSTEP_PCG = 1, PDIPC_GSTEP_SCHUR = 
  *                            vertices (W_rowptr: n_surf_verts + 1 entries,
  *                            W_col: column ids, W_val: weights, NULL = every
  *                            row has one entry of weight 1).  Rows must have
- *                            non-negative weights that sum to 1 within 1e-12
- *                            and distinct columns (else PDIPC_E_INVALID).
- *                            This build embeds the proxy by selection: every
- *                            row must pick one vertex with weight 1; a row
- *                            that interpolates several vertices is rejected
- *                            with PDIPC_E_INVALID.
- *                            W_rowptr = NULL: no W; surf_tris then holds
- *                            simulation vertex ids directly.
+ *                            non-negative weights that sum to 1 within 1e-12,
+ *                            distinct columns and at most 4 entries (else
+ *                            PDIPC_E_INVALID).  Rows may interpolate (a proxy
+ *                            finer than the simulation surface): the contact
+ *                            terms then live on s = W x, and the barrier
+ *                            gradient and Hessian reach x as W^T grad and
+ *                            W^T H W.  The adjoint (pdipc_solve_frame_backward)
+ *                            supports a selection only (every row one weight
+ *                            of 1).  W_rowptr = NULL: no W; surf_tris then
+ *                            holds simulation vertex ids directly.
  *  n_surf_tris, surf_tris    proxy triangles, n_surf_tris x 3 ids of proxy
  *                            vertices (rows of W), or of simulation vertices
  *                            when W_rowptr is NULL
  *  region      n_verts or NULL  1 = collision-aware vertex (block x2 of Eq. 6);
- *                            NULL = the free vertices the proxy uses.  Every
- *                            free proxy vertex must be marked (else
- *                            PDIPC_E_INVALID).
+ *                            NULL = the free simulation vertices the proxy
+ *                            moves with (the columns W uses).  Every such
+ *                            vertex must be marked (else PDIPC_E_INVALID).
  *  youngs, poisson           element weight w_i = 2 mu V_i, mu = E/(2(1+nu))
  */
 typedef struct {

@@ -48,8 +48,10 @@ int32_t pdipc_kernel_timer(void* solver, int32_t which, double* total_ms, int64_
  *   gradient sum_i w_i G_i^T (G_i x - p_i) (device n x 3, zero at fixed).
  * pdipc_debug_contacts: constraint set at x: writes up to cap pairs as
  *   (type, i, j) int32 triples into pairs (device), returns the count in
- *   *count (host).  type 0 = point-triangle (sim vertex, proxy triangle),
- *   type 1 = edge-edge (edge, edge) with edges sorted (lo, hi).
+ *   *count (host).  type 0 = point-triangle (proxy vertex, proxy triangle),
+ *   type 1 = edge-edge (edge, edge) with edges sorted (lo, hi).  Proxy
+ *   vertices are simulation vertex ids for a proxy embedded by selection,
+ *   else rows of W.
  * pdipc_debug_step: one full iteration from x; writes dx (device n x 3) and
  *   the host scalars alpha_m, alpha. */
 int32_t pdipc_debug_local(void* solver, const double* x, double* R, double* energies, double* grad);

@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "Scene", "hex_grid_tets", "boundary_faces", "unique_edges",
-    "random_rotations", "slabs", "face_like", "ramp", "keyframe_sequence",
+    "random_rotations", "slabs", "face_like", "ramp", "keyframe_sequence", "refine_proxy",
     "scene_by_name", "closed_slit_state",
 ]
 
@@ -37,7 +37,8 @@ class Scene:
       tets      (m,4) i32  positively oriented tetrahedra
       dirichlet (n,)  u8   1 = fixed at its rest position
       region    (n,)  u8   1 = collision-aware vertex (the x2 block)
-      surf_tris (F,3) i32  proxy triangles, as simulation vertex ids
+      surf_tris (F,3) i32  proxy triangles, as simulation vertex ids (or, with
+                           W, as proxy vertex ids: rows of W)
       act_a     (m,)  f64  actuation strength at full ramp
       act_R     (m,3,3) f64 actuation frame per tet (det +1)
     """
@@ -56,6 +57,7 @@ class Scene:
     iters: int = 30
     frames: int = 5
     meta: dict = field(default_factory=dict)
+    W: tuple | None = None      # proxy embedding s = W x as CSR (rowptr, col, val); None: selection
 
     @property
     def n(self) -> int:
@@ -445,6 +447,49 @@ def closed_slit_state(scene: Scene, gap: float, seed: int = 0, jitter: float = 0
         moved = np.any(x != scene.X, axis=1)
         x[moved] += rng.uniform(-jitter, jitter, (int(moved.sum()), 3))
     return x
+
+
+# --------------------------------------------------------------------------
+# embedded collision proxy (Section 3.1: s = W x)
+# --------------------------------------------------------------------------
+def refine_proxy(scene: Scene) -> Scene:
+    """The scene with a finer collision proxy embedded in its simulation
+    surface: every proxy triangle is split into four at its edge midpoints.
+    Proxy vertices are the original surface vertices (one weight of 1) and
+    the edge midpoints (weights 1/2, 1/2), so each row of W interpolates the
+    simulation vertices of one surface edge or vertex and sums to 1.
+    ``W`` = (rowptr, col, val) is the n_s x n CSR of s = W x; the proxy
+    triangles index proxy vertices (rows of W).  The collision-aware block
+    is unchanged: the free simulation vertices that W touches."""
+    tris = np.asarray(scene.surf_tris, dtype=np.int64)
+    verts = np.unique(tris.reshape(-1))
+    vmap = np.full(scene.n, -1, dtype=np.int64)
+    vmap[verts] = np.arange(verts.size)
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]], axis=0)
+    edges = np.unique(np.sort(e, axis=1), axis=0)
+    eid = {(int(a), int(b)): verts.size + i for i, (a, b) in enumerate(edges)}
+
+    def mid(a, b):
+        return eid[(min(int(a), int(b)), max(int(a), int(b)))]
+
+    new_tris = []
+    for a, b, c in tris:
+        A, B, Cc = vmap[a], vmap[b], vmap[c]
+        ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+        new_tris += [(A, ab, ca), (ab, B, bc), (ca, bc, Cc), (ab, bc, ca)]
+    ns = verts.size + edges.shape[0]
+    rowptr = np.zeros(ns + 1, dtype=np.int32)
+    rowptr[1:verts.size + 1] = 1
+    rowptr[verts.size + 1:] = 2
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    col = np.concatenate([verts, edges.reshape(-1)]).astype(np.int32)
+    val = np.concatenate([np.ones(verts.size), np.full(2 * edges.shape[0], 0.5)])
+    out = Scene(name=scene.name + "_refined", X=scene.X, tets=scene.tets, dirichlet=scene.dirichlet,
+                region=scene.region, surf_tris=np.asarray(new_tris, dtype=np.int32), act_a=scene.act_a,
+                act_R=scene.act_R, frames=scene.frames, iters=scene.iters, youngs=scene.youngs,
+                poisson=scene.poisson, dhat=scene.dhat, kappa=scene.kappa, meta=dict(scene.meta),
+                W=(rowptr, col, val))
+    return out
 
 
 # --------------------------------------------------------------------------

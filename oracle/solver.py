@@ -19,6 +19,11 @@ Readings:
 * "while not converged" = a fixed number of iterations, or, in tolerance
   mode, until max |alpha dx| <= tol;
 * fixed (Dirichlet) vertices stay at their rest positions and carry no DOFs;
+* an embedded proxy (Section 3.1): with a matrix W (n_s x n, rows summing to
+  1) the collision primitives live on s = W x -- distances, constraint set,
+  candidates, step bound and barrier energies use s, the barrier gradient is
+  W^T grad_s and the projected Hessian W^T H_s W (over 3 DOFs per vertex);
+  without W the proxy is a selection of simulation vertices;
 * adaptive barrier stiffness (optional; the paper says only that IPC
   initialises kappa from the average stiffness and adjusts it adaptively): at
   the start of a frame, if the constraint set at x_t is not empty, kappa is the
@@ -56,6 +61,7 @@ class Problem:
     kappa: float
     barrier_form: int = 0
     kappa_adapt: bool = False
+    W: sp.csr_matrix | None = None     # proxy embedding s = W x (None: selection)
 
     @property
     def n(self):
@@ -63,7 +69,9 @@ class Problem:
 
 
 def setup(X, tets, dirichlet, surf_tris, youngs, poisson, dhat, kappa, barrier_form=0,
-          kappa_adapt=False) -> Problem:
+          kappa_adapt=False, W=None) -> Problem:
+    """W: None (proxy triangles index simulation vertices) or (rowptr, col,
+    val) of s = W x (proxy triangles index rows of W)."""
     X = np.asarray(X, dtype=np.float64)
     tets = np.asarray(tets, dtype=np.int64)
     _, B, V = fem.rest_data(X, tets)
@@ -73,12 +81,34 @@ def setup(X, tets, dirichlet, surf_tris, youngs, poisson, dhat, kappa, barrier_f
     free = fem.free_dofs(dirichlet)
     return Problem(X=X, tets=tets, dirichlet=np.asarray(dirichlet), prox=contact.make_proxy(surf_tris),
                    B=B, V=V, w=w, G=G, H=H, free=free, dhat=float(dhat), kappa=float(kappa),
-                   barrier_form=int(barrier_form), kappa_adapt=bool(kappa_adapt))
+                   barrier_form=int(barrier_form), kappa_adapt=bool(kappa_adapt), W=_embedding(W, X.shape[0]))
+
+
+def _embedding(W, n):
+    if W is None:
+        return None
+    rowptr, col, val = W
+    return sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col), np.asarray(rowptr)),
+                         shape=(len(rowptr) - 1, n))
 
 
 def setup_scene(scene, barrier_form=0, kappa_adapt=False) -> Problem:
     return setup(scene.X, scene.tets, scene.dirichlet, scene.surf_tris, scene.youngs,
-                 scene.poisson, scene.dhat, scene.kappa, barrier_form, kappa_adapt)
+                 scene.poisson, scene.dhat, scene.kappa, barrier_form, kappa_adapt, getattr(scene, "W", None))
+
+
+def proxy_positions(prob: Problem, x: np.ndarray) -> np.ndarray:
+    """Positions of the proxy vertices: s = W x, or x itself for a selection."""
+    return x if prob.W is None else prob.W @ x
+
+
+def _to_sim(prob: Problem, g_s: np.ndarray, B_s: sp.spmatrix):
+    """Gradient and Hessian from proxy DOFs to simulation DOFs: W^T g, W^T B W
+    (with W acting on three coordinates per vertex)."""
+    if prob.W is None:
+        return g_s, B_s
+    W3 = sp.kron(prob.W, sp.identity(3), format="csr")
+    return W3.T @ g_s, (W3.T @ B_s @ W3).tocsc()
 
 
 def pd_gradient(prob: Problem, F: np.ndarray, P: np.ndarray) -> np.ndarray:
@@ -101,15 +131,18 @@ def barrier_terms(prob: Problem, x: np.ndarray, cs: contact.ConstraintSet, kappa
     n3 = 3 * prob.n
     if cs.size == 0:
         return 0.0, np.zeros(n3), sp.csc_matrix((n3, n3)), (np.zeros(0), np.zeros((0, 12)), np.zeros((0, 12, 12)))
-    X4 = contact.pair_points(x, prob.prox, cs.pt, cs.ee)
+    s = proxy_positions(prob, x)
+    X4 = contact.pair_points(s, prob.prox, cs.pt, cs.ee)
     E, Gp, Hp = barrier.pair_derivatives(X4, cs.kind, cs.idx, prob.dhat, kappa, prob.barrier_form)
     Hp = barrier.project_psd(Hp)
     dofs = pair_dofs(prob, cs)
-    g = np.zeros(n3)
+    ns3 = 3 * s.shape[0]
+    g = np.zeros(ns3)
     np.add.at(g, dofs.reshape(-1), Gp.reshape(-1))
     rows = np.repeat(dofs, 12, axis=1).reshape(-1)
     cols = np.tile(dofs, (1, 12)).reshape(-1)
-    Bm = sp.csc_matrix((Hp.reshape(-1), (rows, cols)), shape=(n3, n3))
+    Bm = sp.csc_matrix((Hp.reshape(-1), (rows, cols)), shape=(ns3, ns3))
+    g, Bm = _to_sim(prob, g, Bm)
     return float(E.sum()), g, Bm, (E, Gp, Hp)
 
 
@@ -118,7 +151,7 @@ def total_energy_terms(prob: Problem, x, A, pt, ee, kappa: float | None = None):
     kappa = prob.kappa if kappa is None else kappa
     F = local.deformation_gradients(x, prob.tets, prob.B)
     Ee = local.element_energies(F, A, prob.w)
-    d2, _, _ = contact.pair_distances(x, prob.prox, pt, ee)
+    d2, _, _ = contact.pair_distances(proxy_positions(prob, x), prob.prox, pt, ee)
     Eb = kappa * barrier.barrier(np.sqrt(d2), prob.dhat, prob.barrier_form)
     return Ee, Eb
 
@@ -175,6 +208,8 @@ def affected_vertices(prob: Problem, cs: contact.ConstraintSet) -> np.ndarray:
         return np.zeros(0, np.int64)
     V4 = contact.pair_vertices(prob.prox, cs.pt, cs.ee)
     v = np.unique(V4.reshape(-1))
+    if prob.W is not None:
+        v = np.unique(prob.W[v].indices)
     return v[prob.dirichlet[v] == 0]
 
 
@@ -198,7 +233,7 @@ def iteration(prob: Problem, x: np.ndarray, A: np.ndarray, max_halvings=20, kapp
     kappa = prob.kappa if kappa is None else kappa
     F = local.deformation_gradients(x, prob.tets, prob.B)
     R, P = local.projections(F, A)
-    cs = contact.constraint_set(x, prob.prox, prob.dhat)
+    cs = contact.constraint_set(proxy_positions(prob, x), prob.prox, prob.dhat)
     if cs.size and np.any(cs.d2 <= 0):
         raise ValueError("state is not intersection-free")
     _, gB, Bm, (pE, pg, pH) = barrier_terms(prob, x, cs, kappa)
@@ -209,7 +244,7 @@ def iteration(prob: Problem, x: np.ndarray, A: np.ndarray, max_halvings=20, kapp
     dx = np.zeros(3 * prob.n)
     dx[f] = dxf
     dx = dx.reshape(-1, 3)
-    alpha_m, spt, see = ccd.step_bound(x, dx, prob.prox, prob.dhat)
+    alpha_m, spt, see = ccd.step_bound(proxy_positions(prob, x), proxy_positions(prob, dx), prob.prox, prob.dhat)
     alpha, h, ok = line_search(prob, x, dx, A, alpha_m, spt, see, max_halvings, kappa)
     rec = IterRecord(x=x.copy(), R=R, P=P, cs=cs, pair_E=pE, pair_g=pg, pair_H=pH,
                      g=g, dx=dx, alpha_m=alpha_m, alpha=alpha, halvings=h,
@@ -228,7 +263,7 @@ def frame(prob: Problem, x_t: np.ndarray, A: np.ndarray, iters: int = 30, tol: f
     d2_prev = np.inf
     for k in range(n_it):
         if prob.kappa_adapt:
-            cs = contact.constraint_set(x, prob.prox, prob.dhat)
+            cs = contact.constraint_set(proxy_positions(prob, x), prob.prox, prob.dhat)
             d2_min = float(cs.d2.min()) if cs.size else np.inf
             if k == 0:
                 kappa = balanced_kappa(prob, x, A, cs)

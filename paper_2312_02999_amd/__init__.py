@@ -57,6 +57,8 @@ class Solver:
             X, tets, dirichlet, surf_tris = scene.X, scene.tets, scene.dirichlet, scene.surf_tris
             region = scene.region
             defaults = {k: getattr(scene, k) for k in defaults}
+            if W is None:
+                W = getattr(scene, "W", None)
         youngs, poisson, dhat, kappa = (given[k] if given[k] is not None else defaults[k]
                                         for k in ("youngs", "poisson", "dhat", "kappa"))
         self.device = torch.device(device)

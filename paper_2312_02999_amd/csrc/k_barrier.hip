@@ -264,35 +264,102 @@ void launch_barrier(const PairList& pl, int32_t npairs, int32_t n_pt, const doub
                                                        bo.grad, bo.U);
 }
 
+// ---- embedding s = W x and the pairs' slots over simulation vertices --------------
+__global__ void __launch_bounds__(256) embed_positions_kernel(EmbedDev W, const double* __restrict__ x,
+                                                              double* __restrict__ s) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= 3LL * W.ns) return;
+  const int64_t p = t / 3;
+  const int r = static_cast<int>(t % 3);
+  double acc = 0.0;
+  for (int32_t e = W.ptr[p]; e < W.ptr[p + 1]; ++e) acc += W.val[e] * x[3LL * W.col[e] + r];
+  s[t] = acc;
+}
+
+void launch_embed_positions(const EmbedDev& W, const double* x, double* s, hipStream_t st) {
+  if (W.ns > 0) embed_positions_kernel<<<grid_for(3LL * W.ns, 256), 256, 0, st>>>(W, x, s);
+}
+
+// One thread per pair: the W entries of its four proxy points in order
+// (point, entry); an entry whose simulation vertex already has a slot adds
+// to it, otherwise it opens the next slot.  Slot rows are the weighted sums
+// of the points' gradient and factor rows.
+constexpr int kSlotsW = 16;
+__global__ void __launch_bounds__(128) expand_pairs_kernel(EmbedDev W, const int32_t* __restrict__ v4,
+                                                           int32_t npairs, const double* __restrict__ grad,
+                                                           const double* __restrict__ U, int32_t* __restrict__ sv,
+                                                           double* __restrict__ sg, double* __restrict__ sU) {
+  const int32_t k = blockIdx.x * 128 + threadIdx.x;
+  if (k >= npairs) return;
+  int32_t vert[kSlotsW];
+  int nslot = 0;
+  for (int q = 0; q < kSlotsW; ++q) {
+    vert[q] = -1;
+    for (int r = 0; r < 3; ++r) sg[static_cast<int64_t>(3 * q + r) * npairs + k] = 0.0;
+    for (int e = 0; e < 15; ++e) sU[static_cast<int64_t>(15 * q + e) * npairs + k] = 0.0;
+  }
+  for (int a = 0; a < 4; ++a) {
+    const int32_t p = v4[4 * k + a];
+    for (int32_t e = W.ptr[p]; e < W.ptr[p + 1]; ++e) {
+      const int32_t j = W.col[e];
+      const double w = W.val[e];
+      int q = 0;
+      while (q < nslot && vert[q] != j) ++q;
+      if (q == nslot) vert[nslot++] = j;
+      for (int r = 0; r < 3; ++r) {
+        sg[static_cast<int64_t>(3 * q + r) * npairs + k] += w * grad[static_cast<int64_t>(3 * a + r) * npairs + k];
+        for (int c = 0; c < 5; ++c)
+          sU[static_cast<int64_t>(5 * (3 * q + r) + c) * npairs + k] +=
+              w * U[static_cast<int64_t>(5 * (3 * a + r) + c) * npairs + k];
+      }
+    }
+  }
+  for (int q = 0; q < kSlotsW; ++q) sv[kSlotsW * k + q] = vert[q];
+}
+
+void launch_expand_pairs(const EmbedDev& W, const int32_t* v4, int32_t npairs, const BarrierOut& bo,
+                         int32_t* slot_v, double* slot_grad, double* slot_U, hipStream_t st) {
+  if (npairs > 0)
+    expand_pairs_kernel<<<grid_for(npairs, 128), 128, 0, st>>>(W, v4, npairs, bo.grad, bo.U, slot_v, slot_grad,
+                                                                slot_U);
+}
+
 // ---- vertex incidence ------------------------------------------------------------
-__global__ void inc_count_kernel(const int32_t* __restrict__ v4, int32_t npairs, int32_t* __restrict__ cnt) {
+template <int S>
+__global__ void inc_count_kernel(const int32_t* __restrict__ v, int32_t npairs, int32_t* __restrict__ cnt) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npairs) return;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) atomicAdd(&cnt[v4[4 * k + a]], 1);
+  for (int a = 0; a < S; ++a) {
+    const int32_t j = v[S * k + a];
+    if (j >= 0) atomicAdd(&cnt[j], 1);
+  }
 }
 
-__global__ void inc_fill_kernel(const int32_t* __restrict__ v4, int32_t npairs, int32_t* __restrict__ cursor,
+template <int S>
+__global__ void inc_fill_kernel(const int32_t* __restrict__ v, int32_t npairs, int32_t* __restrict__ cursor,
                                 int32_t* __restrict__ ent) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npairs) return;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int32_t s = atomicAdd(&cursor[v4[4 * k + a]], 1);
-    ent[s] = 4 * k + a;
+  for (int a = 0; a < S; ++a) {
+    const int32_t j = v[S * k + a];
+    if (j < 0) continue;
+    int32_t s = atomicAdd(&cursor[j], 1);
+    ent[s] = S * k + a;
   }
 }
 
-// Sort each proxy vertex's incidence list (keys are unique: 4 * pair + local)
-// into a second array, one wave per vertex: each lane ranks its keys against
-// the whole list (any length), then scatters them to their rank.
-__global__ void __launch_bounds__(256) inc_sort_kernel(int32_t nsv, const int32_t* __restrict__ sv,
+// Sort each vertex's incidence list (keys are unique: S * pair + slot) into
+// a second array, one wave per vertex: each lane ranks its keys against the
+// whole list (any length), then scatters them to their rank.
+__global__ void __launch_bounds__(256) inc_sort_kernel(int32_t nverts, const int32_t* __restrict__ verts,
                                                        const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
                                                        int32_t* __restrict__ out) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
-  if (w >= nsv) return;
-  const int32_t v = sv[w];
+  if (w >= nverts) return;
+  const int32_t v = verts[w];
   const int32_t b = ptr[v], e = ptr[v + 1], cnt = e - b;
   for (int32_t i = lane; i < cnt; i += PDIPC_WAVE) {
     const int32_t key = ent[b + i];
@@ -344,12 +411,15 @@ __global__ void clist_kernel(int32_t n, const int32_t* __restrict__ cflag, const
   if (cflag[v]) clist[cidx[v]] = v;
 }
 
-void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyDev& px, const uint8_t* fixed,
-                     Incidence& inc, void* scan_temp, hipStream_t st, const int32_t* prev_cflag, int32_t* rem_ids,
-                     int32_t* add_ids, int32_t cap) {
+void build_incidence(const PairSlots& ps, int32_t npairs, int32_t n, const uint8_t* fixed, Incidence& inc,
+                     void* scan_temp, hipStream_t st, const int32_t* prev_cflag, int32_t* rem_ids, int32_t* add_ids,
+                     int32_t cap) {
   // counts and (with prev_cflag) the three change counters start at zero
   launch_fill2_i32(inc.cnt, n + 1LL, inc.d_nc + 1, prev_cflag ? 3 : 0, 0, st);
-  if (npairs > 0) inc_count_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cnt);
+  if (npairs > 0) {
+    if (ps.S == 4) inc_count_kernel<4><<<grid_for(npairs, 256), 256, 0, st>>>(ps.v, npairs, inc.cnt);
+    else inc_count_kernel<kSlotsW><<<grid_for(npairs, 256), 256, 0, st>>>(ps.v, npairs, inc.cnt);
+  }
   cflag_kernel<<<grid_for(n + 1LL, 256), 256, 0, st>>>(n, inc.cnt, fixed, inc.cflag, prev_cflag, inc.d_nc + 1,
                                                         rem_ids, add_ids, cap);
   {
@@ -358,16 +428,19 @@ void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyD
                              {inc.cflag, inc.cidx, n + 1LL, inc.d_nc, nullptr, -1, nullptr}};
     launch_exclusive_scans(jobs, 2, scan_temp, st);
   }
-  if (npairs > 0) inc_fill_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(pl.v4, npairs, inc.cursor, inc.raw);
-  if (npairs > 0) inc_sort_kernel<<<grid_for(px.nsv, 4), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.raw, inc.ent);
+  if (npairs > 0) {
+    if (ps.S == 4) inc_fill_kernel<4><<<grid_for(npairs, 256), 256, 0, st>>>(ps.v, npairs, inc.cursor, inc.raw);
+    else inc_fill_kernel<kSlotsW><<<grid_for(npairs, 256), 256, 0, st>>>(ps.v, npairs, inc.cursor, inc.raw);
+    inc_sort_kernel<<<grid_for(inc.nverts, 4), 256, 0, st>>>(inc.nverts, inc.verts, inc.ptr, inc.raw, inc.ent);
+  }
   clist_kernel<<<grid_for(n, 256), 256, 0, st>>>(n, inc.cflag, inc.cidx, inc.clist);
 }
 
-// g[v] += sum of pair gradient rows at v (pair-ascending order), free v only
 // g[v] += sum of the pair gradient rows at v over its incidence entries (free
-// proxy vertices only): one wave per vertex, lanes over entries, then a
-// fixed-order wave sum.
-__global__ void __launch_bounds__(256) add_barrier_grad_kernel(int32_t nsv, const int32_t* __restrict__ sv,
+// vertices only): one wave per vertex, lanes over entries, then a fixed-order
+// wave sum.
+template <int S>
+__global__ void __launch_bounds__(256) add_barrier_grad_kernel(int32_t nverts, const int32_t* __restrict__ verts,
                                                                const int32_t* __restrict__ ptr,
                                                                const int32_t* __restrict__ ent,
                                                                const double* __restrict__ grad, int32_t npairs,
@@ -375,14 +448,14 @@ __global__ void __launch_bounds__(256) add_barrier_grad_kernel(int32_t nsv, cons
                                                                double* __restrict__ g) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * (256 / PDIPC_WAVE) + threadIdx.x / PDIPC_WAVE;
-  if (i >= nsv) return;
-  const int32_t v = sv[i];
+  if (i >= nverts) return;
+  const int32_t v = verts[i];
   const int32_t b = ptr[v], e = ptr[v + 1];
   if (fixed[v] || e == b) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
   for (int32_t t = b + lane; t < e; t += PDIPC_WAVE) {
-    const int32_t k = ent[t] >> 2, a = ent[t] & 3;
+    const int32_t k = ent[t] / S, a = ent[t] % S;
     s0 += grad[static_cast<int64_t>(3 * a) * npairs + k];
     s1 += grad[static_cast<int64_t>(3 * a + 1) * npairs + k];
     s2 += grad[static_cast<int64_t>(3 * a + 2) * npairs + k];
@@ -397,11 +470,16 @@ __global__ void __launch_bounds__(256) add_barrier_grad_kernel(int32_t nsv, cons
   }
 }
 
-void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
-                             const uint8_t* fixed, double* g, hipStream_t st) {
+void launch_add_barrier_grad(const Incidence& inc, const PairSlots& ps, int32_t npairs, const uint8_t* fixed,
+                             double* g, hipStream_t st) {
   if (npairs <= 0) return;
-  add_barrier_grad_kernel<<<grid_for(px.nsv, 256 / PDIPC_WAVE), 256, 0, st>>>(px.nsv, px.sv, inc.ptr, inc.ent,
-                                                                                bo.grad, npairs, fixed, g);
+  const unsigned grid = grid_for(inc.nverts, 256 / PDIPC_WAVE);
+  if (ps.S == 4)
+    add_barrier_grad_kernel<4><<<grid, 256, 0, st>>>(inc.nverts, inc.verts, inc.ptr, inc.ent, ps.grad, npairs, fixed,
+                                                     g);
+  else
+    add_barrier_grad_kernel<kSlotsW><<<grid, 256, 0, st>>>(inc.nverts, inc.verts, inc.ptr, inc.ent, ps.grad, npairs,
+                                                           fixed, g);
 }
 
 // ---- reduced contact system ----------------------------------------------------------
@@ -424,13 +502,15 @@ __global__ void fill_kron_kernel(int32_t nc, const double* __restrict__ Cinv, do
 }
 
 // One wave per c vertex a (its three rows of M).  The wave walks a's incident
-// pairs in ascending order; lane (lb, r, s) adds U_k[3 la + r] . U_k[3 lb + s]
-// into M[3 a + r][3 c(lb) + s].  Within one pair the four local vertices map to
-// distinct c columns, so no two lanes write one entry in the same step and the
-// summation order is fixed.
+// pairs in ascending order; for each group of four slots lb of the pair, lane
+// (lb, r, s) adds U_k[3 la + r] . U_k[3 lb + s] into M[3 a + r][3 c(lb) + s].
+// The slots of one pair name distinct vertices, so no two lanes write one
+// entry in the same step and the summation order is fixed.
+template <int S>
 __global__ void __launch_bounds__(256) add_bcheck_kernel(int32_t nc, const int32_t* __restrict__ clist,
                                                          const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
-                                                         const int32_t* __restrict__ v4, const int32_t* __restrict__ cflag,
+                                                         const int32_t* __restrict__ vslot,
+                                                         const int32_t* __restrict__ cflag,
                                                          const int32_t* __restrict__ cidx, const double* __restrict__ U,
                                                          int32_t npairs, double* __restrict__ M) {
   const int lane = threadIdx.x % PDIPC_WAVE;
@@ -438,62 +518,68 @@ __global__ void __launch_bounds__(256) add_bcheck_kernel(int32_t nc, const int32
   if (ca >= nc) return;
   const int64_t N = 3 * static_cast<int64_t>(nc);
   const int32_t va = clist[ca];
-  const int lb = lane / 9, r = (lane % 9) / 3, sc = lane % 3;
+  const int r = (lane % 9) / 3, sc = lane % 3;
   const bool active = lane < 36;
   for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
-    const int32_t k = ent[t] >> 2, la = ent[t] & 3;
+    const int32_t k = ent[t] / S, la = ent[t] % S;
     if (!active) continue;
-    const int32_t vb = v4[4 * k + lb];
-    if (!cflag[vb]) continue;
-    const int64_t cb = cidx[vb];
-    double acc = 0.0;
+    for (int lb0 = 0; lb0 < S; lb0 += 4) {
+      const int lb = lb0 + lane / 9;
+      const int32_t vb = vslot[S * k + lb];
+      if (vb < 0 || !cflag[vb]) continue;
+      const int64_t cb = cidx[vb];
+      double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
-      acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
-             U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
-    M[(3 * ca + r) * N + 3 * cb + sc] += acc;
+      for (int c = 0; c < 5; ++c)
+        acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
+               U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
+      M[(3 * ca + r) * N + 3 * cb + sc] += acc;
+    }
   }
 }
 
 // Row block a of M = C^-1 + B_check in one pass (reduced systems up to
-// RB_LDS_N unknowns): one workgroup per contact vertex.  The 36 products of
-// each incidence entry (3 rows x 4 pair vertices x 3 columns) are formed by
-// all threads, RB_CHUNK entries at a time, and staged in LDS with their target
-// column; one wave then adds them to the three rows (LDS) entry by entry in
-// incidence order (deterministic), and the rows are written with the
-// C^-1 = C_s^-1 (x) I3 part added.
+// RB_LDS_N unknowns): one workgroup per contact vertex.  The 9 S products of
+// each incidence entry (3 rows x S slots x 3 columns) are formed by all
+// threads, several entries at a time, and staged in LDS with their target
+// column; the first 9 S threads then add them to the three rows (LDS) entry
+// by entry in incidence order (deterministic: the slots of one pair name
+// distinct vertices), and the rows are written with the C^-1 = C_s^-1 (x) I3
+// part added.
 constexpr int RB_LDS_N = 2048;
-constexpr int RB_CHUNK = 7;                 // 7 x 36 products per pass of 256 threads
+template <int S>
 __global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const double* __restrict__ Cinv,
                                                             const int32_t* __restrict__ clist,
                                                             const int32_t* __restrict__ ptr,
                                                             const int32_t* __restrict__ ent,
-                                                            const int32_t* __restrict__ v4,
+                                                            const int32_t* __restrict__ vslot,
                                                             const int32_t* __restrict__ cflag,
                                                             const int32_t* __restrict__ cidx,
                                                             const double* __restrict__ U, int32_t npairs,
                                                             double* __restrict__ M) {
+  constexpr int NP = 9 * S;                   // products per incidence entry
+  constexpr int CHUNK = 256 / NP;             // entries per pass of 256 threads
   extern __shared__ unsigned char smem_raw[];
   double* R = reinterpret_cast<double*>(smem_raw);     // 3 x N
-  __shared__ double P[RB_CHUNK * 36];
-  __shared__ int32_t Q[RB_CHUNK * 36];
+  __shared__ double P[CHUNK * NP];
+  __shared__ int32_t Q[CHUNK * NP];
   const int tid = threadIdx.x;
   const int64_t ca = blockIdx.x;
   const int64_t N = 3 * static_cast<int64_t>(nc);
   for (int64_t i = tid; i < 3 * N; i += blockDim.x) R[i] = 0.0;
   const int32_t va = clist[ca];
   const int32_t t0 = ptr[va], t1 = ptr[va + 1];
-  const int e = tid / 36, l36 = tid % 36;
-  const int lb = l36 / 9, r = (l36 % 9) / 3, sc = l36 % 3;
-  for (int32_t tc = t0; tc < t1; tc += RB_CHUNK) {
-    if (e < RB_CHUNK) {
+  const int e = tid / NP, lp = tid % NP;
+  const int lb = lp / 9, r = (lp % 9) / 3, sc = lp % 3;
+  for (int32_t tc = t0; tc < t1; tc += CHUNK) {
+    if (e < CHUNK) {
       const int32_t t = tc + e;
       double acc = 0.0;
       int32_t q = -1;
       if (t < t1) {
-        const int32_t k = ent[t] >> 2, la = ent[t] & 3;
-        const int32_t vb = v4[4 * k + lb];
-        if (cflag[vb]) {
+        const int32_t k = ent[t] / S, la = ent[t] % S;
+        const int32_t vb = vslot[S * k + lb];
+        if (vb >= 0 && cflag[vb]) {
 #pragma unroll
           for (int c = 0; c < 5; ++c)
             acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
@@ -505,11 +591,11 @@ __global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const do
       Q[tid] = q;
     }
     __syncthreads();
-    if (tid < 36) {
-      const int ne = min(RB_CHUNK, t1 - tc);
+    if (tid < NP) {
+      const int ne = min(CHUNK, t1 - tc);
       for (int ee = 0; ee < ne; ++ee) {
-        const int32_t q = Q[ee * 36 + tid];
-        if (q >= 0) R[q] += P[ee * 36 + tid];
+        const int32_t q = Q[ee * NP + tid];
+        if (q >= 0) R[q] += P[ee * NP + tid];
       }
     }
     __syncthreads();
@@ -522,29 +608,39 @@ __global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const do
     }
 }
 
-void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairList& pl,
-                             int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st) {
+void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairSlots& ps,
+                             int32_t npairs, double* M, hipStream_t st) {
   int64_t N = 3 * static_cast<int64_t>(nc);
   if (N <= RB_LDS_N) {
-    assemble_rows_kernel<<<static_cast<unsigned>(nc), 256, sizeof(double) * 3 * N, st>>>(
-        nc, Cinv, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx, bo.U, npairs, M);
+    const size_t shm = sizeof(double) * 3 * N;
+    if (ps.S == 4)
+      assemble_rows_kernel<4><<<static_cast<unsigned>(nc), 256, shm, st>>>(
+          nc, Cinv, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx, ps.U, npairs, M);
+    else
+      assemble_rows_kernel<kSlotsW><<<static_cast<unsigned>(nc), 256, shm, st>>>(
+          nc, Cinv, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx, ps.U, npairs, M);
     return;
   }
   fill_kron_kernel<<<grid_for(N * N, 256), 256, 0, st>>>(nc, Cinv, M);
-  add_bcheck_kernel<<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, pl.v4, inc.cflag, inc.cidx,
-                                                      bo.U, npairs, M);
+  if (ps.S == 4)
+    add_bcheck_kernel<4><<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx,
+                                                           ps.U, npairs, M);
+  else
+    add_bcheck_kernel<kSlotsW><<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag,
+                                                                 inc.cidx, ps.U, npairs, M);
 }
 
-// w_k = U_k^T u_local (5 per pair), u indexed by c index of each free local vertex
-__global__ void pair_ut_kernel(int32_t npairs, const int32_t* __restrict__ v4, const int32_t* __restrict__ cflag,
+// w_k = U_k^T u_local (5 per pair), u indexed by the c index of each free slot
+template <int S>
+__global__ void pair_ut_kernel(int32_t npairs, const int32_t* __restrict__ vslot, const int32_t* __restrict__ cflag,
                                const int32_t* __restrict__ cidx, const double* __restrict__ U,
                                const double* __restrict__ u, double* __restrict__ w) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npairs) return;
   double acc[5] = {0, 0, 0, 0, 0};
-  for (int lb = 0; lb < 4; ++lb) {
-    int32_t vb = v4[4 * k + lb];
-    if (!cflag[vb]) continue;
+  for (int lb = 0; lb < S; ++lb) {
+    int32_t vb = vslot[S * k + lb];
+    if (vb < 0 || !cflag[vb]) continue;
     int64_t cb = cidx[vb];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -557,8 +653,9 @@ __global__ void pair_ut_kernel(int32_t npairs, const int32_t* __restrict__ v4, c
   for (int c = 0; c < 5; ++c) w[static_cast<int64_t>(c) * npairs + k] = acc[c];
 }
 
-// v_a = sum over incident (pair k, local slot l) of U_{k,l} w_k: one wave per c
+// v_a = sum over incident (pair k, slot l) of U_{k,l} w_k: one wave per c
 // vertex, lanes over its incidence entries, then a fixed-order wave sum.
+template <int S>
 __global__ void __launch_bounds__(256) bu_gather_kernel(int32_t nc, const int32_t* __restrict__ clist,
                                                         const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
                                                         const double* __restrict__ U, const double* __restrict__ w,
@@ -570,7 +667,7 @@ __global__ void __launch_bounds__(256) bu_gather_kernel(int32_t nc, const int32_
   double s[3] = {0, 0, 0};
 #pragma unroll 4
   for (int32_t t = ptr[va] + lane; t < ptr[va + 1]; t += PDIPC_WAVE) {
-    const int32_t k = ent[t] >> 2, la = ent[t] & 3;
+    const int32_t k = ent[t] / S, la = ent[t] % S;
     double wk[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) wk[c] = w[static_cast<int64_t>(c) * npairs + k];
@@ -586,12 +683,18 @@ __global__ void __launch_bounds__(256) bu_gather_kernel(int32_t nc, const int32_
     for (int r = 0; r < 3; ++r) v[3 * ca + r] = s[r];
 }
 
-void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, int32_t npairs, const BarrierOut& bo,
-                         const uint8_t* fixed, const double* u, double* wtmp, double* v, hipStream_t st) {
+void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairSlots& ps, int32_t npairs, const uint8_t* fixed,
+                         const double* u, double* wtmp, double* v, hipStream_t st) {
   (void)fixed;
   if (nc <= 0) return;
-  pair_ut_kernel<<<grid_for(npairs, 256), 256, 0, st>>>(npairs, pl.v4, inc.cflag, inc.cidx, bo.U, u, wtmp);
-  bu_gather_kernel<<<grid_for(nc, 256 / PDIPC_WAVE), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, bo.U, wtmp, npairs, v);
+  const unsigned gp = grid_for(npairs, 256), gc = grid_for(nc, 256 / PDIPC_WAVE);
+  if (ps.S == 4) {
+    pair_ut_kernel<4><<<gp, 256, 0, st>>>(npairs, ps.v, inc.cflag, inc.cidx, ps.U, u, wtmp);
+    bu_gather_kernel<4><<<gc, 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, ps.U, wtmp, npairs, v);
+  } else {
+    pair_ut_kernel<kSlotsW><<<gp, 256, 0, st>>>(npairs, ps.v, inc.cflag, inc.cidx, ps.U, u, wtmp);
+    bu_gather_kernel<kSlotsW><<<gc, 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, ps.U, wtmp, npairs, v);
+  }
 }
 
 }  // namespace pdipc

@@ -158,8 +158,38 @@ struct BarrierOut {
 void launch_barrier(const PairList& pl, int32_t npairs, int32_t n_pt, const double* x, double dhat, double kappa,
                     int form, bool fp32, BarrierOut& bo, hipStream_t st);
 
-// vertex -> (pair, local) incidence (sorted), per-vertex gradient add,
-// affected-set map.  inc_ptr: n + 1, inc_ent: 4 * npairs.
+// Per-pair terms over simulation vertices ("slots"): S slots per pair, the
+// simulation vertex of each (v: S x npairs, -1 = unused), the barrier gradient
+// rows (grad: 3 S x npairs SoA, row 3 slot + coordinate) and the rows of the
+// PSD factor (U: 15 S x npairs SoA, entry 5 (3 slot + coordinate) + column).
+// With the proxy embedded by selection these are the barrier outputs
+// themselves (S = 4, v = the pair's four vertices); with an interpolating
+// embedding s = W x they are W^T applied to them (S = 16: the distinct
+// simulation vertices of the pair's four proxy points).
+struct PairSlots {
+  int32_t S;
+  const int32_t* v;
+  const double* grad;
+  const double* U;
+};
+
+// Proxy embedding s = W x (CSR over the proxy vertices, at most 4 entries
+// per row).
+struct EmbedDev {
+  int32_t ns;
+  const int32_t* ptr;
+  const int32_t* col;
+  const double* val;
+};
+// s (ns x 3) = W x
+void launch_embed_positions(const EmbedDev& W, const double* x, double* s, hipStream_t st);
+// Slots of every pair (S = 16): each proxy point's W entries, merged per
+// simulation vertex in the order they occur; grad and U rows weighted.
+void launch_expand_pairs(const EmbedDev& W, const int32_t* v4, int32_t npairs, const BarrierOut& bo,
+                         int32_t* slot_v, double* slot_grad, double* slot_U, hipStream_t st);
+
+// vertex -> (pair, slot) incidence (sorted), per-vertex gradient add,
+// affected-set map.  inc_ptr: n + 1, inc_ent: S * npairs (entry S k + slot).
 struct Incidence {
   int32_t* cnt;         // n + 1
   int32_t* ptr;         // n + 1
@@ -170,16 +200,18 @@ struct Incidence {
   int32_t* cidx;        // n + 1: exclusive scan of cflag (c index if flagged)
   int32_t* clist;       // n: c index -> sim vertex
   int32_t* d_nc;        // 5: n_c, then the change of c (any, left, entered), then the entry total
+  const int32_t* verts; // the simulation vertices that slots can name, ascending
+  int32_t nverts;
 };
 // Incidence lists, contact flags, ranks and list of c.  With prev_cflag (the
 // flags of an earlier c, n + 1 entries), d_nc[1..3] also receive the change
 // of c (any flag differs, vertices that left, vertices that entered) and, with
 // ids, up to cap of the leaving / entering vertices go to rem_ids / add_ids.
-void build_incidence(const PairList& pl, int32_t npairs, int32_t n, const ProxyDev& px, const uint8_t* fixed,
-                     Incidence& inc, void* scan_temp, hipStream_t st, const int32_t* prev_cflag = nullptr,
+void build_incidence(const PairSlots& ps, int32_t npairs, int32_t n, const uint8_t* fixed, Incidence& inc,
+                     void* scan_temp, hipStream_t st, const int32_t* prev_cflag = nullptr,
                      int32_t* rem_ids = nullptr, int32_t* add_ids = nullptr, int32_t cap = 0);
-void launch_add_barrier_grad(const Incidence& inc, const ProxyDev& px, const BarrierOut& bo, int32_t npairs,
-                             const uint8_t* fixed, double* g, hipStream_t st);
+void launch_add_barrier_grad(const Incidence& inc, const PairSlots& ps, int32_t npairs, const uint8_t* fixed,
+                             double* g, hipStream_t st);
 
 // ---------------------------------------------------------- global (Eq. 7)
 struct FactorDev {
@@ -232,14 +264,14 @@ void launch_unpack(const FactorDev& f, int32_t n, const double* sol, double* dx,
 // C_s = Sigma^-1[c, c] (nc x nc), using x2 index of each c vertex
 void launch_gather_cc(const FactorDev& f, int32_t nc, const int32_t* c_x2, double* Cs, hipStream_t st);
 // M = Cinv (x) I3 + sum_k U_k U_k^T blocks (3nc x 3nc row-major, full)
-void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairList& pl,
-                             int32_t npairs, const BarrierOut& bo, double* M, hipStream_t st);
+void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairSlots& ps,
+                             int32_t npairs, double* M, hipStream_t st);
 // out (nc x 3) = (Cinv (x) I3) z_c, z_c gathered from z (n2 x 3) by c_x2
 void launch_cinv_times_zc(int32_t nc, const double* Cinv, const int32_t* c_x2, const double* z, double* out,
                           hipStream_t st);
 // v (nc x 3) = Bcheck u
-void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairList& pl, int32_t npairs, const BarrierOut& bo,
-                         const uint8_t* fixed, const double* u, double* wtmp, double* v, hipStream_t st);
+void launch_bcheck_apply(int32_t nc, const Incidence& inc, const PairSlots& ps, int32_t npairs, const uint8_t* fixed,
+                         const double* u, double* wtmp, double* v, hipStream_t st);
 // z -= Sigma^-1[:, c] v   (n2 x 3)
 void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* z,
                               hipStream_t st);

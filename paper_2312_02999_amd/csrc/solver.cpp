@@ -167,6 +167,16 @@ struct Solver {
   // work arrays of the balancing gradients
   double kappa = 0.0, d2min_prev = 0.0, eps_d2 = 0.0;
   DBuf<double> ka_gE, ka_gb, ka_R;
+  // proxy embedding s = W x (Section 3.1) when a row of W interpolates:
+  // collision primitives index proxy vertices, positions s and steps W dx
+  // feed the contact kernels, and each pair's terms go to its simulation
+  // vertices through W (slots); otherwise the proxy selects simulation
+  // vertices and the pairs' own terms are used
+  bool embed = false;
+  int32_t n_inc_verts = 0;
+  EmbedDev W{};
+  DBuf<int32_t> w_ptr, w_col, inc_verts, slot_v;
+  DBuf<double> w_val, spos, sdx, slot_g, slot_U;
   int32_t adjoint_iters = 0;
 
   // host helpers
@@ -378,21 +388,33 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
         sum += wv;
       }
       if (!(std::fabs(sum - 1.0) <= 1e-12)) fail(PDIPC_E_INVALID, "a row of W does not sum to 1");
-      if (e - b != 1)
-        fail(PDIPC_E_INVALID, "proxy vertex " + std::to_string(r) +
-                                  " interpolates several vertices: only embedding by selection is supported");
+      if (e - b > 4) fail(PDIPC_E_INVALID, "a row of W has more than 4 entries");
       const int32_t c = md->W_col[b];
-      if (seen[c] >= 0) fail(PDIPC_E_INVALID, "two proxy vertices select the same simulation vertex");
-      seen[c] = r;
-      pick[r] = c;
+      const bool picks = e - b == 1 && (md->W_val ? md->W_val[b] : 1.0) == 1.0 && seen[c] < 0;
+      if (picks) seen[c] = r;
+      pick[r] = picks ? c : -1;
+      if (!picks) S->embed = true;
     }
-    for (int32_t& v : tris) {
+    for (int32_t v : tris)
       if (v < 0 || v >= ns) fail(PDIPC_E_INVALID, "proxy triangle index out of range");
-      v = pick[v];
+    if (!S->embed) {
+      // every row selects its own vertex: resolve the triangles to those
+      for (int32_t& v : tris) v = pick[v];
+    } else {
+      std::vector<int32_t> wp(md->W_rowptr, md->W_rowptr + ns + 1), wc(md->W_col, md->W_col + md->W_rowptr[ns]);
+      std::vector<double> wv(wc.size(), 1.0);
+      if (md->W_val) wv.assign(md->W_val, md->W_val + md->W_rowptr[ns]);
+      S->w_ptr.upload(wp.data(), ns + 1LL, st);
+      S->w_col.upload(wc.data(), static_cast<int64_t>(wc.size()), st);
+      S->w_val.upload(wv.data(), static_cast<int64_t>(wv.size()), st);
+      S->W = EmbedDev{ns, S->w_ptr.p, S->w_col.p, S->w_val.p};
+      S->spos.ensure(3LL * ns);
+      S->sdx.ensure(3LL * ns);
     }
   }
+  const int32_t nproxy = S->embed ? md->n_surf_verts : n;
   for (int32_t v : tris)
-    if (v < 0 || v >= n) fail(PDIPC_E_INVALID, "proxy triangle index out of range");
+    if (v < 0 || v >= nproxy) fail(PDIPC_E_INVALID, "proxy triangle index out of range");
   for (int32_t f = 0; f < F; ++f)
     if (tris[3 * f] == tris[3 * f + 1] || tris[3 * f + 1] == tris[3 * f + 2] || tris[3 * f] == tris[3 * f + 2])
       fail(PDIPC_E_INVALID, "proxy triangle with repeated vertex");
@@ -416,15 +438,27 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   S->nsv = static_cast<int32_t>(svv.size());
   S->nst = F;
   S->nse = static_cast<int32_t>(ev.size());
+  // the simulation vertices the proxy moves with: the proxy vertices
+  // themselves, or the columns of their rows of W
+  std::vector<int32_t> wsupp = svv;
+  if (S->embed) {
+    wsupp.clear();
+    for (int32_t p : svv)
+      for (int32_t e = md->W_rowptr[p]; e < md->W_rowptr[p + 1]; ++e) wsupp.push_back(md->W_col[e]);
+    std::sort(wsupp.begin(), wsupp.end());
+    wsupp.erase(std::unique(wsupp.begin(), wsupp.end()), wsupp.end());
+  }
+  S->inc_verts.upload(wsupp.data(), static_cast<int64_t>(wsupp.size()), st);
+  S->n_inc_verts = static_cast<int32_t>(wsupp.size());
 
   // ---- DOF split (Eq. 6) -----------------------------------------------------------
   std::vector<uint8_t> reg(n, 0);
   if (md->region) {
     for (int32_t v = 0; v < n; ++v) reg[v] = md->region[v] && !md->dirichlet[v];
-    for (int32_t v : svv)
+    for (int32_t v : wsupp)
       if (!md->dirichlet[v] && !reg[v]) fail(PDIPC_E_INVALID, "a free proxy vertex is outside the marked region");
   } else {
-    for (int32_t v : svv) reg[v] = md->dirichlet[v] ? 0 : 1;
+    for (int32_t v : wsupp) reg[v] = md->dirichlet[v] ? 0 : 1;
   }
   std::vector<int32_t> x1, x2, vblock(n, -1), vlocal(n, -1);
   for (int32_t v = 0; v < n; ++v) {
@@ -715,6 +749,16 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   return PDIPC_OK;
 }
 
+// Positions the contact kernels read: s = W x (computed by
+// update_proxy_positions), or x itself.
+static const double* proxy_x(Solver* S) { return S->embed ? S->spos.p : S->x.p; }
+static const double* proxy_dx(Solver* S) { return S->embed ? S->sdx.p : S->dx.p; }
+static void update_proxy_positions(Solver* S, const double* x) {
+  if (S->embed) launch_embed_positions(S->W, x, S->spos.p, S->st);
+}
+static void update_proxy_step(Solver* S) {
+  if (S->embed) launch_embed_positions(S->W, S->dx.p, S->sdx.p, S->st);
+}
 static void grow_pairs(Solver* S, PairList& pl, DBuf<int32_t>& ty, DBuf<int32_t>& ii, DBuf<int32_t>& jj,
                        DBuf<int32_t>& v4, int64_t need) {
   int64_t cap = std::max<int64_t>(need + need / 2 + 256, pl.cap);
@@ -756,7 +800,7 @@ static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee, int32_t
   S->bb.scan_temp = S->scan_tmp.p;
   for (int attempt = 0; attempt < 3; ++attempt) {
     int64_t need = 0;
-    int rc = filter_active(S->cand, S->cand_n, S->cand_pt, S->x.p, S->opt.dhat, pl, S->cflagbuf.p, S->cposbuf.p,
+    int rc = filter_active(S->cand, S->cand_n, S->cand_pt, proxy_x(S), S->opt.dhat, pl, S->cflagbuf.p, S->cposbuf.p,
                            S->totals.p + 4, S->h_counts + 4, S->scan_tmp.p, npt, nee, S->st, &need, near_ties);
     if (rc == 0) return;
     grow_pairs(S, pl, S->act_type, S->act_i, S->act_j, S->act_v4, need);
@@ -764,17 +808,36 @@ static void pairs_from_candidates(Solver* S, int32_t* npt, int32_t* nee, int32_t
   fail(PDIPC_E_NOMEM, "pair list growth failed");
 }
 
+static constexpr int kEmbedSlots = 16;   // slots per pair with an interpolating W
+
 static void ensure_pair_arrays(Solver* S, int64_t np) {
   int64_t cap = std::max<int64_t>(np, 1);
+  const int64_t slots = S->embed ? kEmbedSlots : 4;
   if (S->b_energy.cap < cap) {
     int64_t c = cap + cap / 2 + 256;
-    S->b_energy.ensure(c); S->b_grad.ensure(12 * c); S->b_U.ensure(60 * c); S->inc_ent.ensure(4 * c);
-    S->inc_raw.ensure(4 * c);
+    S->b_energy.ensure(c); S->b_grad.ensure(12 * c); S->b_U.ensure(60 * c); S->inc_ent.ensure(slots * c);
+    S->inc_raw.ensure(slots * c);
     S->wtmp.ensure(5 * c);
+    if (S->embed) {
+      S->slot_v.ensure(slots * c);
+      S->slot_g.ensure(3 * slots * c);
+      S->slot_U.ensure(15 * slots * c);
+    }
   }
   S->bo = BarrierOut{S->b_energy.p, S->b_grad.p, S->b_U.p};
   S->inc = Incidence{S->inc_cnt.p, S->inc_ptr.p, S->inc_cursor.p, S->inc_raw.p, S->inc_ent.p, S->inc_cflag.p,
-                     S->inc_cidx.p, S->inc_clist.p, S->inc_nc.p};
+                     S->inc_cidx.p, S->inc_clist.p, S->inc_nc.p, S->inc_verts.p, S->n_inc_verts};
+}
+
+// The active pairs' terms over simulation vertices.
+static PairSlots pair_slots(Solver* S) {
+  if (!S->embed) return PairSlots{4, S->act.v4, S->bo.grad, S->bo.U};
+  return PairSlots{kEmbedSlots, S->slot_v.p, S->slot_g.p, S->slot_U.p};
+}
+
+// The barrier terms of the np active pairs over simulation vertices.
+static void expand_pair_terms(Solver* S, int32_t np) {
+  if (S->embed) launch_expand_pairs(S->W, S->act.v4, np, S->bo, S->slot_v.p, S->slot_g.p, S->slot_U.p, S->st);
 }
 
 static LocalArgs local_args(Solver* S) { return LocalArgs{S->m, S->tets.p, S->Bm.p, S->w.p, S->A.p}; }
@@ -858,10 +921,11 @@ static double balanced_kappa(Solver* S, int32_t npt, int32_t np) {
   S->ka_gb.ensure(n3);
   S->ka_R.ensure(9LL * S->m);
   S->prod.ensure(n3);
-  launch_barrier(S->act, np, npt, S->x.p, S->opt.dhat, 1.0, S->opt.barrier_form, false, S->bo, st);
-  build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st);
+  launch_barrier(S->act, np, npt, proxy_x(S), S->opt.dhat, 1.0, S->opt.barrier_form, false, S->bo, st);
+  expand_pair_terms(S, np);
+  build_incidence(pair_slots(S), np, S->n, S->fixed.p, S->inc, S->scan_tmp.p, st);
   launch_fill_f64(S->ka_gb.p, n3, 0.0, st);
-  launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->ka_gb.p, st);
+  launch_add_barrier_grad(S->inc, pair_slots(S), np, S->fixed.p, S->ka_gb.p, st);
   // PD gradient at x from the frame's starting rotations (kept unchanged)
   launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->ka_R.p, S->E0.p, S->tetg.p, false, st);
   launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->ka_gE.p, st);
@@ -880,7 +944,7 @@ static void adapt_kappa(Solver* S, bool frame_start, int32_t npt, int32_t np) {
   double d2min = INFINITY;
   if (np > 0) {
     S->tpair.ensure(np);
-    launch_pair_min_dist2(S->act, np, npt, S->x.p, S->tpair.p, S->st);
+    launch_pair_min_dist2(S->act, np, npt, proxy_x(S), S->tpair.p, S->st);
     launch_min_clamp1(S->tpair.p, np, S->scal.p, S->red_tmp.p, S->st);
     d2min = read_scalar_d(S, S->scal.p);
   }
@@ -897,13 +961,14 @@ static void adapt_kappa(Solver* S, bool frame_start, int32_t npt, int32_t np) {
 static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool defer = false) {
   const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
   hipStream_t st = S->st;
+  update_proxy_positions(S, S->x.p);
   if (S->cand_valid && !first_check) pairs_from_candidates(S, &io.npt, &io.nee, &io.near_ties);
-  else pairs(S, true, S->x.p, nullptr, &io.npt, &io.nee);
+  else pairs(S, true, proxy_x(S), nullptr, &io.npt, &io.nee);
   const int32_t np = io.npt + io.nee;
   ensure_pair_arrays(S, np);
   if (first_check && np > 0) {
     S->tpair.ensure(np);
-    launch_pair_min_dist2(S->act, np, io.npt, S->x.p, S->tpair.p, st);
+    launch_pair_min_dist2(S->act, np, io.npt, proxy_x(S), S->tpair.p, st);
     launch_min_clamp1(S->tpair.p, np, S->scal.p, S->red_tmp.p, st);
     double dmin2 = read_scalar_d(S, S->scal.p);
     if (!(dmin2 > 0.0)) fail(PDIPC_E_INTERSECTING, "input state has a contact pair at distance 0");
@@ -912,8 +977,9 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
   io.kappa = S->kappa;
   {
     ScopedTimer tm(S, TK_BARRIER);
-    launch_barrier(S->act, np, io.npt, S->x.p, S->opt.dhat, S->kappa, S->opt.barrier_form, fp32, S->bo, st);
+    launch_barrier(S->act, np, io.npt, proxy_x(S), S->opt.dhat, S->kappa, S->opt.barrier_form, fp32, S->bo, st);
   }
+  expand_pair_terms(S, np);
   {
     // against the c of the current C^-1: the change of c, and the vertices
     // that left / entered it listed for the incremental update
@@ -922,7 +988,7 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
       S->cset_ids.ensure(2 * kCinvMaxDelta);
       ids = S->cset_ids.p;
     }
-    build_incidence(S->act, np, S->n, S->px, S->fixed.p, S->inc, S->scan_tmp.p, st,
+    build_incidence(pair_slots(S), np, S->n, S->fixed.p, S->inc, S->scan_tmp.p, st,
                     S->cinv_valid ? S->prev_cflag.p : nullptr, ids, ids ? ids + kCinvMaxDelta : nullptr,
                     kCinvMaxDelta);
   }
@@ -938,7 +1004,7 @@ static void assemble_gradient(Solver* S, bool first_check, IterOut& io, bool def
     launch_local_step(local_args(S), S->x.p, S->Rtet.p, S->Rtet.p, S->E0.p, S->tetg.p, fp32, st, e0, e1);
   }
   launch_gather_vertex_grad(S->n, S->m, S->vt_ptr.p, S->vt_ent.p, S->tetg.p, S->fixed.p, S->g.p, st);
-  launch_add_barrier_grad(S->inc, S->px, S->bo, np, S->fixed.p, S->g.p, st);
+  launch_add_barrier_grad(S->inc, pair_slots(S), np, S->fixed.p, S->g.p, st);
   stage_mark(S, 2);
   if (!defer) finish_readback(S, io);
 }
@@ -1118,7 +1184,7 @@ static void global_step(Solver* S, IterOut& io) {
     }
     S->cinv_incr_ok = true;
     HIPCHK(hipEventRecord(S->ev_cinv, sd));          // C^-1 and c_x2 ready
-    launch_assemble_reduced(nc, S->Cinv.p, S->inc, S->act, np, S->bo, S->Mred.p, sd);
+    launch_assemble_reduced(nc, S->Cinv.p, S->inc, pair_slots(S), np, S->Mred.p, sd);
     // The factorisation is queued in two parts with the rest of the main
     // stream's sweep between them, so that neither stream waits for the host.
     const int64_t nlaunch = dense_cholesky_launches(N3);
@@ -1166,7 +1232,7 @@ static void global_step(Solver* S, IterOut& io) {
       }
     }
     if (!mixed || fallback) dense_chol_solve_into<double>(S->ML.p, S->MLi.p, N3, S->rhs.p, S->u.p, st);
-    launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
+    launch_bcheck_apply(nc, S->inc, pair_slots(S), np, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
     if (hinv_path) launch_hinv_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p, st);
     else launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
   } else {
@@ -1230,7 +1296,7 @@ static void global_step_pcg(Solver* S, IterOut& io) {
     launch_pd_matvec(local_args(S), S->n, S->vt_ptr.p, S->vt_ent.p, S->fixed.p, p, S->tetg.p, q, st);
     if (nc > 0 && np > 0) {
       launch_gather_c(nc, S->inc.clist, p, S->cg_pc.p, st);
-      launch_bcheck_apply(nc, S->inc, S->act, np, S->bo, S->fixed.p, S->cg_pc.p, S->wtmp.p, S->cg_vc.p, st);
+      launch_bcheck_apply(nc, S->inc, pair_slots(S), np, S->fixed.p, S->cg_pc.p, S->wtmp.p, S->cg_vc.p, st);
       launch_scatter_add_c(nc, S->inc.clist, S->cg_vc.p, q, st);
     }
   };
@@ -1287,7 +1353,7 @@ static void global_step_schur(Solver* S, IterOut& io) {
       S->Mred.ensure(9LL * nc * nc);
       S->c_x2.ensure(nc);
       launch_fill_f64(S->Cs.p, static_cast<int64_t>(nc) * nc, 0.0, st);
-      launch_assemble_reduced(nc, S->Cs.p, S->inc, S->act, np, S->bo, S->Mred.p, st);
+      launch_assemble_reduced(nc, S->Cs.p, S->inc, pair_slots(S), np, S->Mred.p, st);
       launch_c_to_x2(nc, S->inc.clist, S->vert2x2.p, S->c_x2.p, st);
       launch_scatter_block(nc, S->c_x2.p, S->Mred.p, f.n2, S->shat.p, st);
     }
@@ -1333,7 +1399,8 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   hipStream_t st = S->st;
   const bool fp32 = S->opt.precision == PDIPC_MIXED_FP32;
   int32_t cpt = 0, cee = 0;
-  pairs(S, false, S->x.p, S->dx.p, &cpt, &cee);
+  update_proxy_step(S);
+  pairs(S, false, proxy_x(S), proxy_dx(S), &cpt, &cee);
   const int32_t ncand = cpt + cee;
   io.ncand = ncand;
   S->cand_n = ncand;
@@ -1347,7 +1414,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   {
     ScopedTimer tm(S, TK_CCD);
     // with the candidates' barrier energies at x, the line search's reference
-    nccd = launch_ccd(S->cand, ncand, cpt, S->x.p, S->dx.p, S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p,
+    nccd = launch_ccd(S->cand, ncand, cpt, proxy_x(S), proxy_dx(S), S->opt.ccd_eta, S->opt.ccd_steps, S->tpair.p,
                       S->ccd_part.p, st, S->opt.dhat, S->kappa, S->opt.barrier_form, S->bE0.p);
   }
   // back-tracking line search on the device: trials read alpha from the state
@@ -1362,7 +1429,8 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
       ScopedTimer tm(S, TK_TRIAL);
       launch_trial_energy(local_args(S), S->x.p, S->dx.p, ls, S->Rtet.p, S->E0.p, S->dE.p, fp32, st);
     }
-    launch_pair_barrier_energy(S->cand, ncand, cpt, S->x.p, S->dx.p, ls, S->opt.dhat, S->kappa, S->opt.barrier_form,
+    launch_pair_barrier_energy(S->cand, ncand, cpt, proxy_x(S), proxy_dx(S), ls, S->opt.dhat, S->kappa,
+                               S->opt.barrier_form,
                                S->bE0.p, S->bdE.p, st);
     launch_sum2_decide(S->dE.p, S->m, S->bdE.p, ncand, ls, S->red_tmp.p, S->opt.ls_max_halvings, st);
   };
@@ -1507,6 +1575,7 @@ static int32_t do_solve_frame(Solver* S, const double* x_in, double* x_out, pdip
 // Eq. 7 and 11), then dL/da from lambda.
 static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
   if (!S->have_solution) fail(PDIPC_E_INVALID, "no converged frame to differentiate");
+  if (S->embed) fail(PDIPC_E_INVALID, "the adjoint supports a proxy embedded by selection only");
   if (!S->have_scalar) fail(PDIPC_E_INVALID, "the actuation was not set through pdipc_set_actuation_scalar");
   hipStream_t st = S->st;
   const int64_t n3 = 3LL * S->n;
@@ -1797,7 +1866,8 @@ int32_t pdipc_debug_contacts(void* h, const double* x, int32_t* out, int32_t cap
   return guarded(S, [&] {
     int32_t npt = 0, nee = 0;
     S->cand_valid = false;
-    pairs(S, true, x, nullptr, &npt, &nee);
+    update_proxy_positions(S, x);
+    pairs(S, true, S->embed ? S->spos.p : x, nullptr, &npt, &nee);
     const int32_t np = npt + nee;
     *count = np;
     if (out && np > 0) {

@@ -661,3 +661,85 @@ def test_adaptive_kappa_matches_oracle():
         [ref.kappa[k + 1] / ref.kappa[k] for k in range(len(kg) - 1)]
     assert np.allclose(kg, ref.kappa, rtol=1e-9, atol=0)
     assert err < 1e-9, err
+
+
+# --------------------------------------------------------------------------
+# embedded proxy s = W x (Section 3.1): a finer proxy whose edge midpoints
+# interpolate two simulation vertices
+# --------------------------------------------------------------------------
+def test_embedded_proxy_contact_set_and_iteration_c1():
+    """C1 with its facing surfaces refined (midpoints on W rows of two
+    weights): the constraint set on s = W x equals the oracle's pair for
+    pair (proxy vertex ids), and one iteration's dx, alpha_m and alpha match
+    within 1e-9."""
+    sc = mg.refine_proxy(mg.slabs(0))
+    S = _solver(sc)
+    A = _set_act(S, sc, 0.4)
+    x = _pressed(sc, 8e-4, seed=1)
+    prob = osolver.setup_scene(sc)
+    s = osolver.proxy_positions(prob, x)
+    cs = ocontact.constraint_set(s, prob.prox, prob.dhat)
+    want = np.concatenate([np.c_[np.zeros(len(cs.pt), np.int64), cs.pt],
+                           np.c_[np.ones(len(cs.ee), np.int64), cs.ee]]).astype(np.int64)
+    pairs = S.debug_contacts(_t(x))
+    assert len(want) > 100
+    assert np.array_equal(pairs.astype(np.int64), want)
+    dx, am, al = S.debug_step(_t(x))
+    _, rec, _ = osolver.iteration(prob, x, A)
+    err = np.abs(dx.cpu().numpy() - rec.dx).max() / np.abs(rec.dx).max()
+    print(f"embedded proxy C1: pairs {len(want)} n_c {len(osolver.affected_vertices(prob, rec.cs))} "
+          f"dx err {err:.3e} alpha_m {am} / {rec.alpha_m}")
+    assert err < 1e-9, err
+    assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
+    assert abs(al - rec.alpha) <= 1e-9 * max(1.0, rec.alpha)
+
+
+@pytest.mark.parametrize("method", [0, 1, 2])
+def test_embedded_proxy_frames_match_oracle(method):
+    """The refined tiny scene's frames with each global step (the method, CG
+    baseline, Schur complement only): positions within 1e-9 of the
+    bounding-box diagonal of the oracle's."""
+    sc = mg.refine_proxy(mg.scene_by_name("tiny"))
+    S = _solver(sc, iters=sc.iters, global_method=method, cg_tol=1e-13)
+    prob = osolver.setup_scene(sc)
+    x = sc.X.copy()
+    xg = _t(x)
+    diag = np.linalg.norm(sc.X.max(0) - sc.X.min(0))
+    for t in range(sc.frames):
+        A = _set_act(S, sc, (t + 1) / sc.frames)
+        xg, st = S.solve_frame(xg, stats=True)
+        r = osolver.frame(prob, x, A, iters=sc.iters)
+        x = r.x
+        err = np.abs(xg.cpu().numpy() - x).max() / diag
+        print(f"embedded tiny, global step {method}, frame {t}: err {err:.3e} n_c {st['n_c']} / {max(r.n_c)}")
+        assert err < 1e-9, (t, err)
+    assert max(r.n_c) > 0
+
+
+def test_selection_written_as_W_is_the_plain_proxy():
+    """An explicit selection W (one weight of 1 per row) runs the plain
+    proxy's path: the same frame, bit for bit."""
+    sc = mg.slabs(0, nx=4, ny=4, nz=1, gap=1e-3)
+    verts = np.unique(sc.surf_tris)
+    local = np.searchsorted(verts, sc.surf_tris).astype(np.int32)
+    W = (np.arange(verts.size + 1, dtype=np.int32), verts.astype(np.int32), np.ones(verts.size))
+    from paper_2312_02999_amd import Solver
+    S0 = Solver(sc, iters=10)
+    S1 = Solver(X=sc.X, tets=sc.tets, dirichlet=sc.dirichlet, surf_tris=local, region=sc.region, W=W, iters=10)
+    a, R = _t(sc.actuation_at(1.0)), _t(sc.act_R.reshape(-1, 9))
+    S0.set_actuation_scalar(a, R)
+    S1.set_actuation_scalar(a, R)
+    x0 = S0.solve_frame(_t(sc.X)).cpu().numpy()
+    x1 = S1.solve_frame(_t(sc.X)).cpu().numpy()
+    assert np.array_equal(x0, x1)
+
+
+def test_embedded_proxy_adjoint_is_rejected():
+    from paper_2312_02999_amd import PdipcError
+    sc = mg.refine_proxy(mg.scene_by_name("tiny"))
+    S = _solver(sc, iters=3)
+    _set_act(S, sc, 0.5)
+    x = S.solve_frame(_t(sc.X))
+    with pytest.raises(PdipcError) as ei:
+        S.solve_frame_backward(torch.ones_like(x))
+    assert "E_INVALID" in str(ei.value)

@@ -165,12 +165,18 @@ def test_init_validates_the_proxy_embedding():
     val[2] = 0.9
     rc, msg = _init_rc(sc, W=(rp, sv, val), tris=local)
     assert rc == -1 and "sum to 1" in msg
-    # a row interpolating two vertices (barycentric embedding)
+    # a row interpolating two vertices (barycentric embedding) is accepted;
+    # more than four entries in a row are not
     rp2 = np.concatenate([[0, 2], np.arange(2, k + 1) + 1])
     col2 = np.concatenate([[sv[0], sv[0] + 1], sv[1:]])
     val2 = np.concatenate([[0.5, 0.5], np.ones(k - 1)])
     rc, msg = _init_rc(sc, W=(rp2, col2, val2), tris=local)
-    assert rc == -1 and "selection" in msg
+    assert rc != -1, msg          # past validation (without a GPU the device work then fails)
+    rp5 = np.concatenate([[0, 5], np.arange(2, k + 1) + 4])
+    col5 = np.concatenate([sv[:5], sv[1:]])
+    val5 = np.concatenate([np.full(5, 0.2), np.ones(k - 1)])
+    rc, msg = _init_rc(sc, W=(rp5, col5, val5), tris=local)
+    assert rc == -1 and "more than 4" in msg
     # negative weight, column out of range, triangle index beyond the rows
     val3 = np.ones(k)
     val3[1] = -0.0 - 1e-3

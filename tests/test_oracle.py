@@ -818,3 +818,94 @@ def _energy_at_kappa(prob, x, A, kappa):
     Ee = local.element_energies(F, A, prob.w)
     cs = contact.constraint_set(x, prob.prox, prob.dhat)
     return float(Ee.sum()) + kappa * float(barrier.barrier(np.sqrt(cs.d2), prob.dhat, prob.barrier_form).sum())
+
+
+# --------------------------------------------------------------------------
+# embedded proxy s = W x (Section 3.1)
+# --------------------------------------------------------------------------
+def _selection_embedding(sc):
+    """The scene's own proxy written as an explicit selection W (one weight
+    of 1 per row) with triangles over proxy vertex ids."""
+    verts = np.unique(sc.surf_tris.reshape(-1))
+    vmap = np.full(sc.n, -1)
+    vmap[verts] = np.arange(verts.size)
+    rowptr = np.arange(verts.size + 1, dtype=np.int32)
+    return vmap[sc.surf_tris].astype(np.int32), (rowptr, verts.astype(np.int32), np.ones(verts.size))
+
+
+def _pressed(sc, depth, seed=1, amp=5e-5):
+    x = sc.X.copy()
+    top = sc.X[:, 2].max()
+    x[sc.X[:, 2] > 0.5 * top, 2] -= depth
+    rng = np.random.default_rng(seed)
+    x += rng.uniform(-amp, amp, x.shape) * (sc.dirichlet[:, None] == 0)
+    return x
+
+
+def test_selection_embedding_equals_the_plain_proxy():
+    """W = an explicit selection reproduces the plain proxy's iteration and
+    frame bit for bit."""
+    sc = mg.slabs(0, nx=4, ny=4, nz=1, gap=1e-3)
+    tris, W = _selection_embedding(sc)
+    p0 = solver.setup_scene(sc)
+    p1 = solver.setup(sc.X, sc.tets, sc.dirichlet, tris, sc.youngs, sc.poisson, sc.dhat, sc.kappa, W=W)
+    x = _pressed(sc, 8e-4)
+    A = fem.actuation_matrices(0.4 * sc.act_a, sc.act_R)
+    x0, r0, _ = solver.iteration(p0, x, A)
+    x1, r1, _ = solver.iteration(p1, x, A)
+    assert r0.cs.size > 0 and r1.cs.size == r0.cs.size
+    assert np.array_equal(r0.dx, r1.dx) and r0.alpha == r1.alpha and np.array_equal(x0, x1)
+    assert np.array_equal(solver.affected_vertices(p0, r0.cs), solver.affected_vertices(p1, r1.cs))
+
+
+def test_embedded_barrier_gradient_against_finite_differences():
+    """With the refined proxy (edge midpoints interpolate two vertices), the
+    barrier gradient over simulation DOFs equals central differences of
+    kappa sum_k b(d_k(W x)) with the pair set held fixed."""
+    sc = mg.refine_proxy(mg.slabs(0, nx=3, ny=3, nz=1, gap=1e-3))
+    prob = solver.setup_scene(sc)
+    x = _pressed(sc, 7e-4, seed=2)
+    s = solver.proxy_positions(prob, x)
+    cs = contact.constraint_set(s, prob.prox, prob.dhat)
+    assert cs.size > 20
+    E, g, Bm, _ = solver.barrier_terms(prob, x, cs)
+
+    def energy(y):
+        d2, _, _ = contact.pair_distances(prob.W @ y, prob.prox, cs.pt, cs.ee)
+        return prob.kappa * barrier.barrier(np.sqrt(d2), prob.dhat).sum()
+    assert np.isclose(E, energy(x), rtol=1e-12)
+    rng = np.random.default_rng(4)
+    moved = np.unique(prob.W[np.unique(contact.pair_vertices(prob.prox, cs.pt, cs.ee))].indices)
+    for v in rng.choice(moved, 6, replace=False):
+        for r in range(3):
+            e = np.zeros_like(x)
+            e[v, r] = 1e-9
+            fd = (energy(x + e) - energy(x - e)) / 2e-9
+            assert np.isclose(g[3 * v + r], fd, rtol=1e-4, atol=1e-6 * np.abs(g).max()), (v, r)
+    # the projected Hessian is symmetric PSD over the simulation DOFs
+    Bd = Bm.toarray()[np.ix_(prob.free, prob.free)]
+    assert np.allclose(Bd, Bd.T, atol=1e-12 * np.abs(Bd).max())
+    assert np.linalg.eigvalsh(Bd).min() >= -1e-9 * np.abs(Bd).max()
+
+
+def test_embedded_frames_stay_intersection_free_and_energy_decreases():
+    sc = mg.refine_proxy(mg.slabs(0, nx=3, ny=3, nz=1, gap=1e-3))
+    prob = solver.setup_scene(sc)
+    x = sc.X.copy()
+    for t in (0.5, 1.0):
+        A = fem.actuation_matrices(t * sc.act_a, sc.act_R)
+        r = solver.frame(prob, x, A, iters=8, trace=True)
+
+        def total(y):
+            F = local.deformation_gradients(y, prob.tets, prob.B)
+            s = solver.proxy_positions(prob, y)
+            cs = contact.constraint_set(s, prob.prox, prob.dhat)
+            return float(local.element_energies(F, A, prob.w).sum()) + \
+                prob.kappa * float(barrier.barrier(np.sqrt(cs.d2), prob.dhat).sum())
+        E = [total(rec.x) for rec in r.trace] + [total(r.x)]
+        assert all(E[k + 1] <= E[k] + 1e-14 * abs(E[k]) for k in range(len(E) - 1)), E
+        x = r.x
+        assert contact.min_distance(solver.proxy_positions(prob, x), prob.prox) > 0
+    assert max(r.n_pt) > 0
+    # the contact set on the proxy reaches vertices that only the midpoints touch
+    assert max(r.n_c) > 0
