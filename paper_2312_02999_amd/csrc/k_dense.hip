@@ -578,6 +578,55 @@ __device__ void factor_invert_wg64(T (*W)[LD6], T (*X)[LD6], int kb, int64_t k0,
   __syncthreads();
 }
 
+// Each thread's 16 elements of a 64 x 64 tile, all loads in flight before the
+// first LDS write (a loop with the write inside waits on every load in turn):
+// S[r][c] = get(r, c), or S[c][r] when TR.
+template <typename T, bool TR, typename G>
+__device__ __forceinline__ void stage_tile64(T (*S)[LD6], G get) {
+  T v[16];
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    v[it] = get(idx / NB6, idx % NB6);
+  }
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    if (TR) S[idx % NB6][idx / NB6] = v[it];
+    else S[idx / NB6][idx % NB6] = v[it];
+  }
+}
+
+// Two tiles at once (32 loads in flight).
+template <typename T, bool TR1, bool TR2, typename G1, typename G2>
+__device__ __forceinline__ void stage_tiles64(T (*S1)[LD6], G1 get1, T (*S2)[LD6], G2 get2) {
+  T v[16], u[16];
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    v[it] = get1(idx / NB6, idx % NB6);
+    u[it] = get2(idx / NB6, idx % NB6);
+  }
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int idx = threadIdx.x + 256 * it, r = idx / NB6, c = idx % NB6;
+    if (TR1) S1[c][r] = v[it];
+    else S1[r][c] = v[it];
+    if (TR2) S2[c][r] = u[it];
+    else S2[r][c] = u[it];
+  }
+}
+
+// Each thread's 16 elements of a 64 x 64 LDS tile to memory: put(r, c, S[r][c]).
+template <typename T, typename P>
+__device__ __forceinline__ void flush_tile64(const T (*S)[LD6], P put) {
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    put(idx / NB6, idx % NB6, S[idx / NB6][idx % NB6]);
+  }
+}
+
 // Block 0: factor and invert the first diagonal block.
 template <typename T>
 __global__ void __launch_bounds__(256) chol64_first_kernel(const T* __restrict__ A, int64_t n, T* __restrict__ dinv,
@@ -587,13 +636,10 @@ __global__ void __launch_bounds__(256) chol64_first_kernel(const T* __restrict__
   __shared__ T dk[NB6];
   const int kb = static_cast<int>(n < NB6 ? n : NB6);
   if (threadIdx.x == 0) *info = 0;
-  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
-    const int r = idx / NB6, c = idx % NB6;
-    W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
-  }
+  stage_tile64<T, false>(W, [&](int r, int c) { return (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0)); });
   __syncthreads();
   factor_invert_wg64<T>(W, X, kb, 0, info, dk);
-  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) Dinv[idx] = X[idx / NB6][idx % NB6];
+  flush_tile64<T>(X, [&](int r, int c, T v) { Dinv[r * NB6 + c] = v; });
   if (threadIdx.x < kb) dinv[threadIdx.x] = dk[threadIdx.x];
 }
 
@@ -613,11 +659,9 @@ __global__ void __launch_bounds__(256) chol64_panel_kernel(T* __restrict__ A, in
   zero_acc<T>(acc);
   if (t < m) {
     const int64_t i0 = (k + 1 + t) * NB6;
-    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
-      const int r = idx / NB6, c = idx % NB6;
-      Ds[r][c] = D[idx];
-      Bs[r][c] = (i0 + r < n && c < kb) ? A[(i0 + r) * n + k0 + c] : T(0);
-    }
+    stage_tiles64<T, false, false>(
+        Ds, [&](int r, int c) { return D[r * NB6 + c]; },
+        Bs, [&](int r, int c) { return (i0 + r < n && c < kb) ? A[(i0 + r) * n + k0 + c] : T(0); });
     __syncthreads();
     tile_gemm64<T, false, true>(Bs, Ds, acc);        // L_ik[r][c] = sum_p A_ik[r][p] D[c][p]
 #pragma unroll
@@ -635,21 +679,21 @@ __global__ void __launch_bounds__(256) chol64_panel_kernel(T* __restrict__ A, in
   const int64_t j = t - m, j0 = j * NB6;
   if (j == k) {
     // Y_kk = L_kk^-1
-    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
-      const int r = idx / NB6, c = idx % NB6;
-      if (r < kb && c < kb) {
-        F[(k0 + r) * n + k0 + c] = D[r * NB6 + c];
-        Yt[(k0 + c) * n + k0 + r] = D[r * NB6 + c];
-      }
-    }
+    stage_tile64<T, false>(Ds, [&](int r, int c) { return D[r * NB6 + c]; });
+    __syncthreads();
+    flush_tile64<T>(Ds, [&](int r, int c, T v) {
+      if (r < kb && c < kb) F[(k0 + r) * n + k0 + c] = v;
+    });
+    flush_tile64<T>(Ds, [&](int c, int r, T) {
+      if (r < kb && c < kb) Yt[(k0 + c) * n + k0 + r] = Ds[r][c];
+    });
     return;
   }
   // Y_kj = L_kk^-1 B_kj, B_kj[p][c] kept at A[(j0 + c) n + k0 + p]
-  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
-    const int r = idx / NB6, c = idx % NB6;
-    Ds[r][c] = D[idx];
-    Bs[c][r] = (r < kb) ? A[(j0 + c) * n + k0 + r] : T(0);      // Bs[c][p] = B_kj[p][c]
-  }
+  // Bs[c][p] = B_kj[p][c], read along rows of A (coalesced)
+  stage_tiles64<T, false, false>(
+      Ds, [&](int r, int c) { return D[r * NB6 + c]; },
+      Bs, [&](int c, int p) { return (p < kb) ? A[(j0 + c) * n + k0 + p] : T(0); });
   __syncthreads();
   tile_gemm64<T, false, true>(Ds, Bs, acc);          // Y[r][c] = sum_p D[r][p] B[p][c]
 #pragma unroll
@@ -687,11 +731,9 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
     while (t >= m - ii) { t -= m - ii; ++ii; }
     const int64_t bj = k + 1 + ii, bi = bj + t, i0 = bi * NB6, j0 = bj * NB6;
     const bool diag_next = bi == k + 1 && bj == k + 1;
-    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
-      const int r = idx / NB6, c = idx % NB6;
-      Li[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);
-      Lj[r][c] = (j0 + r < n) ? A[(j0 + r) * n + k0 + c] : T(0);
-    }
+    stage_tiles64<T, false, false>(
+        Li, [&](int r, int c) { return (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0); },
+        Lj, [&](int r, int c) { return (j0 + r < n) ? A[(j0 + r) * n + k0 + c] : T(0); });
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -735,7 +777,7 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
     const int kb = static_cast<int>(n - i0 < NB6 ? n - i0 : NB6);
     factor_invert_wg64<T>(W, X, kb, i0, info, dk);
     T* D = Dinv + (k + 1) * NB6 * NB6;
-    for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) D[idx] = X[idx / NB6][idx % NB6];
+    flush_tile64<T>(X, [&](int r, int c, T v) { D[r * NB6 + c] = v; });
     if (threadIdx.x < kb) dinv[i0 + threadIdx.x] = dk[threadIdx.x];
     return;
   }
@@ -743,11 +785,9 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
   t -= m * (m + 1) / 2;
   const int64_t bi = k + 1 + t / (k + 1), bj = t % (k + 1), i0 = bi * NB6, j0 = bj * NB6;
   const int kb = static_cast<int>(n - k0 < NB6 ? n - k0 : NB6);     // k < bi, so block k is full
-  for (int idx = threadIdx.x; idx < NB6 * NB6; idx += 256) {
-    const int r = idx / NB6, c = idx % NB6;
-    Li[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);      // L_ik
-    Lj[r][c] = (r < kb) ? F[(k0 + r) * n + j0 + c] : T(0);          // Y_kj[p = r][c]
-  }
+  stage_tiles64<T, false, false>(
+      Li, [&](int r, int c) { return (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0); },     // L_ik
+      Lj, [&](int r, int c) { return (r < kb) ? F[(k0 + r) * n + j0 + c] : T(0); });       // Y_kj[p = r][c]
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
