@@ -78,41 +78,51 @@ __device__ __forceinline__ float rsqrt_nr(float d) {
 
 // Factor and invert the 16 x 16 block W[o..o+16)[o..o+16) of a 32-wide
 // diagonal tile with one wave.  Lanes 0-15 hold its rows; lanes 32-47 carry
-// the identity through the same steps (the column of L is broadcast by
-// readlane into scalar registers) and so forward-substitute it, ending with
-// column c of the block's inverse in lane 32 + c.  The inverse goes to Xs,
-// 1 / diag to dk[o..o+16); a non-positive pivot is replaced by 1 and the
-// first such column (tile index + 1, below kb) is kept in first_bad.  The
-// unrolled loop is kept free of branches so that the row stays in registers.
+// the identity through the same steps and so forward-substitute it, ending
+// with column c of the block's inverse in lane 32 + c.  Per pivot the next
+// column is updated first (one readlane), so the chain from one pivot to the
+// next is rsqrt -> mul -> fma -> readlane; the other columns take the column of
+// L from LDS.  The inverse goes to Xs, 1 / diag to dk[o..o+16).  Pivots are
+// kept as they come: a non-positive one turns the rest of the factor into
+// NaN, and the first such column (tile index + 1, below kb) goes to first_bad
+// from one ballot at the end.  The unrolled loop is free of branches, so the
+// row stays in registers.
 template <typename T, int LD = 33>
 __device__ __forceinline__ void factor_invert16(const T (*W)[LD], int o, T (*Xs)[17], T* dk, int kb,
                                                 int& first_bad) {
+  __shared__ T bc[PDIPC_WAVE];
+  __shared__ T piv[16];
   const int lane = threadIdx.x;
   const int rr = lane & 15;
   const bool rowlane = lane < 16;
   T a[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = rowlane ? W[o + rr][o + c] : (c == rr ? T(1) : T(0));
-  T myinv = T(1);
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    T d = read_lane(a[j], j);
-    const bool ok = d > T(0);
-    first_bad = (!ok && first_bad == 0 && o + j < kb) ? o + j + 1 : first_bad;
-    d = ok ? d : T(1);
+    const T d = read_lane(a[j], j);
+    piv[j] = d;
     const T isd = rsqrt_nr(d);
-    const T l = (lane == j) ? d * isd : a[j] * isd;
+    dk[o + j] = isd;
+    const T l = a[j] * isd;             // lane j: d / sqrt(d)
     a[j] = l;
-    myinv = (lane == j) ? isd : myinv;
+    if (j + 1 < 16) {
+      const T ln = read_lane(l, j + 1);
+      a[j + 1] -= l * ln;
+    }
+    if (j + 2 < 16) {
+      bc[lane] = l;
 #pragma unroll
-    for (int c = j + 1; c < 16; ++c) a[c] -= l * read_lane(l, c);
+      for (int c = j + 2; c < 16; ++c) a[c] -= l * bc[c];
+    }
   }
-  if (rowlane) {
-    dk[o + rr] = myinv;
-  } else if (lane >= 32 && lane < 48) {
+  if (lane >= 32 && lane < 48) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) Xs[r][rr] = a[r];
   }
+  const bool bad = rowlane && o + rr < kb && !(piv[rr] > T(0));
+  const unsigned long long m = __ballot(bad);
+  if (m != 0 && first_bad == 0) first_bad = o + __ffsll(m);
   __builtin_amdgcn_wave_barrier();
 }
 

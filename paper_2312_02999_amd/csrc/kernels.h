@@ -314,7 +314,8 @@ void set_last_error(const char* msg);
 // row-major) and aux its transpose; aux (dense_aux_size(n) entries) then holds
 // 1 / diag(L) (n), the inverses of the diagonal blocks and solve scratch
 // (4 n).  The factor L itself is not kept, and the strict upper part of F is
-// not written.  *d_info <- 0 ok, else 1 + the first failing column.
+// not written.  *d_info <- 0 ok, else 1 + the first failing column (the
+// outputs are then NaN from that column on).
 constexpr int64_t dense_blocks_size(int64_t n) { return ((n + 63) / 64) * 64 * 64; }
 constexpr int64_t dense_tmp_offset(int64_t n) { return n * n + n + dense_blocks_size(n); }
 constexpr int64_t dense_aux_size(int64_t n) { return dense_tmp_offset(n) + 4 * n + 64; }

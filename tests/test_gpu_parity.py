@@ -120,7 +120,7 @@ def test_frames_tiny_scene():
         assert err < 1e-9, (t, err)
 
 
-@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2048, 2049, 2100, 3001])
+@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2048, 2049, 2100, 2112, 3001, 4097])
 def test_dense_spd_kernels(n):
     """Cholesky, solve and inverse against numpy at ragged multi-tile sizes,
     on both sides of the switch from 32- to 64-wide blocks (2049)."""
@@ -138,6 +138,9 @@ def test_dense_spd_kernels(n):
     # single right-hand side (the solver's case)
     x1, _ = dense_spd(_t(A), _t(b[:, 0]))
     assert np.abs(x1.cpu().numpy() - xr[:, 0]).max() < 1e-10 * max(1.0, np.abs(xr).max())
+    # the workgroups' order within a launch does not change a bit
+    x2, inv2 = dense_spd(_t(A), _t(b), inverse=True)
+    assert torch.equal(x2, x) and torch.equal(inv2, inv)
 
 
 @pytest.mark.parametrize("n,bad", [(70, 66), (2100, 2070), (2100, 40)])
