@@ -27,21 +27,29 @@ HBM_PEAK_GBS = 8000.0
 # dense matrix-core peaks of MI355X (TFLOP/s) by the reduced factor's type
 MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}
 
-# HBM bytes per local-step launch from two rocprofv3 counter passes
-# (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy
-# of known size; valid only for the workload and kernel source they were taken
-# on (profiles/local_step_kernel_face50k_pmc.md).
-LOCAL_STEP_TRAFFIC = {"workload": "face50k-r1", "source_sha256_prefix": "54fa61f8b0518b46", "bytes": 103978783}
+# HBM bytes per timer interval of a kernel family, from two rocprofv3 counter
+# passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters read for a plain
+# copy of known size (--copy-probe); valid only for the workload, precision and
+# kernel sources they were taken on (the summaries in profiles/ give the
+# commands).  Filled in from measurements; an entry whose sources changed
+# reports null.
+MEASURED_TRAFFIC = {}
 
 
-def measured_traffic(workload: str):
+def _sources_digest(files) -> str:
     import hashlib
-    path = os.path.join(ROOT, "paper_2312_02999_amd", "csrc", "k_local.hip")
-    with open(path, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()[:16]
-    t = LOCAL_STEP_TRAFFIC
-    ok = workload == t["workload"] and digest == t["source_sha256_prefix"]
-    return t["bytes"] if ok else None
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2312_02999_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family: str, workload: str, precision: str):
+    t = MEASURED_TRAFFIC.get(family)
+    if t is None or t["workload"] != workload or t["precision"] != precision:
+        return None
+    return t["bytes"] if _sources_digest(t["sources"]) == t["sha256_prefix"] else None
 
 
 def progress(msg: str) -> None:
@@ -193,6 +201,17 @@ def rooflines(sc, r, reduced_type):
             e["frac"] = round(e["achieved"] / e["peak"], 4)
         out.append(e)
     return out
+
+
+def copy_probe():
+    """A plain 256 MiB device copy: its FETCH_SIZE / WRITE_SIZE per dispatch
+    scale the counters of the solver's kernels to bytes."""
+    import torch
+    a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8}))
 
 
 def cpu_baseline(sc, a, budget_s=20.0):
@@ -366,6 +385,8 @@ def main():
         r.pop("x_final")
         out = {"only": args.only, **summary(r), "rooflines": rooflines(sc, r, "f64")}
         print(json.dumps(out))
+        if args.copy_probe:
+            copy_probe()
         return
     fp64 = run_precision(sc, FP64, args.steps, args.warmup)
     mixed = run_precision(sc, MIXED_FP32, args.steps, args.warmup, **mixed_kw)
@@ -385,7 +406,7 @@ def main():
     dom = max(roofs_mixed, key=lambda e: e["total_ms"])
     roof = {"bound": dom["bound"], "kernel": dom["kernel"], "achieved": dom.get("achieved"),
             "peak": dom.get("peak"), "unit": dom.get("unit"), "frac": dom.get("frac"),
-            "traffic": measured_traffic(args.workload) if dom["kernel"] == "local_step_kernel" else None,
+            "traffic": measured_traffic(dom["kernel"], args.workload, "mixed"),
             "avg_us": dom["avg_us"], "intervals": dom["intervals"],
             "work_per_interval": dom.get("work_per_interval"), "per_unit": dom.get("per_unit")}
     if not args.no_cpu_baseline:
@@ -414,13 +435,7 @@ def main():
     }
     print(json.dumps(out))
     if args.copy_probe:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
-        # scale the counters of the solver's kernels to bytes
-        a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8}))
+        copy_probe()
 
 
 if __name__ == "__main__":

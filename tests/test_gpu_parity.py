@@ -120,10 +120,11 @@ def test_frames_tiny_scene():
         assert err < 1e-9, (t, err)
 
 
-@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2048, 2049, 2100, 2112, 3001, 4097])
+@pytest.mark.parametrize("n", [5, 64, 130, 257, 700, 2048, 2049, 2100, 2112, 3001, 4097, 6200])
 def test_dense_spd_kernels(n):
     """Cholesky, solve and inverse against numpy at ragged multi-tile sizes,
-    on both sides of the switch from 32- to 64-wide blocks (2049)."""
+    on both sides of the switch from 32- to 64-wide blocks (2049), up to 97
+    blocks of 64."""
     from paper_2312_02999_amd import dense_spd
     rng = np.random.default_rng(n)
     G = rng.standard_normal((n, n))
@@ -132,7 +133,8 @@ def test_dense_spd_kernels(n):
     x, inv = dense_spd(_t(A), _t(b), inverse=True)
     xr = np.linalg.solve(A, b)
     assert np.abs(x.cpu().numpy() - xr).max() < 1e-10 * max(1.0, np.abs(xr).max())
-    assert np.abs(inv.cpu().numpy() - np.linalg.inv(A)).max() < 1e-10 * np.abs(np.linalg.inv(A)).max()
+    Ai = np.linalg.inv(A)
+    assert np.abs(inv.cpu().numpy() - Ai).max() < 1e-10 * np.abs(Ai).max()
     xf, _ = dense_spd(_t(A), _t(b), precision=1)
     assert np.abs(xf.cpu().numpy() - xr).max() < 1e-3 * max(1.0, np.abs(xr).max())
     # single right-hand side (the solver's case)
