@@ -33,7 +33,11 @@ MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}
 # kernel sources they were taken on (the summaries in profiles/ give the
 # commands).  Filled in from measurements; an entry whose sources changed
 # reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "reduced Cholesky (Eq. 11 system)": {
+        "workload": "face50k", "precision": "mixed", "sources": ["k_dense.hip"],
+        "sha256_prefix": "37926eeeb54c7ac9", "bytes": 1401469237},
+}
 
 
 def _sources_digest(files) -> str:
@@ -203,6 +207,24 @@ def rooflines(sc, r, reduced_type):
     return out
 
 
+def run_dense(n: int, reps: int = 6):
+    """The dense SPD factorisation and solve of the reduced system's kernels on
+    a seeded n x n SPD matrix (G G^T / n + I / 2), reps times."""
+    import torch
+    from paper_2312_02999_amd import dense_spd
+    rng = np.random.default_rng(0)
+    G = rng.standard_normal((n, n))
+    A = G @ G.T / n + 0.5 * np.eye(n)
+    b = rng.standard_normal((n, 1))
+    At = torch.tensor(A, device="cuda")
+    bt = torch.tensor(b, device="cuda")
+    for _ in range(reps):
+        x, _ = dense_spd(At, bt)
+    torch.cuda.synchronize()
+    res = float(np.abs(A @ x.cpu().numpy() - b).max())
+    print(json.dumps({"dense_n": n, "factorisations": reps, "max_residual": res}))
+
+
 def copy_probe():
     """A plain 256 MiB device copy: its FETCH_SIZE / WRITE_SIZE per dispatch
     scale the counters of the solver's kernels to bytes."""
@@ -348,6 +370,9 @@ def main():
                     help="time the Table 1 global-step configurations at kappa and 10 kappa instead")
     ap.add_argument("--fp32-reduced-min", type=int, default=None,
                     help="mixed path: smallest reduced system solved with the refined FP32 factor")
+    ap.add_argument("--dense", type=int, default=0, metavar="N",
+                    help="only factor and solve a seeded N x N SPD system six times through the library's dense "
+                         "kernels (for kernel traces and counters of the reduced factorisation alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -370,6 +395,9 @@ def main():
     progress(f"scene {args.workload} generated (n={sc.n}, m={sc.m})")
     if args.adjoint:
         print(json.dumps(run_adjoint(sc)))
+        return
+    if args.dense:
+        run_dense(args.dense)
         return
     if args.table1:
         rows = run_table1(sc, args.steps, args.warmup, sc.kappa)
