@@ -265,7 +265,7 @@ def cpu_baseline(sc, a, budget_s=20.0):
                       f"scaled to {sc.iters} iterations/frame ({sec_per_it:.2f} s/iteration)"}
 
 
-def run_adjoint(sc, n_targets=500, n_dirs=2, n_params=4, h_dir=1e-4, seed=1):
+def run_adjoint(sc, n_targets=500, n_dirs=2, n_params=64, h_dir=1e-4, h_param=1e-3, seed=1):
     """Adjoint of a converged frame on the face mesh against central finite
     differences of the same GPU solver (tolerance mode).  Targets are the
     converged positions of seeded proxy vertices at 0.6 x the strength field;
@@ -308,16 +308,21 @@ def run_adjoint(sc, n_targets=500, n_dirs=2, n_params=4, h_dir=1e-4, seed=1):
     top = np.argsort(-np.abs(g))[:n_params]
     for i in top:
         e = np.zeros(sc.m)
-        h = 1e-3
-        e[i] = h
-        fd = (loss(solve(a + e, xs)[0]) - loss(solve(a - e, xs)[0])) / (2 * h)
+        e[i] = h_param
+        fd = (loss(solve(a + e, xs)[0]) - loss(solve(a - e, xs)[0])) / (2 * h_param)
         errs.append(("tet", int(i), float(g[i]), fd))
+        if len(errs) % 8 == 0:
+            progress(f"adjoint: {len(errs)} finite-difference checks done")
     S.close()
     rel = [abs(ad - fd) / max(abs(fd), 1e-300) for _, _, ad, fd in errs]
+    rel_t = sorted(r for (k, _, _, _), r in zip(errs, rel) if k == "tet")
     return {"metric": "adjoint of a converged frame: backward ms and agreement with finite differences",
             "workload": f"{sc.n} vertices, {sc.m} tets, {sc.m} actuation parameters",
             "backward_ms": round(ms_bwd, 2), "loss": L0, "iters_targets": st_t["iters"],
             "iters_frame": st_s["iters"], "max_rel_err_fd": max(rel),
+            "params_checked": len(rel_t), "h_param": h_param, "h_dir": h_dir,
+            "median_rel_err_params": rel_t[len(rel_t) // 2] if rel_t else None,
+            "max_rel_err_params": rel_t[-1] if rel_t else None,
             "checks": [{"kind": k, "index": i, "adjoint": ad, "fd": fd} for k, i, ad, fd in errs]}
 
 
@@ -370,6 +375,11 @@ def main():
                     help="time the Table 1 global-step configurations at kappa and 10 kappa instead")
     ap.add_argument("--fp32-reduced-min", type=int, default=None,
                     help="mixed path: smallest reduced system solved with the refined FP32 factor")
+    ap.add_argument("--adjoint-params", type=int, default=64,
+                    help="with --adjoint: the actuation parameters (largest gradient entries) checked by central "
+                         "differences")
+    ap.add_argument("--adjoint-h", type=float, default=1e-3,
+                    help="with --adjoint: the central-difference step of a single parameter")
     ap.add_argument("--dense", type=int, default=0, metavar="N",
                     help="only factor and solve a seeded N x N SPD system six times through the library's dense "
                          "kernels (for kernel traces and counters of the reduced factorisation alone)")
@@ -388,13 +398,14 @@ def main():
         from paper_2312_02999_amd import serve
         for prec in (MIXED_FP32, FP64):
             progress(f"serving {args.serving} requests ({'mixed' if prec else 'fp64'})")
-            rep = serve.run_serving(n_requests=args.serving, precision=prec)
+            rep = serve.run_serving(n_requests=args.serving, precision=prec,
+                                    on_done=lambda k, n: progress(f"request {k}/{n} done") if k % 8 == 0 else None)
             print(json.dumps({"metric": "serving: request latency and frames/s", **rep}), flush=True)
         return
     sc = mg.scene_by_name(args.workload)
     progress(f"scene {args.workload} generated (n={sc.n}, m={sc.m})")
     if args.adjoint:
-        print(json.dumps(run_adjoint(sc)))
+        print(json.dumps(run_adjoint(sc, n_params=args.adjoint_params, h_param=args.adjoint_h)))
         return
     if args.dense:
         run_dense(args.dense)

@@ -206,8 +206,10 @@ def poisson_workload(n_requests: int, rate: float, sizes: list[str], frames: int
 
 
 def run_serving(n_requests=256, rate=200.0, sizes=("face5k", "face20k", "face50k", "face100k"), frames=10,
-                slots=4, budget_gb=64.0, precision=MIXED_FP32, iters=None, seed=0):
-    """Replay a Poisson arrival stream against a Server; returns the report."""
+                slots=4, budget_gb=64.0, precision=MIXED_FP32, iters=None, seed=0, on_done=None):
+    """Replay a Poisson arrival stream against a Server; returns the report.
+    on_done(k, n), if given, is called as the k-th request (in submission
+    order) has finished."""
     import meshgen as mg
     scenes = {s: mg.scene_by_name(s) for s in sorted(set(sizes))}
     offsets, names = poisson_workload(n_requests, rate, list(sizes), frames, seed)
@@ -221,8 +223,10 @@ def run_serving(n_requests=256, rate=200.0, sizes=("face5k", "face20k", "face50k
         sc = scenes[nm]
         seq = [sc.actuation_at((t + 1) / frames) for t in range(frames)]
         futs.append(srv.submit(nm, sc, seq, arrival=t0 + off))
-    for f in futs:
+    for k, f in enumerate(futs):
         f.result()
+        if on_done is not None:
+            on_done(k + 1, len(futs))
     rep = latency_report(srv.completed)
     srv.close()
     rep.update({"slots": slots, "rate": rate, "sizes": list(sizes), "precision": "mixed" if precision else "fp64"})
