@@ -191,6 +191,14 @@ __device__ __forceinline__ void store_diag32(const T (*X)[33], const T* dk, int 
   if (threadIdx.x < kb) dinv[k0 + threadIdx.x] = dk[threadIdx.x];
 }
 
+// p[idx] if ok, else 0, with the load issued either way (from p[0] when not
+// ok), so that a run of such loads has no branches and stays in flight.
+template <typename T>
+__device__ __forceinline__ T load_if(const T* __restrict__ p, int64_t idx, bool ok) {
+  const T v = p[ok ? idx : 0];
+  return ok ? v : T(0);
+}
+
 // ---- L^-1 along the factorisation (NB = 32) ----------------------------------
 // The substitution L Y = I runs block by block with the factor: Y_kj =
 // L_kk^-1 B_kj, then B_ij -= L_ik Y_kj for i > k, starting from B = I.  The
@@ -218,26 +226,51 @@ __device__ __forceinline__ void rhs_tile_step(T* __restrict__ A, int64_t n, int6
   const int rb = 16 * (w / 2), cb = 16 * (w % 2);
   const int lr = lane % 16, lk = lane / 16;
   const T* D = Dinv + k * NB * NB;
+  // every load in flight before the first LDS write (B_kj is read for the
+  // diagonal tile too, from block (k, k), and not used there)
+  T vd[4], vi[4], vb[4], pre[4];
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
     const int idx = threadIdx.x + 256 * it;
     const int r = idx / NB, c = idx % NB;
-    Ds[r][c] = D[idx];
-    Ai[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);
-    if (!diag) Bk[c][r] = A[(j0 + r) * n + k0 + c];       // B_kj[c][r]; block k is full
+    vd[it] = D[idx];
+    vi[it] = load_if(A, (i0 + r) * n + k0 + c, i0 + r < n);
+    vb[it] = A[(j0 + r) * n + k0 + c];                    // block k is full
   }
-  T pre[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = rb + mfma_row<T>(lk, q), c = cb + lr;
-    pre[q] = (!diag && i0 + r < n) ? A[(j0 + c) * n + i0 + r] : T(0);
+    pre[q] = load_if(A, (j0 + c) * n + i0 + r, !diag && i0 + r < n);
+  }
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    const int r = idx / NB, c = idx % NB;
+    Ds[r][c] = vd[it];
+    Ai[r][c] = vi[it];
+    Bk[c][r] = vb[it];                                    // B_kj[c][r]
   }
   __syncthreads();
   typename MfmaVec<T>::type pm = {T(0), T(0), T(0), T(0)}, ym = {T(0), T(0), T(0), T(0)};
+  {
+    T a[NB / 4], d[NB / 4];
 #pragma unroll
-  for (int q0 = 0; q0 < NB; q0 += 4) {
-    pm = mfma16x16x4(Ai[rb + lr][q0 + lk], Ds[cb + lr][q0 + lk], pm);
-    if (!diag) ym = mfma16x16x4(Ds[rb + lr][q0 + lk], Bk[q0 + lk][cb + lr], ym);
+    for (int s = 0; s < NB / 4; ++s) {
+      a[s] = Ai[rb + lr][4 * s + lk];
+      d[s] = Ds[cb + lr][4 * s + lk];
+    }
+#pragma unroll
+    for (int s = 0; s < NB / 4; ++s) pm = mfma16x16x4(a[s], d[s], pm);
+  }
+  if (!diag) {
+    T d[NB / 4], b[NB / 4];
+#pragma unroll
+    for (int s = 0; s < NB / 4; ++s) {
+      d[s] = Ds[rb + lr][4 * s + lk];
+      b[s] = Bk[4 * s + lk][cb + lr];
+    }
+#pragma unroll
+    for (int s = 0; s < NB / 4; ++s) ym = mfma16x16x4(d[s], b[s], ym);
   }
   __syncthreads();
 #pragma unroll
@@ -257,8 +290,16 @@ __device__ __forceinline__ void rhs_tile_step(T* __restrict__ A, int64_t n, int6
     }
   }
   typename MfmaVec<T>::type acc = {T(0), T(0), T(0), T(0)};
+  {
+    T a[NB / 4], b[NB / 4];
 #pragma unroll
-  for (int p0 = 0; p0 < NB; p0 += 4) acc = mfma16x16x4(Ta[p0 + lk][rb + lr], Yk[p0 + lk][cb + lr], acc);
+    for (int s = 0; s < NB / 4; ++s) {
+      a[s] = Ta[4 * s + lk][rb + lr];
+      b[s] = Yk[4 * s + lk][cb + lr];
+    }
+#pragma unroll
+    for (int s = 0; s < NB / 4; ++s) acc = mfma16x16x4(a[s], b[s], acc);
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = rb + mfma_row<T>(lk, q), c = cb + lr;
@@ -352,7 +393,6 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   T (*Tb)[NB + 1] = Aj;
   T (*W)[NB + 1] = Ds;    // then the tile to factor
   __shared__ T dk[NB];
-  constexpr int TL = NB / 32;
   const int64_t nblk = (n + NB - 1) / NB;
   const int64_t m = nblk - k - 1;
   int64_t t = blockIdx.x, ii = 0;
@@ -369,100 +409,85 @@ __global__ void __launch_bounds__(256) chol_update_kernel(T* __restrict__ A, int
   const int lane = threadIdx.x % PDIPC_WAVE, w = threadIdx.x / PDIPC_WAVE;
   const int rb = (NB / 2) * (w / 2), cb = (NB / 2) * (w % 2);
   const int lr = lane % 16, lk = lane / 16;
+  T pre[4];
   {
+    // every load in flight before the first LDS write (A_jk is read for the
+    // diagonal tiles too, and not used there)
     const T* D = Dinv + k * NB * NB;
+    T vd[4], vi[4], vj[4];
 #pragma unroll
-    for (int it = 0; it < NB * NB / 256; ++it) {
+    for (int it = 0; it < 4; ++it) {
       const int idx = threadIdx.x + 256 * it;
       const int r = idx / NB, c = idx % NB;
-      Ds[r][c] = D[idx];
-      Ai[r][c] = (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0);
-      if (!same) Aj[r][c] = (j0 + r < n) ? A[(j0 + r) * n + k0 + c] : T(0);
+      vd[it] = D[idx];
+      vi[it] = load_if(A, (i0 + r) * n + k0 + c, i0 + r < n);
+      vj[it] = load_if(A, (j0 + r) * n + k0 + c, j0 + r < n);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t gr = i0 + rb + mfma_row<T>(lk, q), gc = j0 + cb + lr;
+      pre[q] = load_if(A, gr * n + gc, gr < n && gc < n);
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      const int r = idx / NB, c = idx % NB;
+      Ds[r][c] = vd[it];
+      Ai[r][c] = vi[it];
+      Aj[r][c] = vj[it];
     }
   }
-  T pre[TL][TL][4];
-#pragma unroll
-  for (int x = 0; x < TL; ++x)
-#pragma unroll
-    for (int y = 0; y < TL; ++y)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t gr = i0 + rb + 16 * x + mfma_row<T>(lk, q), gc = j0 + cb + 16 * y + lr;
-        pre[x][y][q] = (gr < n && gc < n) ? A[gr * n + gc] : T(0);
-      }
   __syncthreads();
+  // panels on the matrix cores: wave w owns a 16 x 16 quadrant; a diagonal
+  // tile forms one panel
+  typename MfmaVec<T>::type pi = {T(0), T(0), T(0), T(0)}, pj = pi;
   {
-    // panels on the matrix cores: wave w owns an NB/2 x NB/2 quadrant
-    typename MfmaVec<T>::type pi[TL][TL], pj[TL][TL];
+    T ai[NB / 4], aj[NB / 4], bd[NB / 4];
 #pragma unroll
-    for (int x = 0; x < TL; ++x)
-#pragma unroll
-      for (int y = 0; y < TL; ++y) {
-        pi[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
-        pj[x][y] = pi[x][y];
-      }
-#pragma unroll
-    for (int q0 = 0; q0 < NB; q0 += 4) {
-      T ai[TL], aj[TL], bd[TL];
-#pragma unroll
-      for (int x = 0; x < TL; ++x) {
-        ai[x] = Ai[rb + 16 * x + lr][q0 + lk];
-        aj[x] = Aj[rb + 16 * x + lr][q0 + lk];
-        bd[x] = Ds[cb + 16 * x + lr][q0 + lk];
-      }
-#pragma unroll
-      for (int x = 0; x < TL; ++x)
-#pragma unroll
-        for (int y = 0; y < TL; ++y) {
-          pi[x][y] = mfma16x16x4(ai[x], bd[y], pi[x][y]);
-          if (!same) pj[x][y] = mfma16x16x4(aj[x], bd[y], pj[x][y]);
-        }
+    for (int s = 0; s < NB / 4; ++s) {
+      ai[s] = Ai[rb + lr][4 * s + lk];
+      bd[s] = Ds[cb + lr][4 * s + lk];
     }
-    __syncthreads();      // Ai/Aj become the transposed panels
+    if (same) {
 #pragma unroll
-    for (int x = 0; x < TL; ++x)
+      for (int s = 0; s < NB / 4; ++s) pi = mfma16x16x4(ai[s], bd[s], pi);
+    } else {
 #pragma unroll
-      for (int y = 0; y < TL; ++y)
+      for (int s = 0; s < NB / 4; ++s) aj[s] = Aj[rb + lr][4 * s + lk];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = rb + 16 * x + mfma_row<T>(lk, q), p = cb + 16 * y + lr;
-          Ta[p][r] = pi[x][y][q];
-          if (!same) Tb[p][r] = pj[x][y][q];
-        }
+      for (int s = 0; s < NB / 4; ++s) {
+        pi = mfma16x16x4(ai[s], bd[s], pi);
+        pj = mfma16x16x4(aj[s], bd[s], pj);
+      }
+    }
+  }
+  __syncthreads();      // Ai/Aj become the transposed panels
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rb + mfma_row<T>(lk, q), p = cb + lr;
+    Ta[p][r] = pi[q];
+    Tb[p][r] = pj[q];     // unused by a diagonal tile
   }
   __syncthreads();
   T (*Tbs)[NB + 1] = same ? Ta : Tb;
   {
-    typename MfmaVec<T>::type acc[TL][TL];
+    typename MfmaVec<T>::type acc = {T(0), T(0), T(0), T(0)};
+    T av[NB / 4], bv[NB / 4];
 #pragma unroll
-    for (int x = 0; x < TL; ++x)
-#pragma unroll
-      for (int y = 0; y < TL; ++y) acc[x][y] = typename MfmaVec<T>::type{T(0), T(0), T(0), T(0)};
-#pragma unroll 4
-    for (int p0 = 0; p0 < NB; p0 += 4) {
-      T av[TL], bv[TL];
-#pragma unroll
-      for (int x = 0; x < TL; ++x) {
-        av[x] = Ta[p0 + lk][rb + 16 * x + lr];
-        bv[x] = Tbs[p0 + lk][cb + 16 * x + lr];
-      }
-#pragma unroll
-      for (int x = 0; x < TL; ++x)
-#pragma unroll
-        for (int y = 0; y < TL; ++y) acc[x][y] = mfma16x16x4(av[x], bv[y], acc[x][y]);
+    for (int s = 0; s < NB / 4; ++s) {
+      av[s] = Ta[4 * s + lk][rb + lr];
+      bv[s] = Tbs[4 * s + lk][cb + lr];
     }
 #pragma unroll
-    for (int x = 0; x < TL; ++x)
+    for (int s = 0; s < NB / 4; ++s) acc = mfma16x16x4(av[s], bv[s], acc);
 #pragma unroll
-      for (int y = 0; y < TL; ++y)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = rb + 16 * x + mfma_row<T>(lk, q), c = cb + 16 * y + lr;
-          const int64_t gr = i0 + r, gc = j0 + c;
-          const T v = pre[x][y][q] - acc[x][y][q];
-          if (last) W[r][c] = (gr < n && gc < n) ? v : (r == c ? T(1) : T(0));
-          else if (gr < n && gc < n) A[gr * n + gc] = v;
-        }
+    for (int q = 0; q < 4; ++q) {
+      const int r = rb + mfma_row<T>(lk, q), c = cb + lr;
+      const int64_t gr = i0 + r, gc = j0 + c;
+      const T v = pre[q] - acc[q];
+      if (last) W[r][c] = (gr < n && gc < n) ? v : (r == c ? T(1) : T(0));
+      else if (gr < n && gc < n) A[gr * n + gc] = v;
+    }
   }
   if (!last) return;
   __syncthreads();
