@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(256) chol_lastrow_kernel(const T* __restrict__
     const int idx = threadIdx.x + 256 * it;
     Ds[idx / NB][idx % NB] = D[idx];
     const int r = idx % NB, c = idx / NB;
-    Bl[r][c] = (!diag && r < kb) ? A[(j0 + c) * n + i0 + r] : T(0);
+    Bl[r][c] = load_if(A, (j0 + c) * n + i0 + r, !diag && r < kb);
   }
   __syncthreads();
   if (!diag) {
@@ -366,7 +366,8 @@ __global__ void __launch_bounds__(256) chol_first_kernel(const T* __restrict__ A
   for (int it = 0; it < NB * NB / 256; ++it) {
     const int idx = threadIdx.x + 256 * it;
     const int r = idx / NB, c = idx % NB;
-    W[r][c] = (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0));
+    const bool in = r < kb && c < kb;
+    W[r][c] = in ? load_if(A, r * n + c, in) : (r == c ? T(1) : T(0));
   }
   __syncthreads();
   if (threadIdx.x < PDIPC_WAVE) factor_invert_wave32<T>(W, X, kb, 0, info, Sc, dk);
@@ -671,7 +672,10 @@ __global__ void __launch_bounds__(256) chol64_first_kernel(const T* __restrict__
   __shared__ T dk[NB6];
   const int kb = static_cast<int>(n < NB6 ? n : NB6);
   if (threadIdx.x == 0) *info = 0;
-  stage_tile64<T, false>(W, [&](int r, int c) { return (r < kb && c < kb) ? A[r * n + c] : (r == c ? T(1) : T(0)); });
+  stage_tile64<T, false>(W, [&](int r, int c) {
+    const bool in = r < kb && c < kb;
+    return in ? load_if(A, r * n + c, in) : (r == c ? T(1) : T(0));
+  });
   __syncthreads();
   factor_invert_wg64<T>(W, X, kb, 0, info, dk);
   flush_tile64<T>(X, [&](int r, int c, T v) { Dinv[r * NB6 + c] = v; });
@@ -696,7 +700,7 @@ __global__ void __launch_bounds__(256) chol64_panel_kernel(T* __restrict__ A, in
     const int64_t i0 = (k + 1 + t) * NB6;
     stage_tiles64<T, false, false>(
         Ds, [&](int r, int c) { return D[r * NB6 + c]; },
-        Bs, [&](int r, int c) { return (i0 + r < n && c < kb) ? A[(i0 + r) * n + k0 + c] : T(0); });
+        Bs, [&](int r, int c) { return load_if(A, (i0 + r) * n + k0 + c, i0 + r < n && c < kb); });
     __syncthreads();
     tile_gemm64<T, false, true>(Bs, Ds, acc);        // L_ik[r][c] = sum_p A_ik[r][p] D[c][p]
 #pragma unroll
@@ -728,7 +732,7 @@ __global__ void __launch_bounds__(256) chol64_panel_kernel(T* __restrict__ A, in
   // Bs[c][p] = B_kj[p][c], read along rows of A (coalesced)
   stage_tiles64<T, false, false>(
       Ds, [&](int r, int c) { return D[r * NB6 + c]; },
-      Bs, [&](int c, int p) { return (p < kb) ? A[(j0 + c) * n + k0 + p] : T(0); });
+      Bs, [&](int c, int p) { return load_if(A, (j0 + c) * n + k0 + p, p < kb); });
   __syncthreads();
   tile_gemm64<T, false, true>(Ds, Bs, acc);          // Y[r][c] = sum_p D[r][p] B[p][c]
 #pragma unroll
@@ -767,8 +771,8 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
     const int64_t bj = k + 1 + ii, bi = bj + t, i0 = bi * NB6, j0 = bj * NB6;
     const bool diag_next = bi == k + 1 && bj == k + 1;
     stage_tiles64<T, false, false>(
-        Li, [&](int r, int c) { return (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0); },
-        Lj, [&](int r, int c) { return (j0 + r < n) ? A[(j0 + r) * n + k0 + c] : T(0); });
+        Li, [&](int r, int c) { return load_if(A, (i0 + r) * n + k0 + c, i0 + r < n); },
+        Lj, [&](int r, int c) { return load_if(A, (j0 + r) * n + k0 + c, j0 + r < n); });
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -777,7 +781,7 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
         for (int q = 0; q < 4; ++q) {
           int r, c;
           quad_pos<T>(x, y, q, r, c);
-          pre[x][y][q] = (i0 + r < n && j0 + c < n) ? A[(i0 + r) * n + j0 + c] : T(0);
+          pre[x][y][q] = load_if(A, (i0 + r) * n + j0 + c, i0 + r < n && j0 + c < n);
         }
     __syncthreads();
     tile_gemm64<T, false, true>(Li, Lj, acc);        // sum_p L_ik[r][p] L_jk[c][p]
@@ -821,8 +825,8 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
   const int64_t bi = k + 1 + t / (k + 1), bj = t % (k + 1), i0 = bi * NB6, j0 = bj * NB6;
   const int kb = static_cast<int>(n - k0 < NB6 ? n - k0 : NB6);     // k < bi, so block k is full
   stage_tiles64<T, false, false>(
-      Li, [&](int r, int c) { return (i0 + r < n) ? A[(i0 + r) * n + k0 + c] : T(0); },     // L_ik
-      Lj, [&](int r, int c) { return (r < kb) ? F[(k0 + r) * n + j0 + c] : T(0); });       // Y_kj[p = r][c]
+      Li, [&](int r, int c) { return load_if(A, (i0 + r) * n + k0 + c, i0 + r < n); },       // L_ik
+      Lj, [&](int r, int c) { return load_if(F, (k0 + r) * n + j0 + c, r < kb); });         // Y_kj[p = r][c]
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -831,7 +835,7 @@ __global__ void __launch_bounds__(256) chol64_update_kernel(T* __restrict__ A, i
       for (int q = 0; q < 4; ++q) {
         int r, c;
         quad_pos<T>(x, y, q, r, c);
-        pre[x][y][q] = (bj < k && i0 + r < n) ? A[(j0 + c) * n + i0 + r] : T(0);
+        pre[x][y][q] = load_if(A, (j0 + c) * n + i0 + r, bj < k && i0 + r < n);
       }
   __syncthreads();
   tile_gemm64<T, false, false>(Li, Lj, acc);         // sum_p L_ik[r][p] Y_kj[p][c]
