@@ -195,14 +195,15 @@ __device__ __forceinline__ bool box_overlap(const double* a, const double* b, do
          a[2] <= b[5] + dhat && b[2] <= a[5] + dhat;
 }
 
-// One wave per query.  The query's box spans at most 2 x 2 x 2 cells; for
-// each, the lanes test the cell's hash bucket 64 entries at a time (buckets
-// are short but several dozen long where the mesh is dense, so a serial scan
-// would be a long chain of dependent loads).  A pair is reported only in the
-// first cell both boxes share, so each appears once.
+// One wave per query.  The query's box spans at most 2 x 2 x 2 cells; the
+// bucket ranges of all of them are read at once, and the lanes test their
+// entries as one range, 64 at a time (buckets are short but several dozen
+// long where the mesh is dense, so a serial scan would be a long chain of
+// dependent loads).  A pair is reported only in the first cell both boxes
+// share, so each appears once.
 struct QueryCtx {
   bool is_pt;
-  const double* qb;
+  double qb[6];
   int32_t qv[2];
   int32_t ql[3], qu[3];
   double o[3], h;
@@ -213,15 +214,18 @@ __device__ __forceinline__ QueryCtx query_ctx(const QueryArgs& qa, int64_t q) {
   QueryCtx c;
   c.is_pt = q < px.nsv;
   c.qv[0] = c.qv[1] = 0;
+  const double* qb;
   if (c.is_pt) {
-    c.qb = qa.vbox + 6 * q;
+    qb = qa.vbox + 6 * q;
     c.qv[0] = px.sv[q];
   } else {
     const int64_t e = q - px.nsv;
-    c.qb = qa.ebox + 6 * e;
+    qb = qa.ebox + 6 * e;
     c.qv[0] = px.se[2 * e];
     c.qv[1] = px.se[2 * e + 1];
   }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) c.qb[r] = qb[r];
   c.o[0] = qa.params[0]; c.o[1] = qa.params[1]; c.o[2] = qa.params[2];
   c.h = qa.params[3];
   const double pad = qa.params[4];
@@ -240,22 +244,32 @@ __device__ __forceinline__ int32_t query_test(const QueryArgs& qa, const QueryCt
   const int32_t* ids = c.is_pt ? qa.t_id : qa.e_id;
   const uint64_t* keys = c.is_pt ? qa.t_key : qa.e_key;
   const double* pbox = c.is_pt ? qa.tbox : qa.ebox;
-  if (keys[s] != key) return -1;
+  // the entry's key and id, then the partner's box and vertices, each group
+  // loaded at once (a valid entry's id indexes both, whatever its key)
+  const uint64_t ks = keys[s];
   const int32_t p = ids[s];
+  const double* bp = pbox + 6 * static_cast<int64_t>(p);
+  double b[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) b[r] = bp[r];
+  int32_t w0, w1, w2 = -1;
+  if (c.is_pt) {
+    w0 = px.st[3 * p]; w1 = px.st[3 * p + 1]; w2 = px.st[3 * p + 2];
+  } else {
+    w0 = px.se[2 * p]; w1 = px.se[2 * p + 1];
+  }
+  if (ks != key) return -1;
   if (!c.is_pt && p <= q - px.nsv) return -1;
-  const double* b = pbox + 6 * static_cast<int64_t>(p);
   const int32_t pl0 = cell_of(b[0], c.o[0], c.h), pl1 = cell_of(b[1], c.o[1], c.h), pl2 = cell_of(b[2], c.o[2], c.h);
   if (max(c.ql[0], pl0) != i || max(c.ql[1], pl1) != j || max(c.ql[2], pl2) != k) return -1;
   if (!box_overlap(c.qb, b, qa.dhat)) return -1;
   int32_t v4[4];
   if (c.is_pt) {
-    const int32_t t0 = px.st[3 * p], t1 = px.st[3 * p + 1], t2 = px.st[3 * p + 2];
-    if (c.qv[0] == t0 || c.qv[0] == t1 || c.qv[0] == t2) return -1;
-    v4[0] = c.qv[0]; v4[1] = t0; v4[2] = t1; v4[3] = t2;
+    if (c.qv[0] == w0 || c.qv[0] == w1 || c.qv[0] == w2) return -1;
+    v4[0] = c.qv[0]; v4[1] = w0; v4[2] = w1; v4[3] = w2;
   } else {
-    const int32_t b0 = px.se[2 * p], b1 = px.se[2 * p + 1];
-    if (c.qv[0] == b0 || c.qv[0] == b1 || c.qv[1] == b0 || c.qv[1] == b1) return -1;
-    v4[0] = c.qv[0]; v4[1] = c.qv[1]; v4[2] = b0; v4[3] = b1;
+    if (c.qv[0] == w0 || c.qv[0] == w1 || c.qv[1] == w0 || c.qv[1] == w1) return -1;
+    v4[0] = c.qv[0]; v4[1] = c.qv[1]; v4[2] = w0; v4[3] = w1;
   }
   if (qa.dist) {
     double P[4][3];
@@ -274,24 +288,44 @@ __device__ __forceinline__ int32_t query_wave(const QueryArgs& qa, int64_t q, Em
   const int lane = threadIdx.x % PDIPC_WAVE;
   const QueryCtx c = query_ctx(qa, q);
   const int32_t* start = c.is_pt ? qa.t_start : qa.e_start;
-  int32_t total = 0;
-  for (int slot = 0; slot < 8; ++slot) {
-    const int32_t i = c.ql[0] + (slot & 1), j = c.ql[1] + ((slot >> 1) & 1), k = c.ql[2] + (slot >> 2);
-    if (i > c.qu[0] || j > c.qu[1] || k > c.qu[2]) continue;      // uniform across the wave
-    const uint32_t hh = cell_hash(i, j, k, qa.mask);
-    const uint64_t key = cell_key(i, j, k);
-    const int32_t s0 = start[hh], s1 = start[hh + 1];
-    for (int32_t base = s0; base < s1; base += PDIPC_WAVE) {
-      const int32_t s = base + lane;
-      const int32_t p = s < s1 ? query_test(qa, c, q, s, key, i, j, k) : -1;
-      const uint64_t m = __ballot(p >= 0);
-      if (p >= 0) {
-        const int32_t below = static_cast<int32_t>(
-            __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
-        emit(p, total + below);
-      }
-      total += static_cast<int32_t>(__popcll(m));
+  // lane l < 8 reads the bucket range of cell slot l (empty outside the box)
+  int32_t s0 = 0, len = 0;
+  if (lane < 8) {
+    const int32_t i = c.ql[0] + (lane & 1), j = c.ql[1] + ((lane >> 1) & 1), k = c.ql[2] + (lane >> 2);
+    if (i <= c.qu[0] && j <= c.qu[1] && k <= c.qu[2]) {
+      const uint32_t hh = cell_hash(i, j, k, qa.mask);
+      s0 = start[hh];
+      len = start[hh + 1] - s0;
     }
+  }
+  // the slots' entries one after another: slot l covers [off[l], off[l + 1])
+  int32_t off[9], sb[8];
+  off[0] = 0;
+#pragma unroll
+  for (int l = 0; l < 8; ++l) {
+    sb[l] = __builtin_amdgcn_readlane(s0, l);
+    off[l + 1] = off[l] + __builtin_amdgcn_readlane(len, l);
+  }
+  int32_t total = 0;
+  for (int32_t f0 = 0; f0 < off[8]; f0 += PDIPC_WAVE) {
+    const int32_t f = f0 + lane;
+    int slot = 0;
+#pragma unroll
+    for (int l = 1; l < 8; ++l) slot += f >= off[l] ? 1 : 0;
+    int32_t s = 0, base = 0;
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      if (slot == l) { s = sb[l]; base = off[l]; }
+    s += f - base;
+    const int32_t i = c.ql[0] + (slot & 1), j = c.ql[1] + ((slot >> 1) & 1), k = c.ql[2] + (slot >> 2);
+    const int32_t p = f < off[8] ? query_test(qa, c, q, s, cell_key(i, j, k), i, j, k) : -1;
+    const uint64_t m = __ballot(p >= 0);
+    if (p >= 0) {
+      const int32_t below = static_cast<int32_t>(
+          __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
+      emit(p, total + below);
+    }
+    total += static_cast<int32_t>(__popcll(m));
   }
   return total;
 }
