@@ -260,6 +260,10 @@ void launch_unpack(const FactorDev& f, int32_t n, const double* sol, double* dx,
   if (N > 0) unpack_kernel<<<grid_for(N, 256), 256, 0, st>>>(N, f.ext2vert, sol, dx);
 }
 
+void launch_unpack_range(const FactorDev& f, int32_t j0, int32_t j1, const double* sol, double* dx, hipStream_t st) {
+  if (j1 > j0) unpack_kernel<<<grid_for(j1 - j0, 256), 256, 0, st>>>(j1 - j0, f.ext2vert + j0, sol + 3LL * j0, dx);
+}
+
 // W_J = P_J Dinv_J per supernode (P_J = L[R(J), cols(J)], r x s row-major;
 // Dinv_J lower triangular, s x s row-major): one workgroup per node.
 __global__ void __launch_bounds__(256) panel_dinv_kernel(const int32_t* __restrict__ node_s,
@@ -377,9 +381,15 @@ void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x
 void launch_hinv_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* sol,
                              hipStream_t st) {
   const int64_t N = static_cast<int64_t>(f.n1) + f.n2;
-  if (nc > 0 && f.n2 > 0)
-    rows_update_kernel<<<grid_for(N, PDIPC_WAVE), SC_WAVES * PDIPC_WAVE, 0, st>>>(N, N, nc, c_x2, f.hinv_x2, v,
-                                                                                  sol);
+  launch_hinv_cols_update_range(f, nc, c_x2, v, sol, 0, N, st);
+}
+
+void launch_hinv_cols_update_range(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* sol,
+                                   int64_t j0, int64_t j1, hipStream_t st) {
+  const int64_t N = static_cast<int64_t>(f.n1) + f.n2;
+  if (nc > 0 && f.n2 > 0 && j1 > j0)
+    rows_update_kernel<<<grid_for(j1 - j0, PDIPC_WAVE), SC_WAVES * PDIPC_WAVE, 0, st>>>(
+        j1 - j0, N, nc, c_x2, f.hinv_x2 + j0, v, sol + 3 * j0);
 }
 
 // sol's x2 rows = columns q0, q0 + 1, q0 + 2 of Sigma^-1 (one per right-hand side)

@@ -259,6 +259,8 @@ void launch_backward_sweep(const FactorDev& f, const double* y, double* sol, hip
 // dx (n x 3) from sol (ext) at the free vertices; the fixed vertices' entries
 // are not written (the caller keeps them zero)
 void launch_unpack(const FactorDev& f, int32_t n, const double* sol, double* dx, hipStream_t st);
+// Rows [j0, j1) of the extended order only.
+void launch_unpack_range(const FactorDev& f, int32_t j0, int32_t j1, const double* sol, double* dx, hipStream_t st);
 
 // ------------------------------------------------- reduced contact system
 // C_s = Sigma^-1[c, c] (nc x nc), using x2 index of each c vertex
@@ -279,6 +281,9 @@ void launch_sigma_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x
 // stored rows x2 of H_s^-1 (f.hinv_x2)
 void launch_hinv_cols_update(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* sol,
                              hipStream_t st);
+// The same for rows [j0, j1) of the extended order (x1 rows first, then x2).
+void launch_hinv_cols_update_range(const FactorDev& f, int32_t nc, const int32_t* c_x2, const double* v, double* sol,
+                                   int64_t j0, int64_t j1, hipStream_t st);
 // Rows x2 of H_s^-1 into K (n2 x (n1 + n2)): column q of Sigma^-1 is the x2
 // part of H_s^-1 e_q, and the backward sweep with y1 = 0 gives its x1 part,
 // -H11^-1 H12 Sigma^-1 e_q; three columns per sweep.  y and sol are the

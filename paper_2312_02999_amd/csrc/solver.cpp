@@ -188,6 +188,10 @@ struct Solver {
   // runs concurrently with the sweeps of the global step
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_cinv = nullptr;
+  // the x1 rows of the contact correction run on the second stream beside the
+  // CCD (which reads proxy vertices, all in x2); the line search waits for them
+  hipEvent_t ev_rows = nullptr, ev_x1 = nullptr;
+  bool x1_pending = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   double timer_ms = 0.0;
@@ -208,6 +212,8 @@ struct Solver {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_cinv) (void)hipEventDestroy(ev_cinv);
+    if (ev_rows) (void)hipEventDestroy(ev_rows);
+    if (ev_x1) (void)hipEventDestroy(ev_x1);
     if (side) (void)hipStreamDestroy(side);
     if (h_scal) (void)hipHostFree(h_scal);
     if (h_counts) (void)hipHostFree(h_counts);
@@ -551,6 +557,8 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   HIPCHK(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S->ev_cinv, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&S->ev_rows, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&S->ev_x1, hipEventDisableTiming));
   for (hipEvent_t& e : S->sev) HIPCHK(hipEventCreate(&e));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_scal), 16 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&S->h_counts), 8 * sizeof(int32_t), hipHostMallocDefault));
@@ -1233,8 +1241,21 @@ static void global_step(Solver* S, IterOut& io) {
     }
     if (!mixed || fallback) dense_chol_solve_into<double>(S->ML.p, S->MLi.p, N3, S->rhs.p, S->u.p, st);
     launch_bcheck_apply(nc, S->inc, pair_slots(S), np, S->fixed.p, S->u.p, S->wtmp.p, S->vvec.p, st);
-    if (hinv_path) launch_hinv_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p, st);
-    else launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
+    if (hinv_path) {
+      // the x2 rows now; the x1 rows (all but n2 of them) and their unpacking
+      // on the second stream, which the line search joins (the CCD before it
+      // reads proxy vertices only, all in x2)
+      HIPCHK(hipEventRecord(S->ev_rows, st));
+      launch_hinv_cols_update_range(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p, f.n1, Next, st);
+      HIPCHK(hipStreamWaitEvent(S->side, S->ev_rows, 0));
+      launch_hinv_cols_update_range(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p, 0, f.n1, S->side);
+      launch_unpack_range(f, 0, f.n1, S->solvec.p, S->dx.p, S->side);
+      HIPCHK(hipEventRecord(S->ev_x1, S->side));
+      S->x1_pending = true;
+      launch_unpack_range(f, f.n1, f.n1 + f.n2, S->solvec.p, S->dx.p, st);
+      return;
+    }
+    launch_sigma_cols_update(f, nc, S->c_x2.p, S->vvec.p, S->solvec.p + n1x3, st);
   } else {
     rest_of_forward();
   }
@@ -1243,6 +1264,14 @@ static void global_step(Solver* S, IterOut& io) {
     launch_backward_sweep(f, S->yvec.p, S->solvec.p, st);
   }
   launch_unpack(f, S->n, S->solvec.p, S->dx.p, st);
+}
+
+// The main stream takes the x1 rows of dx from the second stream (queued by a
+// global step that corrected them there).
+static void join_x1(Solver* S) {
+  if (!S->x1_pending) return;
+  HIPCHK(hipStreamWaitEvent(S->st, S->ev_x1, 0));
+  S->x1_pending = false;
 }
 
 // ---- comparison configurations of Table 1 -------------------------------------
@@ -1422,6 +1451,7 @@ static void step_and_search(Solver* S, IterOut& io, bool apply) {
   // (the first trial is accepted in nearly every iteration: 4 halvings in 240
   // on the 50k face, so a second queued trial costs more than its round trip)
   stage_mark(S, 4);
+  join_x1(S);                          // the trials read dx everywhere
   double* ls = S->lsbuf.p;
   launch_ls_init(ls, S->ccd_part.p, nccd, st);
   auto trial = [&]() {
@@ -1607,6 +1637,7 @@ static int32_t do_backward(Solver* S, const double* dLdx, double* dLda) {
   auto precond = [&](const double* r, double* z) {
     launch_axpby(n3, -1.0, r, 0.0, S->g.p, st);     // g = -r  =>  dx = Hhat^-1 r
     global_step(S, io);
+    join_x1(S);
     HIPCHK(hipMemcpyAsync(z, S->dx.p, sizeof(double) * n3, hipMemcpyDeviceToDevice, st));
   };
   auto dot = [&](const double* a, const double* b) {
