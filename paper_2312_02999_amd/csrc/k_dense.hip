@@ -1214,7 +1214,7 @@ __device__ __forceinline__ void sweep_all(double (*A)[33], int m, int32_t* info)
 // T = Ci_KR (Ci_RR)^-1 (nk x r); every workgroup inverts Ci_RR itself
 __global__ void __launch_bounds__(256) cinv_t_kernel(const double* __restrict__ Ci, int32_t nold, CinvLists L,
                                                      int32_t nk, int32_t r, double* __restrict__ T,
-                                                     int32_t* info) {
+                                                     double* __restrict__ G, int32_t* info) {
   __shared__ double Ri[32][33];
   for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
     const int i = e / r, j = e % r;
@@ -1230,34 +1230,50 @@ __global__ void __launch_bounds__(256) cinv_t_kernel(const double* __restrict__ 
   double acc = 0.0;
   for (int p = 0; p < r; ++p) acc -= row[L.rem_old[p]] * Ri[p][q];
   T[idx] = acc;
+  G[static_cast<int64_t>(q) * nk + i] = row[L.rem_old[q]];       // Ci_KR, transposed for the next kernel
 }
 
-// CK = Ci_KK - T Ci_RK (nk x nk)
+// CK = Ci_KK - T Ci_RK (nk x nk); Ci_RK[p][j] = Ci[kept j][removed p] comes
+// from G, row p of which neighbouring threads read contiguously
 __global__ void cinv_keep_kernel(const double* __restrict__ Ci, int32_t nold, CinvLists L, int32_t nk, int32_t r,
-                                 const double* __restrict__ T, double* __restrict__ CK) {
+                                 const double* __restrict__ T, const double* __restrict__ G,
+                                 double* __restrict__ CK) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(nk) * nk) return;
   const int64_t i = idx / nk, j = idx % nk;
-  const double* rowj = Ci + static_cast<int64_t>(L.kept_old[j]) * nold;
   double v = Ci[static_cast<int64_t>(L.kept_old[i]) * nold + L.kept_old[j]];
-  for (int p = 0; p < r; ++p) v -= T[i * r + p] * rowj[L.rem_old[p]];
+  for (int p = 0; p < r; ++p) v -= T[i * r + p] * G[static_cast<int64_t>(p) * nk + j];
   CK[idx] = v;
 }
 
-// W = CK B with B = Sigma^-1[K, A] (nk x a); one wave per row of CK
+// W = CK B with B = Sigma^-1[K, A] (nk x a, a <= 32); one wave per row of
+// CK, all a columns in one pass over the row
 __global__ void __launch_bounds__(256) cinv_w_kernel(const double* __restrict__ CK, int32_t nk, CinvLists L,
                                                      int32_t a, const double* __restrict__ Si, int32_t n2,
                                                      double* __restrict__ W) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
   const int lane = threadIdx.x % PDIPC_WAVE;
   if (i >= nk) return;
-  for (int q = 0; q < a; ++q) {
-    const double* sq = Si + static_cast<int64_t>(L.add_x2[q]) * n2;      // Sigma^-1 is symmetric
-    double acc = 0.0;
-    for (int64_t j = lane; j < nk; j += PDIPC_WAVE) acc += CK[i * nk + j] * sq[L.kept_x2[j]];
-    acc = wave_sum_d(acc);
-    if (lane == 0) W[i * a + q] = acc;
+  double acc[32];
+  const double* sq[32];                                                  // Sigma^-1 is symmetric
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    acc[q] = 0.0;
+    sq[q] = Si + static_cast<int64_t>(L.add_x2[q < a ? q : 0]) * n2;
   }
+  for (int64_t j = lane; j < nk; j += PDIPC_WAVE) {
+    const double c = CK[i * nk + j];
+    const int32_t kx = L.kept_x2[j];
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
+      if (q < a) acc[q] += c * sq[q][kx];
+  }
+#pragma unroll
+  for (int q = 0; q < 32; ++q)
+    if (q < a) {
+      const double s = wave_sum_d(acc[q]);
+      if (lane == 0) W[i * a + q] = s;
+    }
 }
 
 // Sm = D - B^T W (a x a); one wave per entry
@@ -1328,9 +1344,9 @@ void launch_cinv_update(const CinvUpdateArgs& u, hipStream_t st) {
                                                          u.rem_ids, u.add_ids, u.L, u.info);
   if (u.r > 0)
     cinv_t_kernel<<<grid_for(static_cast<int64_t>(nk) * u.r, 256), 256, 0, st>>>(u.Ci, u.nold, u.L, nk, u.r, u.T,
-                                                                                 u.info);
+                                                                                 u.G, u.info);
   cinv_keep_kernel<<<grid_for(static_cast<int64_t>(nk) * nk, 256), 256, 0, st>>>(u.Ci, u.nold, u.L, nk, u.r, u.T,
-                                                                                 u.CK);
+                                                                                 u.G, u.CK);
   if (u.a > 0) {
     cinv_w_kernel<<<static_cast<unsigned>((nk + 3) / 4), 256, 0, st>>>(u.CK, nk, u.L, u.a, u.Si, u.n2, u.W);
     cinv_schur_kernel<<<static_cast<unsigned>((u.a * u.a + 3) / 4), 256, 0, st>>>(u.Si, u.n2, u.L, nk, u.a, u.W,

@@ -375,6 +375,7 @@ struct CinvUpdateArgs {
   const double* Si;                  // Sigma^-1 (n2 x n2)
   double *Sm, *Sinv;                 // a x a, 32 x 32
   double *T, *W, *V;                 // nk x r, nk x a, nk x a
+  double* G;                         // r x nk: G[q][i] = Ci[kept i][removed q]
   double* CK;                        // nk x nk
   double* out;                       // nc x nc
 };

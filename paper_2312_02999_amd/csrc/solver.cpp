@@ -1145,7 +1145,7 @@ static void global_step(Solver* S, IterOut& io) {
         ScopedTimer tm(S, TK_CINV_UPDATE, sd);
         const int32_t r = io.c_removed, a = io.c_added;
         S->cupd_i.ensure(2LL * nk + 2 * kCinvMaxDelta + nc);
-        S->cupd_d.ensure(32 * 32 + a * a + static_cast<int64_t>(nk) * (r + 2 * a + nk));
+        S->cupd_d.ensure(32 * 32 + a * a + static_cast<int64_t>(nk) * (2 * r + 2 * a + nk));
         S->Cinv_next.ensure(static_cast<int64_t>(nc) * nc);
         CinvUpdateArgs u{};
         u.n = S->n; u.nold = S->nc_prev; u.nc = nc; u.r = r; u.a = a; u.n2 = f.n2;
@@ -1166,6 +1166,7 @@ static void global_step(Solver* S, IterOut& io) {
         u.Sinv = dp; dp += 32 * 32;
         u.Sm = dp; dp += a * a;
         u.T = dp; dp += static_cast<int64_t>(nk) * r;
+        u.G = dp; dp += static_cast<int64_t>(nk) * r;
         u.W = dp; dp += static_cast<int64_t>(nk) * a;
         u.V = dp; dp += static_cast<int64_t>(nk) * a;
         u.CK = dp;
