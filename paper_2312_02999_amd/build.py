@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libpdipc.so")
 ARCH = os.environ.get("PDIPC_ARCH", "gfx950")
 
 SOURCES = ["k_local.hip", "k_util.hip", "k_contact.hip", "k_barrier.hip", "k_factor.hip", "k_dense.hip",
-           "k_adjoint.hip", "k_variants.hip", "k_noalloc.hip", "solver.cpp", "host_factor.cpp"]
+           "k_cinv.hip", "k_adjoint.hip", "k_variants.hip", "k_noalloc.hip", "solver.cpp", "host_factor.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
