@@ -492,61 +492,18 @@ void launch_c_to_x2(int32_t nc, const int32_t* clist, const int32_t* vert2x2, in
   if (nc > 0) c_to_x2_kernel<<<grid_for(nc, 256), 256, 0, st>>>(nc, clist, vert2x2, c_x2);
 }
 
-// M[3a+r][3b+s] = Cinv[a][b] delta_rs
-__global__ void fill_kron_kernel(int32_t nc, const double* __restrict__ Cinv, double* __restrict__ M) {
-  int64_t N = 3 * static_cast<int64_t>(nc);
-  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= N * N) return;
-  int64_t row = idx / N, col = idx % N;
-  M[idx] = (row % 3 == col % 3) ? Cinv[(row / 3) * nc + col / 3] : 0.0;
-}
-
-// One wave per c vertex a (its three rows of M).  The wave walks a's incident
-// pairs in ascending order; for each group of four slots lb of the pair, lane
-// (lb, r, s) adds U_k[3 la + r] . U_k[3 lb + s] into M[3 a + r][3 c(lb) + s].
-// The slots of one pair name distinct vertices, so no two lanes write one
-// entry in the same step and the summation order is fixed.
-template <int S>
-__global__ void __launch_bounds__(256) add_bcheck_kernel(int32_t nc, const int32_t* __restrict__ clist,
-                                                         const int32_t* __restrict__ ptr, const int32_t* __restrict__ ent,
-                                                         const int32_t* __restrict__ vslot,
-                                                         const int32_t* __restrict__ cflag,
-                                                         const int32_t* __restrict__ cidx, const double* __restrict__ U,
-                                                         int32_t npairs, double* __restrict__ M) {
-  const int lane = threadIdx.x % PDIPC_WAVE;
-  const int64_t ca = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
-  if (ca >= nc) return;
-  const int64_t N = 3 * static_cast<int64_t>(nc);
-  const int32_t va = clist[ca];
-  const int r = (lane % 9) / 3, sc = lane % 3;
-  const bool active = lane < 36;
-  for (int32_t t = ptr[va]; t < ptr[va + 1]; ++t) {
-    const int32_t k = ent[t] / S, la = ent[t] % S;
-    if (!active) continue;
-    for (int lb0 = 0; lb0 < S; lb0 += 4) {
-      const int lb = lb0 + lane / 9;
-      const int32_t vb = vslot[S * k + lb];
-      if (vb < 0 || !cflag[vb]) continue;
-      const int64_t cb = cidx[vb];
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < 5; ++c)
-        acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
-               U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
-      M[(3 * ca + r) * N + 3 * cb + sc] += acc;
-    }
-  }
-}
-
-// Row block a of M = C^-1 + B_check in one pass (reduced systems up to
-// RB_LDS_N unknowns): one workgroup per contact vertex.  The 9 S products of
+// Row block a of M = C^-1 + B_check in one pass: one workgroup per contact
+// vertex and block of up to RB_LDS_N columns (grid y), so that the block's
+// three rows fit in LDS.  The 9 S products of
 // each incidence entry (3 rows x S slots x 3 columns) are formed by all
-// threads, several entries at a time, and staged in LDS with their target
-// column; the first 9 S threads then add them to the three rows (LDS) entry
-// by entry in incidence order (deterministic: the slots of one pair name
-// distinct vertices), and the rows are written with the C^-1 = C_s^-1 (x) I3
-// part added.
+// threads, RB_GROUPS x (256 / 9 S) entries at a time with every thread's loads
+// for its RB_GROUPS entries issued together, and staged in LDS with their
+// target column; the first 9 S threads then add those in the block to the
+// three rows (LDS) entry by entry in incidence order (deterministic: the slots
+// of one pair name distinct vertices), and the rows are written with the
+// C^-1 = C_s^-1 (x) I3 part added.
 constexpr int RB_LDS_N = 2048;
+constexpr int RB_GROUPS = 4;
 template <int S>
 __global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const double* __restrict__ Cinv,
                                                             const int32_t* __restrict__ clist,
@@ -558,41 +515,70 @@ __global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const do
                                                             const double* __restrict__ U, int32_t npairs,
                                                             double* __restrict__ M) {
   constexpr int NP = 9 * S;                   // products per incidence entry
-  constexpr int CHUNK = 256 / NP;             // entries per pass of 256 threads
+  constexpr int CHUNK = 256 / NP;             // entries per group of 256 threads
+  constexpr int PASS = RB_GROUPS * CHUNK;     // entries per pass
   extern __shared__ unsigned char smem_raw[];
-  double* R = reinterpret_cast<double*>(smem_raw);     // 3 x N
-  __shared__ double P[CHUNK * NP];
-  __shared__ int32_t Q[CHUNK * NP];
+  double* R = reinterpret_cast<double*>(smem_raw);     // 3 x Wc
+  __shared__ double P[PASS * NP];
+  __shared__ int32_t Q[PASS * NP];
   const int tid = threadIdx.x;
   const int64_t ca = blockIdx.x;
   const int64_t N = 3 * static_cast<int64_t>(nc);
-  for (int64_t i = tid; i < 3 * N; i += blockDim.x) R[i] = 0.0;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * RB_LDS_N;
+  const int64_t Wc = N - c0 < RB_LDS_N ? N - c0 : RB_LDS_N;
+  for (int64_t i = tid; i < 3 * Wc; i += blockDim.x) R[i] = 0.0;
   const int32_t va = clist[ca];
   const int32_t t0 = ptr[va], t1 = ptr[va + 1];
   const int e = tid / NP, lp = tid % NP;
   const int lb = lp / 9, r = (lp % 9) / 3, sc = lp % 3;
-  for (int32_t tc = t0; tc < t1; tc += CHUNK) {
+  for (int32_t tc = t0; tc < t1; tc += PASS) {
     if (e < CHUNK) {
-      const int32_t t = tc + e;
-      double acc = 0.0;
-      int32_t q = -1;
-      if (t < t1) {
-        const int32_t k = ent[t] / S, la = ent[t] % S;
-        const int32_t vb = vslot[S * k + lb];
-        if (vb >= 0 && cflag[vb]) {
+      // entry g of this thread: tc + e + CHUNK g; an entry past the end, or a
+      // slot that is not in c, reads pair 0 and slot vertex 0 and adds nothing
+      int32_t k[RB_GROUPS], la[RB_GROUPS], vb[RB_GROUPS];
+      bool ok[RB_GROUPS];
 #pragma unroll
-          for (int c = 0; c < 5; ++c)
-            acc += U[static_cast<int64_t>(5 * (3 * la + r) + c) * npairs + k] *
-                   U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k];
-          q = static_cast<int32_t>(r * N + 3 * static_cast<int64_t>(cidx[vb]) + sc);
+      for (int g = 0; g < RB_GROUPS; ++g) {
+        const int32_t t = tc + e + CHUNK * g;
+        ok[g] = t < t1;
+        const int32_t en = ent[ok[g] ? t : t0];
+        k[g] = en / S;
+        la[g] = en % S;
+      }
+      double ua[RB_GROUPS][5], ub[RB_GROUPS][5];
+#pragma unroll
+      for (int g = 0; g < RB_GROUPS; ++g) {
+        vb[g] = vslot[S * k[g] + lb];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          ua[g][c] = U[static_cast<int64_t>(5 * (3 * la[g] + r) + c) * npairs + k[g]];
+          ub[g][c] = U[static_cast<int64_t>(5 * (3 * lb + sc) + c) * npairs + k[g]];
         }
       }
-      P[tid] = acc;
-      Q[tid] = q;
+      int32_t fl[RB_GROUPS], ci[RB_GROUPS];
+#pragma unroll
+      for (int g = 0; g < RB_GROUPS; ++g) {
+        const int32_t v = vb[g] >= 0 ? vb[g] : 0;
+        fl[g] = cflag[v];
+        ci[g] = cidx[v];
+      }
+#pragma unroll
+      for (int g = 0; g < RB_GROUPS; ++g) {
+        double acc = 0.0;
+        int32_t q = -1;
+        const int64_t col = 3 * static_cast<int64_t>(ci[g]) + sc - c0;
+        if (ok[g] && vb[g] >= 0 && fl[g] && col >= 0 && col < Wc) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) acc += ua[g][c] * ub[g][c];
+          q = static_cast<int32_t>(r * Wc + col);
+        }
+        P[(g * CHUNK + e) * NP + lp] = acc;
+        Q[(g * CHUNK + e) * NP + lp] = q;
+      }
     }
     __syncthreads();
     if (tid < NP) {
-      const int ne = min(CHUNK, t1 - tc);
+      const int ne = min(PASS, t1 - tc);
       for (int ee = 0; ee < ne; ++ee) {
         const int32_t q = Q[ee * NP + tid];
         if (q >= 0) R[q] += P[ee * NP + tid];
@@ -602,32 +588,25 @@ __global__ void __launch_bounds__(256) assemble_rows_kernel(int32_t nc, const do
   }
   if (t0 >= t1) __syncthreads();               // R zeroed by every thread
   for (int rr = 0; rr < 3; ++rr)
-    for (int64_t col = tid; col < N; col += blockDim.x) {
+    for (int64_t cl = tid; cl < Wc; cl += blockDim.x) {
+      const int64_t col = c0 + cl;
       const double kron = (col % 3 == rr) ? Cinv[ca * nc + col / 3] : 0.0;
-      M[(3 * ca + rr) * N + col] = kron + R[rr * N + col];
+      M[(3 * ca + rr) * N + col] = kron + R[rr * Wc + cl];
     }
 }
 
 void launch_assemble_reduced(int32_t nc, const double* Cinv, const Incidence& inc, const PairSlots& ps,
                              int32_t npairs, double* M, hipStream_t st) {
-  int64_t N = 3 * static_cast<int64_t>(nc);
-  if (N <= RB_LDS_N) {
-    const size_t shm = sizeof(double) * 3 * N;
-    if (ps.S == 4)
-      assemble_rows_kernel<4><<<static_cast<unsigned>(nc), 256, shm, st>>>(
-          nc, Cinv, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx, ps.U, npairs, M);
-    else
-      assemble_rows_kernel<kSlotsW><<<static_cast<unsigned>(nc), 256, shm, st>>>(
-          nc, Cinv, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx, ps.U, npairs, M);
-    return;
-  }
-  fill_kron_kernel<<<grid_for(N * N, 256), 256, 0, st>>>(nc, Cinv, M);
+  const int64_t N = 3 * static_cast<int64_t>(nc);
+  if (nc <= 0) return;
+  const size_t shm = sizeof(double) * 3 * (N < RB_LDS_N ? N : RB_LDS_N);
+  const dim3 grid(static_cast<unsigned>(nc), static_cast<unsigned>((N + RB_LDS_N - 1) / RB_LDS_N));
   if (ps.S == 4)
-    add_bcheck_kernel<4><<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx,
-                                                           ps.U, npairs, M);
+    assemble_rows_kernel<4><<<grid, 256, shm, st>>>(nc, Cinv, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag, inc.cidx,
+                                                    ps.U, npairs, M);
   else
-    add_bcheck_kernel<kSlotsW><<<grid_for(nc, 4), 256, 0, st>>>(nc, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag,
-                                                                 inc.cidx, ps.U, npairs, M);
+    assemble_rows_kernel<kSlotsW><<<grid, 256, shm, st>>>(nc, Cinv, inc.clist, inc.ptr, inc.ent, ps.v, inc.cflag,
+                                                          inc.cidx, ps.U, npairs, M);
 }
 
 // w_k = U_k^T u_local (5 per pair), u indexed by the c index of each free slot
