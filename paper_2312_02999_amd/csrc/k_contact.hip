@@ -333,13 +333,22 @@ __device__ __forceinline__ int32_t query_wave(const QueryArgs& qa, int64_t q, Em
 constexpr int QT = 256;
 constexpr int QW = QT / PDIPC_WAVE;   // queries per workgroup
 
-__global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount) {
+// Counts each query's partners and keeps the first kQueryKeep of them; the
+// largest count above kQueryKeep goes to *over (zero before the launch).
+__global__ void __launch_bounds__(QT) query_count_kernel(QueryArgs qa, int32_t* __restrict__ qcount,
+                                                         int32_t* __restrict__ qbuf, int32_t* __restrict__ over) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * QW + threadIdx.x / PDIPC_WAVE;
   const int64_t nq = static_cast<int64_t>(qa.px.nsv) + qa.px.nse;
   if (blockIdx.x == 0 && threadIdx.x == 0) qcount[nq] = 0;     // sentinel of the scan
   if (q >= nq) return;
-  const int32_t c = query_wave(qa, q, [&](int32_t, int32_t) {});
-  if (threadIdx.x % PDIPC_WAVE == 0) qcount[q] = c;
+  int32_t* keep = qbuf + q * kQueryKeep;
+  const int32_t c = query_wave(qa, q, [&](int32_t p, int32_t r) {
+    if (r < kQueryKeep) keep[r] = p;
+  });
+  if (threadIdx.x % PDIPC_WAVE == 0) {
+    qcount[q] = c;
+    if (c > kQueryKeep) atomicMax(over, c);
+  }
 }
 
 __global__ void __launch_bounds__(QT) query_fill_kernel(QueryArgs qa, const int32_t* __restrict__ qoff,
@@ -351,22 +360,25 @@ __global__ void __launch_bounds__(QT) query_fill_kernel(QueryArgs qa, const int3
   query_wave(qa, q, [&](int32_t p, int32_t r) { tmpj[b + r] = p; });
 }
 
-// one wave per query: rank its partners (unique ids) and emit sorted pairs
+// one wave per query: rank its partners (unique ids) and emit sorted pairs;
+// the partners are read from src + q * stride (the counting pass's kept
+// ones), or, with stride 0, from src + qoff[q] (the second pass's)
 __global__ void __launch_bounds__(256) query_emit_kernel(ProxyDev px, const int32_t* __restrict__ qoff,
-                                                         const int32_t* __restrict__ tmpj, int32_t* __restrict__ ptype,
-                                                         int32_t* __restrict__ pi, int32_t* __restrict__ pj,
-                                                         int32_t* __restrict__ pv4) {
+                                                         const int32_t* __restrict__ src, int64_t stride,
+                                                         int32_t* __restrict__ ptype, int32_t* __restrict__ pi,
+                                                         int32_t* __restrict__ pj, int32_t* __restrict__ pv4) {
   const int lane = threadIdx.x % PDIPC_WAVE;
   const int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / PDIPC_WAVE;
   const int64_t nq = static_cast<int64_t>(px.nsv) + px.nse;
   if (q >= nq) return;
   const int32_t b = qoff[q], e = qoff[q + 1], cnt = e - b;
+  const int64_t base = stride > 0 ? q * stride : b;                  // partner a at src[base + a]
   const bool is_pt = q < px.nsv;
   const int32_t qi = is_pt ? px.sv[q] : static_cast<int32_t>(q - px.nsv);
   for (int32_t a = lane; a < cnt; a += PDIPC_WAVE) {
-    const int32_t key = tmpj[b + a];
+    const int32_t key = src[base + a];
     int32_t rank = 0;
-    for (int32_t j = 0; j < cnt; ++j) rank += tmpj[b + j] < key ? 1 : 0;
+    for (int32_t j = 0; j < cnt; ++j) rank += src[base + j] < key ? 1 : 0;
     const int32_t o = b + rank;
     ptype[o] = is_pt ? 0 : 1;
     pi[o] = qi;
@@ -419,7 +431,8 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
 
   QueryArgs qa{px, x, bb.vbox, bb.tbox, bb.ebox, bb.params, mask, bb.t_count, bb.t_id, bb.t_key,
                bb.e_count, bb.e_id, bb.e_key, dhat, distance_filter};
-  query_count_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count);
+  launch_fill_i32(bb.d_totals + 7, 1, 0, st);
+  query_count_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count, bb.qbuf, bb.d_totals + 7);
   {
     // per-query offsets; the offset of the first edge query is the PT count
     const ScanJob job{bb.q_count, bb.q_count, nq + 1, bb.d_totals, nullptr, px.nsv, bb.d_totals + 1};
@@ -427,18 +440,21 @@ int find_pairs(const ProxyDev& px, const BroadPhaseBuffers& bb, const double* x,
   }
   int32_t* h_tot = bb.h_totals;
   hipMemcpyAsync(h_tot, bb.d_totals, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
+  hipMemcpyAsync(h_tot + 7, bb.d_totals + 7, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
   const int32_t npairs = h_tot[0];
   if (h_tot[2] > bb.ent_cap || h_tot[3] > bb.ent_cap) return -1;   // grid sizing broke
-  if (npairs > out.cap || npairs > bb.tmp_cap) {
+  const bool kept = h_tot[7] == 0;        // every query's partners are in qbuf
+  if (npairs > out.cap || (!kept && npairs > bb.tmp_cap)) {
     *needed = npairs;
     return 1;
   }
   *n_pt = h_tot[1];
   *n_ee = npairs - h_tot[1];
   if (npairs > 0) {
-    query_fill_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count, bb.tmpj);
-    query_emit_kernel<<<grid_for(nq, 4), 256, 0, st>>>(px, bb.q_count, bb.tmpj, out.type, out.i, out.j, out.v4);
+    if (!kept) query_fill_kernel<<<grid_for(nq, QW), QT, 0, st>>>(qa, bb.q_count, bb.tmpj);
+    query_emit_kernel<<<grid_for(nq, 4), 256, 0, st>>>(px, bb.q_count, kept ? bb.qbuf : bb.tmpj,
+                                                       kept ? kQueryKeep : 0, out.type, out.i, out.j, out.v4);
   }
   return 0;
 }

@@ -84,6 +84,9 @@ struct ProxyDev {
   const int32_t* se;    // 2 x nse (AoS (lo, hi) sim ids), sorted
 };
 
+// Partners a query keeps from its counting pass; the broad phase walks the
+// grid a second time only when some query has more.
+constexpr int32_t kQueryKeep = 64;
 struct BroadPhaseBuffers {
   // boxes: 6 doubles per primitive (lo xyz, hi xyz)
   double* vbox;         // nsv
@@ -101,9 +104,10 @@ struct BroadPhaseBuffers {
   uint64_t* e_key;
   int64_t ent_cap;      // capacity of each entry array
   int32_t* q_count;     // nsv + nse + 1 per-query counts / offsets
-  int32_t* tmpj;        // unsorted partner ids
+  int32_t* qbuf;        // (nsv + nse) x kQueryKeep: each query's first partners, in discovery order
+  int32_t* tmpj;        // unsorted partner ids (queries with more than kQueryKeep partners)
   int64_t tmp_cap;
-  int32_t* d_totals;    // [0] pairs total
+  int32_t* d_totals;    // [0] pairs total, [7] largest partner count above kQueryKeep (else 0)
   int32_t* h_totals;    // pinned host copy of d_totals (4 entries)
   void* scan_temp;
   void* red_temp;

@@ -121,7 +121,7 @@ struct Solver {
   ProxyDev px{};
   BroadPhaseBuffers bb{};
   DBuf<double> vbox, tbox, ebox, params;
-  DBuf<int32_t> t_count, t_cursor, t_id, e_count, e_cursor, e_id, q_count, totals, tmpj;
+  DBuf<int32_t> t_count, t_cursor, t_id, e_count, e_cursor, e_id, q_count, qbuf, totals, tmpj;
   DBuf<uint64_t> t_key, e_key;
   DBuf<char> scan_tmp, red_tmp;
   DBuf<int32_t> act_type, act_i, act_j, act_v4, cand_type, cand_i, cand_j, cand_v4;
@@ -734,6 +734,7 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   for (auto* b : {&S->t_count, &S->t_cursor, &S->e_count, &S->e_cursor}) b->ensure(T + 1);
   S->t_id.ensure(ent); S->e_id.ensure(ent); S->t_key.ensure(ent); S->e_key.ensure(ent);
   S->q_count.ensure(8LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1);
+  S->qbuf.ensure(static_cast<int64_t>(kQueryKeep) * (static_cast<int64_t>(S->nsv) + S->nse) + 1);
   S->totals.ensure(8);
   const int64_t scan_n = std::max<int64_t>({T + 1, 8LL * (static_cast<int64_t>(S->nsv) + S->nse) + 1,
                                             static_cast<int64_t>(n) + 1});
@@ -744,7 +745,8 @@ static int32_t do_init(const pdipc_mesh_desc* md, const pdipc_options* op, Solve
   bb.table_bits = bits;
   bb.t_count = S->t_count.p; bb.t_cursor = S->t_cursor.p; bb.t_id = S->t_id.p; bb.t_key = S->t_key.p;
   bb.e_count = S->e_count.p; bb.e_cursor = S->e_cursor.p; bb.e_id = S->e_id.p; bb.e_key = S->e_key.p;
-  bb.ent_cap = ent; bb.q_count = S->q_count.p; bb.d_totals = S->totals.p; bb.h_totals = S->h_counts;
+  bb.ent_cap = ent; bb.q_count = S->q_count.p; bb.qbuf = S->qbuf.p; bb.d_totals = S->totals.p;
+  bb.h_totals = S->h_counts;
   S->tmpj.ensure(4LL * S->nsv + 1024);
   bb.tmpj = S->tmpj.p;
   bb.tmp_cap = S->tmpj.cap;
@@ -1815,7 +1817,7 @@ void pdipc_destroy(void* h) {
   if (S->st) (void)hipStreamSynchronize(S->st);
   DBuf<int32_t>* bi[] = {&S->tets, &S->vt_ptr, &S->vt_ent, &S->sv, &S->stri, &S->sedge, &S->node_c0, &S->node_s,
                          &S->node_r, &S->level_nodes, &S->frows, &S->fcol, &S->ext2vert, &S->vert2x2, &S->lvl_rows, &S->lvl_row_node, &S->t_count,
-                         &S->t_cursor, &S->t_id, &S->e_count, &S->e_cursor, &S->e_id, &S->q_count, &S->totals, &S->tmpj,
+                         &S->t_cursor, &S->t_id, &S->e_count, &S->e_cursor, &S->e_id, &S->q_count, &S->qbuf, &S->totals, &S->tmpj,
                          &S->act_type, &S->act_i, &S->act_j, &S->act_v4, &S->cand_type, &S->cand_i, &S->cand_j,
                          &S->cand_v4, &S->inc_cnt, &S->inc_ptr, &S->inc_cursor, &S->inc_ent, &S->inc_raw, &S->inc_cflag,
                          &S->inc_cidx, &S->inc_clist, &S->inc_nc, &S->c_x2, &S->info, &S->cflagbuf, &S->cposbuf};
