@@ -83,6 +83,24 @@ def test_contact_set_bit_exact_c1(depth):
     assert np.array_equal(pairs.astype(np.int64), ref)
 
 
+def test_contact_set_many_partners_per_query_c1():
+    """C1 pressed with d_hat = 2 cm (about twice the edge length): 58 914 pairs,
+    and hundreds of queries have more partners than the 64 the broad phase's
+    counting pass keeps, so the second walk of the grid runs.  The set is
+    bit-exact against the oracle's."""
+    sc = mg.slabs(0)
+    dhat = 0.02
+    S = _solver(sc, dhat=dhat)
+    x = _pressed(sc, 9e-4)
+    pairs = S.debug_contacts(_t(x))
+    cs = ocontact.constraint_set(x, ocontact.make_proxy(sc.surf_tris), dhat)
+    ref = np.concatenate([np.c_[np.zeros(len(cs.pt), np.int64), cs.pt],
+                          np.c_[np.ones(len(cs.ee), np.int64), cs.ee]]).astype(np.int64)
+    # the case: point queries (vertex) and edge queries (lower edge) above 64
+    assert max(np.bincount(cs.pt[:, 0]).max(), np.bincount(cs.ee[:, 0]).max()) > 64
+    assert np.array_equal(pairs.astype(np.int64), ref)
+
+
 def test_contact_set_empty_when_apart():
     sc = mg.slabs(0)
     S = _solver(sc)
@@ -502,6 +520,35 @@ def test_single_iteration_face50k_closed_slit(precision):
     assert perr < tol, perr
     assert abs(am - rec.alpha_m) <= tol * max(1.0, rec.alpha_m)
     assert abs(al - rec.alpha) <= tol * max(1.0, rec.alpha)
+
+
+def test_single_iteration_face50k_reduced_system_above_2048():
+    """The 50k face with its slit closed and d_hat = 0.8 mm: 20 336 pairs over
+    995 contact vertices, so the reduced system has 2985 unknowns: assembled
+    in two column blocks and factored with 64-wide blocks.  Contact set
+    bit-exact; one FP64 iteration's dx within 1e-9 of max |dx|, alpha_m and
+    alpha within 1e-9."""
+    from paper_2312_02999_amd import Solver
+    sc = mg.scene_by_name("face50k")
+    sc.dhat = 8e-4
+    x = mg.closed_slit_state(sc, 3e-4, seed=1, jitter=2e-5)
+    prob = osolver.setup_scene(sc)
+    A = ofem.actuation_matrices(0.5 * sc.act_a, sc.act_R)
+    _, rec, _ = osolver.iteration(prob, x, A)
+    nc = len(osolver.affected_vertices(prob, rec.cs))
+    assert 3 * nc > 2048
+    S = Solver(sc, precision=0)
+    S.set_actuation_scalar(_t(0.5 * sc.act_a), _t(sc.act_R.reshape(-1, 9)))
+    pairs = S.debug_contacts(_t(x))
+    want = np.concatenate([np.c_[np.zeros(len(rec.cs.pt), np.int64), rec.cs.pt],
+                           np.c_[np.ones(len(rec.cs.ee), np.int64), rec.cs.ee]]).astype(np.int64)
+    assert np.array_equal(pairs.astype(np.int64), want)
+    dx, am, al = S.debug_step(_t(x))
+    err = np.abs(dx.cpu().numpy() - rec.dx).max() / np.abs(rec.dx).max()
+    print(f"face50k, 3 n_c = {3 * nc}: dx err {err:.3e} alpha_m {am} / {rec.alpha_m} alpha {al} / {rec.alpha}")
+    assert err < 1e-9, err
+    assert abs(am - rec.alpha_m) <= 1e-9 * max(1.0, rec.alpha_m)
+    assert abs(al - rec.alpha) <= 1e-9 * max(1.0, rec.alpha)
 
 
 def test_nonfinite_actuation_is_rejected():
