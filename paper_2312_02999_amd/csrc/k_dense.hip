@@ -935,7 +935,19 @@ __global__ void __launch_bounds__(256) tri_gemv_kernel(const T* __restrict__ M, 
   const T* Mr = M + row * n;
   T s[4] = {T(0), T(0), T(0), T(0)};
   if (nrhs == 1) {
-    for (int64_t c = c0 + lane; c < c1; c += PDIPC_WAVE) s[0] += Mr[c] * x[c];
+    // four partial sums, so that each lane has eight loads in flight
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    int64_t c = c0 + lane;
+    for (; c + 3 * PDIPC_WAVE < c1; c += 4 * PDIPC_WAVE) {
+      const T m0 = Mr[c], m1 = Mr[c + PDIPC_WAVE], m2 = Mr[c + 2 * PDIPC_WAVE], m3 = Mr[c + 3 * PDIPC_WAVE];
+      const T x0 = x[c], x1 = x[c + PDIPC_WAVE], x2 = x[c + 2 * PDIPC_WAVE], x3 = x[c + 3 * PDIPC_WAVE];
+      a0 += m0 * x0;
+      a1 += m1 * x1;
+      a2 += m2 * x2;
+      a3 += m3 * x3;
+    }
+    for (; c < c1; c += PDIPC_WAVE) a0 += Mr[c] * x[c];
+    s[0] = (a0 + a1) + (a2 + a3);
   } else {
     for (int64_t c = c0 + lane; c < c1; c += PDIPC_WAVE) {
       const T m = Mr[c];
