@@ -36,7 +36,7 @@ MFMA_PEAK_TFS = {"f64": 78.6, "f32": 157.3}
 MEASURED_TRAFFIC = {
     "reduced Cholesky (Eq. 11 system)": {
         "workload": "face50k", "precision": "mixed", "sources": ["k_dense.hip"],
-        "sha256_prefix": "fb6e134e6227443a", "bytes": 1400933750},
+        "sha256_prefix": "2bfebeeb07074475", "bytes": 1400951280},
 }
 
 
